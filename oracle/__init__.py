@@ -1,0 +1,217 @@
+"""Plain FP64 CPU oracle of the TRT-R lattice Boltzmann step (arXiv:2312.10316).
+
+TEST INFRASTRUCTURE ONLY.  This package is the checker, not the product: only ``tests/``,
+``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may import it.  It shares no
+code with the HIP library (``paper_2312_10316_amd``) and never imports it.
+
+The arithmetic lives in ``lbm_oracle.c`` (plain C, compiled with ``gcc -O2 -ffp-contract=off``, no
+fast-math, twice: FP64 and FP64-complex for complex-step derivatives).  This module only marshals
+numpy arrays.  Reductions (mass, the RMS error of Sec. 3, Eq. (33)) are computed here with
+``math.fsum`` (correctly rounded sums), in the definitions' own terms.
+
+Array layout: populations ``g[9, ny, nx]`` (pre-collision, time t_n); fields ``[ny, nx]``; node
+(j, k) is ``[k, j]``.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lbm_oracle.c")
+_LIB = os.path.join(_HERE, "liblbm_oracle.so")
+
+AUX_LOCAL, AUX_FLUX, AUX_NONE = 0, 1, 2
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle (both builds) into one shared object; returns its path."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    objs = []
+    for tag, extra in (("r", []), ("z", ["-DORC_COMPLEX"])):
+        obj = os.path.join(_HERE, f"_lbm_oracle_{tag}.o")
+        subprocess.run(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                        "-Wall", "-c", _SRC, "-o", obj] + extra, check=True)
+        objs.append(obj)
+    tmp = _LIB + ".tmp"
+    subprocess.run(["gcc", "-shared", "-o", tmp] + objs + ["-lm"], check=True)
+    os.replace(tmp, _LIB)
+    for o in objs:
+        os.remove(o)
+    return _LIB
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("dx", ctypes.c_double),
+                ("dt", ctypes.c_double), ("lambda_", ctypes.c_double), ("D_const", ctypes.c_double),
+                ("aux", ctypes.c_int)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        P = ctypes.c_void_p
+        dbl, i32 = ctypes.c_double, ctypes.c_int
+        zc = ctypes.c_double * 2  # C99 double _Complex is passed like struct {double re, im}
+        lib.orc_lattice.argtypes = [P, P, P]
+        lib.orc_equilibrium.argtypes = [dbl, dbl, dbl, dbl, P]
+        lib.orc_collide.argtypes = [P, dbl, dbl, dbl, dbl, dbl, P]
+        lib.orc_relaxation.argtypes = [dbl, dbl, dbl, dbl, P, P]
+        for pre in ("orc_", "orc_z_"):
+            getattr(lib, pre + "init").argtypes = [P, P, P, P, P]
+            getattr(lib, pre + "phi").argtypes = [P, P, P]
+            getattr(lib, pre + "step").argtypes = [P, P, P, P, P, P, P, P]
+            getattr(lib, pre + "run").argtypes = [P, P, i32, P, P, P, P, P, P]
+        del zc
+        _lib = lib
+    return _lib
+
+
+@dataclass
+class Problem:
+    """One periodic instance: lattice, time step, magic parameter, constant D, aux-term form."""
+    nx: int
+    ny: int
+    dx: float
+    dt: float
+    lam: float
+    D_const: float = 0.0
+    aux: int = AUX_LOCAL
+
+    def _c(self) -> _Problem:
+        return _Problem(self.nx, self.ny, self.dx, self.dt, self.lam, self.D_const, self.aux)
+
+    @property
+    def c(self) -> float:
+        return self.dx / self.dt
+
+
+def _arr(a, shape, cplx):
+    dt = np.complex128 if cplx else np.float64
+    a = np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=dt), shape))
+    return a
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def lattice():
+    """(ex[9], ey[9], w[9]) in the oracle's velocity order (lattice units, e = c * (ex, ey))."""
+    lib = _load()
+    ex = np.zeros(9, np.int32)
+    ey = np.zeros(9, np.int32)
+    w = np.zeros(9, np.float64)
+    lib.orc_lattice(_ptr(ex), _ptr(ey), _ptr(w))
+    return ex.astype(np.int64), ey.astype(np.int64), w
+
+
+def equilibrium(phi: float, ux: float, uy: float, c: float) -> np.ndarray:
+    out = np.zeros(9)
+    _load().orc_equilibrium(phi, ux, uy, c, _ptr(out))
+    return out
+
+
+def collide(g, ux: float, uy: float, tau1: float, tau2: float, c: float) -> np.ndarray:
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    out = np.zeros(9)
+    _load().orc_collide(_ptr(g), ux, uy, tau1, tau2, c, _ptr(out))
+    return out
+
+
+def relaxation(kappa: float, dx: float, dt: float, lam: float):
+    t1 = ctypes.c_double()
+    t2 = ctypes.c_double()
+    _load().orc_relaxation(kappa, dx, dt, lam, ctypes.byref(t1), ctypes.byref(t2))
+    return t1.value, t2.value
+
+
+def _fields(p: Problem, ux, uy, D, S, dSdt, cplx):
+    sh = (p.ny, p.nx)
+    ux = _arr(ux, sh, cplx)
+    uy = _arr(uy, sh, cplx)
+    D = None if D is None else _arr(D, sh, cplx)
+    S = None if S is None else _arr(S, sh, cplx)
+    dSdt = None if dSdt is None else _arr(dSdt, sh, cplx)
+    return ux, uy, D, S, dSdt
+
+
+def init(p: Problem, phi0, ux, uy, cplx: bool = False) -> np.ndarray:
+    """g_i = g_eq_i(phi0, u) (the initial condition of Sec. 3)."""
+    lib = _load()
+    sh = (p.ny, p.nx)
+    phi0 = _arr(phi0, sh, cplx)
+    ux, uy, *_ = _fields(p, ux, uy, None, None, None, cplx)
+    g = np.zeros((9,) + sh, np.complex128 if cplx else np.float64)
+    pc = p._c()
+    (lib.orc_z_init if cplx else lib.orc_init)(ctypes.byref(pc), _ptr(phi0), _ptr(ux), _ptr(uy), _ptr(g))
+    return g
+
+
+def phi(p: Problem, g) -> np.ndarray:
+    lib = _load()
+    cplx = np.iscomplexobj(g)
+    g = np.ascontiguousarray(g, dtype=np.complex128 if cplx else np.float64)
+    out = np.zeros((p.ny, p.nx), g.dtype)
+    pc = p._c()
+    (lib.orc_z_phi if cplx else lib.orc_phi)(ctypes.byref(pc), _ptr(g), _ptr(out))
+    return out
+
+
+def step(p: Problem, g, ux, uy, D=None, S=None, dSdt=None) -> np.ndarray:
+    """One step of Eq. (14) on a copy of g; returns the new pre-collision populations."""
+    lib = _load()
+    cplx = np.iscomplexobj(g) or any(np.iscomplexobj(a) for a in (ux, uy, D, S, dSdt) if a is not None)
+    g = np.ascontiguousarray(g, dtype=np.complex128 if cplx else np.float64)
+    ux, uy, D, S, dSdt = _fields(p, ux, uy, D, S, dSdt, cplx)
+    out = np.empty_like(g)
+    pc = p._c()
+    (lib.orc_z_step if cplx else lib.orc_step)(ctypes.byref(pc), _ptr(g), _ptr(out), _ptr(ux), _ptr(uy),
+                                               _ptr(D), _ptr(S), _ptr(dSdt))
+    return out
+
+
+def run(p: Problem, g, nsteps: int, ux, uy, D=None, S=None, dSdt=None) -> np.ndarray:
+    """nsteps steps with fixed u, D, S, dS/dt; returns the final populations (input untouched)."""
+    lib = _load()
+    cplx = np.iscomplexobj(g) or any(np.iscomplexobj(a) for a in (ux, uy, D, S, dSdt) if a is not None)
+    g = np.array(g, dtype=np.complex128 if cplx else np.float64, copy=True, order="C")
+    ux, uy, D, S, dSdt = _fields(p, ux, uy, D, S, dSdt, cplx)
+    work = np.empty_like(g)
+    pc = p._c()
+    (lib.orc_z_run if cplx else lib.orc_run)(ctypes.byref(pc), _ptr(g), int(nsteps), _ptr(ux), _ptr(uy),
+                                             _ptr(D), _ptr(S), _ptr(dSdt), _ptr(work))
+    return g
+
+
+# ---- diagnostics: the definitions written out with correctly rounded sums ---------------------
+
+def mass(phi_field) -> float:
+    """sum_x phi (correctly rounded)."""
+    return math.fsum(np.asarray(phi_field, dtype=np.float64).ravel().tolist())
+
+
+def rms_error(phi_num, phi_ref) -> float:
+    """E_r = sqrt(sum |phi_num - phi_ref|^2 / (Nx Ny)), Sec. 3, Eq. (33)."""
+    d = (np.asarray(phi_num, np.float64) - np.asarray(phi_ref, np.float64)).ravel()
+    return math.sqrt(math.fsum((d * d).tolist()) / d.size)
+
+
+def l2_rel_error(phi_num, phi_ref) -> float:
+    d = (np.asarray(phi_num, np.float64) - np.asarray(phi_ref, np.float64)).ravel()
+    r = np.asarray(phi_ref, np.float64).ravel()
+    return math.sqrt(math.fsum((d * d).tolist()) / math.fsum((r * r).tolist()))
+
+
+def max_abs_error(phi_num, phi_ref) -> float:
+    return float(np.max(np.abs(np.asarray(phi_num, np.float64) - np.asarray(phi_ref, np.float64))))

@@ -1,0 +1,72 @@
+"""Mutation check of the oracle pins (CPU only).
+
+Each case plants one plausible mistake in a private copy of the oracle's C source (a dropped term,
+a wrong sign, factor or index, a transposed operand, a reversed streaming direction), builds that
+copy, and runs the pin suite against it in a subprocess.  Every mutant must fail at least one pin.
+The repository's oracle is never modified.
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PINS = os.path.join(ROOT, "tests", "test_oracle_pins.py")
+
+MUTANTS = [
+    ("drop third-order equilibrium", "+ s3 / (6.0 * cs2 * cs2 * cs2)", ""),
+    ("equilibrium second-order factor", "s2 / (2.0 * cs2 * cs2)", "s2 / (cs2 * cs2)"),
+    ("Hermite H2 without delta", "- cs2 * kd(a, b);\n}", ";\n}"),
+    ("Hermite H3 index", "ecomp(i, b, c) * kd(g, a)", "ecomp(i, b, c) * kd(a, b)"),
+    ("velocity sign", "{0, 0, 1, 0, -1, 1, 1, -1, -1}", "{0, 0, 1, 0, -1, -1, 1, -1, -1}"),
+    ("omega1 factor", "(1.0 - 1.0 / tau1) * W[i] * r1", "(1.0 - 0.5 / tau1) * W[i] * r1"),
+    ("omega2 from tau1", "(1.0 - 1.0 / tau2) * W[i] * r2", "(1.0 - 1.0 / tau1) * W[i] * r2"),
+    ("second-order neq factor", "* r2 / (2.0 * cs2 * cs2)", "* r2 / (cs2 * cs2)"),
+    ("tau1 from kappa", "*tau1 = 0.5 + kappa / (cs2 * dt);", "*tau1 = 0.5 + 2.0 * kappa / (cs2 * dt);"),
+    ("tau2 from Lambda", "*tau2 = 0.5 + lambda / (*tau1 - 0.5);", "*tau2 = 0.5 + lambda * (*tau1 - 0.5);"),
+    ("beta", "real beta = 1.0 - 1.0 / (2.0 * tau1);", "real beta = 1.0 - 1.0 / tau1;"),
+    ("aux sign", "real G = W[i] * eA / cs2 * beta;", "real G = -W[i] * eA / cs2 * beta;"),
+    ("aux transposed gradient", "u[a][nb[b][1]] - u[a][nb[b][0]]", "u[b][nb[a][1]] - u[b][nb[a][0]]"),
+    ("aux without phi", "A[a] = phi * s;", "A[a] = s;"),
+    ("aux difference spacing",
+     "real dbua = (u[a][nb[b][1]] - u[a][nb[b][0]]) / (2.0 * dx);",
+     "real dbua = (u[a][nb[b][1]] - u[a][nb[b][0]]) / dx;"),
+    ("aux neighbour", "nb[1][0] = (size_t)wrap(y - 1, ny) * nx + x;", "nb[1][0] = (size_t)wrap(y + 1, ny) * nx + x;"),
+    ("aux without dt", "real P = C[i] + dt * G +", "real P = C[i] + G +"),
+    ("flux-form sign", "s += dflux - un[a] * dmass;", "s += dflux + un[a] * dmass;"),
+    ("flux-form index", "real dmass = (phi_all[q] * u[b][q] - phi_all[m] * u[b][m])",
+     "real dmass = (phi_all[q] * u[a][q] - phi_all[m] * u[a][m])"),
+    ("source zeroth order", "real F = W[i] * src +", "real F ="),
+    ("source without beta", "+ beta * W[i] * eu / cs2 * src", "+ W[i] * eu / cs2 * src"),
+    ("source derivative half", "0.5 * dt * dt * dF", "dt * dt * dF"),
+    ("source derivative operand", "beta * W[i] * eu / cs2 * dsrc;", "beta * W[i] * eu / cs2 * src;"),
+    ("streaming direction", "wrap(y + EY[i], ny) * nx + wrap(x + EX[i], nx)",
+     "wrap(y - EY[i], ny) * nx + wrap(x - EX[i], nx)"),
+]
+
+_PLUGIN = '''
+import importlib.util, os, sys
+spec = importlib.util.spec_from_file_location("oracle", os.environ["MUTANT_ORACLE"])
+mod = importlib.util.module_from_spec(spec)
+sys.modules["oracle"] = mod
+spec.loader.exec_module(mod)
+'''
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(name, old, new, tmp_path):
+    with open(os.path.join(ROOT, "oracle", "lbm_oracle.c")) as fh:
+        src = fh.read()
+    assert src.count(old) == 1, f"mutation site for '{name}' must be unique"
+    mdir = tmp_path / "oracle"
+    shutil.copytree(os.path.join(ROOT, "oracle"), mdir,
+                    ignore=shutil.ignore_patterns("*.so", "*.o", "__pycache__"))
+    (mdir / "lbm_oracle.c").write_text(src.replace(old, new))
+    (tmp_path / "mutant_plugin.py").write_text(_PLUGIN)
+    env = dict(os.environ, MUTANT_ORACLE=str(mdir / "__init__.py"), PYTHONPATH=str(tmp_path))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "mutant_plugin", "-p", "no:cacheprovider",
+                        PINS], cwd=str(tmp_path), env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1, f"mutant '{name}' survived the pins:\n{r.stdout[-2000:]}"
+    assert "FAILED" in r.stdout
