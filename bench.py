@@ -1,0 +1,208 @@
+"""Throughput of the TRT-R D2Q9 step on one MI355X: MLUPS and fraction of the HBM roofline.
+
+A "step" is one time step of the whole hot path (one fused pull-stream-collide launch per step)
+over the full lattice.  Default workload: the rotating Gaussian pulse on a periodic 2048^2 lattice
+(c = dx/dt = 10, U0 = pi, D = 1e-3, Lambda = 1/4), warmup + timed steps = 3200 (t = 0.3125).
+The headline `value` is FP32 storage; FP64, FP64-storage/FP32-math and shifted FP16 storage are
+timed on the same workload and reported under "modes" with their errors against the closed form and
+against the FP64 path.
+
+    python bench.py [--gpus 1] [--steps 3000] [--warmup 200] [--n 2048] [--modes f32,f64,f64s_f32m,f16s]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "D2Q9 TRT-R MLUPS & % HBM roofline, FP32/FP16 vs FP64 at fixed L2 error"
+HBM_PEAK_GBPS = 8000.0
+STORE_BYTES = {"f64": 8, "f64s_f32m": 8, "f32": 4, "f16s": 2}
+FIELD_BYTES = {"f64": 8, "f64s_f32m": 4, "f32": 4, "f16s": 4}
+KERNEL_SRC = os.path.join(ROOT, "paper_2312_10316_amd", "csrc", "lbm_kernels.hip")
+
+
+def bytes_per_lup(mode: str, variable_D: bool) -> int:
+    """Algorithmic HBM bytes per lattice update: 9 populations read + 9 written, u (2 components),
+    D when it is a field."""
+    return 18 * STORE_BYTES[mode] + 2 * FIELD_BYTES[mode] + (FIELD_BYTES[mode] if variable_D else 0)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("lbm_kernels.hip", "lbm_device.h", "lbm_internal.h"):
+        with open(os.path.join(ROOT, "paper_2312_10316_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(mode: str, n: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    e = d.get("entries", {}).get(f"{mode}_{n}")
+    return None if e is None else e.get("bytes_per_launch")
+
+
+def run_mode(mode, n, steps, warmup, torch, W, lbm, Solver, graph=True):
+    cfg = W.PulseConfig(N=n, steps=warmup + steps)
+    f = W.rotating_pulse(cfg)
+    dev = {k: torch.from_numpy(f[k]).cuda() for k in ("phi0", "ux", "uy")}
+    p = lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, mode)
+    stream = torch.cuda.current_stream()
+    s = Solver([(p, dev)], stream=stream)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ref = torch.from_numpy(W.pulse_reference(cfg, f)).cuda()
+    st, phi = s.macros(ref=ref, want_phi=True)
+    s.close()
+    lups = float(n) * n * steps
+    return {
+        "mlups": lups / (ms * 1e-3) / 1e6,
+        "ms_per_step": ms / steps,
+        "E_r": st["rms_err"],
+        "L2_rel": st["l2_rel_err"],
+        "max_err": st["max_abs_err"],
+        "mass": st["mass"],
+        "nonfinite": st["nonfinite"],
+        "t_end": cfg.t_end,
+    }, phi
+
+
+def copy_bandwidth(torch, nbytes=2 << 30, reps=20):
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
+def cpu_baseline(n, budget_s=15.0):
+    """The FP64 oracle (single thread, as it stands) on a bounded sample of the same workload."""
+    import oracle as O
+    import workloads as W
+    cfg = W.PulseConfig(N=n, steps=3200)
+    f = W.rotating_pulse(cfg)
+    p = O.Problem(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, O.AUX_LOCAL)
+    g = O.init(p, f["phi0"], f["ux"], f["uy"])
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        g = O.step(p, g, f["ux"], f["uy"])
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 50:
+            break
+    return {"value": n * n * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{n}^2 rotating pulse, {steps} of 3200 steps, FP64 plain C oracle, 1 thread, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--modes", default="f32,f64,f64s_f32m,f16s")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads as W
+    from paper_2312_10316_amd import Solver, lbm
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    lbm.lib()  # the HIP library is required
+
+    modes = [m.strip() for m in args.modes.split(",") if m.strip()]
+    head = "f32" if "f32" in modes else modes[0]
+    results, phis = {}, {}
+    for m in modes:
+        results[m], phis[m] = run_mode(m, args.n, args.steps, args.warmup, torch, W, lbm, Solver)
+        print(f"# {m}: {results[m]['mlups']:.0f} MLUPS, {results[m]['ms_per_step']:.4f} ms/step, "
+              f"E_r {results[m]['E_r']:.4e}", file=sys.stderr, flush=True)
+    if "f64" in phis:
+        ref = phis["f64"]
+        for m in modes:
+            d = (phis[m] - ref).abs()
+            results[m]["max_err_vs_f64"] = float(d.max())
+            results[m]["l2_err_vs_f64"] = float(torch.sqrt((d * d).sum() / (ref * ref).sum()))
+            results[m]["speedup_vs_f64"] = results[m]["mlups"] / results["f64"]["mlups"]
+    for m in modes:
+        bpl = bytes_per_lup(m, False)
+        results[m]["bytes_per_lup"] = bpl
+        results[m]["hbm_gbps_algorithmic"] = results[m]["mlups"] * 1e6 * bpl / 1e9
+        results[m]["roofline_frac"] = results[m]["hbm_gbps_algorithmic"] / HBM_PEAK_GBPS
+
+    copy_gbps = copy_bandwidth(torch)
+    r = results[head]
+    n2 = float(args.n) ** 2
+    achieved = r["hbm_gbps_algorithmic"]
+    traffic = traffic_from_profile(head, args.n)
+    out = {
+        "metric": METRIC,
+        "value": round(r["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "f64": "f64", "f64s_f32m": "f64-store/f32", "f16s": "f16-store/f32"}[head],
+        "data": "synthetic",
+        "config": {"workload": f"rotating Gaussian pulse, periodic {args.n}^2, c=10, U0=pi, D=1e-3, Lambda=1/4, "
+                               f"{args.warmup}+{args.steps} steps", "N": args.n, "storage": head,
+                   "aux": "local (Eq. 16)"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": None if traffic is None else round(traffic * n2 / n2, 1),
+                     "bytes_per_lup": r["bytes_per_lup"], "lups_per_launch": int(n2),
+                     "copy_gbps_measured": round(copy_gbps, 1),
+                     "frac_of_copy": round(achieved / copy_gbps, 4)},
+        "modes": {m: {k: (round(v, 6) if isinstance(v, float) and abs(v) >= 1e-3 else v) for k, v in results[m].items()}
+                  for m in modes},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.n)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,155 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) TRT-R D2Q9 lattice Boltzmann library.
+ *
+ * The library advances the two-relaxation-time regularized (TRT-R) lattice Boltzmann model for the
+ * convection-diffusion equation with variable coefficients (Y. Yu, Z. Qin, H. Yuan, S. Shu,
+ * arXiv:2312.10316):
+ *
+ *     d_t phi + d_a(phi u_a) = d_a(kappa d_a phi) + S                     (Sec. 2.1, Eq. (1))
+ *
+ * on periodic D2Q9 lattices.  One step is the evolution equation of Sec. 2.2, Eq. (14): the TRT-R
+ * collision of Eq. (12) (third-order Hermite equilibrium, Eq. (6); Hermite-regularized first- and
+ * second-order non-equilibrium moments, Eqs. (8) and (13), relaxed with tau1 and tau2), the
+ * first-order discrete-velocity source of Eq. (3) with its time derivative, and the space-derivative
+ * auxiliary term of Sec. 2.3, Eq. (16), followed by streaming.  tau1 follows from kappa by
+ * kappa = (tau1 - 1/2) c_s^2 dt and tau2 from the magic parameter Lambda = (tau1 - 1/2)(tau2 - 1/2)
+ * (Sec. 2.4).  D2Q9: e_i in {(0,0), (+-c,0), (0,+-c), (+-c,+-c)}, c = dx/dt, c_s^2 = c^2/3 (Sec. 2.2).
+ *
+ * Conventions shared by every entry point:
+ *   - Memory: every pointer marked "device" is HIP device memory of the current device; pointers
+ *     marked "host" are host memory.  The caller owns every buffer it passes.  Fields are FP64,
+ *     row-major [ny][nx] (node (j, k) at index k*nx + j), with no padding.
+ *   - Streams: all work is enqueued on the stream given to lbm_init (a hipStream_t; NULL is the
+ *     default stream).  Calls are asynchronous unless stated otherwise.  Input fields must stay
+ *     valid until the stream has passed the call that reads them.
+ *   - Errors: every function returns an int status (LBM_OK = 0, or a negative LBM_E_* code);
+ *     nothing throws across the ABI.  Arguments are validated before anything is launched;
+ *     lbm_last_error() returns a message for the calling thread's most recent failure.
+ *   - Threads: a context is used by one host thread at a time.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1
+
+enum lbm_status {
+    LBM_OK = 0,
+    LBM_E_ARG = -1,        /* invalid argument; nothing was launched */
+    LBM_E_HIP = -2,        /* a HIP runtime call or kernel launch failed */
+    LBM_E_STATE = -3,      /* NULL or unusable context, instance index out of range */
+    LBM_E_NONFINITE = -4,  /* lbm_macros found a non-finite phi: the run blew up (the stability
+                              criterion of Sec. 3); the statistics are still written */
+    LBM_E_UNSUPPORTED = -5 /* valid request that this build does not implement */
+};
+
+/* Population storage.  F16S stores h = f16_rne((g_i - w_i phi_ref) * 2^scale_log2) and decodes
+ * g_i = h * 2^-scale_log2 + w_i phi_ref; collision arithmetic is then FP32. */
+enum lbm_store { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16S = 2 };
+/* Collision arithmetic.  LBM_MATH_F64 requires LBM_STORE_F64. */
+enum lbm_math { LBM_MATH_F64 = 0, LBM_MATH_F32 = 1 };
+/* Auxiliary term G_i (Sec. 2.3):
+ *   LOCAL: Eq. (16), phi u_b d_b u_a with phi at the node and d_b the central difference of u;
+ *   FLUX:  d_b(phi u_a u_b) - u_a d_b(phi u_b) with phi at the four axis neighbours (same time
+ *          level), central differences -- equal to Eq. (16) by the product rule;
+ *   NONE:  G_i = 0 (ablation). */
+enum lbm_aux { LBM_AUX_LOCAL = 0, LBM_AUX_FLUX = 1, LBM_AUX_NONE = 2 };
+
+/* One problem instance: the paper's problem statement on a periodic lattice. */
+typedef struct lbm_params {
+    int32_t nx, ny;       /* lattice size, each >= 3 */
+    double dx, dt;        /* lattice spacing and time step, finite and > 0 */
+    double lambda;        /* magic parameter Lambda > 0 */
+    double D_const;       /* kappa when lbm_fields.D is NULL (> 0); ignored otherwise */
+    int32_t store;        /* enum lbm_store */
+    int32_t math;         /* enum lbm_math */
+    int32_t aux;          /* enum lbm_aux */
+    int32_t scale_log2;   /* F16S only: 0..24 */
+    double phi_ref;       /* F16S only: background value removed before encoding */
+} lbm_params;
+
+/* Fields of one instance (device, FP64, [ny][nx]).  u is in physical units; D > 0 everywhere.
+ * They are read during lbm_init only (copied to the library's own layout). */
+typedef struct lbm_fields {
+    const double *phi0;   /* initial phi, required */
+    const double *ux;     /* velocity x-component, required */
+    const double *uy;     /* velocity y-component, required */
+    const double *D;      /* diffusion coefficient kappa(x), or NULL for D_const */
+} lbm_fields;
+
+/* Diagnostics of one instance (host struct filled by lbm_macros). */
+typedef struct lbm_stats {
+    double mass;          /* sum_x phi, FP64 compensated summation */
+    double rms_err;       /* E_r = sqrt(sum (phi - ref)^2 / (nx ny)) (Sec. 3, Eq. (33)); 0 without ref */
+    double l2_rel_err;    /* ||phi - ref||_2 / ||ref||_2; 0 without ref */
+    double max_abs_err;   /* max |phi - ref|; 0 without ref */
+    double max_abs_phi;   /* max |phi| over finite values */
+    int64_t nonfinite;    /* number of nodes whose phi is NaN or infinite */
+    int64_t step;         /* time steps taken since lbm_init (or set by lbm_state_load) */
+} lbm_stats;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Bytes of device workspace that lbm_init needs for n_inst instances (p: host array [n_inst]).
+ * Returns LBM_E_ARG for invalid parameters. */
+int lbm_workspace_size(int32_t n_inst, const lbm_params *p, size_t *bytes);
+
+/* Creates a context for n_inst instances (p, f: host arrays [n_inst]; the pointers inside f are
+ * device pointers) and writes the initial state g_i = g_eq_i(phi0, u) (Sec. 3 set-up).
+ * workspace: device buffer of at least lbm_workspace_size() bytes, 256-byte aligned, borrowed until
+ * lbm_free; or NULL, in which case the library allocates (and later frees) its own.
+ * stream: hipStream_t for all later work, or NULL.  Synchronizes the stream once (to check the
+ * F16S range: LBM_E_ARG if |g_eq - w_i phi_ref| * 2^scale_log2 would overflow FP16).
+ * On success *ctx is set; on failure *ctx is NULL and nothing is owned. */
+int lbm_init(lbm_ctx **ctx, int32_t n_inst, const lbm_params *p, const lbm_fields *f,
+             void *workspace, size_t workspace_bytes, void *stream);
+
+/* Advances every instance by nsteps >= 0 steps of Eq. (14).  Asynchronous.
+ * ux, uy: host arrays [n_inst] of device FP64 [ny][nx] velocity fields that replace u from this
+ *         call on, or NULL (both) to keep the current u.
+ * S, dSdt: host arrays [n_inst] of device FP64 [ny][nx] source S and its time derivative, held
+ *         constant over this call's steps, or NULL (both) for no source.  An entry may be NULL for an
+ *         instance without a source; dSdt entries may be NULL (zero derivative). */
+int lbm_step(lbm_ctx *ctx, int32_t nsteps, const double *const *ux, const double *const *uy,
+             const double *const *S, const double *const *dSdt);
+
+/* Diagnostics of instance inst: phi = sum_i g_i at the current time.  phi_out (device FP64
+ * [ny][nx], nullable) receives phi; ref (device FP64 [ny][nx], nullable) is the field the error
+ * statistics are taken against; out (host) receives the statistics.  Synchronizes the stream.
+ * Returns LBM_E_NONFINITE if any phi is NaN or infinite (out is still filled). */
+int lbm_macros(lbm_ctx *ctx, int32_t inst, double *phi_out, const double *ref, lbm_stats *out);
+
+/* Pre-collision populations g_i(x, t) of instance inst, decoded to FP64, into g_out (device FP64
+ * [9][ny][nx], velocity order 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1)
+ * 8:(1,-1)).  Asynchronous. */
+int lbm_populations(lbm_ctx *ctx, int32_t inst, double *g_out);
+
+/* Checkpoint of instance inst: the raw population state in the library's storage format.
+ * lbm_state_bytes gives its size; save copies it to dst (device), load restores it from src
+ * (device) and sets the step counter.  Asynchronous.  A run resumed from a checkpoint is bitwise
+ * identical to the uninterrupted run. */
+int lbm_state_bytes(lbm_ctx *ctx, int32_t inst, size_t *bytes);
+int lbm_state_save(lbm_ctx *ctx, int32_t inst, void *dst);
+int lbm_state_load(lbm_ctx *ctx, int32_t inst, const void *src, int64_t step);
+
+/* Synchronizes the context's stream and releases everything the library allocated (never caller
+ * memory).  NULL is accepted. */
+int lbm_free(lbm_ctx *ctx);
+
+/* Message for the calling thread's most recent failed call ("" if none).  Never NULL. */
+const char *lbm_last_error(void);
+
+/* LBM_ABI_VERSION of the loaded library. */
+int lbm_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

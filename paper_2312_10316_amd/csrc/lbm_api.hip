@@ -1,0 +1,419 @@
+// lbm_api.hip -- C ABI of the TRT-R D2Q9 library (declared in include/lbm.h).
+//
+// Host side only: argument validation, the workspace layout, and the order of kernel launches on
+// the caller's stream.  Every arithmetic step of the method runs in the kernels of lbm_kernels.hip.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(LBM_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int mode_of(const lbm_params &p)
+{
+    if (p.store == LBM_STORE_F64) return p.math == LBM_MATH_F64 ? MODE_F64_F64 : MODE_F64_F32;
+    if (p.store == LBM_STORE_F32) return MODE_F32_F32;
+    return MODE_F16S_F32;
+}
+size_t store_bytes(int mode) { return mode == MODE_F32_F32 ? 4 : (mode == MODE_F16S_F32 ? 2 : 8); }
+size_t math_bytes(int mode) { return mode == MODE_F64_F64 ? 8 : 4; }
+
+Layout layout_of(const lbm_params &p)
+{
+    Layout L;
+    L.nx = p.nx;
+    L.ny = p.ny;
+    L.pitch = (int64_t)align_up((size_t)p.nx, 64);
+    L.plane = L.pitch * p.ny;
+    return L;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int validate(const lbm_params &p, int k)
+{
+    if (p.nx < 3 || p.ny < 3) return fail(LBM_E_ARG, "instance %d: nx=%d, ny=%d must be >= 3", k, p.nx, p.ny);
+    if ((int64_t)p.nx * p.ny > ((int64_t)1 << 31))
+        return fail(LBM_E_ARG, "instance %d: nx*ny exceeds 2^31 nodes", k);
+    if (!finite_pos(p.dx) || !finite_pos(p.dt)) return fail(LBM_E_ARG, "instance %d: dx and dt must be finite and > 0", k);
+    if (!finite_pos(p.lambda)) return fail(LBM_E_ARG, "instance %d: lambda must be finite and > 0", k);
+    if (p.store < LBM_STORE_F64 || p.store > LBM_STORE_F16S) return fail(LBM_E_ARG, "instance %d: unknown store %d", k, p.store);
+    if (p.math != LBM_MATH_F64 && p.math != LBM_MATH_F32) return fail(LBM_E_ARG, "instance %d: unknown math %d", k, p.math);
+    if (p.math == LBM_MATH_F64 && p.store != LBM_STORE_F64)
+        return fail(LBM_E_ARG, "instance %d: FP64 math needs FP64 storage", k);
+    if (p.aux < LBM_AUX_LOCAL || p.aux > LBM_AUX_NONE) return fail(LBM_E_ARG, "instance %d: unknown aux %d", k, p.aux);
+    if (p.store == LBM_STORE_F16S) {
+        if (p.scale_log2 < 0 || p.scale_log2 > 24)
+            return fail(LBM_E_ARG, "instance %d: scale_log2=%d outside 0..24", k, p.scale_log2);
+        if (!std::isfinite(p.phi_ref)) return fail(LBM_E_ARG, "instance %d: phi_ref is not finite", k);
+    }
+    return LBM_OK;
+}
+
+struct Instance {
+    lbm_params p;
+    int mode;
+    Layout L;
+    char *buf[2];
+    void *ux, *uy, *k, *s;
+    bool has_D;
+    bool has_src;
+    int cur;
+    int64_t step;
+    F16Params f16;
+};
+
+// Per instance: 2 population buffers (9 planes each) and 4 math-type fields (ux, uy, k, s).
+size_t pops_bytes(const lbm_params &p) { return align_up((size_t)layout_of(p).plane * 9 * store_bytes(mode_of(p)), kAlign); }
+size_t field_bytes(const lbm_params &p) { return align_up((size_t)layout_of(p).plane * math_bytes(mode_of(p)), kAlign); }
+size_t instance_bytes(const lbm_params &p) { return 2 * pops_bytes(p) + 4 * field_bytes(p); }
+
+// Shared scratch: macro partials, the macro result, and a flag word.
+constexpr size_t kPartialBytes = (size_t)kMacroBlocks * kMacroPartialDoubles * sizeof(double);
+constexpr size_t kScratchBytes = kPartialBytes + 256 + 256;
+
+F16Params f16_of(const lbm_params &p)
+{
+    F16Params f{};
+    if (p.store == LBM_STORE_F16S) {
+        f.scale = std::ldexp(1.0f, p.scale_log2);
+        f.inv_scale = std::ldexp(1.0f, -p.scale_log2);
+        for (int i = 0; i < 9; ++i) f.wref[i] = (float)(kW[i] * p.phi_ref);
+    } else {
+        f.scale = f.inv_scale = 1.0f;
+    }
+    return f;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    std::vector<Instance> inst;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    bool owns_ws = false;
+    double *partials = nullptr;
+    double *result = nullptr;
+    int *flag = nullptr;
+};
+
+namespace {
+
+int prep_field(lbm_ctx *c, Instance &in, const double *a, const double *b, double ca, double cb, void *out,
+               int check_positive)
+{
+    PrepArgs pa;
+    pa.a = a;
+    pa.b = b;
+    pa.out = out;
+    pa.L = in.L;
+    pa.ca = ca;
+    pa.cb = cb;
+    pa.flag = c->flag + 1;
+    pa.check_positive = check_positive;
+    hipError_t e = launch_prep(in.mode, pa, c->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "prep kernel launch");
+}
+
+int set_velocity(lbm_ctx *c, Instance &in, const double *ux, const double *uy)
+{
+    const double s = in.p.dt / in.p.dx;  // lattice units: u dt / dx
+    int rc = prep_field(c, in, ux, nullptr, s, 0.0, in.ux, 0);
+    if (rc == LBM_OK) rc = prep_field(c, in, uy, nullptr, s, 0.0, in.uy, 0);
+    return rc;
+}
+
+bool check_inst(lbm_ctx *c, int32_t inst)
+{
+    return c && inst >= 0 && inst < (int32_t)c->inst.size();
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_abi_version(void) { return LBM_ABI_VERSION; }
+
+const char *lbm_last_error(void) { return g_err; }
+
+int lbm_workspace_size(int32_t n_inst, const lbm_params *p, size_t *bytes)
+{
+    g_err[0] = 0;
+    if (n_inst < 1 || !p || !bytes) return fail(LBM_E_ARG, "lbm_workspace_size: n_inst >= 1, p and bytes required");
+    size_t total = align_up(kScratchBytes, kAlign);
+    for (int k = 0; k < n_inst; ++k) {
+        int rc = validate(p[k], k);
+        if (rc) return rc;
+        total += instance_bytes(p[k]);
+    }
+    *bytes = total;
+    return LBM_OK;
+}
+
+int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_fields *f, void *workspace,
+             size_t workspace_bytes, void *stream)
+{
+    g_err[0] = 0;
+    if (!out) return fail(LBM_E_ARG, "lbm_init: ctx pointer is NULL");
+    *out = nullptr;
+    if (!f) return fail(LBM_E_ARG, "lbm_init: fields are NULL");
+    size_t need = 0;
+    int rc = lbm_workspace_size(n_inst, p, &need);
+    if (rc) return rc;
+    for (int k = 0; k < n_inst; ++k) {
+        if (!f[k].phi0 || !f[k].ux || !f[k].uy) return fail(LBM_E_ARG, "instance %d: phi0, ux and uy are required", k);
+        if (!f[k].D && !finite_pos(p[k].D_const))
+            return fail(LBM_E_ARG, "instance %d: D_const must be finite and > 0 when D is NULL", k);
+    }
+    if (workspace) {
+        if (workspace_bytes < need)
+            return fail(LBM_E_ARG, "lbm_init: workspace of %zu bytes, %zu needed", workspace_bytes, need);
+        if ((uintptr_t)workspace % kAlign) return fail(LBM_E_ARG, "lbm_init: workspace not 256-byte aligned");
+    }
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(LBM_E_ARG, "lbm_init: out of host memory");
+    c->stream = static_cast<hipStream_t>(stream);
+    if (workspace) {
+        c->ws = static_cast<char *>(workspace);
+    } else {
+        hipError_t e = hipMalloc(&c->ws, need);
+        if (e != hipSuccess) {
+            delete c;
+            return hip_fail(e, "lbm_init: hipMalloc of the workspace");
+        }
+        c->owns_ws = true;
+    }
+    char *w = c->ws;
+    c->partials = reinterpret_cast<double *>(w);
+    c->result = reinterpret_cast<double *>(w + kPartialBytes);
+    c->flag = reinterpret_cast<int *>(w + kPartialBytes + 256);
+    w += align_up(kScratchBytes, kAlign);
+    c->inst.resize(n_inst);
+    for (int k = 0; k < n_inst; ++k) {
+        Instance &in = c->inst[k];
+        in.p = p[k];
+        in.mode = mode_of(p[k]);
+        in.L = layout_of(p[k]);
+        const size_t pb = pops_bytes(p[k]), fb = field_bytes(p[k]);
+        in.buf[0] = w;
+        in.buf[1] = w + pb;
+        w += 2 * pb;
+        in.ux = w;
+        in.uy = w + fb;
+        in.k = w + 2 * fb;
+        in.s = w + 3 * fb;
+        w += 4 * fb;
+        in.has_D = f[k].D != nullptr;
+        in.has_src = false;
+        in.cur = 0;
+        in.step = 0;
+        in.f16 = f16_of(p[k]);
+    }
+    hipError_t e = hipMemsetAsync(c->flag, 0, 2 * sizeof(int), c->stream);
+    if (e != hipSuccess) {
+        lbm_free(c);
+        return hip_fail(e, "lbm_init: clearing the flag");
+    }
+    for (int k = 0; k < n_inst && rc == LBM_OK; ++k) {
+        Instance &in = c->inst[k];
+        rc = set_velocity(c, in, f[k].ux, f[k].uy);
+        if (rc == LBM_OK && in.has_D)  // k = tau1 - 1/2 = kappa / (cs^2 dt) = 3 kappa dt / dx^2
+            rc = prep_field(c, in, f[k].D, nullptr, 3.0 * in.p.dt / (in.p.dx * in.p.dx), 0.0, in.k, 1);
+        if (rc == LBM_OK) {
+            InitArgs ia;
+            ia.phi0 = f[k].phi0;
+            ia.ux = in.ux;
+            ia.uy = in.uy;
+            ia.dst = in.buf[0];
+            ia.L = in.L;
+            ia.f16 = in.f16;
+            ia.range_flag = c->flag;
+            e = launch_init(in.mode, ia, c->stream);
+            if (e != hipSuccess) rc = hip_fail(e, "init kernel launch");
+        }
+    }
+    int flag[2] = {0, 0};
+    if (rc == LBM_OK) {
+        e = hipMemcpyAsync(flag, c->flag, sizeof flag, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) rc = hip_fail(e, "lbm_init: synchronizing");
+    }
+    if (rc == LBM_OK && flag[0])
+        rc = fail(LBM_E_ARG, "lbm_init: an F16S population does not fit FP16 at this scale_log2");
+    if (rc == LBM_OK && flag[1]) rc = fail(LBM_E_ARG, "lbm_init: D field has a value that is not finite and > 0");
+    if (rc != LBM_OK) {
+        char keep[512];
+        std::memcpy(keep, g_err, sizeof keep);
+        lbm_free(c);
+        std::memcpy(g_err, keep, sizeof keep);
+        return rc;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *c, int32_t nsteps, const double *const *ux, const double *const *uy, const double *const *S,
+             const double *const *dSdt)
+{
+    g_err[0] = 0;
+    if (!c) return fail(LBM_E_STATE, "lbm_step: NULL context");
+    if (nsteps < 0) return fail(LBM_E_ARG, "lbm_step: nsteps < 0");
+    if ((ux == nullptr) != (uy == nullptr)) return fail(LBM_E_ARG, "lbm_step: give both ux and uy or neither");
+    if (!S && dSdt) return fail(LBM_E_ARG, "lbm_step: dSdt without S");
+    const int n = (int)c->inst.size();
+    if (ux)
+        for (int k = 0; k < n; ++k)
+            if (!ux[k] || !uy[k]) return fail(LBM_E_ARG, "lbm_step: instance %d: NULL velocity entry", k);
+    int rc = LBM_OK;
+    for (int k = 0; k < n && rc == LBM_OK; ++k) {
+        Instance &in = c->inst[k];
+        if (ux) rc = set_velocity(c, in, ux[k], uy[k]);
+        in.has_src = S && S[k];
+        if (rc == LBM_OK && in.has_src)  // s = dt S + dt^2/2 dS/dt (Eq. (14), source terms)
+            rc = prep_field(c, in, S[k], dSdt ? dSdt[k] : nullptr, in.p.dt, 0.5 * in.p.dt * in.p.dt, in.s, 0);
+    }
+    if (rc) return rc;
+    for (int t = 0; t < nsteps; ++t) {
+        for (int k = 0; k < n; ++k) {
+            Instance &in = c->inst[k];
+            StepArgs a;
+            a.src = in.buf[in.cur];
+            a.dst = in.buf[in.cur ^ 1];
+            a.ux = in.ux;
+            a.uy = in.uy;
+            a.k = in.has_D ? in.k : nullptr;
+            a.s = in.has_src ? in.s : nullptr;
+            a.L = in.L;
+            a.rows = 8;
+            a.k_const = 3.0 * in.p.D_const * in.p.dt / (in.p.dx * in.p.dx);
+            a.lambda = in.p.lambda;
+            a.f16 = in.f16;
+            hipError_t e = launch_step(in.mode, in.p.aux, a, c->stream);
+            if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+            in.cur ^= 1;
+            in.step += 1;
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_macros(lbm_ctx *c, int32_t inst, double *phi_out, const double *ref, lbm_stats *out)
+{
+    g_err[0] = 0;
+    if (!check_inst(c, inst)) return fail(LBM_E_STATE, "lbm_macros: bad context or instance %d", inst);
+    if (!out) return fail(LBM_E_ARG, "lbm_macros: out is NULL");
+    Instance &in = c->inst[inst];
+    MacroArgs a;
+    a.src = in.buf[in.cur];
+    a.ref = ref;
+    a.phi_out = phi_out;
+    a.L = in.L;
+    a.f16 = in.f16;
+    a.partials = c->partials;
+    hipError_t e = launch_macros(in.mode, a, c->result, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "macros kernel launch");
+    double r[6];
+    e = hipMemcpyAsync(r, c->result, sizeof r, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "lbm_macros: reading the result");
+    const double nn = (double)in.L.nx * in.L.ny;
+    out->mass = r[0];
+    out->rms_err = ref ? std::sqrt(r[1] / nn) : 0.0;
+    out->l2_rel_err = (ref && r[2] > 0) ? std::sqrt(r[1] / r[2]) : 0.0;
+    out->max_abs_err = ref ? r[3] : 0.0;
+    out->max_abs_phi = r[4];
+    out->nonfinite = (int64_t)r[5];
+    out->step = in.step;
+    if (out->nonfinite > 0) return fail(LBM_E_NONFINITE, "instance %d: %lld non-finite phi values (blow-up)", inst,
+                                        (long long)out->nonfinite);
+    return LBM_OK;
+}
+
+int lbm_populations(lbm_ctx *c, int32_t inst, double *g_out)
+{
+    g_err[0] = 0;
+    if (!check_inst(c, inst)) return fail(LBM_E_STATE, "lbm_populations: bad context or instance %d", inst);
+    if (!g_out) return fail(LBM_E_ARG, "lbm_populations: g_out is NULL");
+    Instance &in = c->inst[inst];
+    PopArgs a;
+    a.src = in.buf[in.cur];
+    a.out = g_out;
+    a.L = in.L;
+    a.f16 = in.f16;
+    hipError_t e = launch_populations(in.mode, a, c->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "populations kernel launch");
+}
+
+int lbm_state_bytes(lbm_ctx *c, int32_t inst, size_t *bytes)
+{
+    g_err[0] = 0;
+    if (!check_inst(c, inst)) return fail(LBM_E_STATE, "lbm_state_bytes: bad context or instance %d", inst);
+    if (!bytes) return fail(LBM_E_ARG, "lbm_state_bytes: bytes is NULL");
+    *bytes = pops_bytes(c->inst[inst].p);
+    return LBM_OK;
+}
+
+int lbm_state_save(lbm_ctx *c, int32_t inst, void *dst)
+{
+    g_err[0] = 0;
+    if (!check_inst(c, inst)) return fail(LBM_E_STATE, "lbm_state_save: bad context or instance %d", inst);
+    if (!dst) return fail(LBM_E_ARG, "lbm_state_save: dst is NULL");
+    Instance &in = c->inst[inst];
+    hipError_t e = hipMemcpyAsync(dst, in.buf[in.cur], pops_bytes(in.p), hipMemcpyDeviceToDevice, c->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_state_save");
+}
+
+int lbm_state_load(lbm_ctx *c, int32_t inst, const void *src, int64_t step)
+{
+    g_err[0] = 0;
+    if (!check_inst(c, inst)) return fail(LBM_E_STATE, "lbm_state_load: bad context or instance %d", inst);
+    if (!src) return fail(LBM_E_ARG, "lbm_state_load: src is NULL");
+    if (step < 0) return fail(LBM_E_ARG, "lbm_state_load: step < 0");
+    Instance &in = c->inst[inst];
+    hipError_t e = hipMemcpyAsync(in.buf[in.cur], src, pops_bytes(in.p), hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "lbm_state_load");
+    in.step = step;
+    return LBM_OK;
+}
+
+int lbm_free(lbm_ctx *c)
+{
+    if (!c) return LBM_OK;
+    int rc = LBM_OK;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) rc = hip_fail(e, "lbm_free: synchronizing");
+    if (c->owns_ws && c->ws) {
+        e = hipFree(c->ws);
+        if (e != hipSuccess && rc == LBM_OK) rc = hip_fail(e, "lbm_free: hipFree");
+    }
+    delete c;
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,188 @@
+// lbm_device.h -- device-side lattice algebra of the TRT-R D2Q9 step (gfx950).
+//
+// Everything here works in lattice units: velocities are e_i / c (components in {-1, 0, 1}), u is
+// stored as u dt / dx, c_s^2 = 1/3, and the relaxation is parameterised by k = tau1 - 1/2 =
+// kappa / (c_s^2 dt) (Sec. 2.4).  In these units one step of Sec. 2.2, Eq. (14) is
+//
+//   P_i = w_i [ a0 + 3 e_i . a1 + 9/2 (e_ia e_ib - delta_ab / 3) a2_ab
+//               + 27/2 (H_i,xxy a3_xxy + H_i,xyy a3_xyy) ]
+//
+// with the post-collision Hermite coefficients
+//   a0    = phi + s                       (s = dt S + dt^2/2 dS/dt, Eq. (3) and its derivative)
+//   a1    = phi u + w1 B + beta (A + u s)  (B = j - phi u: first-order neq moment, Eq. (8);
+//                                           A = phi u.grad u: auxiliary term, Eq. (16))
+//   a2_ab = phi u_a u_b + w2 N_ab         (N_ab = Pi_ab - phi delta_ab/3 - phi u_a u_b, Eq. (13))
+//   a3    = phi u_x^2 u_y, phi u_x u_y^2  (third-order equilibrium; the only non-zero third-order
+//                                           Hermite components on D2Q9, Eq. (6))
+// where w1 = 1 - 1/tau1, w2 = 1 - 1/tau2 and beta = 1 - 1/(2 tau1).  This is Eq. (12) written in
+// moment space: Hermite orthogonality turns the projections of Eqs. (8) and (13) into the raw
+// moments j and Pi, and the relaxed neq content above second order is zero.  Opposite velocities
+// share the even part and flip the odd part, which is the symmetric/antisymmetric (TRT) split.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// D2Q9 velocity order of the population planes.
+constexpr int kEx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int kEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr double kW[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                          1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+template <class M>
+struct Relax {
+    M w1, w2, beta;
+};
+
+// k = tau1 - 1/2 (lattice diffusivity), lambda = magic parameter.
+template <class M>
+__device__ __forceinline__ Relax<M> relax_from_k(M k, M lambda)
+{
+    const M tau1 = M(0.5) + k;
+    const M tau2 = M(0.5) + lambda / k;
+    Relax<M> r;
+    r.w1 = M(1) - M(1) / tau1;
+    r.w2 = M(1) - M(1) / tau2;
+    r.beta = M(1) - M(0.5) / tau1;
+    return r;
+}
+
+// P_i from the Hermite coefficients (see the header comment).
+template <class M>
+__device__ __forceinline__ void reconstruct(M a0, M a1x, M a1y, M a2xx, M a2yy, M a2xy, M a3xxy,
+                                            M a3xyy, M (&P)[9])
+{
+    const M w0 = M(4.0 / 9.0), wa = M(1.0 / 9.0), wd = M(1.0 / 36.0);
+    P[0] = w0 * (a0 - M(1.5) * (a2xx + a2yy));
+    const M ex = a0 + M(3) * a2xx - M(1.5) * a2yy;
+    const M ox = M(3) * a1x - M(4.5) * a3xyy;
+    P[1] = wa * (ex + ox);
+    P[3] = wa * (ex - ox);
+    const M ey = a0 + M(3) * a2yy - M(1.5) * a2xx;
+    const M oy = M(3) * a1y - M(4.5) * a3xxy;
+    P[2] = wa * (ey + oy);
+    P[4] = wa * (ey - oy);
+    const M ed = a0 + M(3) * (a2xx + a2yy);
+    const M e57 = ed + M(9) * a2xy;
+    const M o57 = M(3) * (a1x + a1y) + M(9) * (a3xxy + a3xyy);
+    P[5] = wd * (e57 + o57);
+    P[7] = wd * (e57 - o57);
+    const M e68 = ed - M(9) * a2xy;
+    const M o68 = M(3) * (a1y - a1x) + M(9) * (a3xxy - a3xyy);
+    P[6] = wd * (e68 + o68);
+    P[8] = wd * (e68 - o68);
+}
+
+// Third-order Hermite equilibrium (Eq. (6)) in lattice units.
+template <class M>
+__device__ __forceinline__ void equilibrium(M phi, M ux, M uy, M (&P)[9])
+{
+    const M pux = phi * ux, puy = phi * uy;
+    reconstruct<M>(phi, pux, puy, pux * ux, puy * uy, pux * uy, pux * ux * uy, pux * uy * uy, P);
+}
+
+// TRT-R collision + source + auxiliary term for one node (Eq. (14) without the streaming).
+//   g: pre-collision populations; (ux, uy): lattice velocity; r: relaxation; (Ax, Ay): auxiliary
+//   vector A (already multiplied by phi); s: dt S + dt^2/2 dS/dt (0 without a source).
+template <class M>
+__device__ __forceinline__ void collide(const M (&g)[9], M ux, M uy, const Relax<M> &r, M Ax, M Ay,
+                                        M s, M (&P)[9])
+{
+    const M phi = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
+    const M jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
+    const M jy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
+    const M sd = (g[5] + g[6]) + (g[7] + g[8]);
+    const M pxx = g[1] + g[3] + sd;
+    const M pyy = g[2] + g[4] + sd;
+    const M pxy = (g[5] + g[7]) - (g[6] + g[8]);
+    const M pux = phi * ux, puy = phi * uy;
+    const M euxx = pux * ux, euyy = puy * uy, euxy = pux * uy;  // phi u_a u_b
+    const M third = phi * M(1.0 / 3.0);
+    const M a1x = pux + r.w1 * (jx - pux) + r.beta * (Ax + ux * s);
+    const M a1y = puy + r.w1 * (jy - puy) + r.beta * (Ay + uy * s);
+    const M a2xx = euxx + r.w2 * (pxx - third - euxx);
+    const M a2yy = euyy + r.w2 * (pyy - third - euyy);
+    const M a2xy = euxy + r.w2 * (pxy - euxy);
+    reconstruct<M>(phi + s, a1x, a1y, a2xx, a2yy, a2xy, euxx * uy, euxy * uy, P);
+}
+
+// ---- population storage codecs --------------------------------------------------------------
+
+struct StoreF64 {
+    using T = double;
+};
+struct StoreF32 {
+    using T = float;
+};
+struct StoreF16S {
+    using T = _Float16;
+};
+
+// F16S codec constants: h = f16((g - w_i phi_ref) * 2^k); g = h * 2^-k + w_i phi_ref.
+struct F16Params {
+    float scale, inv_scale;
+    float wref[9];
+};
+
+template <class St, class M>
+struct Codec;
+
+template <>
+struct Codec<StoreF64, double> {
+    __device__ __forceinline__ static double dec(double v, int, const F16Params &) { return v; }
+    __device__ __forceinline__ static double enc(double v, int, const F16Params &) { return v; }
+};
+template <>
+struct Codec<StoreF64, float> {
+    __device__ __forceinline__ static float dec(double v, int, const F16Params &) { return (float)v; }
+    __device__ __forceinline__ static double enc(float v, int, const F16Params &) { return (double)v; }
+};
+template <>
+struct Codec<StoreF32, float> {
+    __device__ __forceinline__ static float dec(float v, int, const F16Params &) { return v; }
+    __device__ __forceinline__ static float enc(float v, int, const F16Params &) { return v; }
+};
+template <>
+struct Codec<StoreF16S, float> {
+    __device__ __forceinline__ static float dec(_Float16 v, int i, const F16Params &c)
+    {
+        return (float)v * c.inv_scale + c.wref[i];
+    }
+    __device__ __forceinline__ static _Float16 enc(float v, int i, const F16Params &c)
+    {
+        return (_Float16)((v - c.wref[i]) * c.scale);  // v_cvt_f16_f32, round to nearest even
+    }
+};
+
+// ---- compensated FP64 accumulation (Neumaier / TwoSum) ------------------------------------
+
+struct CSum {
+    double s, c;
+};
+
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
+{
+    s = a + b;
+    const double bp = s - a;
+    e = (a - (s - bp)) + (b - bp);
+}
+__device__ __forceinline__ void csum_add(CSum &x, double v)
+{
+    double s, e;
+    two_sum(x.s, v, s, e);
+    x.s = s;
+    x.c += e;
+}
+__device__ __forceinline__ CSum csum_merge(CSum a, CSum b)
+{
+    double s, e;
+    two_sum(a.s, b.s, s, e);
+    CSum r;
+    r.s = s;
+    r.c = a.c + b.c + e;
+    return r;
+}
+
+}  // namespace lbm

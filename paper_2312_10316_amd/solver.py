@@ -1,0 +1,66 @@
+"""Convenience wrapper over the C ABI: owns a torch workspace and one library context."""
+from __future__ import annotations
+
+from typing import Optional, Sequence
+
+import torch
+
+from . import lbm as L
+
+
+class Solver:
+    """One or more periodic instances advanced together on the current (or given) stream.
+
+    instances: sequence of (params, fields) pairs; params from ``lbm.make_params``; fields a dict of
+    device FP64 tensors ``phi0``, ``ux``, ``uy`` and optional ``D``, each [ny, nx].
+    """
+
+    def __init__(self, instances: Sequence, stream: Optional[torch.cuda.Stream] = None):
+        self.params = [p for p, _ in instances]
+        self.stream = stream or torch.cuda.current_stream()
+        nbytes = L.lbm_workspace_size(self.params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.ctx = L.lbm_init(self.params, [f for _, f in instances], self.workspace, self.stream)
+        self._keep = None
+
+    def step(self, nsteps: int, ux=None, uy=None, S=None, dSdt=None) -> None:
+        self._keep = (ux, uy, S, dSdt)  # inputs stay alive until the next call
+        L.lbm_step(self.ctx, nsteps, ux, uy, S, dSdt)
+
+    def macros(self, inst: int = 0, ref: Optional[torch.Tensor] = None, want_phi: bool = False,
+               raise_nonfinite: bool = True):
+        p = self.params[inst]
+        phi = torch.empty((p.ny, p.nx), dtype=torch.float64, device="cuda") if want_phi else None
+        stats = L.lbm_macros(self.ctx, inst, phi, ref, raise_nonfinite)
+        return (stats, phi) if want_phi else stats
+
+    def populations(self, inst: int = 0) -> torch.Tensor:
+        p = self.params[inst]
+        out = torch.empty((9, p.ny, p.nx), dtype=torch.float64, device="cuda")
+        L.lbm_populations(self.ctx, inst, out)
+        return out
+
+    def state_save(self, inst: int = 0) -> torch.Tensor:
+        buf = torch.empty(L.lbm_state_bytes(self.ctx, inst), dtype=torch.uint8, device="cuda")
+        L.lbm_state_save(self.ctx, inst, buf)
+        return buf
+
+    def state_load(self, buf: torch.Tensor, step: int, inst: int = 0) -> None:
+        L.lbm_state_load(self.ctx, inst, buf, step)
+
+    def close(self) -> None:
+        if self.ctx is not None:
+            L.lbm_free(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,94 @@
+"""The C-ABI library loads and exports what include/lbm.h declares; host-side validation (CPU only,
+no HIP compute call is made)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2312_10316_amd import lbm as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(lbm_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("lbm_init", "lbm_step", "lbm_macros", "lbm_free"):
+        assert required in names
+    assert set(names) == set(L.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r" T (lbm_\w+)$", out, flags=re.M))
+    assert set(declared_functions()) <= exported
+    assert L.lbm_abi_version() == 1
+
+
+def test_struct_layout_matches_header(tmp_path):
+    prog = tmp_path / "layout.c"
+    prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lbm.h"\n'
+                    'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(lbm_params), '
+                    'offsetof(lbm_params, phi_ref), offsetof(lbm_params, store), sizeof(lbm_fields), '
+                    'sizeof(lbm_stats), offsetof(lbm_stats, nonfinite)); return 0;}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", f"-I{os.path.dirname(HEADER)}", str(prog), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert vals == [ctypes.sizeof(L.lbm_params), L.lbm_params.phi_ref.offset, L.lbm_params.store.offset,
+                    ctypes.sizeof(L.lbm_fields), ctypes.sizeof(L.lbm_stats), L.lbm_stats.nonfinite.offset]
+
+
+def _p(**kw):
+    base = dict(nx=64, ny=64, dx=1 / 32, dt=1 / 320, lam=0.25, D_const=1e-3, mode="f64")
+    base.update(kw)
+    return L.make_params(**base)
+
+
+def test_workspace_size_scales_with_storage():
+    b64 = L.lbm_workspace_size([_p(nx=1024, ny=1024)])
+    b32 = L.lbm_workspace_size([_p(nx=1024, ny=1024, mode="f32")])
+    b16 = L.lbm_workspace_size([_p(nx=1024, ny=1024, mode="f16s")])
+    assert b64 > b32 > b16 > 2 * 9 * 1024 * 1024 * 2
+    assert L.lbm_workspace_size([_p(), _p(nx=100, ny=37)]) > L.lbm_workspace_size([_p()])
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(nx=2), "must be >= 3"),
+    (dict(ny=0), "must be >= 3"),
+    (dict(dx=0.0), "dx and dt"),
+    (dict(dt=float("nan")), "dx and dt"),
+    (dict(lam=-1.0), "lambda"),
+    (dict(scale_log2=40, mode="f16s"), "scale_log2"),
+])
+def test_invalid_parameters_are_rejected(kw, msg):
+    with pytest.raises(L.LbmError) as ei:
+        L.lbm_workspace_size([_p(**kw)])
+    assert ei.value.status == L.LBM_E_ARG
+    assert msg in str(ei.value)
+
+
+def test_fp64_math_needs_fp64_storage():
+    p = _p(mode="f32")
+    p.math = L.LBM_MATH_F64
+    with pytest.raises(L.LbmError, match="FP64 math needs FP64 storage"):
+        L.lbm_workspace_size([p])
+
+
+def test_null_context_calls_fail_cleanly():
+    lib = L.lib()
+    assert lib.lbm_free(None) == L.LBM_OK
+    assert lib.lbm_step(None, 1, None, None, None, None) == L.LBM_E_STATE
+    st = L.lbm_stats()
+    assert lib.lbm_macros(None, 0, None, None, ctypes.byref(st)) == L.LBM_E_STATE
+    assert "bad context" in L.lbm_last_error()
+    assert lib.lbm_init(None, 1, None, None, None, 0, None) == L.LBM_E_ARG

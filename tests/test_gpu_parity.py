@@ -1,0 +1,385 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle, on the same seeded inputs.
+
+FP64 storage + FP64 math must match the oracle to 1e-12 in the normalised max-abs sense
+(max |g_gpu - g_orc| / max |g_orc| over all nine population planes).  Reduced-precision modes are
+held to bounds derived from their rounding units (documented with each test).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from paper_2312_10316_amd import Solver, lbm
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def smooth_field(nx, ny, seed, lo, hi):
+    """Seeded smooth periodic field in [lo, hi] (a few random Fourier modes)."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(nx) * 2 * np.pi / nx
+    y = np.arange(ny) * 2 * np.pi / ny
+    Y, X = np.meshgrid(y, x, indexing="ij")
+    f = np.zeros((ny, nx))
+    for _ in range(4):
+        kx, ky = rng.integers(0, 3, 2)
+        f += rng.uniform(-1, 1) * np.cos(kx * X + ky * Y + rng.uniform(0, 2 * np.pi))
+    f = (f - f.min()) / max(f.max() - f.min(), 1e-300)
+    return lo + (hi - lo) * f
+
+
+def case_fields(nx, ny, seed, U=0.3, D0=2e-3, varD=True):
+    X, Y, dx = W.mesh(nx, ny, -1.0, 1.0)
+    rng = np.random.default_rng(seed)
+    c = 4.0
+    ux = c * (U * smooth_field(nx, ny, seed + 1, -1, 1))
+    uy = c * (U * smooth_field(nx, ny, seed + 2, -1, 1))
+    phi0 = 0.2 + smooth_field(nx, ny, seed + 3, 0, 1) + 0.05 * rng.uniform(0, 1, (ny, nx))
+    D = D0 * smooth_field(nx, ny, seed + 4, 0.5, 1.5) if varD else None
+    return dict(dx=dx, dt=dx / c, ux=ux, uy=uy, phi0=phi0, D=D, D_const=D0)
+
+
+def run_pair(nx, ny, f, steps, aux, lam=0.25, mode="f64", sources=None):
+    """Runs the GPU path and the oracle from g = g_eq(phi0, u); returns (g_gpu, g_orc, stats)."""
+    p = lbm.make_params(nx, ny, f["dx"], f["dt"], lam, f["D_const"], mode, aux)
+    fields = {k: dev(f[k]) for k in ("phi0", "ux", "uy")}
+    if f["D"] is not None:
+        fields["D"] = dev(f["D"])
+    s = Solver([(p, fields)])
+    op = O.Problem(nx, ny, f["dx"], f["dt"], lam, f["D_const"], aux)
+    g = O.init(op, f["phi0"], f["ux"], f["uy"])
+    if sources is None:
+        s.step(steps)
+        g = O.run(op, g, steps, f["ux"], f["uy"], f["D"])
+    else:
+        for t in range(steps):
+            S, dS = sources(t)
+            s.step(1, S=[dev(S)], dSdt=[dev(dS)])
+            g = O.step(op, g, f["ux"], f["uy"], f["D"], S, dS)
+    g_gpu = s.populations().cpu().numpy()
+    st = s.macros()
+    s.close()
+    return g_gpu, g, st
+
+
+# ---- FP64 parity ---------------------------------------------------------------------------------
+
+def test_fp64_rotating_pulse_64():
+    """The 64^2 rotating pulse, 160 steps to t = 0.5, constant D, paper-literal aux term."""
+    cfg = W.C1
+    f = W.rotating_pulse(cfg)
+    f["D"] = None
+    g_gpu, g_orc, st = run_pair(cfg.N, cfg.N, f, cfg.steps, lbm.LBM_AUX_LOCAL)
+    assert rel(g_gpu, g_orc) <= TOL64
+    phi = O.phi(O.Problem(cfg.N, cfg.N, f["dx"], f["dt"], cfg.lam, cfg.D), g_orc)
+    assert abs(st["mass"] - O.mass(phi)) <= 1e-13 * O.mass(phi)
+    assert st["step"] == cfg.steps and st["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("aux", [lbm.LBM_AUX_LOCAL, lbm.LBM_AUX_FLUX, lbm.LBM_AUX_NONE])
+@pytest.mark.parametrize("shape", [(70, 45), (130, 67), (64, 3)])
+def test_fp64_ragged_variable_D(aux, shape):
+    """Several 64-wide column tiles with a ragged tail, rows not a multiple of the walk, variable D,
+    a non-uniform velocity field."""
+    nx, ny = shape
+    f = case_fields(nx, ny, seed=nx * 7 + ny)
+    g_gpu, g_orc, _ = run_pair(nx, ny, f, 25, aux)
+    assert rel(g_gpu, g_orc) <= TOL64
+
+
+@pytest.mark.parametrize("shape", [(3, 3), (3, 5), (5, 3), (65, 4)])
+def test_fp64_degenerate_sizes(shape):
+    nx, ny = shape
+    f = case_fields(nx, ny, seed=3, varD=False)
+    for aux in (lbm.LBM_AUX_LOCAL, lbm.LBM_AUX_FLUX):
+        g_gpu, g_orc, _ = run_pair(nx, ny, f, 10, aux)
+        assert rel(g_gpu, g_orc) <= TOL64
+
+
+def test_fp64_source_path_sec3_benchmark():
+    """The Sec. 3 benchmark on its periodic proxy (N = 40, kappa = 0.05, Lambda = 1/12): time-dependent
+    source S and dS/dt supplied per step."""
+    N, kappa = 40, 0.05
+    x1 = W.x1_problem(N, kappa)
+    f = dict(dx=x1["dx"], dt=x1["dt"], ux=x1["ux"], uy=x1["uy"], phi0=x1["phi0"], D=None, D_const=kappa)
+    g_gpu, g_orc, _ = run_pair(N, N, f, x1["steps"], lbm.LBM_AUX_LOCAL, lam=x1["lam"],
+                               sources=lambda t: x1["source"](t * x1["dt"]))
+    assert rel(g_gpu, g_orc) <= TOL64
+    p = O.Problem(N, N, x1["dx"], x1["dt"], x1["lam"], kappa)
+    er = O.rms_error(O.phi(p, g_gpu), x1["exact"](x1["steps"] * x1["dt"])) * N / (N + 1)
+    assert abs(er / 3.679e-03 - 1) < 1e-3  # Table 2, Present, kappa = 0.05, N = 40
+
+
+# ---- reduced precision against the FP64 oracle ----------------------------------------------------
+
+@pytest.mark.parametrize("mode,bound", [("f64s_f32m", 2e-5), ("f32", 2e-5), ("f16s", 3e-3)])
+def test_reduced_precision_vs_oracle(mode, bound):
+    """64^2 pulse, 160 steps.  Bounds: FP32 math accumulates ~160 steps x a few ulp(2^-24) of the
+    largest population; FP16 storage adds one rounding of 2^-11 relative per stored value per step,
+    damped by the collision (measured values are reported by the benchmark)."""
+    cfg = W.C1
+    f = W.rotating_pulse(cfg)
+    f["D"] = None
+    g_gpu, g_orc, st = run_pair(cfg.N, cfg.N, f, cfg.steps, lbm.LBM_AUX_LOCAL, mode=mode)
+    err = rel(g_gpu, g_orc)
+    assert err <= bound, err
+    assert st["nonfinite"] == 0
+
+
+# ---- full-size one-step parity at the benchmark's launch configuration -----------------------------
+
+def _one_step_after(nx, ny, f, mode, warm, aux=lbm.LBM_AUX_LOCAL):
+    p = lbm.make_params(nx, ny, f["dx"], f["dt"], f["lam"], f["D_const"], mode, aux)
+    fields = {k: dev(f[k]) for k in ("phi0", "ux", "uy")}
+    if f.get("D") is not None:
+        fields["D"] = dev(f["D"])
+    s = Solver([(p, fields)])
+    s.step(warm)
+    g0 = s.populations()
+    s.step(1)
+    g1 = s.populations()
+    s.close()
+    return g0, g1
+
+
+def _windows(n, size, seed):
+    rng = np.random.default_rng(seed)
+    starts = [(0, 0), (n - size // 2, n - size // 2)]  # one window across the periodic seam
+    starts += [tuple(int(v) for v in rng.integers(0, n, 2)) for _ in range(2)]
+    return starts
+
+
+def _gather(g, ys, xs):
+    iy = torch.as_tensor(ys, device=g.device)
+    ix = torch.as_tensor(xs, device=g.device)
+    return g.index_select(1, iy).index_select(2, ix).cpu().numpy()
+
+
+def _oracle_window_step(g0, f, y0, x0, w, m, lam, D_const, aux):
+    """Oracle step on a (w + 2m)^2 window gathered with periodic wrap; only the inner w x w nodes
+    (at distance >= m from the window edge) are valid."""
+    n = g0.shape[-1]
+    ys = (np.arange(y0 - m, y0 + w + m)) % n
+    xs = (np.arange(x0 - m, x0 + w + m)) % n
+    gw = _gather(g0, ys, xs)
+    sub = lambda a: None if a is None else np.ascontiguousarray(a[np.ix_(ys, xs)])
+    p = O.Problem(w + 2 * m, w + 2 * m, f["dx"], f["dt"], lam, D_const, aux)
+    out = O.step(p, gw, sub(f["ux"]), sub(f["uy"]), sub(f.get("D")))
+    # out holds g^{n+1}; nodes within m-1 of the edge see wrapped (wrong) neighbours
+    return out[:, m:-m, m:-m], ys[m:-m], xs[m:-m]
+
+
+@pytest.mark.parametrize("mode,tol", [("f64", TOL64), ("f32", 3e-6)])
+def test_full_size_2048_one_step(mode, tol):
+    """2048^2 pulse in the benchmark's launch configuration: after 40 steps, one more GPU step equals
+    one oracle step from the GPU state (every node is compared)."""
+    cfg = W.C2
+    f = W.rotating_pulse(cfg)
+    f["D"] = None
+    f["lam"] = cfg.lam
+    g0, g1 = _one_step_after(cfg.N, cfg.N, f, mode, 40)
+    p = O.Problem(cfg.N, cfg.N, f["dx"], f["dt"], cfg.lam, cfg.D, O.AUX_LOCAL)
+    want = O.step(p, g0.cpu().numpy(), f["ux"], f["uy"])
+    assert rel(g1.cpu().numpy(), want) <= tol
+
+
+@pytest.mark.parametrize("mode", ["f64", "f64s_f32m", "f32", "f16s"])
+def test_full_size_8192_variable_D_windows(mode):
+    """8192^2 with D(x) = 1e-3 (1 + 0.5 sin(pi x) sin(pi y)): one step after 10, checked on sampled
+    64^2 windows (one across the periodic seam) against the oracle stepping the GPU state."""
+    cfg = W.C3
+    f = W.rotating_pulse(cfg)
+    f["lam"] = cfg.lam
+    g0, g1 = _one_step_after(cfg.N, cfg.N, f, mode, 10)
+    for (y0, x0) in _windows(cfg.N, 64, seed=17):
+        want, ys, xs = _oracle_window_step(g0, f, y0, x0, 64, 2, cfg.lam, cfg.D, O.AUX_LOCAL)
+        got = _gather(g1, ys, xs)
+        if mode == "f64":
+            assert np.abs(got - want).max() <= TOL64 * np.abs(want).max()
+        elif mode == "f16s":
+            # one FP16 rounding (2^-11 relative, round to nearest) of (g - w phi_ref) 2^15, plus the
+            # FP32 collision and the subnormal spacing 2^-24 / 2^15
+            bound = 2.0 ** -11 * np.abs(want) + 2e-6 * np.abs(want).max() + 2.0 ** -39
+            assert np.all(np.abs(got - want) <= bound)
+        else:
+            assert np.abs(got - want).max() <= 3e-6 * np.abs(want).max()
+
+
+def test_full_size_8192_flux_window():
+    cfg = W.C3
+    f = W.rotating_pulse(cfg)
+    f["lam"] = cfg.lam
+    g0, g1 = _one_step_after(cfg.N, cfg.N, f, "f64", 5, aux=lbm.LBM_AUX_FLUX)
+    for (y0, x0) in _windows(cfg.N, 64, seed=19)[:2]:
+        want, ys, xs = _oracle_window_step(g0, f, y0, x0, 64, 3, cfg.lam, cfg.D, O.AUX_FLUX)
+        got = _gather(g1, ys, xs)
+        assert np.abs(got - want).max() <= TOL64 * np.abs(want).max()
+
+
+# ---- diagnostics ----------------------------------------------------------------------------------
+
+def test_reduction_matches_fsum_and_oracle_definitions():
+    cfg = W.PulseConfig(N=300, steps=30)
+    f = W.rotating_pulse(cfg)
+    p = lbm.make_params(cfg.N, cfg.N, f["dx"], f["dt"], cfg.lam, cfg.D, "f64")
+    s = Solver([(p, {k: dev(f[k]) for k in ("phi0", "ux", "uy")})])
+    s.step(cfg.steps)
+    ref = W.pulse_reference(cfg, f)
+    st, phi = s.macros(ref=dev(ref), want_phi=True)
+    s.close()
+    phi = phi.cpu().numpy()
+    m = O.mass(phi)
+    assert abs(st["mass"] - m) <= 4 * math.ulp(m)
+    for key, want in (("rms_err", O.rms_error(phi, ref)), ("l2_rel_err", O.l2_rel_error(phi, ref)),
+                      ("max_abs_err", O.max_abs_error(phi, ref))):
+        assert abs(st[key] - want) <= 4 * math.ulp(want), key
+    assert st["max_abs_phi"] == np.abs(phi).max()
+
+
+def test_reduction_compensation_on_cancelling_data():
+    """phi0 mixing +-1e8 and +-1e-3 values (heavy cancellation): the compensated mass of the initial
+    state equals the correctly rounded sum of the same phi values."""
+    n = 256
+    rng = np.random.default_rng(23)
+    phi0 = rng.uniform(-1, 1, (n, n)) * np.where(rng.uniform(0, 1, (n, n)) < 0.5, 1e8, 1e-3)
+    p = lbm.make_params(n, n, 1.0, 1.0, 0.25, 1e-9, "f64")
+    z = np.zeros((n, n))
+    s = Solver([(p, {"phi0": dev(phi0), "ux": dev(z), "uy": dev(z)})])
+    st, phi = s.macros(want_phi=True)
+    s.close()
+    m = O.mass(phi.cpu().numpy())
+    assert abs(st["mass"] - m) <= 4 * math.ulp(abs(m)) + 1e-300
+
+
+# ---- FP16S codec against numpy's IEEE binary16 ------------------------------------------------------
+
+def test_f16s_decode_exhaustive():
+    """Every 16-bit code, loaded as raw state, decodes to h * 2^-k + w_i phi_ref computed in FP32."""
+    n = 256  # 65536 nodes: every code once per plane
+    k, phi_ref = 15, 0.75
+    p = lbm.make_params(n, n, 1.0, 1.0, 0.25, 1e-3, "f16s", scale_log2=k, phi_ref=phi_ref)
+    z = np.zeros((n, n))
+    s = Solver([(p, {"phi0": dev(np.full((n, n), phi_ref)), "ux": dev(z), "uy": dev(z)})])
+    codes = np.arange(65536, dtype=np.uint16).reshape(n, n)
+    raw = np.zeros(lbm.lbm_state_bytes(s.ctx) // 2, np.uint16)
+    plane = raw.size // 9
+    for i in range(9):
+        raw[i * plane:i * plane + n * n] = codes.ravel()
+    s.state_load(torch.from_numpy(raw.view(np.uint8)).cuda(), 0)
+    g = s.populations().cpu().numpy()
+    s.close()
+    ex, ey, w = O.lattice()
+    h = codes.view(np.float16).astype(np.float32)
+    for i in range(9):
+        want = (h * np.float32(2.0 ** -k) + np.float32(w[i] * phi_ref)).astype(np.float64)
+        got = np.roll(g[i], (-int(ey[i]), -int(ex[i])), (0, 1))  # buf_i(y) = g_i(y + e_i)
+        same = (got == want) | (np.isnan(got) & np.isnan(want))
+        assert same.all(), i
+
+
+def test_f16s_encode_matches_numpy_rne():
+    """u = 0 makes the initial populations w_i phi0 (one FP32 product); their stored codes equal
+    numpy's round-to-nearest-even float16 of (w_i phi0 - w_i phi_ref) 2^k."""
+    n = 1024
+    k, phi_ref = 15, 0.5
+    rng = np.random.default_rng(29)
+    phi0 = rng.uniform(-1.0, 3.0, (n, n))
+    z = np.zeros((n, n))
+    p = lbm.make_params(n, n, 1.0, 1.0, 0.25, 1e-3, "f16s", scale_log2=k, phi_ref=phi_ref)
+    s = Solver([(p, {"phi0": dev(phi0), "ux": dev(z), "uy": dev(z)})])
+    raw = s.state_save().cpu().numpy().view(np.uint16)
+    s.close()
+    plane = raw.size // 9
+    ex, ey, w = O.lattice()
+    p32 = phi0.astype(np.float32)
+    for i in range(9):
+        gi = np.float32(w[i]) * p32
+        want = ((gi - np.float32(w[i] * phi_ref)) * np.float32(2.0 ** k)).astype(np.float16).view(np.uint16)
+        got = raw[i * plane:i * plane + n * n].reshape(n, n)
+        got = np.roll(got, (int(ey[i]), int(ex[i])), (0, 1))
+        assert np.array_equal(got, want), i
+
+
+# ---- failure handling, checkpoints, determinism ----------------------------------------------------
+
+def test_nonfinite_phi_is_reported():
+    n = 32
+    phi0 = np.ones((n, n))
+    phi0[5, 7] = np.nan
+    z = np.zeros((n, n))
+    p = lbm.make_params(n, n, 1.0, 1.0, 0.25, 1e-3, "f64")
+    s = Solver([(p, {"phi0": dev(phi0), "ux": dev(z), "uy": dev(z)})])
+    s.step(3)
+    with pytest.raises(lbm.LbmError) as ei:
+        s.macros()
+    assert ei.value.status == lbm.LBM_E_NONFINITE
+    st = s.macros(raise_nonfinite=False)
+    assert st["nonfinite"] > 0 and st["status"] == lbm.LBM_E_NONFINITE
+    s.close()
+
+
+def test_invalid_fields_rejected_at_init():
+    n = 16
+    z = np.zeros((n, n))
+    D = np.full((n, n), 1e-3)
+    D[3, 3] = -1e-3
+    p = lbm.make_params(n, n, 1.0, 1.0, 0.25, 1e-3, "f64")
+    with pytest.raises(lbm.LbmError, match="D field"):
+        Solver([(p, {"phi0": dev(np.ones((n, n))), "ux": dev(z), "uy": dev(z), "D": dev(D)})])
+    p = lbm.make_params(n, n, 1.0, 1.0, 0.25, 1e-3, "f16s", scale_log2=24)
+    with pytest.raises(lbm.LbmError, match="does not fit FP16"):
+        Solver([(p, {"phi0": dev(np.ones((n, n))), "ux": dev(z), "uy": dev(z)})])
+
+
+@pytest.mark.parametrize("mode", ["f64", "f16s"])
+def test_checkpoint_resume_and_determinism(mode):
+    cfg = W.PulseConfig(N=96, steps=30, D_variable=True)
+    f = W.rotating_pulse(cfg)
+    p = lbm.make_params(cfg.N, cfg.N, f["dx"], f["dt"], cfg.lam, cfg.D, mode)
+    fields = {k: dev(f[k]) for k in ("phi0", "ux", "uy", "D")}
+    a = Solver([(p, fields)])
+    a.step(10)
+    ck = a.state_save()
+    a.step(20)
+    end_a = a.state_save()
+    b = Solver([(p, fields)])
+    b.state_load(ck, 10)
+    b.step(20)
+    end_b = b.state_save()
+    assert b.macros()["step"] == 30
+    assert torch.equal(end_a, end_b)
+    c = Solver([(p, fields)])
+    c.step(30)
+    assert torch.equal(c.state_save(), end_a)
+    for s in (a, b, c):
+        s.close()
+
+
+def test_multi_instance_context_matches_single():
+    cfgs = [W.PulseConfig(N=48, steps=12), W.PulseConfig(N=80, steps=12, U0=2.0, D=3e-3)]
+    inst = []
+    for cfg in cfgs:
+        f = W.rotating_pulse(cfg)
+        inst.append((lbm.make_params(cfg.N, cfg.N, f["dx"], f["dt"], cfg.lam, cfg.D, "f64"),
+                     {k: dev(f[k]) for k in ("phi0", "ux", "uy")}))
+    both = Solver(inst)
+    both.step(12)
+    for k, one in enumerate(inst):
+        s = Solver([one])
+        s.step(12)
+        assert torch.equal(s.populations(), both.populations(k))
+        s.close()
+    both.close()
