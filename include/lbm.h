@@ -133,10 +133,30 @@ int lbm_populations(lbm_ctx *ctx, int32_t inst, double *g_out);
 /* Checkpoint of instance inst: the raw population state in the library's storage format.
  * lbm_state_bytes gives its size; save copies it to dst (device), load restores it from src
  * (device) and sets the step counter.  Asynchronous.  A run resumed from a checkpoint is bitwise
- * identical to the uninterrupted run. */
+ * identical to the uninterrupted run.
+ * Image layout: [ny][9][pitch] elements of the storage type (FP64, FP32 or FP16 code), pitch = nx
+ * rounded up to a multiple of 64, padding zero.  Element (y, i, x) holds the post-collision value
+ * P_i of node (x, y) from the previous step, so that g_i(x, y) = element (y - e_iy, i, x - e_ix)
+ * (periodic); after lbm_init it holds g_eq_i of node (x + e_ix, y + e_iy). */
 int lbm_state_bytes(lbm_ctx *ctx, int32_t inst, size_t *bytes);
 int lbm_state_save(lbm_ctx *ctx, int32_t inst, void *dst);
 int lbm_state_load(lbm_ctx *ctx, int32_t inst, const void *src, int64_t step);
+
+/* Launch shape of the step kernel.  A tuning knob only: results are bitwise independent of it.
+ * Tiles are 64 columns wide; each of a block's 4 waves walks `rows` consecutive lattice rows. */
+typedef struct lbm_launch {
+    int32_t rows;       /* 1..64 */
+    int32_t xcd_remap;  /* 1: consecutive tiles go to blocks on the same XCD (shared L2); 0: hardware order */
+} lbm_launch;
+
+/* Sets (inst = -1: every instance) or reads the launch shape; captured step graphs are dropped. */
+int lbm_set_launch(lbm_ctx *ctx, int32_t inst, const lbm_launch *cfg);
+int lbm_get_launch(lbm_ctx *ctx, int32_t inst, lbm_launch *cfg);
+
+/* Plain streaming copy of `bytes` bytes (multiple of 16; both pointers device, 16-byte aligned) on
+ * `stream`: 16-byte vector loads and non-temporal stores, one pass.  Not part of the method: it is
+ * the reference kernel against which achievable HBM bandwidth and traffic counters are calibrated. */
+int lbm_bench_copy(void *dst, const void *src, size_t bytes, void *stream);
 
 /* Synchronizes the context's stream and releases everything the library allocated (never caller
  * memory).  NULL is accepted. */

@@ -50,9 +50,13 @@ Layout layout_of(const lbm_params &p)
     L.nx = p.nx;
     L.ny = p.ny;
     L.pitch = (int64_t)align_up((size_t)p.nx, 64);
-    L.plane = L.pitch * p.ny;
     return L;
 }
+
+// Default launch shape per storage mode (measured on MI355X at 2048^2 and 8192^2; the autotuner in
+// the Python package can override it per instance): one row per wave with XCD-contiguous tiles
+// for FP64/FP32; FP16 codes (2 bytes per lane) prefer a 4-row walk.
+Launch default_launch(int mode) { return mode == MODE_F16S_F32 ? Launch{4, 1} : Launch{1, 1}; }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
@@ -80,8 +84,9 @@ struct Instance {
     lbm_params p;
     int mode;
     Layout L;
+    Launch lc;
     char *buf[2];
-    void *ux, *uy, *k, *s;
+    void *u, *k, *s;
     bool has_D;
     bool has_src;
     int cur;
@@ -89,10 +94,11 @@ struct Instance {
     F16Params f16;
 };
 
-// Per instance: 2 population buffers (9 planes each) and 4 math-type fields (ux, uy, k, s).
-size_t pops_bytes(const lbm_params &p) { return align_up((size_t)layout_of(p).plane * 9 * store_bytes(mode_of(p)), kAlign); }
-size_t field_bytes(const lbm_params &p) { return align_up((size_t)layout_of(p).plane * math_bytes(mode_of(p)), kAlign); }
-size_t instance_bytes(const lbm_params &p) { return 2 * pops_bytes(p) + 4 * field_bytes(p); }
+// Per instance: 2 population buffers, the velocity pair, and the k and s fields (math type).
+size_t pops_bytes(const lbm_params &p) { return align_up((size_t)pop_elems(layout_of(p)) * store_bytes(mode_of(p)), kAlign); }
+size_t vel_bytes(const lbm_params &p) { return align_up((size_t)vel_elems(layout_of(p)) * math_bytes(mode_of(p)), kAlign); }
+size_t field_bytes(const lbm_params &p) { return align_up((size_t)fld_elems(layout_of(p)) * math_bytes(mode_of(p)), kAlign); }
+size_t instance_bytes(const lbm_params &p) { return 2 * pops_bytes(p) + vel_bytes(p) + 2 * field_bytes(p); }
 
 // Shared scratch: macro partials, the macro result, and a flag word.
 constexpr size_t kPartialBytes = (size_t)kMacroBlocks * kMacroPartialDoubles * sizeof(double);
@@ -113,26 +119,36 @@ F16Params f16_of(const lbm_params &p)
 
 }  // namespace
 
+// Long runs replay a captured graph of kGraphSteps steps (an even count, so every buffer returns
+// to its role); one graph per buffer parity, re-captured when the set of instances with a source
+// changes.
+constexpr int kGraphSteps = 32;
+
 struct lbm_ctx {
     std::vector<Instance> inst;
     hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;  // private stream used only to record graphs
     char *ws = nullptr;
     bool owns_ws = false;
     double *partials = nullptr;
     double *result = nullptr;
     int *flag = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    std::vector<bool> graph_src[2];
 };
 
 namespace {
 
 int prep_field(lbm_ctx *c, Instance &in, const double *a, const double *b, double ca, double cb, void *out,
-               int check_positive)
+               int check_positive, int stride = 1, int comp = 0)
 {
     PrepArgs pa;
     pa.a = a;
     pa.b = b;
     pa.out = out;
     pa.L = in.L;
+    pa.stride = stride;
+    pa.comp = comp;
     pa.ca = ca;
     pa.cb = cb;
     pa.flag = c->flag + 1;
@@ -144,14 +160,89 @@ int prep_field(lbm_ctx *c, Instance &in, const double *a, const double *b, doubl
 int set_velocity(lbm_ctx *c, Instance &in, const double *ux, const double *uy)
 {
     const double s = in.p.dt / in.p.dx;  // lattice units: u dt / dx
-    int rc = prep_field(c, in, ux, nullptr, s, 0.0, in.ux, 0);
-    if (rc == LBM_OK) rc = prep_field(c, in, uy, nullptr, s, 0.0, in.uy, 0);
+    int rc = prep_field(c, in, ux, nullptr, s, 0.0, in.u, 0, 2, 0);
+    if (rc == LBM_OK) rc = prep_field(c, in, uy, nullptr, s, 0.0, in.u, 0, 2, 1);
     return rc;
 }
 
 bool check_inst(lbm_ctx *c, int32_t inst)
 {
     return c && inst >= 0 && inst < (int32_t)c->inst.size();
+}
+
+// Enqueues one step of every instance on stream st (buffers chosen from each instance's cur).
+int enqueue_step(lbm_ctx *c, hipStream_t st)
+{
+    for (Instance &in : c->inst) {
+        StepArgs a;
+        a.src = in.buf[in.cur];
+        a.dst = in.buf[in.cur ^ 1];
+        a.u = in.u;
+        a.k = in.has_D ? in.k : nullptr;
+        a.s = in.has_src ? in.s : nullptr;
+        a.L = in.L;
+        a.lc = in.lc;
+        // constant D: tau1 - 1/2 = kappa / (cs^2 dt) = 3 kappa dt / dx^2, tau2 - 1/2 = Lambda / (tau1 - 1/2)
+        const double k = 3.0 * in.p.D_const * in.p.dt / (in.p.dx * in.p.dx);
+        const double tau1 = 0.5 + k, tau2 = 0.5 + in.p.lambda / k;
+        a.w1 = 1.0 - 1.0 / tau1;
+        a.w2 = 1.0 - 1.0 / tau2;
+        a.beta = 1.0 - 0.5 / tau1;
+        a.lambda = in.p.lambda;
+        a.f16 = in.f16;
+        hipError_t e = launch_step(in.mode, in.p.aux, a, st);
+        if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+        in.cur ^= 1;
+    }
+    return LBM_OK;
+}
+
+void drop_graphs(lbm_ctx *c)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (c->graph[k]) (void)hipGraphExecDestroy(c->graph[k]);
+        c->graph[k] = nullptr;
+        c->graph_src[k].clear();
+    }
+}
+
+// Returns the graph of kGraphSteps steps for the current buffer parity, capturing it if needed.
+int graph_for(lbm_ctx *c, hipGraphExec_t *out)
+{
+    const int par = c->inst[0].cur;
+    std::vector<bool> src(c->inst.size());
+    for (size_t k = 0; k < c->inst.size(); ++k) src[k] = c->inst[k].has_src;
+    if (c->graph[par] && c->graph_src[par] == src) {
+        *out = c->graph[par];
+        return LBM_OK;
+    }
+    if (c->graph[par]) {
+        (void)hipGraphExecDestroy(c->graph[par]);
+        c->graph[par] = nullptr;
+    }
+    if (!c->capture) {
+        hipError_t e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "creating the capture stream");
+    }
+    hipError_t e = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    int rc = LBM_OK;
+    for (int t = 0; t < kGraphSteps && rc == LBM_OK; ++t) rc = enqueue_step(c, c->capture);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->capture, &g);
+    if (rc != LBM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    c->graph[par] = x;
+    c->graph_src[par] = src;
+    *out = x;
+    return LBM_OK;
 }
 
 }  // namespace
@@ -220,25 +311,28 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
         in.p = p[k];
         in.mode = mode_of(p[k]);
         in.L = layout_of(p[k]);
-        const size_t pb = pops_bytes(p[k]), fb = field_bytes(p[k]);
+        const size_t pb = pops_bytes(p[k]), vb = vel_bytes(p[k]), fb = field_bytes(p[k]);
+        in.lc = default_launch(in.mode);
         in.buf[0] = w;
         in.buf[1] = w + pb;
         w += 2 * pb;
-        in.ux = w;
-        in.uy = w + fb;
-        in.k = w + 2 * fb;
-        in.s = w + 3 * fb;
-        w += 4 * fb;
+        in.u = w;
+        w += vb;
+        in.k = w;
+        in.s = w + fb;
+        w += 2 * fb;
         in.has_D = f[k].D != nullptr;
         in.has_src = false;
         in.cur = 0;
         in.step = 0;
         in.f16 = f16_of(p[k]);
     }
-    hipError_t e = hipMemsetAsync(c->flag, 0, 2 * sizeof(int), c->stream);
+    // Zero everything the library owns (padding columns included) so that a state is a
+    // deterministic byte image, then clear the flags.
+    hipError_t e = hipMemsetAsync(c->ws, 0, need, c->stream);
     if (e != hipSuccess) {
         lbm_free(c);
-        return hip_fail(e, "lbm_init: clearing the flag");
+        return hip_fail(e, "lbm_init: clearing the workspace");
     }
     for (int k = 0; k < n_inst && rc == LBM_OK; ++k) {
         Instance &in = c->inst[k];
@@ -248,8 +342,7 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
         if (rc == LBM_OK) {
             InitArgs ia;
             ia.phi0 = f[k].phi0;
-            ia.ux = in.ux;
-            ia.uy = in.uy;
+            ia.u = in.u;
             ia.dst = in.buf[0];
             ia.L = in.L;
             ia.f16 = in.f16;
@@ -299,27 +392,21 @@ int lbm_step(lbm_ctx *c, int32_t nsteps, const double *const *ux, const double *
             rc = prep_field(c, in, S[k], dSdt ? dSdt[k] : nullptr, in.p.dt, 0.5 * in.p.dt * in.p.dt, in.s, 0);
     }
     if (rc) return rc;
-    for (int t = 0; t < nsteps; ++t) {
-        for (int k = 0; k < n; ++k) {
-            Instance &in = c->inst[k];
-            StepArgs a;
-            a.src = in.buf[in.cur];
-            a.dst = in.buf[in.cur ^ 1];
-            a.ux = in.ux;
-            a.uy = in.uy;
-            a.k = in.has_D ? in.k : nullptr;
-            a.s = in.has_src ? in.s : nullptr;
-            a.L = in.L;
-            a.rows = 8;
-            a.k_const = 3.0 * in.p.D_const * in.p.dt / (in.p.dx * in.p.dx);
-            a.lambda = in.p.lambda;
-            a.f16 = in.f16;
-            hipError_t e = launch_step(in.mode, in.p.aux, a, c->stream);
-            if (e != hipSuccess) return hip_fail(e, "step kernel launch");
-            in.cur ^= 1;
-            in.step += 1;
+    int left = nsteps;
+    if (left >= 2 * kGraphSteps) {
+        hipGraphExec_t x = nullptr;
+        rc = graph_for(c, &x);
+        if (rc) return rc;
+        for (; left >= kGraphSteps; left -= kGraphSteps) {
+            hipError_t e = hipGraphLaunch(x, c->stream);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
         }
     }
+    for (; left > 0; --left) {
+        rc = enqueue_step(c, c->stream);
+        if (rc) return rc;
+    }
+    for (Instance &in : c->inst) in.step += nsteps;
     return LBM_OK;
 }
 
@@ -402,12 +489,49 @@ int lbm_state_load(lbm_ctx *c, int32_t inst, const void *src, int64_t step)
     return LBM_OK;
 }
 
+int lbm_set_launch(lbm_ctx *c, int32_t inst, const lbm_launch *cfg)
+{
+    g_err[0] = 0;
+    if (!c || inst < -1 || inst >= (int32_t)c->inst.size())
+        return fail(LBM_E_STATE, "lbm_set_launch: bad context or instance %d", inst);
+    if (!cfg) return fail(LBM_E_ARG, "lbm_set_launch: cfg is NULL");
+    if (cfg->rows < 1 || cfg->rows > 64) return fail(LBM_E_ARG, "lbm_set_launch: rows=%d outside 1..64", cfg->rows);
+    if (cfg->xcd_remap != 0 && cfg->xcd_remap != 1) return fail(LBM_E_ARG, "lbm_set_launch: xcd_remap must be 0 or 1");
+    for (int k = 0; k < (int)c->inst.size(); ++k)
+        if (inst == -1 || inst == k) c->inst[k].lc = Launch{cfg->rows, cfg->xcd_remap};
+    drop_graphs(c);
+    return LBM_OK;
+}
+
+int lbm_get_launch(lbm_ctx *c, int32_t inst, lbm_launch *cfg)
+{
+    g_err[0] = 0;
+    if (!check_inst(c, inst)) return fail(LBM_E_STATE, "lbm_get_launch: bad context or instance %d", inst);
+    if (!cfg) return fail(LBM_E_ARG, "lbm_get_launch: cfg is NULL");
+    cfg->rows = c->inst[inst].lc.rows;
+    cfg->xcd_remap = c->inst[inst].lc.xcd_remap;
+    return LBM_OK;
+}
+
+int lbm_bench_copy(void *dst, const void *src, size_t bytes, void *stream)
+{
+    g_err[0] = 0;
+    if (!dst || !src) return fail(LBM_E_ARG, "lbm_bench_copy: NULL pointer");
+    if (bytes % 16 || (uintptr_t)dst % 16 || (uintptr_t)src % 16)
+        return fail(LBM_E_ARG, "lbm_bench_copy: bytes and pointers must be multiples of 16");
+    if (bytes / 16 > (size_t)UINT32_MAX * 256) return fail(LBM_E_ARG, "lbm_bench_copy: too large");
+    hipError_t e = launch_copy(dst, src, bytes, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "copy kernel launch");
+}
+
 int lbm_free(lbm_ctx *c)
 {
     if (!c) return LBM_OK;
     int rc = LBM_OK;
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) rc = hip_fail(e, "lbm_free: synchronizing");
+    drop_graphs(c);
+    if (c->capture) (void)hipStreamDestroy(c->capture);
     if (c->owns_ws && c->ws) {
         e = hipFree(c->ws);
         if (e != hipSuccess && rc == LBM_OK) rc = hip_fail(e, "lbm_free: hipFree");

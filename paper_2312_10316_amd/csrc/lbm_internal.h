@@ -1,4 +1,15 @@
-// lbm_internal.h -- argument blocks and launchers shared by the C-ABI layer and the kernels.
+// lbm_internal.h -- memory layout, argument blocks and launchers shared by the C-ABI layer and the
+// kernels.
+//
+// HBM layout of one instance (element = storage type for populations, math type for fields):
+//   populations  [ny][9][pitch]   element (i, y, x) at (y*9 + i)*pitch + x   ("row-interleaved")
+//   velocity     [ny][2][pitch]   u_x at (y*2)*pitch + x, u_y at (y*2 + 1)*pitch + x
+//   k, s         [ny][pitch]      scalar fields at y*pitch + x
+// pitch = nx rounded up to a multiple of 64 elements, so every row segment starts 128-byte aligned for
+// every element size.  Keeping the nine segments of one lattice row next to each other turns the 18
+// concurrent streams of a step (9 reads at rows y-1, y, y+1 and 9 writes at row y) into accesses to
+// three neighbouring ~9*pitch windows, which the HBM serves closer to copy bandwidth than nine separate
+// planes.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,32 +28,39 @@ enum Mode : int {
     MODE_F16S_F32 = 3  // shifted/scaled FP16 storage, FP32 math
 };
 
-// Layout of one instance in the workspace.  Population planes and fields share the row pitch
-// (in elements, a multiple of 64 so every row starts 128-byte aligned for every element size).
 struct Layout {
     int32_t nx, ny;
-    int64_t pitch;  // elements per row
-    int64_t plane;  // elements per population plane (>= ny * pitch)
+    int64_t pitch;  // elements per row segment (multiple of 64)
+};
+
+__host__ __device__ __forceinline__ int64_t pop_elems(const Layout &L) { return (int64_t)L.ny * 9 * L.pitch; }
+__host__ __device__ __forceinline__ int64_t vel_elems(const Layout &L) { return (int64_t)L.ny * 2 * L.pitch; }
+__host__ __device__ __forceinline__ int64_t fld_elems(const Layout &L) { return (int64_t)L.ny * L.pitch; }
+
+// Launch shape of the step kernel: a block is 4 waves of 64 lanes; lane = column, each wave walks
+// `rows` consecutive rows; tiles of 64 columns x 4*rows rows.
+struct Launch {
+    int32_t rows;       // 1..64
+    int32_t xcd_remap;  // 1: give consecutive tiles to blocks on the same XCD
 };
 
 struct StepArgs {
-    const void *src;  // 9 planes, storage type
-    void *dst;        // 9 planes, storage type
-    const void *ux;   // math type, lattice units (u dt / dx), pitched
-    const void *uy;
+    const void *src;  // populations, storage type
+    void *dst;        // populations, storage type
+    const void *u;    // velocity, math type, lattice units (u dt / dx)
     const void *k;    // math type, tau1 - 1/2 per node (nullptr: k_const)
     const void *s;    // math type, dt S + dt^2/2 dS/dt per node (nullptr: no source)
     Layout L;
-    int32_t rows;     // rows walked by one thread
-    double k_const;
+    Launch lc;
+    double w1, w2, beta;  // relaxation when k is nullptr: 1 - 1/tau1, 1 - 1/tau2, 1 - 1/(2 tau1)
     double lambda;
     F16Params f16;
 };
 
 struct InitArgs {
     const double *phi0;  // dense FP64 [ny][nx]
-    const void *ux, *uy; // math type, pitched, lattice units
-    void *dst;           // population buffer (storage type)
+    const void *u;       // velocity, math type
+    void *dst;           // populations
     Layout L;
     F16Params f16;
     int *range_flag;     // set to 1 if an F16S value does not fit
@@ -51,20 +69,22 @@ struct InitArgs {
 struct PrepArgs {
     const double *a;   // dense FP64 [ny][nx]
     const double *b;   // second input (nullable)
-    void *out;         // math type, pitched
+    void *out;         // math type
     Layout L;
+    int32_t stride;    // row stride of out in units of pitch (1 for scalar fields, 2 for velocity)
+    int32_t comp;      // component offset in units of pitch (velocity: 0 or 1)
     double ca, cb;     // out = ca * a + cb * b
     int *flag;         // set to 1 if check_positive and a value is not finite and > 0
     int check_positive;
 };
 
 struct MacroArgs {
-    const void *src;   // population buffer holding the current state
+    const void *src;   // populations holding the current state
     const double *ref; // nullable
     double *phi_out;   // nullable
     Layout L;
     F16Params f16;
-    double *partials;  // per block: see kMacroPartialDoubles
+    double *partials;  // per block: kMacroPartialDoubles
 };
 
 constexpr int kMacroPartialDoubles = 10;  // mass(s,c) err2(s,c) ref2(s,c) maxerr maxphi nonfinite pad
@@ -83,5 +103,6 @@ hipError_t launch_init(int mode, const InitArgs &a, hipStream_t st);
 hipError_t launch_prep(int mode, const PrepArgs &a, hipStream_t st);
 hipError_t launch_macros(int mode, const MacroArgs &a, double *result, hipStream_t st);
 hipError_t launch_populations(int mode, const PopArgs &a, hipStream_t st);
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
 
 }  // namespace lbm

@@ -5,6 +5,12 @@
 // g_i(x) = A_i(x - e_i) (streaming of Sec. 2.2, Eq. (14)), and one step reads A with those shifts
 // and writes P_i(x) to buffer B at x.  The initial buffer is written pre-shifted
 // (A_i(x - e_i) = g_eq_i(phi0(x), u(x))) so that the first pull yields g = g_eq(phi0, u).
+//
+// The step is a bandwidth-bound stencil: per node it moves 9 populations in and 9 out plus the
+// velocity (and D when it is a field), against ~250 flops that stay in registers, so it is written
+// for coalesced streaming: lane = column (a wave reads 64 consecutive elements of each row segment),
+// each wave walks a few rows so the velocity stencil's y-neighbours stay in registers, stores are
+// non-temporal, and the tile order can be remapped so neighbouring tiles share an XCD's L2.
 #include "lbm_internal.h"
 
 namespace lbm {
@@ -36,38 +42,73 @@ struct ModeTraits<MODE_F16S_F32> {
 __device__ __forceinline__ int wrap_dec(int v, int n) { return v == 0 ? n - 1 : v - 1; }
 __device__ __forceinline__ int wrap_inc(int v, int n) { return v == n - 1 ? 0 : v + 1; }
 
-// g_i(x, y) = buf_i(x - e_i): row offsets rm = (y-1)*pitch, rc = y*pitch, rp = (y+1)*pitch (wrapped)
-// and columns xm = x-1, xp = x+1 (wrapped).
+// g_i(x, y) = buf_i(x - e_i).  rm, rc, rp: the row blocks (9 segments) of rows y-1, y, y+1 (wrapped);
+// xm, xp: columns x-1, x+1 (wrapped).
 template <class St, class M>
-__device__ __forceinline__ void pull(const typename St::T *__restrict__ src, int64_t plane, int64_t rm,
-                                     int64_t rc, int64_t rp, int xm, int x, int xp,
+__device__ __forceinline__ void pull(const typename St::T *__restrict__ rm, const typename St::T *__restrict__ rc,
+                                     const typename St::T *__restrict__ rp, int64_t pitch, int xm, int x, int xp,
                                      const F16Params &f, M (&g)[9])
 {
     using C = Codec<St, M>;
-    g[0] = C::dec(src[0 * plane + rc + x], 0, f);
-    g[1] = C::dec(src[1 * plane + rc + xm], 1, f);
-    g[2] = C::dec(src[2 * plane + rm + x], 2, f);
-    g[3] = C::dec(src[3 * plane + rc + xp], 3, f);
-    g[4] = C::dec(src[4 * plane + rp + x], 4, f);
-    g[5] = C::dec(src[5 * plane + rm + xm], 5, f);
-    g[6] = C::dec(src[6 * plane + rm + xp], 6, f);
-    g[7] = C::dec(src[7 * plane + rp + xp], 7, f);
-    g[8] = C::dec(src[8 * plane + rp + xm], 8, f);
+    g[0] = C::dec(rc[0 * pitch + x], 0, f);
+    g[1] = C::dec(rc[1 * pitch + xm], 1, f);
+    g[2] = C::dec(rm[2 * pitch + x], 2, f);
+    g[3] = C::dec(rc[3 * pitch + xp], 3, f);
+    g[4] = C::dec(rp[4 * pitch + x], 4, f);
+    g[5] = C::dec(rm[5 * pitch + xm], 5, f);
+    g[6] = C::dec(rm[6 * pitch + xp], 6, f);
+    g[7] = C::dec(rp[7 * pitch + xp], 7, f);
+    g[8] = C::dec(rp[8 * pitch + xm], 8, f);
+}
+
+template <class T>
+__device__ __forceinline__ const T *row_block(const T *base, const Layout &L, int y)
+{
+    return base + (int64_t)y * 9 * L.pitch;
+}
+
+template <class St, class M>
+__device__ __forceinline__ void pull_node(const typename St::T *__restrict__ src, const Layout &L, int x, int y,
+                                          const F16Params &f, M (&g)[9])
+{
+    pull<St, M>(row_block(src, L, wrap_dec(y, L.ny)), row_block(src, L, y), row_block(src, L, wrap_inc(y, L.ny)),
+                L.pitch, wrap_dec(x, L.nx), x, wrap_inc(x, L.nx), f, g);
 }
 
 template <class St, class M>
 __device__ __forceinline__ M phi_at(const typename St::T *__restrict__ src, const Layout &L, int x, int y,
                                     const F16Params &f)
 {
-    const int xm = wrap_dec(x, L.nx), xp = wrap_inc(x, L.nx);
-    const int64_t rm = (int64_t)wrap_dec(y, L.ny) * L.pitch, rc = (int64_t)y * L.pitch,
-                  rp = (int64_t)wrap_inc(y, L.ny) * L.pitch;
     M g[9];
-    pull<St, M>(src, L.plane, rm, rc, rp, xm, x, xp, f, g);
+    pull_node<St, M>(src, L, x, y, f, g);
     return g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
 }
 
-// One step.  Block (64, 4): lane x covers one column, each of the 4 waves walks `rows` rows.
+// Block b -> tile t.  With xcd_remap the hardware's round-robin of blocks over the 8 XCDs
+// (block b runs on XCD b % 8) is inverted so that XCD j works on one contiguous range of tiles.
+__device__ __forceinline__ int tile_of_block(int b, int nb, int remap)
+{
+    if (!remap) return b;
+    const int q = nb >> 3, r = nb & 7, j = b & 7;
+    return j * q + min(j, r) + (b >> 3);
+}
+
+// Element at a 32-bit byte offset from a wave-uniform base: lets the compiler use the scalar-base +
+// 32-bit-lane-offset addressing form instead of per-lane 64-bit address arithmetic.
+template <class T>
+__device__ __forceinline__ T ld_at(const T *base, unsigned byte_off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void st_nt_at(T *base, unsigned byte_off, T v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off));
+}
+
+// One step.  Block (64, 4): lane = column of a 64-wide tile, wave w walks `rows` rows.  The wave's
+// row is uniform (taken with readfirstlane), so row and segment bases live in scalar registers and
+// each load or store needs only a 32-bit lane offset (x, x-1 or x+1).
 template <int MODE, int AUX, bool HAS_K, bool HAS_S>
 __global__ __launch_bounds__(256) void step_kernel(const StepArgs a)
 {
@@ -76,61 +117,89 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a)
     using T = typename St::T;
     using C = Codec<St, M>;
     const int nx = a.L.nx, ny = a.L.ny;
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y0 = (blockIdx.y * 4 + threadIdx.y) * a.rows;
-    if (x >= nx || y0 >= ny) return;
-    const int y1 = min(y0 + a.rows, ny);
-    const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
-    const int64_t pitch = a.L.pitch, plane = a.L.plane;
+    const int64_t pitch = a.L.pitch;
+    const int rows = a.lc.rows;
+    const int ntx = (nx + 63) >> 6;
+    const int t = tile_of_block(blockIdx.x, gridDim.x, a.lc.xcd_remap);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const unsigned x = (unsigned)((t % ntx) * 64) + threadIdx.x;
+    const int y0 = ((t / ntx) * 4 + wave) * rows;
+    if (y0 >= ny) return;
+    const bool live = x < (unsigned)nx;
+    const unsigned xc = live ? x : 0u;  // dead lanes of a ragged tile read column 0 and store nothing
+    const unsigned xm = xc == 0 ? (unsigned)nx - 1 : xc - 1;
+    const unsigned xp = xc == (unsigned)nx - 1 ? 0u : xc + 1;
+    const int y1 = min(y0 + rows, ny);
     const T *__restrict__ src = static_cast<const T *>(a.src);
     T *__restrict__ dst = static_cast<T *>(a.dst);
-    const M *__restrict__ ux = static_cast<const M *>(a.ux);
-    const M *__restrict__ uy = static_cast<const M *>(a.uy);
+    const M *__restrict__ u = static_cast<const M *>(a.u);
     const M *__restrict__ kf = static_cast<const M *>(a.k);
     const M *__restrict__ sf = static_cast<const M *>(a.s);
     const M lam = (M)a.lambda;
-    Relax<M> rconst{};
-    if (!HAS_K) rconst = relax_from_k<M>((M)a.k_const, lam);
+    Relax<M> rconst;
+    rconst.w1 = (M)a.w1;
+    rconst.w2 = (M)a.w2;
+    rconst.beta = (M)a.beta;
 
-    // u in this column at y-1 and y (rolled down the walk)
-    int yprev = wrap_dec(y0, ny);
-    M ux_m = ux[(int64_t)yprev * pitch + x], uy_m = uy[(int64_t)yprev * pitch + x];
-    M ux_c = ux[(int64_t)y0 * pitch + x], uy_c = uy[(int64_t)y0 * pitch + x];
+    // velocity in this column at rows y-1 and y, rolled down the walk
+    const int yprev = wrap_dec(y0, ny);
+    const M *__restrict__ u_m = u + (int64_t)yprev * 2 * pitch;
+    const M *__restrict__ u_c = u + (int64_t)y0 * 2 * pitch;
+    // byte offsets of columns x, x-1, x+1 for population and field element sizes
+    const unsigned bc = xc * (unsigned)sizeof(T), bm = xm * (unsigned)sizeof(T), bp = xp * (unsigned)sizeof(T);
+    const unsigned fc = xc * (unsigned)sizeof(M), fm = xm * (unsigned)sizeof(M), fp = xp * (unsigned)sizeof(M);
+    M ux_m = ld_at(u_m, fc), uy_m = ld_at(u_m + pitch, fc);
+    M ux_c = ld_at(u_c, fc), uy_c = ld_at(u_c + pitch, fc);
 
     for (int y = y0; y < y1; ++y) {
-        const int yn = wrap_inc(y, ny);
-        const int64_t rm = (int64_t)wrap_dec(y, ny) * pitch, rc = (int64_t)y * pitch, rp = (int64_t)yn * pitch;
+        const int ym = wrap_dec(y, ny), yn = wrap_inc(y, ny);
+        const T *__restrict__ rm = src + (int64_t)ym * 9 * pitch;
+        const T *__restrict__ rc = src + (int64_t)y * 9 * pitch;
+        const T *__restrict__ rp = src + (int64_t)yn * 9 * pitch;
         M g[9];
-        pull<St, M>(src, plane, rm, rc, rp, xm, x, xp, a.f16, g);
-        const M ux_p = ux[rp + x], uy_p = uy[rp + x];
+        g[0] = C::dec(ld_at(rc, bc), 0, a.f16);
+        g[1] = C::dec(ld_at(rc + pitch, bm), 1, a.f16);
+        g[2] = C::dec(ld_at(rm + 2 * pitch, bc), 2, a.f16);
+        g[3] = C::dec(ld_at(rc + 3 * pitch, bp), 3, a.f16);
+        g[4] = C::dec(ld_at(rp + 4 * pitch, bc), 4, a.f16);
+        g[5] = C::dec(ld_at(rm + 5 * pitch, bm), 5, a.f16);
+        g[6] = C::dec(ld_at(rm + 6 * pitch, bp), 6, a.f16);
+        g[7] = C::dec(ld_at(rp + 7 * pitch, bp), 7, a.f16);
+        g[8] = C::dec(ld_at(rp + 8 * pitch, bm), 8, a.f16);
+        const M *__restrict__ un = u + (int64_t)yn * 2 * pitch;
+        const M *__restrict__ uc = u + (int64_t)y * 2 * pitch;
+        const M ux_p = ld_at(un, fc), uy_p = ld_at(un + pitch, fc);
 
         M Ax = M(0), Ay = M(0);
         if (AUX == 0) {  // Eq. (16): phi u_b d_b u_a, central differences of u
             const M phi = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
-            const M dxux = (ux[rc + xp] - ux[rc + xm]) * M(0.5);
-            const M dxuy = (uy[rc + xp] - uy[rc + xm]) * M(0.5);
+            const M dxux = (ld_at(uc, fp) - ld_at(uc, fm)) * M(0.5);
+            const M dxuy = (ld_at(uc + pitch, fp) - ld_at(uc + pitch, fm)) * M(0.5);
             const M dyux = (ux_p - ux_m) * M(0.5);
             const M dyuy = (uy_p - uy_m) * M(0.5);
             Ax = phi * (ux_c * dxux + uy_c * dyux);
             Ay = phi * (ux_c * dxuy + uy_c * dyuy);
         } else if (AUX == 1) {  // d_b(phi u_a u_b) - u_a d_b(phi u_b), phi at the axis neighbours
-            const M pw = phi_at<St, M>(src, a.L, xm, y, a.f16);
-            const M pe = phi_at<St, M>(src, a.L, xp, y, a.f16);
-            const M ps = phi_at<St, M>(src, a.L, x, wrap_dec(y, ny), a.f16);
-            const M pn = phi_at<St, M>(src, a.L, x, yn, a.f16);
-            const M uxw = ux[rc + xm], uyw = uy[rc + xm], uxe = ux[rc + xp], uye = uy[rc + xp];
+            const M pw = phi_at<St, M>(src, a.L, (int)xm, y, a.f16);
+            const M pe = phi_at<St, M>(src, a.L, (int)xp, y, a.f16);
+            const M ps = phi_at<St, M>(src, a.L, (int)xc, ym, a.f16);
+            const M pn = phi_at<St, M>(src, a.L, (int)xc, yn, a.f16);
+            const M uxw = ld_at(uc, fm), uyw = ld_at(uc + pitch, fm), uxe = ld_at(uc, fp), uye = ld_at(uc + pitch, fp);
             const M fwx = pw * uxw, fex = pe * uxe;    // phi u_x at the west and east neighbours
             const M fsy = ps * uy_m, fny = pn * uy_p;  // phi u_y at the south and north neighbours
             const M div = (fex - fwx) * M(0.5) + (fny - fsy) * M(0.5);
             Ax = (fex * uxe - fwx * uxw) * M(0.5) + (fny * ux_p - fsy * ux_m) * M(0.5) - ux_c * div;
             Ay = (fex * uye - fwx * uyw) * M(0.5) + (fny * uy_p - fsy * uy_m) * M(0.5) - uy_c * div;
         }
-        const Relax<M> r = HAS_K ? relax_from_k<M>(kf[rc + x], lam) : rconst;
-        const M s = HAS_S ? sf[rc + x] : M(0);
+        const Relax<M> r = HAS_K ? relax_from_k<M>(ld_at(kf + (int64_t)y * pitch, fc), lam) : rconst;
+        const M s = HAS_S ? ld_at(sf + (int64_t)y * pitch, fc) : M(0);
         M P[9];
         collide<M>(g, ux_c, uy_c, r, Ax, Ay, s, P);
+        if (live) {
+            T *__restrict__ out = dst + (int64_t)y * 9 * pitch;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) dst[i * plane + rc + x] = C::enc(P[i], i, a.f16);
+            for (int i = 0; i < 9; ++i) st_nt_at(out + i * pitch, bc, C::enc(P[i], i, a.f16));
+        }
         ux_m = ux_c;
         uy_m = uy_c;
         ux_c = ux_p;
@@ -146,16 +215,14 @@ __global__ __launch_bounds__(256) void init_kernel(const InitArgs a)
     using T = typename St::T;
     using C = Codec<St, M>;
     const int nx = a.L.nx, ny = a.L.ny;
-    const int64_t N = (int64_t)nx * ny;
+    const int64_t N = (int64_t)nx * ny, pitch = a.L.pitch;
     T *dst = static_cast<T *>(a.dst);
-    const M *ux = static_cast<const M *>(a.ux);
-    const M *uy = static_cast<const M *>(a.uy);
+    const M *u = static_cast<const M *>(a.u);
     bool bad = false;
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(n % nx), y = (int)(n / nx);
-        const int64_t q = (int64_t)y * a.L.pitch + x;
         M P[9];
-        equilibrium<M>((M)a.phi0[n], ux[q], uy[q], P);
+        equilibrium<M>((M)a.phi0[n], u[(int64_t)y * 2 * pitch + x], u[((int64_t)y * 2 + 1) * pitch + x], P);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             int xd = x - kEx[i], yd = y - kEy[i];
@@ -165,7 +232,7 @@ __global__ __launch_bounds__(256) void init_kernel(const InitArgs a)
                 const float v = ((float)P[i] - a.f16.wref[i]) * a.f16.scale;
                 bad |= !(fabsf(v) <= 65504.0f);
             }
-            dst[i * a.L.plane + (int64_t)yd * a.L.pitch + xd] = C::enc(P[i], i, a.f16);
+            dst[((int64_t)yd * 9 + i) * pitch + xd] = C::enc(P[i], i, a.f16);
         }
     }
     if (bad) *a.range_flag = 1;  // every writer stores the same value
@@ -183,7 +250,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const PrepArgs a)
         double v = a.ca * a.a[n];
         if (a.b) v += a.cb * a.b[n];
         if (a.check_positive) bad |= !(v > 0.0 && v < INFINITY);
-        out[(int64_t)y * a.L.pitch + x] = (M)v;
+        out[((int64_t)y * a.stride + a.comp) * a.L.pitch + x] = (M)v;
     }
     if (bad) *a.flag = 1;  // every writer stores the same value
 }
@@ -199,6 +266,7 @@ __device__ __forceinline__ CSum csum_shfl_xor(CSum v, int m)
 }
 
 // Reduces (3 compensated sums, 2 maxima, 1 count) over the block; thread 0 gets the result.
+// Within a wave: butterfly shuffles with TwoSum merges; across the 4 waves: LDS.
 __device__ void block_reduce(CSum (&cs)[3], double &mx0, double &mx1, double &cnt)
 {
     __shared__ double sh[4][10];
@@ -244,11 +312,8 @@ __global__ __launch_bounds__(256) void macros_kernel(const MacroArgs a)
     double maxerr = 0, maxphi = 0, nonfinite = 0;
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(n % nx), y = (int)(n / nx);
-        const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
-        const int64_t rm = (int64_t)wrap_dec(y, ny) * a.L.pitch, rc = (int64_t)y * a.L.pitch,
-                      rp = (int64_t)wrap_inc(y, ny) * a.L.pitch;
         M g[9];
-        pull<St, M>(src, a.L.plane, rm, rc, rp, xm, x, xp, a.f16, g);
+        pull_node<St, M>(src, a.L, x, y, a.f16, g);
         double phi = 0;
 #pragma unroll
         for (int i = 0; i < 9; ++i) phi += (double)g[i];
@@ -312,14 +377,19 @@ __global__ __launch_bounds__(256) void populations_kernel(const PopArgs a)
     const T *src = static_cast<const T *>(a.src);
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(n % nx), y = (int)(n / nx);
-        const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
-        const int64_t rm = (int64_t)wrap_dec(y, ny) * a.L.pitch, rc = (int64_t)y * a.L.pitch,
-                      rp = (int64_t)wrap_inc(y, ny) * a.L.pitch;
         M g[9];
-        pull<St, M>(src, a.L.plane, rm, rc, rp, xm, x, xp, a.f16, g);
+        pull_node<St, M>(src, a.L, x, y, a.f16, g);
 #pragma unroll
         for (int i = 0; i < 9; ++i) a.out[i * N + n] = (double)g[i];
     }
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void copy_kernel(const f32x4 *__restrict__ src, f32x4 *__restrict__ dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) __builtin_nontemporal_store(src[i], dst + i);
 }
 
 int grid_for(int64_t n, int block, int cap)
@@ -333,13 +403,13 @@ template <int MODE, int AUX>
 hipError_t launch_step_aux(const StepArgs &a, hipStream_t st)
 {
     dim3 block(64, 4);
-    const int waves_y = (a.L.ny + a.rows - 1) / a.rows;
-    dim3 grid((a.L.nx + 63) / 64, (waves_y + 3) / 4);
+    const int waves_y = (a.L.ny + a.lc.rows - 1) / a.lc.rows;
+    const int nblocks = ((a.L.nx + 63) / 64) * ((waves_y + 3) / 4);
     const bool hk = a.k != nullptr, hs = a.s != nullptr;
-    if (hk && hs) step_kernel<MODE, AUX, true, true><<<grid, block, 0, st>>>(a);
-    else if (hk) step_kernel<MODE, AUX, true, false><<<grid, block, 0, st>>>(a);
-    else if (hs) step_kernel<MODE, AUX, false, true><<<grid, block, 0, st>>>(a);
-    else step_kernel<MODE, AUX, false, false><<<grid, block, 0, st>>>(a);
+    if (hk && hs) step_kernel<MODE, AUX, true, true><<<nblocks, block, 0, st>>>(a);
+    else if (hk) step_kernel<MODE, AUX, true, false><<<nblocks, block, 0, st>>>(a);
+    else if (hs) step_kernel<MODE, AUX, false, true><<<nblocks, block, 0, st>>>(a);
+    else step_kernel<MODE, AUX, false, false><<<nblocks, block, 0, st>>>(a);
     return hipGetLastError();
 }
 
@@ -357,6 +427,7 @@ hipError_t launch_step_mode(int aux, const StepArgs &a, hipStream_t st)
 
 hipError_t launch_step(int mode, int aux, const StepArgs &a, hipStream_t st)
 {
+    if (a.lc.rows < 1 || a.lc.rows > 64) return hipErrorInvalidValue;
     switch (mode) {
     case MODE_F64_F64: return launch_step_mode<MODE_F64_F64>(aux, a, st);
     case MODE_F64_F32: return launch_step_mode<MODE_F64_F32>(aux, a, st);
@@ -413,6 +484,15 @@ hipError_t launch_populations(int mode, const PopArgs &a, hipStream_t st)
     case MODE_F16S_F32: populations_kernel<MODE_F16S_F32><<<g, 256, 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st)
+{
+    const int64_t n = (int64_t)(bytes / 16);
+    if (n == 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    copy_kernel<<<(unsigned)blocks, 256, 0, st>>>(static_cast<const f32x4 *>(src), static_cast<f32x4 *>(dst), n);
     return hipGetLastError();
 }
 

@@ -56,8 +56,18 @@ class lbm_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class lbm_launch(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
+
+
 EXPORTS = ["lbm_workspace_size", "lbm_init", "lbm_step", "lbm_macros", "lbm_populations", "lbm_state_bytes",
-           "lbm_state_save", "lbm_state_load", "lbm_free", "lbm_last_error", "lbm_abi_version"]
+           "lbm_state_save", "lbm_state_load", "lbm_set_launch", "lbm_get_launch", "lbm_bench_copy", "lbm_free",
+           "lbm_last_error", "lbm_abi_version"]
+
+
+def pitch_of(nx: int) -> int:
+    """Row pitch (elements) of the library's layouts: nx rounded up to a multiple of 64."""
+    return (int(nx) + 63) // 64 * 64
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -74,6 +84,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lbm_state_bytes.argtypes = [P, I32, ctypes.POINTER(SZ)]
     lib.lbm_state_save.argtypes = [P, I32, P]
     lib.lbm_state_load.argtypes = [P, I32, P, I64]
+    lib.lbm_set_launch.argtypes = [P, I32, ctypes.POINTER(lbm_launch)]
+    lib.lbm_get_launch.argtypes = [P, I32, ctypes.POINTER(lbm_launch)]
+    lib.lbm_bench_copy.argtypes = [P, P, SZ, P]
     lib.lbm_free.argtypes = [P]
     lib.lbm_last_error.argtypes = []
     lib.lbm_last_error.restype = ctypes.c_char_p
@@ -185,6 +198,25 @@ def lbm_state_save(ctx, inst: int, dst: torch.Tensor) -> None:
 
 def lbm_state_load(ctx, inst: int, src: torch.Tensor, step: int) -> None:
     _check(lib().lbm_state_load(ctx, int(inst), _dptr(src, src.dtype), int(step)))
+
+
+def lbm_set_launch(ctx, inst: int, rows: int, xcd_remap: int = 1) -> None:
+    cfg = lbm_launch(int(rows), int(xcd_remap))
+    _check(lib().lbm_set_launch(ctx, int(inst), ctypes.byref(cfg)))
+
+
+def lbm_get_launch(ctx, inst: int = 0) -> dict:
+    cfg = lbm_launch()
+    _check(lib().lbm_get_launch(ctx, int(inst), ctypes.byref(cfg)))
+    return {"rows": cfg.rows, "xcd_remap": cfg.xcd_remap}
+
+
+def lbm_bench_copy(dst: torch.Tensor, src: torch.Tensor, stream: Optional[torch.cuda.Stream] = None) -> None:
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < n:
+        raise ValueError("dst smaller than src")
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    _check(lib().lbm_bench_copy(dst.data_ptr(), src.data_ptr(), n, s))
 
 
 def lbm_free(ctx) -> None:

@@ -48,6 +48,12 @@ class Solver:
     def state_load(self, buf: torch.Tensor, step: int, inst: int = 0) -> None:
         L.lbm_state_load(self.ctx, inst, buf, step)
 
+    def set_launch(self, rows: int, xcd_remap: int = 1, inst: int = -1) -> None:
+        L.lbm_set_launch(self.ctx, inst, rows, xcd_remap)
+
+    def get_launch(self, inst: int = 0) -> dict:
+        return L.lbm_get_launch(self.ctx, inst)
+
     def close(self) -> None:
         if self.ctx is not None:
             L.lbm_free(self.ctx)
