@@ -126,6 +126,100 @@ def cpu_baseline(n, budget_s=15.0):
             "sample": f"{n}^2 rotating pulse, {steps} of 3200 steps, FP64 plain C oracle, 1 thread, {el:.1f} s"}
 
 
+KERNEL_MODES = {"0": "f64", "1": "f64s_f32m", "2": "f32", "3": "f16s"}
+
+
+def _csv_rows(path):
+    import csv
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _find(dirpath, suffix):
+    for root, _, files in os.walk(dirpath):
+        for f in files:
+            if f.endswith(suffix):
+                return os.path.join(root, f)
+    raise FileNotFoundError(f"no *{suffix} under {dirpath}")
+
+
+def _kernel_label(name: str):
+    """'step_kernel<2, 0, false, false>' -> ('step', 'f32', aux 0, has_k, has_s); copy/other -> None."""
+    import re
+    m = re.search(r"step_kernel<(\d), (\d), (true|false), (true|false)>", name)
+    if m:
+        return ("step", KERNEL_MODES[m.group(1)], int(m.group(2)), m.group(3) == "true", m.group(4) == "true")
+    if "copy_kernel" in name:
+        return ("copy",)
+    return None
+
+
+def summarize_profiles(trace_dir, pmc_dirs, out_dir, command, pmc_commands):
+    """Writes the committed text summaries of rocprofv3 runs: kernel-trace statistics and the
+    FETCH_SIZE / WRITE_SIZE traffic per dispatch, scaled by the copy kernel's reading."""
+    os.makedirs(out_dir, exist_ok=True)
+    lines = ["# rocprofv3 kernel trace: TRT-R D2Q9 step kernels, rotating pulse 2048^2", "",
+             f"Command: `{command}`", "",
+             "| kernel | mode | calls | average (us) | total (ms) |", "|---|---|---|---|---|"]
+    stats = _csv_rows(_find(trace_dir, "kernel_stats.csv"))
+    for r in stats:
+        lab = _kernel_label(r["Name"])
+        if lab is None:
+            continue
+        mode = lab[1] if lab[0] == "step" else "-"
+        lines.append(f"| {r['Name'][:80]} | {mode} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} |")
+    with open(os.path.join(out_dir, "step_kernel_trace_2048.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+    entries, calib = {}, {}
+    for (counter, n), d in pmc_dirs.items():
+        rows = _csv_rows(_find(d, "counter_collection.csv"))
+        per = {}
+        for r in rows:
+            lab = _kernel_label(r.get("Kernel_Name", ""))
+            if lab is None or r.get("Counter_Name") != counter:
+                continue
+            key = "copy" if lab[0] == "copy" else lab[1]
+            per.setdefault(key, []).append(float(r["Counter_Value"]))
+        copy_kib = sorted(per.pop("copy"))[len(per.get("copy", [])) // 2] if "copy" in per else None
+        if copy_kib is not None:
+            calib[(counter, n)] = copy_kib / (2 * 1024 * 1024)  # copy moves 2 GiB each way
+        for mode, vals in per.items():
+            vals = sorted(vals)
+            e = entries.setdefault(f"{mode}_{n}", {})
+            e[counter + "_KiB_median"] = vals[len(vals) // 2]
+            e[counter + "_dispatches"] = len(vals)
+    for key, e in entries.items():
+        mode, n = key.rsplit("_", 1)
+        n = int(n)
+        fac_f = calib.get(("FETCH_SIZE", n), 1.0)
+        fac_w = calib.get(("WRITE_SIZE", n), 1.0)
+        e["fetch_scale"], e["write_scale"] = fac_f, fac_w
+        if "FETCH_SIZE_KiB_median" in e and "WRITE_SIZE_KiB_median" in e:
+            e["bytes_per_launch"] = 1024.0 * (e["FETCH_SIZE_KiB_median"] / fac_f + e["WRITE_SIZE_KiB_median"] / fac_w)
+            e["algorithmic_bytes_per_launch"] = float(n) * n * bytes_per_lup(mode, False)
+            e["traffic_over_algorithmic"] = e["bytes_per_launch"] / e["algorithmic_bytes_per_launch"]
+    out = {"kernel_hash": kernel_hash(), "commands": pmc_commands, "entries": entries,
+           "copy_scale": {f"{c}_{n}": v for (c, n), v in calib.items()}}
+    with open(os.path.join(out_dir, "step_kernel_pmc.json"), "w") as fh:
+        json.dump(out, fh, indent=1, sort_keys=True)
+    md = ["# HBM traffic of the step kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE, one counter per run)", "",
+          "Each counter is divided by what it reads for the library's 2 GiB copy kernel (scale = KiB read / "
+          "KiB moved).", ""] + [f"- `{c}`" for c in pmc_commands] + [
+          "", "| mode | N | FETCH KiB/dispatch | WRITE KiB/dispatch | fetch scale | write scale | HBM bytes/launch | "
+              "algorithmic bytes/launch | ratio |", "|---|---|---|---|---|---|---|---|---|"]
+    for key in sorted(entries):
+        e = entries[key]
+        mode, n = key.rsplit("_", 1)
+        md.append(f"| {mode} | {n} | {e.get('FETCH_SIZE_KiB_median', float('nan')):.0f} | "
+                  f"{e.get('WRITE_SIZE_KiB_median', float('nan')):.0f} | {e['fetch_scale']:.3f} | {e['write_scale']:.3f} | "
+                  f"{e.get('bytes_per_launch', float('nan')):.4g} | {e.get('algorithmic_bytes_per_launch', float('nan')):.4g} | "
+                  f"{e.get('traffic_over_algorithmic', float('nan')):.3f} |")
+    with open(os.path.join(out_dir, "step_kernel_traffic.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,7 +228,20 @@ def main():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--modes", default="f32,f64,f64s_f32m,f16s")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--summarize", metavar="RUNDIR",
+                    help="write profiles/ summaries from rocprofv3 output under RUNDIR (no GPU needed)")
     args = ap.parse_args()
+    if args.summarize:
+        d = args.summarize
+        pmc = {(c, n): os.path.join(d, f"pmc_{c.lower()}_{n}") for c in ("FETCH_SIZE", "WRITE_SIZE") for n in (2048, 8192)}
+        pmc = {k: v for k, v in pmc.items() if os.path.isdir(v)}
+        summarize_profiles(os.path.join(d, "trace"), pmc, os.path.join(ROOT, "profiles"),
+                           "rocprofv3 --kernel-trace --stats --output-format csv -d RUNDIR/trace -o trace -- "
+                           "python3 bench.py",
+                           [f"rocprofv3 --pmc {c} --output-format csv -d RUNDIR/pmc_{c.lower()}_{n} -o pmc -- "
+                            f"python3 bench.py --n {n} --steps 12 --warmup 0 --modes f32,f64,f16s --no-cpu"
+                            for (c, n) in sorted(pmc)])
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built",
               file=sys.stderr)
@@ -193,7 +300,9 @@ def main():
                    "aux": "local (Eq. 16)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": None if traffic is None else round(traffic * n2 / n2, 1),
+                     "traffic": None if traffic is None else round(traffic),
+                     "traffic_unit": "HBM bytes/launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes_per_launch": int(n2 * r["bytes_per_lup"]),
                      "bytes_per_lup": r["bytes_per_lup"], "lups_per_launch": int(n2),
                      "copy_gbps_measured": round(copy_gbps, 1),
                      "frac_of_copy": round(achieved / copy_gbps, 4)},
