@@ -89,6 +89,56 @@ def run_mode(mode, n, steps, warmup, torch, W, lbm, Solver, graph=True):
     }, phi
 
 
+def run_batched(torch, W, lbm, Solver, n_inst=256, steps=2000, eager_steps=100):
+    """The seeded batch of uneven pulse instances (FP32): aggregate MLUPS of serial per-instance
+    launches (eager, and graph-replayed) against the autotuned single-launch batched step."""
+    from paper_2312_10316_amd import autotune
+    draws = W.batched_instances(n_inst, steps=steps)
+    insts = []
+    for d in draws:
+        cfg = d.config
+        f = W.rotating_pulse(cfg)
+        p = lbm.make_params(cfg.N, cfg.N, f["dx"], f["dt"], cfg.lam, cfg.D, "f32")
+        insts.append((p, {k: torch.from_numpy(f[k]).cuda() for k in ("phi0", "ux", "uy")}))
+    nodes = float(sum(d.N * d.N for d in draws))
+    s = Solver(insts)
+
+    def timed(fn, nsteps):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        fn()
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / nsteps
+
+    out = {"instances": n_inst, "nodes": int(nodes), "steps": steps, "storage": "f32",
+           "sizes": f"N log-uniform in [32, 512], seed 231210316 (min {min(d.N for d in draws)}, "
+                    f"max {max(d.N for d in draws)})"}
+    s.set_batch(lbm.LBM_BATCH_SERIAL)
+    s.step(2)
+
+    def eager():
+        for _ in range(eager_steps):
+            s.step(1)
+    ms = timed(eager, eager_steps)
+    out["serial_eager"] = {"ms_per_step": ms, "mlups": nodes / (ms * 1e-3) / 1e6}
+    s.step(64)
+    ms = timed(lambda: s.step(steps), steps)
+    out["serial_graph"] = {"ms_per_step": ms, "mlups": nodes / (ms * 1e-3) / 1e6}
+    t = autotune.tune(s, steps=64, reps=2)
+    ms = timed(lambda: s.step(steps), steps)
+    out["batched"] = {"ms_per_step": ms, "mlups": nodes / (ms * 1e-3) / 1e6,
+                      "config": {"rows": t["best"][0], "xcd_remap": t["best"][1],
+                                 "policy": ["serial", "flat", "strided", "lpt"][t["best"][2]], "blocks": t["best"][3]}}
+    out["speedup_vs_serial_graph"] = out["serial_graph"]["ms_per_step"] / ms
+    out["speedup_vs_serial_eager"] = out["serial_eager"]["ms_per_step"] / ms
+    out["nonfinite_instances"] = sum(1 for k in range(n_inst) if s.macros(k, raise_nonfinite=False)["nonfinite"] > 0)
+    s.close()
+    return out
+
+
 def copy_bandwidth(torch, lbm, nbytes=2 << 30, reps=20):
     """Read + write bandwidth of the library's plain streaming copy kernel (2 GiB, one pass)."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -228,6 +278,7 @@ def main():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--modes", default="f32,f64,f64s_f32m,f16s")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--summarize", metavar="RUNDIR",
                     help="write profiles/ summaries from rocprofv3 output under RUNDIR (no GPU needed)")
     args = ap.parse_args()
@@ -239,7 +290,7 @@ def main():
                            "rocprofv3 --kernel-trace --stats --output-format csv -d RUNDIR/trace -o trace -- "
                            "python3 bench.py",
                            [f"rocprofv3 --pmc {c} --output-format csv -d RUNDIR/pmc_{c.lower()}_{n} -o pmc -- "
-                            f"python3 bench.py --n {n} --steps 12 --warmup 0 --modes f32,f64,f16s --no-cpu"
+                            f"python3 bench.py --n {n} --steps 12 --warmup 0 --modes f32,f64,f16s --no-cpu --no-batched"
                             for (c, n) in sorted(pmc)])
         return
     if args.gpus != 1:
@@ -309,6 +360,11 @@ def main():
         "modes": {m: {k: (round(v, 6) if isinstance(v, float) and abs(v) >= 1e-3 else v) for k, v in results[m].items()}
                   for m in modes},
     }
+    if not args.no_batched:
+        out["batched"] = run_batched(torch, W, lbm, Solver)
+        print(f"# batched: {out['batched']['batched']['mlups']:.0f} MLUPS vs serial graph "
+              f"{out['batched']['serial_graph']['mlups']:.0f}, eager {out['batched']['serial_eager']['mlups']:.0f}",
+              file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.n)
     print(json.dumps(out))

@@ -149,9 +149,54 @@ typedef struct lbm_launch {
     int32_t xcd_remap;  /* 1: consecutive tiles go to blocks on the same XCD (shared L2); 0: hardware order */
 } lbm_launch;
 
-/* Sets (inst = -1: every instance) or reads the launch shape; captured step graphs are dropped. */
+/* Sets (inst = -1: every instance) or reads the launch shape; captured step graphs are dropped.
+ * lbm_set_launch synchronizes the stream. */
 int lbm_set_launch(lbm_ctx *ctx, int32_t inst, const lbm_launch *cfg);
 int lbm_get_launch(lbm_ctx *ctx, int32_t inst, lbm_launch *cfg);
+
+/* How a multi-instance context advances its instances each step.
+ *   SERIAL:  one kernel launch per instance.
+ *   FLAT:    one launch for all instances, one 256-thread block per tile (tiles of all instances in
+ *            one XCD-contiguous list).
+ *   STRIDED: one launch, `blocks` persistent blocks taking the tiles round-robin.
+ *   LPT:     one launch, `blocks` persistent blocks; tiles go longest-first to the least-loaded block.
+ * Batched policies need every instance to share store, math and aux (else LBM_E_UNSUPPORTED).
+ * Default: FLAT when possible with more than one instance, else SERIAL.  Results are bitwise
+ * independent of the policy. */
+enum lbm_batch_policy { LBM_BATCH_SERIAL = 0, LBM_BATCH_FLAT = 1, LBM_BATCH_STRIDED = 2, LBM_BATCH_LPT = 3 };
+typedef struct lbm_batch {
+    int32_t policy;  /* enum lbm_batch_policy */
+    int32_t blocks;  /* persistent blocks for STRIDED / LPT (>= 1; capped at the number of tiles) */
+} lbm_batch;
+
+/* Sets or reads the batch policy; captured step graphs are dropped.  Synchronizes the stream. */
+int lbm_set_batch(lbm_ctx *ctx, const lbm_batch *cfg);
+int lbm_get_batch(lbm_ctx *ctx, lbm_batch *cfg);
+
+/* ---- Adjoint (reverse mode) of the step, for gradients with respect to D(x) ------------------
+ * With u, D and S fixed, one step is affine in the populations: g^{n+1}_i(x + e_i) = sum_j M_ij(x)
+ * g^n_j(x) + c_i(x) (Eq. (14); the equilibrium, Eq. (6), and the auxiliary term, Eq. (16), are linear in
+ * phi).  Adjoint arrays ("lam") hold dL/dg in the arithmetic type (FP64 for LBM_MATH_F64, else FP32),
+ * layout [ny][9][pitch] (pitch as in the state image), element (y, i, x) = dL/dg_i(x, y).
+ * Supported for FP64 and FP32 storage with aux LOCAL or NONE (else LBM_E_UNSUPPORTED).  All
+ * asynchronous on the context's stream; the caller owns every buffer. */
+
+/* Bytes of one adjoint array of instance inst. */
+int lbm_adjoint_bytes(lbm_ctx *ctx, int32_t inst, size_t *bytes);
+
+/* lam_i(x) = dLdphi(x) for every i: the adjoint of phi = sum_i g_i.  dLdphi: device FP64 [ny][nx]. */
+int lbm_adjoint_seed(lbm_ctx *ctx, int32_t inst, const double *dLdphi, void *lam);
+
+/* One step backwards: lam_out_j(x) = sum_i M_ij(x) lam_in_i(x + e_i) (lam_in = dL/dg^{n+1},
+ * lam_out = dL/dg^n; they must not alias), and dLdD(x) += sum_i lam_in_i(x + e_i) dP_i(x)/dD(x)
+ * evaluated at g^n, which `state` holds as a state image (lbm_state_save format).  dLdD: device FP64
+ * [ny][nx], accumulated.  u, D and the source are the instance's current ones. */
+int lbm_adjoint_step(lbm_ctx *ctx, int32_t inst, const void *state, const void *lam_in, void *lam_out,
+                     double *dLdD);
+
+/* dLdphi0(x) = sum_i lam0_i(x) dg_eq_i/dphi0(x): the adjoint of the initial condition
+ * g = g_eq(phi0, u).  dLdphi0: device FP64 [ny][nx] (overwritten). */
+int lbm_adjoint_init(lbm_ctx *ctx, int32_t inst, const void *lam0, double *dLdphi0);
 
 /* Plain streaming copy of `bytes` bytes (multiple of 16; both pointers device, 16-byte aligned) on
  * `stream`: 16-byte vector loads and non-temporal stores, one pass.  Not part of the method: it is

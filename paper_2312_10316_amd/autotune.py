@@ -1,0 +1,123 @@
+"""Autotuner for the step launch: tile shape (rows walked per wave, XCD tile order) and, for a
+multi-instance context, the batch schedule (serial launches, one flat launch, or persistent blocks
+with a round-robin or longest-processing-time assignment of tiles).
+
+Candidates are timed on the caller's own instances with graph-replayed steps; the instances' states
+and step counters are saved first and restored afterwards, so tuning never advances the simulation
+(results do not depend on the launch configuration, bitwise).  Winners are cached in memory and,
+optionally, in a JSON file keyed by the device and the instance shapes.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+from typing import Iterable, Optional
+
+import torch
+
+from . import lbm as L
+
+_MEMO: dict = {}
+
+
+def _key(solver) -> str:
+    dev = torch.cuda.get_device_name()
+    shapes = [(p.nx, p.ny, p.store, p.math, p.aux) for p in solver.params]
+    return hashlib.sha256(json.dumps([dev, shapes]).encode()).hexdigest()[:20]
+
+
+def default_candidates(solver) -> list:
+    """(rows, xcd_remap, policy, blocks) tuples worth timing for this context."""
+    rows_set = (1, 2, 4)
+    out = []
+    multi = len(solver.params) > 1 and len({(p.store, p.math, p.aux) for p in solver.params}) == 1
+    if not multi:
+        for rows in rows_set:
+            for remap in (0, 1):
+                out.append((rows, remap, L.LBM_BATCH_SERIAL, 0))
+        return out
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    for rows in rows_set:
+        out.append((rows, 1, L.LBM_BATCH_SERIAL, 0))
+        out.append((rows, 1, L.LBM_BATCH_FLAT, 0))
+        for mult in (2, 4, 8):
+            out.append((rows, 1, L.LBM_BATCH_LPT, mult * ncu))
+        out.append((rows, 1, L.LBM_BATCH_STRIDED, 4 * ncu))
+    return out
+
+
+def _apply(solver, cand) -> None:
+    rows, remap, policy, blocks = cand
+    solver.set_launch(rows, remap)
+    if len(solver.params) > 1:
+        try:
+            solver.set_batch(policy, blocks)
+        except L.LbmError as e:
+            if e.status != L.LBM_E_UNSUPPORTED:
+                raise
+
+
+def _time(solver, steps: int, reps: int) -> float:
+    solver.step(steps)  # warm-up (captures the graph)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(solver.stream)
+        solver.step(steps)
+        e1.record(solver.stream)
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / steps)
+    return best
+
+
+def tune(solver, candidates: Optional[Iterable] = None, steps: int = 64, reps: int = 2,
+         cache_path: Optional[str] = None, force: bool = False) -> dict:
+    """Times every candidate, applies the fastest and returns
+    {"best": (rows, xcd_remap, policy, blocks), "ms_per_step": {...}, "cached": bool}."""
+    key = _key(solver)
+    cached = None
+    if not force:
+        cached = _MEMO.get(key)
+        if cached is None and cache_path and os.path.exists(cache_path):
+            with open(cache_path) as fh:
+                cached = json.load(fh).get(key)
+    if cached is not None:
+        _apply(solver, tuple(cached["best"]))
+        return dict(cached, cached=True)
+
+    n = len(solver.params)
+    saved = [solver.state_save(k) for k in range(n)]
+    steps0 = [solver.macros(k, raise_nonfinite=False)["step"] for k in range(n)]
+    old_launch = [solver.get_launch(k) for k in range(n)]
+    old_batch = solver.get_batch() if n > 1 else None
+    times = {}
+    try:
+        for cand in (candidates or default_candidates(solver)):
+            _apply(solver, cand)
+            times[json.dumps(list(cand))] = _time(solver, steps, reps)
+    finally:
+        for k in range(n):
+            solver.set_launch(old_launch[k]["rows"], old_launch[k]["xcd_remap"], inst=k)
+        if old_batch is not None:
+            solver.set_batch(old_batch["policy"], old_batch["blocks"])
+        for k in range(n):
+            solver.state_load(saved[k], steps0[k], inst=k)
+        torch.cuda.synchronize()
+    best = min(times, key=times.get)
+    result = {"best": json.loads(best), "ms_per_step": times}
+    _apply(solver, tuple(result["best"]))
+    _MEMO[key] = result
+    if cache_path:
+        data = {}
+        if os.path.exists(cache_path):
+            with open(cache_path) as fh:
+                data = json.load(fh)
+        data[key] = result
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(data, fh, indent=1)
+        os.replace(tmp, cache_path)
+    return dict(result, cached=False)

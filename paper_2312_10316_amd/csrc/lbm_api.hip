@@ -1,12 +1,16 @@
 // lbm_api.hip -- C ABI of the TRT-R D2Q9 library (declared in include/lbm.h).
 //
-// Host side only: argument validation, the workspace layout, and the order of kernel launches on
-// the caller's stream.  Every arithmetic step of the method runs in the kernels of lbm_kernels.hip.
+// Host side only: argument validation, the workspace layout, the batch schedule, graph capture and
+// the order of kernel launches on the caller's stream.  Every arithmetic step of the method runs in
+// the kernels of lbm_kernels.hip.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
+#include <queue>
 #include <vector>
 
 #include "../../include/lbm.h"
@@ -27,10 +31,7 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
-int hip_fail(hipError_t e, const char *what)
-{
-    return fail(LBM_E_HIP, "%s: %s", what, hipGetErrorString(e));
-}
+int hip_fail(hipError_t e, const char *what) { return fail(LBM_E_HIP, "%s: %s", what, hipGetErrorString(e)); }
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -54,8 +55,8 @@ Layout layout_of(const lbm_params &p)
 }
 
 // Default launch shape per storage mode (measured on MI355X at 2048^2 and 8192^2; the autotuner in
-// the Python package can override it per instance): one row per wave with XCD-contiguous tiles
-// for FP64/FP32; FP16 codes (2 bytes per lane) prefer a 4-row walk.
+// the Python package can override it per instance): one row per wave with XCD-contiguous tiles for
+// FP64/FP32; FP16 codes (2 bytes per lane) prefer a 4-row walk.
 Launch default_launch(int mode) { return mode == MODE_F16S_F32 ? Launch{4, 1} : Launch{1, 1}; }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -63,8 +64,7 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 int validate(const lbm_params &p, int k)
 {
     if (p.nx < 3 || p.ny < 3) return fail(LBM_E_ARG, "instance %d: nx=%d, ny=%d must be >= 3", k, p.nx, p.ny);
-    if ((int64_t)p.nx * p.ny > ((int64_t)1 << 31))
-        return fail(LBM_E_ARG, "instance %d: nx*ny exceeds 2^31 nodes", k);
+    if ((int64_t)p.nx * p.ny > ((int64_t)1 << 31)) return fail(LBM_E_ARG, "instance %d: nx*ny exceeds 2^31 nodes", k);
     if (!finite_pos(p.dx) || !finite_pos(p.dt)) return fail(LBM_E_ARG, "instance %d: dx and dt must be finite and > 0", k);
     if (!finite_pos(p.lambda)) return fail(LBM_E_ARG, "instance %d: lambda must be finite and > 0", k);
     if (p.store < LBM_STORE_F64 || p.store > LBM_STORE_F16S) return fail(LBM_E_ARG, "instance %d: unknown store %d", k, p.store);
@@ -80,30 +80,6 @@ int validate(const lbm_params &p, int k)
     return LBM_OK;
 }
 
-struct Instance {
-    lbm_params p;
-    int mode;
-    Layout L;
-    Launch lc;
-    char *buf[2];
-    void *u, *k, *s;
-    bool has_D;
-    bool has_src;
-    int cur;
-    int64_t step;
-    F16Params f16;
-};
-
-// Per instance: 2 population buffers, the velocity pair, and the k and s fields (math type).
-size_t pops_bytes(const lbm_params &p) { return align_up((size_t)pop_elems(layout_of(p)) * store_bytes(mode_of(p)), kAlign); }
-size_t vel_bytes(const lbm_params &p) { return align_up((size_t)vel_elems(layout_of(p)) * math_bytes(mode_of(p)), kAlign); }
-size_t field_bytes(const lbm_params &p) { return align_up((size_t)fld_elems(layout_of(p)) * math_bytes(mode_of(p)), kAlign); }
-size_t instance_bytes(const lbm_params &p) { return 2 * pops_bytes(p) + vel_bytes(p) + 2 * field_bytes(p); }
-
-// Shared scratch: macro partials, the macro result, and a flag word.
-constexpr size_t kPartialBytes = (size_t)kMacroBlocks * kMacroPartialDoubles * sizeof(double);
-constexpr size_t kScratchBytes = kPartialBytes + 256 + 256;
-
 F16Params f16_of(const lbm_params &p)
 {
     F16Params f{};
@@ -117,27 +93,187 @@ F16Params f16_of(const lbm_params &p)
     return f;
 }
 
+struct Instance {
+    lbm_params p;
+    int mode;
+    Layout L;
+    Launch lc;
+    char *buf[2];
+    void *u, *k, *s;
+    bool has_D;
+    bool has_src;
+    int64_t step;
+    F16Params f16;
+};
+
+// Per instance: 2 population buffers, the velocity pair, and the k and s fields (math type).
+size_t pops_bytes(const lbm_params &p) { return align_up((size_t)pop_elems(layout_of(p)) * store_bytes(mode_of(p)), kAlign); }
+size_t vel_bytes(const lbm_params &p) { return align_up((size_t)vel_elems(layout_of(p)) * math_bytes(mode_of(p)), kAlign); }
+size_t field_bytes(const lbm_params &p) { return align_up((size_t)fld_elems(layout_of(p)) * math_bytes(mode_of(p)), kAlign); }
+size_t instance_bytes(const lbm_params &p) { return 2 * pops_bytes(p) + vel_bytes(p) + 2 * field_bytes(p); }
+
+size_t max_items_of(int32_t n_inst, const lbm_params *p)
+{
+    size_t items = 0;  // one row per wave gives the most tiles
+    for (int k = 0; k < n_inst; ++k) items += (size_t)tiles_of(layout_of(p[k]), 1);
+    return items;
+}
+
+// Shared scratch: macro partials, the macro result, two flag words; then the batch tables
+// (instance descriptors, work items, block ranges).
+constexpr size_t kPartialBytes = (size_t)kMacroBlocks * kMacroPartialDoubles * sizeof(double);
+constexpr size_t kScratchBytes = kPartialBytes + 256 + 256;
+
+size_t tables_bytes(int32_t n_inst, const lbm_params *p)
+{
+    const size_t items = max_items_of(n_inst, p);
+    return align_up((size_t)n_inst * sizeof(InstDesc), kAlign) + align_up(items * sizeof(WorkItem), kAlign) +
+           align_up((items + 1) * sizeof(int32_t), kAlign);
+}
+
+// Constant-D relaxation: tau1 - 1/2 = kappa / (cs^2 dt) = 3 kappa dt / dx^2 (Sec. 2.4), and
+// tau2 - 1/2 = Lambda / (tau1 - 1/2) (magic parameter, Sec. 2.4).
+void const_relax(const lbm_params &p, double &w1, double &w2, double &beta)
+{
+    const double k = 3.0 * p.D_const * p.dt / (p.dx * p.dx);
+    const double tau1 = 0.5 + k, tau2 = 0.5 + p.lambda / k;
+    w1 = 1.0 - 1.0 / tau1;
+    w2 = 1.0 - 1.0 / tau2;
+    beta = 1.0 - 0.5 / tau1;
+}
+
+InstDesc desc_of(const Instance &in)
+{
+    InstDesc d{};
+    d.buf[0] = in.buf[0];
+    d.buf[1] = in.buf[1];
+    d.u = in.u;
+    d.k = in.k;
+    d.s = in.s;
+    d.L = in.L;
+    d.lc = in.lc;
+    d.has_k = in.has_D ? 1 : 0;
+    d.has_s = in.has_src ? 1 : 0;
+    if (!in.has_D) const_relax(in.p, d.w1, d.w2, d.beta);
+    d.lambda = in.p.lambda;
+    d.f16 = in.f16;
+    return d;
+}
+
 }  // namespace
 
 // Long runs replay a captured graph of kGraphSteps steps (an even count, so every buffer returns
-// to its role); one graph per buffer parity, re-captured when the set of instances with a source
-// changes.
+// to its role); one graph per buffer parity, dropped whenever a descriptor or the schedule changes.
 constexpr int kGraphSteps = 32;
 
 struct lbm_ctx {
     std::vector<Instance> inst;
+    int parity = 0;                   // the buffer every instance currently reads (they step together)
+    bool uniform = false;             // all instances share mode and aux (a batched launch is possible)
+    lbm_batch batch = {LBM_BATCH_SERIAL, 0};
+    InstDesc *d_desc = nullptr;       // device tables (in the workspace)
+    WorkItem *d_items = nullptr;
+    int32_t *d_block_start = nullptr;
+    int nblocks = 0;                  // grid of the batched launch
+    bool use_block_start = false;
+    std::vector<InstDesc> h_desc;     // host staging of the tables
+    std::vector<WorkItem> h_items;
+    std::vector<int32_t> h_block_start;
     hipStream_t stream = nullptr;
-    hipStream_t capture = nullptr;  // private stream used only to record graphs
+    hipStream_t capture = nullptr;    // private stream used only to record graphs
     char *ws = nullptr;
     bool owns_ws = false;
     double *partials = nullptr;
     double *result = nullptr;
     int *flag = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
-    std::vector<bool> graph_src[2];
 };
 
 namespace {
+
+bool check_inst(lbm_ctx *c, int32_t inst) { return c && inst >= 0 && inst < (int32_t)c->inst.size(); }
+
+void drop_graphs(lbm_ctx *c)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (c->graph[k]) (void)hipGraphExecDestroy(c->graph[k]);
+        c->graph[k] = nullptr;
+    }
+}
+
+bool batched(const lbm_ctx *c) { return c->inst.size() > 1 && c->uniform && c->batch.policy != LBM_BATCH_SERIAL; }
+
+// Rebuilds the descriptors and (for a batched policy) the work list, and uploads them.  The host
+// staging vectors are only rewritten after the stream has drained.
+int refresh_tables(lbm_ctx *c)
+{
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "synchronizing before a table update");
+    drop_graphs(c);
+    const int n = (int)c->inst.size();
+    c->h_desc.resize(n);
+    for (int k = 0; k < n; ++k) c->h_desc[k] = desc_of(c->inst[k]);
+    e = hipMemcpyAsync(c->d_desc, c->h_desc.data(), n * sizeof(InstDesc), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "uploading instance descriptors");
+    if (batched(c)) {
+        // work items in instance order; cost = live nodes of the tile
+        std::vector<WorkItem> items;
+        std::vector<int64_t> cost;
+        for (int k = 0; k < n; ++k) {
+            const Layout &L = c->inst[k].L;
+            const int rows = c->inst[k].lc.rows, ntx = (L.nx + 63) / 64, nt = tiles_of(L, rows);
+            for (int t = 0; t < nt; ++t) {
+                const int x0 = (t % ntx) * 64, y0 = (t / ntx) * 4 * rows;
+                items.push_back(WorkItem{k, t});
+                cost.push_back((int64_t)std::min(64, L.nx - x0) * std::min(4 * rows, L.ny - y0));
+            }
+        }
+        const int ni = (int)items.size();
+        const lbm_batch &b = c->batch;
+        if (b.policy == LBM_BATCH_FLAT) {
+            c->h_items = items;
+            c->use_block_start = false;
+            c->nblocks = ni;
+        } else {
+            const int P = std::min(b.blocks, ni);
+            std::vector<std::vector<int>> per(P);
+            if (b.policy == LBM_BATCH_STRIDED) {
+                for (int i = 0; i < ni; ++i) per[i % P].push_back(i);
+            } else {  // LPT: longest tile first, to the least-loaded block
+                std::vector<int> order(ni);
+                for (int i = 0; i < ni; ++i) order[i] = i;
+                std::stable_sort(order.begin(), order.end(), [&](int a, int z) { return cost[a] > cost[z]; });
+                using Load = std::pair<int64_t, int>;
+                std::priority_queue<Load, std::vector<Load>, std::greater<Load>> pq;
+                for (int j = 0; j < P; ++j) pq.push({0, j});
+                for (int i : order) {
+                    Load l = pq.top();
+                    pq.pop();
+                    per[l.second].push_back(i);
+                    pq.push({l.first + cost[i], l.second});
+                }
+                for (auto &v : per) std::sort(v.begin(), v.end());  // each block walks its tiles in memory order
+            }
+            c->h_items.clear();
+            c->h_block_start.assign(P + 1, 0);
+            for (int j = 0; j < P; ++j) {
+                c->h_block_start[j] = (int32_t)c->h_items.size();
+                for (int i : per[j]) c->h_items.push_back(items[i]);
+            }
+            c->h_block_start[P] = (int32_t)c->h_items.size();
+            c->use_block_start = true;
+            c->nblocks = P;
+            e = hipMemcpyAsync(c->d_block_start, c->h_block_start.data(), (P + 1) * sizeof(int32_t),
+                               hipMemcpyHostToDevice, c->stream);
+            if (e != hipSuccess) return hip_fail(e, "uploading block ranges");
+        }
+        e = hipMemcpyAsync(c->d_items, c->h_items.data(), c->h_items.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
+                           c->stream);
+        if (e != hipSuccess) return hip_fail(e, "uploading work items");
+    }
+    e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "synchronizing after a table update");
+}
 
 int prep_field(lbm_ctx *c, Instance &in, const double *a, const double *b, double ca, double cb, void *out,
                int check_positive, int stride = 1, int comp = 0)
@@ -165,60 +301,37 @@ int set_velocity(lbm_ctx *c, Instance &in, const double *ux, const double *uy)
     return rc;
 }
 
-bool check_inst(lbm_ctx *c, int32_t inst)
-{
-    return c && inst >= 0 && inst < (int32_t)c->inst.size();
-}
-
-// Enqueues one step of every instance on stream st (buffers chosen from each instance's cur).
+// Enqueues one step of every instance on stream st.
 int enqueue_step(lbm_ctx *c, hipStream_t st)
 {
-    for (Instance &in : c->inst) {
-        StepArgs a;
-        a.src = in.buf[in.cur];
-        a.dst = in.buf[in.cur ^ 1];
-        a.u = in.u;
-        a.k = in.has_D ? in.k : nullptr;
-        a.s = in.has_src ? in.s : nullptr;
-        a.L = in.L;
-        a.lc = in.lc;
-        // constant D: tau1 - 1/2 = kappa / (cs^2 dt) = 3 kappa dt / dx^2, tau2 - 1/2 = Lambda / (tau1 - 1/2)
-        const double k = 3.0 * in.p.D_const * in.p.dt / (in.p.dx * in.p.dx);
-        const double tau1 = 0.5 + k, tau2 = 0.5 + in.p.lambda / k;
-        a.w1 = 1.0 - 1.0 / tau1;
-        a.w2 = 1.0 - 1.0 / tau2;
-        a.beta = 1.0 - 0.5 / tau1;
-        a.lambda = in.p.lambda;
-        a.f16 = in.f16;
-        hipError_t e = launch_step(in.mode, in.p.aux, a, st);
-        if (e != hipSuccess) return hip_fail(e, "step kernel launch");
-        in.cur ^= 1;
+    if (batched(c)) {
+        BatchArgs a;
+        a.inst = c->d_desc;
+        a.items = c->d_items;
+        a.block_start = c->use_block_start ? c->d_block_start : nullptr;
+        a.parity = c->parity;
+        hipError_t e = launch_batched_step(c->inst[0].mode, c->inst[0].p.aux, a, c->nblocks, st);
+        if (e != hipSuccess) return hip_fail(e, "batched step kernel launch");
+    } else {
+        for (size_t k = 0; k < c->inst.size(); ++k) {
+            StepArgs a;
+            a.d = c->h_desc[k];
+            a.parity = c->parity;
+            hipError_t e = launch_step(c->inst[k].mode, c->inst[k].p.aux, a, st);
+            if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+        }
     }
+    c->parity ^= 1;
     return LBM_OK;
-}
-
-void drop_graphs(lbm_ctx *c)
-{
-    for (int k = 0; k < 2; ++k) {
-        if (c->graph[k]) (void)hipGraphExecDestroy(c->graph[k]);
-        c->graph[k] = nullptr;
-        c->graph_src[k].clear();
-    }
 }
 
 // Returns the graph of kGraphSteps steps for the current buffer parity, capturing it if needed.
 int graph_for(lbm_ctx *c, hipGraphExec_t *out)
 {
-    const int par = c->inst[0].cur;
-    std::vector<bool> src(c->inst.size());
-    for (size_t k = 0; k < c->inst.size(); ++k) src[k] = c->inst[k].has_src;
-    if (c->graph[par] && c->graph_src[par] == src) {
+    const int par = c->parity;
+    if (c->graph[par]) {
         *out = c->graph[par];
         return LBM_OK;
-    }
-    if (c->graph[par]) {
-        (void)hipGraphExecDestroy(c->graph[par]);
-        c->graph[par] = nullptr;
     }
     if (!c->capture) {
         hipError_t e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking);
@@ -240,7 +353,6 @@ int graph_for(lbm_ctx *c, hipGraphExec_t *out)
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
     c->graph[par] = x;
-    c->graph_src[par] = src;
     *out = x;
     return LBM_OK;
 }
@@ -263,7 +375,7 @@ int lbm_workspace_size(int32_t n_inst, const lbm_params *p, size_t *bytes)
         if (rc) return rc;
         total += instance_bytes(p[k]);
     }
-    *bytes = total;
+    *bytes = total + tables_bytes(n_inst, p);
     return LBM_OK;
 }
 
@@ -283,8 +395,7 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
             return fail(LBM_E_ARG, "instance %d: D_const must be finite and > 0 when D is NULL", k);
     }
     if (workspace) {
-        if (workspace_bytes < need)
-            return fail(LBM_E_ARG, "lbm_init: workspace of %zu bytes, %zu needed", workspace_bytes, need);
+        if (workspace_bytes < need) return fail(LBM_E_ARG, "lbm_init: workspace of %zu bytes, %zu needed", workspace_bytes, need);
         if ((uintptr_t)workspace % kAlign) return fail(LBM_E_ARG, "lbm_init: workspace not 256-byte aligned");
     }
     lbm_ctx *c = new (std::nothrow) lbm_ctx();
@@ -306,13 +417,14 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
     c->flag = reinterpret_cast<int *>(w + kPartialBytes + 256);
     w += align_up(kScratchBytes, kAlign);
     c->inst.resize(n_inst);
+    c->uniform = true;
     for (int k = 0; k < n_inst; ++k) {
         Instance &in = c->inst[k];
         in.p = p[k];
         in.mode = mode_of(p[k]);
         in.L = layout_of(p[k]);
-        const size_t pb = pops_bytes(p[k]), vb = vel_bytes(p[k]), fb = field_bytes(p[k]);
         in.lc = default_launch(in.mode);
+        const size_t pb = pops_bytes(p[k]), vb = vel_bytes(p[k]), fb = field_bytes(p[k]);
         in.buf[0] = w;
         in.buf[1] = w + pb;
         w += 2 * pb;
@@ -323,12 +435,20 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
         w += 2 * fb;
         in.has_D = f[k].D != nullptr;
         in.has_src = false;
-        in.cur = 0;
         in.step = 0;
         in.f16 = f16_of(p[k]);
+        if (in.mode != c->inst[0].mode || in.p.aux != c->inst[0].p.aux) c->uniform = false;
     }
+    const size_t items = max_items_of(n_inst, p);
+    c->d_desc = reinterpret_cast<InstDesc *>(w);
+    w += align_up((size_t)n_inst * sizeof(InstDesc), kAlign);
+    c->d_items = reinterpret_cast<WorkItem *>(w);
+    w += align_up(items * sizeof(WorkItem), kAlign);
+    c->d_block_start = reinterpret_cast<int32_t *>(w);
+    if (n_inst > 1 && c->uniform) c->batch = lbm_batch{LBM_BATCH_FLAT, 0};
+
     // Zero everything the library owns (padding columns included) so that a state is a
-    // deterministic byte image, then clear the flags.
+    // deterministic byte image; this also clears the flags.
     hipError_t e = hipMemsetAsync(c->ws, 0, need, c->stream);
     if (e != hipSuccess) {
         lbm_free(c);
@@ -357,9 +477,9 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) rc = hip_fail(e, "lbm_init: synchronizing");
     }
-    if (rc == LBM_OK && flag[0])
-        rc = fail(LBM_E_ARG, "lbm_init: an F16S population does not fit FP16 at this scale_log2");
+    if (rc == LBM_OK && flag[0]) rc = fail(LBM_E_ARG, "lbm_init: an F16S population does not fit FP16 at this scale_log2");
     if (rc == LBM_OK && flag[1]) rc = fail(LBM_E_ARG, "lbm_init: D field has a value that is not finite and > 0");
+    if (rc == LBM_OK) rc = refresh_tables(c);
     if (rc != LBM_OK) {
         char keep[512];
         std::memcpy(keep, g_err, sizeof keep);
@@ -384,13 +504,17 @@ int lbm_step(lbm_ctx *c, int32_t nsteps, const double *const *ux, const double *
         for (int k = 0; k < n; ++k)
             if (!ux[k] || !uy[k]) return fail(LBM_E_ARG, "lbm_step: instance %d: NULL velocity entry", k);
     int rc = LBM_OK;
+    bool changed = false;
     for (int k = 0; k < n && rc == LBM_OK; ++k) {
         Instance &in = c->inst[k];
         if (ux) rc = set_velocity(c, in, ux[k], uy[k]);
-        in.has_src = S && S[k];
-        if (rc == LBM_OK && in.has_src)  // s = dt S + dt^2/2 dS/dt (Eq. (14), source terms)
+        const bool src = S && S[k];
+        changed |= src != in.has_src;
+        in.has_src = src;
+        if (rc == LBM_OK && src)  // s = dt S + dt^2/2 dS/dt (Eq. (14), source terms)
             rc = prep_field(c, in, S[k], dSdt ? dSdt[k] : nullptr, in.p.dt, 0.5 * in.p.dt * in.p.dt, in.s, 0);
     }
+    if (rc == LBM_OK && changed) rc = refresh_tables(c);
     if (rc) return rc;
     int left = nsteps;
     if (left >= 2 * kGraphSteps) {
@@ -417,7 +541,7 @@ int lbm_macros(lbm_ctx *c, int32_t inst, double *phi_out, const double *ref, lbm
     if (!out) return fail(LBM_E_ARG, "lbm_macros: out is NULL");
     Instance &in = c->inst[inst];
     MacroArgs a;
-    a.src = in.buf[in.cur];
+    a.src = in.buf[c->parity];
     a.ref = ref;
     a.phi_out = phi_out;
     a.L = in.L;
@@ -437,8 +561,8 @@ int lbm_macros(lbm_ctx *c, int32_t inst, double *phi_out, const double *ref, lbm
     out->max_abs_phi = r[4];
     out->nonfinite = (int64_t)r[5];
     out->step = in.step;
-    if (out->nonfinite > 0) return fail(LBM_E_NONFINITE, "instance %d: %lld non-finite phi values (blow-up)", inst,
-                                        (long long)out->nonfinite);
+    if (out->nonfinite > 0)
+        return fail(LBM_E_NONFINITE, "instance %d: %lld non-finite phi values (blow-up)", inst, (long long)out->nonfinite);
     return LBM_OK;
 }
 
@@ -449,7 +573,7 @@ int lbm_populations(lbm_ctx *c, int32_t inst, double *g_out)
     if (!g_out) return fail(LBM_E_ARG, "lbm_populations: g_out is NULL");
     Instance &in = c->inst[inst];
     PopArgs a;
-    a.src = in.buf[in.cur];
+    a.src = in.buf[c->parity];
     a.out = g_out;
     a.L = in.L;
     a.f16 = in.f16;
@@ -472,7 +596,7 @@ int lbm_state_save(lbm_ctx *c, int32_t inst, void *dst)
     if (!check_inst(c, inst)) return fail(LBM_E_STATE, "lbm_state_save: bad context or instance %d", inst);
     if (!dst) return fail(LBM_E_ARG, "lbm_state_save: dst is NULL");
     Instance &in = c->inst[inst];
-    hipError_t e = hipMemcpyAsync(dst, in.buf[in.cur], pops_bytes(in.p), hipMemcpyDeviceToDevice, c->stream);
+    hipError_t e = hipMemcpyAsync(dst, in.buf[c->parity], pops_bytes(in.p), hipMemcpyDeviceToDevice, c->stream);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_state_save");
 }
 
@@ -483,7 +607,7 @@ int lbm_state_load(lbm_ctx *c, int32_t inst, const void *src, int64_t step)
     if (!src) return fail(LBM_E_ARG, "lbm_state_load: src is NULL");
     if (step < 0) return fail(LBM_E_ARG, "lbm_state_load: step < 0");
     Instance &in = c->inst[inst];
-    hipError_t e = hipMemcpyAsync(in.buf[in.cur], src, pops_bytes(in.p), hipMemcpyDeviceToDevice, c->stream);
+    hipError_t e = hipMemcpyAsync(in.buf[c->parity], src, pops_bytes(in.p), hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(e, "lbm_state_load");
     in.step = step;
     return LBM_OK;
@@ -499,8 +623,7 @@ int lbm_set_launch(lbm_ctx *c, int32_t inst, const lbm_launch *cfg)
     if (cfg->xcd_remap != 0 && cfg->xcd_remap != 1) return fail(LBM_E_ARG, "lbm_set_launch: xcd_remap must be 0 or 1");
     for (int k = 0; k < (int)c->inst.size(); ++k)
         if (inst == -1 || inst == k) c->inst[k].lc = Launch{cfg->rows, cfg->xcd_remap};
-    drop_graphs(c);
-    return LBM_OK;
+    return refresh_tables(c);
 }
 
 int lbm_get_launch(lbm_ctx *c, int32_t inst, lbm_launch *cfg)
@@ -511,6 +634,99 @@ int lbm_get_launch(lbm_ctx *c, int32_t inst, lbm_launch *cfg)
     cfg->rows = c->inst[inst].lc.rows;
     cfg->xcd_remap = c->inst[inst].lc.xcd_remap;
     return LBM_OK;
+}
+
+int lbm_set_batch(lbm_ctx *c, const lbm_batch *cfg)
+{
+    g_err[0] = 0;
+    if (!c) return fail(LBM_E_STATE, "lbm_set_batch: NULL context");
+    if (!cfg) return fail(LBM_E_ARG, "lbm_set_batch: cfg is NULL");
+    if (cfg->policy < LBM_BATCH_SERIAL || cfg->policy > LBM_BATCH_LPT)
+        return fail(LBM_E_ARG, "lbm_set_batch: unknown policy %d", cfg->policy);
+    if ((cfg->policy == LBM_BATCH_STRIDED || cfg->policy == LBM_BATCH_LPT) && cfg->blocks < 1)
+        return fail(LBM_E_ARG, "lbm_set_batch: persistent policies need blocks >= 1");
+    if (cfg->policy != LBM_BATCH_SERIAL && !c->uniform)
+        return fail(LBM_E_UNSUPPORTED, "lbm_set_batch: instances differ in storage/arithmetic or aux form");
+    c->batch = *cfg;
+    return refresh_tables(c);
+}
+
+int lbm_get_batch(lbm_ctx *c, lbm_batch *cfg)
+{
+    g_err[0] = 0;
+    if (!c) return fail(LBM_E_STATE, "lbm_get_batch: NULL context");
+    if (!cfg) return fail(LBM_E_ARG, "lbm_get_batch: cfg is NULL");
+    *cfg = c->batch;
+    return LBM_OK;
+}
+
+namespace {
+int adjoint_ok(lbm_ctx *c, int32_t inst, const char *who)
+{
+    if (!check_inst(c, inst)) return fail(LBM_E_STATE, "%s: bad context or instance %d", who, inst);
+    const Instance &in = c->inst[inst];
+    if (in.mode == MODE_F16S_F32) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for FP16 storage", who);
+    if (in.p.aux == LBM_AUX_FLUX) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for the flux form of the aux term", who);
+    return LBM_OK;
+}
+}  // namespace
+
+int lbm_adjoint_bytes(lbm_ctx *c, int32_t inst, size_t *bytes)
+{
+    g_err[0] = 0;
+    int rc = adjoint_ok(c, inst, "lbm_adjoint_bytes");
+    if (rc) return rc;
+    if (!bytes) return fail(LBM_E_ARG, "lbm_adjoint_bytes: bytes is NULL");
+    const Instance &in = c->inst[inst];
+    *bytes = (size_t)pop_elems(in.L) * math_bytes(in.mode);
+    return LBM_OK;
+}
+
+int lbm_adjoint_seed(lbm_ctx *c, int32_t inst, const double *dLdphi, void *lam)
+{
+    g_err[0] = 0;
+    int rc = adjoint_ok(c, inst, "lbm_adjoint_seed");
+    if (rc) return rc;
+    if (!dLdphi || !lam) return fail(LBM_E_ARG, "lbm_adjoint_seed: NULL pointer");
+    const Instance &in = c->inst[inst];
+    hipError_t e = launch_adjoint_seed(in.mode, dLdphi, lam, in.L, c->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "adjoint seed kernel launch");
+}
+
+int lbm_adjoint_step(lbm_ctx *c, int32_t inst, const void *state, const void *lam_in, void *lam_out, double *dLdD)
+{
+    g_err[0] = 0;
+    int rc = adjoint_ok(c, inst, "lbm_adjoint_step");
+    if (rc) return rc;
+    if (!state || !lam_in || !lam_out || !dLdD) return fail(LBM_E_ARG, "lbm_adjoint_step: NULL pointer");
+    if (lam_in == lam_out) return fail(LBM_E_ARG, "lbm_adjoint_step: lam_in and lam_out must not alias");
+    const Instance &in = c->inst[inst];
+    AdjArgs a;
+    a.state = state;
+    a.lam_in = lam_in;
+    a.lam_out = lam_out;
+    a.u = in.u;
+    a.k = in.has_D ? in.k : nullptr;
+    a.s = in.has_src ? in.s : nullptr;
+    a.L = in.L;
+    a.k_const = 3.0 * in.p.D_const * in.p.dt / (in.p.dx * in.p.dx);
+    a.lambda = in.p.lambda;
+    a.dk_dD = 3.0 * in.p.dt / (in.p.dx * in.p.dx);
+    a.f16 = in.f16;
+    a.grad = dLdD;
+    hipError_t e = launch_adjoint(in.mode, in.p.aux, a, c->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "adjoint kernel launch");
+}
+
+int lbm_adjoint_init(lbm_ctx *c, int32_t inst, const void *lam0, double *dLdphi0)
+{
+    g_err[0] = 0;
+    int rc = adjoint_ok(c, inst, "lbm_adjoint_init");
+    if (rc) return rc;
+    if (!lam0 || !dLdphi0) return fail(LBM_E_ARG, "lbm_adjoint_init: NULL pointer");
+    const Instance &in = c->inst[inst];
+    hipError_t e = launch_adjoint_init(in.mode, lam0, in.u, dLdphi0, in.L, c->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "adjoint init kernel launch");
 }
 
 int lbm_bench_copy(void *dst, const void *src, size_t bytes, void *stream)

@@ -44,18 +44,44 @@ struct Launch {
     int32_t xcd_remap;  // 1: give consecutive tiles to blocks on the same XCD
 };
 
-struct StepArgs {
-    const void *src;  // populations, storage type
-    void *dst;        // populations, storage type
-    const void *u;    // velocity, math type, lattice units (u dt / dx)
-    const void *k;    // math type, tau1 - 1/2 per node (nullptr: k_const)
-    const void *s;    // math type, dt S + dt^2/2 dS/dt per node (nullptr: no source)
+// Everything a step kernel needs about one instance.  Single-instance launches pass it by value;
+// the batched kernel reads an array of them from device memory (wave-uniform, scalar loads).
+struct InstDesc {
+    void *buf[2];       // population buffers; a step reads buf[parity] and writes buf[parity ^ 1]
+    const void *u;      // velocity, math type, lattice units (u dt / dx)
+    const void *k;      // math type, tau1 - 1/2 per node (used when has_k)
+    const void *s;      // math type, dt S + dt^2/2 dS/dt per node (used when has_s)
     Layout L;
     Launch lc;
-    double w1, w2, beta;  // relaxation when k is nullptr: 1 - 1/tau1, 1 - 1/tau2, 1 - 1/(2 tau1)
+    int32_t has_k, has_s;
+    double w1, w2, beta;  // relaxation when !has_k: 1 - 1/tau1, 1 - 1/tau2, 1 - 1/(2 tau1)
     double lambda;
     F16Params f16;
 };
+
+struct StepArgs {
+    InstDesc d;
+    int32_t parity;
+};
+
+// Work item of the batched step: tile `tile` of instance `inst`.
+struct WorkItem {
+    int32_t inst, tile;
+};
+
+struct BatchArgs {
+    const InstDesc *inst;     // [n_inst]
+    const WorkItem *items;    // grouped by block when block_start is given
+    const int32_t *block_start;  // [nblocks + 1], or nullptr: block b runs item b (XCD-contiguous order)
+    int32_t parity;
+};
+
+// Number of 64-column x (4 * rows)-row tiles of one instance.
+__host__ __device__ __forceinline__ int tiles_of(const Layout &L, int rows)
+{
+    const int waves_y = (L.ny + rows - 1) / rows;
+    return ((L.nx + 63) / 64) * ((waves_y + 3) / 4);
+}
 
 struct InitArgs {
     const double *phi0;  // dense FP64 [ny][nx]
@@ -97,12 +123,31 @@ struct PopArgs {
     F16Params f16;
 };
 
-// Launchers (lbm_kernels.hip).  All return the hipError_t of the launch.
+// Adjoint of one step (lbm_adjoint.hip).
+struct AdjArgs {
+    const void *state;   // state image (storage type, population layout) holding g^n
+    const void *lam_in;  // dL/dg^{n+1}: math type, [ny][9][pitch], lam_i(x) at (y*9 + i)*pitch + x
+    void *lam_out;       // dL/dg^n, same layout
+    const void *u;       // velocity (math type, lattice units)
+    const void *k;       // tau1 - 1/2 per node, or nullptr: k_const
+    const void *s;       // dt S + dt^2/2 dS/dt per node, or nullptr
+    Layout L;
+    double k_const, lambda;
+    double dk_dD;        // d(tau1 - 1/2)/dD = 3 dt / dx^2
+    F16Params f16;
+    double *grad;        // dL/dD, FP64 [ny][nx], accumulated
+};
+
+// Launchers (lbm_kernels.hip, lbm_adjoint.hip).  All return the hipError_t of the launch.
 hipError_t launch_step(int mode, int aux, const StepArgs &a, hipStream_t st);
+hipError_t launch_batched_step(int mode, int aux, const BatchArgs &a, int nblocks, hipStream_t st);
 hipError_t launch_init(int mode, const InitArgs &a, hipStream_t st);
 hipError_t launch_prep(int mode, const PrepArgs &a, hipStream_t st);
 hipError_t launch_macros(int mode, const MacroArgs &a, double *result, hipStream_t st);
 hipError_t launch_populations(int mode, const PopArgs &a, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
+hipError_t launch_adjoint(int mode, int aux, const AdjArgs &a, hipStream_t st);
+hipError_t launch_adjoint_seed(int mode, const double *dphi, void *lam, const Layout &L, hipStream_t st);
+hipError_t launch_adjoint_init(int mode, const void *lam, const void *u, double *dphi0, const Layout &L, hipStream_t st);
 
 }  // namespace lbm

@@ -106,11 +106,11 @@ __device__ __forceinline__ void st_nt_at(T *base, unsigned byte_off, T v)
     __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off));
 }
 
-// One step.  Block (64, 4): lane = column of a 64-wide tile, wave w walks `rows` rows.  The wave's
-// row is uniform (taken with readfirstlane), so row and segment bases live in scalar registers and
-// each load or store needs only a 32-bit lane offset (x, x-1 or x+1).
+// One tile of one step.  Block (64, 4): lane = column of a 64-wide tile, wave `wave` walks
+// `rows` rows.  The wave's row is uniform (taken with readfirstlane), so row and segment bases live in
+// scalar registers and each load or store needs only a 32-bit lane offset (x, x-1 or x+1).
 template <int MODE, int AUX, bool HAS_K, bool HAS_S>
-__global__ __launch_bounds__(256) void step_kernel(const StepArgs a)
+__device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int t, int wave)
 {
     using St = typename ModeTraits<MODE>::St;
     using M = typename ModeTraits<MODE>::M;
@@ -120,8 +120,6 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a)
     const int64_t pitch = a.L.pitch;
     const int rows = a.lc.rows;
     const int ntx = (nx + 63) >> 6;
-    const int t = tile_of_block(blockIdx.x, gridDim.x, a.lc.xcd_remap);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const unsigned x = (unsigned)((t % ntx) * 64) + threadIdx.x;
     const int y0 = ((t / ntx) * 4 + wave) * rows;
     if (y0 >= ny) return;
@@ -130,8 +128,8 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a)
     const unsigned xm = xc == 0 ? (unsigned)nx - 1 : xc - 1;
     const unsigned xp = xc == (unsigned)nx - 1 ? 0u : xc + 1;
     const int y1 = min(y0 + rows, ny);
-    const T *__restrict__ src = static_cast<const T *>(a.src);
-    T *__restrict__ dst = static_cast<T *>(a.dst);
+    const T *__restrict__ src = static_cast<const T *>(a.buf[parity]);
+    T *__restrict__ dst = static_cast<T *>(a.buf[parity ^ 1]);
     const M *__restrict__ u = static_cast<const M *>(a.u);
     const M *__restrict__ kf = static_cast<const M *>(a.k);
     const M *__restrict__ sf = static_cast<const M *>(a.s);
@@ -204,6 +202,41 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a)
         uy_m = uy_c;
         ux_c = ux_p;
         uy_c = uy_p;
+    }
+}
+
+// Single instance: block b -> tile (XCD-remapped if requested).
+template <int MODE, int AUX, bool HAS_K, bool HAS_S>
+__global__ __launch_bounds__(256) void step_kernel(const StepArgs a)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    process_tile<MODE, AUX, HAS_K, HAS_S>(a.d, a.parity, tile_of_block(blockIdx.x, gridDim.x, a.d.lc.xcd_remap), wave);
+}
+
+// Many instances in one launch: each block runs a range of (instance, tile) work items; the
+// instance descriptor is wave-uniform and read with scalar loads.
+template <int MODE, int AUX>
+__global__ __launch_bounds__(256) void batched_step_kernel(const BatchArgs a)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    int beg, end;
+    if (a.block_start) {
+        beg = a.block_start[blockIdx.x];
+        end = a.block_start[blockIdx.x + 1];
+    } else {
+        beg = tile_of_block(blockIdx.x, gridDim.x, 1);
+        end = beg + 1;
+    }
+    for (int it = beg; it < end; ++it) {
+        const WorkItem w = a.items[it];
+        const InstDesc &d = a.inst[w.inst];
+        if (d.has_k) {
+            if (d.has_s) process_tile<MODE, AUX, true, true>(d, a.parity, w.tile, wave);
+            else process_tile<MODE, AUX, true, false>(d, a.parity, w.tile, wave);
+        } else {
+            if (d.has_s) process_tile<MODE, AUX, false, true>(d, a.parity, w.tile, wave);
+            else process_tile<MODE, AUX, false, false>(d, a.parity, w.tile, wave);
+        }
     }
 }
 
@@ -403,9 +436,8 @@ template <int MODE, int AUX>
 hipError_t launch_step_aux(const StepArgs &a, hipStream_t st)
 {
     dim3 block(64, 4);
-    const int waves_y = (a.L.ny + a.lc.rows - 1) / a.lc.rows;
-    const int nblocks = ((a.L.nx + 63) / 64) * ((waves_y + 3) / 4);
-    const bool hk = a.k != nullptr, hs = a.s != nullptr;
+    const int nblocks = tiles_of(a.d.L, a.d.lc.rows);
+    const bool hk = a.d.has_k, hs = a.d.has_s;
     if (hk && hs) step_kernel<MODE, AUX, true, true><<<nblocks, block, 0, st>>>(a);
     else if (hk) step_kernel<MODE, AUX, true, false><<<nblocks, block, 0, st>>>(a);
     else if (hs) step_kernel<MODE, AUX, false, true><<<nblocks, block, 0, st>>>(a);
@@ -423,16 +455,40 @@ hipError_t launch_step_mode(int aux, const StepArgs &a, hipStream_t st)
     }
 }
 
+template <int MODE>
+hipError_t launch_batched_mode(int aux, const BatchArgs &a, int nblocks, hipStream_t st)
+{
+    dim3 block(64, 4);
+    switch (aux) {
+    case 0: batched_step_kernel<MODE, 0><<<nblocks, block, 0, st>>>(a); break;
+    case 1: batched_step_kernel<MODE, 1><<<nblocks, block, 0, st>>>(a); break;
+    default: batched_step_kernel<MODE, 2><<<nblocks, block, 0, st>>>(a); break;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_step(int mode, int aux, const StepArgs &a, hipStream_t st)
 {
-    if (a.lc.rows < 1 || a.lc.rows > 64) return hipErrorInvalidValue;
+    if (a.d.lc.rows < 1 || a.d.lc.rows > 64) return hipErrorInvalidValue;
     switch (mode) {
     case MODE_F64_F64: return launch_step_mode<MODE_F64_F64>(aux, a, st);
     case MODE_F64_F32: return launch_step_mode<MODE_F64_F32>(aux, a, st);
     case MODE_F32_F32: return launch_step_mode<MODE_F32_F32>(aux, a, st);
     case MODE_F16S_F32: return launch_step_mode<MODE_F16S_F32>(aux, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batched_step(int mode, int aux, const BatchArgs &a, int nblocks, hipStream_t st)
+{
+    if (nblocks < 1) return hipErrorInvalidValue;
+    switch (mode) {
+    case MODE_F64_F64: return launch_batched_mode<MODE_F64_F64>(aux, a, nblocks, st);
+    case MODE_F64_F32: return launch_batched_mode<MODE_F64_F32>(aux, a, nblocks, st);
+    case MODE_F32_F32: return launch_batched_mode<MODE_F32_F32>(aux, a, nblocks, st);
+    case MODE_F16S_F32: return launch_batched_mode<MODE_F16S_F32>(aux, a, nblocks, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -60,8 +60,15 @@ class lbm_launch(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
 
 
+class lbm_batch(ctypes.Structure):
+    _fields_ = [("policy", ctypes.c_int32), ("blocks", ctypes.c_int32)]
+
+
+LBM_BATCH_SERIAL, LBM_BATCH_FLAT, LBM_BATCH_STRIDED, LBM_BATCH_LPT = 0, 1, 2, 3
+
 EXPORTS = ["lbm_workspace_size", "lbm_init", "lbm_step", "lbm_macros", "lbm_populations", "lbm_state_bytes",
-           "lbm_state_save", "lbm_state_load", "lbm_set_launch", "lbm_get_launch", "lbm_bench_copy", "lbm_free",
+           "lbm_state_save", "lbm_state_load", "lbm_set_launch", "lbm_get_launch", "lbm_set_batch", "lbm_get_batch",
+           "lbm_adjoint_bytes", "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_init", "lbm_bench_copy", "lbm_free",
            "lbm_last_error", "lbm_abi_version"]
 
 
@@ -86,6 +93,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lbm_state_load.argtypes = [P, I32, P, I64]
     lib.lbm_set_launch.argtypes = [P, I32, ctypes.POINTER(lbm_launch)]
     lib.lbm_get_launch.argtypes = [P, I32, ctypes.POINTER(lbm_launch)]
+    lib.lbm_set_batch.argtypes = [P, ctypes.POINTER(lbm_batch)]
+    lib.lbm_get_batch.argtypes = [P, ctypes.POINTER(lbm_batch)]
+    lib.lbm_adjoint_bytes.argtypes = [P, I32, ctypes.POINTER(SZ)]
+    lib.lbm_adjoint_seed.argtypes = [P, I32, P, P]
+    lib.lbm_adjoint_step.argtypes = [P, I32, P, P, P, P]
+    lib.lbm_adjoint_init.argtypes = [P, I32, P, P]
     lib.lbm_bench_copy.argtypes = [P, P, SZ, P]
     lib.lbm_free.argtypes = [P]
     lib.lbm_last_error.argtypes = []
@@ -209,6 +222,37 @@ def lbm_get_launch(ctx, inst: int = 0) -> dict:
     cfg = lbm_launch()
     _check(lib().lbm_get_launch(ctx, int(inst), ctypes.byref(cfg)))
     return {"rows": cfg.rows, "xcd_remap": cfg.xcd_remap}
+
+
+def lbm_set_batch(ctx, policy: int, blocks: int = 0) -> None:
+    cfg = lbm_batch(int(policy), int(blocks))
+    _check(lib().lbm_set_batch(ctx, ctypes.byref(cfg)))
+
+
+def lbm_get_batch(ctx) -> dict:
+    cfg = lbm_batch()
+    _check(lib().lbm_get_batch(ctx, ctypes.byref(cfg)))
+    return {"policy": cfg.policy, "blocks": cfg.blocks}
+
+
+def lbm_adjoint_bytes(ctx, inst: int = 0) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().lbm_adjoint_bytes(ctx, int(inst), ctypes.byref(out)))
+    return out.value
+
+
+def lbm_adjoint_seed(ctx, inst: int, dLdphi: torch.Tensor, lam: torch.Tensor) -> None:
+    _check(lib().lbm_adjoint_seed(ctx, int(inst), _dptr(dLdphi), _dptr(lam, lam.dtype)))
+
+
+def lbm_adjoint_step(ctx, inst: int, state: torch.Tensor, lam_in: torch.Tensor, lam_out: torch.Tensor,
+                     dLdD: torch.Tensor) -> None:
+    _check(lib().lbm_adjoint_step(ctx, int(inst), _dptr(state, state.dtype), _dptr(lam_in, lam_in.dtype),
+                                  _dptr(lam_out, lam_out.dtype), _dptr(dLdD)))
+
+
+def lbm_adjoint_init(ctx, inst: int, lam0: torch.Tensor, dLdphi0: torch.Tensor) -> None:
+    _check(lib().lbm_adjoint_init(ctx, int(inst), _dptr(lam0, lam0.dtype), _dptr(dLdphi0)))
 
 
 def lbm_bench_copy(dst: torch.Tensor, src: torch.Tensor, stream: Optional[torch.cuda.Stream] = None) -> None:

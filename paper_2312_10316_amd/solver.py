@@ -54,6 +54,12 @@ class Solver:
     def get_launch(self, inst: int = 0) -> dict:
         return L.lbm_get_launch(self.ctx, inst)
 
+    def set_batch(self, policy: int, blocks: int = 0) -> None:
+        L.lbm_set_batch(self.ctx, policy, blocks)
+
+    def get_batch(self) -> dict:
+        return L.lbm_get_batch(self.ctx)
+
     def close(self) -> None:
         if self.ctx is not None:
             L.lbm_free(self.ctx)

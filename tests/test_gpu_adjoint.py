@@ -1,0 +1,185 @@
+"""The hand-written adjoint of the step against the oracle: explicit transpose of the population
+Jacobian, complex-step derivatives of the oracle (tangent-linear reference), central finite
+differences, and the sqrt(T)-checkpointed autograd path."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from paper_2312_10316_amd import Solver, adjoint, lbm
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def lam_to_lib(lam9, pitch, dtype):
+    """[9, ny, nx] -> flat [ny][9][pitch] adjoint layout."""
+    _, ny, nx = lam9.shape
+    out = np.zeros((ny, 9, pitch))
+    out[:, :, :nx] = np.transpose(lam9, (1, 0, 2))
+    return torch.from_numpy(out.astype(dtype).ravel()).cuda()
+
+
+def lam_from_lib(flat, nx, ny, pitch):
+    a = flat.cpu().numpy().astype(np.float64).reshape(ny, 9, pitch)[:, :, :nx]
+    return np.ascontiguousarray(np.transpose(a, (1, 0, 2)))
+
+
+def tiny_problem(nx=16, ny=16, U0=1.0, c=4.0, D0=5e-3):
+    X, Y, dx = W.mesh(nx, ny, -1.0, 1.0)
+    dt = dx / c
+    phi0 = np.exp(-((X - 0.3) ** 2 + (Y + 0.1) ** 2) / (2 * 0.25 ** 2))
+    return dict(X=X, Y=Y, dx=dx, dt=dt, ux=-U0 * Y, uy=U0 * X, phi0=phi0, lam=0.25, D0=D0, nx=nx, ny=ny)
+
+
+@pytest.mark.parametrize("aux", [lbm.LBM_AUX_LOCAL, lbm.LBM_AUX_NONE])
+def test_adjoint_step_is_the_transpose(aux):
+    """On a 7 x 5 lattice the oracle's step is a 315 x 315 matrix A (columns = steps of unit
+    vectors); the GPU adjoint step must return A^T lambda."""
+    nx, ny = 7, 5
+    pr = tiny_problem(nx, ny, U0=1.3, c=3.0)
+    rng = np.random.default_rng(41)
+    D = pr["D0"] * (1 + 0.4 * rng.uniform(-1, 1, (ny, nx)))
+    p = lbm.make_params(nx, ny, pr["dx"], pr["dt"], pr["lam"], pr["D0"], "f64", aux)
+    s = Solver([(p, {"phi0": dev(pr["phi0"]), "ux": dev(pr["ux"]), "uy": dev(pr["uy"]), "D": dev(D)})])
+    s.step(3)
+    state = s.state_save()
+    lam_in = rng.uniform(-1, 1, (9, ny, nx))
+    pitch = lbm.pitch_of(nx)
+    li = lam_to_lib(lam_in, pitch, np.float64)
+    lo = torch.empty_like(li)
+    grad = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    lbm.lbm_adjoint_step(s.ctx, 0, state, li, lo, grad)
+    got = lam_from_lib(lo, nx, ny, pitch)
+    s.close()
+    op = O.Problem(nx, ny, pr["dx"], pr["dt"], pr["lam"], pr["D0"], aux)
+    n = 9 * nx * ny
+    A = np.empty((n, n))
+    for col in range(n):
+        e = np.zeros(n)
+        e[col] = 1.0
+        A[:, col] = O.step(op, e.reshape(9, ny, nx), pr["ux"], pr["uy"], D).ravel()
+    want = (A.T @ lam_in.ravel()).reshape(9, ny, nx)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def _oracle_loss(pr, D, target, nsteps, phi0=None):
+    op = O.Problem(pr["nx"], pr["ny"], pr["dx"], pr["dt"], pr["lam"], pr["D0"], O.AUX_LOCAL)
+    cplx = np.iscomplexobj(D) or (phi0 is not None and np.iscomplexobj(phi0))
+    g0 = O.init(op, pr["phi0"] if phi0 is None else phi0, pr["ux"], pr["uy"], cplx=cplx)
+    g = O.run(op, g0, nsteps, pr["ux"], pr["uy"], D)
+    phi = O.phi(op, g)
+    return 0.5 * np.sum((phi - target) ** 2)
+
+
+def _spec(pr, nsteps, mode="f64", segment=None):
+    return adjoint.RunSpec(pr["nx"], pr["ny"], pr["dx"], pr["dt"], pr["lam"], dev(pr["phi0"]), dev(pr["ux"]),
+                           dev(pr["uy"]), nsteps, mode, lbm.LBM_AUX_LOCAL, segment)
+
+
+def _target(pr, nsteps):
+    op = O.Problem(pr["nx"], pr["ny"], pr["dx"], pr["dt"], pr["lam"], pr["D0"], O.AUX_LOCAL)
+    g = O.run(op, O.init(op, pr["phi0"], pr["ux"], pr["uy"]), nsteps, pr["ux"], pr["uy"],
+              np.full((pr["ny"], pr["nx"]), pr["D0"]))
+    return O.phi(op, g)
+
+
+@pytest.mark.parametrize("segment", [None, 1, 7, 20])
+def test_gradient_wrt_D_matches_complex_step_and_fd(segment):
+    """16^2 lattice, 20 steps, FP64: dL/dD from the checkpointed adjoint (any checkpoint interval)
+    against the oracle's complex-step directional derivatives and central finite differences."""
+    pr = tiny_problem()
+    nsteps = 20
+    theta = W.control_theta(4, seed=231210316 + 6, D0=pr["D0"])
+    Dnp = W.D_from_control(theta, pr["nx"], pr["ny"])
+    target = _target(pr, nsteps)
+    D = dev(Dnp).requires_grad_(True)
+    spec = _spec(pr, nsteps, segment=segment)
+    phi = adjoint.simulate(D, spec)
+    loss = 0.5 * ((phi - dev(target)) ** 2).sum()
+    loss.backward()
+    grad = D.grad.cpu().numpy()
+    assert abs(loss.item() - _oracle_loss(pr, Dnp, target, nsteps)) <= 1e-12 * loss.item()
+    rng = np.random.default_rng(231210316 + 7)
+    h = 1e-30
+    for _ in range(3):
+        dD = rng.uniform(-1, 1, Dnp.shape) * pr["D0"]
+        cs = _oracle_loss(pr, Dnp + 1j * h * dD, target, nsteps).imag / h
+        adj = float(np.sum(grad * dD))
+        assert abs(adj - cs) <= 1e-9 * abs(cs), (adj, cs)
+        eps = 1e-6
+        lp = _oracle_loss(pr, Dnp + eps * dD, target, nsteps)
+        lm = _oracle_loss(pr, Dnp - eps * dD, target, nsteps)
+        fd = (lp - lm) / (2 * eps)
+        assert abs(adj - fd) <= 1e-6 * abs(fd), (adj, fd)
+
+
+def test_gradient_wrt_control_grid_and_phi0():
+    """Autograd through D = By theta Bx^T: every d/dtheta against the oracle's complex step; the
+    adjoint of the initial condition against a complex-step derivative in phi0."""
+    pr = tiny_problem()
+    nsteps = 20
+    theta0 = W.control_theta(4, seed=231210316 + 6, D0=pr["D0"])
+    target = _target(pr, nsteps)
+    By = adjoint.bspline_operator(pr["ny"], 4)
+    Bx = adjoint.bspline_operator(pr["nx"], 4)
+    theta = dev(theta0).requires_grad_(True)
+    spec = _spec(pr, nsteps, segment=5)
+    phi = adjoint.simulate(adjoint.D_from_control(theta, By, Bx), spec)
+    (0.5 * ((phi - dev(target)) ** 2).sum()).backward()
+    g = theta.grad.cpu().numpy()
+    h = 1e-30
+    for a in range(4):
+        for b in range(4):
+            th = theta0.astype(complex)
+            th[a, b] += 1j * h
+            cs = _oracle_loss(pr, W.D_from_control(th, pr["nx"], pr["ny"]), target, nsteps).imag / h
+            assert abs(g[a, b] - cs) <= 1e-9 * np.abs(g).max(), (a, b, g[a, b], cs)
+    dphi0 = spec.stats["dL_dphi0"].cpu().numpy()
+    rng = np.random.default_rng(5)
+    dp = rng.uniform(-1, 1, dphi0.shape)
+    cs = _oracle_loss(pr, W.D_from_control(theta0, pr["nx"], pr["ny"]), target, nsteps,
+                      phi0=pr["phi0"] + 1j * h * dp).imag / h
+    assert abs(np.sum(dphi0 * dp) - cs) <= 1e-9 * abs(cs)
+
+
+def test_fp32_gradient_at_512_against_fp64():
+    """512^2 pulse, 400 steps, D on a 32 x 32 control grid: the FP32 forward + adjoint gradient
+    against the FP64 one (same checkpointing)."""
+    cfg = W.PulseConfig(N=W.C5_N, steps=W.C5_STEPS)
+    f = W.rotating_pulse(cfg)
+    pr = dict(nx=cfg.N, ny=cfg.N, dx=f["dx"], dt=f["dt"], lam=cfg.lam, phi0=f["phi0"], ux=f["ux"], uy=f["uy"],
+              D0=cfg.D)
+    By = adjoint.bspline_operator(cfg.N, W.C5_CTRL)
+    theta0 = W.control_theta(W.C5_CTRL)
+    tgt_spec = _spec(pr, cfg.steps, "f64")
+    with torch.no_grad():
+        target = adjoint.simulate(dev(np.full((cfg.N, cfg.N), cfg.D)), tgt_spec)
+    grads = {}
+    for mode in ("f64", "f32"):
+        theta = dev(theta0).requires_grad_(True)
+        spec = _spec(pr, cfg.steps, mode)
+        phi = adjoint.simulate(adjoint.D_from_control(theta, By, By), spec)
+        (0.5 * ((phi - target) ** 2).sum()).backward()
+        grads[mode] = theta.grad.cpu().numpy()
+        assert spec.stats["checkpoints"] == 20 and spec.stats["segment"] == 20
+    rel = np.linalg.norm(grads["f32"] - grads["f64"]) / np.linalg.norm(grads["f64"])
+    print(f"FP32 vs FP64 control-grid gradient, relative L2 difference {rel:.3e}")
+    assert rel < 1e-2
+
+
+def test_adjoint_rejects_unsupported_modes():
+    pr = tiny_problem(8, 8)
+    for mode, aux in (("f16s", lbm.LBM_AUX_LOCAL), ("f64", lbm.LBM_AUX_FLUX)):
+        p = lbm.make_params(8, 8, pr["dx"], pr["dt"], pr["lam"], pr["D0"], mode, aux)
+        s = Solver([(p, {"phi0": dev(pr["phi0"]), "ux": dev(pr["ux"]), "uy": dev(pr["uy"])})])
+        with pytest.raises(lbm.LbmError) as ei:
+            lbm.lbm_adjoint_bytes(s.ctx)
+        assert ei.value.status == lbm.LBM_E_UNSUPPORTED
+        s.close()

@@ -186,3 +186,31 @@ def batched_instances(n: int = 256, seed: int = 231210316, steps: int = 2000, n_
 def random_populations(shape, seed: int, lo: float = 0.0, hi: float = 1.0):
     """Seeded uniform random values (used as arbitrary population states in tests)."""
     return np.random.default_rng(seed).uniform(lo, hi, shape)
+
+
+# ---- D(x) on a control grid (gradient workloads) ---------------------------------------------
+
+def bspline_matrix(n_nodes: int, n_ctrl: int) -> np.ndarray:
+    """Periodic uniform cubic B-spline basis: B[j, a] = b3((j/n_nodes - a/n_ctrl) * n_ctrl) with the
+    argument wrapped to the period; b3 is the cubic B-spline (a positive partition of unity)."""
+    t = np.arange(n_nodes)[:, None] / n_nodes * n_ctrl - np.arange(n_ctrl)[None, :]
+    t = (t + n_ctrl / 2.0) % n_ctrl - n_ctrl / 2.0
+    a = np.abs(t)
+    return np.where(a < 1.0, (4.0 - 6.0 * a * a + 3.0 * a ** 3) / 6.0,
+                    np.where(a < 2.0, (2.0 - a) ** 3 / 6.0, 0.0))
+
+
+def D_from_control(theta: np.ndarray, nx: int, ny: int) -> np.ndarray:
+    """D[y, x] = sum_ab By[y, a] theta[a, b] Bx[x, b] (bicubic periodic B-spline surface)."""
+    By = bspline_matrix(ny, theta.shape[0])
+    Bx = bspline_matrix(nx, theta.shape[1])
+    return By @ theta @ Bx.T
+
+
+def control_theta(n_ctrl: int = 32, seed: int = 231210316 + 5, D0: float = 1e-3, amp: float = 0.3) -> np.ndarray:
+    """Seeded control values D0 (1 + amp (2U - 1)) on an n_ctrl x n_ctrl grid."""
+    rng = np.random.default_rng(seed)
+    return D0 * (1.0 + amp * (2.0 * rng.uniform(0.0, 1.0, (n_ctrl, n_ctrl)) - 1.0))
+
+
+C5_N, C5_STEPS, C5_CTRL = 512, 400, 32  # 512^2 pulse, 400 steps, 32 x 32 control grid
