@@ -139,6 +139,124 @@ def run_batched(torch, W, lbm, Solver, n_inst=256, steps=2000, eager_steps=100):
     return out
 
 
+def _timed_steps(torch, s, nsteps):
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.step(nsteps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / max(nsteps, 1)
+
+
+def run_precision_8192(torch, W, lbm, Solver, n=8192, steps=1000):
+    """8192^2, D(x) = 1e-3 (1 + 0.5 sin(pi x) sin(pi y)), 1000 steps: every storage mode, errors of
+    phi against the FP64 run, mass drift."""
+    cfg = W.PulseConfig(N=n, steps=steps, D_variable=True)
+    f = W.rotating_pulse(cfg)
+    dev = {k: torch.from_numpy(f[k]).cuda() for k in ("phi0", "ux", "uy", "D")}
+    out, ref = {}, None
+    for mode in ("f64", "f64s_f32m", "f32", "f16s"):
+        s = Solver([(lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, mode), dev)])
+        m0 = s.macros()["mass"]
+        s.step(64)
+        ms = _timed_steps(torch, s, steps - 64)
+        st, phi = s.macros(want_phi=True, raise_nonfinite=False)
+        s.close()
+        r = {"mlups": n * n / (ms * 1e-3) / 1e6, "ms_per_step": ms,
+             "hbm_gbps_algorithmic": n * n / (ms * 1e-3) * bytes_per_lup(mode, True) / 1e9,
+             "bytes_per_lup": bytes_per_lup(mode, True), "mass_drift": st["mass"] / m0 - 1.0,
+             "nonfinite": st["nonfinite"]}
+        if mode == "f64":
+            ref = phi
+        else:
+            d = (phi - ref).abs()
+            r["max_err_vs_f64"] = float(d.max())
+            r["l2_rel_err_vs_f64"] = float(torch.sqrt((d * d).sum() / (ref * ref).sum()))
+            del d
+        r["roofline_frac"] = r["hbm_gbps_algorithmic"] / HBM_PEAK_GBPS
+        out[mode] = r
+        del phi
+    del ref, dev
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_refinement(torch, W, lbm, Solver, sizes=(64, 128, 256, 512, 1024, 2048), modes=("f64", "f32", "f16s")):
+    """E_r against the closed-form pulse at t = 0.3125 under acoustic (c = 10) and diffusive
+    (dx^2/dt fixed at its 256^2 value) refinement; least-squares orders over N >= 256 (the coarse grids
+    under-resolve sigma0 = 0.1); N* = finest N at which a reduced-precision mode stays within 5 % of the
+    FP64 E_r."""
+    import numpy as np
+    out = {}
+    for scaling in ("acoustic", "diffusive"):
+        res = {m: [] for m in modes}
+        for N in sizes:
+            cfg = W.refinement(N, scaling)
+            f = W.rotating_pulse(cfg)
+            dev = {k: torch.from_numpy(f[k]).cuda() for k in ("phi0", "ux", "uy")}
+            ref = torch.from_numpy(W.pulse_reference(cfg, f)).cuda()
+            for m in modes:
+                s = Solver([(lbm.make_params(N, N, f["dx"], cfg.dt, cfg.lam, cfg.D, m), dev)])
+                s.step(cfg.steps)
+                res[m].append(s.macros(ref=ref, raise_nonfinite=False)["rms_err"])
+                s.close()
+        entry = {"N": list(sizes), "E_r": res}
+        for m in modes:
+            e = np.array(res[m])
+            ok = np.isfinite(e) & (e > 0) & (np.array(sizes) >= 256)
+            entry.setdefault("order", {})[m] = (float(-np.polyfit(np.log(np.array(sizes)[ok]), np.log(e[ok]), 1)[0])
+                                                if ok.sum() >= 2 else None)
+            if m != "f64":
+                within = [N for N, a, b in zip(sizes, res[m], res["f64"]) if np.isfinite(a) and a <= 1.05 * b]
+                entry.setdefault("N_star", {})[m] = max(within) if within else None
+        out[scaling] = entry
+    return out
+
+
+def run_flux(torch, W, lbm, Solver, n=2048, steps=3000):
+    cfg = W.PulseConfig(N=n, steps=steps)
+    f = W.rotating_pulse(cfg)
+    dev = {k: torch.from_numpy(f[k]).cuda() for k in ("phi0", "ux", "uy")}
+    out = {}
+    for mode in ("f32", "f64"):
+        s = Solver([(lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, mode, lbm.LBM_AUX_FLUX), dev)])
+        s.step(64)
+        ms = _timed_steps(torch, s, steps)
+        s.close()
+        out[mode] = {"mlups": n * n / (ms * 1e-3) / 1e6, "ms_per_step": ms, "launch": "rows=8, xcd_remap=1"}
+    return out
+
+
+def run_adjoint(torch, W, lbm, Solver):
+    """512^2 pulse, 400 steps, FP32 forward with sqrt(T) checkpoints; D on a 32 x 32 bicubic control
+    grid; loss = 1/2 sum (phi_T - phi_target)^2 against the run with D = 1e-3."""
+    from paper_2312_10316_amd import adjoint
+    cfg = W.PulseConfig(N=W.C5_N, steps=W.C5_STEPS)
+    f = W.rotating_pulse(cfg)
+    dv = lambda a: torch.from_numpy(a).cuda()
+    mk = lambda mode: adjoint.RunSpec(cfg.N, cfg.N, f["dx"], f["dt"], cfg.lam, dv(f["phi0"]), dv(f["ux"]),
+                                      dv(f["uy"]), cfg.steps, mode)
+    B = adjoint.bspline_operator(cfg.N, W.C5_CTRL)
+    with torch.no_grad():
+        target = adjoint.simulate(torch.full((cfg.N, cfg.N), cfg.D, dtype=torch.float64, device="cuda"), mk("f32"))
+    theta = dv(W.control_theta(W.C5_CTRL)).requires_grad_(True)
+    spec = mk("f32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phi = adjoint.simulate(adjoint.D_from_control(theta, B, B), spec)
+    loss = 0.5 * ((phi - target) ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"N": cfg.N, "steps": cfg.steps, "control_grid": W.C5_CTRL, "checkpoints": spec.stats["checkpoints"],
+            "forward_s": t1 - t0, "backward_s": t2 - t1, "backward_over_forward": (t2 - t1) / (t1 - t0),
+            "loss": float(loss.detach()), "grad_norm": float(theta.grad.norm())}
+
+
 def copy_bandwidth(torch, lbm, nbytes=2 << 30, reps=20):
     """Read + write bandwidth of the library's plain streaming copy kernel (2 GiB, one pass)."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -279,6 +397,8 @@ def main():
     ap.add_argument("--modes", default="f32,f64,f64s_f32m,f16s")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-studies", action="store_true",
+                    help="skip the 8192^2 precision, refinement, flux-form and adjoint studies")
     ap.add_argument("--summarize", metavar="RUNDIR",
                     help="write profiles/ summaries from rocprofv3 output under RUNDIR (no GPU needed)")
     args = ap.parse_args()
@@ -290,7 +410,7 @@ def main():
                            "rocprofv3 --kernel-trace --stats --output-format csv -d RUNDIR/trace -o trace -- "
                            "python3 bench.py",
                            [f"rocprofv3 --pmc {c} --output-format csv -d RUNDIR/pmc_{c.lower()}_{n} -o pmc -- "
-                            f"python3 bench.py --n {n} --steps 12 --warmup 0 --modes f32,f64,f16s --no-cpu --no-batched"
+                            f"python3 bench.py --n {n} --steps 12 --warmup 0 --modes f32,f64,f16s --no-cpu --no-batched --no-studies"
                             for (c, n) in sorted(pmc)])
         return
     if args.gpus != 1:
@@ -365,6 +485,15 @@ def main():
         print(f"# batched: {out['batched']['batched']['mlups']:.0f} MLUPS vs serial graph "
               f"{out['batched']['serial_graph']['mlups']:.0f}, eager {out['batched']['serial_eager']['mlups']:.0f}",
               file=sys.stderr, flush=True)
+    if not args.no_studies:
+        for name, fn in (("precision_8192_variable_D", run_precision_8192), ("refinement", run_refinement),
+                         ("flux_aux_2048", run_flux), ("adjoint_512", run_adjoint)):
+            t0 = time.perf_counter()
+            try:
+                out[name] = fn(torch, W, lbm, Solver)
+            except Exception as e:  # a failed study is reported, not fatal to the line
+                out[name] = {"error": f"{type(e).__name__}: {e}"}
+            print(f"# {name}: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.n)
     print(json.dumps(out))

@@ -56,8 +56,12 @@ Layout layout_of(const lbm_params &p)
 
 // Default launch shape per storage mode (measured on MI355X at 2048^2 and 8192^2; the autotuner in
 // the Python package can override it per instance): one row per wave with XCD-contiguous tiles for
-// FP64/FP32; FP16 codes (2 bytes per lane) prefer a 4-row walk.
-Launch default_launch(int mode) { return mode == MODE_F16S_F32 ? Launch{4, 1} : Launch{1, 1}; }
+// FP64/FP32; FP16 codes (2 bytes per lane) prefer a 4-row walk.  The flux form of the aux term pulls one extra row per walk, so it walks 8 rows.
+Launch default_launch(int mode, int aux)
+{
+    if (aux == LBM_AUX_FLUX) return Launch{8, 1};
+    return mode == MODE_F16S_F32 ? Launch{4, 1} : Launch{1, 1};
+}
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
@@ -423,7 +427,7 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
         in.p = p[k];
         in.mode = mode_of(p[k]);
         in.L = layout_of(p[k]);
-        in.lc = default_launch(in.mode);
+        in.lc = default_launch(in.mode, in.p.aux);
         const size_t pb = pops_bytes(p[k]), vb = vel_bytes(p[k]), fb = field_bytes(p[k]);
         in.buf[0] = w;
         in.buf[1] = w + pb;

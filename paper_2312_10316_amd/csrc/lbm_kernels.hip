@@ -106,8 +106,8 @@ __device__ __forceinline__ void st_nt_at(T *base, unsigned byte_off, T v)
     __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off));
 }
 
-// One tile of one step.  Block (64, 4): lane = column of a 64-wide tile, wave `wave` walks
-// `rows` rows.  The wave's row is uniform (taken with readfirstlane), so row and segment bases live in
+// One tile of one step with the local auxiliary term (or none).  Block (64, 4): lane = column of a
+// 64-wide tile, wave `wave` walks `rows` rows.  The wave's row is uniform (taken with readfirstlane), so row and segment bases live in
 // scalar registers and each load or store needs only a 32-bit lane offset (x, x-1 or x+1).
 template <int MODE, int AUX, bool HAS_K, bool HAS_S>
 __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int t, int wave)
@@ -177,17 +177,6 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
             const M dyuy = (uy_p - uy_m) * M(0.5);
             Ax = phi * (ux_c * dxux + uy_c * dyux);
             Ay = phi * (ux_c * dxuy + uy_c * dyuy);
-        } else if (AUX == 1) {  // d_b(phi u_a u_b) - u_a d_b(phi u_b), phi at the axis neighbours
-            const M pw = phi_at<St, M>(src, a.L, (int)xm, y, a.f16);
-            const M pe = phi_at<St, M>(src, a.L, (int)xp, y, a.f16);
-            const M ps = phi_at<St, M>(src, a.L, (int)xc, ym, a.f16);
-            const M pn = phi_at<St, M>(src, a.L, (int)xc, yn, a.f16);
-            const M uxw = ld_at(uc, fm), uyw = ld_at(uc + pitch, fm), uxe = ld_at(uc, fp), uye = ld_at(uc + pitch, fp);
-            const M fwx = pw * uxw, fex = pe * uxe;    // phi u_x at the west and east neighbours
-            const M fsy = ps * uy_m, fny = pn * uy_p;  // phi u_y at the south and north neighbours
-            const M div = (fex - fwx) * M(0.5) + (fny - fsy) * M(0.5);
-            Ax = (fex * uxe - fwx * uxw) * M(0.5) + (fny * ux_p - fsy * ux_m) * M(0.5) - ux_c * div;
-            Ay = (fex * uye - fwx * uyw) * M(0.5) + (fny * uy_p - fsy * uy_m) * M(0.5) - uy_c * div;
         }
         const Relax<M> r = HAS_K ? relax_from_k<M>(ld_at(kf + (int64_t)y * pitch, fc), lam) : rconst;
         const M s = HAS_S ? ld_at(sf + (int64_t)y * pitch, fc) : M(0);
@@ -205,12 +194,111 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
     }
 }
 
+// One tile of one step with the flux form of the auxiliary term, which needs phi at the four axis
+// neighbours at the same time level.  The walk down the rows is software-pipelined: the pull of row
+// y+1 gives both the next node's populations and phi(x, y+1), phi(x, y-1) is kept from the previous
+// row, and phi(x-1, y), phi(x+1, y) come from the neighbouring lanes (wave shuffles); only the lanes
+// at the tile's edges (and next to the periodic seam) pull their outside neighbour explicitly.
+template <int MODE, bool HAS_K, bool HAS_S>
+__device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity, int t, int wave)
+{
+    using St = typename ModeTraits<MODE>::St;
+    using M = typename ModeTraits<MODE>::M;
+    using T = typename St::T;
+    using C = Codec<St, M>;
+    const int nx = a.L.nx, ny = a.L.ny;
+    const int64_t pitch = a.L.pitch;
+    const int rows = a.lc.rows;
+    const int ntx = (nx + 63) >> 6;
+    const unsigned lane = threadIdx.x;
+    const unsigned x = (unsigned)((t % ntx) * 64) + lane;
+    const int y0 = ((t / ntx) * 4 + wave) * rows;
+    if (y0 >= ny) return;
+    const bool live = x < (unsigned)nx;
+    const unsigned xc = live ? x : 0u;
+    const unsigned xm = xc == 0 ? (unsigned)nx - 1 : xc - 1;
+    const unsigned xp = xc == (unsigned)nx - 1 ? 0u : xc + 1;
+    const bool need_w = lane == 0;                                  // west neighbour not in this wave
+    const bool need_e = lane == 63 || (live && xc == (unsigned)nx - 1);  // east neighbour not in this wave
+    const int y1 = min(y0 + rows, ny);
+    const T *__restrict__ src = static_cast<const T *>(a.buf[parity]);
+    T *__restrict__ dst = static_cast<T *>(a.buf[parity ^ 1]);
+    const M *__restrict__ u = static_cast<const M *>(a.u);
+    const M *__restrict__ kf = static_cast<const M *>(a.k);
+    const M *__restrict__ sf = static_cast<const M *>(a.s);
+    const M lam = (M)a.lambda;
+    Relax<M> rconst;
+    rconst.w1 = (M)a.w1;
+    rconst.w2 = (M)a.w2;
+    rconst.beta = (M)a.beta;
+    auto row_pull = [&](int yy, M (&g)[9]) {
+        pull<St, M>(row_block(src, a.L, wrap_dec(yy, ny)), row_block(src, a.L, yy), row_block(src, a.L, wrap_inc(yy, ny)),
+                    pitch, (int)xm, (int)xc, (int)xp, a.f16, g);
+    };
+    auto sum9 = [](const M (&g)[9]) { return g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8]; };
+
+    M g[9], gn[9];
+    row_pull(y0, g);
+    M phi_c = sum9(g);
+    M phi_m;
+    {
+        M gm[9];
+        row_pull(wrap_dec(y0, ny), gm);
+        phi_m = sum9(gm);
+    }
+    const int yprev = wrap_dec(y0, ny);
+    M ux_m = u[(int64_t)yprev * 2 * pitch + xc], uy_m = u[((int64_t)yprev * 2 + 1) * pitch + xc];
+    M ux_c = u[(int64_t)y0 * 2 * pitch + xc], uy_c = u[((int64_t)y0 * 2 + 1) * pitch + xc];
+    for (int y = y0; y < y1; ++y) {
+        const int yn = wrap_inc(y, ny);
+        row_pull(yn, gn);
+        const M phi_p = sum9(gn);
+        const M *__restrict__ uc = u + (int64_t)y * 2 * pitch;
+        const M *__restrict__ un = u + (int64_t)yn * 2 * pitch;
+        const M ux_p = un[xc], uy_p = un[pitch + xc];
+        M pw = __shfl_up(phi_c, 1, 64), pe = __shfl_down(phi_c, 1, 64);
+        if (need_w) pw = phi_at<St, M>(src, a.L, (int)xm, y, a.f16);
+        if (need_e) pe = phi_at<St, M>(src, a.L, (int)xp, y, a.f16);
+        const M uxw = uc[xm], uyw = uc[pitch + xm], uxe = uc[xp], uye = uc[pitch + xp];
+        const M fwx = pw * uxw, fex = pe * uxe;          // phi u_x at the west and east neighbours
+        const M fsy = phi_m * uy_m, fny = phi_p * uy_p;  // phi u_y at the south and north neighbours
+        const M div = (fex - fwx) * M(0.5) + (fny - fsy) * M(0.5);
+        const M Ax = (fex * uxe - fwx * uxw) * M(0.5) + (fny * ux_p - fsy * ux_m) * M(0.5) - ux_c * div;
+        const M Ay = (fex * uye - fwx * uyw) * M(0.5) + (fny * uy_p - fsy * uy_m) * M(0.5) - uy_c * div;
+        const Relax<M> r = HAS_K ? relax_from_k<M>(kf[(int64_t)y * pitch + xc], lam) : rconst;
+        const M s = HAS_S ? sf[(int64_t)y * pitch + xc] : M(0);
+        M P[9];
+        collide<M>(g, ux_c, uy_c, r, Ax, Ay, s, P);
+        if (live) {
+            T *__restrict__ out = dst + (int64_t)y * 9 * pitch;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(C::enc(P[i], i, a.f16), (out + i * pitch) + x);
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = gn[i];
+        phi_m = phi_c;
+        phi_c = phi_p;
+        ux_m = ux_c;
+        uy_m = uy_c;
+        ux_c = ux_p;
+        uy_c = uy_p;
+    }
+}
+
+// Dispatch of one tile to the aux-term form.
+template <int MODE, int AUX, bool HAS_K, bool HAS_S>
+__device__ __forceinline__ void run_tile(const InstDesc &d, int parity, int t, int wave)
+{
+    if constexpr (AUX == 1) process_tile_flux<MODE, HAS_K, HAS_S>(d, parity, t, wave);
+    else process_tile<MODE, AUX, HAS_K, HAS_S>(d, parity, t, wave);
+}
+
 // Single instance: block b -> tile (XCD-remapped if requested).
 template <int MODE, int AUX, bool HAS_K, bool HAS_S>
 __global__ __launch_bounds__(256) void step_kernel(const StepArgs a)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
-    process_tile<MODE, AUX, HAS_K, HAS_S>(a.d, a.parity, tile_of_block(blockIdx.x, gridDim.x, a.d.lc.xcd_remap), wave);
+    run_tile<MODE, AUX, HAS_K, HAS_S>(a.d, a.parity, tile_of_block(blockIdx.x, gridDim.x, a.d.lc.xcd_remap), wave);
 }
 
 // Many instances in one launch: each block runs a range of (instance, tile) work items; the
@@ -231,11 +319,11 @@ __global__ __launch_bounds__(256) void batched_step_kernel(const BatchArgs a)
         const WorkItem w = a.items[it];
         const InstDesc &d = a.inst[w.inst];
         if (d.has_k) {
-            if (d.has_s) process_tile<MODE, AUX, true, true>(d, a.parity, w.tile, wave);
-            else process_tile<MODE, AUX, true, false>(d, a.parity, w.tile, wave);
+            if (d.has_s) run_tile<MODE, AUX, true, true>(d, a.parity, w.tile, wave);
+            else run_tile<MODE, AUX, true, false>(d, a.parity, w.tile, wave);
         } else {
-            if (d.has_s) process_tile<MODE, AUX, false, true>(d, a.parity, w.tile, wave);
-            else process_tile<MODE, AUX, false, false>(d, a.parity, w.tile, wave);
+            if (d.has_s) run_tile<MODE, AUX, false, true>(d, a.parity, w.tile, wave);
+            else run_tile<MODE, AUX, false, false>(d, a.parity, w.tile, wave);
         }
     }
 }

@@ -411,11 +411,12 @@ def test_graph_replay_matches_eager_steps():
     b.close()
 
 
-@pytest.mark.parametrize("mode", ["f64", "f16s"])
-def test_launch_shape_does_not_change_results(mode):
+@pytest.mark.parametrize("mode,aux", [("f64", lbm.LBM_AUX_LOCAL), ("f16s", lbm.LBM_AUX_LOCAL),
+                                      ("f64", lbm.LBM_AUX_FLUX), ("f32", lbm.LBM_AUX_FLUX)])
+def test_launch_shape_does_not_change_results(mode, aux):
     cfg = W.PulseConfig(N=200, steps=0, D_variable=True)
     f = W.rotating_pulse(cfg)
-    p = lbm.make_params(cfg.N, cfg.N - 37, f["dx"], f["dt"], cfg.lam, cfg.D, mode)
+    p = lbm.make_params(cfg.N, cfg.N - 37, f["dx"], f["dt"], cfg.lam, cfg.D, mode, aux)
     fields = {k: dev(np.ascontiguousarray(f[k][:cfg.N - 37])) for k in ("phi0", "ux", "uy", "D")}
     states = []
     for rows, remap in ((1, 0), (4, 1), (7, 1), (64, 0)):
