@@ -7,7 +7,7 @@
  *
  *     d_t phi + d_a(phi u_a) = d_a(kappa d_a phi) + S                     (Sec. 2.1, Eq. (1))
  *
- * on periodic D2Q9 lattices.  One step is the evolution equation of Sec. 2.2, Eq. (14): the TRT-R
+ * on D2Q9 lattices, periodic or with Dirichlet edges.  One step is the evolution equation of Sec. 2.2, Eq. (14): the TRT-R
  * collision of Eq. (12) (third-order Hermite equilibrium, Eq. (6); Hermite-regularized first- and
  * second-order non-equilibrium moments, Eqs. (8) and (13), relaxed with tau1 and tau2), the
  * first-order discrete-velocity source of Eq. (3) with its time derivative, and the space-derivative
@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 1
+#define LBM_ABI_VERSION 2
 
 enum lbm_status {
     LBM_OK = 0,
@@ -61,7 +61,16 @@ enum lbm_math { LBM_MATH_F64 = 0, LBM_MATH_F32 = 1 };
  *   NONE:  G_i = 0 (ablation). */
 enum lbm_aux { LBM_AUX_LOCAL = 0, LBM_AUX_FLUX = 1, LBM_AUX_NONE = 2 };
 
-/* One problem instance: the paper's problem statement on a periodic lattice. */
+/* Boundary treatment.  PERIODIC: both axes wrap.  NEE: the first and last rows and columns are
+ * Dirichlet nodes handled by non-equilibrium extrapolation (the boundary scheme of the benchmark of
+ * Sec. 3; Guo, Zheng & Shi 2002): before each collision, every boundary node x_b takes
+ * g_i(x_b) = g_eq_i(phi_b(x_b), u(x_b)) + [g_i(x_f) - g_eq_i(phi(x_f), u(x_f))], x_f its interior
+ * neighbour along the inward normal (diagonal at corners), phi_b set by lbm_set_dirichlet.  The
+ * differences of u in the LOCAL auxiliary term are one-sided across an edge.  NEE is available with
+ * aux LOCAL or NONE, runs one launch per instance, and has no adjoint. */
+enum lbm_boundary { LBM_BC_PERIODIC = 0, LBM_BC_NEE = 1 };
+
+/* One problem instance: the paper's problem statement on a lattice. */
 typedef struct lbm_params {
     int32_t nx, ny;       /* lattice size, each >= 3 */
     double dx, dt;        /* lattice spacing and time step, finite and > 0 */
@@ -72,6 +81,8 @@ typedef struct lbm_params {
     int32_t aux;          /* enum lbm_aux */
     int32_t scale_log2;   /* F16S only: 0..24 */
     double phi_ref;       /* F16S only: background value removed before encoding */
+    int32_t boundary;     /* enum lbm_boundary */
+    int32_t reserved;     /* must be 0 */
 } lbm_params;
 
 /* Fields of one instance (device, FP64, [ny][nx]).  u is in physical units; D > 0 everywhere.
@@ -118,6 +129,12 @@ int lbm_init(lbm_ctx **ctx, int32_t n_inst, const lbm_params *p, const lbm_field
  *         instance without a source; dSdt entries may be NULL (zero derivative). */
 int lbm_step(lbm_ctx *ctx, int32_t nsteps, const double *const *ux, const double *const *uy,
              const double *const *S, const double *const *dSdt);
+
+/* Dirichlet values of an LBM_BC_NEE instance: phi_b (device FP64 [ny][nx], copied; only its
+ * boundary entries take effect) is used from the next step on, and by lbm_macros / lbm_populations,
+ * which report the boundary nodes after extrapolation (so phi = phi_b there).  Before the first call
+ * the values are phi0's.  Asynchronous (stream order).  LBM_E_STATE for a periodic instance. */
+int lbm_set_dirichlet(lbm_ctx *ctx, int32_t inst, const double *phi_b);
 
 /* Diagnostics of instance inst: phi = sum_i g_i at the current time.  phi_out (device FP64
  * [ny][nx], nullable) receives phi; ref (device FP64 [ny][nx], nullable) is the field the error

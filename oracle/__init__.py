@@ -27,6 +27,7 @@ _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 AUX_LOCAL, AUX_FLUX, AUX_NONE = 0, 1, 2
+BC_PERIODIC, BC_NEE = 0, 1
 
 
 def build(force: bool = False) -> str:
@@ -50,7 +51,7 @@ def build(force: bool = False) -> str:
 class _Problem(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("dx", ctypes.c_double),
                 ("dt", ctypes.c_double), ("lambda_", ctypes.c_double), ("D_const", ctypes.c_double),
-                ("aux", ctypes.c_int)]
+                ("aux", ctypes.c_int), ("boundary", ctypes.c_int)]
 
 
 _lib = None
@@ -72,6 +73,7 @@ def _load():
             getattr(lib, pre + "phi").argtypes = [P, P, P]
             getattr(lib, pre + "step").argtypes = [P, P, P, P, P, P, P, P]
             getattr(lib, pre + "run").argtypes = [P, P, i32, P, P, P, P, P, P]
+            getattr(lib, pre + "apply_nee").argtypes = [P, P, P, P, P]
         del zc
         _lib = lib
     return _lib
@@ -79,7 +81,7 @@ def _load():
 
 @dataclass
 class Problem:
-    """One periodic instance: lattice, time step, magic parameter, constant D, aux-term form."""
+    """One instance: lattice, time step, magic parameter, constant D, aux-term form, edge treatment."""
     nx: int
     ny: int
     dx: float
@@ -87,9 +89,10 @@ class Problem:
     lam: float
     D_const: float = 0.0
     aux: int = AUX_LOCAL
+    boundary: int = BC_PERIODIC   # BC_NEE: one-sided derivatives of u across the edges (apply_nee per step)
 
     def _c(self) -> _Problem:
-        return _Problem(self.nx, self.ny, self.dx, self.dt, self.lam, self.D_const, self.aux)
+        return _Problem(self.nx, self.ny, self.dx, self.dt, self.lam, self.D_const, self.aux, self.boundary)
 
     @property
     def c(self) -> float:
@@ -191,6 +194,19 @@ def run(p: Problem, g, nsteps: int, ux, uy, D=None, S=None, dSdt=None) -> np.nda
     pc = p._c()
     (lib.orc_z_run if cplx else lib.orc_run)(ctypes.byref(pc), _ptr(g), int(nsteps), _ptr(ux), _ptr(uy),
                                              _ptr(D), _ptr(S), _ptr(dSdt), _ptr(work))
+    return g
+
+
+def apply_nee(p: Problem, g, ux, uy, phi_b) -> np.ndarray:
+    """Dirichlet edges by non-equilibrium extrapolation (the boundary scheme of Sec. 3), applied to
+    a copy of the pre-collision state g; phi_b [ny, nx] holds the boundary values."""
+    lib = _load()
+    cplx = np.iscomplexobj(g) or np.iscomplexobj(phi_b)
+    g = np.array(g, dtype=np.complex128 if cplx else np.float64, copy=True, order="C")
+    ux, uy, *_ = _fields(p, ux, uy, None, None, None, cplx)
+    pb = _arr(phi_b, (p.ny, p.nx), cplx)
+    pc = p._c()
+    (lib.orc_z_apply_nee if cplx else lib.orc_apply_nee)(ctypes.byref(pc), _ptr(g), _ptr(ux), _ptr(uy), _ptr(pb))
     return g
 
 

@@ -58,6 +58,9 @@ typedef struct orc_problem {
     double D_const;    /* diffusion coefficient kappa when no field is given */
     int aux;           /* 0: auxiliary term of Eq. (16) with local phi; 1: flux-difference form;
                           2: no auxiliary term (ablation) */
+    int boundary;      /* 0: periodic; 1: Dirichlet edges (the first and last rows and columns are
+                          rebuilt by apply_nee before each step; across an edge the derivatives of
+                          u in the auxiliary term are one-sided instead of wrapped) */
 } orc_problem;
 
 #ifndef ORC_COMPLEX
@@ -211,15 +214,22 @@ void ORC(step)(const orc_problem *p, const real *g_in, real *g_out, const real *
             nb[1][1] = (size_t)wrap(y + 1, ny) * nx + x;
             const real *u[2] = {ux, uy};
             real un[2] = {ux[n], uy[n]};
+            /* difference stencil d_b u ~ (u[hi] - u[lo]) / h: central, or one-sided at a Dirichlet edge */
+            size_t lo[2] = {nb[0][0], nb[1][0]}, hi[2] = {nb[0][1], nb[1][1]};
+            double h[2] = {2.0 * dx, 2.0 * dx};
+            if (p->boundary == 1) {
+                if (x == 0) { lo[0] = n; h[0] = dx; } else if (x == nx - 1) { hi[0] = n; h[0] = dx; }
+                if (y == 0) { lo[1] = n; h[1] = dx; } else if (y == ny - 1) { hi[1] = n; h[1] = dx; }
+            }
 
             /* A_a multiplies w_i e_ia / cs2 (1 - 1/(2 tau1)) in G_i */
             real A[2] = {0, 0};
             if (p->aux == 0) {
-                /* Eq. (16): phi u_b d_b u_a, d_b by central differences of the nodal u */
+                /* Eq. (16): phi u_b d_b u_a, d_b by differences of the nodal u */
                 for (int a = 0; a < 2; ++a) {
                     real s = 0;
                     for (int b = 0; b < 2; ++b) {
-                        real dbua = (u[a][nb[b][1]] - u[a][nb[b][0]]) / (2.0 * dx);
+                        real dbua = (u[a][hi[b]] - u[a][lo[b]]) / h[b];
                         s += un[b] * dbua;
                     }
                     A[a] = phi * s;
@@ -259,6 +269,33 @@ void ORC(step)(const orc_problem *p, const real *g_in, real *g_out, const real *
         }
     }
     free(phi_all);
+}
+
+/* Dirichlet edges by non-equilibrium extrapolation (Guo, Zheng and Shi, Chinese Physics 2002), the
+ * boundary scheme of the benchmark of Sec. 3: the first and last rows and columns are boundary nodes;
+ * at each boundary node x_b, with x_f its interior neighbour along the inward normal (the diagonal
+ * neighbour at a corner),
+ *   g_i(x_b) = g_eq_i(phi_b(x_b), u(x_b)) + [ g_i(x_f) - g_eq_i(phi(x_f), u(x_f)) ],  phi(x_f) = sum_i g_i(x_f).
+ * Applied in place to the pre-collision state at t_n, before the step.  phi_b: [ny][nx] (only
+ * boundary entries are read). */
+void ORC(apply_nee)(const orc_problem *p, real *g, const real *ux, const real *uy, const real *phi_b)
+{
+    const int nx = p->nx, ny = p->ny;
+    const size_t N = (size_t)nx * ny;
+    const double c = p->dx / p->dt;
+    for (int y = 0; y < ny; ++y) {
+        for (int x = 0; x < nx; ++x) {
+            if (!(x == 0 || x == nx - 1 || y == 0 || y == ny - 1)) continue;
+            const int xf = x + (x == 0) - (x == nx - 1), yf = y + (y == 0) - (y == ny - 1);
+            const size_t b = (size_t)y * nx + x, f = (size_t)yf * nx + xf;
+            real phif = 0;
+            for (int i = 0; i < 9; ++i) phif += g[i * N + f];
+            real geq_f[9], geq_b[9];
+            ORC(equilibrium)(phif, ux[f], uy[f], c, geq_f);
+            ORC(equilibrium)(phi_b[b], ux[b], uy[b], c, geq_b);
+            for (int i = 0; i < 9; ++i) g[i * N + b] = geq_b[i] + (g[i * N + f] - geq_f[i]);
+        }
+    }
 }
 
 /* nsteps repeated steps on g (in place); work holds 9*nx*ny values of scratch. */

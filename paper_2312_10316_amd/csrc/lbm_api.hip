@@ -76,6 +76,11 @@ int validate(const lbm_params &p, int k)
     if (p.math == LBM_MATH_F64 && p.store != LBM_STORE_F64)
         return fail(LBM_E_ARG, "instance %d: FP64 math needs FP64 storage", k);
     if (p.aux < LBM_AUX_LOCAL || p.aux > LBM_AUX_NONE) return fail(LBM_E_ARG, "instance %d: unknown aux %d", k, p.aux);
+    if (p.boundary != LBM_BC_PERIODIC && p.boundary != LBM_BC_NEE)
+        return fail(LBM_E_ARG, "instance %d: unknown boundary %d", k, p.boundary);
+    if (p.reserved != 0) return fail(LBM_E_ARG, "instance %d: reserved field must be 0", k);
+    if (p.boundary == LBM_BC_NEE && p.aux == LBM_AUX_FLUX)
+        return fail(LBM_E_UNSUPPORTED, "instance %d: the flux form of the aux term has no Dirichlet edges", k);
     if (p.store == LBM_STORE_F16S) {
         if (p.scale_log2 < 0 || p.scale_log2 > 24)
             return fail(LBM_E_ARG, "instance %d: scale_log2=%d outside 0..24", k, p.scale_log2);
@@ -103,7 +108,7 @@ struct Instance {
     Layout L;
     Launch lc;
     char *buf[2];
-    void *u, *k, *s;
+    void *u, *k, *s, *bc;
     bool has_D;
     bool has_src;
     int64_t step;
@@ -114,7 +119,10 @@ struct Instance {
 size_t pops_bytes(const lbm_params &p) { return align_up((size_t)pop_elems(layout_of(p)) * store_bytes(mode_of(p)), kAlign); }
 size_t vel_bytes(const lbm_params &p) { return align_up((size_t)vel_elems(layout_of(p)) * math_bytes(mode_of(p)), kAlign); }
 size_t field_bytes(const lbm_params &p) { return align_up((size_t)fld_elems(layout_of(p)) * math_bytes(mode_of(p)), kAlign); }
-size_t instance_bytes(const lbm_params &p) { return 2 * pops_bytes(p) + vel_bytes(p) + 2 * field_bytes(p); }
+size_t instance_bytes(const lbm_params &p)
+{
+    return 2 * pops_bytes(p) + vel_bytes(p) + (p.boundary == LBM_BC_NEE ? 3 : 2) * field_bytes(p);
+}
 
 size_t max_items_of(int32_t n_inst, const lbm_params *p)
 {
@@ -158,6 +166,8 @@ InstDesc desc_of(const Instance &in)
     d.lc = in.lc;
     d.has_k = in.has_D ? 1 : 0;
     d.has_s = in.has_src ? 1 : 0;
+    d.bc = in.bc;
+    d.nee = in.p.boundary == LBM_BC_NEE ? 1 : 0;
     if (!in.has_D) const_relax(in.p, d.w1, d.w2, d.beta);
     d.lambda = in.p.lambda;
     d.f16 = in.f16;
@@ -437,11 +447,17 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
         in.k = w;
         in.s = w + fb;
         w += 2 * fb;
+        in.bc = nullptr;
+        if (p[k].boundary == LBM_BC_NEE) {
+            in.bc = w;
+            w += fb;
+        }
         in.has_D = f[k].D != nullptr;
         in.has_src = false;
         in.step = 0;
         in.f16 = f16_of(p[k]);
-        if (in.mode != c->inst[0].mode || in.p.aux != c->inst[0].p.aux) c->uniform = false;
+        if (in.mode != c->inst[0].mode || in.p.aux != c->inst[0].p.aux || in.p.boundary != LBM_BC_PERIODIC)
+            c->uniform = false;  // batched launches cover periodic instances of one storage/aux form
     }
     const size_t items = max_items_of(n_inst, p);
     c->d_desc = reinterpret_cast<InstDesc *>(w);
@@ -463,6 +479,8 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
         rc = set_velocity(c, in, f[k].ux, f[k].uy);
         if (rc == LBM_OK && in.has_D)  // k = tau1 - 1/2 = kappa / (cs^2 dt) = 3 kappa dt / dx^2
             rc = prep_field(c, in, f[k].D, nullptr, 3.0 * in.p.dt / (in.p.dx * in.p.dx), 0.0, in.k, 1);
+        if (rc == LBM_OK && in.bc)  // Dirichlet values start as phi0 on the edges
+            rc = prep_field(c, in, f[k].phi0, nullptr, 1.0, 0.0, in.bc, 0);
         if (rc == LBM_OK) {
             InitArgs ia;
             ia.phi0 = f[k].phi0;
@@ -550,6 +568,8 @@ int lbm_macros(lbm_ctx *c, int32_t inst, double *phi_out, const double *ref, lbm
     a.phi_out = phi_out;
     a.L = in.L;
     a.f16 = in.f16;
+    a.edge.u = in.u;
+    a.edge.bc = in.bc;
     a.partials = c->partials;
     hipError_t e = launch_macros(in.mode, a, c->result, c->stream);
     if (e != hipSuccess) return hip_fail(e, "macros kernel launch");
@@ -570,6 +590,16 @@ int lbm_macros(lbm_ctx *c, int32_t inst, double *phi_out, const double *ref, lbm
     return LBM_OK;
 }
 
+int lbm_set_dirichlet(lbm_ctx *c, int32_t inst, const double *phi_b)
+{
+    g_err[0] = 0;
+    if (!check_inst(c, inst)) return fail(LBM_E_STATE, "lbm_set_dirichlet: bad context or instance %d", inst);
+    if (!phi_b) return fail(LBM_E_ARG, "lbm_set_dirichlet: phi_b is NULL");
+    Instance &in = c->inst[inst];
+    if (in.p.boundary != LBM_BC_NEE) return fail(LBM_E_STATE, "lbm_set_dirichlet: instance %d is periodic", inst);
+    return prep_field(c, in, phi_b, nullptr, 1.0, 0.0, in.bc, 0);
+}
+
 int lbm_populations(lbm_ctx *c, int32_t inst, double *g_out)
 {
     g_err[0] = 0;
@@ -581,6 +611,8 @@ int lbm_populations(lbm_ctx *c, int32_t inst, double *g_out)
     a.out = g_out;
     a.L = in.L;
     a.f16 = in.f16;
+    a.edge.u = in.u;
+    a.edge.bc = in.bc;
     hipError_t e = launch_populations(in.mode, a, c->stream);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "populations kernel launch");
 }
@@ -671,6 +703,7 @@ int adjoint_ok(lbm_ctx *c, int32_t inst, const char *who)
     const Instance &in = c->inst[inst];
     if (in.mode == MODE_F16S_F32) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for FP16 storage", who);
     if (in.p.aux == LBM_AUX_FLUX) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for the flux form of the aux term", who);
+    if (in.p.boundary != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for Dirichlet edges", who);
     return LBM_OK;
 }
 }  // namespace

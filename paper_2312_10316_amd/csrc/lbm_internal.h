@@ -54,6 +54,8 @@ struct InstDesc {
     Layout L;
     Launch lc;
     int32_t has_k, has_s;
+    const void *bc;     // Dirichlet values phi_b (math type, [ny][pitch]) of a non-equilibrium-extrapolation edge
+    int32_t nee;        // 1: the first/last rows and columns are Dirichlet nodes (bc)
     double w1, w2, beta;  // relaxation when !has_k: 1 - 1/tau1, 1 - 1/tau2, 1 - 1/(2 tau1)
     double lambda;
     F16Params f16;
@@ -104,12 +106,19 @@ struct PrepArgs {
     int check_positive;
 };
 
+// Boundary data the diagnostics need to report the extrapolated Dirichlet nodes.
+struct EdgeArgs {
+    const void *u;     // velocity (math type)
+    const void *bc;    // phi_b (math type), or nullptr for a periodic instance
+};
+
 struct MacroArgs {
     const void *src;   // populations holding the current state
     const double *ref; // nullable
     double *phi_out;   // nullable
     Layout L;
     F16Params f16;
+    EdgeArgs edge;
     double *partials;  // per block: kMacroPartialDoubles
 };
 
@@ -121,6 +130,7 @@ struct PopArgs {
     double *out;  // dense FP64 [9][ny][nx]
     Layout L;
     F16Params f16;
+    EdgeArgs edge;
 };
 
 // Adjoint of one step (lbm_adjoint.hip).

@@ -75,6 +75,30 @@ __device__ __forceinline__ void pull_node(const typename St::T *__restrict__ src
                 L.pitch, wrap_dec(x, L.nx), x, wrap_inc(x, L.nx), f, g);
 }
 
+// Dirichlet node (x, y) of a non-equilibrium-extrapolation edge (Guo, Zheng & Shi 2002; the boundary
+// scheme of the benchmark of Sec. 3): g = g_eq(phi_b, u) + [g(x_f) - g_eq(phi(x_f), u(x_f))], x_f the
+// interior neighbour along the inward normal (diagonal at a corner).
+__device__ __forceinline__ bool on_edge(int x, int y, const Layout &L)
+{
+    return x == 0 || y == 0 || x == L.nx - 1 || y == L.ny - 1;
+}
+
+template <class St, class M>
+__device__ __forceinline__ void nee_replace(const typename St::T *__restrict__ src, const M *__restrict__ u,
+                                            const M *__restrict__ bc, const Layout &L, int x, int y,
+                                            const F16Params &f, M (&g)[9])
+{
+    const int xf = x + (x == 0) - (x == L.nx - 1), yf = y + (y == 0) - (y == L.ny - 1);
+    M gf[9];
+    pull_node<St, M>(src, L, xf, yf, f, gf);
+    const M phif = gf[0] + gf[1] + gf[2] + gf[3] + gf[4] + gf[5] + gf[6] + gf[7] + gf[8];
+    M ef[9], eb[9];
+    equilibrium<M>(phif, u[(int64_t)yf * 2 * L.pitch + xf], u[((int64_t)yf * 2 + 1) * L.pitch + xf], ef);
+    equilibrium<M>(bc[(int64_t)y * L.pitch + x], u[(int64_t)y * 2 * L.pitch + x], u[((int64_t)y * 2 + 1) * L.pitch + x], eb);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) g[i] = eb[i] + (gf[i] - ef[i]);
+}
+
 template <class St, class M>
 __device__ __forceinline__ M phi_at(const typename St::T *__restrict__ src, const Layout &L, int x, int y,
                                     const F16Params &f)
@@ -109,7 +133,7 @@ __device__ __forceinline__ void st_nt_at(T *base, unsigned byte_off, T v)
 // One tile of one step with the local auxiliary term (or none).  Block (64, 4): lane = column of a
 // 64-wide tile, wave `wave` walks `rows` rows.  The wave's row is uniform (taken with readfirstlane), so row and segment bases live in
 // scalar registers and each load or store needs only a 32-bit lane offset (x, x-1 or x+1).
-template <int MODE, int AUX, bool HAS_K, bool HAS_S>
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, bool NEE = false>
 __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int t, int wave)
 {
     using St = typename ModeTraits<MODE>::St;
@@ -164,6 +188,10 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
         g[6] = C::dec(ld_at(rm + 6 * pitch, bp), 6, a.f16);
         g[7] = C::dec(ld_at(rp + 7 * pitch, bp), 7, a.f16);
         g[8] = C::dec(ld_at(rp + 8 * pitch, bm), 8, a.f16);
+        if constexpr (NEE) {
+            if (y == 0 || y == ny - 1 || xc == 0 || xc == (unsigned)nx - 1)
+                nee_replace<St, M>(src, u, static_cast<const M *>(a.bc), a.L, (int)xc, y, a.f16, g);
+        }
         const M *__restrict__ un = u + (int64_t)yn * 2 * pitch;
         const M *__restrict__ uc = u + (int64_t)y * 2 * pitch;
         const M ux_p = ld_at(un, fc), uy_p = ld_at(un + pitch, fc);
@@ -171,10 +199,18 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
         M Ax = M(0), Ay = M(0);
         if (AUX == 0) {  // Eq. (16): phi u_b d_b u_a, central differences of u
             const M phi = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
-            const M dxux = (ld_at(uc, fp) - ld_at(uc, fm)) * M(0.5);
-            const M dxuy = (ld_at(uc + pitch, fp) - ld_at(uc + pitch, fm)) * M(0.5);
-            const M dyux = (ux_p - ux_m) * M(0.5);
-            const M dyuy = (uy_p - uy_m) * M(0.5);
+            // across a Dirichlet edge the difference is one-sided (the wrapped neighbour is not adjacent)
+            unsigned fl = fm, fr = fp;
+            M hx = M(0.5), hy = M(0.5), uxl = ux_m, uyl = uy_m, uxr = ux_p, uyr = uy_p;
+            if constexpr (NEE) {
+                if (xc == 0) { fl = fc; hx = M(1); } else if (xc == (unsigned)nx - 1) { fr = fc; hx = M(1); }
+                if (y == 0) { uxl = ux_c; uyl = uy_c; hy = M(1); }
+                else if (y == ny - 1) { uxr = ux_c; uyr = uy_c; hy = M(1); }
+            }
+            const M dxux = (ld_at(uc, fr) - ld_at(uc, fl)) * hx;
+            const M dxuy = (ld_at(uc + pitch, fr) - ld_at(uc + pitch, fl)) * hx;
+            const M dyux = (uxr - uxl) * hy;
+            const M dyuy = (uyr - uyl) * hy;
             Ax = phi * (ux_c * dxux + uy_c * dyux);
             Ay = phi * (ux_c * dxuy + uy_c * dyuy);
         }
@@ -286,19 +322,19 @@ __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity,
 }
 
 // Dispatch of one tile to the aux-term form.
-template <int MODE, int AUX, bool HAS_K, bool HAS_S>
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, bool NEE = false>
 __device__ __forceinline__ void run_tile(const InstDesc &d, int parity, int t, int wave)
 {
     if constexpr (AUX == 1) process_tile_flux<MODE, HAS_K, HAS_S>(d, parity, t, wave);
-    else process_tile<MODE, AUX, HAS_K, HAS_S>(d, parity, t, wave);
+    else process_tile<MODE, AUX, HAS_K, HAS_S, NEE>(d, parity, t, wave);
 }
 
 // Single instance: block b -> tile (XCD-remapped if requested).
-template <int MODE, int AUX, bool HAS_K, bool HAS_S>
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, bool NEE>
 __global__ __launch_bounds__(256) void step_kernel(const StepArgs a)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
-    run_tile<MODE, AUX, HAS_K, HAS_S>(a.d, a.parity, tile_of_block(blockIdx.x, gridDim.x, a.d.lc.xcd_remap), wave);
+    run_tile<MODE, AUX, HAS_K, HAS_S, NEE>(a.d, a.parity, tile_of_block(blockIdx.x, gridDim.x, a.d.lc.xcd_remap), wave);
 }
 
 // Many instances in one launch: each block runs a range of (instance, tile) work items; the
@@ -435,6 +471,8 @@ __global__ __launch_bounds__(256) void macros_kernel(const MacroArgs a)
         const int x = (int)(n % nx), y = (int)(n / nx);
         M g[9];
         pull_node<St, M>(src, a.L, x, y, a.f16, g);
+        if (a.edge.bc && on_edge(x, y, a.L))
+            nee_replace<St, M>(src, static_cast<const M *>(a.edge.u), static_cast<const M *>(a.edge.bc), a.L, x, y, a.f16, g);
         double phi = 0;
 #pragma unroll
         for (int i = 0; i < 9; ++i) phi += (double)g[i];
@@ -500,6 +538,8 @@ __global__ __launch_bounds__(256) void populations_kernel(const PopArgs a)
         const int x = (int)(n % nx), y = (int)(n / nx);
         M g[9];
         pull_node<St, M>(src, a.L, x, y, a.f16, g);
+        if (a.edge.bc && on_edge(x, y, a.L))
+            nee_replace<St, M>(src, static_cast<const M *>(a.edge.u), static_cast<const M *>(a.edge.bc), a.L, x, y, a.f16, g);
 #pragma unroll
         for (int i = 0; i < 9; ++i) a.out[i * N + n] = (double)g[i];
     }
@@ -520,17 +560,28 @@ int grid_for(int64_t n, int block, int cap)
     return (int)(g < 1 ? 1 : g);
 }
 
-template <int MODE, int AUX>
-hipError_t launch_step_aux(const StepArgs &a, hipStream_t st)
+template <int MODE, int AUX, bool NEE>
+hipError_t launch_step_bc(const StepArgs &a, hipStream_t st)
 {
     dim3 block(64, 4);
     const int nblocks = tiles_of(a.d.L, a.d.lc.rows);
     const bool hk = a.d.has_k, hs = a.d.has_s;
-    if (hk && hs) step_kernel<MODE, AUX, true, true><<<nblocks, block, 0, st>>>(a);
-    else if (hk) step_kernel<MODE, AUX, true, false><<<nblocks, block, 0, st>>>(a);
-    else if (hs) step_kernel<MODE, AUX, false, true><<<nblocks, block, 0, st>>>(a);
-    else step_kernel<MODE, AUX, false, false><<<nblocks, block, 0, st>>>(a);
+    if (hk && hs) step_kernel<MODE, AUX, true, true, NEE><<<nblocks, block, 0, st>>>(a);
+    else if (hk) step_kernel<MODE, AUX, true, false, NEE><<<nblocks, block, 0, st>>>(a);
+    else if (hs) step_kernel<MODE, AUX, false, true, NEE><<<nblocks, block, 0, st>>>(a);
+    else step_kernel<MODE, AUX, false, false, NEE><<<nblocks, block, 0, st>>>(a);
     return hipGetLastError();
+}
+
+template <int MODE, int AUX>
+hipError_t launch_step_aux(const StepArgs &a, hipStream_t st)
+{
+    if constexpr (AUX == 1) {
+        if (a.d.nee) return hipErrorInvalidValue;  // the flux form has no Dirichlet edges
+        return launch_step_bc<MODE, AUX, false>(a, st);
+    } else {
+        return a.d.nee ? launch_step_bc<MODE, AUX, true>(a, st) : launch_step_bc<MODE, AUX, false>(a, st);
+    }
 }
 
 template <int MODE>

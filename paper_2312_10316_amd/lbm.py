@@ -19,6 +19,7 @@ LBM_OK, LBM_E_ARG, LBM_E_HIP, LBM_E_STATE, LBM_E_NONFINITE, LBM_E_UNSUPPORTED = 
 LBM_STORE_F64, LBM_STORE_F32, LBM_STORE_F16S = 0, 1, 2
 LBM_MATH_F64, LBM_MATH_F32 = 0, 1
 LBM_AUX_LOCAL, LBM_AUX_FLUX, LBM_AUX_NONE = 0, 1, 2
+LBM_BC_PERIODIC, LBM_BC_NEE = 0, 1
 
 # names of the population storage / arithmetic combinations
 MODES = {
@@ -40,7 +41,7 @@ class lbm_params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("dx", ctypes.c_double), ("dt", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("D_const", ctypes.c_double), ("store", ctypes.c_int32),
                 ("math", ctypes.c_int32), ("aux", ctypes.c_int32), ("scale_log2", ctypes.c_int32),
-                ("phi_ref", ctypes.c_double)]
+                ("phi_ref", ctypes.c_double), ("boundary", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class lbm_fields(ctypes.Structure):
@@ -66,7 +67,7 @@ class lbm_batch(ctypes.Structure):
 
 LBM_BATCH_SERIAL, LBM_BATCH_FLAT, LBM_BATCH_STRIDED, LBM_BATCH_LPT = 0, 1, 2, 3
 
-EXPORTS = ["lbm_workspace_size", "lbm_init", "lbm_step", "lbm_macros", "lbm_populations", "lbm_state_bytes",
+EXPORTS = ["lbm_workspace_size", "lbm_init", "lbm_step", "lbm_set_dirichlet", "lbm_macros", "lbm_populations", "lbm_state_bytes",
            "lbm_state_save", "lbm_state_load", "lbm_set_launch", "lbm_get_launch", "lbm_set_batch", "lbm_get_batch",
            "lbm_adjoint_bytes", "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_init", "lbm_bench_copy", "lbm_free",
            "lbm_last_error", "lbm_abi_version"]
@@ -87,6 +88,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lbm_init.argtypes = [ctypes.POINTER(P), I32, ctypes.POINTER(lbm_params), ctypes.POINTER(lbm_fields), P, SZ, P]
     lib.lbm_step.argtypes = [P, I32, PP, PP, PP, PP]
     lib.lbm_macros.argtypes = [P, I32, P, P, ctypes.POINTER(lbm_stats)]
+    lib.lbm_set_dirichlet.argtypes = [P, I32, P]
     lib.lbm_populations.argtypes = [P, I32, P]
     lib.lbm_state_bytes.argtypes = [P, I32, ctypes.POINTER(SZ)]
     lib.lbm_state_save.argtypes = [P, I32, P]
@@ -142,10 +144,10 @@ def _ptr_array(ts: Optional[Sequence[Optional[torch.Tensor]]]):
 
 
 def make_params(nx, ny, dx, dt, lam, D_const=0.0, mode="f64", aux=LBM_AUX_LOCAL, scale_log2=15,
-                phi_ref=0.0) -> lbm_params:
+                phi_ref=0.0, boundary=LBM_BC_PERIODIC) -> lbm_params:
     store, math = MODES[mode]
     return lbm_params(int(nx), int(ny), float(dx), float(dt), float(lam), float(D_const), store, math, int(aux),
-                      int(scale_log2), float(phi_ref))
+                      int(scale_log2), float(phi_ref), int(boundary), 0)
 
 
 def lbm_abi_version() -> int:
@@ -182,6 +184,10 @@ def lbm_step(ctx, nsteps: int, ux=None, uy=None, S=None, dSdt=None) -> None:
     pu, pv, ps, pd = (_ptr_array(a) for a in (ux, uy, S, dSdt))
     _check(lib().lbm_step(ctx, int(nsteps), pu[0] if pu else None, pv[0] if pv else None, ps[0] if ps else None,
                           pd[0] if pd else None))
+
+
+def lbm_set_dirichlet(ctx, inst: int, phi_b: torch.Tensor) -> None:
+    _check(lib().lbm_set_dirichlet(ctx, int(inst), _dptr(phi_b)))
 
 
 def lbm_macros(ctx, inst: int = 0, phi_out: Optional[torch.Tensor] = None, ref: Optional[torch.Tensor] = None,

@@ -27,6 +27,10 @@ class Solver:
         self._keep = (ux, uy, S, dSdt)  # inputs stay alive until the next call
         L.lbm_step(self.ctx, nsteps, ux, uy, S, dSdt)
 
+    def set_dirichlet(self, phi_b: torch.Tensor, inst: int = 0) -> None:
+        self._keep_bc = phi_b
+        L.lbm_set_dirichlet(self.ctx, inst, phi_b)
+
     def macros(self, inst: int = 0, ref: Optional[torch.Tensor] = None, want_phi: bool = False,
                raise_nonfinite: bool = True):
         p = self.params[inst]

@@ -1,0 +1,171 @@
+"""Dirichlet edges by non-equilibrium extrapolation (the boundary scheme of Sec. 3) on the HIP path,
+through the C ABI, against the FP64 oracle's apply_nee + step on the same seeded inputs."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from paper_2312_10316_amd import Solver, lbm
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def nee_case(nx, ny, seed):
+    """A pulse in a linear shear-plus-rotation flow on [-1, 1]^2 with variable D, a moving Dirichlet
+    value on the edges and a time-dependent source (all seeded)."""
+    X, Y, dx = W.mesh(nx, ny, -1.0, 1.0)
+    rng = np.random.default_rng(seed)
+    c = 4.0
+    ux = c * (0.2 - 0.3 * Y + 0.1 * X)
+    uy = c * (0.25 * X - 0.1 * Y)
+    phi0 = 0.3 + np.exp(-((X - 0.2) ** 2 + (Y + 0.1) ** 2) / 0.1)
+    D = 2e-3 * (1 + 0.5 * rng.uniform(-1, 1, (ny, nx)))
+    S0 = rng.uniform(-1, 1, (ny, nx))
+
+    def phi_b(t):
+        return 0.3 + 0.1 * np.sin(3.0 * X + 2.0 * Y + 5.0 * t)
+
+    def source(t):
+        return S0 * np.cos(4.0 * t), -4.0 * S0 * np.sin(4.0 * t)
+
+    return dict(dx=dx, dt=dx / c, ux=ux, uy=uy, phi0=phi0, D=D, D_const=2e-3, phi_b=phi_b, source=source)
+
+
+def run_nee_pair(nx, ny, f, steps, mode="f64", rows=None, lam=0.25):
+    p = lbm.make_params(nx, ny, f["dx"], f["dt"], lam, f["D_const"], mode, lbm.LBM_AUX_LOCAL,
+                        boundary=lbm.LBM_BC_NEE)
+    fields = {k: dev(f[k]) for k in ("phi0", "ux", "uy")}
+    if f["D"] is not None:
+        fields["D"] = dev(f["D"])
+    s = Solver([(p, fields)])
+    if rows is not None:
+        s.set_launch(rows)
+    op = O.Problem(nx, ny, f["dx"], f["dt"], lam, f["D_const"], O.AUX_LOCAL, O.BC_NEE)
+    g = O.init(op, f["phi0"], f["ux"], f["uy"])
+    for n in range(steps):
+        t = n * f["dt"]
+        pb = f["phi_b"](t)
+        S, dS = f["source"](t)
+        s.set_dirichlet(dev(pb))
+        s.step(1, S=[dev(S)], dSdt=[dev(dS)])
+        g = O.step(op, O.apply_nee(op, g, f["ux"], f["uy"], pb), f["ux"], f["uy"], f["D"], S, dS)
+    pb = f["phi_b"](steps * f["dt"])
+    s.set_dirichlet(dev(pb))
+    g_gpu = s.populations().cpu().numpy()
+    _, phi = s.macros(want_phi=True)
+    s.close()
+    return g_gpu, O.apply_nee(op, g, f["ux"], f["uy"], pb), phi.cpu().numpy(), pb
+
+
+@pytest.mark.parametrize("shape", [(70, 45), (130, 67), (3, 3), (64, 5)])
+def test_nee_fp64_parity(shape):
+    nx, ny = shape
+    f = nee_case(nx, ny, 7 + nx)
+    g_gpu, g_orc, phi, pb = run_nee_pair(nx, ny, f, 25)
+    assert rel(g_gpu, g_orc) <= TOL64
+    edge = np.zeros((ny, nx), bool)
+    edge[0, :] = edge[-1, :] = edge[:, 0] = edge[:, -1] = True
+    np.testing.assert_allclose(phi[edge], pb[edge], rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("rows", [1, 2, 4])
+def test_nee_launch_shape_does_not_change_results(rows):
+    f = nee_case(97, 70, 3)
+    a, _, _, _ = run_nee_pair(97, 70, f, 12, rows=1)
+    b, _, _, _ = run_nee_pair(97, 70, f, 12, rows=rows)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("mode,bound", [("f64s_f32m", 2e-5), ("f32", 2e-5), ("f16s", 1e-2)])
+def test_nee_reduced_precision(mode, bound):
+    f = nee_case(70, 45, 11)
+    g_gpu, g_orc, _, _ = run_nee_pair(70, 45, f, 40, mode=mode)
+    err = rel(g_gpu, g_orc)
+    print(f"{mode}: normalised max error vs FP64 oracle {err:.3e}")
+    assert err <= bound
+
+
+def test_nee_table2_on_the_dirichlet_grid():
+    """The Sec. 3 benchmark on the paper's (N+1)^2 grid, N = 40, kappa = 0.05: the closed form on
+    the edges every step; E_r is compared with Table 2 as printed (3.679e-3)."""
+    N, kappa = 40, 0.05
+    x1 = W.x1_problem(N, kappa, dirichlet=True)
+    n = x1["nx"]
+    f = dict(dx=x1["dx"], dt=x1["dt"], ux=x1["ux"], uy=x1["uy"], phi0=x1["phi0"], D=None, D_const=kappa,
+             phi_b=x1["exact"], source=x1["source"])
+    g_gpu, g_orc, phi, _ = run_nee_pair(n, n, f, x1["steps"], lam=x1["lam"])
+    assert rel(g_gpu, g_orc) <= TOL64
+    er = O.rms_error(phi, x1["exact"](x1["steps"] * x1["dt"]))
+    assert abs(er / 3.679e-03 - 1) < 1e-3
+
+
+def test_nee_multi_step_replay_matches_single_steps():
+    """With a fixed Dirichlet value, nsteps in one call (graph replay) equals nsteps single calls."""
+    f = nee_case(80, 66, 5)
+    p = lbm.make_params(80, 66, f["dx"], f["dt"], 0.25, f["D_const"], "f64", lbm.LBM_AUX_LOCAL,
+                        boundary=lbm.LBM_BC_NEE)
+    out = []
+    for chunks in ([70], [1] * 70):
+        s = Solver([(p, {k: dev(f[k]) for k in ("phi0", "ux", "uy", "D")})])
+        s.set_dirichlet(dev(f["phi_b"](0.0)))
+        for c in chunks:
+            s.step(c)
+        out.append(s.populations().cpu().numpy())
+        s.close()
+    assert np.array_equal(out[0], out[1])
+
+
+def test_nee_and_periodic_instances_share_a_context():
+    f = nee_case(70, 45, 9)
+    fields = {k: dev(f[k]) for k in ("phi0", "ux", "uy", "D")}
+    pn = lbm.make_params(70, 45, f["dx"], f["dt"], 0.25, f["D_const"], "f64", lbm.LBM_AUX_LOCAL,
+                         boundary=lbm.LBM_BC_NEE)
+    pp = lbm.make_params(70, 45, f["dx"], f["dt"], 0.25, f["D_const"], "f64", lbm.LBM_AUX_LOCAL)
+    pb = dev(f["phi_b"](0.0))
+    both = Solver([(pn, fields), (pp, fields)])
+    both.set_dirichlet(pb, inst=0)
+    both.step(9)
+    got = [both.populations(i).cpu().numpy() for i in range(2)]
+    both.close()
+    for k, p in enumerate((pn, pp)):
+        s = Solver([(p, fields)])
+        if k == 0:
+            s.set_dirichlet(pb)
+        s.step(9)
+        assert np.array_equal(s.populations().cpu().numpy(), got[k])
+        s.close()
+
+
+def test_nee_errors():
+    f = nee_case(16, 16, 1)
+    fields = {k: dev(f[k]) for k in ("phi0", "ux", "uy")}
+    bad = lbm.make_params(16, 16, f["dx"], f["dt"], 0.25, 1e-3, "f64", lbm.LBM_AUX_LOCAL, boundary=2)
+    with pytest.raises(lbm.LbmError) as ei:
+        Solver([(bad, fields)])
+    assert ei.value.status == lbm.LBM_E_ARG
+    flux = lbm.make_params(16, 16, f["dx"], f["dt"], 0.25, 1e-3, "f64", lbm.LBM_AUX_FLUX, boundary=lbm.LBM_BC_NEE)
+    with pytest.raises(lbm.LbmError) as ei:
+        Solver([(flux, fields)])
+    assert ei.value.status == lbm.LBM_E_UNSUPPORTED
+    per = Solver([(lbm.make_params(16, 16, f["dx"], f["dt"], 0.25, 1e-3, "f64", lbm.LBM_AUX_LOCAL), fields)])
+    with pytest.raises(lbm.LbmError) as ei:
+        per.set_dirichlet(dev(np.ones((16, 16))))
+    assert ei.value.status == lbm.LBM_E_STATE
+    per.close()
+    nee = Solver([(lbm.make_params(16, 16, f["dx"], f["dt"], 0.25, 1e-3, "f64", lbm.LBM_AUX_LOCAL,
+                                   boundary=lbm.LBM_BC_NEE), fields)])
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.lbm_adjoint_bytes(nee.ctx)
+    assert ei.value.status == lbm.LBM_E_UNSUPPORTED
+    nee.close()

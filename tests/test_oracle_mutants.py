@@ -28,11 +28,16 @@ MUTANTS = [
     ("tau2 from Lambda", "*tau2 = 0.5 + lambda / (*tau1 - 0.5);", "*tau2 = 0.5 + lambda * (*tau1 - 0.5);"),
     ("beta", "real beta = 1.0 - 1.0 / (2.0 * tau1);", "real beta = 1.0 - 1.0 / tau1;"),
     ("aux sign", "real G = W[i] * eA / cs2 * beta;", "real G = -W[i] * eA / cs2 * beta;"),
-    ("aux transposed gradient", "u[a][nb[b][1]] - u[a][nb[b][0]]", "u[b][nb[a][1]] - u[b][nb[a][0]]"),
+    ("aux transposed gradient", "u[a][hi[b]] - u[a][lo[b]]", "u[b][hi[a]] - u[b][lo[a]]"),
     ("aux without phi", "A[a] = phi * s;", "A[a] = s;"),
-    ("aux difference spacing",
-     "real dbua = (u[a][nb[b][1]] - u[a][nb[b][0]]) / (2.0 * dx);",
-     "real dbua = (u[a][nb[b][1]] - u[a][nb[b][0]]) / dx;"),
+    ("aux difference spacing", "double h[2] = {2.0 * dx, 2.0 * dx};", "double h[2] = {dx, dx};"),
+    ("one-sided edge spacing", "if (x == 0) { lo[0] = n; h[0] = dx; }", "if (x == 0) { lo[0] = n; h[0] = 2.0 * dx; }"),
+    ("one-sided edge side", "else if (y == ny - 1) { hi[1] = n; h[1] = dx; }",
+     "else if (y == ny - 1) { lo[1] = n; h[1] = dx; }"),
+    ("NEE sign", "geq_b[i] + (g[i * N + f] - geq_f[i])", "geq_b[i] - (g[i * N + f] - geq_f[i])"),
+    ("NEE neighbour row", "yf = y + (y == 0) - (y == ny - 1);", "yf = y + (y == 0);"),
+    ("NEE equilibrium velocity", "ORC(equilibrium)(phi_b[b], ux[b], uy[b], c, geq_b);",
+     "ORC(equilibrium)(phi_b[b], ux[f], uy[f], c, geq_b);"),
     ("aux neighbour", "nb[1][0] = (size_t)wrap(y - 1, ny) * nx + x;", "nb[1][0] = (size_t)wrap(y + 1, ny) * nx + x;"),
     ("aux without dt", "real P = C[i] + dt * G +", "real P = C[i] + G +"),
     ("flux-form sign", "s += dflux - un[a] * dmass;", "s += dflux + un[a] * dmass;"),

@@ -134,11 +134,13 @@ def test_relaxation_pair():
 
 # ---- one step seen through its moments (Sec. 2.2, Eq. (14) with Eqs. (3), (16)) ----------------
 
-@pytest.mark.parametrize("aux", [O.AUX_LOCAL, O.AUX_NONE])
-def test_step_moments_with_source_and_aux(aux):
+@pytest.mark.parametrize("aux,boundary", [(O.AUX_LOCAL, O.BC_PERIODIC), (O.AUX_NONE, O.BC_PERIODIC),
+                                          (O.AUX_LOCAL, O.BC_NEE)])
+def test_step_moments_with_source_and_aux(aux, boundary):
     """Un-stream one oracle step and check all nine moments of P_i at every node away from the
-    periodic seam.  With the solid-body rotation u = (-U0 y, U0 x) the central difference is exact,
-    so u_b d_b u_a is the closed form (-U0^2 x, -U0^2 y) (centripetal)."""
+    periodic seam (periodic) or at every node including the edges (Dirichlet edges, where the
+    derivative across the edge is one-sided).  With the solid-body rotation u = (-U0 y, U0 x) both
+    differences are exact, so u_b d_b u_a is the closed form (-U0^2 x, -U0^2 y) (centripetal)."""
     n = 12
     U0 = 1.3
     X, Y, dx = W.mesh(n, n, -1.0, 1.0)
@@ -152,15 +154,16 @@ def test_step_moments_with_source_and_aux(aux):
     g = rng.uniform(0.0, 0.2, (9, n, n))
     S = rng.uniform(-1, 1, (n, n))
     dS = rng.uniform(-1, 1, (n, n))
-    p = O.Problem(n, n, dx, dt, lam, 0.0, aux)
+    p = O.Problem(n, n, dx, dt, lam, 0.0, aux, boundary)
     out = O.step(p, g, ux, uy, D, S, dS)
     ex, ey, _ = _E(1.0)
     P = np.empty_like(out)
     for i in range(9):  # P_i(x) = g_i^{n+1}(x + e_i dt)
         P[i] = np.roll(out[i], shift=(-int(ey[i]), -int(ex[i])), axis=(0, 1))
     Ec = _E(c)
-    for k in range(1, n - 1):
-        for jx in range(1, n - 1):
+    nodes = range(n) if boundary == O.BC_NEE else range(1, n - 1)
+    for k in nodes:
+        for jx in nodes:
             gl = g[:, k, jx]
             phi = gl.sum()
             j = np.array([(Ec[0] * gl).sum(), (Ec[1] * gl).sum()])
@@ -306,6 +309,53 @@ def test_rotating_pulse_closed_form_second_order():
     assert all(1.7 < o < 2.2 for o in orders), (errs, orders)
 
 
+# ---- Dirichlet edges by non-equilibrium extrapolation (the boundary scheme of Sec. 3) ----------
+
+def test_nee_edge_moments():
+    """apply_nee rebuilds each edge node from its inward neighbour x_f (diagonal at a corner): the
+    new node carries phi = phi_b and j = phi_b u_b + (j_f - phi_f u_f), because g_eq carries the
+    moments phi and phi u; interior nodes are untouched.  Checked with x_f found independently."""
+    nx, ny = 7, 6
+    X, Y, dx = W.mesh(nx, ny, -1.0, 1.0)
+    dt = dx / 3.0
+    c = dx / dt
+    rng = np.random.default_rng(17)
+    g = rng.uniform(0.0, 0.2, (9, ny, nx))
+    ux = c * rng.uniform(-0.1, 0.1, (ny, nx))
+    uy = c * rng.uniform(-0.1, 0.1, (ny, nx))
+    phi_b = rng.uniform(0.5, 1.5, (ny, nx))
+    p = O.Problem(nx, ny, dx, dt, 0.25, 1e-3, O.AUX_LOCAL, O.BC_NEE)
+    out = O.apply_nee(p, g, ux, uy, phi_b)
+    Ec = _E(c)
+    for y in range(ny):
+        for x in range(nx):
+            if 0 < x < nx - 1 and 0 < y < ny - 1:
+                assert np.array_equal(out[:, y, x], g[:, y, x])
+                continue
+            xf = 1 if x == 0 else (nx - 2 if x == nx - 1 else x)
+            yf = 1 if y == 0 else (ny - 2 if y == ny - 1 else y)
+            gf = g[:, yf, xf]
+            phif = gf.sum()
+            jf = np.array([(Ec[0] * gf).sum(), (Ec[1] * gf).sum()])
+            got = out[:, y, x]
+            assert abs(got.sum() - phi_b[y, x]) < 1e-14
+            want_j = phi_b[y, x] * np.array([ux[y, x], uy[y, x]]) + jf - phif * np.array([ux[yf, xf], uy[yf, xf]])
+            np.testing.assert_allclose([(Ec[0] * got).sum(), (Ec[1] * got).sum()], want_j, rtol=0, atol=1e-13 * c)
+
+
+def test_nee_equilibrium_is_a_fixed_point():
+    """A state at equilibrium everywhere, with phi_b equal to its own phi, is left unchanged."""
+    n = 6
+    X, Y, dx = W.mesh(n, n, -1.0, 1.0)
+    dt = dx / 4.0
+    rng = np.random.default_rng(19)
+    phi = rng.uniform(0.5, 1.5, (n, n))
+    ux, uy = -2.0 * Y, 1.5 * X
+    p = O.Problem(n, n, dx, dt, 0.25, 1e-3, O.AUX_LOCAL, O.BC_NEE)
+    g = O.init(p, phi, ux, uy)
+    np.testing.assert_allclose(O.apply_nee(p, g, ux, uy, phi), g, rtol=0, atol=1e-14)
+
+
 # ---- P9 / P14: the paper's printed Table 2 ----------------------------------------------------
 
 def _x1_error(N, kappa, aux):
@@ -335,6 +385,33 @@ def test_table2_present_column(kappa):
     for k in range(1, 5):
         order = math.log(errs[k - 1] / errs[k]) / math.log(t["N"][k] / t["N"][k - 1])
         assert abs(order - t["order"][kappa][k]) < 0.01, (k, order)
+
+
+def _x1_error_dirichlet(N, kappa):
+    """The benchmark on the paper's own grid: N + 1 nodes per axis, the closed form imposed on the
+    four edges by non-equilibrium extrapolation before every step and before the final read-out."""
+    f = W.x1_problem(N, kappa, dirichlet=True)
+    n = f["nx"]
+    p = O.Problem(n, n, f["dx"], f["dt"], f["lam"], kappa, O.AUX_LOCAL, O.BC_NEE)
+    g = O.init(p, f["phi0"], f["ux"], f["uy"])
+    for s in range(f["steps"]):
+        t = s * f["dt"]
+        g = O.apply_nee(p, g, f["ux"], f["uy"], f["exact"](t))
+        S, dS = f["source"](t)
+        g = O.step(p, g, f["ux"], f["uy"], None, S, dS)
+    T = f["steps"] * f["dt"]
+    g = O.apply_nee(p, g, f["ux"], f["uy"], f["exact"](T))
+    return O.rms_error(O.phi(p, g), f["exact"](T))
+
+
+@pytest.mark.parametrize("kappa", ["0.005", "0.01", "0.05"])
+def test_table2_on_the_dirichlet_grid(kappa):
+    """On the (N+1)^2 grid with Dirichlet edges the oracle reproduces the 'Present' column of
+    Table 2 directly (no node-count factor) to its printed digits."""
+    t = _table2()
+    for N, want in zip(t["N"], t["E_r"][kappa]):
+        e = _x1_error_dirichlet(N, float(kappa))
+        assert abs(e / want - 1) < 1e-3, (N, e, want)
 
 
 def test_table2_typo_reading():

@@ -123,13 +123,20 @@ def refinement(N: int, scaling: str = "acoustic", t_end: float = 0.3125, N0: int
 
 # ---- the benchmark of Sec. 3 on a periodic lattice ------------------------------------------
 
-def x1_problem(N: int, kappa: float, lam: float = 1.0 / 12.0, t_end: float = 1.0):
-    """Rotating-flow pulse held stationary by a source (Sec. 3), periodic proxy on [-2pi, 2pi]^2.
+def x1_problem(N: int, kappa: float, lam: float = 1.0 / 12.0, t_end: float = 1.0, dirichlet: bool = False):
+    """Rotating-flow pulse held stationary by a source (Sec. 3) on [-2pi, 2pi]^2 with dx = 4 pi / N.
 
+    Periodic proxy (N nodes per axis) or, with ``dirichlet``, the N + 1 nodes x_j = -2 pi + j dx,
+    j = 0..N, whose first and last rows and columns carry the closed form as Dirichlet values.
     Diffusive scaling dx^2/dt = 0.16 pi^2 (Sec. 3.2).  Returns a dict with fields, a function
     ``source(t) -> (S, dSdt)`` and ``exact(t)``."""
     L = 4.0 * PI
-    X, Y, dx = mesh(N, N, -2.0 * PI, 2.0 * PI)
+    if dirichlet:
+        x = -2.0 * PI + (4.0 * PI / N) * np.arange(N + 1)
+        Y, X = np.meshgrid(x, x, indexing="ij")
+        dx = 4.0 * PI / N
+    else:
+        X, Y, dx = mesh(N, N, -2.0 * PI, 2.0 * PI)
     dt = dx * dx / (0.16 * PI * PI)
     steps = int(round(t_end / dt))
     ux = -Y
@@ -144,8 +151,9 @@ def x1_problem(N: int, kappa: float, lam: float = 1.0 / 12.0, t_end: float = 1.0
     def exact(t: float):
         return np.exp(-(q + 2.0 * kappa * t))
 
+    n = X.shape[0]
     return dict(X=X, Y=Y, dx=dx, dt=dt, steps=steps, lam=lam, D_const=kappa, ux=ux, uy=uy,
-                phi0=np.exp(-q), source=source, exact=exact, nx=N, ny=N, L=L)
+                phi0=np.exp(-q), source=source, exact=exact, nx=n, ny=n, L=L)
 
 
 # ---- batched instances -----------------------------------------------------------------------
