@@ -37,7 +37,7 @@ def bytes_per_lup(mode: str, variable_D: bool) -> int:
 
 def kernel_hash() -> str:
     h = hashlib.sha256()
-    for name in ("lbm_kernels.hip", "lbm_device.h", "lbm_internal.h"):
+    for name in ("lbm_kernels.hip", "lbm_device.h", "lbm_internal.h", "lbm_api.hip"):
         with open(os.path.join(ROOT, "paper_2312_10316_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -229,6 +229,55 @@ def run_flux(torch, W, lbm, Solver, n=2048, steps=3000):
     return out
 
 
+def run_dirichlet(torch, W, lbm, Solver, sizes=(100, 200, 400, 800), kappa=0.05, n_tp=2048, tp_steps=2000):
+    """The Sec. 3 benchmark on its own (N+1)^2 grid with Dirichlet edges by non-equilibrium
+    extrapolation: E_r at t = 1 (Table 2 extended past N = 100) per storage mode, with S, dS/dt and
+    the Dirichlet values of the closed form supplied every step; and the throughput of the
+    Dirichlet-edge step kernel at (n_tp+1)^2 (graph-replayed, S and phi_b held fixed)."""
+    import numpy as np
+    out = {"kappa": kappa, "N": list(sizes), "E_r": {}, "order": {}}
+    for mode in ("f64", "f32", "f16s"):
+        errs = []
+        for N in sizes:
+            x1 = W.x1_problem(N, kappa, dirichlet=True)
+            n = x1["nx"]
+            dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+            p = lbm.make_params(n, n, x1["dx"], x1["dt"], x1["lam"], kappa, mode, lbm.LBM_AUX_LOCAL,
+                                boundary=lbm.LBM_BC_NEE)
+            s = Solver([(p, {k: dv(x1[k]) for k in ("phi0", "ux", "uy")})])
+            S0 = dv(x1["source"](0.0)[0])
+            q_exact0 = dv(x1["exact"](0.0))
+            for k in range(x1["steps"]):  # S(t), phi(t) decay as exp(-2 kappa t) from their t = 0 forms
+                a = math.exp(-2.0 * kappa * k * x1["dt"])
+                s.set_dirichlet(q_exact0 * a)
+                S = S0 * a
+                s.step(1, S=[S], dSdt=[S * (-2.0 * kappa)])
+            T = x1["steps"] * x1["dt"]
+            ref = q_exact0 * math.exp(-2.0 * kappa * T)
+            s.set_dirichlet(ref)
+            errs.append(s.macros(ref=ref)["rms_err"])
+            s.close()
+        out["E_r"][mode] = errs
+        out["order"][mode] = [None] + [math.log(errs[k - 1] / errs[k]) / math.log(sizes[k] / sizes[k - 1])
+                                       for k in range(1, len(sizes))]
+    x1 = W.x1_problem(n_tp, kappa, dirichlet=True)
+    n = x1["nx"]
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    S, dS = (dv(a) for a in x1["source"](0.0))
+    tp = {}
+    for mode in ("f32", "f64"):
+        for bc in (lbm.LBM_BC_NEE, lbm.LBM_BC_PERIODIC):
+            p = lbm.make_params(n, n, x1["dx"], x1["dt"], x1["lam"], kappa, mode, lbm.LBM_AUX_LOCAL, boundary=bc)
+            s = Solver([(p, {k: dv(x1[k]) for k in ("phi0", "ux", "uy")})])
+            s.step(64, S=[S], dSdt=[dS])
+            ms = _timed_steps(torch, s, tp_steps)
+            s.close()
+            tp[f"{mode}_{'nee' if bc == lbm.LBM_BC_NEE else 'periodic'}"] = {
+                "mlups": n * n / (ms * 1e-3) / 1e6, "ms_per_step": ms}
+    out["throughput"] = {"nodes": f"{n}^2", "with_source": True, **tp}
+    return out
+
+
 def run_adjoint(torch, W, lbm, Solver):
     """512^2 pulse, 400 steps, FP32 forward with sqrt(T) checkpoints; D on a 32 x 32 bicubic control
     grid; loss = 1/2 sum (phi_T - phi_target)^2 against the run with D = 1e-3."""
@@ -312,9 +361,10 @@ def _find(dirpath, suffix):
 
 
 def _kernel_label(name: str):
-    """'step_kernel<2, 0, false, false>' -> ('step', 'f32', aux 0, has_k, has_s); copy/other -> None."""
+    """'step_kernel<2, 0, false, false, false>' (mode, aux, has_k, has_s, Dirichlet edges) ->
+    ('step', 'f32', aux 0, has_k, has_s) for the periodic kernels; copy -> ('copy',); other -> None."""
     import re
-    m = re.search(r"step_kernel<(\d), (\d), (true|false), (true|false)>", name)
+    m = re.search(r"step_kernel<(\d), (\d), (true|false), (true|false), false>", name)
     if m:
         return ("step", KERNEL_MODES[m.group(1)], int(m.group(2)), m.group(3) == "true", m.group(4) == "true")
     if "copy_kernel" in name:
@@ -408,7 +458,7 @@ def main():
         pmc = {k: v for k, v in pmc.items() if os.path.isdir(v)}
         summarize_profiles(os.path.join(d, "trace"), pmc, os.path.join(ROOT, "profiles"),
                            "rocprofv3 --kernel-trace --stats --output-format csv -d RUNDIR/trace -o trace -- "
-                           "python3 bench.py",
+                           "python3 bench.py --no-cpu --no-batched --no-studies",
                            [f"rocprofv3 --pmc {c} --output-format csv -d RUNDIR/pmc_{c.lower()}_{n} -o pmc -- "
                             f"python3 bench.py --n {n} --steps 12 --warmup 0 --modes f32,f64,f16s --no-cpu --no-batched --no-studies"
                             for (c, n) in sorted(pmc)])
@@ -487,7 +537,8 @@ def main():
               file=sys.stderr, flush=True)
     if not args.no_studies:
         for name, fn in (("precision_8192_variable_D", run_precision_8192), ("refinement", run_refinement),
-                         ("flux_aux_2048", run_flux), ("adjoint_512", run_adjoint)):
+                         ("flux_aux_2048", run_flux), ("dirichlet_sec3", run_dirichlet),
+                         ("adjoint_512", run_adjoint)):
             t0 = time.perf_counter()
             try:
                 out[name] = fn(torch, W, lbm, Solver)

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 2
+#define LBM_ABI_VERSION 3
 
 enum lbm_status {
     LBM_OK = 0,
@@ -151,11 +151,15 @@ int lbm_populations(lbm_ctx *ctx, int32_t inst, double *g_out);
  * lbm_state_bytes gives its size; save copies it to dst (device), load restores it from src
  * (device) and sets the step counter.  Asynchronous.  A run resumed from a checkpoint is bitwise
  * identical to the uninterrupted run.
- * Image layout: [ny][9][pitch] elements of the storage type (FP64, FP32 or FP16 code), pitch = nx
- * rounded up to a multiple of 64, padding zero.  Element (y, i, x) holds the post-collision value
+ * Image layout: [ny][9][pitch] elements of the storage type (FP64, FP32 or FP16 code), pitch as
+ * returned by lbm_pitch, padding zero.  Element (y, i, x) holds the post-collision value
  * P_i of node (x, y) from the previous step, so that g_i(x, y) = element (y - e_iy, i, x - e_ix)
  * (periodic); after lbm_init it holds g_eq_i of node (x + e_ix, y + e_iy). */
 int lbm_state_bytes(lbm_ctx *ctx, int32_t inst, size_t *bytes);
+/* Row pitch (elements) of an instance's layouts (state image, adjoint arrays): nx rounded up to a
+ * multiple of 64, plus 64 when that many storage elements span a multiple of 4 KiB.  Host only (no
+ * device work, no context).  LBM_E_ARG for invalid parameters. */
+int lbm_pitch(const lbm_params *p, int64_t *pitch);
 int lbm_state_save(lbm_ctx *ctx, int32_t inst, void *dst);
 int lbm_state_load(lbm_ctx *ctx, int32_t inst, const void *src, int64_t step);
 

@@ -70,12 +70,14 @@ LBM_BATCH_SERIAL, LBM_BATCH_FLAT, LBM_BATCH_STRIDED, LBM_BATCH_LPT = 0, 1, 2, 3
 EXPORTS = ["lbm_workspace_size", "lbm_init", "lbm_step", "lbm_set_dirichlet", "lbm_macros", "lbm_populations", "lbm_state_bytes",
            "lbm_state_save", "lbm_state_load", "lbm_set_launch", "lbm_get_launch", "lbm_set_batch", "lbm_get_batch",
            "lbm_adjoint_bytes", "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_init", "lbm_bench_copy", "lbm_free",
-           "lbm_last_error", "lbm_abi_version"]
+           "lbm_pitch", "lbm_last_error", "lbm_abi_version"]
 
 
-def pitch_of(nx: int) -> int:
-    """Row pitch (elements) of the library's layouts: nx rounded up to a multiple of 64."""
-    return (int(nx) + 63) // 64 * 64
+def pitch_of(p: "lbm_params") -> int:
+    """Row pitch (elements) of the library's layouts for instance parameters p (lbm_pitch)."""
+    out = ctypes.c_int64()
+    _check(lib().lbm_pitch(ctypes.byref(p), ctypes.byref(out)))
+    return out.value
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -91,6 +93,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lbm_set_dirichlet.argtypes = [P, I32, P]
     lib.lbm_populations.argtypes = [P, I32, P]
     lib.lbm_state_bytes.argtypes = [P, I32, ctypes.POINTER(SZ)]
+    lib.lbm_pitch.argtypes = [ctypes.POINTER(lbm_params), ctypes.POINTER(I64)]
     lib.lbm_state_save.argtypes = [P, I32, P]
     lib.lbm_state_load.argtypes = [P, I32, P, I64]
     lib.lbm_set_launch.argtypes = [P, I32, ctypes.POINTER(lbm_launch)]

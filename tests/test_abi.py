@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True, check=True).stdout
     exported = set(re.findall(r" T (lbm_\w+)$", out, flags=re.M))
     assert set(declared_functions()) <= exported
-    assert L.lbm_abi_version() == 2
+    assert L.lbm_abi_version() == 3
 
 
 def test_struct_layout_matches_header(tmp_path):
@@ -60,6 +60,20 @@ def test_workspace_size_scales_with_storage():
     b16 = L.lbm_workspace_size([_p(nx=1024, ny=1024, mode="f16s")])
     assert b64 > b32 > b16 > 2 * 9 * 1024 * 1024 * 2
     assert L.lbm_workspace_size([_p(), _p(nx=100, ny=37)]) > L.lbm_workspace_size([_p()])
+
+
+@pytest.mark.parametrize("mode,esize", [("f64", 8), ("f32", 4), ("f16s", 2)])
+def test_pitch_rule(mode, esize):
+    """Host-only layout query: nx rounded up to 64 elements, plus 64 when the rounded row segment
+    would span a multiple of 4 KiB (the population rows of every width avoid 4 KiB strides)."""
+    for nx in (3, 63, 64, 65, 100, 512, 1000, 1024, 2048, 2049, 3072, 4096, 8192):
+        pitch = L.pitch_of(_p(nx=nx, ny=5, mode=mode))
+        assert pitch >= nx and pitch % 64 == 0 and pitch - nx < 128
+        assert (pitch * esize) % 4096 != 0
+        base = (nx + 63) // 64 * 64
+        assert pitch == base or (base * esize) % 4096 == 0
+    with pytest.raises(L.LbmError):
+        L.pitch_of(_p(nx=2))
 
 
 @pytest.mark.parametrize("kw,msg", [

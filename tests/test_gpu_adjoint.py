@@ -51,7 +51,7 @@ def test_adjoint_step_is_the_transpose(aux):
     s.step(3)
     state = s.state_save()
     lam_in = rng.uniform(-1, 1, (9, ny, nx))
-    pitch = lbm.pitch_of(nx)
+    pitch = lbm.pitch_of(p)
     li = lam_to_lib(lam_in, pitch, np.float64)
     lo = torch.empty_like(li)
     grad = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")

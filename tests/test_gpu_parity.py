@@ -276,7 +276,7 @@ def test_f16s_decode_exhaustive():
     z = np.zeros((n, n))
     s = Solver([(p, {"phi0": dev(np.full((n, n), phi_ref)), "ux": dev(z), "uy": dev(z)})])
     codes = np.arange(65536, dtype=np.uint16).reshape(n, n)
-    pitch = lbm.pitch_of(n)
+    pitch = lbm.pitch_of(p)
     raw = np.zeros(lbm.lbm_state_bytes(s.ctx) // 2, np.uint16)
     img = raw[:n * 9 * pitch].reshape(n, 9, pitch)  # image layout [ny][9][pitch]
     for i in range(9):
@@ -308,7 +308,7 @@ def test_f16s_encode_matches_numpy_rne(phi_ref):
     s = Solver([(p, {"phi0": dev(phi0), "ux": dev(z), "uy": dev(z)})])
     raw = s.state_save().cpu().numpy().view(np.uint16)
     s.close()
-    pitch = lbm.pitch_of(n)
+    pitch = lbm.pitch_of(p)
     img = raw[:n * 9 * pitch].reshape(n, 9, pitch)
     ex, ey, w = O.lattice()
     p32 = phi0.astype(np.float32)
