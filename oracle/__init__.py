@@ -27,7 +27,7 @@ _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 AUX_LOCAL, AUX_FLUX, AUX_NONE = 0, 1, 2
-BC_PERIODIC, BC_NEE = 0, 1
+BC_PERIODIC, BC_NEE, BC_WALLS = 0, 1, 2
 
 
 def build(force: bool = False) -> str:
@@ -51,7 +51,7 @@ def build(force: bool = False) -> str:
 class _Problem(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("dx", ctypes.c_double),
                 ("dt", ctypes.c_double), ("lambda_", ctypes.c_double), ("D_const", ctypes.c_double),
-                ("aux", ctypes.c_int), ("boundary", ctypes.c_int)]
+                ("aux", ctypes.c_int), ("boundary", ctypes.c_int), ("tau3", ctypes.c_double)]
 
 
 _lib = None
@@ -67,12 +67,13 @@ def _load():
         lib.orc_lattice.argtypes = [P, P, P]
         lib.orc_equilibrium.argtypes = [dbl, dbl, dbl, dbl, P]
         lib.orc_collide.argtypes = [P, dbl, dbl, dbl, dbl, dbl, P]
+        lib.orc_collide_mrt.argtypes = [P, dbl, dbl, dbl, dbl, dbl, dbl, P]
         lib.orc_relaxation.argtypes = [dbl, dbl, dbl, dbl, P, P]
         for pre in ("orc_", "orc_z_"):
             getattr(lib, pre + "init").argtypes = [P, P, P, P, P]
             getattr(lib, pre + "phi").argtypes = [P, P, P]
-            getattr(lib, pre + "step").argtypes = [P, P, P, P, P, P, P, P]
-            getattr(lib, pre + "run").argtypes = [P, P, i32, P, P, P, P, P, P]
+            getattr(lib, pre + "step").argtypes = [P, P, P, P, P, P, P, P, P]
+            getattr(lib, pre + "run").argtypes = [P, P, i32, P, P, P, P, P, P, P]
             getattr(lib, pre + "apply_nee").argtypes = [P, P, P, P, P]
         del zc
         _lib = lib
@@ -89,10 +90,13 @@ class Problem:
     lam: float
     D_const: float = 0.0
     aux: int = AUX_LOCAL
-    boundary: int = BC_PERIODIC   # BC_NEE: one-sided derivatives of u across the edges (apply_nee per step)
+    boundary: int = BC_PERIODIC   # BC_NEE: one-sided derivatives of u across the edges (apply_nee per step);
+                                  # BC_WALLS: halfway anti-bounce-back walls below row 0 and above row ny-1
+    tau3: float = 0.0             # MRT-R third-order relaxation time; 0 (or 1): TRT-R
 
     def _c(self) -> _Problem:
-        return _Problem(self.nx, self.ny, self.dx, self.dt, self.lam, self.D_const, self.aux, self.boundary)
+        return _Problem(self.nx, self.ny, self.dx, self.dt, self.lam, self.D_const, self.aux, self.boundary,
+                        self.tau3)
 
     @property
     def c(self) -> float:
@@ -129,6 +133,13 @@ def collide(g, ux: float, uy: float, tau1: float, tau2: float, c: float) -> np.n
     g = np.ascontiguousarray(g, dtype=np.float64)
     out = np.zeros(9)
     _load().orc_collide(_ptr(g), ux, uy, tau1, tau2, c, _ptr(out))
+    return out
+
+
+def collide_mrt(g, ux: float, uy: float, tau1: float, tau2: float, tau3: float, c: float) -> np.ndarray:
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    out = np.zeros(9)
+    _load().orc_collide_mrt(_ptr(g), ux, uy, tau1, tau2, tau3, c, _ptr(out))
     return out
 
 
@@ -171,29 +182,41 @@ def phi(p: Problem, g) -> np.ndarray:
     return out
 
 
-def step(p: Problem, g, ux, uy, D=None, S=None, dSdt=None) -> np.ndarray:
-    """One step of Eq. (14) on a copy of g; returns the new pre-collision populations."""
+def _walls(p: Problem, phi_b, cplx):
+    if p.boundary != BC_WALLS:
+        return None
+    if phi_b is None:
+        raise ValueError("walls need phi_b (rows 0 and ny-1 hold the bottom and top wall values)")
+    return _arr(phi_b, (p.ny, p.nx), cplx)
+
+
+def step(p: Problem, g, ux, uy, D=None, S=None, dSdt=None, phi_b=None) -> np.ndarray:
+    """One step of Eq. (14) on a copy of g; returns the new pre-collision populations.  For walls,
+    phi_b [ny, nx] holds the wall values (rows 0 and ny-1) at the new time level."""
     lib = _load()
-    cplx = np.iscomplexobj(g) or any(np.iscomplexobj(a) for a in (ux, uy, D, S, dSdt) if a is not None)
+    cplx = np.iscomplexobj(g) or any(np.iscomplexobj(a) for a in (ux, uy, D, S, dSdt, phi_b) if a is not None)
     g = np.ascontiguousarray(g, dtype=np.complex128 if cplx else np.float64)
     ux, uy, D, S, dSdt = _fields(p, ux, uy, D, S, dSdt, cplx)
+    pb = _walls(p, phi_b, cplx)
     out = np.empty_like(g)
     pc = p._c()
     (lib.orc_z_step if cplx else lib.orc_step)(ctypes.byref(pc), _ptr(g), _ptr(out), _ptr(ux), _ptr(uy),
-                                               _ptr(D), _ptr(S), _ptr(dSdt))
+                                               _ptr(D), _ptr(S), _ptr(dSdt), _ptr(pb))
     return out
 
 
-def run(p: Problem, g, nsteps: int, ux, uy, D=None, S=None, dSdt=None) -> np.ndarray:
-    """nsteps steps with fixed u, D, S, dS/dt; returns the final populations (input untouched)."""
+def run(p: Problem, g, nsteps: int, ux, uy, D=None, S=None, dSdt=None, phi_b=None) -> np.ndarray:
+    """nsteps steps with fixed u, D, S, dS/dt (and wall values); returns the final populations
+    (input untouched)."""
     lib = _load()
-    cplx = np.iscomplexobj(g) or any(np.iscomplexobj(a) for a in (ux, uy, D, S, dSdt) if a is not None)
+    cplx = np.iscomplexobj(g) or any(np.iscomplexobj(a) for a in (ux, uy, D, S, dSdt, phi_b) if a is not None)
     g = np.array(g, dtype=np.complex128 if cplx else np.float64, copy=True, order="C")
     ux, uy, D, S, dSdt = _fields(p, ux, uy, D, S, dSdt, cplx)
+    pb = _walls(p, phi_b, cplx)
     work = np.empty_like(g)
     pc = p._c()
     (lib.orc_z_run if cplx else lib.orc_run)(ctypes.byref(pc), _ptr(g), int(nsteps), _ptr(ux), _ptr(uy),
-                                             _ptr(D), _ptr(S), _ptr(dSdt), _ptr(work))
+                                             _ptr(D), _ptr(S), _ptr(dSdt), _ptr(pb), _ptr(work))
     return g
 
 

@@ -29,7 +29,11 @@
  *     phi = sum_i g_i at the neighbours at the same time level.
  *   - the time derivative of F_i uses the supplied dS/dt and a time-independent u within the step
  *     (Sec. 2.3 assumption).
- *   - the lattice is periodic in x and y.
+ *   - the lattice is periodic in x and y, unless Dirichlet edges (non-equilibrium extrapolation)
+ *     or walls (halfway anti-bounce-back) are selected; across such a boundary the difference of u
+ *     in the auxiliary term is one-sided.
+ *   - the anti-bounce-back wall value enters through the even part of the equilibrium at the wall
+ *     value and the velocity of the boundary node, at the time the reflected population arrives.
  */
 #include <stdlib.h>
 #include <string.h>
@@ -60,7 +64,9 @@ typedef struct orc_problem {
                           2: no auxiliary term (ablation) */
     int boundary;      /* 0: periodic; 1: Dirichlet edges (the first and last rows and columns are
                           rebuilt by apply_nee before each step; across an edge the derivatives of
-                          u in the auxiliary term are one-sided instead of wrapped) */
+                          u in the auxiliary term are one-sided instead of wrapped); 2: walls at
+                          y = -dx/2 and y = (ny - 1/2) dx by halfway anti-bounce-back, x periodic */
+    double tau3;       /* MRT-R third-order relaxation time (Sec. 2.2, Eq. (10)); 0 or 1: TRT-R */
 } orc_problem;
 
 #ifndef ORC_COMPLEX
@@ -118,11 +124,14 @@ void ORC(relaxation)(real kappa, double dx, double dt, double lambda, real *tau1
     *tau2 = 0.5 + lambda / (*tau1 - 0.5);
 }
 
-/* TRT-R collision operator, Sec. 2.2, Eq. (12), with the non-equilibrium moments of Eq. (8)
- * (B_a = sum_i H_a (g_i - g_eq_i)) and Eq. (13) (B_ab = sum_i H_ab (g_i - g_eq_i)):
- *   C_i = g_eq_i + (1 - 1/tau1) w_i H_a B_a / cs2 + (1 - 1/tau2) w_i H_ab B_ab / (2 cs2^2).
+/* MRT-R collision operator, Sec. 2.2, Eq. (10), truncated after the third order, with the
+ * non-equilibrium moments B_a = sum_i H_a (g_i - g_eq_i) (Eq. (8)), B_ab (Eq. (13)) and
+ * B_abg = sum_i H_abg (g_i - g_eq_i):
+ *   C_i = g_eq_i + (1 - 1/tau1) w_i H_a B_a / cs2 + (1 - 1/tau2) w_i H_ab B_ab / (2 cs2^2)
+ *               + (1 - 1/tau3) w_i H_abg B_abg / (6 cs2^3).
+ * tau3 = 1 drops the third-order non-equilibrium part: the TRT-R operator of Eq. (12).
  * phi is the zeroth moment sum_i g_i (Sec. 2.2: B_0^neq = 0). */
-void ORC(collide)(const real *g, real ux, real uy, real tau1, real tau2, double c, real *out)
+void ORC(collide_mrt)(const real *g, real ux, real uy, real tau1, real tau2, real tau3, double c, real *out)
 {
     double cs2 = c * c / 3.0;
     real phi = 0;
@@ -131,20 +140,44 @@ void ORC(collide)(const real *g, real ux, real uy, real tau1, real tau2, double 
     ORC(equilibrium)(phi, ux, uy, c, geq);
     real B1[2] = {0, 0};
     real B2[2][2] = {{0, 0}, {0, 0}};
+    real B3[2][2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
     for (int i = 0; i < 9; ++i) {
         real gneq = g[i] - geq[i];  /* Eq. (5) */
         for (int a = 0; a < 2; ++a) B1[a] += herm1(i, a, c) * gneq;
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b) B2[a][b] += herm2(i, a, b, c) * gneq;
+        if (tau3 != 1.0)  /* the third-order term vanishes for tau3 = 1 */
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b)
+                    for (int d = 0; d < 2; ++d) B3[a][b][d] += herm3(i, a, b, d, c) * gneq;
     }
     for (int i = 0; i < 9; ++i) {
-        real r1 = 0, r2 = 0;
+        real r1 = 0, r2 = 0, r3 = 0;
         for (int a = 0; a < 2; ++a) r1 += herm1(i, a, c) * B1[a];
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b) r2 += herm2(i, a, b, c) * B2[a][b];
+        if (tau3 != 1.0)
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b)
+                    for (int d = 0; d < 2; ++d) r3 += herm3(i, a, b, d, c) * B3[a][b][d];
         out[i] = geq[i] + (1.0 - 1.0 / tau1) * W[i] * r1 / cs2
-                        + (1.0 - 1.0 / tau2) * W[i] * r2 / (2.0 * cs2 * cs2);
+                        + (1.0 - 1.0 / tau2) * W[i] * r2 / (2.0 * cs2 * cs2)
+                        + (1.0 - 1.0 / tau3) * W[i] * r3 / (6.0 * cs2 * cs2 * cs2);
     }
+}
+
+/* TRT-R collision operator, Sec. 2.2, Eq. (12): the MRT-R operator with tau3 = 1. */
+void ORC(collide)(const real *g, real ux, real uy, real tau1, real tau2, double c, real *out)
+{
+    ORC(collide_mrt)(g, ux, uy, tau1, tau2, 1.0, c, out);
+}
+
+/* index of the velocity opposite to e_i */
+static int opposite(int i)
+{
+    for (int j = 0; j < 9; ++j)
+        if (EX[j] == -EX[i] && EY[j] == -EY[i]) return j;
+    return -1;
 }
 
 static int wrap(int k, int n) { return ((k % n) + n) % n; }
@@ -174,11 +207,16 @@ void ORC(phi)(const orc_problem *p, const real *g, real *phi)
 
 /* One time step of the TRT-R evolution equation, Sec. 2.2, Eq. (14):
  *   g_i(x + e_i dt, t + dt) = C_i + dt G_i + dt F_i + (dt^2 / 2) d_t F_i
- * with C_i of Eq. (12), F_i of Eq. (3), G_i of Eq. (16) (or the selected reading), evaluated at
- * every node x at time t_n and streamed to x + e_i dt on the periodic lattice.
- * g_in / g_out: [9][ny][nx].  D, S, dSdt may be NULL (constant D_const; no source). */
+ * with C_i of Eq. (12) (Eq. (10) when tau3 is set), F_i of Eq. (3), G_i of Eq. (16) (or the selected
+ * reading), evaluated at every node x at time t_n and streamed to x + e_i dt on the periodic lattice.
+ * With walls (boundary 2) a population that would cross y = -dx/2 or y = (ny - 1/2) dx returns to
+ * its node reversed, by halfway anti-bounce-back for a Dirichlet value phi_w:
+ *   g_opp(i)(x, t + dt) = -P_i(x) + 2 g_eq_i^+(phi_w, u(x)),  g_eq^+ = (g_eq_i + g_eq_opp(i)) / 2,
+ * with phi_w = phi_b[x] of row 0 (bottom wall) or of row ny - 1 (top wall) at time t + dt.
+ * g_in / g_out: [9][ny][nx].  D, S, dSdt may be NULL (constant D_const; no source); phi_b
+ * ([ny][nx]) is read for walls only. */
 void ORC(step)(const orc_problem *p, const real *g_in, real *g_out, const real *ux, const real *uy,
-               const real *D, const real *S, const real *dSdt)
+               const real *D, const real *S, const real *dSdt, const real *phi_b)
 {
     const int nx = p->nx, ny = p->ny;
     const size_t N = (size_t)nx * ny;
@@ -204,7 +242,8 @@ void ORC(step)(const orc_problem *p, const real *g_in, real *g_out, const real *
             real beta = 1.0 - 1.0 / (2.0 * tau1);
 
             real C[9];
-            ORC(collide)(g, ux[n], uy[n], tau1, tau2, c, C);
+            const real tau3 = p->tau3 == 0.0 ? 1.0 : p->tau3;
+            ORC(collide_mrt)(g, ux[n], uy[n], tau1, tau2, tau3, c, C);
 
             /* neighbours along +/- x and +/- y */
             size_t nb[2][2];  /* nb[b][0] = x - e_b, nb[b][1] = x + e_b */
@@ -219,8 +258,14 @@ void ORC(step)(const orc_problem *p, const real *g_in, real *g_out, const real *
             double h[2] = {2.0 * dx, 2.0 * dx};
             if (p->boundary == 1) {
                 if (x == 0) { lo[0] = n; h[0] = dx; } else if (x == nx - 1) { hi[0] = n; h[0] = dx; }
+            }
+            if (p->boundary == 1 || p->boundary == 2) {
                 if (y == 0) { lo[1] = n; h[1] = dx; } else if (y == ny - 1) { hi[1] = n; h[1] = dx; }
             }
+            /* even part of the equilibrium at the wall value, for walls */
+            real geq_w[9];
+            const int wall_row = p->boundary == 2 && (y == 0 || y == ny - 1);
+            if (wall_row) ORC(equilibrium)(phi_b[n], ux[n], uy[n], c, geq_w);
 
             /* A_a multiplies w_i e_ia / cs2 (1 - 1/(2 tau1)) in G_i */
             real A[2] = {0, 0};
@@ -263,7 +308,13 @@ void ORC(step)(const orc_problem *p, const real *g_in, real *g_out, const real *
                 real F = W[i] * src + beta * W[i] * eu / cs2 * src;
                 real dF = W[i] * dsrc + beta * W[i] * eu / cs2 * dsrc;
                 real P = C[i] + dt * G + dt * F + 0.5 * dt * dt * dF;
-                size_t dst = (size_t)wrap(y + EY[i], ny) * nx + wrap(x + EX[i], nx);
+                const int ty = y + EY[i];
+                if (wall_row && (ty < 0 || ty >= ny)) {  /* halfway anti-bounce-back */
+                    const int o = opposite(i);
+                    g_out[o * N + n] = -P + (geq_w[i] + geq_w[o]);
+                    continue;
+                }
+                size_t dst = (size_t)wrap(ty, ny) * nx + wrap(x + EX[i], nx);
                 g_out[i * N + dst] = P;
             }
         }
@@ -300,11 +351,11 @@ void ORC(apply_nee)(const orc_problem *p, real *g, const real *ux, const real *u
 
 /* nsteps repeated steps on g (in place); work holds 9*nx*ny values of scratch. */
 void ORC(run)(const orc_problem *p, real *g, int nsteps, const real *ux, const real *uy,
-              const real *D, const real *S, const real *dSdt, real *work)
+              const real *D, const real *S, const real *dSdt, const real *phi_b, real *work)
 {
     size_t bytes = (size_t)9 * p->nx * p->ny * sizeof(real);
     for (int s = 0; s < nsteps; ++s) {
-        ORC(step)(p, g, work, ux, uy, D, S, dSdt);
+        ORC(step)(p, g, work, ux, uy, D, S, dSdt, phi_b);
         memcpy(g, work, bytes);
     }
 }

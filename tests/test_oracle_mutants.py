@@ -34,6 +34,11 @@ MUTANTS = [
     ("one-sided edge spacing", "if (x == 0) { lo[0] = n; h[0] = dx; }", "if (x == 0) { lo[0] = n; h[0] = 2.0 * dx; }"),
     ("one-sided edge side", "else if (y == ny - 1) { hi[1] = n; h[1] = dx; }",
      "else if (y == ny - 1) { lo[1] = n; h[1] = dx; }"),
+    ("anti-bounce-back sign", "g_out[o * N + n] = -P + (geq_w[i] + geq_w[o]);", "g_out[o * N + n] = P + (geq_w[i] + geq_w[o]);"),
+    ("anti-bounce-back odd part", "-P + (geq_w[i] + geq_w[o])", "-P + 2.0 * geq_w[i]"),
+    ("walls keep the wrapped derivative", "if (p->boundary == 1 || p->boundary == 2) {", "if (p->boundary == 1) {"),
+    ("MRT third-order rate", "(1.0 - 1.0 / tau3) * W[i] * r3", "(1.0 - 1.0 / tau2) * W[i] * r3"),
+    ("MRT third-order factor", "r3 / (6.0 * cs2 * cs2 * cs2)", "r3 / (2.0 * cs2 * cs2 * cs2)"),
     ("NEE sign", "geq_b[i] + (g[i * N + f] - geq_f[i])", "geq_b[i] - (g[i * N + f] - geq_f[i])"),
     ("NEE neighbour row", "yf = y + (y == 0) - (y == ny - 1);", "yf = y + (y == 0);"),
     ("NEE equilibrium velocity", "ORC(equilibrium)(phi_b[b], ux[b], uy[b], c, geq_b);",
@@ -47,7 +52,7 @@ MUTANTS = [
     ("source without beta", "+ beta * W[i] * eu / cs2 * src", "+ W[i] * eu / cs2 * src"),
     ("source derivative half", "0.5 * dt * dt * dF", "dt * dt * dF"),
     ("source derivative operand", "beta * W[i] * eu / cs2 * dsrc;", "beta * W[i] * eu / cs2 * src;"),
-    ("streaming direction", "wrap(y + EY[i], ny) * nx + wrap(x + EX[i], nx)",
+    ("streaming direction", "wrap(ty, ny) * nx + wrap(x + EX[i], nx)",
      "wrap(y - EY[i], ny) * nx + wrap(x - EX[i], nx)"),
 ]
 

@@ -85,11 +85,12 @@ def _moments9(f, ex, ey):
                      (ex * ex * ey * ey * f).sum()])
 
 
-def _expected_post_moments(phi, j, Pi, ux, uy, om1, om2, cs2, s_eff=0.0, V=(0.0, 0.0)):
+def _expected_post_moments(phi, j, Pi, ux, uy, om1, om2, cs2, s_eff=0.0, V=(0.0, 0.0), om3=0.0, B3=(0.0, 0.0)):
     """All nine raw moments of the post-collision (plus source/aux) populations, from the
     orthogonality of the Hermite basis on D2Q9: the zeroth moment is conserved (plus the source),
-    the first relaxes with 1 - 1/tau1, the second Hermite moment with 1 - 1/tau2, and the third- and
-    fourth-order moments follow from the equilibrium and the projected non-equilibrium parts."""
+    the first relaxes with 1 - 1/tau1, the second Hermite moment with 1 - 1/tau2, the third Hermite
+    moments (xxy, xyy) with 1 - 1/tau3 (0 for TRT-R: B3 is the third-order non-equilibrium moment),
+    and the fourth-order moment follows from the equilibrium and the projected parts."""
     u = np.array([ux, uy])
     B = j - phi * u
     N = Pi - cs2 * phi * np.eye(2) - phi * np.outer(u, u)
@@ -97,8 +98,8 @@ def _expected_post_moments(phi, j, Pi, ux, uy, om1, om2, cs2, s_eff=0.0, V=(0.0,
     m1 = phi * u + om1 * B + np.asarray(V)
     H2 = phi * np.outer(u, u) + om2 * N
     m2 = H2 + cs2 * m0 * np.eye(2)
-    mxxy = cs2 * phi * uy + phi * ux * ux * uy + om1 * cs2 * B[1] + cs2 * V[1]
-    mxyy = cs2 * phi * ux + phi * ux * uy * uy + om1 * cs2 * B[0] + cs2 * V[0]
+    mxxy = cs2 * phi * uy + phi * ux * ux * uy + om1 * cs2 * B[1] + cs2 * V[1] + om3 * B3[0]
+    mxyy = cs2 * phi * ux + phi * ux * uy * uy + om1 * cs2 * B[0] + cs2 * V[0] + om3 * B3[1]
     mxxyy = phi * cs2 * (cs2 + ux * ux + uy * uy) + om2 * cs2 * (N[0, 0] + N[1, 1]) + cs2 * cs2 * s_eff
     return np.array([m0, m1[0], m1[1], m2[0, 0], m2[1, 1], m2[0, 1], mxxy, mxyy, mxxyy])
 
@@ -122,6 +123,31 @@ def test_collision_moments(seed):
     np.testing.assert_allclose(got / scale, want / scale, rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("seed", [7, 8, 9])
+def test_mrt_collision_moments(seed):
+    """MRT-R (Eq. (10) to third order): the third Hermite moments relax with 1 - 1/tau3 from their
+    equilibrium values phi u_x^2 u_y, phi u_x u_y^2, by B_xxy = sum (e_x^2 e_y - cs2 e_y) g - phi u_x^2 u_y
+    (and likewise xyy); every other moment is that of TRT-R; tau3 = 1 is TRT-R exactly."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.5, 4.0)
+    cs2 = c * c / 3
+    g = rng.uniform(0.0, 0.3, 9)
+    ux, uy = rng.uniform(-0.3, 0.3, 2) * c
+    tau1, tau2, tau3 = rng.uniform(0.51, 2.0, 3)
+    C = O.collide_mrt(g, ux, uy, tau1, tau2, tau3, c)
+    ex, ey, _ = _E(c)
+    phi = g.sum()
+    j = np.array([(ex * g).sum(), (ey * g).sum()])
+    Pi = np.array([[(ex * ex * g).sum(), (ex * ey * g).sum()], [(ex * ey * g).sum(), (ey * ey * g).sum()]])
+    B3 = ((ex * ex * ey * g).sum() - cs2 * j[1] - phi * ux * ux * uy,
+          (ex * ey * ey * g).sum() - cs2 * j[0] - phi * ux * uy * uy)
+    want = _expected_post_moments(phi, j, Pi, ux, uy, 1 - 1 / tau1, 1 - 1 / tau2, cs2, om3=1 - 1 / tau3, B3=B3)
+    got = _moments9(C, ex, ey)
+    scale = np.array([1, c, c, c * c, c * c, c * c, c ** 3, c ** 3, c ** 4])
+    np.testing.assert_allclose(got / scale, want / scale, rtol=0, atol=1e-13)
+    assert np.array_equal(O.collide_mrt(g, ux, uy, tau1, tau2, 1.0, c), O.collide(g, ux, uy, tau1, tau2, c))
+
+
 def test_relaxation_pair():
     # kappa = (tau1 - 1/2) cs2 dt and Lambda = (tau1 - 1/2)(tau2 - 1/2) (Sec. 2.4)
     dx, dt, lam = 0.03, 0.002, 0.25
@@ -135,12 +161,14 @@ def test_relaxation_pair():
 # ---- one step seen through its moments (Sec. 2.2, Eq. (14) with Eqs. (3), (16)) ----------------
 
 @pytest.mark.parametrize("aux,boundary", [(O.AUX_LOCAL, O.BC_PERIODIC), (O.AUX_NONE, O.BC_PERIODIC),
-                                          (O.AUX_LOCAL, O.BC_NEE)])
+                                          (O.AUX_LOCAL, O.BC_NEE), (O.AUX_LOCAL, O.BC_WALLS)])
 def test_step_moments_with_source_and_aux(aux, boundary):
     """Un-stream one oracle step and check all nine moments of P_i at every node away from the
-    periodic seam (periodic) or at every node including the edges (Dirichlet edges, where the
-    derivative across the edge is one-sided).  With the solid-body rotation u = (-U0 y, U0 x) both
-    differences are exact, so u_b d_b u_a is the closed form (-U0^2 x, -U0^2 y) (centripetal)."""
+    periodic seam (periodic), at every node including the edges (Dirichlet edges, where the
+    derivative across the edge is one-sided), or on every row (walls: a population that crossed a
+    wall came back as -P_i + 2 g_eq^+(phi_w), which the test inverts with g_eq from the oracle's
+    equilibrium).  With the solid-body rotation u = (-U0 y, U0 x) both differences are exact, so
+    u_b d_b u_a is the closed form (-U0^2 x, -U0^2 y) (centripetal)."""
     n = 12
     U0 = 1.3
     X, Y, dx = W.mesh(n, n, -1.0, 1.0)
@@ -155,14 +183,24 @@ def test_step_moments_with_source_and_aux(aux, boundary):
     S = rng.uniform(-1, 1, (n, n))
     dS = rng.uniform(-1, 1, (n, n))
     p = O.Problem(n, n, dx, dt, lam, 0.0, aux, boundary)
-    out = O.step(p, g, ux, uy, D, S, dS)
+    phi_w = rng.uniform(0.2, 0.8, (n, n))
+    out = O.step(p, g, ux, uy, D, S, dS, phi_b=phi_w if boundary == O.BC_WALLS else None)
     ex, ey, _ = _E(1.0)
     P = np.empty_like(out)
     for i in range(9):  # P_i(x) = g_i^{n+1}(x + e_i dt)
         P[i] = np.roll(out[i], shift=(-int(ey[i]), -int(ex[i])), axis=(0, 1))
+    if boundary == O.BC_WALLS:
+        opp = [int(np.flatnonzero((ex == -ex[i]) & (ey == -ey[i]))[0]) for i in range(9)]
+        for k in (0, n - 1):
+            for jx in range(n):
+                ge = O.equilibrium(phi_w[k, jx], ux[k, jx], uy[k, jx], c)
+                for i in range(9):
+                    if (k == 0 and ey[i] < 0) or (k == n - 1 and ey[i] > 0):
+                        P[i, k, jx] = -out[opp[i], k, jx] + ge[i] + ge[opp[i]]
     Ec = _E(c)
     nodes = range(n) if boundary == O.BC_NEE else range(1, n - 1)
-    for k in nodes:
+    rows = range(n) if boundary in (O.BC_NEE, O.BC_WALLS) else range(1, n - 1)
+    for k in rows:
         for jx in nodes:
             gl = g[:, k, jx]
             phi = gl.sum()
@@ -354,6 +392,46 @@ def test_nee_equilibrium_is_a_fixed_point():
     p = O.Problem(n, n, dx, dt, 0.25, 1e-3, O.AUX_LOCAL, O.BC_NEE)
     g = O.init(p, phi, ux, uy)
     np.testing.assert_allclose(O.apply_nee(p, g, ux, uy, phi), g, rtol=0, atol=1e-14)
+
+
+# ---- walls by halfway anti-bounce-back; the slip-free free parameter (Sec. 3.3) -----------------
+
+def _channel_error(tau1, tau2, ny=12, nx=3, phi_bot=0.3, phi_top=0.7, S0=2e-3):
+    """Steady diffusion across a channel with walls at y = -1/2 and y = ny - 1/2 (lattice units),
+    wall values phi_bot / phi_top, uniform source S0, u = 0: the exact profile is
+    phi = phi_bot + (phi_top - phi_bot) (y + 1/2) / ny + S0 / (2 kappa) (y + 1/2)(ny - 1/2 - y).
+    Returns the relative RMS error of the converged oracle solution."""
+    cs2 = 1.0 / 3.0
+    kappa = (tau1 - 0.5) * cs2
+    p = O.Problem(nx, ny, 1.0, 1.0, (tau1 - 0.5) * (tau2 - 0.5), kappa, O.AUX_LOCAL, O.BC_WALLS)
+    z = np.zeros((ny, nx))
+    pb = np.zeros((ny, nx))
+    pb[0, :], pb[-1, :] = phi_bot, phi_top
+    S = np.full((ny, nx), S0)
+    g = O.init(p, np.full((ny, nx), 0.5), z, z)
+    prev = None
+    for _ in range(400):
+        g = O.run(p, g, 2000, z, z, None, S, None, phi_b=pb)
+        phi = O.phi(p, g)
+        if prev is not None and np.abs(phi - prev).max() < 1e-15:
+            break
+        prev = phi
+    y = np.arange(ny)[:, None] + 0.5
+    exact = phi_bot + (phi_top - phi_bot) * y / ny + S0 / (2 * kappa) * y * (ny - y)
+    return float(np.sqrt(np.mean((phi - exact) ** 2)) / np.abs(exact).max())
+
+
+@pytest.mark.parametrize("tau1", [0.6, 0.8, 1.2])
+def test_slip_free_relation_of_the_free_parameter(tau1):
+    """The free relaxation time tau2 = 3(1 - 4 tau1) / (8(1 - 2 tau1)) of Sec. 3.3 (tau1 = 0.8 gives
+    1.375) makes the halfway anti-bounce-back walls slip-free: the linear-plus-parabolic steady
+    profile is reproduced to round-off, while tau2 off that value leaves an O(1e-4) wall error."""
+    tau2 = 3 * (1 - 4 * tau1) / (8 * (1 - 2 * tau1))
+    if tau1 == 0.8:
+        assert abs(tau2 - 1.375) < 1e-15
+    assert _channel_error(tau1, tau2) < 1e-12
+    assert _channel_error(tau1, tau2 + 0.15) > 1e-5
+    assert _channel_error(tau1, tau2 - 0.15) > 1e-5
 
 
 # ---- P9 / P14: the paper's printed Table 2 ----------------------------------------------------
