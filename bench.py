@@ -361,10 +361,10 @@ def _find(dirpath, suffix):
 
 
 def _kernel_label(name: str):
-    """'step_kernel<2, 0, false, false, false>' (mode, aux, has_k, has_s, Dirichlet edges) ->
-    ('step', 'f32', aux 0, has_k, has_s) for the periodic kernels; copy -> ('copy',); other -> None."""
+    """'step_kernel<2, 0, false, false, 0, false>' (mode, aux, has_k, has_s, boundary, MRT-R) ->
+    ('step', 'f32', aux 0, has_k, has_s) for the periodic TRT-R kernels; copy -> ('copy',); other -> None."""
     import re
-    m = re.search(r"step_kernel<(\d), (\d), (true|false), (true|false), false>", name)
+    m = re.search(r"step_kernel<(\d), (\d), (true|false), (true|false), 0, false>", name)
     if m:
         return ("step", KERNEL_MODES[m.group(1)], int(m.group(2)), m.group(3) == "true", m.group(4) == "true")
     if "copy_kernel" in name:

@@ -67,8 +67,14 @@ enum lbm_aux { LBM_AUX_LOCAL = 0, LBM_AUX_FLUX = 1, LBM_AUX_NONE = 2 };
  * g_i(x_b) = g_eq_i(phi_b(x_b), u(x_b)) + [g_i(x_f) - g_eq_i(phi(x_f), u(x_f))], x_f its interior
  * neighbour along the inward normal (diagonal at corners), phi_b set by lbm_set_dirichlet.  The
  * differences of u in the LOCAL auxiliary term are one-sided across an edge.  NEE is available with
- * aux LOCAL or NONE, runs one launch per instance, and has no adjoint. */
-enum lbm_boundary { LBM_BC_PERIODIC = 0, LBM_BC_NEE = 1 };
+ * aux LOCAL or NONE, runs one launch per instance, and has no adjoint.
+ * WALLS: x wraps; Dirichlet walls lie halfway below row 0 and above row ny - 1 (at y = -dx/2 and
+ * y = (ny - 1/2) dx), by halfway anti-bounce-back (the wall scheme of Sec. 3.3): a population that
+ * would cross a wall returns to its node reversed, g_opp(i) = -P_i + 2 g_eq_i^+(phi_w, u(node)),
+ * with g_eq^+ the even part of the equilibrium and phi_w from row 0 (bottom wall) or row ny - 1 (top
+ * wall) of lbm_set_dirichlet's array.  The y-differences of u in the LOCAL auxiliary term are
+ * one-sided on those rows.  Available with aux LOCAL or NONE; one launch per instance; no adjoint. */
+enum lbm_boundary { LBM_BC_PERIODIC = 0, LBM_BC_NEE = 1, LBM_BC_WALLS = 2 };
 
 /* One problem instance: the paper's problem statement on a lattice. */
 typedef struct lbm_params {
@@ -83,6 +89,9 @@ typedef struct lbm_params {
     double phi_ref;       /* F16S only: background value removed before encoding */
     int32_t boundary;     /* enum lbm_boundary */
     int32_t reserved;     /* must be 0 */
+    double tau3;          /* MRT-R (Sec. 2.2, Eq. (10), truncated after third order): relaxation time of
+                             the third-order Hermite non-equilibrium moments, finite and > 1/2;
+                             0 (or 1) selects the TRT-R operator of Eq. (12), which drops them */
 } lbm_params;
 
 /* Fields of one instance (device, FP64, [ny][nx]).  u is in physical units; D > 0 everywhere.
@@ -130,10 +139,13 @@ int lbm_init(lbm_ctx **ctx, int32_t n_inst, const lbm_params *p, const lbm_field
 int lbm_step(lbm_ctx *ctx, int32_t nsteps, const double *const *ux, const double *const *uy,
              const double *const *S, const double *const *dSdt);
 
-/* Dirichlet values of an LBM_BC_NEE instance: phi_b (device FP64 [ny][nx], copied; only its
- * boundary entries take effect) is used from the next step on, and by lbm_macros / lbm_populations,
- * which report the boundary nodes after extrapolation (so phi = phi_b there).  Before the first call
- * the values are phi0's.  Asynchronous (stream order).  LBM_E_STATE for a periodic instance. */
+/* Dirichlet values of an LBM_BC_NEE or LBM_BC_WALLS instance: phi_b (device FP64 [ny][nx], copied;
+ * only its boundary entries take effect: the edge nodes for NEE, rows 0 and ny - 1 as the bottom and
+ * top wall values for WALLS).  They are the values of the current time level: the next step applies
+ * them to the state it starts from, and lbm_macros / lbm_populations report that state with them
+ * (NEE: phi = phi_b on the edges; WALLS: the reflected populations of rows 0 and ny - 1).  Before the
+ * first call the values are phi0's, for which the initial state is g_eq(phi0, u) everywhere.
+ * Asynchronous (stream order).  LBM_E_STATE for a periodic instance. */
 int lbm_set_dirichlet(lbm_ctx *ctx, int32_t inst, const double *phi_b);
 
 /* Diagnostics of instance inst: phi = sum_i g_i at the current time.  phi_out (device FP64

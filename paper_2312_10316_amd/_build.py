@@ -14,7 +14,7 @@ ARCH = "gfx950"
 # -packed-fp32-ops: no v_pk_{add,mul,fma}_f32 in generated code.
 HIPCC_FLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-               "-fno-gpu-rdc", "-ffp-contract=fast"]
+               "-fno-gpu-rdc", "-ffp-contract=fast-honor-pragmas"]
 
 
 def hipcc() -> str:

@@ -87,11 +87,13 @@ int validate(const lbm_params &p, int k)
     if (p.math == LBM_MATH_F64 && p.store != LBM_STORE_F64)
         return fail(LBM_E_ARG, "instance %d: FP64 math needs FP64 storage", k);
     if (p.aux < LBM_AUX_LOCAL || p.aux > LBM_AUX_NONE) return fail(LBM_E_ARG, "instance %d: unknown aux %d", k, p.aux);
-    if (p.boundary != LBM_BC_PERIODIC && p.boundary != LBM_BC_NEE)
+    if (p.boundary < LBM_BC_PERIODIC || p.boundary > LBM_BC_WALLS)
         return fail(LBM_E_ARG, "instance %d: unknown boundary %d", k, p.boundary);
     if (p.reserved != 0) return fail(LBM_E_ARG, "instance %d: reserved field must be 0", k);
-    if (p.boundary == LBM_BC_NEE && p.aux == LBM_AUX_FLUX)
-        return fail(LBM_E_UNSUPPORTED, "instance %d: the flux form of the aux term has no Dirichlet edges", k);
+    if (p.boundary != LBM_BC_PERIODIC && p.aux == LBM_AUX_FLUX)
+        return fail(LBM_E_UNSUPPORTED, "instance %d: the flux form of the aux term is periodic only", k);
+    if (p.tau3 != 0.0 && !(std::isfinite(p.tau3) && p.tau3 > 0.5))
+        return fail(LBM_E_ARG, "instance %d: tau3 must be 0 (TRT-R) or finite and > 1/2", k);
     if (p.store == LBM_STORE_F16S) {
         if (p.scale_log2 < 0 || p.scale_log2 > 24)
             return fail(LBM_E_ARG, "instance %d: scale_log2=%d outside 0..24", k, p.scale_log2);
@@ -132,7 +134,7 @@ size_t vel_bytes(const lbm_params &p) { return align_up((size_t)vel_elems(layout
 size_t field_bytes(const lbm_params &p) { return align_up((size_t)fld_elems(layout_of(p)) * math_bytes(mode_of(p)), kAlign); }
 size_t instance_bytes(const lbm_params &p)
 {
-    return 2 * pops_bytes(p) + vel_bytes(p) + (p.boundary == LBM_BC_NEE ? 3 : 2) * field_bytes(p);
+    return 2 * pops_bytes(p) + vel_bytes(p) + (p.boundary != LBM_BC_PERIODIC ? 3 : 2) * field_bytes(p);
 }
 
 size_t max_items_of(int32_t n_inst, const lbm_params *p)
@@ -178,8 +180,9 @@ InstDesc desc_of(const Instance &in)
     d.has_k = in.has_D ? 1 : 0;
     d.has_s = in.has_src ? 1 : 0;
     d.bc = in.bc;
-    d.nee = in.p.boundary == LBM_BC_NEE ? 1 : 0;
+    d.bckind = in.p.boundary;
     if (!in.has_D) const_relax(in.p, d.w1, d.w2, d.beta);
+    d.w3 = in.p.tau3 == 0.0 ? 0.0 : 1.0 - 1.0 / in.p.tau3;
     d.lambda = in.p.lambda;
     d.f16 = in.f16;
     return d;
@@ -469,7 +472,7 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
         in.s = w + fb;
         w += 2 * fb;
         in.bc = nullptr;
-        if (p[k].boundary == LBM_BC_NEE) {
+        if (p[k].boundary != LBM_BC_PERIODIC) {
             in.bc = w;
             w += fb;
         }
@@ -477,8 +480,9 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
         in.has_src = false;
         in.step = 0;
         in.f16 = f16_of(p[k]);
-        if (in.mode != c->inst[0].mode || in.p.aux != c->inst[0].p.aux || in.p.boundary != LBM_BC_PERIODIC)
-            c->uniform = false;  // batched launches cover periodic instances of one storage/aux form
+        if (in.mode != c->inst[0].mode || in.p.aux != c->inst[0].p.aux || in.p.boundary != LBM_BC_PERIODIC ||
+            (in.p.tau3 != 0.0 && in.p.tau3 != 1.0))
+            c->uniform = false;  // batched launches cover periodic TRT-R instances of one storage/aux form
     }
     const size_t items = max_items_of(n_inst, p);
     c->d_desc = reinterpret_cast<InstDesc *>(w);
@@ -500,7 +504,7 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
         rc = set_velocity(c, in, f[k].ux, f[k].uy);
         if (rc == LBM_OK && in.has_D)  // k = tau1 - 1/2 = kappa / (cs^2 dt) = 3 kappa dt / dx^2
             rc = prep_field(c, in, f[k].D, nullptr, 3.0 * in.p.dt / (in.p.dx * in.p.dx), 0.0, in.k, 1);
-        if (rc == LBM_OK && in.bc)  // Dirichlet values start as phi0 on the edges
+        if (rc == LBM_OK && in.bc)  // Dirichlet (edge or wall) values start as phi0's
             rc = prep_field(c, in, f[k].phi0, nullptr, 1.0, 0.0, in.bc, 0);
         if (rc == LBM_OK) {
             InitArgs ia;
@@ -510,6 +514,7 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
             ia.L = in.L;
             ia.f16 = in.f16;
             ia.range_flag = c->flag;
+            ia.walls = in.p.boundary == LBM_BC_WALLS ? 1 : 0;
             e = launch_init(in.mode, ia, c->stream);
             if (e != hipSuccess) rc = hip_fail(e, "init kernel launch");
         }
@@ -591,6 +596,7 @@ int lbm_macros(lbm_ctx *c, int32_t inst, double *phi_out, const double *ref, lbm
     a.f16 = in.f16;
     a.edge.u = in.u;
     a.edge.bc = in.bc;
+    a.edge.kind = in.p.boundary;
     a.partials = c->partials;
     hipError_t e = launch_macros(in.mode, a, c->result, c->stream);
     if (e != hipSuccess) return hip_fail(e, "macros kernel launch");
@@ -617,7 +623,7 @@ int lbm_set_dirichlet(lbm_ctx *c, int32_t inst, const double *phi_b)
     if (!check_inst(c, inst)) return fail(LBM_E_STATE, "lbm_set_dirichlet: bad context or instance %d", inst);
     if (!phi_b) return fail(LBM_E_ARG, "lbm_set_dirichlet: phi_b is NULL");
     Instance &in = c->inst[inst];
-    if (in.p.boundary != LBM_BC_NEE) return fail(LBM_E_STATE, "lbm_set_dirichlet: instance %d is periodic", inst);
+    if (in.p.boundary == LBM_BC_PERIODIC) return fail(LBM_E_STATE, "lbm_set_dirichlet: instance %d is periodic", inst);
     return prep_field(c, in, phi_b, nullptr, 1.0, 0.0, in.bc, 0);
 }
 
@@ -634,6 +640,7 @@ int lbm_populations(lbm_ctx *c, int32_t inst, double *g_out)
     a.f16 = in.f16;
     a.edge.u = in.u;
     a.edge.bc = in.bc;
+    a.edge.kind = in.p.boundary;
     hipError_t e = launch_populations(in.mode, a, c->stream);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "populations kernel launch");
 }
@@ -724,7 +731,8 @@ int adjoint_ok(lbm_ctx *c, int32_t inst, const char *who)
     const Instance &in = c->inst[inst];
     if (in.mode == MODE_F16S_F32) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for FP16 storage", who);
     if (in.p.aux == LBM_AUX_FLUX) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for the flux form of the aux term", who);
-    if (in.p.boundary != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for Dirichlet edges", who);
+    if (in.p.boundary != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for Dirichlet edges or walls", who);
+    if (in.p.tau3 != 0.0 && in.p.tau3 != 1.0) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for the MRT-R operator", who);
     return LBM_OK;
 }
 }  // namespace

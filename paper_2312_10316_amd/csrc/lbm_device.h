@@ -28,17 +28,19 @@ namespace lbm {
 // D2Q9 velocity order of the population planes.
 constexpr int kEx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 constexpr int kEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};  // e_kOpp[i] = -e_i
 constexpr double kW[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
                           1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
+// w3 = 1 - 1/tau3 relaxes the third-order non-equilibrium moments (MRT-R, Eq. (10)); 0 is TRT-R.
 template <class M>
 struct Relax {
-    M w1, w2, beta;
+    M w1, w2, beta, w3;
 };
 
 // k = tau1 - 1/2 (lattice diffusivity), lambda = magic parameter.
 template <class M>
-__device__ __forceinline__ Relax<M> relax_from_k(M k, M lambda)
+__device__ __forceinline__ Relax<M> relax_from_k(M k, M lambda, M w3)
 {
     const M tau1 = M(0.5) + k;
     const M tau2 = M(0.5) + lambda / k;
@@ -46,6 +48,7 @@ __device__ __forceinline__ Relax<M> relax_from_k(M k, M lambda)
     r.w1 = M(1) - M(1) / tau1;
     r.w2 = M(1) - M(1) / tau2;
     r.beta = M(1) - M(0.5) / tau1;
+    r.w3 = w3;
     return r;
 }
 
@@ -86,7 +89,7 @@ __device__ __forceinline__ void equilibrium(M phi, M ux, M uy, M (&P)[9])
 // TRT-R collision + source + auxiliary term for one node (Eq. (14) without the streaming).
 //   g: pre-collision populations; (ux, uy): lattice velocity; r: relaxation; (Ax, Ay): auxiliary
 //   vector A (already multiplied by phi); s: dt S + dt^2/2 dS/dt (0 without a source).
-template <class M>
+template <class M, bool MRT = false>
 __device__ __forceinline__ void collide(const M (&g)[9], M ux, M uy, const Relax<M> &r, M Ax, M Ay,
                                         M s, M (&P)[9])
 {
@@ -105,7 +108,16 @@ __device__ __forceinline__ void collide(const M (&g)[9], M ux, M uy, const Relax
     const M a2xx = euxx + r.w2 * (pxx - third - euxx);
     const M a2yy = euyy + r.w2 * (pyy - third - euyy);
     const M a2xy = euxy + r.w2 * (pxy - euxy);
-    reconstruct<M>(phi + s, a1x, a1y, a2xx, a2yy, a2xy, euxx * uy, euxy * uy, P);
+    // third Hermite moments: the equilibrium's phi u_x^2 u_y, phi u_x u_y^2 (TRT-R), plus for MRT-R
+    // w3 times the non-equilibrium part sum_i H_i,xxy g_i - phi u_x^2 u_y, H_xxy = e_y (e_x^2 - 1/3)
+    M a3xxy = euxx * uy, a3xyy = euxy * uy;
+    if constexpr (MRT) {
+        const M qxxy = (g[5] + g[6]) - (g[7] + g[8]);
+        const M qxyy = (g[5] - g[6]) - (g[7] - g[8]);
+        a3xxy += r.w3 * (qxxy - jy * M(1.0 / 3.0) - a3xxy);
+        a3xyy += r.w3 * (qxyy - jx * M(1.0 / 3.0) - a3xyy);
+    }
+    reconstruct<M>(phi + s, a1x, a1y, a2xx, a2yy, a2xy, a3xxy, a3xyy, P);
 }
 
 // ---- population storage codecs --------------------------------------------------------------
@@ -152,7 +164,11 @@ struct Codec<StoreF16S, float> {
     }
     __device__ __forceinline__ static _Float16 enc(float v, int i, const F16Params &c)
     {
-        return (_Float16)((v - c.wref[i]) * c.scale);  // v_cvt_f16_f32, round to nearest even
+        // The shift is a plain FP32 subtraction of the rounded value v (never fused with the product
+        // that formed v), so the stored code does not depend on how the caller's arithmetic is
+        // contracted; the power-of-two scale is exact; v_cvt_f16_f32 rounds to nearest even.
+#pragma clang fp contract(off)
+        return (_Float16)((v - c.wref[i]) * c.scale);
     }
 };
 

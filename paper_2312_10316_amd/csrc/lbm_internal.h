@@ -54,9 +54,11 @@ struct InstDesc {
     Layout L;
     Launch lc;
     int32_t has_k, has_s;
-    const void *bc;     // Dirichlet values phi_b (math type, [ny][pitch]) of a non-equilibrium-extrapolation edge
-    int32_t nee;        // 1: the first/last rows and columns are Dirichlet nodes (bc)
+    const void *bc;     // Dirichlet values (math type, [ny][pitch]): phi_b of the edge nodes (NEE), or
+                        // the wall values of the walls below row 0 / above row ny - 1 (walls)
+    int32_t bckind;     // 0 periodic, 1 NEE edges, 2 walls (lbm_boundary)
     double w1, w2, beta;  // relaxation when !has_k: 1 - 1/tau1, 1 - 1/tau2, 1 - 1/(2 tau1)
+    double w3;          // 1 - 1/tau3 (MRT-R); 0 for TRT-R
     double lambda;
     F16Params f16;
 };
@@ -92,6 +94,7 @@ struct InitArgs {
     Layout L;
     F16Params f16;
     int *range_flag;     // set to 1 if an F16S value does not fit
+    int32_t walls;       // 1: no node lies across y = -1/2 or y = ny - 1/2 (walls)
 };
 
 struct PrepArgs {
@@ -109,7 +112,8 @@ struct PrepArgs {
 // Boundary data the diagnostics need to report the extrapolated Dirichlet nodes.
 struct EdgeArgs {
     const void *u;     // velocity (math type)
-    const void *bc;    // phi_b (math type), or nullptr for a periodic instance
+    const void *bc;    // Dirichlet values (math type), or nullptr for a periodic instance
+    int32_t kind;      // lbm_boundary: 1 NEE edges, 2 walls
 };
 
 struct MacroArgs {

@@ -42,6 +42,19 @@ struct ModeTraits<MODE_F16S_F32> {
 __device__ __forceinline__ int wrap_dec(int v, int n) { return v == 0 ? n - 1 : v - 1; }
 __device__ __forceinline__ int wrap_inc(int v, int n) { return v == n - 1 ? 0 : v + 1; }
 
+// Element at a 32-bit byte offset from a wave-uniform base: lets the compiler use the scalar-base +
+// 32-bit-lane-offset addressing form instead of per-lane 64-bit address arithmetic.
+template <class T>
+__device__ __forceinline__ T ld_at(const T *base, unsigned byte_off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void st_nt_at(T *base, unsigned byte_off, T v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off));
+}
+
 // g_i(x, y) = buf_i(x - e_i).  rm, rc, rp: the row blocks (9 segments) of rows y-1, y, y+1 (wrapped);
 // xm, xp: columns x-1, x+1 (wrapped).
 template <class St, class M>
@@ -99,6 +112,47 @@ __device__ __forceinline__ void nee_replace(const typename St::T *__restrict__ s
     for (int i = 0; i < 9; ++i) g[i] = eb[i] + (gf[i] - ef[i]);
 }
 
+// Walls (halfway anti-bounce-back) below row 0 and above row ny - 1: a population that crossed the
+// wall returns to its node reversed, g_i = -P_opp(i) + 2 g_eq_i^+(phi_w, u), with
+// 2 g_eq_i^+ = g_eq_i + g_eq_opp(i), P_opp(i) the node's own post-collision value of the previous step
+// (element (y, opp(i), x)) and phi_w the wall value stored in row y of bc.  Applies to y = 0
+// (i = 2, 5, 6 arrive from below) and y = ny - 1 (i = 4, 7, 8 arrive from above).
+template <class St, class M>
+__device__ __forceinline__ void wall_replace(const typename St::T *__restrict__ row, unsigned boff, M phiw, M ux,
+                                             M uy, bool bottom, const F16Params &f, int64_t pitch, M (&g)[9])
+{
+    using C = Codec<St, M>;
+    M e[9];
+    equilibrium<M>(phiw, ux, uy, e);
+    if (bottom) {
+        g[2] = (e[2] + e[4]) - C::dec(ld_at(row + 4 * pitch, boff), 4, f);
+        g[5] = (e[5] + e[7]) - C::dec(ld_at(row + 7 * pitch, boff), 7, f);
+        g[6] = (e[6] + e[8]) - C::dec(ld_at(row + 8 * pitch, boff), 8, f);
+    } else {
+        g[4] = (e[4] + e[2]) - C::dec(ld_at(row + 2 * pitch, boff), 2, f);
+        g[7] = (e[7] + e[5]) - C::dec(ld_at(row + 5 * pitch, boff), 5, f);
+        g[8] = (e[8] + e[6]) - C::dec(ld_at(row + 6 * pitch, boff), 6, f);
+    }
+}
+
+// The state of node (x, y) as the step sees it before collision: the pull, then the boundary rule.
+template <class St, class M>
+__device__ __forceinline__ void state_node(const typename St::T *__restrict__ src, const EdgeArgs &edge, const Layout &L,
+                                           int x, int y, const F16Params &f, M (&g)[9])
+{
+    pull_node<St, M>(src, L, x, y, f, g);
+    const M *u = static_cast<const M *>(edge.u);
+    const M *bc = static_cast<const M *>(edge.bc);
+    if (edge.kind == 1 && on_edge(x, y, L)) {
+        nee_replace<St, M>(src, u, bc, L, x, y, f, g);
+    } else if (edge.kind == 2 && (y == 0 || y == L.ny - 1)) {
+        const int64_t p = L.pitch;
+        wall_replace<St, M>(src + (int64_t)y * 9 * p, (unsigned)x * (unsigned)sizeof(typename St::T),
+                            bc[(int64_t)y * p + x], u[(int64_t)y * 2 * p + x], u[((int64_t)y * 2 + 1) * p + x],
+                            y == 0, f, p, g);
+    }
+}
+
 template <class St, class M>
 __device__ __forceinline__ M phi_at(const typename St::T *__restrict__ src, const Layout &L, int x, int y,
                                     const F16Params &f)
@@ -117,23 +171,11 @@ __device__ __forceinline__ int tile_of_block(int b, int nb, int remap)
     return j * q + min(j, r) + (b >> 3);
 }
 
-// Element at a 32-bit byte offset from a wave-uniform base: lets the compiler use the scalar-base +
-// 32-bit-lane-offset addressing form instead of per-lane 64-bit address arithmetic.
-template <class T>
-__device__ __forceinline__ T ld_at(const T *base, unsigned byte_off)
-{
-    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
-}
-template <class T>
-__device__ __forceinline__ void st_nt_at(T *base, unsigned byte_off, T v)
-{
-    __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off));
-}
 
 // One tile of one step with the local auxiliary term (or none).  Block (64, 4): lane = column of a
 // 64-wide tile, wave `wave` walks `rows` rows.  The wave's row is uniform (taken with readfirstlane), so row and segment bases live in
 // scalar registers and each load or store needs only a 32-bit lane offset (x, x-1 or x+1).
-template <int MODE, int AUX, bool HAS_K, bool HAS_S, bool NEE = false>
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC = 0, bool MRT = false>
 __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int t, int wave)
 {
     using St = typename ModeTraits<MODE>::St;
@@ -162,6 +204,7 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
     rconst.w1 = (M)a.w1;
     rconst.w2 = (M)a.w2;
     rconst.beta = (M)a.beta;
+    rconst.w3 = (M)a.w3;
 
     // velocity in this column at rows y-1 and y, rolled down the walk
     const int yprev = wrap_dec(y0, ny);
@@ -188,9 +231,13 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
         g[6] = C::dec(ld_at(rm + 6 * pitch, bp), 6, a.f16);
         g[7] = C::dec(ld_at(rp + 7 * pitch, bp), 7, a.f16);
         g[8] = C::dec(ld_at(rp + 8 * pitch, bm), 8, a.f16);
-        if constexpr (NEE) {
+        if constexpr (BC == 1) {
             if (y == 0 || y == ny - 1 || xc == 0 || xc == (unsigned)nx - 1)
                 nee_replace<St, M>(src, u, static_cast<const M *>(a.bc), a.L, (int)xc, y, a.f16, g);
+        } else if constexpr (BC == 2) {
+            if (y == 0 || y == ny - 1)
+                wall_replace<St, M>(rc, bc, ld_at(static_cast<const M *>(a.bc) + (int64_t)y * pitch, fc), ux_c, uy_c,
+                                    y == 0, a.f16, pitch, g);
         }
         const M *__restrict__ un = u + (int64_t)yn * 2 * pitch;
         const M *__restrict__ uc = u + (int64_t)y * 2 * pitch;
@@ -202,8 +249,10 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
             // across a Dirichlet edge the difference is one-sided (the wrapped neighbour is not adjacent)
             unsigned fl = fm, fr = fp;
             M hx = M(0.5), hy = M(0.5), uxl = ux_m, uyl = uy_m, uxr = ux_p, uyr = uy_p;
-            if constexpr (NEE) {
+            if constexpr (BC == 1) {
                 if (xc == 0) { fl = fc; hx = M(1); } else if (xc == (unsigned)nx - 1) { fr = fc; hx = M(1); }
+            }
+            if constexpr (BC != 0) {
                 if (y == 0) { uxl = ux_c; uyl = uy_c; hy = M(1); }
                 else if (y == ny - 1) { uxr = ux_c; uyr = uy_c; hy = M(1); }
             }
@@ -214,10 +263,10 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
             Ax = phi * (ux_c * dxux + uy_c * dyux);
             Ay = phi * (ux_c * dxuy + uy_c * dyuy);
         }
-        const Relax<M> r = HAS_K ? relax_from_k<M>(ld_at(kf + (int64_t)y * pitch, fc), lam) : rconst;
+        const Relax<M> r = HAS_K ? relax_from_k<M>(ld_at(kf + (int64_t)y * pitch, fc), lam, rconst.w3) : rconst;
         const M s = HAS_S ? ld_at(sf + (int64_t)y * pitch, fc) : M(0);
         M P[9];
-        collide<M>(g, ux_c, uy_c, r, Ax, Ay, s, P);
+        collide<M, MRT>(g, ux_c, uy_c, r, Ax, Ay, s, P);
         if (live) {
             T *__restrict__ out = dst + (int64_t)y * 9 * pitch;
 #pragma unroll
@@ -235,7 +284,7 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
 // y+1 gives both the next node's populations and phi(x, y+1), phi(x, y-1) is kept from the previous
 // row, and phi(x-1, y), phi(x+1, y) come from the neighbouring lanes (wave shuffles); only the lanes
 // at the tile's edges (and next to the periodic seam) pull their outside neighbour explicitly.
-template <int MODE, bool HAS_K, bool HAS_S>
+template <int MODE, bool HAS_K, bool HAS_S, bool MRT = false>
 __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity, int t, int wave)
 {
     using St = typename ModeTraits<MODE>::St;
@@ -267,6 +316,7 @@ __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity,
     rconst.w1 = (M)a.w1;
     rconst.w2 = (M)a.w2;
     rconst.beta = (M)a.beta;
+    rconst.w3 = (M)a.w3;
     auto row_pull = [&](int yy, M (&g)[9]) {
         pull<St, M>(row_block(src, a.L, wrap_dec(yy, ny)), row_block(src, a.L, yy), row_block(src, a.L, wrap_inc(yy, ny)),
                     pitch, (int)xm, (int)xc, (int)xp, a.f16, g);
@@ -301,10 +351,10 @@ __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity,
         const M div = (fex - fwx) * M(0.5) + (fny - fsy) * M(0.5);
         const M Ax = (fex * uxe - fwx * uxw) * M(0.5) + (fny * ux_p - fsy * ux_m) * M(0.5) - ux_c * div;
         const M Ay = (fex * uye - fwx * uyw) * M(0.5) + (fny * uy_p - fsy * uy_m) * M(0.5) - uy_c * div;
-        const Relax<M> r = HAS_K ? relax_from_k<M>(kf[(int64_t)y * pitch + xc], lam) : rconst;
+        const Relax<M> r = HAS_K ? relax_from_k<M>(kf[(int64_t)y * pitch + xc], lam, rconst.w3) : rconst;
         const M s = HAS_S ? sf[(int64_t)y * pitch + xc] : M(0);
         M P[9];
-        collide<M>(g, ux_c, uy_c, r, Ax, Ay, s, P);
+        collide<M, MRT>(g, ux_c, uy_c, r, Ax, Ay, s, P);
         if (live) {
             T *__restrict__ out = dst + (int64_t)y * 9 * pitch;
 #pragma unroll
@@ -322,19 +372,19 @@ __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity,
 }
 
 // Dispatch of one tile to the aux-term form.
-template <int MODE, int AUX, bool HAS_K, bool HAS_S, bool NEE = false>
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC = 0, bool MRT = false>
 __device__ __forceinline__ void run_tile(const InstDesc &d, int parity, int t, int wave)
 {
-    if constexpr (AUX == 1) process_tile_flux<MODE, HAS_K, HAS_S>(d, parity, t, wave);
-    else process_tile<MODE, AUX, HAS_K, HAS_S, NEE>(d, parity, t, wave);
+    if constexpr (AUX == 1) process_tile_flux<MODE, HAS_K, HAS_S, MRT>(d, parity, t, wave);
+    else process_tile<MODE, AUX, HAS_K, HAS_S, BC, MRT>(d, parity, t, wave);
 }
 
 // Single instance: block b -> tile (XCD-remapped if requested).
-template <int MODE, int AUX, bool HAS_K, bool HAS_S, bool NEE>
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC, bool MRT>
 __global__ __launch_bounds__(256) void step_kernel(const StepArgs a)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
-    run_tile<MODE, AUX, HAS_K, HAS_S, NEE>(a.d, a.parity, tile_of_block(blockIdx.x, gridDim.x, a.d.lc.xcd_remap), wave);
+    run_tile<MODE, AUX, HAS_K, HAS_S, BC, MRT>(a.d, a.parity, tile_of_block(blockIdx.x, gridDim.x, a.d.lc.xcd_remap), wave);
 }
 
 // Many instances in one launch: each block runs a range of (instance, tile) work items; the
@@ -384,10 +434,19 @@ __global__ __launch_bounds__(256) void init_kernel(const InitArgs a)
         for (int i = 0; i < 9; ++i) {
             int xd = x - kEx[i], yd = y - kEy[i];
             xd = xd < 0 ? xd + nx : (xd >= nx ? xd - nx : xd);
+            const bool across = yd < 0 || yd >= ny;
             yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
             if (MODE == MODE_F16S_F32) {
                 const float v = ((float)P[i] - a.f16.wref[i]) * a.f16.scale;
                 bad |= !(fabsf(v) <= 65504.0f);
+            }
+            if (a.walls && across) {
+                // No node lies beyond the wall.  Instead this node's own slot of the opposite,
+                // wall-bound direction (read only by the reflection) takes g_eq_opp(i), so that the
+                // reflection returns g_eq_i while the wall value is phi0's.
+                const int o = kOpp[i];
+                dst[((int64_t)y * 9 + o) * pitch + x] = C::enc(P[o], o, a.f16);
+                continue;
             }
             dst[((int64_t)yd * 9 + i) * pitch + xd] = C::enc(P[i], i, a.f16);
         }
@@ -470,9 +529,7 @@ __global__ __launch_bounds__(256) void macros_kernel(const MacroArgs a)
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(n % nx), y = (int)(n / nx);
         M g[9];
-        pull_node<St, M>(src, a.L, x, y, a.f16, g);
-        if (a.edge.bc && on_edge(x, y, a.L))
-            nee_replace<St, M>(src, static_cast<const M *>(a.edge.u), static_cast<const M *>(a.edge.bc), a.L, x, y, a.f16, g);
+        state_node<St, M>(src, a.edge, a.L, x, y, a.f16, g);
         double phi = 0;
 #pragma unroll
         for (int i = 0; i < 9; ++i) phi += (double)g[i];
@@ -537,9 +594,7 @@ __global__ __launch_bounds__(256) void populations_kernel(const PopArgs a)
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(n % nx), y = (int)(n / nx);
         M g[9];
-        pull_node<St, M>(src, a.L, x, y, a.f16, g);
-        if (a.edge.bc && on_edge(x, y, a.L))
-            nee_replace<St, M>(src, static_cast<const M *>(a.edge.u), static_cast<const M *>(a.edge.bc), a.L, x, y, a.f16, g);
+        state_node<St, M>(src, a.edge, a.L, x, y, a.f16, g);
 #pragma unroll
         for (int i = 0; i < 9; ++i) a.out[i * N + n] = (double)g[i];
     }
@@ -560,27 +615,39 @@ int grid_for(int64_t n, int block, int cap)
     return (int)(g < 1 ? 1 : g);
 }
 
-template <int MODE, int AUX, bool NEE>
-hipError_t launch_step_bc(const StepArgs &a, hipStream_t st)
+template <int MODE, int AUX, int BC, bool MRT>
+hipError_t launch_step_var(const StepArgs &a, hipStream_t st)
 {
     dim3 block(64, 4);
     const int nblocks = tiles_of(a.d.L, a.d.lc.rows);
     const bool hk = a.d.has_k, hs = a.d.has_s;
-    if (hk && hs) step_kernel<MODE, AUX, true, true, NEE><<<nblocks, block, 0, st>>>(a);
-    else if (hk) step_kernel<MODE, AUX, true, false, NEE><<<nblocks, block, 0, st>>>(a);
-    else if (hs) step_kernel<MODE, AUX, false, true, NEE><<<nblocks, block, 0, st>>>(a);
-    else step_kernel<MODE, AUX, false, false, NEE><<<nblocks, block, 0, st>>>(a);
+    if (hk && hs) step_kernel<MODE, AUX, true, true, BC, MRT><<<nblocks, block, 0, st>>>(a);
+    else if (hk) step_kernel<MODE, AUX, true, false, BC, MRT><<<nblocks, block, 0, st>>>(a);
+    else if (hs) step_kernel<MODE, AUX, false, true, BC, MRT><<<nblocks, block, 0, st>>>(a);
+    else step_kernel<MODE, AUX, false, false, BC, MRT><<<nblocks, block, 0, st>>>(a);
     return hipGetLastError();
+}
+
+// MRT-R (w3 != 0) is a separate instantiation so that the TRT-R kernels keep their registers.
+template <int MODE, int AUX, int BC>
+hipError_t launch_step_bc(const StepArgs &a, hipStream_t st)
+{
+    return a.d.w3 != 0.0 ? launch_step_var<MODE, AUX, BC, true>(a, st) : launch_step_var<MODE, AUX, BC, false>(a, st);
 }
 
 template <int MODE, int AUX>
 hipError_t launch_step_aux(const StepArgs &a, hipStream_t st)
 {
     if constexpr (AUX == 1) {
-        if (a.d.nee) return hipErrorInvalidValue;  // the flux form has no Dirichlet edges
-        return launch_step_bc<MODE, AUX, false>(a, st);
+        if (a.d.bckind != 0) return hipErrorInvalidValue;  // the flux form is periodic only
+        return launch_step_bc<MODE, AUX, 0>(a, st);
     } else {
-        return a.d.nee ? launch_step_bc<MODE, AUX, true>(a, st) : launch_step_bc<MODE, AUX, false>(a, st);
+        switch (a.d.bckind) {
+        case 0: return launch_step_bc<MODE, AUX, 0>(a, st);
+        case 1: return launch_step_bc<MODE, AUX, 1>(a, st);
+        case 2: return launch_step_bc<MODE, AUX, 2>(a, st);
+        default: return hipErrorInvalidValue;
+        }
     }
 }
 

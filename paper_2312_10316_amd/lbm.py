@@ -19,7 +19,7 @@ LBM_OK, LBM_E_ARG, LBM_E_HIP, LBM_E_STATE, LBM_E_NONFINITE, LBM_E_UNSUPPORTED = 
 LBM_STORE_F64, LBM_STORE_F32, LBM_STORE_F16S = 0, 1, 2
 LBM_MATH_F64, LBM_MATH_F32 = 0, 1
 LBM_AUX_LOCAL, LBM_AUX_FLUX, LBM_AUX_NONE = 0, 1, 2
-LBM_BC_PERIODIC, LBM_BC_NEE = 0, 1
+LBM_BC_PERIODIC, LBM_BC_NEE, LBM_BC_WALLS = 0, 1, 2
 
 # names of the population storage / arithmetic combinations
 MODES = {
@@ -41,7 +41,8 @@ class lbm_params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("dx", ctypes.c_double), ("dt", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("D_const", ctypes.c_double), ("store", ctypes.c_int32),
                 ("math", ctypes.c_int32), ("aux", ctypes.c_int32), ("scale_log2", ctypes.c_int32),
-                ("phi_ref", ctypes.c_double), ("boundary", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("phi_ref", ctypes.c_double), ("boundary", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tau3", ctypes.c_double)]
 
 
 class lbm_fields(ctypes.Structure):
@@ -147,10 +148,10 @@ def _ptr_array(ts: Optional[Sequence[Optional[torch.Tensor]]]):
 
 
 def make_params(nx, ny, dx, dt, lam, D_const=0.0, mode="f64", aux=LBM_AUX_LOCAL, scale_log2=15,
-                phi_ref=0.0, boundary=LBM_BC_PERIODIC) -> lbm_params:
+                phi_ref=0.0, boundary=LBM_BC_PERIODIC, tau3=0.0) -> lbm_params:
     store, math = MODES[mode]
     return lbm_params(int(nx), int(ny), float(dx), float(dt), float(lam), float(D_const), store, math, int(aux),
-                      int(scale_log2), float(phi_ref), int(boundary), 0)
+                      int(scale_log2), float(phi_ref), int(boundary), 0, float(tau3))
 
 
 def lbm_abi_version() -> int:

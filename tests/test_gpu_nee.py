@@ -150,7 +150,7 @@ def test_nee_and_periodic_instances_share_a_context():
 def test_nee_errors():
     f = nee_case(16, 16, 1)
     fields = {k: dev(f[k]) for k in ("phi0", "ux", "uy")}
-    bad = lbm.make_params(16, 16, f["dx"], f["dt"], 0.25, 1e-3, "f64", lbm.LBM_AUX_LOCAL, boundary=2)
+    bad = lbm.make_params(16, 16, f["dx"], f["dt"], 0.25, 1e-3, "f64", lbm.LBM_AUX_LOCAL, boundary=3)
     with pytest.raises(lbm.LbmError) as ei:
         Solver([(bad, fields)])
     assert ei.value.status == lbm.LBM_E_ARG

@@ -295,10 +295,10 @@ def test_f16s_decode_exhaustive():
 
 @pytest.mark.parametrize("phi_ref", [0.0, 0.5])
 def test_f16s_encode_matches_numpy_rne(phi_ref):
-    """u = 0 makes the initial populations w_i phi0; the kernel forms w_i phi0 - w_i phi_ref with one
-    fused multiply-add (one FP32 rounding of the exact value), scales by 2^k (exact) and rounds to
-    FP16.  The stored codes equal numpy's round-to-nearest-even float16 of the same FP32 value,
-    formed here from the exact product in extended precision."""
+    """u = 0 makes the initial populations the FP32 products w_i phi0; the encoder subtracts the
+    FP32 shift w_i phi_ref (a separate rounding, never fused with the product), scales by 2^k (exact)
+    and rounds to FP16.  The stored codes equal numpy's round-to-nearest-even float16 of the same FP32
+    value, formed here with numpy's IEEE float32 arithmetic."""
     n = 1024
     k = 15
     rng = np.random.default_rng(29)
@@ -313,8 +313,7 @@ def test_f16s_encode_matches_numpy_rne(phi_ref):
     ex, ey, w = O.lattice()
     p32 = phi0.astype(np.float32)
     for i in range(9):
-        exact = np.longdouble(np.float32(w[i])) * p32.astype(np.longdouble) - np.longdouble(np.float32(w[i] * phi_ref))
-        d32 = exact.astype(np.float32)  # one rounding of the (exactly representable) fused result
+        d32 = np.float32(w[i]) * p32 - np.float32(w[i] * phi_ref)  # two FP32 roundings
         want = (d32 * np.float32(2.0 ** k)).astype(np.float16).view(np.uint16)
         got = np.roll(img[:, i, :n], (int(ey[i]), int(ex[i])), (0, 1))
         assert np.array_equal(got, want), i
