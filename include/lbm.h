@@ -89,7 +89,7 @@ typedef struct lbm_params {
     double phi_ref;       /* F16S only: background value removed before encoding */
     int32_t boundary;     /* enum lbm_boundary */
     int32_t reserved;     /* must be 0 */
-    double tau3;          /* MRT-R (Sec. 2.2, Eq. (10), truncated after third order): relaxation time of
+    double tau3;          /* MRT-R (Sec. 2.2, Eq. (11), truncated after third order): relaxation time of
                              the third-order Hermite non-equilibrium moments, finite and > 1/2;
                              0 (or 1) selects the TRT-R operator of Eq. (12), which drops them */
 } lbm_params;

@@ -66,7 +66,7 @@ typedef struct orc_problem {
                           rebuilt by apply_nee before each step; across an edge the derivatives of
                           u in the auxiliary term are one-sided instead of wrapped); 2: walls at
                           y = -dx/2 and y = (ny - 1/2) dx by halfway anti-bounce-back, x periodic */
-    double tau3;       /* MRT-R third-order relaxation time (Sec. 2.2, Eq. (10)); 0 or 1: TRT-R */
+    double tau3;       /* MRT-R third-order relaxation time (Sec. 2.2, Eq. (11)); 0 or 1: TRT-R */
 } orc_problem;
 
 #ifndef ORC_COMPLEX
@@ -124,7 +124,7 @@ void ORC(relaxation)(real kappa, double dx, double dt, double lambda, real *tau1
     *tau2 = 0.5 + lambda / (*tau1 - 0.5);
 }
 
-/* MRT-R collision operator, Sec. 2.2, Eq. (10), truncated after the third order, with the
+/* MRT-R collision operator, Sec. 2.2, Eq. (11), truncated after the third order, with the
  * non-equilibrium moments B_a = sum_i H_a (g_i - g_eq_i) (Eq. (8)), B_ab (Eq. (13)) and
  * B_abg = sum_i H_abg (g_i - g_eq_i):
  *   C_i = g_eq_i + (1 - 1/tau1) w_i H_a B_a / cs2 + (1 - 1/tau2) w_i H_ab B_ab / (2 cs2^2)
@@ -207,7 +207,7 @@ void ORC(phi)(const orc_problem *p, const real *g, real *phi)
 
 /* One time step of the TRT-R evolution equation, Sec. 2.2, Eq. (14):
  *   g_i(x + e_i dt, t + dt) = C_i + dt G_i + dt F_i + (dt^2 / 2) d_t F_i
- * with C_i of Eq. (12) (Eq. (10) when tau3 is set), F_i of Eq. (3), G_i of Eq. (16) (or the selected
+ * with C_i of Eq. (12) (Eq. (11) when tau3 is set), F_i of Eq. (3), G_i of Eq. (16) (or the selected
  * reading), evaluated at every node x at time t_n and streamed to x + e_i dt on the periodic lattice.
  * With walls (boundary 2) a population that would cross y = -dx/2 or y = (ny - 1/2) dx returns to
  * its node reversed, by halfway anti-bounce-back for a Dirichlet value phi_w:

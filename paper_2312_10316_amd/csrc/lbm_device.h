@@ -32,7 +32,7 @@ constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};  // e_kOpp[i] = -e_i
 constexpr double kW[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
                           1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
-// w3 = 1 - 1/tau3 relaxes the third-order non-equilibrium moments (MRT-R, Eq. (10)); 0 is TRT-R.
+// w3 = 1 - 1/tau3 relaxes the third-order non-equilibrium moments (MRT-R, Eq. (11)); 0 is TRT-R.
 template <class M>
 struct Relax {
     M w1, w2, beta, w3;

@@ -125,7 +125,7 @@ def test_collision_moments(seed):
 
 @pytest.mark.parametrize("seed", [7, 8, 9])
 def test_mrt_collision_moments(seed):
-    """MRT-R (Eq. (10) to third order): the third Hermite moments relax with 1 - 1/tau3 from their
+    """MRT-R (Eq. (11) to third order): the third Hermite moments relax with 1 - 1/tau3 from their
     equilibrium values phi u_x^2 u_y, phi u_x u_y^2, by B_xxy = sum (e_x^2 e_y - cs2 e_y) g - phi u_x^2 u_y
     (and likewise xyy); every other moment is that of TRT-R; tau3 = 1 is TRT-R exactly."""
     rng = np.random.default_rng(seed)
