@@ -5,7 +5,8 @@ TEST INFRASTRUCTURE ONLY.  This package is the checker, not the product: only ``
 code with the HIP library (``paper_2312_10316_amd``) and never imports it.
 
 The arithmetic lives in ``lbm_oracle.c`` (plain C, compiled with ``gcc -O2 -ffp-contract=off``, no
-fast-math, twice: FP64 and FP64-complex for complex-step derivatives).  This module only marshals
+fast-math, twice: FP64 and FP64-complex for complex-step derivatives) and, for the D3Q19 lattice, in
+``lbm_oracle_d3q19.c`` (FP64).  This module only marshals
 numpy arrays.  Reductions (mass, the RMS error of Sec. 3, Eq. (33)) are computed here with
 ``math.fsum`` (correctly rounded sums), in the definitions' own terms.
 
@@ -24,6 +25,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
+_SRC3 = os.path.join(_HERE, "lbm_oracle_d3q19.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 AUX_LOCAL, AUX_FLUX, AUX_NONE = 0, 1, 2
@@ -32,13 +34,14 @@ BC_PERIODIC, BC_NEE, BC_WALLS = 0, 1, 2
 
 def build(force: bool = False) -> str:
     """Compile the oracle (both builds) into one shared object; returns its path."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+    if (not force and os.path.exists(_LIB)
+            and os.path.getmtime(_LIB) >= max(os.path.getmtime(_SRC), os.path.getmtime(_SRC3))):
         return _LIB
     objs = []
-    for tag, extra in (("r", []), ("z", ["-DORC_COMPLEX"])):
+    for tag, src, extra in (("r", _SRC, []), ("z", _SRC, ["-DORC_COMPLEX"]), ("3", _SRC3, [])):
         obj = os.path.join(_HERE, f"_lbm_oracle_{tag}.o")
         subprocess.run(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                        "-Wall", "-c", _SRC, "-o", obj] + extra, check=True)
+                        "-Wall", "-c", src, "-o", obj] + extra, check=True)
         objs.append(obj)
     tmp = _LIB + ".tmp"
     subprocess.run(["gcc", "-shared", "-o", tmp] + objs + ["-lm"], check=True)
@@ -75,6 +78,13 @@ def _load():
             getattr(lib, pre + "step").argtypes = [P, P, P, P, P, P, P, P, P]
             getattr(lib, pre + "run").argtypes = [P, P, i32, P, P, P, P, P, P, P]
             getattr(lib, pre + "apply_nee").argtypes = [P, P, P, P, P]
+        lib.orc3_lattice.argtypes = [P, P, P, P]
+        lib.orc3_equilibrium.argtypes = [dbl, P, dbl, P]
+        lib.orc3_collide.argtypes = [P, P, dbl, dbl, dbl, P]
+        lib.orc3_init.argtypes = [P, P, P, P]
+        lib.orc3_phi.argtypes = [P, P, P]
+        lib.orc3_step.argtypes = [P, P, P, P, P, P, P]
+        lib.orc3_run.argtypes = [P, P, i32, P, P, P, P, P]
         del zc
         _lib = lib
     return _lib
@@ -254,3 +264,101 @@ def l2_rel_error(phi_num, phi_ref) -> float:
 
 def max_abs_error(phi_num, phi_ref) -> float:
     return float(np.max(np.abs(np.asarray(phi_num, np.float64) - np.asarray(phi_ref, np.float64))))
+
+
+# ---- D3Q19 ----------------------------------------------------------------------------------------
+
+class _Problem3(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("dx", ctypes.c_double),
+                ("dt", ctypes.c_double), ("lambda_", ctypes.c_double), ("D_const", ctypes.c_double),
+                ("aux", ctypes.c_int)]
+
+
+@dataclass
+class Problem3:
+    """One periodic D3Q19 instance.  Arrays: populations g[19, nz, ny, nx]; u[3, nz, ny, nx];
+    scalar fields [nz, ny, nx]; node (j, k, l) is [l, k, j]."""
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dt: float
+    lam: float
+    D_const: float = 0.0
+    aux: int = AUX_LOCAL
+
+    def _c(self) -> _Problem3:
+        return _Problem3(self.nx, self.ny, self.nz, self.dx, self.dt, self.lam, self.D_const, self.aux)
+
+    @property
+    def c(self) -> float:
+        return self.dx / self.dt
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+
+def lattice3():
+    """(ex[19], ey[19], ez[19], w[19]) of the D3Q19 oracle (lattice units)."""
+    lib = _load()
+    e = [np.zeros(19, np.int32) for _ in range(3)]
+    w = np.zeros(19, np.float64)
+    lib.orc3_lattice(*(_ptr(a) for a in e), _ptr(w))
+    return tuple(a.astype(np.int64) for a in e) + (w,)
+
+
+def equilibrium3(phi: float, u, c: float) -> np.ndarray:
+    out = np.zeros(19)
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    _load().orc3_equilibrium(phi, _ptr(uu), c, _ptr(out))
+    return out
+
+
+def collide3(g, u, tau1: float, tau2: float, c: float) -> np.ndarray:
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(19)
+    _load().orc3_collide(_ptr(g), _ptr(uu), tau1, tau2, c, _ptr(out))
+    return out
+
+
+def _f3(p: Problem3, a):
+    return None if a is None else np.ascontiguousarray(np.broadcast_to(np.asarray(a, np.float64), p.shape))
+
+
+def _u3(p: Problem3, u):
+    return np.ascontiguousarray(np.broadcast_to(np.asarray(u, np.float64), (3,) + p.shape))
+
+
+def init3(p: Problem3, phi0, u) -> np.ndarray:
+    g = np.zeros((19,) + p.shape)
+    pc = p._c()
+    _load().orc3_init(ctypes.byref(pc), _ptr(_f3(p, phi0)), _ptr(_u3(p, u)), _ptr(g))
+    return g
+
+
+def phi3(p: Problem3, g) -> np.ndarray:
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    out = np.zeros(p.shape)
+    pc = p._c()
+    _load().orc3_phi(ctypes.byref(pc), _ptr(g), _ptr(out))
+    return out
+
+
+def step3(p: Problem3, g, u, D=None, S=None, dSdt=None) -> np.ndarray:
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    out = np.empty_like(g)
+    pc = p._c()
+    _load().orc3_step(ctypes.byref(pc), _ptr(g), _ptr(out), _ptr(_u3(p, u)), _ptr(_f3(p, D)), _ptr(_f3(p, S)),
+                      _ptr(_f3(p, dSdt)))
+    return out
+
+
+def run3(p: Problem3, g, nsteps: int, u, D=None, S=None, dSdt=None) -> np.ndarray:
+    g = np.array(g, dtype=np.float64, copy=True, order="C")
+    work = np.empty_like(g)
+    pc = p._c()
+    _load().orc3_run(ctypes.byref(pc), _ptr(g), int(nsteps), _ptr(_u3(p, u)), _ptr(_f3(p, D)), _ptr(_f3(p, S)),
+                     _ptr(_f3(p, dSdt)), _ptr(work))
+    return g

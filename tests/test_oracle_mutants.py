@@ -14,6 +14,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PINS = os.path.join(ROOT, "tests", "test_oracle_pins.py")
+PINS_D3Q19 = os.path.join(ROOT, "tests", "test_oracle_pins_d3q19.py")
 
 MUTANTS = [
     ("drop third-order equilibrium", "+ s3 / (6.0 * cs2 * cs2 * cs2)", ""),
@@ -56,6 +57,23 @@ MUTANTS = [
      "wrap(y - EY[i], ny) * nx + wrap(x - EX[i], nx)"),
 ]
 
+MUTANTS_D3Q19 = [
+    ("z velocity table", "static const int EZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};",
+     "static const int EZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1};"),
+    ("edge weight", "1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};",
+     "1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 18.0};"),
+    ("drop third-order equilibrium", "+ s3 / (6.0 * cs2 * cs2 * cs2)", ""),
+    ("tau2 from tau1", "(1.0 - 1.0 / tau2) * W[i] * r2", "(1.0 - 1.0 / tau1) * W[i] * r2"),
+    ("z difference neighbour", "lo[2] = ((size_t)wrap(z - 1, nz) * ny + y) * nx + x;",
+     "lo[2] = ((size_t)wrap(z + 1, nz) * ny + y) * nx + x;"),
+    ("aux without phi", "A[a] = phi * s;", "A[a] = s;"),
+    ("source without beta", "+ beta * W[i] * eu / cs2 * src;", "+ W[i] * eu / cs2 * src;"),
+    ("z streaming direction", "wrap(z + EZ[i], nz)", "wrap(z - EZ[i], nz)"),
+    ("tau1 from kappa", "const double tau1 = 0.5 + kappa / (cs2 * dt);", "const double tau1 = 0.5 + 2.0 * kappa / (cs2 * dt);"),
+    ("velocity components swapped", "const double un[3] = {u[n], u[N + n], u[2 * N + n]};",
+     "const double un[3] = {u[n], u[2 * N + n], u[N + n]};"),
+]
+
 _PLUGIN = '''
 import importlib.util, os, sys
 spec = importlib.util.spec_from_file_location("oracle", os.environ["MUTANT_ORACLE"])
@@ -65,18 +83,27 @@ spec.loader.exec_module(mod)
 '''
 
 
-@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_mutant_is_caught(name, old, new, tmp_path):
-    with open(os.path.join(ROOT, "oracle", "lbm_oracle.c")) as fh:
+def _run_mutant(name, old, new, tmp_path, source, pins):
+    with open(os.path.join(ROOT, "oracle", source)) as fh:
         src = fh.read()
     assert src.count(old) == 1, f"mutation site for '{name}' must be unique"
     mdir = tmp_path / "oracle"
     shutil.copytree(os.path.join(ROOT, "oracle"), mdir,
                     ignore=shutil.ignore_patterns("*.so", "*.o", "__pycache__"))
-    (mdir / "lbm_oracle.c").write_text(src.replace(old, new))
+    (mdir / source).write_text(src.replace(old, new))
     (tmp_path / "mutant_plugin.py").write_text(_PLUGIN)
     env = dict(os.environ, MUTANT_ORACLE=str(mdir / "__init__.py"), PYTHONPATH=str(tmp_path))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "mutant_plugin", "-p", "no:cacheprovider",
-                        PINS], cwd=str(tmp_path), env=env, capture_output=True, text=True, timeout=600)
+                        pins], cwd=str(tmp_path), env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, f"mutant '{name}' survived the pins:\n{r.stdout[-2000:]}"
     assert "FAILED" in r.stdout
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(name, old, new, tmp_path):
+    _run_mutant(name, old, new, tmp_path, "lbm_oracle.c", PINS)
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS_D3Q19, ids=[m[0] for m in MUTANTS_D3Q19])
+def test_d3q19_mutant_is_caught(name, old, new, tmp_path):
+    _run_mutant(name, old, new, tmp_path, "lbm_oracle_d3q19.c", PINS_D3Q19)
