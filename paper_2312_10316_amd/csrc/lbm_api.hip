@@ -62,6 +62,8 @@ Layout layout_of(const lbm_params &p)
     L.nx = p.nx;
     L.ny = p.ny;
     L.pitch = pitch_of(p);
+    L.nz = p.lattice == LBM_LATTICE_D3Q19 ? p.nz : 1;
+    L.q = p.lattice == LBM_LATTICE_D3Q19 ? 19 : 9;
     return L;
 }
 
@@ -79,7 +81,13 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 int validate(const lbm_params &p, int k)
 {
     if (p.nx < 3 || p.ny < 3) return fail(LBM_E_ARG, "instance %d: nx=%d, ny=%d must be >= 3", k, p.nx, p.ny);
-    if ((int64_t)p.nx * p.ny > ((int64_t)1 << 31)) return fail(LBM_E_ARG, "instance %d: nx*ny exceeds 2^31 nodes", k);
+    if (p.lattice != LBM_LATTICE_D2Q9 && p.lattice != LBM_LATTICE_D3Q19)
+        return fail(LBM_E_ARG, "instance %d: unknown lattice %d", k, p.lattice);
+    if (p.lattice == LBM_LATTICE_D2Q9 && p.nz != 0 && p.nz != 1)
+        return fail(LBM_E_ARG, "instance %d: nz=%d on a D2Q9 lattice (0 or 1)", k, p.nz);
+    if (p.lattice == LBM_LATTICE_D3Q19 && p.nz < 3) return fail(LBM_E_ARG, "instance %d: nz=%d must be >= 3", k, p.nz);
+    const int64_t nodes = (int64_t)p.nx * p.ny * (p.lattice == LBM_LATTICE_D3Q19 ? p.nz : 1);
+    if (nodes > ((int64_t)1 << 31)) return fail(LBM_E_ARG, "instance %d: more than 2^31 nodes", k);
     if (!finite_pos(p.dx) || !finite_pos(p.dt)) return fail(LBM_E_ARG, "instance %d: dx and dt must be finite and > 0", k);
     if (!finite_pos(p.lambda)) return fail(LBM_E_ARG, "instance %d: lambda must be finite and > 0", k);
     if (p.store < LBM_STORE_F64 || p.store > LBM_STORE_F16S) return fail(LBM_E_ARG, "instance %d: unknown store %d", k, p.store);
@@ -94,6 +102,12 @@ int validate(const lbm_params &p, int k)
         return fail(LBM_E_UNSUPPORTED, "instance %d: the flux form of the aux term is periodic only", k);
     if (p.tau3 != 0.0 && !(std::isfinite(p.tau3) && p.tau3 > 0.5))
         return fail(LBM_E_ARG, "instance %d: tau3 must be 0 (TRT-R) or finite and > 1/2", k);
+    if (p.lattice == LBM_LATTICE_D3Q19) {
+        if (p.store == LBM_STORE_F16S) return fail(LBM_E_UNSUPPORTED, "instance %d: no FP16 storage on D3Q19", k);
+        if (p.aux == LBM_AUX_FLUX) return fail(LBM_E_UNSUPPORTED, "instance %d: the flux form is D2Q9 only", k);
+        if (p.boundary != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "instance %d: D3Q19 is periodic only", k);
+        if (p.tau3 != 0.0 && p.tau3 != 1.0) return fail(LBM_E_UNSUPPORTED, "instance %d: no MRT-R on D3Q19", k);
+    }
     if (p.store == LBM_STORE_F16S) {
         if (p.scale_log2 < 0 || p.scale_log2 > 24)
             return fail(LBM_E_ARG, "instance %d: scale_log2=%d outside 0..24", k, p.scale_log2);
@@ -321,13 +335,17 @@ int prep_field(lbm_ctx *c, Instance &in, const double *a, const double *b, doubl
     return e == hipSuccess ? LBM_OK : hip_fail(e, "prep kernel launch");
 }
 
-int set_velocity(lbm_ctx *c, Instance &in, const double *ux, const double *uy)
+int set_velocity(lbm_ctx *c, Instance &in, const double *ux, const double *uy, const double *uz = nullptr)
 {
     const double s = in.p.dt / in.p.dx;  // lattice units: u dt / dx
-    int rc = prep_field(c, in, ux, nullptr, s, 0.0, in.u, 0, 2, 0);
-    if (rc == LBM_OK) rc = prep_field(c, in, uy, nullptr, s, 0.0, in.u, 0, 2, 1);
+    const int d = dim_of(in.L);
+    int rc = prep_field(c, in, ux, nullptr, s, 0.0, in.u, 0, d, 0);
+    if (rc == LBM_OK) rc = prep_field(c, in, uy, nullptr, s, 0.0, in.u, 0, d, 1);
+    if (rc == LBM_OK && d == 3) rc = prep_field(c, in, uz, nullptr, s, 0.0, in.u, 0, d, 2);
     return rc;
 }
+
+bool is3d(const Instance &in) { return in.L.q == 19; }
 
 // Enqueues one step of every instance on stream st.
 int enqueue_step(lbm_ctx *c, hipStream_t st)
@@ -345,7 +363,8 @@ int enqueue_step(lbm_ctx *c, hipStream_t st)
             StepArgs a;
             a.d = c->h_desc[k];
             a.parity = c->parity;
-            hipError_t e = launch_step(c->inst[k].mode, c->inst[k].p.aux, a, st);
+            hipError_t e = is3d(c->inst[k]) ? launch_step3(c->inst[k].mode, c->inst[k].p.aux, a, st)
+                                             : launch_step(c->inst[k].mode, c->inst[k].p.aux, a, st);
             if (e != hipSuccess) return hip_fail(e, "step kernel launch");
         }
     }
@@ -429,6 +448,7 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
     if (rc) return rc;
     for (int k = 0; k < n_inst; ++k) {
         if (!f[k].phi0 || !f[k].ux || !f[k].uy) return fail(LBM_E_ARG, "instance %d: phi0, ux and uy are required", k);
+        if (p[k].lattice == LBM_LATTICE_D3Q19 && !f[k].uz) return fail(LBM_E_ARG, "instance %d: uz is required on D3Q19", k);
         if (!f[k].D && !finite_pos(p[k].D_const))
             return fail(LBM_E_ARG, "instance %d: D_const must be finite and > 0 when D is NULL", k);
     }
@@ -481,8 +501,8 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
         in.step = 0;
         in.f16 = f16_of(p[k]);
         if (in.mode != c->inst[0].mode || in.p.aux != c->inst[0].p.aux || in.p.boundary != LBM_BC_PERIODIC ||
-            (in.p.tau3 != 0.0 && in.p.tau3 != 1.0))
-            c->uniform = false;  // batched launches cover periodic TRT-R instances of one storage/aux form
+            (in.p.tau3 != 0.0 && in.p.tau3 != 1.0) || in.p.lattice != LBM_LATTICE_D2Q9)
+            c->uniform = false;  // batched launches cover periodic D2Q9 TRT-R instances of one storage/aux form
     }
     const size_t items = max_items_of(n_inst, p);
     c->d_desc = reinterpret_cast<InstDesc *>(w);
@@ -501,7 +521,7 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
     }
     for (int k = 0; k < n_inst && rc == LBM_OK; ++k) {
         Instance &in = c->inst[k];
-        rc = set_velocity(c, in, f[k].ux, f[k].uy);
+        rc = set_velocity(c, in, f[k].ux, f[k].uy, f[k].uz);
         if (rc == LBM_OK && in.has_D)  // k = tau1 - 1/2 = kappa / (cs^2 dt) = 3 kappa dt / dx^2
             rc = prep_field(c, in, f[k].D, nullptr, 3.0 * in.p.dt / (in.p.dx * in.p.dx), 0.0, in.k, 1);
         if (rc == LBM_OK && in.bc)  // Dirichlet (edge or wall) values start as phi0's
@@ -515,7 +535,7 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
             ia.f16 = in.f16;
             ia.range_flag = c->flag;
             ia.walls = in.p.boundary == LBM_BC_WALLS ? 1 : 0;
-            e = launch_init(in.mode, ia, c->stream);
+            e = is3d(in) ? launch_init3(in.mode, ia, c->stream) : launch_init(in.mode, ia, c->stream);
             if (e != hipSuccess) rc = hip_fail(e, "init kernel launch");
         }
     }
@@ -549,8 +569,10 @@ int lbm_step(lbm_ctx *c, int32_t nsteps, const double *const *ux, const double *
     if (!S && dSdt) return fail(LBM_E_ARG, "lbm_step: dSdt without S");
     const int n = (int)c->inst.size();
     if (ux)
-        for (int k = 0; k < n; ++k)
+        for (int k = 0; k < n; ++k) {
             if (!ux[k] || !uy[k]) return fail(LBM_E_ARG, "lbm_step: instance %d: NULL velocity entry", k);
+            if (is3d(c->inst[k])) return fail(LBM_E_ARG, "lbm_step: instance %d is D3Q19: use lbm_set_velocity", k);
+        }
     int rc = LBM_OK;
     bool changed = false;
     for (int k = 0; k < n && rc == LBM_OK; ++k) {
@@ -598,13 +620,14 @@ int lbm_macros(lbm_ctx *c, int32_t inst, double *phi_out, const double *ref, lbm
     a.edge.bc = in.bc;
     a.edge.kind = in.p.boundary;
     a.partials = c->partials;
-    hipError_t e = launch_macros(in.mode, a, c->result, c->stream);
+    hipError_t e = is3d(in) ? launch_macros3(in.mode, a, c->result, c->stream)
+                            : launch_macros(in.mode, a, c->result, c->stream);
     if (e != hipSuccess) return hip_fail(e, "macros kernel launch");
     double r[6];
     e = hipMemcpyAsync(r, c->result, sizeof r, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "lbm_macros: reading the result");
-    const double nn = (double)in.L.nx * in.L.ny;
+    const double nn = (double)in.L.nx * in.L.ny * in.L.nz;
     out->mass = r[0];
     out->rms_err = ref ? std::sqrt(r[1] / nn) : 0.0;
     out->l2_rel_err = (ref && r[2] > 0) ? std::sqrt(r[1] / r[2]) : 0.0;
@@ -615,6 +638,15 @@ int lbm_macros(lbm_ctx *c, int32_t inst, double *phi_out, const double *ref, lbm
     if (out->nonfinite > 0)
         return fail(LBM_E_NONFINITE, "instance %d: %lld non-finite phi values (blow-up)", inst, (long long)out->nonfinite);
     return LBM_OK;
+}
+
+int lbm_set_velocity(lbm_ctx *c, int32_t inst, const double *ux, const double *uy, const double *uz)
+{
+    g_err[0] = 0;
+    if (!check_inst(c, inst)) return fail(LBM_E_STATE, "lbm_set_velocity: bad context or instance %d", inst);
+    Instance &in = c->inst[inst];
+    if (!ux || !uy || (is3d(in) && !uz)) return fail(LBM_E_ARG, "lbm_set_velocity: a velocity component is NULL");
+    return set_velocity(c, in, ux, uy, uz);
 }
 
 int lbm_set_dirichlet(lbm_ctx *c, int32_t inst, const double *phi_b)
@@ -641,7 +673,7 @@ int lbm_populations(lbm_ctx *c, int32_t inst, double *g_out)
     a.edge.u = in.u;
     a.edge.bc = in.bc;
     a.edge.kind = in.p.boundary;
-    hipError_t e = launch_populations(in.mode, a, c->stream);
+    hipError_t e = is3d(in) ? launch_populations3(in.mode, a, c->stream) : launch_populations(in.mode, a, c->stream);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "populations kernel launch");
 }
 
@@ -733,6 +765,7 @@ int adjoint_ok(lbm_ctx *c, int32_t inst, const char *who)
     if (in.p.aux == LBM_AUX_FLUX) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for the flux form of the aux term", who);
     if (in.p.boundary != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for Dirichlet edges or walls", who);
     if (in.p.tau3 != 0.0 && in.p.tau3 != 1.0) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for the MRT-R operator", who);
+    if (is3d(in)) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint on D3Q19", who);
     return LBM_OK;
 }
 }  // namespace

@@ -5,6 +5,8 @@
 //   populations  [ny][9][pitch]   element (i, y, x) at (y*9 + i)*pitch + x   ("row-interleaved")
 //   velocity     [ny][2][pitch]   u_x at (y*2)*pitch + x, u_y at (y*2 + 1)*pitch + x
 //   k, s         [ny][pitch]      scalar fields at y*pitch + x
+// A D3Q19 instance has ny*nz rows, row r = z*ny + y: populations [nz][ny][19][pitch], velocity
+// [nz][ny][3][pitch], k and s [nz][ny][pitch].
 // pitch = nx rounded up to a multiple of 64 elements, so every row segment starts 128-byte aligned for
 // every element size.  Keeping the nine segments of one lattice row next to each other turns the 18
 // concurrent streams of a step (9 reads at rows y-1, y, y+1 and 9 writes at row y) into accesses to
@@ -31,11 +33,15 @@ enum Mode : int {
 struct Layout {
     int32_t nx, ny;
     int64_t pitch;  // elements per row segment (multiple of 64)
+    int32_t nz;     // 1 for D2Q9
+    int32_t q;      // velocities: 9 (D2Q9) or 19 (D3Q19)
 };
 
-__host__ __device__ __forceinline__ int64_t pop_elems(const Layout &L) { return (int64_t)L.ny * 9 * L.pitch; }
-__host__ __device__ __forceinline__ int64_t vel_elems(const Layout &L) { return (int64_t)L.ny * 2 * L.pitch; }
-__host__ __device__ __forceinline__ int64_t fld_elems(const Layout &L) { return (int64_t)L.ny * L.pitch; }
+__host__ __device__ __forceinline__ int64_t rows_of(const Layout &L) { return (int64_t)L.ny * L.nz; }
+__host__ __device__ __forceinline__ int dim_of(const Layout &L) { return L.q == 19 ? 3 : 2; }
+__host__ __device__ __forceinline__ int64_t pop_elems(const Layout &L) { return rows_of(L) * L.q * L.pitch; }
+__host__ __device__ __forceinline__ int64_t vel_elems(const Layout &L) { return rows_of(L) * dim_of(L) * L.pitch; }
+__host__ __device__ __forceinline__ int64_t fld_elems(const Layout &L) { return rows_of(L) * L.pitch; }
 
 // Launch shape of the step kernel: a block is 4 waves of 64 lanes; lane = column, each wave walks
 // `rows` consecutive rows; tiles of 64 columns x 4*rows rows.
@@ -83,7 +89,7 @@ struct BatchArgs {
 // Number of 64-column x (4 * rows)-row tiles of one instance.
 __host__ __device__ __forceinline__ int tiles_of(const Layout &L, int rows)
 {
-    const int waves_y = (L.ny + rows - 1) / rows;
+    const int waves_y = (int)((rows_of(L) + rows - 1) / rows);
     return ((L.nx + 63) / 64) * ((waves_y + 3) / 4);
 }
 
@@ -158,9 +164,15 @@ hipError_t launch_batched_step(int mode, int aux, const BatchArgs &a, int nblock
 hipError_t launch_init(int mode, const InitArgs &a, hipStream_t st);
 hipError_t launch_prep(int mode, const PrepArgs &a, hipStream_t st);
 hipError_t launch_macros(int mode, const MacroArgs &a, double *result, hipStream_t st);
+hipError_t launch_macros_finalize(const double *partials, int nblocks, double *result, hipStream_t st);
 hipError_t launch_populations(int mode, const PopArgs &a, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
 hipError_t launch_adjoint(int mode, int aux, const AdjArgs &a, hipStream_t st);
+// D3Q19 (lbm_kernels3d.hip): storage modes F64_F64, F64_F32, F32_F32; aux LOCAL or NONE; periodic.
+hipError_t launch_step3(int mode, int aux, const StepArgs &a, hipStream_t st);
+hipError_t launch_init3(int mode, const InitArgs &a, hipStream_t st);
+hipError_t launch_macros3(int mode, const MacroArgs &a, double *result, hipStream_t st);
+hipError_t launch_populations3(int mode, const PopArgs &a, hipStream_t st);
 hipError_t launch_adjoint_seed(int mode, const double *dphi, void *lam, const Layout &L, hipStream_t st);
 hipError_t launch_adjoint_init(int mode, const void *lam, const void *u, double *dphi0, const Layout &L, hipStream_t st);
 

@@ -1,0 +1,108 @@
+// lbm_kernel_common.h -- device helpers shared by the D2Q9 and D3Q19 kernel files: storage/math
+// traits, wave-uniform addressing, the XCD-aware tile order and the compensated block reduction.
+#pragma once
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+template <int MODE>
+struct ModeTraits;
+template <>
+struct ModeTraits<MODE_F64_F64> {
+    using St = StoreF64;
+    using M = double;
+};
+template <>
+struct ModeTraits<MODE_F64_F32> {
+    using St = StoreF64;
+    using M = float;
+};
+template <>
+struct ModeTraits<MODE_F32_F32> {
+    using St = StoreF32;
+    using M = float;
+};
+template <>
+struct ModeTraits<MODE_F16S_F32> {
+    using St = StoreF16S;
+    using M = float;
+};
+
+__device__ __forceinline__ int wrap_dec(int v, int n) { return v == 0 ? n - 1 : v - 1; }
+__device__ __forceinline__ int wrap_inc(int v, int n) { return v == n - 1 ? 0 : v + 1; }
+
+// Element at a 32-bit byte offset from a wave-uniform base: lets the compiler use the scalar-base +
+// 32-bit-lane-offset addressing form instead of per-lane 64-bit address arithmetic.
+template <class T>
+__device__ __forceinline__ T ld_at(const T *base, unsigned byte_off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void st_nt_at(T *base, unsigned byte_off, T v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off));
+}
+
+// Block b -> tile t.  With xcd_remap the hardware's round-robin of blocks over the 8 XCDs
+// (block b runs on XCD b % 8) is inverted so that XCD j works on one contiguous range of tiles.
+__device__ __forceinline__ int tile_of_block(int b, int nb, int remap)
+{
+    if (!remap) return b;
+    const int q = nb >> 3, r = nb & 7, j = b & 7;
+    return j * q + min(j, r) + (b >> 3);
+}
+
+// ---- diagnostics ------------------------------------------------------------------------------
+
+__device__ __forceinline__ CSum csum_shfl_xor(CSum v, int m)
+{
+    CSum o;
+    o.s = __shfl_xor(v.s, m);
+    o.c = __shfl_xor(v.c, m);
+    return o;
+}
+
+// Reduces (3 compensated sums, 2 maxima, 1 count) over the block; thread 0 gets the result.
+// Within a wave: butterfly shuffles with TwoSum merges; across the 4 waves: LDS.
+__device__ inline void block_reduce(CSum (&cs)[3], double &mx0, double &mx1, double &cnt)
+{
+    __shared__ double sh[4][10];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) cs[k] = csum_merge(cs[k], csum_shfl_xor(cs[k], m));
+        mx0 = fmax(mx0, __shfl_xor(mx0, m));
+        mx1 = fmax(mx1, __shfl_xor(mx1, m));
+        cnt += __shfl_xor(cnt, m);
+    }
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (lane == 0) {
+        for (int k = 0; k < 3; ++k) {
+            sh[wave][2 * k] = cs[k].s;
+            sh[wave][2 * k + 1] = cs[k].c;
+        }
+        sh[wave][6] = mx0;
+        sh[wave][7] = mx1;
+        sh[wave][8] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x / 64); ++w) {
+            for (int k = 0; k < 3; ++k) cs[k] = csum_merge(cs[k], CSum{sh[w][2 * k], sh[w][2 * k + 1]});
+            mx0 = fmax(mx0, sh[w][6]);
+            mx1 = fmax(mx1, sh[w][7]);
+            cnt += sh[w][8];
+        }
+    }
+}
+
+inline int grid_for(int64_t n, int block, int cap)
+{
+    int64_t g = (n + block - 1) / block;
+    if (g > cap) g = cap;
+    return (int)(g < 1 ? 1 : g);
+}
+
+}  // namespace lbm

@@ -12,48 +12,12 @@
 // each wave walks a few rows so the velocity stencil's y-neighbours stay in registers, stores are
 // non-temporal, and the tile order can be remapped so neighbouring tiles share an XCD's L2.
 #include "lbm_internal.h"
+#include "lbm_kernel_common.h"
 
 namespace lbm {
 namespace {
 
-template <int MODE>
-struct ModeTraits;
-template <>
-struct ModeTraits<MODE_F64_F64> {
-    using St = StoreF64;
-    using M = double;
-};
-template <>
-struct ModeTraits<MODE_F64_F32> {
-    using St = StoreF64;
-    using M = float;
-};
-template <>
-struct ModeTraits<MODE_F32_F32> {
-    using St = StoreF32;
-    using M = float;
-};
-template <>
-struct ModeTraits<MODE_F16S_F32> {
-    using St = StoreF16S;
-    using M = float;
-};
 
-__device__ __forceinline__ int wrap_dec(int v, int n) { return v == 0 ? n - 1 : v - 1; }
-__device__ __forceinline__ int wrap_inc(int v, int n) { return v == n - 1 ? 0 : v + 1; }
-
-// Element at a 32-bit byte offset from a wave-uniform base: lets the compiler use the scalar-base +
-// 32-bit-lane-offset addressing form instead of per-lane 64-bit address arithmetic.
-template <class T>
-__device__ __forceinline__ T ld_at(const T *base, unsigned byte_off)
-{
-    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
-}
-template <class T>
-__device__ __forceinline__ void st_nt_at(T *base, unsigned byte_off, T v)
-{
-    __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off));
-}
 
 // g_i(x, y) = buf_i(x - e_i).  rm, rc, rp: the row blocks (9 segments) of rows y-1, y, y+1 (wrapped);
 // xm, xp: columns x-1, x+1 (wrapped).
@@ -162,14 +126,6 @@ __device__ __forceinline__ M phi_at(const typename St::T *__restrict__ src, cons
     return g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
 }
 
-// Block b -> tile t.  With xcd_remap the hardware's round-robin of blocks over the 8 XCDs
-// (block b runs on XCD b % 8) is inverted so that XCD j works on one contiguous range of tiles.
-__device__ __forceinline__ int tile_of_block(int b, int nb, int remap)
-{
-    if (!remap) return b;
-    const int q = nb >> 3, r = nb & 7, j = b & 7;
-    return j * q + min(j, r) + (b >> 3);
-}
 
 
 // One tile of one step with the local auxiliary term (or none).  Block (64, 4): lane = column of a
@@ -458,11 +414,12 @@ template <class M>
 __global__ __launch_bounds__(256) void prep_kernel(const PrepArgs a)
 {
     const int nx = a.L.nx;
-    const int64_t N = (int64_t)nx * a.L.ny;
+    const int64_t N = (int64_t)nx * rows_of(a.L);
     M *out = static_cast<M *>(a.out);
     bool bad = false;
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(n % nx), y = (int)(n / nx);
+        const int x = (int)(n % nx);
+        const int64_t y = n / nx;  // row: y, or z*ny + y on D3Q19
         double v = a.ca * a.a[n];
         if (a.b) v += a.cb * a.b[n];
         if (a.check_positive) bad |= !(v > 0.0 && v < INFINITY);
@@ -472,48 +429,6 @@ __global__ __launch_bounds__(256) void prep_kernel(const PrepArgs a)
 }
 
 // ---- diagnostics -------------------------------------------------------------------------------
-
-__device__ __forceinline__ CSum csum_shfl_xor(CSum v, int m)
-{
-    CSum o;
-    o.s = __shfl_xor(v.s, m);
-    o.c = __shfl_xor(v.c, m);
-    return o;
-}
-
-// Reduces (3 compensated sums, 2 maxima, 1 count) over the block; thread 0 gets the result.
-// Within a wave: butterfly shuffles with TwoSum merges; across the 4 waves: LDS.
-__device__ void block_reduce(CSum (&cs)[3], double &mx0, double &mx1, double &cnt)
-{
-    __shared__ double sh[4][10];
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) cs[k] = csum_merge(cs[k], csum_shfl_xor(cs[k], m));
-        mx0 = fmax(mx0, __shfl_xor(mx0, m));
-        mx1 = fmax(mx1, __shfl_xor(mx1, m));
-        cnt += __shfl_xor(cnt, m);
-    }
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    if (lane == 0) {
-        for (int k = 0; k < 3; ++k) {
-            sh[wave][2 * k] = cs[k].s;
-            sh[wave][2 * k + 1] = cs[k].c;
-        }
-        sh[wave][6] = mx0;
-        sh[wave][7] = mx1;
-        sh[wave][8] = cnt;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < (int)(blockDim.x / 64); ++w) {
-            for (int k = 0; k < 3; ++k) cs[k] = csum_merge(cs[k], CSum{sh[w][2 * k], sh[w][2 * k + 1]});
-            mx0 = fmax(mx0, sh[w][6]);
-            mx1 = fmax(mx1, sh[w][7]);
-            cnt += sh[w][8];
-        }
-    }
-}
 
 template <int MODE>
 __global__ __launch_bounds__(256) void macros_kernel(const MacroArgs a)
@@ -608,12 +523,6 @@ __global__ __launch_bounds__(256) void copy_kernel(const f32x4 *__restrict__ src
     if (i < n) __builtin_nontemporal_store(src[i], dst + i);
 }
 
-int grid_for(int64_t n, int block, int cap)
-{
-    int64_t g = (n + block - 1) / block;
-    if (g > cap) g = cap;
-    return (int)(g < 1 ? 1 : g);
-}
 
 template <int MODE, int AUX, int BC, bool MRT>
 hipError_t launch_step_var(const StepArgs &a, hipStream_t st)
@@ -714,7 +623,7 @@ hipError_t launch_init(int mode, const InitArgs &a, hipStream_t st)
 
 hipError_t launch_prep(int mode, const PrepArgs &a, hipStream_t st)
 {
-    const int g = grid_for((int64_t)a.L.nx * a.L.ny, 256, 8192);
+    const int g = grid_for((int64_t)a.L.nx * rows_of(a.L), 256, 8192);
     if (mode == MODE_F64_F64) prep_kernel<double><<<g, 256, 0, st>>>(a);
     else prep_kernel<float><<<g, 256, 0, st>>>(a);
     return hipGetLastError();
@@ -732,7 +641,12 @@ hipError_t launch_macros(int mode, const MacroArgs &a, double *result, hipStream
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    macros_finalize<<<1, 256, 0, st>>>(a.partials, g, result);
+    return launch_macros_finalize(a.partials, g, result, st);
+}
+
+hipError_t launch_macros_finalize(const double *partials, int nblocks, double *result, hipStream_t st)
+{
+    macros_finalize<<<1, 256, 0, st>>>(partials, nblocks, result);
     return hipGetLastError();
 }
 

@@ -1,0 +1,407 @@
+// lbm_kernels3d.hip -- HIP kernels of the TRT-R step on the D3Q19 lattice for gfx950 (the
+// three-dimensional extension of Sec. 2.2).
+//
+// Velocities (lattice units), in this order: 0:(0,0,0); 1,2:(+-1,0,0); 3,4:(0,+-1,0); 5,6:(0,0,+-1);
+// 7:(1,1,0) 8:(-1,-1,0) 9:(1,-1,0) 10:(-1,1,0); 11:(1,0,1) 12:(-1,0,-1) 13:(1,0,-1) 14:(-1,0,1);
+// 15:(0,1,1) 16:(0,-1,-1) 17:(0,1,-1) 18:(0,-1,1); weights 1/3, 1/18, 1/36; i and i + 1 (odd i) are
+// opposite.  One step of Eq. (14) in moment form (c_s^2 = 1/3):
+//
+//   P_i = w_i [ a0 + 3 e_i.a1 + 9/2 (e_i.a2.e_i - tr a2 / 3) + 9/2 phi ((e_i.u)^3 - (e_i.u) |u|^2) ]
+//
+// with a0 = phi + s, a1 = phi u + w1 (j - phi u) + beta (A + u s), a2 = phi u u + w2 (Pi - phi I/3
+// - phi u u) exactly as on D2Q9 (Eqs. (3), (8), (12), (13), (16)), and the last term H3 : phi u u u,
+// the third-order part of the equilibrium (Eq. (6)) contracted in closed form; on D3Q19 the tensors
+// H_xxx and H_xyz vanish, so it carries exactly the xxy-type components the lattice supports.
+//
+// Layout: row r = z*ny + y holds the 19 segments of that lattice row; a wave owns one row of a
+// 64-column tile, so the row bases of the nine rows (y, z), (y+-1, z), (y, z+-1), (y+-1, z+-1) it
+// pulls from are wave-uniform scalars and every access is base + 32-bit lane offset.  Stores are
+// non-temporal and tiles follow the XCD-contiguous order of the D2Q9 kernels.
+#include "lbm_internal.h"
+#include "lbm_kernel_common.h"
+
+namespace lbm {
+namespace {
+
+constexpr int kQ3 = 19;
+constexpr int kEx3[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int kEy3[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int kEz3[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+template <class M>
+struct Coef3 {
+    M a0, a1x, a1y, a1z, axx, ayy, azz, axy, axz, ayz;  // post-collision Hermite coefficients
+    M phi, ux, uy, uz;                                  // for the third-order equilibrium term
+};
+
+template <class M>
+__device__ __forceinline__ void reconstruct3(const Coef3<M> &c, M (&P)[19])
+{
+    const M usq = c.ux * c.ux + c.uy * c.uy + c.uz * c.uz;
+    const M base = c.a0 - M(1.5) * (c.axx + c.ayy + c.azz);
+    P[0] = M(1.0 / 3.0) * base;
+    auto pair = [&](int i, M w, M eu, M ea, M eae) {
+        const M ev = w * (base + M(4.5) * eae);
+        const M od = w * (M(3) * ea + M(4.5) * c.phi * eu * (eu * eu - usq));
+        P[i] = ev + od;
+        P[i + 1] = ev - od;
+    };
+    const M wa = M(1.0 / 18.0), wd = M(1.0 / 36.0);
+    pair(1, wa, c.ux, c.a1x, c.axx);
+    pair(3, wa, c.uy, c.a1y, c.ayy);
+    pair(5, wa, c.uz, c.a1z, c.azz);
+    pair(7, wd, c.ux + c.uy, c.a1x + c.a1y, c.axx + c.ayy + M(2) * c.axy);
+    pair(9, wd, c.ux - c.uy, c.a1x - c.a1y, c.axx + c.ayy - M(2) * c.axy);
+    pair(11, wd, c.ux + c.uz, c.a1x + c.a1z, c.axx + c.azz + M(2) * c.axz);
+    pair(13, wd, c.ux - c.uz, c.a1x - c.a1z, c.axx + c.azz - M(2) * c.axz);
+    pair(15, wd, c.uy + c.uz, c.a1y + c.a1z, c.ayy + c.azz + M(2) * c.ayz);
+    pair(17, wd, c.uy - c.uz, c.a1y - c.a1z, c.ayy + c.azz - M(2) * c.ayz);
+}
+
+template <class M>
+__device__ __forceinline__ void equilibrium3(M phi, M ux, M uy, M uz, M (&P)[19])
+{
+    Coef3<M> c;
+    c.a0 = phi;
+    c.a1x = phi * ux;
+    c.a1y = phi * uy;
+    c.a1z = phi * uz;
+    c.axx = c.a1x * ux;
+    c.ayy = c.a1y * uy;
+    c.azz = c.a1z * uz;
+    c.axy = c.a1x * uy;
+    c.axz = c.a1x * uz;
+    c.ayz = c.a1y * uz;
+    c.phi = phi;
+    c.ux = ux;
+    c.uy = uy;
+    c.uz = uz;
+    reconstruct3<M>(c, P);
+}
+
+// TRT-R collision plus source and auxiliary term (A = phi u.grad u, lattice units).
+template <class M>
+__device__ __forceinline__ void collide3(const M (&g)[19], M ux, M uy, M uz, const Relax<M> &r, M Ax, M Ay, M Az,
+                                         M s, M (&P)[19])
+{
+    M phi = g[0];
+#pragma unroll
+    for (int i = 1; i < 19; ++i) phi += g[i];
+    const M jx = (g[1] - g[2]) + (g[7] - g[8]) + (g[9] - g[10]) + (g[11] - g[12]) + (g[13] - g[14]);
+    const M jy = (g[3] - g[4]) + (g[7] - g[8]) - (g[9] - g[10]) + (g[15] - g[16]) + (g[17] - g[18]);
+    const M jz = (g[5] - g[6]) + (g[11] - g[12]) - (g[13] - g[14]) + (g[15] - g[16]) - (g[17] - g[18]);
+    const M sxy = (g[7] + g[8]) + (g[9] + g[10]);
+    const M sxz = (g[11] + g[12]) + (g[13] + g[14]);
+    const M syz = (g[15] + g[16]) + (g[17] + g[18]);
+    const M pxx = (g[1] + g[2]) + sxy + sxz;
+    const M pyy = (g[3] + g[4]) + sxy + syz;
+    const M pzz = (g[5] + g[6]) + sxz + syz;
+    const M pxy = (g[7] + g[8]) - (g[9] + g[10]);
+    const M pxz = (g[11] + g[12]) - (g[13] + g[14]);
+    const M pyz = (g[15] + g[16]) - (g[17] + g[18]);
+    const M pux = phi * ux, puy = phi * uy, puz = phi * uz, third = phi * M(1.0 / 3.0);
+    Coef3<M> c;
+    c.a0 = phi + s;
+    c.a1x = pux + r.w1 * (jx - pux) + r.beta * (Ax + ux * s);
+    c.a1y = puy + r.w1 * (jy - puy) + r.beta * (Ay + uy * s);
+    c.a1z = puz + r.w1 * (jz - puz) + r.beta * (Az + uz * s);
+    const M exx = pux * ux, eyy = puy * uy, ezz = puz * uz, exy = pux * uy, exz = pux * uz, eyz = puy * uz;
+    c.axx = exx + r.w2 * (pxx - third - exx);
+    c.ayy = eyy + r.w2 * (pyy - third - eyy);
+    c.azz = ezz + r.w2 * (pzz - third - ezz);
+    c.axy = exy + r.w2 * (pxy - exy);
+    c.axz = exz + r.w2 * (pxz - exz);
+    c.ayz = eyz + r.w2 * (pyz - eyz);
+    c.phi = phi;
+    c.ux = ux;
+    c.uy = uy;
+    c.uz = uz;
+    reconstruct3<M>(c, P);
+}
+
+// g_i(x, y, z) = buf_i(x - e_i) for one node (diagnostics).
+template <class St, class M>
+__device__ __forceinline__ void pull_node3(const typename St::T *__restrict__ src, const Layout &L, int x, int y, int z,
+                                           M (&g)[19])
+{
+    using C = Codec<St, M>;
+    const F16Params none{};
+#pragma unroll
+    for (int i = 0; i < kQ3; ++i) {
+        int xs = x - kEx3[i], ys = y - kEy3[i], zs = z - kEz3[i];
+        xs = xs < 0 ? xs + L.nx : (xs >= L.nx ? xs - L.nx : xs);
+        ys = ys < 0 ? ys + L.ny : (ys >= L.ny ? ys - L.ny : ys);
+        zs = zs < 0 ? zs + L.nz : (zs >= L.nz ? zs - L.nz : zs);
+        g[i] = C::dec(src[(((int64_t)zs * L.ny + ys) * kQ3 + i) * L.pitch + xs], i, none);
+    }
+}
+
+template <int MODE, int AUX, bool HAS_K, bool HAS_S>
+__global__ __launch_bounds__(256) void step3_kernel(const StepArgs sa)
+{
+    using St = typename ModeTraits<MODE>::St;
+    using M = typename ModeTraits<MODE>::M;
+    using T = typename St::T;
+    using C = Codec<St, M>;
+    const InstDesc &a = sa.d;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int t = tile_of_block(blockIdx.x, gridDim.x, a.lc.xcd_remap);
+    const int nx = a.L.nx, ny = a.L.ny, nz = a.L.nz;
+    const int R = ny * nz;
+    const int64_t pitch = a.L.pitch;
+    const int rows = a.lc.rows;
+    const int ntx = (nx + 63) >> 6;
+    const unsigned x = (unsigned)((t % ntx) * 64) + threadIdx.x;
+    const int r0 = ((t / ntx) * 4 + wave) * rows;
+    if (r0 >= R) return;
+    const bool live = x < (unsigned)nx;
+    const unsigned xc = live ? x : 0u;  // dead lanes of a ragged tile read column 0 and store nothing
+    const unsigned xm = xc == 0 ? (unsigned)nx - 1 : xc - 1;
+    const unsigned xp = xc == (unsigned)nx - 1 ? 0u : xc + 1;
+    const unsigned bc = xc * (unsigned)sizeof(T), bm = xm * (unsigned)sizeof(T), bp = xp * (unsigned)sizeof(T);
+    const unsigned fc = xc * (unsigned)sizeof(M), fm = xm * (unsigned)sizeof(M), fp = xp * (unsigned)sizeof(M);
+    const T *__restrict__ src = static_cast<const T *>(a.buf[sa.parity]);
+    T *__restrict__ dst = static_cast<T *>(a.buf[sa.parity ^ 1]);
+    const M *__restrict__ u = static_cast<const M *>(a.u);
+    const M *__restrict__ kf = static_cast<const M *>(a.k);
+    const M *__restrict__ sf = static_cast<const M *>(a.s);
+    Relax<M> rconst;
+    rconst.w1 = (M)a.w1;
+    rconst.w2 = (M)a.w2;
+    rconst.beta = (M)a.beta;
+    rconst.w3 = M(0);
+    const int r1 = min(r0 + rows, R);
+    for (int r = r0; r < r1; ++r) {
+        const int z = r / ny, y = r - z * ny;
+        const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny), zm = wrap_dec(z, nz), zp = wrap_inc(z, nz);
+        auto blk = [&](int yy, int zz) { return src + ((int64_t)zz * ny + yy) * kQ3 * pitch; };
+        const T *__restrict__ b00 = blk(y, z);
+        const T *__restrict__ bm0 = blk(ym, z);
+        const T *__restrict__ bp0 = blk(yp, z);
+        const T *__restrict__ b0m = blk(y, zm);
+        const T *__restrict__ b0p = blk(y, zp);
+        const F16Params &f = a.f16;
+        M g[19];
+        g[0] = C::dec(ld_at(b00, bc), 0, f);
+        g[1] = C::dec(ld_at(b00 + 1 * pitch, bm), 1, f);
+        g[2] = C::dec(ld_at(b00 + 2 * pitch, bp), 2, f);
+        g[3] = C::dec(ld_at(bm0 + 3 * pitch, bc), 3, f);
+        g[4] = C::dec(ld_at(bp0 + 4 * pitch, bc), 4, f);
+        g[5] = C::dec(ld_at(b0m + 5 * pitch, bc), 5, f);
+        g[6] = C::dec(ld_at(b0p + 6 * pitch, bc), 6, f);
+        g[7] = C::dec(ld_at(bm0 + 7 * pitch, bm), 7, f);
+        g[8] = C::dec(ld_at(bp0 + 8 * pitch, bp), 8, f);
+        g[9] = C::dec(ld_at(bp0 + 9 * pitch, bm), 9, f);
+        g[10] = C::dec(ld_at(bm0 + 10 * pitch, bp), 10, f);
+        g[11] = C::dec(ld_at(b0m + 11 * pitch, bm), 11, f);
+        g[12] = C::dec(ld_at(b0p + 12 * pitch, bp), 12, f);
+        g[13] = C::dec(ld_at(b0p + 13 * pitch, bm), 13, f);
+        g[14] = C::dec(ld_at(b0m + 14 * pitch, bp), 14, f);
+        g[15] = C::dec(ld_at(blk(ym, zm) + 15 * pitch, bc), 15, f);
+        g[16] = C::dec(ld_at(blk(yp, zp) + 16 * pitch, bc), 16, f);
+        g[17] = C::dec(ld_at(blk(ym, zp) + 17 * pitch, bc), 17, f);
+        g[18] = C::dec(ld_at(blk(yp, zm) + 18 * pitch, bc), 18, f);
+
+        auto vrow = [&](int yy, int zz) { return u + ((int64_t)zz * ny + yy) * 3 * pitch; };
+        const M *__restrict__ uc = vrow(y, z);
+        const M ux = ld_at(uc, fc), uy = ld_at(uc + pitch, fc), uz = ld_at(uc + 2 * pitch, fc);
+        M Ax = M(0), Ay = M(0), Az = M(0);
+        if (AUX == 0) {  // Eq. (16): phi u_b d_b u_a, central differences of u
+            M phi = g[0];
+#pragma unroll
+            for (int i = 1; i < 19; ++i) phi += g[i];
+            const M *__restrict__ uym = vrow(ym, z), *__restrict__ uyp = vrow(yp, z);
+            const M *__restrict__ uzm = vrow(y, zm), *__restrict__ uzp = vrow(y, zp);
+            M dd[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const M dxc = ld_at(uc + c * pitch, fp) - ld_at(uc + c * pitch, fm);
+                const M dyc = ld_at(uyp + c * pitch, fc) - ld_at(uym + c * pitch, fc);
+                const M dzc = ld_at(uzp + c * pitch, fc) - ld_at(uzm + c * pitch, fc);
+                dd[c] = M(0.5) * (ux * dxc + uy * dyc + uz * dzc);
+            }
+            Ax = phi * dd[0];
+            Ay = phi * dd[1];
+            Az = phi * dd[2];
+        }
+        const Relax<M> rr = HAS_K ? relax_from_k<M>(ld_at(kf + (int64_t)r * pitch, fc), (M)a.lambda, M(0)) : rconst;
+        const M s = HAS_S ? ld_at(sf + (int64_t)r * pitch, fc) : M(0);
+        M P[19];
+        collide3<M>(g, ux, uy, uz, rr, Ax, Ay, Az, s, P);
+        if (live) {
+            T *__restrict__ out = dst + (int64_t)r * kQ3 * pitch;
+#pragma unroll
+            for (int i = 0; i < kQ3; ++i) st_nt_at(out + i * pitch, bc, C::enc(P[i], i, f));
+        }
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void init3_kernel(const InitArgs a)
+{
+    using St = typename ModeTraits<MODE>::St;
+    using M = typename ModeTraits<MODE>::M;
+    using T = typename St::T;
+    using C = Codec<St, M>;
+    const int nx = a.L.nx, ny = a.L.ny, nz = a.L.nz;
+    const int64_t N = (int64_t)nx * ny * nz, pitch = a.L.pitch;
+    T *dst = static_cast<T *>(a.dst);
+    const M *u = static_cast<const M *>(a.u);
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(n % nx);
+        const int64_t r = n / nx;
+        const int y = (int)(r % ny), z = (int)(r / ny);
+        const M *ur = u + r * 3 * pitch;
+        M P[19];
+        equilibrium3<M>((M)a.phi0[n], ur[x], ur[pitch + x], ur[2 * pitch + x], P);
+#pragma unroll
+        for (int i = 0; i < kQ3; ++i) {  // written pre-shifted: buf_i(x - e_i) = g_eq_i(x)
+            int xd = x - kEx3[i], yd = y - kEy3[i], zd = z - kEz3[i];
+            xd = xd < 0 ? xd + nx : (xd >= nx ? xd - nx : xd);
+            yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
+            zd = zd < 0 ? zd + nz : (zd >= nz ? zd - nz : zd);
+            dst[(((int64_t)zd * ny + yd) * kQ3 + i) * pitch + xd] = C::enc(P[i], i, a.f16);
+        }
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void macros3_kernel(const MacroArgs a)
+{
+    using St = typename ModeTraits<MODE>::St;
+    using M = typename ModeTraits<MODE>::M;
+    using T = typename St::T;
+    const int nx = a.L.nx, ny = a.L.ny;
+    const int64_t N = (int64_t)nx * ny * a.L.nz;
+    const T *src = static_cast<const T *>(a.src);
+    CSum cs[3] = {{0, 0}, {0, 0}, {0, 0}};  // mass, sum err^2, sum ref^2
+    double maxerr = 0, maxphi = 0, nonfinite = 0;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(n % nx);
+        const int64_t r = n / nx;
+        M g[19];
+        pull_node3<St, M>(src, a.L, x, (int)(r % ny), (int)(r / ny), g);
+        double phi = 0;
+#pragma unroll
+        for (int i = 0; i < kQ3; ++i) phi += (double)g[i];
+        if (a.phi_out) a.phi_out[n] = phi;
+        if (!isfinite(phi)) {
+            nonfinite += 1;
+            continue;
+        }
+        csum_add(cs[0], phi);
+        maxphi = fmax(maxphi, fabs(phi));
+        if (a.ref) {
+            const double rv = a.ref[n], d = phi - rv;
+            csum_add(cs[1], d * d);
+            csum_add(cs[2], rv * rv);
+            maxerr = fmax(maxerr, fabs(d));
+        }
+    }
+    block_reduce(cs, maxerr, maxphi, nonfinite);
+    if (threadIdx.x == 0) {
+        double *p = a.partials + (int64_t)blockIdx.x * kMacroPartialDoubles;
+        for (int k = 0; k < 3; ++k) {
+            p[2 * k] = cs[k].s;
+            p[2 * k + 1] = cs[k].c;
+        }
+        p[6] = maxerr;
+        p[7] = maxphi;
+        p[8] = nonfinite;
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void populations3_kernel(const PopArgs a)
+{
+    using St = typename ModeTraits<MODE>::St;
+    using M = typename ModeTraits<MODE>::M;
+    using T = typename St::T;
+    const int nx = a.L.nx, ny = a.L.ny;
+    const int64_t N = (int64_t)nx * ny * a.L.nz;
+    const T *src = static_cast<const T *>(a.src);
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(n % nx);
+        const int64_t r = n / nx;
+        M g[19];
+        pull_node3<St, M>(src, a.L, x, (int)(r % ny), (int)(r / ny), g);
+#pragma unroll
+        for (int i = 0; i < kQ3; ++i) a.out[i * N + n] = (double)g[i];
+    }
+}
+
+template <int MODE, int AUX>
+hipError_t launch_step3_aux(const StepArgs &a, hipStream_t st)
+{
+    dim3 block(64, 4);
+    const int nblocks = tiles_of(a.d.L, a.d.lc.rows);
+    const bool hk = a.d.has_k, hs = a.d.has_s;
+    if (hk && hs) step3_kernel<MODE, AUX, true, true><<<nblocks, block, 0, st>>>(a);
+    else if (hk) step3_kernel<MODE, AUX, true, false><<<nblocks, block, 0, st>>>(a);
+    else if (hs) step3_kernel<MODE, AUX, false, true><<<nblocks, block, 0, st>>>(a);
+    else step3_kernel<MODE, AUX, false, false><<<nblocks, block, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_step3_mode(int aux, const StepArgs &a, hipStream_t st)
+{
+    switch (aux) {
+    case 0: return launch_step3_aux<MODE, 0>(a, st);
+    case 2: return launch_step3_aux<MODE, 2>(a, st);
+    default: return hipErrorInvalidValue;  // the flux form is two-dimensional only
+    }
+}
+
+}  // namespace
+
+hipError_t launch_step3(int mode, int aux, const StepArgs &a, hipStream_t st)
+{
+    if (a.d.lc.rows < 1 || a.d.lc.rows > 64 || a.d.L.q != kQ3) return hipErrorInvalidValue;
+    switch (mode) {
+    case MODE_F64_F64: return launch_step3_mode<MODE_F64_F64>(aux, a, st);
+    case MODE_F64_F32: return launch_step3_mode<MODE_F64_F32>(aux, a, st);
+    case MODE_F32_F32: return launch_step3_mode<MODE_F32_F32>(aux, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_init3(int mode, const InitArgs &a, hipStream_t st)
+{
+    const int g = grid_for((int64_t)a.L.nx * a.L.ny * a.L.nz, 256, 8192);
+    switch (mode) {
+    case MODE_F64_F64: init3_kernel<MODE_F64_F64><<<g, 256, 0, st>>>(a); break;
+    case MODE_F64_F32: init3_kernel<MODE_F64_F32><<<g, 256, 0, st>>>(a); break;
+    case MODE_F32_F32: init3_kernel<MODE_F32_F32><<<g, 256, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_macros3(int mode, const MacroArgs &a, double *result, hipStream_t st)
+{
+    const int g = grid_for((int64_t)a.L.nx * a.L.ny * a.L.nz, 256, kMacroBlocks);
+    switch (mode) {
+    case MODE_F64_F64: macros3_kernel<MODE_F64_F64><<<g, 256, 0, st>>>(a); break;
+    case MODE_F64_F32: macros3_kernel<MODE_F64_F32><<<g, 256, 0, st>>>(a); break;
+    case MODE_F32_F32: macros3_kernel<MODE_F32_F32><<<g, 256, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_macros_finalize(a.partials, g, result, st);
+}
+
+hipError_t launch_populations3(int mode, const PopArgs &a, hipStream_t st)
+{
+    const int g = grid_for((int64_t)a.L.nx * a.L.ny * a.L.nz, 256, 8192);
+    switch (mode) {
+    case MODE_F64_F64: populations3_kernel<MODE_F64_F64><<<g, 256, 0, st>>>(a); break;
+    case MODE_F64_F32: populations3_kernel<MODE_F64_F32><<<g, 256, 0, st>>>(a); break;
+    case MODE_F32_F32: populations3_kernel<MODE_F32_F32><<<g, 256, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -20,6 +20,7 @@ LBM_STORE_F64, LBM_STORE_F32, LBM_STORE_F16S = 0, 1, 2
 LBM_MATH_F64, LBM_MATH_F32 = 0, 1
 LBM_AUX_LOCAL, LBM_AUX_FLUX, LBM_AUX_NONE = 0, 1, 2
 LBM_BC_PERIODIC, LBM_BC_NEE, LBM_BC_WALLS = 0, 1, 2
+LBM_LATTICE_D2Q9, LBM_LATTICE_D3Q19 = 0, 1
 
 # names of the population storage / arithmetic combinations
 MODES = {
@@ -42,11 +43,12 @@ class lbm_params(ctypes.Structure):
                 ("lambda_", ctypes.c_double), ("D_const", ctypes.c_double), ("store", ctypes.c_int32),
                 ("math", ctypes.c_int32), ("aux", ctypes.c_int32), ("scale_log2", ctypes.c_int32),
                 ("phi_ref", ctypes.c_double), ("boundary", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("tau3", ctypes.c_double)]
+                ("tau3", ctypes.c_double), ("lattice", ctypes.c_int32), ("nz", ctypes.c_int32)]
 
 
 class lbm_fields(ctypes.Structure):
-    _fields_ = [("phi0", ctypes.c_void_p), ("ux", ctypes.c_void_p), ("uy", ctypes.c_void_p), ("D", ctypes.c_void_p)]
+    _fields_ = [("phi0", ctypes.c_void_p), ("ux", ctypes.c_void_p), ("uy", ctypes.c_void_p), ("D", ctypes.c_void_p),
+                ("uz", ctypes.c_void_p)]
 
 
 class lbm_stats(ctypes.Structure):
@@ -68,7 +70,7 @@ class lbm_batch(ctypes.Structure):
 
 LBM_BATCH_SERIAL, LBM_BATCH_FLAT, LBM_BATCH_STRIDED, LBM_BATCH_LPT = 0, 1, 2, 3
 
-EXPORTS = ["lbm_workspace_size", "lbm_init", "lbm_step", "lbm_set_dirichlet", "lbm_macros", "lbm_populations", "lbm_state_bytes",
+EXPORTS = ["lbm_workspace_size", "lbm_init", "lbm_step", "lbm_set_velocity", "lbm_set_dirichlet", "lbm_macros", "lbm_populations", "lbm_state_bytes",
            "lbm_state_save", "lbm_state_load", "lbm_set_launch", "lbm_get_launch", "lbm_set_batch", "lbm_get_batch",
            "lbm_adjoint_bytes", "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_init", "lbm_bench_copy", "lbm_free",
            "lbm_pitch", "lbm_last_error", "lbm_abi_version"]
@@ -92,6 +94,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lbm_step.argtypes = [P, I32, PP, PP, PP, PP]
     lib.lbm_macros.argtypes = [P, I32, P, P, ctypes.POINTER(lbm_stats)]
     lib.lbm_set_dirichlet.argtypes = [P, I32, P]
+    lib.lbm_set_velocity.argtypes = [P, I32, P, P, P]
     lib.lbm_populations.argtypes = [P, I32, P]
     lib.lbm_state_bytes.argtypes = [P, I32, ctypes.POINTER(SZ)]
     lib.lbm_pitch.argtypes = [ctypes.POINTER(lbm_params), ctypes.POINTER(I64)]
@@ -148,10 +151,12 @@ def _ptr_array(ts: Optional[Sequence[Optional[torch.Tensor]]]):
 
 
 def make_params(nx, ny, dx, dt, lam, D_const=0.0, mode="f64", aux=LBM_AUX_LOCAL, scale_log2=15,
-                phi_ref=0.0, boundary=LBM_BC_PERIODIC, tau3=0.0) -> lbm_params:
+                phi_ref=0.0, boundary=LBM_BC_PERIODIC, tau3=0.0, nz=0) -> lbm_params:
+    """nz >= 3 selects the D3Q19 lattice (nx * ny * nz nodes); nz = 0 is D2Q9."""
     store, math = MODES[mode]
+    lattice = LBM_LATTICE_D3Q19 if nz else LBM_LATTICE_D2Q9
     return lbm_params(int(nx), int(ny), float(dx), float(dt), float(lam), float(D_const), store, math, int(aux),
-                      int(scale_log2), float(phi_ref), int(boundary), 0, float(tau3))
+                      int(scale_log2), float(phi_ref), int(boundary), 0, float(tau3), lattice, int(nz))
 
 
 def lbm_abi_version() -> int:
@@ -171,11 +176,12 @@ def lbm_workspace_size(params: Sequence[lbm_params]) -> int:
 
 def lbm_init(params: Sequence[lbm_params], fields: Sequence[dict], workspace: Optional[torch.Tensor] = None,
              stream: Optional[torch.cuda.Stream] = None) -> ctypes.c_void_p:
-    """fields[k]: dict with device FP64 tensors phi0, ux, uy and optional D (each [ny, nx])."""
+    """fields[k]: dict with device FP64 tensors phi0, ux, uy, optional D, and uz on D3Q19 (each [ny, nx],
+    D3Q19 [nz, ny, nx])."""
     n = len(params)
     parr = (lbm_params * n)(*params)
-    farr = (lbm_fields * n)(*[lbm_fields(_dptr(f["phi0"]), _dptr(f["ux"]), _dptr(f["uy"]), _dptr(f.get("D")))
-                              for f in fields])
+    farr = (lbm_fields * n)(*[lbm_fields(_dptr(f["phi0"]), _dptr(f["ux"]), _dptr(f["uy"]), _dptr(f.get("D")),
+                                         _dptr(f.get("uz"))) for f in fields])
     ws_ptr = None if workspace is None else workspace.data_ptr()
     ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     s = (stream or torch.cuda.current_stream()).cuda_stream
@@ -188,6 +194,10 @@ def lbm_step(ctx, nsteps: int, ux=None, uy=None, S=None, dSdt=None) -> None:
     pu, pv, ps, pd = (_ptr_array(a) for a in (ux, uy, S, dSdt))
     _check(lib().lbm_step(ctx, int(nsteps), pu[0] if pu else None, pv[0] if pv else None, ps[0] if ps else None,
                           pd[0] if pd else None))
+
+
+def lbm_set_velocity(ctx, inst: int, ux: torch.Tensor, uy: torch.Tensor, uz: Optional[torch.Tensor] = None) -> None:
+    _check(lib().lbm_set_velocity(ctx, int(inst), _dptr(ux), _dptr(uy), _dptr(uz)))
 
 
 def lbm_set_dirichlet(ctx, inst: int, phi_b: torch.Tensor) -> None:

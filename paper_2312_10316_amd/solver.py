@@ -27,20 +27,30 @@ class Solver:
         self._keep = (ux, uy, S, dSdt)  # inputs stay alive until the next call
         L.lbm_step(self.ctx, nsteps, ux, uy, S, dSdt)
 
+    def _shape(self, inst: int):
+        p = self.params[inst]
+        return (p.nz, p.ny, p.nx) if p.lattice == L.LBM_LATTICE_D3Q19 else (p.ny, p.nx)
+
+    def _q(self, inst: int) -> int:
+        return 19 if self.params[inst].lattice == L.LBM_LATTICE_D3Q19 else 9
+
+    def set_velocity(self, ux: torch.Tensor, uy: torch.Tensor, uz: Optional[torch.Tensor] = None,
+                     inst: int = 0) -> None:
+        self._keep_u = (ux, uy, uz)
+        L.lbm_set_velocity(self.ctx, inst, ux, uy, uz)
+
     def set_dirichlet(self, phi_b: torch.Tensor, inst: int = 0) -> None:
         self._keep_bc = phi_b
         L.lbm_set_dirichlet(self.ctx, inst, phi_b)
 
     def macros(self, inst: int = 0, ref: Optional[torch.Tensor] = None, want_phi: bool = False,
                raise_nonfinite: bool = True):
-        p = self.params[inst]
-        phi = torch.empty((p.ny, p.nx), dtype=torch.float64, device="cuda") if want_phi else None
+        phi = torch.empty(self._shape(inst), dtype=torch.float64, device="cuda") if want_phi else None
         stats = L.lbm_macros(self.ctx, inst, phi, ref, raise_nonfinite)
         return (stats, phi) if want_phi else stats
 
     def populations(self, inst: int = 0) -> torch.Tensor:
-        p = self.params[inst]
-        out = torch.empty((9, p.ny, p.nx), dtype=torch.float64, device="cuda")
+        out = torch.empty((self._q(inst),) + self._shape(inst), dtype=torch.float64, device="cuda")
         L.lbm_populations(self.ctx, inst, out)
         return out
 

@@ -156,6 +156,44 @@ def x1_problem(N: int, kappa: float, lam: float = 1.0 / 12.0, t_end: float = 1.0
                 phi0=np.exp(-q), source=source, exact=exact, nx=n, ny=n, L=L)
 
 
+# ---- D3Q19: the rotating pulse in three dimensions ---------------------------------------------
+
+def mesh3(nx: int, ny: int, nz: int, lo: float, hi: float):
+    """Vertex-centred periodic coordinates, arrays [nz, ny, nx]."""
+    x, dx = lattice_coords(nx, lo, hi)
+    y, _ = lattice_coords(ny, lo, hi)
+    z, _ = lattice_coords(nz, lo, hi)
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    return X, Y, Z, dx
+
+
+def pulse3_exact(X, Y, Z, t: float, U0: float, D: float, xc0: float, yc0: float, zc0: float, sigma0: float):
+    """Closed-form Gaussian pulse in the solid-body rotation about the z axis (constant D, no source,
+    unbounded space): phi = (s0^2/s^2)^(3/2) exp(-|x - R(U0 t) x_c0|^2 / (2 s^2)), s^2 = s0^2 + 2 D t."""
+    a = U0 * t
+    xc = math.cos(a) * xc0 - math.sin(a) * yc0
+    yc = math.sin(a) * xc0 + math.cos(a) * yc0
+    s2 = sigma0 * sigma0 + 2.0 * D * t
+    r2 = (X - xc) ** 2 + (Y - yc) ** 2 + (Z - zc0) ** 2
+    return (sigma0 * sigma0 / s2) ** 1.5 * np.exp(-r2 / (2.0 * s2))
+
+
+def rotating_pulse3(cfg: PulseConfig) -> dict:
+    """D3Q19 rotating pulse on [-1, 1]^3 (N^3 nodes): u = (-U0 y, U0 x, 0), centre (xc0, yc0, 0)."""
+    X, Y, Z, dx = mesh3(cfg.N, cfg.N, cfg.N, -1.0, 1.0)
+    u = np.stack([-cfg.U0 * Y, cfg.U0 * X, np.zeros_like(X)])
+    phi0 = pulse3_exact(X, Y, Z, 0.0, cfg.U0, cfg.D, cfg.xc0, cfg.yc0, 0.0, cfg.sigma0)
+    return dict(X=X, Y=Y, Z=Z, dx=dx, dt=cfg.dt, lam=cfg.lam, D_const=cfg.D, u=u, phi0=phi0, n=cfg.N)
+
+
+def pulse3_reference(cfg: PulseConfig, fields: dict, steps: Optional[int] = None):
+    t = (cfg.steps if steps is None else steps) * cfg.dt
+    return pulse3_exact(fields["X"], fields["Y"], fields["Z"], t, cfg.U0, cfg.D, cfg.xc0, cfg.yc0, 0.0, cfg.sigma0)
+
+
+C6 = PulseConfig(N=256, steps=800)  # D3Q19 rotating pulse, 256^3, t = 0.3125
+
+
 # ---- batched instances -----------------------------------------------------------------------
 
 @dataclass
