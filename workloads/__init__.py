@@ -191,7 +191,7 @@ def pulse3_reference(cfg: PulseConfig, fields: dict, steps: Optional[int] = None
     return pulse3_exact(fields["X"], fields["Y"], fields["Z"], t, cfg.U0, cfg.D, cfg.xc0, cfg.yc0, 0.0, cfg.sigma0)
 
 
-C6 = PulseConfig(N=256, steps=800)  # D3Q19 rotating pulse, 256^3, t = 0.3125
+C6 = PulseConfig(N=256, steps=400)  # D3Q19 rotating pulse, 256^3, t = 0.3125
 
 
 # ---- batched instances -----------------------------------------------------------------------
