@@ -178,7 +178,18 @@ def run_precision_8192(torch, W, lbm, Solver, n=8192, steps=1000):
         r["roofline_frac"] = r["hbm_gbps_algorithmic"] / HBM_PEAK_GBPS
         out[mode] = r
         del phi
-    del ref, dev
+    # offset pulse: phi0 + 1 on a background of 1 with the FP16 shift phi_ref = 1 (the stored codes
+    # carry g - w_i, so the background costs no precision); errors of phi - 1 against the FP64 run
+    dev["phi0"] = dev["phi0"] + 1.0
+    s = Solver([(lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, "f16s", phi_ref=1.0), dev)])
+    s.step(steps)
+    st, phi = s.macros(want_phi=True, raise_nonfinite=False)
+    s.close()
+    d = (phi - 1.0 - ref).abs()
+    out["f16s_offset_phi_ref_1"] = {"max_err_vs_f64": float(d.max()),
+                                    "l2_rel_err_vs_f64": float(torch.sqrt((d * d).sum() / (ref * ref).sum())),
+                                    "nonfinite": st["nonfinite"]}
+    del d, phi, ref, dev
     torch.cuda.empty_cache()
     return out
 
@@ -393,10 +404,10 @@ def _find(dirpath, suffix):
 
 
 def _kernel_label(name: str):
-    """'step_kernel<2, 0, false, false, 0, false>' (mode, aux, has_k, has_s, boundary, MRT-R) ->
+    """'step_kernel<2, 0, false, false, 0, false, 1>' (mode, aux, has_k, has_s, boundary, MRT-R, walk) ->
     ('step', 'f32', aux 0, has_k, has_s) for the periodic TRT-R kernels; copy -> ('copy',); other -> None."""
     import re
-    m = re.search(r"step_kernel<(\d), (\d), (true|false), (true|false), 0, false>", name)
+    m = re.search(r"step_kernel<(\d), (\d), (true|false), (true|false), 0, false, \d>", name)
     if m:
         return ("step", KERNEL_MODES[m.group(1)], int(m.group(2)), m.group(3) == "true", m.group(4) == "true")
     if "copy_kernel" in name:

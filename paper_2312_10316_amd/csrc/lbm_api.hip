@@ -67,16 +67,17 @@ Layout layout_of(const lbm_params &p)
     return L;
 }
 
-// Default launch shape per storage mode (measured on MI355X at 2048^2 and 8192^2; the autotuner in
-// the Python package can override it per instance): one row per wave with XCD-contiguous tiles for
-// FP64/FP32; FP16 codes (2 bytes per lane) prefer a 4-row walk.  The flux form of the aux term pulls one extra row per walk, so it walks 8 rows.
+// Default launch shape (measured on MI355X at 2048^2 and 8192^2; the autotuner in the Python
+// package can override it per instance): one row per wave with XCD-contiguous tiles for every
+// storage mode (the one-row kernels are compiled without a walking loop).  The flux form of the
+// aux term pulls one extra row per walk, so it walks 8 rows.
 // D3Q19: one row per wave; XCD-contiguous tiles for FP32 storage, hardware order for FP64 storage
 // (measured at 256^3 and 384^3: +5 % each way).
 Launch default_launch(int mode, int aux, int lattice)
 {
     if (lattice == LBM_LATTICE_D3Q19) return Launch{1, mode == MODE_F32_F32 ? 1 : 0};
     if (aux == LBM_AUX_FLUX) return Launch{8, 1};
-    return mode == MODE_F16S_F32 ? Launch{4, 1} : Launch{1, 1};
+    return Launch{1, 1};
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }

@@ -131,7 +131,9 @@ __device__ __forceinline__ M phi_at(const typename St::T *__restrict__ src, cons
 // One tile of one step with the local auxiliary term (or none).  Block (64, 4): lane = column of a
 // 64-wide tile, wave `wave` walks `rows` rows.  The wave's row is uniform (taken with readfirstlane), so row and segment bases live in
 // scalar registers and each load or store needs only a 32-bit lane offset (x, x-1 or x+1).
-template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC = 0, bool MRT = false>
+// ROWS > 0 fixes the walk length at compile time (the common one-row launch then has no loop, and
+// every access keeps the scalar-base + 32-bit-offset form); 0 takes it from the launch shape.
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC = 0, bool MRT = false, int ROWS = 0>
 __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int t, int wave)
 {
     using St = typename ModeTraits<MODE>::St;
@@ -140,7 +142,7 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
     using C = Codec<St, M>;
     const int nx = a.L.nx, ny = a.L.ny;
     const int64_t pitch = a.L.pitch;
-    const int rows = a.lc.rows;
+    const int rows = ROWS > 0 ? ROWS : a.lc.rows;
     const int ntx = (nx + 63) >> 6;
     const unsigned x = (unsigned)((t % ntx) * 64) + threadIdx.x;
     const int y0 = ((t / ntx) * 4 + wave) * rows;
@@ -328,19 +330,19 @@ __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity,
 }
 
 // Dispatch of one tile to the aux-term form.
-template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC = 0, bool MRT = false>
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC = 0, bool MRT = false, int ROWS = 0>
 __device__ __forceinline__ void run_tile(const InstDesc &d, int parity, int t, int wave)
 {
     if constexpr (AUX == 1) process_tile_flux<MODE, HAS_K, HAS_S, MRT>(d, parity, t, wave);
-    else process_tile<MODE, AUX, HAS_K, HAS_S, BC, MRT>(d, parity, t, wave);
+    else process_tile<MODE, AUX, HAS_K, HAS_S, BC, MRT, ROWS>(d, parity, t, wave);
 }
 
 // Single instance: block b -> tile (XCD-remapped if requested).
-template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC, bool MRT>
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC, bool MRT, int ROWS>
 __global__ __launch_bounds__(256) void step_kernel(const StepArgs a)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
-    run_tile<MODE, AUX, HAS_K, HAS_S, BC, MRT>(a.d, a.parity, tile_of_block(blockIdx.x, gridDim.x, a.d.lc.xcd_remap), wave);
+    run_tile<MODE, AUX, HAS_K, HAS_S, BC, MRT, ROWS>(a.d, a.parity, tile_of_block(blockIdx.x, gridDim.x, a.d.lc.xcd_remap), wave);
 }
 
 // Many instances in one launch: each block runs a range of (instance, tile) work items; the
@@ -524,17 +526,30 @@ __global__ __launch_bounds__(256) void copy_kernel(const f32x4 *__restrict__ src
 }
 
 
-template <int MODE, int AUX, int BC, bool MRT>
-hipError_t launch_step_var(const StepArgs &a, hipStream_t st)
+template <int MODE, int AUX, int BC, bool MRT, int ROWS>
+hipError_t launch_step_rows(const StepArgs &a, hipStream_t st)
 {
     dim3 block(64, 4);
     const int nblocks = tiles_of(a.d.L, a.d.lc.rows);
     const bool hk = a.d.has_k, hs = a.d.has_s;
-    if (hk && hs) step_kernel<MODE, AUX, true, true, BC, MRT><<<nblocks, block, 0, st>>>(a);
-    else if (hk) step_kernel<MODE, AUX, true, false, BC, MRT><<<nblocks, block, 0, st>>>(a);
-    else if (hs) step_kernel<MODE, AUX, false, true, BC, MRT><<<nblocks, block, 0, st>>>(a);
-    else step_kernel<MODE, AUX, false, false, BC, MRT><<<nblocks, block, 0, st>>>(a);
+    if (hk && hs) step_kernel<MODE, AUX, true, true, BC, MRT, ROWS><<<nblocks, block, 0, st>>>(a);
+    else if (hk) step_kernel<MODE, AUX, true, false, BC, MRT, ROWS><<<nblocks, block, 0, st>>>(a);
+    else if (hs) step_kernel<MODE, AUX, false, true, BC, MRT, ROWS><<<nblocks, block, 0, st>>>(a);
+    else step_kernel<MODE, AUX, false, false, BC, MRT, ROWS><<<nblocks, block, 0, st>>>(a);
     return hipGetLastError();
+}
+
+// The periodic TRT-R local/no-aux kernels have a one-row instantiation for the default shape: with
+// no loop left, every load keeps the scalar-base + 32-bit-offset form (the walking loop's strength-
+// reduced 64-bit vector addresses cost ~160 instructions and ~28 VGPRs per wave).  Every other shape
+// walks the launch's row count.
+template <int MODE, int AUX, int BC, bool MRT>
+hipError_t launch_step_var(const StepArgs &a, hipStream_t st)
+{
+    if constexpr (AUX != 1 && BC == 0 && !MRT) {
+        if (a.d.lc.rows == 1) return launch_step_rows<MODE, AUX, BC, MRT, 1>(a, st);
+    }
+    return launch_step_rows<MODE, AUX, BC, MRT, 0>(a, st);
 }
 
 // MRT-R (w3 != 0) is a separate instantiation so that the TRT-R kernels keep their registers.

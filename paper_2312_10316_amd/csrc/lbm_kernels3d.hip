@@ -136,6 +136,8 @@ __device__ __forceinline__ void pull_node3(const typename St::T *__restrict__ sr
     }
 }
 
+// Unlike the D2Q9 kernel this one keeps the walking loop for the one-row default: a compile-time
+// one-row instantiation frees VGPRs but measured 2-8 % slower at 256^3 and 384^3.
 template <int MODE, int AUX, bool HAS_K, bool HAS_S>
 __global__ __launch_bounds__(256) void step3_kernel(const StepArgs sa)
 {
