@@ -249,7 +249,7 @@ int lbm_adjoint_step(lbm_ctx *ctx, int32_t inst, const void *state, const void *
 int lbm_adjoint_init(lbm_ctx *ctx, int32_t inst, const void *lam0, double *dLdphi0);
 
 /* Plain streaming copy of `bytes` bytes (multiple of 16; both pointers device, 16-byte aligned) on
- * `stream`: 16-byte vector loads and non-temporal stores, one pass.  Not part of the method: it is
+ * `stream`: 16-byte non-temporal vector loads and stores, one pass.  Not part of the method: it is
  * the reference kernel against which achievable HBM bandwidth and traffic counters are calibrated. */
 int lbm_bench_copy(void *dst, const void *src, size_t bytes, void *stream);
 
