@@ -360,6 +360,8 @@ int enqueue_step(lbm_ctx *c, hipStream_t st)
         a.items = c->d_items;
         a.block_start = c->use_block_start ? c->d_block_start : nullptr;
         a.parity = c->parity;
+        a.one_row = 1;
+        for (const Instance &in : c->inst) a.one_row &= in.lc.rows == 1 ? 1 : 0;
         hipError_t e = launch_batched_step(c->inst[0].mode, c->inst[0].p.aux, a, c->nblocks, st);
         if (e != hipSuccess) return hip_fail(e, "batched step kernel launch");
     } else {

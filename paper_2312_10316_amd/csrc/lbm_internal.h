@@ -84,6 +84,7 @@ struct BatchArgs {
     const WorkItem *items;    // grouped by block when block_start is given
     const int32_t *block_start;  // [nblocks + 1], or nullptr: block b runs item b (XCD-contiguous order)
     int32_t parity;
+    int32_t one_row;             // every instance walks one row per wave (the loop-free instantiation)
 };
 
 // Number of 64-column x (4 * rows)-row tiles of one instance.

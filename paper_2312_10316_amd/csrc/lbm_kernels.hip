@@ -347,7 +347,7 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs a)
 
 // Many instances in one launch: each block runs a range of (instance, tile) work items; the
 // instance descriptor is wave-uniform and read with scalar loads.
-template <int MODE, int AUX>
+template <int MODE, int AUX, int ROWS>
 __global__ __launch_bounds__(256) void batched_step_kernel(const BatchArgs a)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
@@ -363,11 +363,11 @@ __global__ __launch_bounds__(256) void batched_step_kernel(const BatchArgs a)
         const WorkItem w = a.items[it];
         const InstDesc &d = a.inst[w.inst];
         if (d.has_k) {
-            if (d.has_s) run_tile<MODE, AUX, true, true>(d, a.parity, w.tile, wave);
-            else run_tile<MODE, AUX, true, false>(d, a.parity, w.tile, wave);
+            if (d.has_s) run_tile<MODE, AUX, true, true, 0, false, ROWS>(d, a.parity, w.tile, wave);
+            else run_tile<MODE, AUX, true, false, 0, false, ROWS>(d, a.parity, w.tile, wave);
         } else {
-            if (d.has_s) run_tile<MODE, AUX, false, true>(d, a.parity, w.tile, wave);
-            else run_tile<MODE, AUX, false, false>(d, a.parity, w.tile, wave);
+            if (d.has_s) run_tile<MODE, AUX, false, true, 0, false, ROWS>(d, a.parity, w.tile, wave);
+            else run_tile<MODE, AUX, false, false, 0, false, ROWS>(d, a.parity, w.tile, wave);
         }
     }
 }
@@ -593,9 +593,15 @@ hipError_t launch_batched_mode(int aux, const BatchArgs &a, int nblocks, hipStre
 {
     dim3 block(64, 4);
     switch (aux) {
-    case 0: batched_step_kernel<MODE, 0><<<nblocks, block, 0, st>>>(a); break;
-    case 1: batched_step_kernel<MODE, 1><<<nblocks, block, 0, st>>>(a); break;
-    default: batched_step_kernel<MODE, 2><<<nblocks, block, 0, st>>>(a); break;
+    case 0:
+        if (a.one_row) batched_step_kernel<MODE, 0, 1><<<nblocks, block, 0, st>>>(a);
+        else batched_step_kernel<MODE, 0, 0><<<nblocks, block, 0, st>>>(a);
+        break;
+    case 1: batched_step_kernel<MODE, 1, 0><<<nblocks, block, 0, st>>>(a); break;
+    default:
+        if (a.one_row) batched_step_kernel<MODE, 2, 1><<<nblocks, block, 0, st>>>(a);
+        else batched_step_kernel<MODE, 2, 0><<<nblocks, block, 0, st>>>(a);
+        break;
     }
     return hipGetLastError();
 }
