@@ -91,6 +91,38 @@ def test_invalid_parameters_are_rejected(kw, msg):
     assert msg in str(ei.value)
 
 
+def test_maximum_sizes():
+    """2^31 nodes is the largest instance (D2Q9 and D3Q19); one more node is rejected; the
+    workspace of the largest FP16 instance is its 2 x 9 x 2 bytes per node plus fields."""
+    big = _p(nx=65536, ny=32768, mode="f16s")  # 2^31 nodes
+    ws = L.lbm_workspace_size([big])
+    assert ws > 2 * 9 * 2 * (1 << 31)
+    with pytest.raises(L.LbmError, match="2\\^31"):
+        L.lbm_workspace_size([_p(nx=65536, ny=32769)])
+    assert L.lbm_workspace_size([_p(nx=1024, ny=1024, nz=2048)]) > 2 * 19 * 8 * (1 << 31)
+    with pytest.raises(L.LbmError, match="2\\^31"):
+        L.lbm_workspace_size([_p(nx=1024, ny=1024, nz=2049)])
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(nz=2), "must be >= 3"),
+    (dict(nz=-5), "must be >= 3"),
+])
+def test_invalid_d3q19_parameters(kw, msg):
+    with pytest.raises(L.LbmError) as ei:
+        L.lbm_workspace_size([_p(**kw)])
+    assert ei.value.status == L.LBM_E_ARG
+    assert msg in str(ei.value)
+
+
+def test_d3q19_unsupported_combinations():
+    for kw in (dict(nz=8, mode="f16s"), dict(nz=8, aux=L.LBM_AUX_FLUX), dict(nz=8, boundary=L.LBM_BC_NEE),
+               dict(nz=8, tau3=0.9)):
+        with pytest.raises(L.LbmError) as ei:
+            L.lbm_workspace_size([_p(**kw)])
+        assert ei.value.status == L.LBM_E_UNSUPPORTED, kw
+
+
 def test_fp64_math_needs_fp64_storage():
     p = _p(mode="f32")
     p.math = L.LBM_MATH_F64
