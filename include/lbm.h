@@ -86,7 +86,7 @@ enum lbm_lattice { LBM_LATTICE_D2Q9 = 0, LBM_LATTICE_D3Q19 = 1 };
 
 /* One problem instance: the paper's problem statement on a lattice. */
 typedef struct lbm_params {
-    int32_t nx, ny;       /* lattice size, each >= 3 */
+    int32_t nx, ny;       /* lattice size, each >= 3; nx <= 2^24, nodes <= 2^31 */
     double dx, dt;        /* lattice spacing and time step, finite and > 0 */
     double lambda;        /* magic parameter Lambda > 0 */
     double D_const;       /* kappa when lbm_fields.D is NULL (> 0); ignored otherwise */

@@ -92,6 +92,8 @@ int validate(const lbm_params &p, int k)
     if (p.lattice == LBM_LATTICE_D3Q19 && p.nz < 3) return fail(LBM_E_ARG, "instance %d: nz=%d must be >= 3", k, p.nz);
     const int64_t nodes = (int64_t)p.nx * p.ny * (p.lattice == LBM_LATTICE_D3Q19 ? p.nz : 1);
     if (nodes > ((int64_t)1 << 31)) return fail(LBM_E_ARG, "instance %d: more than 2^31 nodes", k);
+    if ((int64_t)p.nx > ((int64_t)1 << 24))  // kernels address a lattice row's segments with 32-bit byte offsets
+        return fail(LBM_E_ARG, "instance %d: nx=%d exceeds 2^24", k, p.nx);
     if (!finite_pos(p.dx) || !finite_pos(p.dt)) return fail(LBM_E_ARG, "instance %d: dx and dt must be finite and > 0", k);
     if (!finite_pos(p.lambda)) return fail(LBM_E_ARG, "instance %d: lambda must be finite and > 0", k);
     if (p.store < LBM_STORE_F64 || p.store > LBM_STORE_F16S) return fail(LBM_E_ARG, "instance %d: unknown store %d", k, p.store);

@@ -226,9 +226,11 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
         M P[9];
         collide<M, MRT>(g, ux_c, uy_c, r, Ax, Ay, s, P);
         if (live) {
+            // one scalar row base and 32-bit lane offsets keep every store in the saddr form
             T *__restrict__ out = dst + (int64_t)y * 9 * pitch;
+            const unsigned pb = (unsigned)(pitch * (int64_t)sizeof(T));
 #pragma unroll
-            for (int i = 0; i < 9; ++i) st_nt_at(out + i * pitch, bc, C::enc(P[i], i, a.f16));
+            for (int i = 0; i < 9; ++i) st_nt_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, a.f16));
         }
         ux_m = ux_c;
         uy_m = uy_c;

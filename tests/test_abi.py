@@ -99,6 +99,10 @@ def test_maximum_sizes():
     assert ws > 2 * 9 * 2 * (1 << 31)
     with pytest.raises(L.LbmError, match="2\\^31"):
         L.lbm_workspace_size([_p(nx=65536, ny=32769)])
+    L.lbm_workspace_size([_p(nx=1 << 24, ny=3)])  # the longest row
+    L.lbm_workspace_size([_p(nx=1 << 24, ny=3, nz=3)])
+    with pytest.raises(L.LbmError, match="2\\^24"):
+        L.lbm_workspace_size([_p(nx=(1 << 24) + 1, ny=3)])
     assert L.lbm_workspace_size([_p(nx=1024, ny=1024, nz=2048)]) > 2 * 19 * 8 * (1 << 31)
     with pytest.raises(L.LbmError, match="2\\^31"):
         L.lbm_workspace_size([_p(nx=1024, ny=1024, nz=2049)])
