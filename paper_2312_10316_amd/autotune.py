@@ -23,7 +23,8 @@ _MEMO: dict = {}
 
 def _key(solver) -> str:
     dev = torch.cuda.get_device_name()
-    shapes = [(p.nx, p.ny, p.store, p.math, p.aux) for p in solver.params]
+    shapes = [(p.nx, p.ny, p.nz, p.lattice, p.store, p.math, p.aux, p.boundary, p.tau3 not in (0.0, 1.0))
+              for p in solver.params]
     return hashlib.sha256(json.dumps([dev, shapes]).encode()).hexdigest()[:20]
 
 

@@ -1,0 +1,66 @@
+"""The launch autotuner on the GPU: it times candidates on the caller's instances without
+advancing them (states and step counters restored bitwise), applies the winner, and caches it."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from paper_2312_10316_amd import Solver, autotune, lbm
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def pulse_instance(n, mode="f32", seed=0):
+    cfg = W.PulseConfig(N=n, steps=10, U0=2.0 + 0.1 * seed)
+    f = W.rotating_pulse(cfg)
+    p = lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, mode)
+    return p, {k: dev(f[k]) for k in ("phi0", "ux", "uy")}
+
+
+def states(s):
+    return [s.populations(k).cpu().numpy() for k in range(len(s.params))]
+
+
+@pytest.mark.parametrize("multi", [False, True])
+def test_tuning_does_not_advance_and_results_do_not_depend_on_the_winner(multi, tmp_path):
+    inst = [pulse_instance(n, seed=k) for k, n in enumerate((96, 130, 64, 200))] if multi else [pulse_instance(160)]
+    s = Solver(inst)
+    s.step(7)
+    before = states(s)
+    cands = [(1, 1, lbm.LBM_BATCH_SERIAL, 0), (2, 0, lbm.LBM_BATCH_SERIAL, 0)]
+    if multi:
+        cands += [(1, 1, lbm.LBM_BATCH_FLAT, 0), (1, 1, lbm.LBM_BATCH_LPT, 512), (2, 1, lbm.LBM_BATCH_STRIDED, 256)]
+    cache = str(tmp_path / "tune.json")
+    r = autotune.tune(s, cands, steps=16, reps=1, cache_path=cache, force=True)
+    assert tuple(r["best"]) in [tuple(c) for c in cands] and not r["cached"]
+    assert all(np.array_equal(a, b) for a, b in zip(before, states(s)))
+    assert all(s.macros(k)["step"] == 7 for k in range(len(inst)))
+    rows, remap, policy, blocks = r["best"]
+    assert s.get_launch(0) == {"rows": rows, "xcd_remap": remap}
+    s.step(20)
+    tuned = states(s)
+    s.close()
+    ref = Solver(inst)
+    ref.step(27)
+    assert all(np.array_equal(a, b) for a, b in zip(tuned, states(ref)))
+    ref.close()
+    again = Solver(inst)
+    r2 = autotune.tune(again, cands, steps=16, reps=1, cache_path=cache)
+    assert r2["cached"] and r2["best"] == r["best"]
+    again.close()
+
+
+def test_tuning_a_d3q19_instance():
+    X, Y, Z, dx = W.mesh3(70, 20, 12, -1.0, 1.0)
+    p = lbm.make_params(70, 20, dx, dx / 4, 0.25, 2e-3, "f32", nz=12)
+    f = {"phi0": dev(1 + np.exp(-(X ** 2 + Y ** 2 + Z ** 2) / 0.1)), "ux": dev(-Y), "uy": dev(X), "uz": dev(0 * X)}
+    s = Solver([(p, f)])
+    before = states(s)
+    r = autotune.tune(s, [(1, 0, 0, 0), (1, 1, 0, 0), (2, 1, 0, 0)], steps=8, reps=1, force=True)
+    assert all(np.array_equal(a, b) for a, b in zip(before, states(s)))
+    assert s.get_launch(0)["rows"] == r["best"][0]
+    s.close()
