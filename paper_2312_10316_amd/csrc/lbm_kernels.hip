@@ -117,13 +117,21 @@ __device__ __forceinline__ void state_node(const typename St::T *__restrict__ sr
     }
 }
 
-template <class St, class M>
-__device__ __forceinline__ M phi_at(const typename St::T *__restrict__ src, const Layout &L, int x, int y,
-                                    const F16Params &f)
+// Value of v in lane k (uniform k), broadcast to the wave.
+template <class M>
+__device__ __forceinline__ M lane_read(M v, int k);
+template <>
+__device__ __forceinline__ float lane_read<float>(float v, int k)
 {
-    M g[9];
-    pull_node<St, M>(src, L, x, y, f, g);
-    return g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+template <>
+__device__ __forceinline__ double lane_read<double>(double v, int k)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 
@@ -242,8 +250,11 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
 // One tile of one step with the flux form of the auxiliary term, which needs phi at the four axis
 // neighbours at the same time level.  The walk down the rows is software-pipelined: the pull of row
 // y+1 gives both the next node's populations and phi(x, y+1), phi(x, y-1) is kept from the previous
-// row, and phi(x-1, y), phi(x+1, y) come from the neighbouring lanes (wave shuffles); only the lanes
-// at the tile's edges (and next to the periodic seam) pull their outside neighbour explicitly.
+// row, and phi(x-1, y), phi(x+1, y) come from the neighbouring lanes (wave shuffles).  The two halo
+// nodes just outside the wave (west of its first lane, east of its last live lane, wrapped at the
+// periodic seam) are pulled cooperatively: lanes 0-8 load the nine populations of the west node and
+// lanes 9-17 those of the east node in one gather, and their sums come back by lane reads, in the
+// same order as every other phi.
 template <int MODE, bool HAS_K, bool HAS_S, bool MRT = false>
 __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity, int t, int wave)
 {
@@ -263,9 +274,26 @@ __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity,
     const unsigned xc = live ? x : 0u;
     const unsigned xm = xc == 0 ? (unsigned)nx - 1 : xc - 1;
     const unsigned xp = xc == (unsigned)nx - 1 ? 0u : xc + 1;
-    const bool need_w = lane == 0;                                  // west neighbour not in this wave
-    const bool need_e = lane == 63 || (live && xc == (unsigned)nx - 1);  // east neighbour not in this wave
+    // byte offsets of columns x, x-1, x+1 (population and field element sizes): scalar bases + 32-bit offsets
+    const unsigned bc = xc * (unsigned)sizeof(T), bm = xm * (unsigned)sizeof(T), bp = xp * (unsigned)sizeof(T);
+    const unsigned fc = xc * (unsigned)sizeof(M), fm = xm * (unsigned)sizeof(M), fp = xp * (unsigned)sizeof(M);
     const int y1 = min(y0 + rows, ny);
+    // halo gather set-up: lane l < 18 loads population l % 9 of the west (l < 9) or east halo node
+    const int x0t = (t % ntx) * 64;
+    const int last = min(63, nx - 1 - x0t);              // last live lane of this wave
+    const int xw = x0t == 0 ? nx - 1 : x0t - 1;           // west halo column
+    const int xe = x0t + last + 1 == nx ? 0 : x0t + last + 1;  // east halo column
+    const int hi = (int)(lane % 9u);
+    const int hex = hi == 1 || hi == 5 || hi == 8 ? 1 : (hi == 3 || hi == 6 || hi == 7 ? -1 : 0);
+    const int hey = hi == 2 || hi == 5 || hi == 6 ? 1 : (hi == 4 || hi == 7 || hi == 8 ? -1 : 0);
+    int hxs = (lane < 9u ? xw : xe) - hex;
+    hxs = hxs < 0 ? hxs + nx : (hxs >= nx ? hxs - nx : hxs);
+    M hwref = M(0);
+    if constexpr (MODE == MODE_F16S_F32) {
+        const F16Params &f = a.f16;
+        hwref = hi == 0 ? f.wref[0] : hi == 1 ? f.wref[1] : hi == 2 ? f.wref[2] : hi == 3 ? f.wref[3]
+              : hi == 4 ? f.wref[4] : hi == 5 ? f.wref[5] : hi == 6 ? f.wref[6] : hi == 7 ? f.wref[7] : f.wref[8];
+    }
     const T *__restrict__ src = static_cast<const T *>(a.buf[parity]);
     T *__restrict__ dst = static_cast<T *>(a.buf[parity ^ 1]);
     const M *__restrict__ u = static_cast<const M *>(a.u);
@@ -278,8 +306,18 @@ __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity,
     rconst.beta = (M)a.beta;
     rconst.w3 = (M)a.w3;
     auto row_pull = [&](int yy, M (&g)[9]) {
-        pull<St, M>(row_block(src, a.L, wrap_dec(yy, ny)), row_block(src, a.L, yy), row_block(src, a.L, wrap_inc(yy, ny)),
-                    pitch, (int)xm, (int)xc, (int)xp, a.f16, g);
+        const T *__restrict__ rm = src + (int64_t)wrap_dec(yy, ny) * 9 * pitch;
+        const T *__restrict__ rc = src + (int64_t)yy * 9 * pitch;
+        const T *__restrict__ rp = src + (int64_t)wrap_inc(yy, ny) * 9 * pitch;
+        g[0] = C::dec(ld_at(rc, bc), 0, a.f16);
+        g[1] = C::dec(ld_at(rc + pitch, bm), 1, a.f16);
+        g[2] = C::dec(ld_at(rm + 2 * pitch, bc), 2, a.f16);
+        g[3] = C::dec(ld_at(rc + 3 * pitch, bp), 3, a.f16);
+        g[4] = C::dec(ld_at(rp + 4 * pitch, bc), 4, a.f16);
+        g[5] = C::dec(ld_at(rm + 5 * pitch, bm), 5, a.f16);
+        g[6] = C::dec(ld_at(rm + 6 * pitch, bp), 6, a.f16);
+        g[7] = C::dec(ld_at(rp + 7 * pitch, bp), 7, a.f16);
+        g[8] = C::dec(ld_at(rp + 8 * pitch, bm), 8, a.f16);
     };
     auto sum9 = [](const M (&g)[9]) { return g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8]; };
 
@@ -293,32 +331,49 @@ __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity,
         phi_m = sum9(gm);
     }
     const int yprev = wrap_dec(y0, ny);
-    M ux_m = u[(int64_t)yprev * 2 * pitch + xc], uy_m = u[((int64_t)yprev * 2 + 1) * pitch + xc];
-    M ux_c = u[(int64_t)y0 * 2 * pitch + xc], uy_c = u[((int64_t)y0 * 2 + 1) * pitch + xc];
+    M ux_m = ld_at(u + (int64_t)yprev * 2 * pitch, fc), uy_m = ld_at(u + ((int64_t)yprev * 2 + 1) * pitch, fc);
+    M ux_c = ld_at(u + (int64_t)y0 * 2 * pitch, fc), uy_c = ld_at(u + ((int64_t)y0 * 2 + 1) * pitch, fc);
     for (int y = y0; y < y1; ++y) {
         const int yn = wrap_inc(y, ny);
         row_pull(yn, gn);
         const M phi_p = sum9(gn);
         const M *__restrict__ uc = u + (int64_t)y * 2 * pitch;
         const M *__restrict__ un = u + (int64_t)yn * 2 * pitch;
-        const M ux_p = un[xc], uy_p = un[pitch + xc];
+        const M ux_p = ld_at(un, fc), uy_p = ld_at(un + pitch, fc);
         M pw = __shfl_up(phi_c, 1, 64), pe = __shfl_down(phi_c, 1, 64);
-        if (need_w) pw = phi_at<St, M>(src, a.L, (int)xm, y, a.f16);
-        if (need_e) pe = phi_at<St, M>(src, a.L, (int)xp, y, a.f16);
-        const M uxw = uc[xm], uyw = uc[pitch + xm], uxe = uc[xp], uye = uc[pitch + xp];
+        {
+            int hys = y - hey;
+            hys = hys < 0 ? hys + ny : (hys >= ny ? hys - ny : hys);
+            M hv = M(0);
+            if (lane < 18u) {
+                const T raw = src[((int64_t)hys * 9 + hi) * pitch + hxs];
+                if constexpr (MODE == MODE_F16S_F32) hv = (float)raw * a.f16.inv_scale + hwref;
+                else hv = C::dec(raw, 0, a.f16);
+            }
+            M phw = lane_read<M>(hv, 0), phe = lane_read<M>(hv, 9);
+#pragma unroll
+            for (int k = 1; k < 9; ++k) {
+                phw += lane_read<M>(hv, k);
+                phe += lane_read<M>(hv, 9 + k);
+            }
+            if (lane == 0u) pw = phw;
+            if ((int)lane == last) pe = phe;
+        }
+        const M uxw = ld_at(uc, fm), uyw = ld_at(uc + pitch, fm), uxe = ld_at(uc, fp), uye = ld_at(uc + pitch, fp);
         const M fwx = pw * uxw, fex = pe * uxe;          // phi u_x at the west and east neighbours
         const M fsy = phi_m * uy_m, fny = phi_p * uy_p;  // phi u_y at the south and north neighbours
         const M div = (fex - fwx) * M(0.5) + (fny - fsy) * M(0.5);
         const M Ax = (fex * uxe - fwx * uxw) * M(0.5) + (fny * ux_p - fsy * ux_m) * M(0.5) - ux_c * div;
         const M Ay = (fex * uye - fwx * uyw) * M(0.5) + (fny * uy_p - fsy * uy_m) * M(0.5) - uy_c * div;
-        const Relax<M> r = HAS_K ? relax_from_k<M>(kf[(int64_t)y * pitch + xc], lam, rconst.w3) : rconst;
-        const M s = HAS_S ? sf[(int64_t)y * pitch + xc] : M(0);
+        const Relax<M> r = HAS_K ? relax_from_k<M>(ld_at(kf + (int64_t)y * pitch, fc), lam, rconst.w3) : rconst;
+        const M s = HAS_S ? ld_at(sf + (int64_t)y * pitch, fc) : M(0);
         M P[9];
         collide<M, MRT>(g, ux_c, uy_c, r, Ax, Ay, s, P);
         if (live) {
             T *__restrict__ out = dst + (int64_t)y * 9 * pitch;
+            const unsigned pb = (unsigned)(pitch * (int64_t)sizeof(T));
 #pragma unroll
-            for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(C::enc(P[i], i, a.f16), (out + i * pitch) + x);
+            for (int i = 0; i < 9; ++i) st_nt_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, a.f16));
         }
 #pragma unroll
         for (int i = 0; i < 9; ++i) g[i] = gn[i];
