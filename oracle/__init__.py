@@ -5,8 +5,8 @@ TEST INFRASTRUCTURE ONLY.  This package is the checker, not the product: only ``
 code with the HIP library (``paper_2312_10316_amd``) and never imports it.
 
 The arithmetic lives in ``lbm_oracle.c`` (plain C, compiled with ``gcc -O2 -ffp-contract=off``, no
-fast-math, twice: FP64 and FP64-complex for complex-step derivatives) and, for the D3Q19 lattice, in
-``lbm_oracle_d3q19.c`` (FP64).  This module only marshals
+fast-math, twice: FP64 and FP64-complex for complex-step derivatives) and, for the D3Q19 and D3Q27
+lattices, in ``lbm_oracle_3d.c`` (FP64).  This module only marshals
 numpy arrays.  Reductions (mass, the RMS error of Sec. 3, Eq. (33)) are computed here with
 ``math.fsum`` (correctly rounded sums), in the definitions' own terms.
 
@@ -25,7 +25,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
-_SRC3 = os.path.join(_HERE, "lbm_oracle_d3q19.c")
+_SRC3 = os.path.join(_HERE, "lbm_oracle_3d.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 AUX_LOCAL, AUX_FLUX, AUX_NONE = 0, 1, 2
@@ -78,9 +78,9 @@ def _load():
             getattr(lib, pre + "step").argtypes = [P, P, P, P, P, P, P, P, P]
             getattr(lib, pre + "run").argtypes = [P, P, i32, P, P, P, P, P, P, P]
             getattr(lib, pre + "apply_nee").argtypes = [P, P, P, P, P]
-        lib.orc3_lattice.argtypes = [P, P, P, P]
-        lib.orc3_equilibrium.argtypes = [dbl, P, dbl, P]
-        lib.orc3_collide.argtypes = [P, P, dbl, dbl, dbl, P]
+        lib.orc3_lattice.argtypes = [i32, P, P, P, P]
+        lib.orc3_equilibrium.argtypes = [i32, dbl, P, dbl, P]
+        lib.orc3_collide.argtypes = [i32, P, P, dbl, dbl, dbl, P]
         lib.orc3_init.argtypes = [P, P, P, P]
         lib.orc3_phi.argtypes = [P, P, P]
         lib.orc3_step.argtypes = [P, P, P, P, P, P, P]
@@ -266,18 +266,18 @@ def max_abs_error(phi_num, phi_ref) -> float:
     return float(np.max(np.abs(np.asarray(phi_num, np.float64) - np.asarray(phi_ref, np.float64))))
 
 
-# ---- D3Q19 ----------------------------------------------------------------------------------------
+# ---- D3Q19 / D3Q27 -------------------------------------------------------------------------------
 
 class _Problem3(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("dx", ctypes.c_double),
                 ("dt", ctypes.c_double), ("lambda_", ctypes.c_double), ("D_const", ctypes.c_double),
-                ("aux", ctypes.c_int)]
+                ("aux", ctypes.c_int), ("q", ctypes.c_int)]
 
 
 @dataclass
 class Problem3:
-    """One periodic D3Q19 instance.  Arrays: populations g[19, nz, ny, nx]; u[3, nz, ny, nx];
-    scalar fields [nz, ny, nx]; node (j, k, l) is [l, k, j]."""
+    """One periodic D3Q19 (q = 19) or D3Q27 (q = 27) instance.  Arrays: populations g[q, nz, ny, nx];
+    u[3, nz, ny, nx]; scalar fields [nz, ny, nx]; node (j, k, l) is [l, k, j]."""
     nx: int
     ny: int
     nz: int
@@ -286,9 +286,14 @@ class Problem3:
     lam: float
     D_const: float = 0.0
     aux: int = AUX_LOCAL
+    q: int = 19
+
+    def __post_init__(self):
+        if self.q not in (19, 27):
+            raise ValueError("q must be 19 or 27")
 
     def _c(self) -> _Problem3:
-        return _Problem3(self.nx, self.ny, self.nz, self.dx, self.dt, self.lam, self.D_const, self.aux)
+        return _Problem3(self.nx, self.ny, self.nz, self.dx, self.dt, self.lam, self.D_const, self.aux, self.q)
 
     @property
     def c(self) -> float:
@@ -299,27 +304,35 @@ class Problem3:
         return (self.nz, self.ny, self.nx)
 
 
-def lattice3():
-    """(ex[19], ey[19], ez[19], w[19]) of the D3Q19 oracle (lattice units)."""
+def _q(q: int) -> int:
+    if q not in (19, 27):
+        raise ValueError("q must be 19 or 27")
+    return q
+
+
+def lattice3(q: int = 19):
+    """(ex[q], ey[q], ez[q], w[q]) of the D3Q19 or D3Q27 oracle (lattice units)."""
     lib = _load()
-    e = [np.zeros(19, np.int32) for _ in range(3)]
-    w = np.zeros(19, np.float64)
-    lib.orc3_lattice(*(_ptr(a) for a in e), _ptr(w))
+    e = [np.zeros(_q(q), np.int32) for _ in range(3)]
+    w = np.zeros(q, np.float64)
+    lib.orc3_lattice(q, *(_ptr(a) for a in e), _ptr(w))
     return tuple(a.astype(np.int64) for a in e) + (w,)
 
 
-def equilibrium3(phi: float, u, c: float) -> np.ndarray:
-    out = np.zeros(19)
+def equilibrium3(phi: float, u, c: float, q: int = 19) -> np.ndarray:
+    out = np.zeros(_q(q))
     uu = np.ascontiguousarray(u, dtype=np.float64)
-    _load().orc3_equilibrium(phi, _ptr(uu), c, _ptr(out))
+    _load().orc3_equilibrium(q, phi, _ptr(uu), c, _ptr(out))
     return out
 
 
 def collide3(g, u, tau1: float, tau2: float, c: float) -> np.ndarray:
+    """TRT-R collision of one node; the lattice follows from len(g) (19 or 27)."""
     g = np.ascontiguousarray(g, dtype=np.float64)
+    q = _q(len(g))
     uu = np.ascontiguousarray(u, dtype=np.float64)
-    out = np.zeros(19)
-    _load().orc3_collide(_ptr(g), _ptr(uu), tau1, tau2, c, _ptr(out))
+    out = np.zeros(q)
+    _load().orc3_collide(q, _ptr(g), _ptr(uu), tau1, tau2, c, _ptr(out))
     return out
 
 
@@ -331,15 +344,22 @@ def _u3(p: Problem3, u):
     return np.ascontiguousarray(np.broadcast_to(np.asarray(u, np.float64), (3,) + p.shape))
 
 
+def _g3(p: Problem3, g):
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    if g.shape != (p.q,) + p.shape:
+        raise ValueError(f"populations must have shape {(p.q,) + p.shape}, got {g.shape}")
+    return g
+
+
 def init3(p: Problem3, phi0, u) -> np.ndarray:
-    g = np.zeros((19,) + p.shape)
+    g = np.zeros((p.q,) + p.shape)
     pc = p._c()
     _load().orc3_init(ctypes.byref(pc), _ptr(_f3(p, phi0)), _ptr(_u3(p, u)), _ptr(g))
     return g
 
 
 def phi3(p: Problem3, g) -> np.ndarray:
-    g = np.ascontiguousarray(g, dtype=np.float64)
+    g = _g3(p, g)
     out = np.zeros(p.shape)
     pc = p._c()
     _load().orc3_phi(ctypes.byref(pc), _ptr(g), _ptr(out))
@@ -347,7 +367,7 @@ def phi3(p: Problem3, g) -> np.ndarray:
 
 
 def step3(p: Problem3, g, u, D=None, S=None, dSdt=None) -> np.ndarray:
-    g = np.ascontiguousarray(g, dtype=np.float64)
+    g = _g3(p, g)
     out = np.empty_like(g)
     pc = p._c()
     _load().orc3_step(ctypes.byref(pc), _ptr(g), _ptr(out), _ptr(_u3(p, u)), _ptr(_f3(p, D)), _ptr(_f3(p, S)),
@@ -356,7 +376,7 @@ def step3(p: Problem3, g, u, D=None, S=None, dSdt=None) -> np.ndarray:
 
 
 def run3(p: Problem3, g, nsteps: int, u, D=None, S=None, dSdt=None) -> np.ndarray:
-    g = np.array(g, dtype=np.float64, copy=True, order="C")
+    g = np.array(_g3(p, g), dtype=np.float64, copy=True, order="C")
     work = np.empty_like(g)
     pc = p._c()
     _load().orc3_run(ctypes.byref(pc), _ptr(g), int(nsteps), _ptr(_u3(p, u)), _ptr(_f3(p, D)), _ptr(_f3(p, S)),

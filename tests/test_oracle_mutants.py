@@ -14,7 +14,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PINS = os.path.join(ROOT, "tests", "test_oracle_pins.py")
-PINS_D3Q19 = os.path.join(ROOT, "tests", "test_oracle_pins_d3q19.py")
+PINS_3D = os.path.join(ROOT, "tests", "test_oracle_pins_3d.py")
 
 MUTANTS = [
     ("drop third-order equilibrium", "+ s3 / (6.0 * cs2 * cs2 * cs2)", ""),
@@ -57,9 +57,9 @@ MUTANTS = [
      "wrap(y - EY[i], ny) * nx + wrap(x - EX[i], nx)"),
 ]
 
-MUTANTS_D3Q19 = [
-    ("z velocity table", "static const int EZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};",
-     "static const int EZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1};"),
+MUTANTS_3D = [
+    ("z velocity table", "static const int EZ[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,",
+     "static const int EZ[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1,"),
     ("edge weight", "1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};",
      "1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 18.0};"),
     ("drop third-order equilibrium", "+ s3 / (6.0 * cs2 * cs2 * cs2)", ""),
@@ -72,6 +72,16 @@ MUTANTS_D3Q19 = [
     ("tau1 from kappa", "const double tau1 = 0.5 + kappa / (cs2 * dt);", "const double tau1 = 0.5 + 2.0 * kappa / (cs2 * dt);"),
     ("velocity components swapped", "const double un[3] = {u[n], u[N + n], u[2 * N + n]};",
      "const double un[3] = {u[n], u[2 * N + n], u[N + n]};"),
+    # D3Q27 only
+    ("D3Q27 corner x table", "1, -1, 1, -1, 1, -1, -1, 1};", "1, -1, 1, -1, -1, 1, -1, 1};"),
+    ("D3Q27 corner z table", "1, -1, -1, 1, 1, -1, 1, -1};", "1, -1, 1, -1, 1, -1, 1, -1};"),
+    ("D3Q27 face weight", "2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0,",
+     "2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 1.0 / 18.0,"),
+    ("D3Q27 corner weight", "1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0};",
+     "1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0, 1.0 / 108.0};"),
+    ("D3Q27 edge and corner weights exchanged",
+     "1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0,\n                               1.0 / 216.0",
+     "1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 216.0,\n                               1.0 / 54.0"),
 ]
 
 _PLUGIN = '''
@@ -104,6 +114,6 @@ def test_mutant_is_caught(name, old, new, tmp_path):
     _run_mutant(name, old, new, tmp_path, "lbm_oracle.c", PINS)
 
 
-@pytest.mark.parametrize("name,old,new", MUTANTS_D3Q19, ids=[m[0] for m in MUTANTS_D3Q19])
-def test_d3q19_mutant_is_caught(name, old, new, tmp_path):
-    _run_mutant(name, old, new, tmp_path, "lbm_oracle_d3q19.c", PINS_D3Q19)
+@pytest.mark.parametrize("name,old,new", MUTANTS_3D, ids=[m[0] for m in MUTANTS_3D])
+def test_3d_mutant_is_caught(name, old, new, tmp_path):
+    _run_mutant(name, old, new, tmp_path, "lbm_oracle_3d.c", PINS_3D)
