@@ -289,11 +289,12 @@ def run_dirichlet(torch, W, lbm, Solver, sizes=(100, 200, 400, 800), kappa=0.05,
     return out
 
 
-def run_d3q19(torch, W, lbm, Solver, sizes=(64, 128, 256), tp_steps=400):
-    """D3Q19 rotating pulse about the z axis on [-1, 1]^3 (c = 10, D = 1e-3, t = 0.3125): E_r against
-    the closed form per storage mode and size, and the step's throughput at the largest size."""
+def run_3d(torch, W, lbm, Solver, q=19, sizes=(64, 128, 256), tp_steps=400):
+    """Rotating pulse about the z axis on [-1, 1]^3 (c = 10, D = 1e-3, t = 0.3125) on the D3Q19 or
+    D3Q27 lattice: E_r against the closed form per storage mode and size, and the step's throughput
+    at the largest size."""
     import numpy as np
-    BYTES = {"f64": 19 * 16 + 24, "f64s_f32m": 19 * 16 + 12, "f32": 19 * 8 + 12}
+    BYTES = {"f64": q * 16 + 24, "f64s_f32m": q * 16 + 12, "f32": q * 8 + 12}
     out = {"N": list(sizes), "E_r": {m: [] for m in BYTES}, "throughput": {}}
     dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     for n in sizes:
@@ -301,13 +302,14 @@ def run_d3q19(torch, W, lbm, Solver, sizes=(64, 128, 256), tp_steps=400):
         f = W.rotating_pulse3(cfg)
         fields = {"phi0": dv(f["phi0"]), "ux": dv(f["u"][0]), "uy": dv(f["u"][1]), "uz": dv(f["u"][2])}
         ref = dv(W.pulse3_reference(cfg, f))
+        mk = lambda mode: lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, mode, nz=n, lattice=q)
         for mode in BYTES:
-            s = Solver([(lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, mode, nz=n), fields)])
+            s = Solver([(mk(mode), fields)])
             if n == sizes[-1]:
                 s.step(64)
                 ms = _timed_steps(torch, s, tp_steps)
                 s.close()
-                s = Solver([(lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, mode, nz=n), fields)])
+                s = Solver([(mk(mode), fields)])
                 mlups = n ** 3 / (ms * 1e-3) / 1e6
                 out["throughput"][mode] = {"mlups": mlups, "ms_per_step": ms, "bytes_per_lup": BYTES[mode],
                                            "hbm_gbps_algorithmic": mlups * BYTES[mode] / 1e3,
@@ -580,7 +582,8 @@ def main():
               file=sys.stderr, flush=True)
     if not args.no_studies:
         for name, fn in (("precision_8192_variable_D", run_precision_8192), ("refinement", run_refinement),
-                         ("flux_aux_2048", run_flux), ("dirichlet_sec3", run_dirichlet), ("d3q19", run_d3q19),
+                         ("flux_aux_2048", run_flux), ("dirichlet_sec3", run_dirichlet), ("d3q19", run_3d),
+                         ("d3q27", lambda *a: run_3d(*a, q=27)),
                          ("adjoint_512", run_adjoint)):
             t0 = time.perf_counter()
             try:

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 4
+#define LBM_ABI_VERSION 5
 
 enum lbm_status {
     LBM_OK = 0,
@@ -76,13 +76,17 @@ enum lbm_aux { LBM_AUX_LOCAL = 0, LBM_AUX_FLUX = 1, LBM_AUX_NONE = 2 };
  * one-sided on those rows.  Available with aux LOCAL or NONE; one launch per instance; no adjoint. */
 enum lbm_boundary { LBM_BC_PERIODIC = 0, LBM_BC_NEE = 1, LBM_BC_WALLS = 2 };
 
-/* Lattice.  D2Q9 (Sec. 2.2).  D3Q19: the three-dimensional extension (Sec. 2.2 calls it
+/* Lattice.  D2Q9 (Sec. 2.2).  D3Q19 and D3Q27: the three-dimensional extension (Sec. 2.2 calls it
  * straightforward) with the same operator written over three axes: velocities 0:(0,0,0);
  * 1,2:(+-1,0,0); 3,4:(0,+-1,0); 5,6:(0,0,+-1); 7:(1,1,0) 8:(-1,-1,0) 9:(1,-1,0) 10:(-1,1,0);
  * 11:(1,0,1) 12:(-1,0,-1) 13:(1,0,-1) 14:(-1,0,1); 15:(0,1,1) 16:(0,-1,-1) 17:(0,1,-1) 18:(0,-1,1),
- * weights 1/3, 1/18, 1/36, c_s^2 = c^2/3.  D3Q19 instances are periodic, use FP64 or FP32 storage,
- * aux LOCAL or NONE and TRT-R (tau3 0 or 1), run one launch per instance and have no adjoint. */
-enum lbm_lattice { LBM_LATTICE_D2Q9 = 0, LBM_LATTICE_D3Q19 = 1 };
+ * weights 1/3, 1/18, 1/36 (D3Q19); D3Q27 adds the corners 19:(1,1,1) 20:(-1,-1,-1) 21:(1,1,-1)
+ * 22:(-1,-1,1) 23:(1,-1,1) 24:(-1,1,-1) 25:(-1,1,1) 26:(1,-1,-1), with weights 8/27, 2/27, 1/54,
+ * 1/216; c_s^2 = c^2/3.  The third-order equilibrium keeps every Hermite component the lattice
+ * supports (D3Q27 keeps H_xyz, D3Q19 does not).  3D instances are periodic, use FP64 or FP32
+ * storage, aux LOCAL or NONE and TRT-R (tau3 0 or 1), run one launch per instance and have no
+ * adjoint. */
+enum lbm_lattice { LBM_LATTICE_D2Q9 = 0, LBM_LATTICE_D3Q19 = 1, LBM_LATTICE_D3Q27 = 2 };
 
 /* One problem instance: the paper's problem statement on a lattice. */
 typedef struct lbm_params {
@@ -101,17 +105,17 @@ typedef struct lbm_params {
                              the third-order Hermite non-equilibrium moments, finite and > 1/2;
                              0 (or 1) selects the TRT-R operator of Eq. (12), which drops them */
     int32_t lattice;      /* enum lbm_lattice */
-    int32_t nz;           /* D3Q19: lattice size in z, >= 3 (nx * ny * nz <= 2^31); D2Q9: 0 or 1 */
+    int32_t nz;           /* 3D lattices: size in z, >= 3 (nx * ny * nz <= 2^31); D2Q9: 0 or 1 */
 } lbm_params;
 
-/* Fields of one instance (device, FP64, [ny][nx]; D3Q19: [nz][ny][nx]).  u is in physical units;
+/* Fields of one instance (device, FP64, [ny][nx]; 3D lattices: [nz][ny][nx]).  u is in physical units;
  * D > 0 everywhere.  They are read during lbm_init only (copied to the library's own layout). */
 typedef struct lbm_fields {
     const double *phi0;   /* initial phi, required */
     const double *ux;     /* velocity x-component, required */
     const double *uy;     /* velocity y-component, required */
     const double *D;      /* diffusion coefficient kappa(x), or NULL for D_const */
-    const double *uz;     /* velocity z-component: required on D3Q19, ignored on D2Q9 */
+    const double *uz;     /* velocity z-component: required on 3D lattices, ignored on D2Q9 */
 } lbm_fields;
 
 /* Diagnostics of one instance (host struct filled by lbm_macros). */
@@ -143,7 +147,7 @@ int lbm_init(lbm_ctx **ctx, int32_t n_inst, const lbm_params *p, const lbm_field
 
 /* Advances every instance by nsteps >= 0 steps of Eq. (14).  Asynchronous.
  * ux, uy: host arrays [n_inst] of device FP64 [ny][nx] velocity fields that replace u from this
- *         call on, or NULL (both) to keep the current u.  Not for D3Q19 instances (LBM_E_ARG): their
+ *         call on, or NULL (both) to keep the current u.  Not for 3D instances (LBM_E_ARG): their
  *         velocity is replaced with lbm_set_velocity.
  * S, dSdt: host arrays [n_inst] of device FP64 [ny][nx] source S and its time derivative, held
  *         constant over this call's steps, or NULL (both) for no source.  An entry may be NULL for an
@@ -152,7 +156,7 @@ int lbm_step(lbm_ctx *ctx, int32_t nsteps, const double *const *ux, const double
              const double *const *S, const double *const *dSdt);
 
 /* Replaces the velocity of instance inst from the next step on (device FP64 fields in the layout of
- * lbm_fields; uz required on D3Q19, ignored on D2Q9).  Asynchronous (stream order). */
+ * lbm_fields; uz required on 3D lattices, ignored on D2Q9).  Asynchronous (stream order). */
 int lbm_set_velocity(lbm_ctx *ctx, int32_t inst, const double *ux, const double *uy, const double *uz);
 
 /* Dirichlet values of an LBM_BC_NEE or LBM_BC_WALLS instance: phi_b (device FP64 [ny][nx], copied;
@@ -165,14 +169,14 @@ int lbm_set_velocity(lbm_ctx *ctx, int32_t inst, const double *ux, const double 
 int lbm_set_dirichlet(lbm_ctx *ctx, int32_t inst, const double *phi_b);
 
 /* Diagnostics of instance inst: phi = sum_i g_i at the current time.  phi_out (device FP64
- * [ny][nx], D3Q19 [nz][ny][nx], nullable) receives phi; ref (same shape, nullable) is the field the error
+ * [ny][nx], 3D [nz][ny][nx], nullable) receives phi; ref (same shape, nullable) is the field the error
  * statistics are taken against; out (host) receives the statistics.  Synchronizes the stream.
  * Returns LBM_E_NONFINITE if any phi is NaN or infinite (out is still filled). */
 int lbm_macros(lbm_ctx *ctx, int32_t inst, double *phi_out, const double *ref, lbm_stats *out);
 
 /* Pre-collision populations g_i(x, t) of instance inst, decoded to FP64, into g_out (device FP64
  * [9][ny][nx], velocity order 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1)
- * 8:(1,-1); D3Q19: [19][nz][ny][nx] in the order of enum lbm_lattice).  Asynchronous. */
+ * 8:(1,-1); D3Q19 / D3Q27: [19 / 27][nz][ny][nx] in the order of enum lbm_lattice).  Asynchronous. */
 int lbm_populations(lbm_ctx *ctx, int32_t inst, double *g_out);
 
 /* Checkpoint of instance inst: the raw population state in the library's storage format.
@@ -182,8 +186,8 @@ int lbm_populations(lbm_ctx *ctx, int32_t inst, double *g_out);
  * Image layout: [ny][9][pitch] elements of the storage type (FP64, FP32 or FP16 code), pitch as
  * returned by lbm_pitch, padding zero.  Element (y, i, x) holds the post-collision value
  * P_i of node (x, y) from the previous step, so that g_i(x, y) = element (y - e_iy, i, x - e_ix)
- * (periodic); after lbm_init it holds g_eq_i of node (x + e_ix, y + e_iy).  D3Q19: [nz][ny][19][pitch],
- * element (z, y, i, x) likewise. */
+ * (periodic); after lbm_init it holds g_eq_i of node (x + e_ix, y + e_iy).  D3Q19 / D3Q27:
+ * [nz][ny][19 / 27][pitch], element (z, y, i, x) likewise. */
 int lbm_state_bytes(lbm_ctx *ctx, int32_t inst, size_t *bytes);
 /* Row pitch (elements) of an instance's layouts (state image, adjoint arrays): nx rounded up to a
  * multiple of 64, plus 64 when that many storage elements span a multiple of 4 KiB.  Host only (no

@@ -62,8 +62,8 @@ Layout layout_of(const lbm_params &p)
     L.nx = p.nx;
     L.ny = p.ny;
     L.pitch = pitch_of(p);
-    L.nz = p.lattice == LBM_LATTICE_D3Q19 ? p.nz : 1;
-    L.q = p.lattice == LBM_LATTICE_D3Q19 ? 19 : 9;
+    L.nz = p.lattice == LBM_LATTICE_D2Q9 ? 1 : p.nz;
+    L.q = p.lattice == LBM_LATTICE_D3Q27 ? 27 : (p.lattice == LBM_LATTICE_D3Q19 ? 19 : 9);
     return L;
 }
 
@@ -71,11 +71,11 @@ Layout layout_of(const lbm_params &p)
 // package can override it per instance): one row per wave with XCD-contiguous tiles for every
 // storage mode (the one-row kernels are compiled without a walking loop).  The flux form of the
 // aux term pulls one extra row per walk, so it walks 8 rows.
-// D3Q19: one row per wave; XCD-contiguous tiles for FP32 storage, hardware order for FP64 storage
-// (measured at 256^3 and 384^3: +5 % each way).
+// D3Q19 and D3Q27: one row per wave; XCD-contiguous tiles for FP32 storage, hardware order for FP64
+// storage (measured on D3Q19 at 256^3 and 384^3: +5 % each way).
 Launch default_launch(int mode, int aux, int lattice)
 {
-    if (lattice == LBM_LATTICE_D3Q19) return Launch{1, mode == MODE_F32_F32 ? 1 : 0};
+    if (lattice != LBM_LATTICE_D2Q9) return Launch{1, mode == MODE_F32_F32 ? 1 : 0};
     if (aux == LBM_AUX_FLUX) return Launch{8, 1};
     return Launch{1, 1};
 }
@@ -85,12 +85,13 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 int validate(const lbm_params &p, int k)
 {
     if (p.nx < 3 || p.ny < 3) return fail(LBM_E_ARG, "instance %d: nx=%d, ny=%d must be >= 3", k, p.nx, p.ny);
-    if (p.lattice != LBM_LATTICE_D2Q9 && p.lattice != LBM_LATTICE_D3Q19)
+    if (p.lattice != LBM_LATTICE_D2Q9 && p.lattice != LBM_LATTICE_D3Q19 && p.lattice != LBM_LATTICE_D3Q27)
         return fail(LBM_E_ARG, "instance %d: unknown lattice %d", k, p.lattice);
-    if (p.lattice == LBM_LATTICE_D2Q9 && p.nz != 0 && p.nz != 1)
+    const bool three_d = p.lattice != LBM_LATTICE_D2Q9;
+    if (!three_d && p.nz != 0 && p.nz != 1)
         return fail(LBM_E_ARG, "instance %d: nz=%d on a D2Q9 lattice (0 or 1)", k, p.nz);
-    if (p.lattice == LBM_LATTICE_D3Q19 && p.nz < 3) return fail(LBM_E_ARG, "instance %d: nz=%d must be >= 3", k, p.nz);
-    const int64_t nodes = (int64_t)p.nx * p.ny * (p.lattice == LBM_LATTICE_D3Q19 ? p.nz : 1);
+    if (three_d && p.nz < 3) return fail(LBM_E_ARG, "instance %d: nz=%d must be >= 3", k, p.nz);
+    const int64_t nodes = (int64_t)p.nx * p.ny * (three_d ? p.nz : 1);
     if (nodes > ((int64_t)1 << 31)) return fail(LBM_E_ARG, "instance %d: more than 2^31 nodes", k);
     if ((int64_t)p.nx > ((int64_t)1 << 24))  // kernels address a lattice row's segments with 32-bit byte offsets
         return fail(LBM_E_ARG, "instance %d: nx=%d exceeds 2^24", k, p.nx);
@@ -108,11 +109,11 @@ int validate(const lbm_params &p, int k)
         return fail(LBM_E_UNSUPPORTED, "instance %d: the flux form of the aux term is periodic only", k);
     if (p.tau3 != 0.0 && !(std::isfinite(p.tau3) && p.tau3 > 0.5))
         return fail(LBM_E_ARG, "instance %d: tau3 must be 0 (TRT-R) or finite and > 1/2", k);
-    if (p.lattice == LBM_LATTICE_D3Q19) {
-        if (p.store == LBM_STORE_F16S) return fail(LBM_E_UNSUPPORTED, "instance %d: no FP16 storage on D3Q19", k);
+    if (three_d) {
+        if (p.store == LBM_STORE_F16S) return fail(LBM_E_UNSUPPORTED, "instance %d: no FP16 storage on 3D lattices", k);
         if (p.aux == LBM_AUX_FLUX) return fail(LBM_E_UNSUPPORTED, "instance %d: the flux form is D2Q9 only", k);
-        if (p.boundary != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "instance %d: D3Q19 is periodic only", k);
-        if (p.tau3 != 0.0 && p.tau3 != 1.0) return fail(LBM_E_UNSUPPORTED, "instance %d: no MRT-R on D3Q19", k);
+        if (p.boundary != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "instance %d: 3D lattices are periodic only", k);
+        if (p.tau3 != 0.0 && p.tau3 != 1.0) return fail(LBM_E_UNSUPPORTED, "instance %d: no MRT-R on 3D lattices", k);
     }
     if (p.store == LBM_STORE_F16S) {
         if (p.scale_log2 < 0 || p.scale_log2 > 24)
@@ -351,7 +352,7 @@ int set_velocity(lbm_ctx *c, Instance &in, const double *ux, const double *uy, c
     return rc;
 }
 
-bool is3d(const Instance &in) { return in.L.q == 19; }
+bool is3d(const Instance &in) { return in.L.q != 9; }
 
 // Enqueues one step of every instance on stream st.
 int enqueue_step(lbm_ctx *c, hipStream_t st)
@@ -456,7 +457,8 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
     if (rc) return rc;
     for (int k = 0; k < n_inst; ++k) {
         if (!f[k].phi0 || !f[k].ux || !f[k].uy) return fail(LBM_E_ARG, "instance %d: phi0, ux and uy are required", k);
-        if (p[k].lattice == LBM_LATTICE_D3Q19 && !f[k].uz) return fail(LBM_E_ARG, "instance %d: uz is required on D3Q19", k);
+        if (p[k].lattice != LBM_LATTICE_D2Q9 && !f[k].uz)
+            return fail(LBM_E_ARG, "instance %d: uz is required on 3D lattices", k);
         if (!f[k].D && !finite_pos(p[k].D_const))
             return fail(LBM_E_ARG, "instance %d: D_const must be finite and > 0 when D is NULL", k);
     }
@@ -579,7 +581,7 @@ int lbm_step(lbm_ctx *c, int32_t nsteps, const double *const *ux, const double *
     if (ux)
         for (int k = 0; k < n; ++k) {
             if (!ux[k] || !uy[k]) return fail(LBM_E_ARG, "lbm_step: instance %d: NULL velocity entry", k);
-            if (is3d(c->inst[k])) return fail(LBM_E_ARG, "lbm_step: instance %d is D3Q19: use lbm_set_velocity", k);
+            if (is3d(c->inst[k])) return fail(LBM_E_ARG, "lbm_step: instance %d is three-dimensional: use lbm_set_velocity", k);
         }
     int rc = LBM_OK;
     bool changed = false;
@@ -773,7 +775,7 @@ int adjoint_ok(lbm_ctx *c, int32_t inst, const char *who)
     if (in.p.aux == LBM_AUX_FLUX) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for the flux form of the aux term", who);
     if (in.p.boundary != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for Dirichlet edges or walls", who);
     if (in.p.tau3 != 0.0 && in.p.tau3 != 1.0) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for the MRT-R operator", who);
-    if (is3d(in)) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint on D3Q19", who);
+    if (is3d(in)) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint on 3D lattices", who);
     return LBM_OK;
 }
 }  // namespace

@@ -5,8 +5,8 @@
 //   populations  [ny][9][pitch]   element (i, y, x) at (y*9 + i)*pitch + x   ("row-interleaved")
 //   velocity     [ny][2][pitch]   u_x at (y*2)*pitch + x, u_y at (y*2 + 1)*pitch + x
 //   k, s         [ny][pitch]      scalar fields at y*pitch + x
-// A D3Q19 instance has ny*nz rows, row r = z*ny + y: populations [nz][ny][19][pitch], velocity
-// [nz][ny][3][pitch], k and s [nz][ny][pitch].
+// A D3Q19 (D3Q27) instance has ny*nz rows, row r = z*ny + y: populations [nz][ny][19 (27)][pitch],
+// velocity [nz][ny][3][pitch], k and s [nz][ny][pitch].
 // pitch = nx rounded up to a multiple of 64 elements, so every row segment starts 128-byte aligned for
 // every element size.  Keeping the nine segments of one lattice row next to each other turns the 18
 // concurrent streams of a step (9 reads at rows y-1, y, y+1 and 9 writes at row y) into accesses to
@@ -34,11 +34,11 @@ struct Layout {
     int32_t nx, ny;
     int64_t pitch;  // elements per row segment (multiple of 64)
     int32_t nz;     // 1 for D2Q9
-    int32_t q;      // velocities: 9 (D2Q9) or 19 (D3Q19)
+    int32_t q;      // velocities: 9 (D2Q9), 19 (D3Q19) or 27 (D3Q27)
 };
 
 __host__ __device__ __forceinline__ int64_t rows_of(const Layout &L) { return (int64_t)L.ny * L.nz; }
-__host__ __device__ __forceinline__ int dim_of(const Layout &L) { return L.q == 19 ? 3 : 2; }
+__host__ __device__ __forceinline__ int dim_of(const Layout &L) { return L.q == 9 ? 2 : 3; }
 __host__ __device__ __forceinline__ int64_t pop_elems(const Layout &L) { return rows_of(L) * L.q * L.pitch; }
 __host__ __device__ __forceinline__ int64_t vel_elems(const Layout &L) { return rows_of(L) * dim_of(L) * L.pitch; }
 __host__ __device__ __forceinline__ int64_t fld_elems(const Layout &L) { return rows_of(L) * L.pitch; }
@@ -169,7 +169,8 @@ hipError_t launch_macros_finalize(const double *partials, int nblocks, double *r
 hipError_t launch_populations(int mode, const PopArgs &a, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
 hipError_t launch_adjoint(int mode, int aux, const AdjArgs &a, hipStream_t st);
-// D3Q19 (lbm_kernels3d.hip): storage modes F64_F64, F64_F32, F32_F32; aux LOCAL or NONE; periodic.
+// D3Q19 and D3Q27 (lbm_kernels3d.hip, chosen by L.q): storage modes F64_F64, F64_F32, F32_F32; aux
+// LOCAL or NONE; periodic.
 hipError_t launch_step3(int mode, int aux, const StepArgs &a, hipStream_t st);
 hipError_t launch_init3(int mode, const InitArgs &a, hipStream_t st);
 hipError_t launch_macros3(int mode, const MacroArgs &a, double *result, hipStream_t st);

@@ -1,19 +1,22 @@
-// lbm_kernels3d.hip -- HIP kernels of the TRT-R step on the D3Q19 lattice for gfx950 (the
-// three-dimensional extension of Sec. 2.2).
+// lbm_kernels3d.hip -- HIP kernels of the TRT-R step on the D3Q19 and D3Q27 lattices for gfx950
+// (the three-dimensional extension of Sec. 2.2).
 //
 // Velocities (lattice units), in this order: 0:(0,0,0); 1,2:(+-1,0,0); 3,4:(0,+-1,0); 5,6:(0,0,+-1);
 // 7:(1,1,0) 8:(-1,-1,0) 9:(1,-1,0) 10:(-1,1,0); 11:(1,0,1) 12:(-1,0,-1) 13:(1,0,-1) 14:(-1,0,1);
-// 15:(0,1,1) 16:(0,-1,-1) 17:(0,1,-1) 18:(0,-1,1); weights 1/3, 1/18, 1/36; i and i + 1 (odd i) are
-// opposite.  One step of Eq. (14) in moment form (c_s^2 = 1/3):
+// 15:(0,1,1) 16:(0,-1,-1) 17:(0,1,-1) 18:(0,-1,1) (D3Q19: weights 1/3, 1/18, 1/36); D3Q27 adds
+// 19:(1,1,1) 20:(-1,-1,-1) 21:(1,1,-1) 22:(-1,-1,1) 23:(1,-1,1) 24:(-1,1,-1) 25:(-1,1,1)
+// 26:(1,-1,-1) (weights 8/27, 2/27, 1/54, 1/216).  i and i + 1 (odd i) are opposite.  One step of
+// Eq. (14) in moment form (c_s^2 = 1/3):
 //
 //   P_i = w_i [ a0 + 3 e_i.a1 + 9/2 (e_i.a2.e_i - tr a2 / 3) + 9/2 phi ((e_i.u)^3 - (e_i.u) |u|^2) ]
 //
 // with a0 = phi + s, a1 = phi u + w1 (j - phi u) + beta (A + u s), a2 = phi u u + w2 (Pi - phi I/3
 // - phi u u) exactly as on D2Q9 (Eqs. (3), (8), (12), (13), (16)), and the last term H3 : phi u u u,
-// the third-order part of the equilibrium (Eq. (6)) contracted in closed form; on D3Q19 the tensors
-// H_xxx and H_xyz vanish, so it carries exactly the xxy-type components the lattice supports.
+// the third-order part of the equilibrium (Eq. (6)) contracted in closed form.  H_xxx-type tensors
+// vanish at every velocity of both lattices and H_xyz at every D3Q19 velocity, so the closed form
+// carries exactly the components each lattice supports (D3Q27 keeps the xyz one).
 //
-// Layout: row r = z*ny + y holds the 19 segments of that lattice row; a wave owns one row of a
+// Layout: row r = z*ny + y holds the Q segments of that lattice row; a wave owns one row of a
 // 64-column tile, so the row bases of the nine rows (y, z), (y+-1, z), (y, z+-1), (y+-1, z+-1) it
 // pulls from are wave-uniform scalars and every access is base + 32-bit lane offset.  Stores are
 // non-temporal and tiles follow the XCD-contiguous order of the D2Q9 kernels.
@@ -23,10 +26,21 @@
 namespace lbm {
 namespace {
 
-constexpr int kQ3 = 19;
-constexpr int kEx3[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-constexpr int kEy3[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-constexpr int kEz3[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+constexpr int kEx3[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1};
+constexpr int kEy3[27] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, -1, 1, 1, -1};
+constexpr int kEz3[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1, 1, -1, -1, 1, 1, -1, 1, -1};
+
+// Weights of the rest, face (axis), edge and corner velocities.
+template <int Q>
+struct Weights3;
+template <>
+struct Weights3<19> {
+    static constexpr double rest = 1.0 / 3.0, face = 1.0 / 18.0, edge = 1.0 / 36.0;
+};
+template <>
+struct Weights3<27> {
+    static constexpr double rest = 8.0 / 27.0, face = 2.0 / 27.0, edge = 1.0 / 54.0, corner = 1.0 / 216.0;
+};
 
 template <class M>
 struct Coef3 {
@@ -34,19 +48,21 @@ struct Coef3 {
     M phi, ux, uy, uz;                                  // for the third-order equilibrium term
 };
 
-template <class M>
-__device__ __forceinline__ void reconstruct3(const Coef3<M> &c, M (&P)[19])
+template <int Q, class M>
+__device__ __forceinline__ void reconstruct3(const Coef3<M> &c, M (&P)[Q])
 {
+    using Wt = Weights3<Q>;
     const M usq = c.ux * c.ux + c.uy * c.uy + c.uz * c.uz;
-    const M base = c.a0 - M(1.5) * (c.axx + c.ayy + c.azz);
-    P[0] = M(1.0 / 3.0) * base;
+    const M tr = c.axx + c.ayy + c.azz;
+    const M base = c.a0 - M(1.5) * tr;
+    P[0] = M(Wt::rest) * base;
     auto pair = [&](int i, M w, M eu, M ea, M eae) {
         const M ev = w * (base + M(4.5) * eae);
         const M od = w * (M(3) * ea + M(4.5) * c.phi * eu * (eu * eu - usq));
         P[i] = ev + od;
         P[i + 1] = ev - od;
     };
-    const M wa = M(1.0 / 18.0), wd = M(1.0 / 36.0);
+    const M wa = M(Wt::face), wd = M(Wt::edge);
     pair(1, wa, c.ux, c.a1x, c.axx);
     pair(3, wa, c.uy, c.a1y, c.ayy);
     pair(5, wa, c.uz, c.a1z, c.azz);
@@ -56,10 +72,17 @@ __device__ __forceinline__ void reconstruct3(const Coef3<M> &c, M (&P)[19])
     pair(13, wd, c.ux - c.uz, c.a1x - c.a1z, c.axx + c.azz - M(2) * c.axz);
     pair(15, wd, c.uy + c.uz, c.a1y + c.a1z, c.ayy + c.azz + M(2) * c.ayz);
     pair(17, wd, c.uy - c.uz, c.a1y - c.a1z, c.ayy + c.azz - M(2) * c.ayz);
+    if constexpr (Q == 27) {  // corners (1,1,1), (1,1,-1), (1,-1,1), (-1,1,1) and their opposites
+        const M wc = M(Wt::corner);
+        pair(19, wc, c.ux + c.uy + c.uz, c.a1x + c.a1y + c.a1z, tr + M(2) * (c.axy + c.axz + c.ayz));
+        pair(21, wc, c.ux + c.uy - c.uz, c.a1x + c.a1y - c.a1z, tr + M(2) * (c.axy - c.axz - c.ayz));
+        pair(23, wc, c.ux - c.uy + c.uz, c.a1x - c.a1y + c.a1z, tr + M(2) * (c.axz - c.axy - c.ayz));
+        pair(25, wc, c.uy + c.uz - c.ux, c.a1y + c.a1z - c.a1x, tr + M(2) * (c.ayz - c.axy - c.axz));
+    }
 }
 
-template <class M>
-__device__ __forceinline__ void equilibrium3(M phi, M ux, M uy, M uz, M (&P)[19])
+template <int Q, class M>
+__device__ __forceinline__ void equilibrium3(M phi, M ux, M uy, M uz, M (&P)[Q])
 {
     Coef3<M> c;
     c.a0 = phi;
@@ -76,29 +99,44 @@ __device__ __forceinline__ void equilibrium3(M phi, M ux, M uy, M uz, M (&P)[19]
     c.ux = ux;
     c.uy = uy;
     c.uz = uz;
-    reconstruct3<M>(c, P);
+    reconstruct3<Q, M>(c, P);
 }
 
 // TRT-R collision plus source and auxiliary term (A = phi u.grad u, lattice units).
-template <class M>
-__device__ __forceinline__ void collide3(const M (&g)[19], M ux, M uy, M uz, const Relax<M> &r, M Ax, M Ay, M Az,
-                                         M s, M (&P)[19])
+template <int Q, class M>
+__device__ __forceinline__ void collide3(const M (&g)[Q], M ux, M uy, M uz, const Relax<M> &r, M Ax, M Ay, M Az,
+                                         M s, M (&P)[Q])
 {
     M phi = g[0];
 #pragma unroll
-    for (int i = 1; i < 19; ++i) phi += g[i];
-    const M jx = (g[1] - g[2]) + (g[7] - g[8]) + (g[9] - g[10]) + (g[11] - g[12]) + (g[13] - g[14]);
-    const M jy = (g[3] - g[4]) + (g[7] - g[8]) - (g[9] - g[10]) + (g[15] - g[16]) + (g[17] - g[18]);
-    const M jz = (g[5] - g[6]) + (g[11] - g[12]) - (g[13] - g[14]) + (g[15] - g[16]) - (g[17] - g[18]);
+    for (int i = 1; i < Q; ++i) phi += g[i];
+    M jx = (g[1] - g[2]) + (g[7] - g[8]) + (g[9] - g[10]) + (g[11] - g[12]) + (g[13] - g[14]);
+    M jy = (g[3] - g[4]) + (g[7] - g[8]) - (g[9] - g[10]) + (g[15] - g[16]) + (g[17] - g[18]);
+    M jz = (g[5] - g[6]) + (g[11] - g[12]) - (g[13] - g[14]) + (g[15] - g[16]) - (g[17] - g[18]);
     const M sxy = (g[7] + g[8]) + (g[9] + g[10]);
     const M sxz = (g[11] + g[12]) + (g[13] + g[14]);
     const M syz = (g[15] + g[16]) + (g[17] + g[18]);
-    const M pxx = (g[1] + g[2]) + sxy + sxz;
-    const M pyy = (g[3] + g[4]) + sxy + syz;
-    const M pzz = (g[5] + g[6]) + sxz + syz;
-    const M pxy = (g[7] + g[8]) - (g[9] + g[10]);
-    const M pxz = (g[11] + g[12]) - (g[13] + g[14]);
-    const M pyz = (g[15] + g[16]) - (g[17] + g[18]);
+    M pxx = (g[1] + g[2]) + sxy + sxz;
+    M pyy = (g[3] + g[4]) + sxy + syz;
+    M pzz = (g[5] + g[6]) + sxz + syz;
+    M pxy = (g[7] + g[8]) - (g[9] + g[10]);
+    M pxz = (g[11] + g[12]) - (g[13] + g[14]);
+    M pyz = (g[15] + g[16]) - (g[17] + g[18]);
+    if constexpr (Q == 27) {
+        // differences and sums of the opposite corner pairs along (1,1,1), (1,1,-1), (1,-1,1), (-1,1,1)
+        const M da = g[19] - g[20], db = g[21] - g[22], dc = g[23] - g[24], dd = g[25] - g[26];
+        const M sa = g[19] + g[20], sb = g[21] + g[22], sc = g[23] + g[24], sd = g[25] + g[26];
+        jx += (da + db) + (dc - dd);
+        jy += (da + db) - (dc - dd);
+        jz += (da - db) + (dc + dd);
+        const M sall = (sa + sb) + (sc + sd);
+        pxx += sall;
+        pyy += sall;
+        pzz += sall;
+        pxy += (sa + sb) - (sc + sd);
+        pxz += (sa - sb) + (sc - sd);
+        pyz += (sa - sb) - (sc - sd);
+    }
     const M pux = phi * ux, puy = phi * uy, puz = phi * uz, third = phi * M(1.0 / 3.0);
     Coef3<M> c;
     c.a0 = phi + s;
@@ -116,29 +154,29 @@ __device__ __forceinline__ void collide3(const M (&g)[19], M ux, M uy, M uz, con
     c.ux = ux;
     c.uy = uy;
     c.uz = uz;
-    reconstruct3<M>(c, P);
+    reconstruct3<Q, M>(c, P);
 }
 
 // g_i(x, y, z) = buf_i(x - e_i) for one node (diagnostics).
-template <class St, class M>
+template <int Q, class St, class M>
 __device__ __forceinline__ void pull_node3(const typename St::T *__restrict__ src, const Layout &L, int x, int y, int z,
-                                           M (&g)[19])
+                                           M (&g)[Q])
 {
     using C = Codec<St, M>;
     const F16Params none{};
 #pragma unroll
-    for (int i = 0; i < kQ3; ++i) {
+    for (int i = 0; i < Q; ++i) {
         int xs = x - kEx3[i], ys = y - kEy3[i], zs = z - kEz3[i];
         xs = xs < 0 ? xs + L.nx : (xs >= L.nx ? xs - L.nx : xs);
         ys = ys < 0 ? ys + L.ny : (ys >= L.ny ? ys - L.ny : ys);
         zs = zs < 0 ? zs + L.nz : (zs >= L.nz ? zs - L.nz : zs);
-        g[i] = C::dec(src[(((int64_t)zs * L.ny + ys) * kQ3 + i) * L.pitch + xs], i, none);
+        g[i] = C::dec(src[(((int64_t)zs * L.ny + ys) * Q + i) * L.pitch + xs], i, none);
     }
 }
 
 // Unlike the D2Q9 kernel this one keeps the walking loop for the one-row default: a compile-time
 // one-row instantiation frees VGPRs but measured 2-8 % slower at 256^3 and 384^3.
-template <int MODE, int AUX, bool HAS_K, bool HAS_S>
+template <int Q, int MODE, int AUX, bool HAS_K, bool HAS_S>
 __global__ __launch_bounds__(256) void step3_kernel(const StepArgs sa)
 {
     using St = typename ModeTraits<MODE>::St;
@@ -176,14 +214,14 @@ __global__ __launch_bounds__(256) void step3_kernel(const StepArgs sa)
     for (int r = r0; r < r1; ++r) {
         const int z = r / ny, y = r - z * ny;
         const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny), zm = wrap_dec(z, nz), zp = wrap_inc(z, nz);
-        auto blk = [&](int yy, int zz) { return src + ((int64_t)zz * ny + yy) * kQ3 * pitch; };
+        auto blk = [&](int yy, int zz) { return src + ((int64_t)zz * ny + yy) * Q * pitch; };
         const T *__restrict__ b00 = blk(y, z);
         const T *__restrict__ bm0 = blk(ym, z);
         const T *__restrict__ bp0 = blk(yp, z);
         const T *__restrict__ b0m = blk(y, zm);
         const T *__restrict__ b0p = blk(y, zp);
         const F16Params &f = a.f16;
-        M g[19];
+        M g[Q];
         g[0] = C::dec(ld_at(b00, bc), 0, f);
         g[1] = C::dec(ld_at(b00 + 1 * pitch, bm), 1, f);
         g[2] = C::dec(ld_at(b00 + 2 * pitch, bp), 2, f);
@@ -203,6 +241,16 @@ __global__ __launch_bounds__(256) void step3_kernel(const StepArgs sa)
         g[16] = C::dec(ld_at(blk(yp, zp) + 16 * pitch, bc), 16, f);
         g[17] = C::dec(ld_at(blk(ym, zp) + 17 * pitch, bc), 17, f);
         g[18] = C::dec(ld_at(blk(yp, zm) + 18 * pitch, bc), 18, f);
+        if constexpr (Q == 27) {  // corners: pulled from (x - e_x, y - e_y, z - e_z)
+            g[19] = C::dec(ld_at(blk(ym, zm) + 19 * pitch, bm), 19, f);
+            g[20] = C::dec(ld_at(blk(yp, zp) + 20 * pitch, bp), 20, f);
+            g[21] = C::dec(ld_at(blk(ym, zp) + 21 * pitch, bm), 21, f);
+            g[22] = C::dec(ld_at(blk(yp, zm) + 22 * pitch, bp), 22, f);
+            g[23] = C::dec(ld_at(blk(yp, zm) + 23 * pitch, bm), 23, f);
+            g[24] = C::dec(ld_at(blk(ym, zp) + 24 * pitch, bp), 24, f);
+            g[25] = C::dec(ld_at(blk(ym, zm) + 25 * pitch, bp), 25, f);
+            g[26] = C::dec(ld_at(blk(yp, zp) + 26 * pitch, bm), 26, f);
+        }
 
         auto vrow = [&](int yy, int zz) { return u + ((int64_t)zz * ny + yy) * 3 * pitch; };
         const M *__restrict__ uc = vrow(y, z);
@@ -211,7 +259,7 @@ __global__ __launch_bounds__(256) void step3_kernel(const StepArgs sa)
         if (AUX == 0) {  // Eq. (16): phi u_b d_b u_a, central differences of u
             M phi = g[0];
 #pragma unroll
-            for (int i = 1; i < 19; ++i) phi += g[i];
+            for (int i = 1; i < Q; ++i) phi += g[i];
             const M *__restrict__ uym = vrow(ym, z), *__restrict__ uyp = vrow(yp, z);
             const M *__restrict__ uzm = vrow(y, zm), *__restrict__ uzp = vrow(y, zp);
             M dd[3];
@@ -228,17 +276,17 @@ __global__ __launch_bounds__(256) void step3_kernel(const StepArgs sa)
         }
         const Relax<M> rr = HAS_K ? relax_from_k<M>(ld_at(kf + (int64_t)r * pitch, fc), (M)a.lambda, M(0)) : rconst;
         const M s = HAS_S ? ld_at(sf + (int64_t)r * pitch, fc) : M(0);
-        M P[19];
-        collide3<M>(g, ux, uy, uz, rr, Ax, Ay, Az, s, P);
+        M P[Q];
+        collide3<Q, M>(g, ux, uy, uz, rr, Ax, Ay, Az, s, P);
         if (live) {
-            T *__restrict__ out = dst + (int64_t)r * kQ3 * pitch;
+            T *__restrict__ out = dst + (int64_t)r * Q * pitch;
 #pragma unroll
-            for (int i = 0; i < kQ3; ++i) st_nt_at(out + i * pitch, bc, C::enc(P[i], i, f));
+            for (int i = 0; i < Q; ++i) st_nt_at(out + i * pitch, bc, C::enc(P[i], i, f));
         }
     }
 }
 
-template <int MODE>
+template <int Q, int MODE>
 __global__ __launch_bounds__(256) void init3_kernel(const InitArgs a)
 {
     using St = typename ModeTraits<MODE>::St;
@@ -254,20 +302,20 @@ __global__ __launch_bounds__(256) void init3_kernel(const InitArgs a)
         const int64_t r = n / nx;
         const int y = (int)(r % ny), z = (int)(r / ny);
         const M *ur = u + r * 3 * pitch;
-        M P[19];
-        equilibrium3<M>((M)a.phi0[n], ur[x], ur[pitch + x], ur[2 * pitch + x], P);
+        M P[Q];
+        equilibrium3<Q, M>((M)a.phi0[n], ur[x], ur[pitch + x], ur[2 * pitch + x], P);
 #pragma unroll
-        for (int i = 0; i < kQ3; ++i) {  // written pre-shifted: buf_i(x - e_i) = g_eq_i(x)
+        for (int i = 0; i < Q; ++i) {  // written pre-shifted: buf_i(x - e_i) = g_eq_i(x)
             int xd = x - kEx3[i], yd = y - kEy3[i], zd = z - kEz3[i];
             xd = xd < 0 ? xd + nx : (xd >= nx ? xd - nx : xd);
             yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
             zd = zd < 0 ? zd + nz : (zd >= nz ? zd - nz : zd);
-            dst[(((int64_t)zd * ny + yd) * kQ3 + i) * pitch + xd] = C::enc(P[i], i, a.f16);
+            dst[(((int64_t)zd * ny + yd) * Q + i) * pitch + xd] = C::enc(P[i], i, a.f16);
         }
     }
 }
 
-template <int MODE>
+template <int Q, int MODE>
 __global__ __launch_bounds__(256) void macros3_kernel(const MacroArgs a)
 {
     using St = typename ModeTraits<MODE>::St;
@@ -281,11 +329,11 @@ __global__ __launch_bounds__(256) void macros3_kernel(const MacroArgs a)
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(n % nx);
         const int64_t r = n / nx;
-        M g[19];
-        pull_node3<St, M>(src, a.L, x, (int)(r % ny), (int)(r / ny), g);
+        M g[Q];
+        pull_node3<Q, St, M>(src, a.L, x, (int)(r % ny), (int)(r / ny), g);
         double phi = 0;
 #pragma unroll
-        for (int i = 0; i < kQ3; ++i) phi += (double)g[i];
+        for (int i = 0; i < Q; ++i) phi += (double)g[i];
         if (a.phi_out) a.phi_out[n] = phi;
         if (!isfinite(phi)) {
             nonfinite += 1;
@@ -313,7 +361,7 @@ __global__ __launch_bounds__(256) void macros3_kernel(const MacroArgs a)
     }
 }
 
-template <int MODE>
+template <int Q, int MODE>
 __global__ __launch_bounds__(256) void populations3_kernel(const PopArgs a)
 {
     using St = typename ModeTraits<MODE>::St;
@@ -325,32 +373,32 @@ __global__ __launch_bounds__(256) void populations3_kernel(const PopArgs a)
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(n % nx);
         const int64_t r = n / nx;
-        M g[19];
-        pull_node3<St, M>(src, a.L, x, (int)(r % ny), (int)(r / ny), g);
+        M g[Q];
+        pull_node3<Q, St, M>(src, a.L, x, (int)(r % ny), (int)(r / ny), g);
 #pragma unroll
-        for (int i = 0; i < kQ3; ++i) a.out[i * N + n] = (double)g[i];
+        for (int i = 0; i < Q; ++i) a.out[i * N + n] = (double)g[i];
     }
 }
 
-template <int MODE, int AUX>
+template <int Q, int MODE, int AUX>
 hipError_t launch_step3_aux(const StepArgs &a, hipStream_t st)
 {
     dim3 block(64, 4);
     const int nblocks = tiles_of(a.d.L, a.d.lc.rows);
     const bool hk = a.d.has_k, hs = a.d.has_s;
-    if (hk && hs) step3_kernel<MODE, AUX, true, true><<<nblocks, block, 0, st>>>(a);
-    else if (hk) step3_kernel<MODE, AUX, true, false><<<nblocks, block, 0, st>>>(a);
-    else if (hs) step3_kernel<MODE, AUX, false, true><<<nblocks, block, 0, st>>>(a);
-    else step3_kernel<MODE, AUX, false, false><<<nblocks, block, 0, st>>>(a);
+    if (hk && hs) step3_kernel<Q, MODE, AUX, true, true><<<nblocks, block, 0, st>>>(a);
+    else if (hk) step3_kernel<Q, MODE, AUX, true, false><<<nblocks, block, 0, st>>>(a);
+    else if (hs) step3_kernel<Q, MODE, AUX, false, true><<<nblocks, block, 0, st>>>(a);
+    else step3_kernel<Q, MODE, AUX, false, false><<<nblocks, block, 0, st>>>(a);
     return hipGetLastError();
 }
 
-template <int MODE>
+template <int Q, int MODE>
 hipError_t launch_step3_mode(int aux, const StepArgs &a, hipStream_t st)
 {
     switch (aux) {
-    case 0: return launch_step3_aux<MODE, 0>(a, st);
-    case 2: return launch_step3_aux<MODE, 2>(a, st);
+    case 0: return launch_step3_aux<Q, MODE, 0>(a, st);
+    case 2: return launch_step3_aux<Q, MODE, 2>(a, st);
     default: return hipErrorInvalidValue;  // the flux form is two-dimensional only
     }
 }
@@ -359,34 +407,43 @@ hipError_t launch_step3_mode(int aux, const StepArgs &a, hipStream_t st)
 
 hipError_t launch_step3(int mode, int aux, const StepArgs &a, hipStream_t st)
 {
-    if (a.d.lc.rows < 1 || a.d.lc.rows > 64 || a.d.L.q != kQ3) return hipErrorInvalidValue;
+    if (a.d.lc.rows < 1 || a.d.lc.rows > 64) return hipErrorInvalidValue;
+    if (a.d.L.q != 19 && a.d.L.q != 27) return hipErrorInvalidValue;
+    const bool q27 = a.d.L.q == 27;
     switch (mode) {
-    case MODE_F64_F64: return launch_step3_mode<MODE_F64_F64>(aux, a, st);
-    case MODE_F64_F32: return launch_step3_mode<MODE_F64_F32>(aux, a, st);
-    case MODE_F32_F32: return launch_step3_mode<MODE_F32_F32>(aux, a, st);
+    case MODE_F64_F64:
+        return q27 ? launch_step3_mode<27, MODE_F64_F64>(aux, a, st) : launch_step3_mode<19, MODE_F64_F64>(aux, a, st);
+    case MODE_F64_F32:
+        return q27 ? launch_step3_mode<27, MODE_F64_F32>(aux, a, st) : launch_step3_mode<19, MODE_F64_F32>(aux, a, st);
+    case MODE_F32_F32:
+        return q27 ? launch_step3_mode<27, MODE_F32_F32>(aux, a, st) : launch_step3_mode<19, MODE_F32_F32>(aux, a, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_init3(int mode, const InitArgs &a, hipStream_t st)
+namespace {
+
+template <int Q>
+hipError_t launch_init3_q(int mode, const InitArgs &a, hipStream_t st)
 {
     const int g = grid_for((int64_t)a.L.nx * a.L.ny * a.L.nz, 256, 8192);
     switch (mode) {
-    case MODE_F64_F64: init3_kernel<MODE_F64_F64><<<g, 256, 0, st>>>(a); break;
-    case MODE_F64_F32: init3_kernel<MODE_F64_F32><<<g, 256, 0, st>>>(a); break;
-    case MODE_F32_F32: init3_kernel<MODE_F32_F32><<<g, 256, 0, st>>>(a); break;
+    case MODE_F64_F64: init3_kernel<Q, MODE_F64_F64><<<g, 256, 0, st>>>(a); break;
+    case MODE_F64_F32: init3_kernel<Q, MODE_F64_F32><<<g, 256, 0, st>>>(a); break;
+    case MODE_F32_F32: init3_kernel<Q, MODE_F32_F32><<<g, 256, 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_macros3(int mode, const MacroArgs &a, double *result, hipStream_t st)
+template <int Q>
+hipError_t launch_macros3_q(int mode, const MacroArgs &a, double *result, hipStream_t st)
 {
     const int g = grid_for((int64_t)a.L.nx * a.L.ny * a.L.nz, 256, kMacroBlocks);
     switch (mode) {
-    case MODE_F64_F64: macros3_kernel<MODE_F64_F64><<<g, 256, 0, st>>>(a); break;
-    case MODE_F64_F32: macros3_kernel<MODE_F64_F32><<<g, 256, 0, st>>>(a); break;
-    case MODE_F32_F32: macros3_kernel<MODE_F32_F32><<<g, 256, 0, st>>>(a); break;
+    case MODE_F64_F64: macros3_kernel<Q, MODE_F64_F64><<<g, 256, 0, st>>>(a); break;
+    case MODE_F64_F32: macros3_kernel<Q, MODE_F64_F32><<<g, 256, 0, st>>>(a); break;
+    case MODE_F32_F32: macros3_kernel<Q, MODE_F32_F32><<<g, 256, 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
@@ -394,16 +451,40 @@ hipError_t launch_macros3(int mode, const MacroArgs &a, double *result, hipStrea
     return launch_macros_finalize(a.partials, g, result, st);
 }
 
-hipError_t launch_populations3(int mode, const PopArgs &a, hipStream_t st)
+template <int Q>
+hipError_t launch_populations3_q(int mode, const PopArgs &a, hipStream_t st)
 {
     const int g = grid_for((int64_t)a.L.nx * a.L.ny * a.L.nz, 256, 8192);
     switch (mode) {
-    case MODE_F64_F64: populations3_kernel<MODE_F64_F64><<<g, 256, 0, st>>>(a); break;
-    case MODE_F64_F32: populations3_kernel<MODE_F64_F32><<<g, 256, 0, st>>>(a); break;
-    case MODE_F32_F32: populations3_kernel<MODE_F32_F32><<<g, 256, 0, st>>>(a); break;
+    case MODE_F64_F64: populations3_kernel<Q, MODE_F64_F64><<<g, 256, 0, st>>>(a); break;
+    case MODE_F64_F32: populations3_kernel<Q, MODE_F64_F32><<<g, 256, 0, st>>>(a); break;
+    case MODE_F32_F32: populations3_kernel<Q, MODE_F32_F32><<<g, 256, 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_init3(int mode, const InitArgs &a, hipStream_t st)
+{
+    if (a.L.q == 27) return launch_init3_q<27>(mode, a, st);
+    if (a.L.q == 19) return launch_init3_q<19>(mode, a, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_macros3(int mode, const MacroArgs &a, double *result, hipStream_t st)
+{
+    if (a.L.q == 27) return launch_macros3_q<27>(mode, a, result, st);
+    if (a.L.q == 19) return launch_macros3_q<19>(mode, a, result, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_populations3(int mode, const PopArgs &a, hipStream_t st)
+{
+    if (a.L.q == 27) return launch_populations3_q<27>(mode, a, st);
+    if (a.L.q == 19) return launch_populations3_q<19>(mode, a, st);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace lbm

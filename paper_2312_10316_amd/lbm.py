@@ -20,7 +20,8 @@ LBM_STORE_F64, LBM_STORE_F32, LBM_STORE_F16S = 0, 1, 2
 LBM_MATH_F64, LBM_MATH_F32 = 0, 1
 LBM_AUX_LOCAL, LBM_AUX_FLUX, LBM_AUX_NONE = 0, 1, 2
 LBM_BC_PERIODIC, LBM_BC_NEE, LBM_BC_WALLS = 0, 1, 2
-LBM_LATTICE_D2Q9, LBM_LATTICE_D3Q19 = 0, 1
+LBM_LATTICE_D2Q9, LBM_LATTICE_D3Q19, LBM_LATTICE_D3Q27 = 0, 1, 2
+LATTICE_Q = {LBM_LATTICE_D2Q9: 9, LBM_LATTICE_D3Q19: 19, LBM_LATTICE_D3Q27: 27}
 
 # names of the population storage / arithmetic combinations
 MODES = {
@@ -151,10 +152,14 @@ def _ptr_array(ts: Optional[Sequence[Optional[torch.Tensor]]]):
 
 
 def make_params(nx, ny, dx, dt, lam, D_const=0.0, mode="f64", aux=LBM_AUX_LOCAL, scale_log2=15,
-                phi_ref=0.0, boundary=LBM_BC_PERIODIC, tau3=0.0, nz=0) -> lbm_params:
-    """nz >= 3 selects the D3Q19 lattice (nx * ny * nz nodes); nz = 0 is D2Q9."""
+                phi_ref=0.0, boundary=LBM_BC_PERIODIC, tau3=0.0, nz=0, lattice=None) -> lbm_params:
+    """nz >= 3 selects a 3D lattice (nx * ny * nz nodes): D3Q19 unless lattice says D3Q27 (19 or 27
+    are accepted for the LBM_LATTICE_* values); nz = 0 is D2Q9."""
     store, math = MODES[mode]
-    lattice = LBM_LATTICE_D3Q19 if nz else LBM_LATTICE_D2Q9
+    if lattice is None:
+        lattice = LBM_LATTICE_D3Q19 if nz else LBM_LATTICE_D2Q9
+    else:
+        lattice = {9: LBM_LATTICE_D2Q9, 19: LBM_LATTICE_D3Q19, 27: LBM_LATTICE_D3Q27}.get(int(lattice), int(lattice))
     return lbm_params(int(nx), int(ny), float(dx), float(dt), float(lam), float(D_const), store, math, int(aux),
                       int(scale_log2), float(phi_ref), int(boundary), 0, float(tau3), lattice, int(nz))
 
@@ -176,8 +181,8 @@ def lbm_workspace_size(params: Sequence[lbm_params]) -> int:
 
 def lbm_init(params: Sequence[lbm_params], fields: Sequence[dict], workspace: Optional[torch.Tensor] = None,
              stream: Optional[torch.cuda.Stream] = None) -> ctypes.c_void_p:
-    """fields[k]: dict with device FP64 tensors phi0, ux, uy, optional D, and uz on D3Q19 (each [ny, nx],
-    D3Q19 [nz, ny, nx])."""
+    """fields[k]: dict with device FP64 tensors phi0, ux, uy, optional D, and uz on 3D lattices (each
+    [ny, nx], 3D [nz, ny, nx])."""
     n = len(params)
     parr = (lbm_params * n)(*params)
     farr = (lbm_fields * n)(*[lbm_fields(_dptr(f["phi0"]), _dptr(f["ux"]), _dptr(f["uy"]), _dptr(f.get("D")),

@@ -29,10 +29,10 @@ class Solver:
 
     def _shape(self, inst: int):
         p = self.params[inst]
-        return (p.nz, p.ny, p.nx) if p.lattice == L.LBM_LATTICE_D3Q19 else (p.ny, p.nx)
+        return (p.ny, p.nx) if p.lattice == L.LBM_LATTICE_D2Q9 else (p.nz, p.ny, p.nx)
 
     def _q(self, inst: int) -> int:
-        return 19 if self.params[inst].lattice == L.LBM_LATTICE_D3Q19 else 9
+        return L.LATTICE_Q[self.params[inst].lattice]
 
     def set_velocity(self, ux: torch.Tensor, uy: torch.Tensor, uz: Optional[torch.Tensor] = None,
                      inst: int = 0) -> None:

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True, check=True).stdout
     exported = set(re.findall(r" T (lbm_\w+)$", out, flags=re.M))
     assert set(declared_functions()) <= exported
-    assert L.lbm_abi_version() == 4
+    assert L.lbm_abi_version() == 5
 
 
 def test_struct_layout_matches_header(tmp_path):
@@ -111,20 +111,34 @@ def test_maximum_sizes():
 @pytest.mark.parametrize("kw,msg", [
     (dict(nz=2), "must be >= 3"),
     (dict(nz=-5), "must be >= 3"),
+    (dict(nz=2, lattice=27), "must be >= 3"),
+    (dict(nz=8, lattice=3), "unknown lattice"),
+    (dict(nz=8, lattice=-1), "unknown lattice"),
 ])
-def test_invalid_d3q19_parameters(kw, msg):
+def test_invalid_3d_parameters(kw, msg):
     with pytest.raises(L.LbmError) as ei:
         L.lbm_workspace_size([_p(**kw)])
     assert ei.value.status == L.LBM_E_ARG
     assert msg in str(ei.value)
 
 
-def test_d3q19_unsupported_combinations():
-    for kw in (dict(nz=8, mode="f16s"), dict(nz=8, aux=L.LBM_AUX_FLUX), dict(nz=8, boundary=L.LBM_BC_NEE),
-               dict(nz=8, tau3=0.9)):
+@pytest.mark.parametrize("q", [19, 27])
+def test_3d_unsupported_combinations(q):
+    for kw in (dict(mode="f16s"), dict(aux=L.LBM_AUX_FLUX), dict(boundary=L.LBM_BC_NEE), dict(tau3=0.9)):
         with pytest.raises(L.LbmError) as ei:
-            L.lbm_workspace_size([_p(**kw)])
+            L.lbm_workspace_size([_p(nz=8, lattice=q, **kw)])
         assert ei.value.status == L.LBM_E_UNSUPPORTED, kw
+
+
+def test_d3q27_workspace_holds_27_planes():
+    """Two population buffers of 27 planes (plus the same fields as D3Q19): the difference to a
+    D3Q19 instance of the same size is exactly 2 x 8 planes of the storage type."""
+    for mode, elem in (("f64", 8), ("f32", 4)):
+        a = L.lbm_workspace_size([_p(nx=100, ny=20, nz=10, mode=mode, lattice=19)])
+        b = L.lbm_workspace_size([_p(nx=100, ny=20, nz=10, mode=mode, lattice=27)])
+        pitch = L.pitch_of(_p(nx=100, ny=20, nz=10, mode=mode, lattice=27))
+        assert b - a >= 2 * 8 * 20 * 10 * pitch * elem
+        assert b - a <= 2 * 8 * 20 * 10 * pitch * elem + 4096
 
 
 def test_fp64_math_needs_fp64_storage():
