@@ -197,10 +197,17 @@ int lbm_state_save(lbm_ctx *ctx, int32_t inst, void *dst);
 int lbm_state_load(lbm_ctx *ctx, int32_t inst, const void *src, int64_t step);
 
 /* Launch shape of the step kernel.  A tuning knob only: results are bitwise independent of it.
- * Tiles are 64 columns wide; each of a block's 4 waves walks `rows` consecutive lattice rows. */
+ * A block is 4 waves of 64 lanes (lane = column); each wave walks `rows` consecutive lattice rows.
+ * tile_width 64 stacks the block's waves along y (tiles of 64 columns x 4*rows rows); 256 puts them
+ * side by side along x (256 columns x rows rows), so that each population row segment a block
+ * reads or writes is 1 KiB (FP32) of contiguous memory.  max_waves caps the waves resident on each
+ * SIMD (3..8; 0: as many as the registers allow) by reserving unused LDS per block; it applies to
+ * one-instance launches (the SERIAL policy), not to the batched kernel. */
 typedef struct lbm_launch {
-    int32_t rows;       /* 1..64 */
-    int32_t xcd_remap;  /* 1: consecutive tiles go to blocks on the same XCD (shared L2); 0: hardware order */
+    int32_t rows;        /* 1..64 */
+    int32_t xcd_remap;   /* 1: consecutive tiles go to blocks on the same XCD (shared L2); 0: hardware order */
+    int32_t tile_width;  /* 64 or 256 */
+    int32_t max_waves;   /* 0 or 3..8 */
 } lbm_launch;
 
 /* Sets (inst = -1: every instance) or reads the launch shape; captured step graphs are dropped.

@@ -1,6 +1,7 @@
-"""Autotuner for the step launch: tile shape (rows walked per wave, XCD tile order) and, for a
-multi-instance context, the batch schedule (serial launches, one flat launch, or persistent blocks
-with a round-robin or longest-processing-time assignment of tiles).
+"""Autotuner for the step launch: tile shape (rows walked per wave, XCD tile order, 64- or
+256-column tiles), a cap on the waves resident per SIMD, and, for a multi-instance context, the
+batch schedule (serial launches, one flat launch, or persistent blocks with a round-robin or
+longest-processing-time assignment of tiles).
 
 Candidates are timed on the caller's own instances with graph-replayed steps; the instances' states
 and step counters are saved first and restored afterwards, so tuning never advances the simulation
@@ -25,32 +26,34 @@ def _key(solver) -> str:
     dev = torch.cuda.get_device_name()
     shapes = [(p.nx, p.ny, p.nz, p.lattice, p.store, p.math, p.aux, p.boundary, p.tau3 not in (0.0, 1.0))
               for p in solver.params]
-    return hashlib.sha256(json.dumps([dev, shapes]).encode()).hexdigest()[:20]
+    return hashlib.sha256(json.dumps(["launch-v2", dev, shapes]).encode()).hexdigest()[:20]
 
 
 def default_candidates(solver) -> list:
-    """(rows, xcd_remap, policy, blocks) tuples worth timing for this context."""
-    rows_set = (1, 2, 4)
+    """(rows, xcd_remap, tile_width, max_waves, policy, blocks) tuples worth timing for this context."""
     out = []
     multi = len(solver.params) > 1 and len({(p.store, p.math, p.aux) for p in solver.params}) == 1
     if not multi:
-        for rows in rows_set:
-            for remap in (0, 1):
-                out.append((rows, remap, L.LBM_BATCH_SERIAL, 0))
+        for width, rows_set in ((64, (1, 2, 4)), (256, (1, 2))):
+            for rows in rows_set:
+                for remap in (0, 1):
+                    for cap in (0, 4, 5):
+                        out.append((rows, remap, width, cap, L.LBM_BATCH_SERIAL, 0))
         return out
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
-    for rows in rows_set:
-        out.append((rows, 1, L.LBM_BATCH_SERIAL, 0))
-        out.append((rows, 1, L.LBM_BATCH_FLAT, 0))
-        for mult in (2, 4, 8):
-            out.append((rows, 1, L.LBM_BATCH_LPT, mult * ncu))
-        out.append((rows, 1, L.LBM_BATCH_STRIDED, 4 * ncu))
+    for width in (64, 256):
+        for rows in (1, 2, 4):
+            out.append((rows, 1, width, 0, L.LBM_BATCH_SERIAL, 0))
+            out.append((rows, 1, width, 0, L.LBM_BATCH_FLAT, 0))
+            for mult in (2, 4, 8):
+                out.append((rows, 1, width, 0, L.LBM_BATCH_LPT, mult * ncu))
+            out.append((rows, 1, width, 0, L.LBM_BATCH_STRIDED, 4 * ncu))
     return out
 
 
 def _apply(solver, cand) -> None:
-    rows, remap, policy, blocks = cand
-    solver.set_launch(rows, remap)
+    rows, remap, width, cap, policy, blocks = cand
+    solver.set_launch(rows, remap, tile_width=width, max_waves=cap)
     if len(solver.params) > 1:
         try:
             solver.set_batch(policy, blocks)
@@ -77,7 +80,8 @@ def _time(solver, steps: int, reps: int) -> float:
 def tune(solver, candidates: Optional[Iterable] = None, steps: int = 64, reps: int = 2,
          cache_path: Optional[str] = None, force: bool = False) -> dict:
     """Times every candidate, applies the fastest and returns
-    {"best": (rows, xcd_remap, policy, blocks), "ms_per_step": {...}, "cached": bool}."""
+    {"best": (rows, xcd_remap, tile_width, max_waves, policy, blocks), "ms_per_step": {...},
+    "cached": bool}."""
     key = _key(solver)
     cached = None
     if not force:
@@ -101,7 +105,8 @@ def tune(solver, candidates: Optional[Iterable] = None, steps: int = 64, reps: i
             times[json.dumps(list(cand))] = _time(solver, steps, reps)
     finally:
         for k in range(n):
-            solver.set_launch(old_launch[k]["rows"], old_launch[k]["xcd_remap"], inst=k)
+            o = old_launch[k]
+            solver.set_launch(o["rows"], o["xcd_remap"], inst=k, tile_width=o["tile_width"], max_waves=o["max_waves"])
         if old_batch is not None:
             solver.set_batch(old_batch["policy"], old_batch["blocks"])
         for k in range(n):

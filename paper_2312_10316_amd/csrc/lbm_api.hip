@@ -67,17 +67,39 @@ Layout layout_of(const lbm_params &p)
     return L;
 }
 
-// Default launch shape (measured on MI355X at 2048^2 and 8192^2; the autotuner in the Python
-// package can override it per instance): one row per wave with XCD-contiguous tiles for every
-// storage mode (the one-row kernels are compiled without a walking loop).  The flux form of the
-// aux term pulls one extra row per walk, so it walks 8 rows.
-// D3Q19 and D3Q27: one row per wave; XCD-contiguous tiles for FP32 storage, hardware order for FP64
-// storage (measured on D3Q19 at 256^3 and 384^3: +5 % each way).
-Launch default_launch(int mode, int aux, int lattice)
+// Dynamic LDS that a 256-thread block must reserve so that at most max_waves of its waves are
+// resident per SIMD (4 waves per block, 4 SIMDs per CU: max_waves blocks per CU): half-way between
+// the per-block sizes that fit max_waves + 1 and max_waves blocks in the CU's LDS, so allocation
+// granularity cannot tip the count.  0 (no cap) when the LDS size is unknown.
+int lds_reserve_for(int max_waves, int lds_per_cu)
 {
-    if (lattice != LBM_LATTICE_D2Q9) return Launch{1, mode == MODE_F32_F32 ? 1 : 0};
-    if (aux == LBM_AUX_FLUX) return Launch{8, 1};
-    return Launch{1, 1};
+    if (max_waves <= 0 || lds_per_cu <= 0) return 0;
+    const int lo = lds_per_cu / (max_waves + 1), hi = lds_per_cu / max_waves;
+    return ((lo + hi) / 2) & ~511;
+}
+
+// Default launch shape (measured on MI355X; the autotuner in the Python package can override it per
+// instance).  D2Q9: one row per wave (the one-row kernels are compiled without a walking loop),
+// XCD-contiguous 256-column tiles, and for FP32 storage at most 5 waves per SIMD (2048^2: +4.5 %
+// over full occupancy; 256-column tiles: FP64 +1 %, FP16 +2 %; FP16 loses 4-20 % under a cap).  The
+// flux form of the aux term pulls one extra row per walk, so it walks 8 rows of 64-column tiles.
+// D3Q19 and D3Q27 (256^3): one row per wave, 256-column tiles in hardware order, at most 4 waves per
+// SIMD for FP32 storage (FP32 +17 % on D3Q19 and +14 % on D3Q27 over 64-column tiles at full
+// occupancy; FP64 +1-6 %).
+Launch default_launch(int mode, int aux, int lattice, int lds_per_cu)
+{
+    Launch lc{1, 1, 1, 0, 0, 0};
+    if (lattice != LBM_LATTICE_D2Q9) {
+        lc.xcd_remap = 0;
+        lc.max_waves = mode == MODE_F32_F32 ? 4 : 0;
+    } else if (aux == LBM_AUX_FLUX) {
+        lc.rows = 8;
+        lc.wide = 0;
+    } else {
+        lc.max_waves = mode == MODE_F32_F32 ? 5 : 0;
+    }
+    lc.lds_reserve = lds_reserve_for(lc.max_waves, lds_per_cu);
+    return lc;
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -160,8 +182,11 @@ size_t instance_bytes(const lbm_params &p)
 
 size_t max_items_of(int32_t n_inst, const lbm_params *p)
 {
-    size_t items = 0;  // one row per wave gives the most tiles
-    for (int k = 0; k < n_inst; ++k) items += (size_t)tiles_of(layout_of(p[k]), 1);
+    size_t items = 0;  // one row per wave gives the most tiles, of either width
+    for (int k = 0; k < n_inst; ++k) {
+        const Layout L = layout_of(p[k]);
+        items += (size_t)std::max(tiles_of(L, 1, 0), tiles_of(L, 1, 1));
+    }
     return items;
 }
 
@@ -230,6 +255,7 @@ struct lbm_ctx {
     std::vector<int32_t> h_block_start;
     hipStream_t stream = nullptr;
     hipStream_t capture = nullptr;    // private stream used only to record graphs
+    int lds_per_cu = 0;               // LDS bytes per CU of the device (for the wave cap)
     char *ws = nullptr;
     bool owns_ws = false;
     double *partials = nullptr;
@@ -270,11 +296,14 @@ int refresh_tables(lbm_ctx *c)
         std::vector<int64_t> cost;
         for (int k = 0; k < n; ++k) {
             const Layout &L = c->inst[k].L;
-            const int rows = c->inst[k].lc.rows, ntx = (L.nx + 63) / 64, nt = tiles_of(L, rows);
+            const Launch &lc = c->inst[k].lc;
+            const int nt = tiles_of(L, lc.rows, lc.wide);
+            const int tw = lc.wide ? 256 : 64, th = lc.wide ? lc.rows : 4 * lc.rows;  // tile extent
             for (int t = 0; t < nt; ++t) {
-                const int x0 = (t % ntx) * 64, y0 = (t / ntx) * 4 * rows;
+                int x0, y0;
+                tile_origin(L, lc, t, 0, x0, y0);
                 items.push_back(WorkItem{k, t});
-                cost.push_back((int64_t)std::min(64, L.nx - x0) * std::min(4 * rows, L.ny - y0));
+                cost.push_back((int64_t)std::min(tw, L.nx - x0) * std::min(th, L.ny - y0));
             }
         }
         const int ni = (int)items.size();
@@ -469,6 +498,12 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
     lbm_ctx *c = new (std::nothrow) lbm_ctx();
     if (!c) return fail(LBM_E_ARG, "lbm_init: out of host memory");
     c->stream = static_cast<hipStream_t>(stream);
+    {
+        int dev = 0, lds = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess)
+            c->lds_per_cu = lds;
+    }
     if (workspace) {
         c->ws = static_cast<char *>(workspace);
     } else {
@@ -491,7 +526,7 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
         in.p = p[k];
         in.mode = mode_of(p[k]);
         in.L = layout_of(p[k]);
-        in.lc = default_launch(in.mode, in.p.aux, in.p.lattice);
+        in.lc = default_launch(in.mode, in.p.aux, in.p.lattice, c->lds_per_cu);
         const size_t pb = pops_bytes(p[k]), vb = vel_bytes(p[k]), fb = field_bytes(p[k]);
         in.buf[0] = w;
         in.buf[1] = w + pb;
@@ -727,8 +762,14 @@ int lbm_set_launch(lbm_ctx *c, int32_t inst, const lbm_launch *cfg)
     if (!cfg) return fail(LBM_E_ARG, "lbm_set_launch: cfg is NULL");
     if (cfg->rows < 1 || cfg->rows > 64) return fail(LBM_E_ARG, "lbm_set_launch: rows=%d outside 1..64", cfg->rows);
     if (cfg->xcd_remap != 0 && cfg->xcd_remap != 1) return fail(LBM_E_ARG, "lbm_set_launch: xcd_remap must be 0 or 1");
+    if (cfg->tile_width != 64 && cfg->tile_width != 256)
+        return fail(LBM_E_ARG, "lbm_set_launch: tile_width=%d must be 64 or 256", cfg->tile_width);
+    if (cfg->max_waves != 0 && (cfg->max_waves < 3 || cfg->max_waves > 8))
+        return fail(LBM_E_ARG, "lbm_set_launch: max_waves=%d must be 0 or 3..8", cfg->max_waves);
+    const Launch lc{cfg->rows, cfg->xcd_remap, cfg->tile_width == 256 ? 1 : 0, cfg->max_waves,
+                    lds_reserve_for(cfg->max_waves, c->lds_per_cu), 0};
     for (int k = 0; k < (int)c->inst.size(); ++k)
-        if (inst == -1 || inst == k) c->inst[k].lc = Launch{cfg->rows, cfg->xcd_remap};
+        if (inst == -1 || inst == k) c->inst[k].lc = lc;
     return refresh_tables(c);
 }
 
@@ -737,8 +778,11 @@ int lbm_get_launch(lbm_ctx *c, int32_t inst, lbm_launch *cfg)
     g_err[0] = 0;
     if (!check_inst(c, inst)) return fail(LBM_E_STATE, "lbm_get_launch: bad context or instance %d", inst);
     if (!cfg) return fail(LBM_E_ARG, "lbm_get_launch: cfg is NULL");
-    cfg->rows = c->inst[inst].lc.rows;
-    cfg->xcd_remap = c->inst[inst].lc.xcd_remap;
+    const Launch &lc = c->inst[inst].lc;
+    cfg->rows = lc.rows;
+    cfg->xcd_remap = lc.xcd_remap;
+    cfg->tile_width = lc.wide ? 256 : 64;
+    cfg->max_waves = lc.max_waves;
     return LBM_OK;
 }
 

@@ -44,10 +44,15 @@ __host__ __device__ __forceinline__ int64_t vel_elems(const Layout &L) { return 
 __host__ __device__ __forceinline__ int64_t fld_elems(const Layout &L) { return rows_of(L) * L.pitch; }
 
 // Launch shape of the step kernel: a block is 4 waves of 64 lanes; lane = column, each wave walks
-// `rows` consecutive rows; tiles of 64 columns x 4*rows rows.
+// `rows` consecutive rows.  Narrow tiles stack the waves along the rows (64 columns x 4*rows rows);
+// wide tiles put them side by side (256 columns x rows rows).
 struct Launch {
-    int32_t rows;       // 1..64
-    int32_t xcd_remap;  // 1: give consecutive tiles to blocks on the same XCD
+    int32_t rows;         // 1..64
+    int32_t xcd_remap;    // 1: give consecutive tiles to blocks on the same XCD
+    int32_t wide;         // 1: 256-column tiles; 0: 64-column tiles
+    int32_t max_waves;    // cap on resident waves per SIMD (0: none)
+    int32_t lds_reserve;  // dynamic LDS bytes reserved per block to enforce max_waves (0: none)
+    int32_t pad_;
 };
 
 // Everything a step kernel needs about one instance.  Single-instance launches pass it by value;
@@ -87,11 +92,27 @@ struct BatchArgs {
     int32_t one_row;             // every instance walks one row per wave (the loop-free instantiation)
 };
 
-// Number of 64-column x (4 * rows)-row tiles of one instance.
-__host__ __device__ __forceinline__ int tiles_of(const Layout &L, int rows)
+// Number of tiles of one instance: 64 columns x (4 * rows) rows, or (wide) 256 columns x rows rows.
+__host__ __device__ __forceinline__ int tiles_of(const Layout &L, int rows, int wide)
 {
     const int waves_y = (int)((rows_of(L) + rows - 1) / rows);
-    return ((L.nx + 63) / 64) * ((waves_y + 3) / 4);
+    return wide ? ((L.nx + 255) / 256) * waves_y : ((L.nx + 63) / 64) * ((waves_y + 3) / 4);
+}
+
+// First column and first row of the strip that wave `wave` (0..3) of tile t walks.  The wave has
+// nothing to do when x0 >= nx or r0 >= rows_of(L).
+__host__ __device__ __forceinline__ void tile_origin(const Layout &L, const Launch &lc, int t, int wave, int &x0,
+                                                     int &r0)
+{
+    if (lc.wide) {
+        const int ntx = (L.nx + 255) >> 8;
+        x0 = (t % ntx) * 256 + wave * 64;
+        r0 = (t / ntx) * lc.rows;
+    } else {
+        const int ntx = (L.nx + 63) >> 6;
+        x0 = (t % ntx) * 64;
+        r0 = ((t / ntx) * 4 + wave) * lc.rows;
+    }
 }
 
 struct InitArgs {

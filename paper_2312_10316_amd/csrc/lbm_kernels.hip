@@ -151,10 +151,10 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
     const int nx = a.L.nx, ny = a.L.ny;
     const int64_t pitch = a.L.pitch;
     const int rows = ROWS > 0 ? ROWS : a.lc.rows;
-    const int ntx = (nx + 63) >> 6;
-    const unsigned x = (unsigned)((t % ntx) * 64) + threadIdx.x;
-    const int y0 = ((t / ntx) * 4 + wave) * rows;
-    if (y0 >= ny) return;
+    int x0, y0;
+    tile_origin(a.L, a.lc, t, wave, x0, y0);
+    if (y0 >= ny || x0 >= nx) return;
+    const unsigned x = (unsigned)x0 + threadIdx.x;
     const bool live = x < (unsigned)nx;
     const unsigned xc = live ? x : 0u;  // dead lanes of a ragged tile read column 0 and store nothing
     const unsigned xm = xc == 0 ? (unsigned)nx - 1 : xc - 1;
@@ -265,11 +265,11 @@ __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity,
     const int nx = a.L.nx, ny = a.L.ny;
     const int64_t pitch = a.L.pitch;
     const int rows = a.lc.rows;
-    const int ntx = (nx + 63) >> 6;
     const unsigned lane = threadIdx.x;
-    const unsigned x = (unsigned)((t % ntx) * 64) + lane;
-    const int y0 = ((t / ntx) * 4 + wave) * rows;
-    if (y0 >= ny) return;
+    int x0t, y0;  // the wave's first column and first row
+    tile_origin(a.L, a.lc, t, wave, x0t, y0);
+    if (y0 >= ny || x0t >= nx) return;
+    const unsigned x = (unsigned)x0t + lane;
     const bool live = x < (unsigned)nx;
     const unsigned xc = live ? x : 0u;
     const unsigned xm = xc == 0 ? (unsigned)nx - 1 : xc - 1;
@@ -279,7 +279,6 @@ __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity,
     const unsigned fc = xc * (unsigned)sizeof(M), fm = xm * (unsigned)sizeof(M), fp = xp * (unsigned)sizeof(M);
     const int y1 = min(y0 + rows, ny);
     // halo gather set-up: lane l < 18 loads population l % 9 of the west (l < 9) or east halo node
-    const int x0t = (t % ntx) * 64;
     const int last = min(63, nx - 1 - x0t);              // last live lane of this wave
     const int xw = x0t == 0 ? nx - 1 : x0t - 1;           // west halo column
     const int xe = x0t + last + 1 == nx ? 0 : x0t + last + 1;  // east halo column
@@ -590,12 +589,13 @@ template <int MODE, int AUX, int BC, bool MRT, int ROWS>
 hipError_t launch_step_rows(const StepArgs &a, hipStream_t st)
 {
     dim3 block(64, 4);
-    const int nblocks = tiles_of(a.d.L, a.d.lc.rows);
+    const int nblocks = tiles_of(a.d.L, a.d.lc.rows, a.d.lc.wide);
+    const size_t lds = (size_t)a.d.lc.lds_reserve;  // unused LDS that caps the resident waves
     const bool hk = a.d.has_k, hs = a.d.has_s;
-    if (hk && hs) step_kernel<MODE, AUX, true, true, BC, MRT, ROWS><<<nblocks, block, 0, st>>>(a);
-    else if (hk) step_kernel<MODE, AUX, true, false, BC, MRT, ROWS><<<nblocks, block, 0, st>>>(a);
-    else if (hs) step_kernel<MODE, AUX, false, true, BC, MRT, ROWS><<<nblocks, block, 0, st>>>(a);
-    else step_kernel<MODE, AUX, false, false, BC, MRT, ROWS><<<nblocks, block, 0, st>>>(a);
+    if (hk && hs) step_kernel<MODE, AUX, true, true, BC, MRT, ROWS><<<nblocks, block, lds, st>>>(a);
+    else if (hk) step_kernel<MODE, AUX, true, false, BC, MRT, ROWS><<<nblocks, block, lds, st>>>(a);
+    else if (hs) step_kernel<MODE, AUX, false, true, BC, MRT, ROWS><<<nblocks, block, lds, st>>>(a);
+    else step_kernel<MODE, AUX, false, false, BC, MRT, ROWS><<<nblocks, block, lds, st>>>(a);
     return hipGetLastError();
 }
 
@@ -667,7 +667,8 @@ hipError_t launch_batched_mode(int aux, const BatchArgs &a, int nblocks, hipStre
 
 hipError_t launch_step(int mode, int aux, const StepArgs &a, hipStream_t st)
 {
-    if (a.d.lc.rows < 1 || a.d.lc.rows > 64) return hipErrorInvalidValue;
+    if (a.d.lc.rows < 1 || a.d.lc.rows > 64 || a.d.lc.lds_reserve < 0 || a.d.lc.lds_reserve > 65536)
+        return hipErrorInvalidValue;
     switch (mode) {
     case MODE_F64_F64: return launch_step_mode<MODE_F64_F64>(aux, a, st);
     case MODE_F64_F32: return launch_step_mode<MODE_F64_F32>(aux, a, st);

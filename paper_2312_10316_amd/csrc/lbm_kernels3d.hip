@@ -190,10 +190,10 @@ __global__ __launch_bounds__(256) void step3_kernel(const StepArgs sa)
     const int R = ny * nz;
     const int64_t pitch = a.L.pitch;
     const int rows = a.lc.rows;
-    const int ntx = (nx + 63) >> 6;
-    const unsigned x = (unsigned)((t % ntx) * 64) + threadIdx.x;
-    const int r0 = ((t / ntx) * 4 + wave) * rows;
-    if (r0 >= R) return;
+    int x0, r0;
+    tile_origin(a.L, a.lc, t, wave, x0, r0);
+    if (r0 >= R || x0 >= nx) return;
+    const unsigned x = (unsigned)x0 + threadIdx.x;
     const bool live = x < (unsigned)nx;
     const unsigned xc = live ? x : 0u;  // dead lanes of a ragged tile read column 0 and store nothing
     const unsigned xm = xc == 0 ? (unsigned)nx - 1 : xc - 1;
@@ -384,12 +384,13 @@ template <int Q, int MODE, int AUX>
 hipError_t launch_step3_aux(const StepArgs &a, hipStream_t st)
 {
     dim3 block(64, 4);
-    const int nblocks = tiles_of(a.d.L, a.d.lc.rows);
+    const int nblocks = tiles_of(a.d.L, a.d.lc.rows, a.d.lc.wide);
+    const size_t lds = (size_t)a.d.lc.lds_reserve;  // unused LDS that caps the resident waves
     const bool hk = a.d.has_k, hs = a.d.has_s;
-    if (hk && hs) step3_kernel<Q, MODE, AUX, true, true><<<nblocks, block, 0, st>>>(a);
-    else if (hk) step3_kernel<Q, MODE, AUX, true, false><<<nblocks, block, 0, st>>>(a);
-    else if (hs) step3_kernel<Q, MODE, AUX, false, true><<<nblocks, block, 0, st>>>(a);
-    else step3_kernel<Q, MODE, AUX, false, false><<<nblocks, block, 0, st>>>(a);
+    if (hk && hs) step3_kernel<Q, MODE, AUX, true, true><<<nblocks, block, lds, st>>>(a);
+    else if (hk) step3_kernel<Q, MODE, AUX, true, false><<<nblocks, block, lds, st>>>(a);
+    else if (hs) step3_kernel<Q, MODE, AUX, false, true><<<nblocks, block, lds, st>>>(a);
+    else step3_kernel<Q, MODE, AUX, false, false><<<nblocks, block, lds, st>>>(a);
     return hipGetLastError();
 }
 
@@ -407,7 +408,8 @@ hipError_t launch_step3_mode(int aux, const StepArgs &a, hipStream_t st)
 
 hipError_t launch_step3(int mode, int aux, const StepArgs &a, hipStream_t st)
 {
-    if (a.d.lc.rows < 1 || a.d.lc.rows > 64) return hipErrorInvalidValue;
+    if (a.d.lc.rows < 1 || a.d.lc.rows > 64 || a.d.lc.lds_reserve < 0 || a.d.lc.lds_reserve > 65536)
+        return hipErrorInvalidValue;
     if (a.d.L.q != 19 && a.d.L.q != 27) return hipErrorInvalidValue;
     const bool q27 = a.d.L.q == 27;
     switch (mode) {

@@ -162,6 +162,23 @@ def test_3d_full_size_256_windows(mode, q):
 
 
 @pytest.mark.parametrize("q", LATTICES)
+@pytest.mark.parametrize("mode", ["f64", "f32"])
+def test_3d_launch_shape_does_not_change_results(q, mode):
+    """Rows per wave, tile width, tile order and the wave cap are tuning knobs only: bitwise equal
+    states on a ragged lattice (70 columns: a 256-column tile holds two live waves)."""
+    f = case3(70, 7, 5, 47)
+    states = []
+    for rows, remap, width, cap in ((1, 0, 64, 0), (1, 0, 256, 5), (3, 1, 256, 0), (2, 1, 64, 6), (64, 0, 256, 8)):
+        s, _ = solver3(f, mode, q=q)
+        s.set_launch(rows, remap, tile_width=width, max_waves=cap)
+        s.step(9)
+        states.append(s.state_save())
+        s.close()
+    for st in states[1:]:
+        assert torch.equal(st, states[0])
+
+
+@pytest.mark.parametrize("q", LATTICES)
 def test_3d_graph_replay_and_checkpoint(q):
     f = case3(72, 6, 5, 41)
     s, _ = solver3(f, "f32", q=q)

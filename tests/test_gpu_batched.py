@@ -54,9 +54,11 @@ def test_batched_policies_match_serial_bitwise(mode):
 def test_batched_matches_separate_contexts_and_rows():
     insts = [instance(c, "f32")[:2] for c in mixed_configs()]
     s = Solver(insts)
-    s.set_launch(3, 1, inst=2)  # a different tile shape for one instance
-    s.set_batch(lbm.LBM_BATCH_LPT, 11)
-    s.step(40)
+    s.set_launch(3, 1, inst=2)  # different tile shapes for two instances
+    s.set_launch(2, 1, inst=0, tile_width=256)
+    for policy, blocks in ((lbm.LBM_BATCH_LPT, 11), (lbm.LBM_BATCH_FLAT, 0)):
+        s.set_batch(policy, blocks)
+        s.step(20)
     for k, one in enumerate(insts):
         t = Solver([one])
         t.step(40)

@@ -410,6 +410,24 @@ def test_graph_replay_matches_eager_steps():
     b.close()
 
 
+def test_launch_defaults_and_bad_launch_shapes():
+    cfg = W.PulseConfig(N=64, steps=0)
+    f = W.rotating_pulse(cfg)
+    fields = {k: dev(f[k]) for k in ("phi0", "ux", "uy")}
+    want = {"f32": (1, 1, 256, 5), "f64": (1, 1, 256, 0), "f16s": (1, 1, 256, 0)}
+    for mode, (rows, remap, width, cap) in want.items():
+        s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, mode), fields)])
+        assert s.get_launch() == {"rows": rows, "xcd_remap": remap, "tile_width": width, "max_waves": cap}
+        s.close()
+    s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, "f32", lbm.LBM_AUX_FLUX), fields)])
+    assert s.get_launch() == {"rows": 8, "xcd_remap": 1, "tile_width": 64, "max_waves": 0}
+    for kw in (dict(tile_width=128), dict(tile_width=0), dict(max_waves=2), dict(max_waves=9), dict(max_waves=-1)):
+        with pytest.raises(lbm.LbmError) as ei:
+            s.set_launch(1, 1, **kw)
+        assert ei.value.status == lbm.LBM_E_ARG, kw
+    s.close()
+
+
 @pytest.mark.parametrize("mode,aux", [("f64", lbm.LBM_AUX_LOCAL), ("f16s", lbm.LBM_AUX_LOCAL),
                                       ("f64", lbm.LBM_AUX_FLUX), ("f32", lbm.LBM_AUX_FLUX)])
 def test_launch_shape_does_not_change_results(mode, aux):
@@ -418,10 +436,11 @@ def test_launch_shape_does_not_change_results(mode, aux):
     p = lbm.make_params(cfg.N, cfg.N - 37, f["dx"], f["dt"], cfg.lam, cfg.D, mode, aux)
     fields = {k: dev(np.ascontiguousarray(f[k][:cfg.N - 37])) for k in ("phi0", "ux", "uy", "D")}
     states = []
-    for rows, remap in ((1, 0), (4, 1), (7, 1), (64, 0)):
+    for rows, remap, width, cap in ((1, 0, 64, 0), (4, 1, 64, 6), (7, 1, 256, 0), (64, 0, 64, 0), (1, 1, 256, 5),
+                                    (3, 0, 256, 8)):
         s = Solver([(p, fields)])
-        s.set_launch(rows, remap)
-        assert s.get_launch() == {"rows": rows, "xcd_remap": remap}
+        s.set_launch(rows, remap, tile_width=width, max_waves=cap)
+        assert s.get_launch() == {"rows": rows, "xcd_remap": remap, "tile_width": width, "max_waves": cap}
         s.step(70)
         states.append(s.state_save())
         s.close()
