@@ -75,6 +75,7 @@ def run_mode(mode, n, steps, warmup, torch, W, lbm, Solver, graph=True):
     ms = e0.elapsed_time(e1)
     ref = torch.from_numpy(W.pulse_reference(cfg, f)).cuda()
     st, phi = s.macros(ref=ref, want_phi=True)
+    launch = s.get_launch()
     s.close()
     lups = float(n) * n * steps
     return {
@@ -86,6 +87,7 @@ def run_mode(mode, n, steps, warmup, torch, W, lbm, Solver, graph=True):
         "mass": st["mass"],
         "nonfinite": st["nonfinite"],
         "t_end": cfg.t_end,
+        "launch": launch,
     }, phi
 
 
@@ -236,8 +238,9 @@ def run_flux(torch, W, lbm, Solver, n=2048, steps=3000):
         s = Solver([(lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, mode, lbm.LBM_AUX_FLUX), dev)])
         s.step(64)
         ms = _timed_steps(torch, s, steps)
+        launch = s.get_launch()
         s.close()
-        out[mode] = {"mlups": n * n / (ms * 1e-3) / 1e6, "ms_per_step": ms, "launch": "rows=8, xcd_remap=1"}
+        out[mode] = {"mlups": n * n / (ms * 1e-3) / 1e6, "ms_per_step": ms, "launch": launch}
     return out
 
 

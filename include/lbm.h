@@ -205,7 +205,10 @@ int lbm_state_load(lbm_ctx *ctx, int32_t inst, const void *src, int64_t step);
  * one-instance launches (the SERIAL policy), not to the batched kernel. */
 typedef struct lbm_launch {
     int32_t rows;        /* 1..64 */
-    int32_t xcd_remap;   /* 1: consecutive tiles go to blocks on the same XCD (shared L2); 0: hardware order */
+    int32_t xcd_remap;   /* tile order over the 8 XCDs (each has its own L2): 0 hardware order (tiles of a row
+                            interleave over the XCDs); 1 row bands (XCD j takes one contiguous range of
+                            tiles); 2 column bands (XCD j takes 1/8 of the tile columns, row by row;
+                            as 0 when the tiles per row are not a multiple of 8) */
     int32_t tile_width;  /* 64 or 256 */
     int32_t max_waves;   /* 0 or 3..8 */
 } lbm_launch;

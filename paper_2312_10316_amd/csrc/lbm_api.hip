@@ -78,25 +78,34 @@ int lds_reserve_for(int max_waves, int lds_per_cu)
     return ((lo + hi) / 2) & ~511;
 }
 
-// Default launch shape (measured on MI355X; the autotuner in the Python package can override it per
-// instance).  D2Q9: one row per wave (the one-row kernels are compiled without a walking loop),
-// XCD-contiguous 256-column tiles, and for FP32 storage at most 5 waves per SIMD (2048^2: +4.5 %
-// over full occupancy; 256-column tiles: FP64 +1 %, FP16 +2 %; FP16 loses 4-20 % under a cap).  The
-// flux form of the aux term pulls one extra row per walk, so it walks 8 rows of 64-column tiles.
-// D3Q19 and D3Q27 (256^3): one row per wave, 256-column tiles in hardware order, at most 4 waves per
-// SIMD for FP32 storage (FP32 +17 % on D3Q19 and +14 % on D3Q27 over 64-column tiles at full
-// occupancy; FP64 +1-6 %).
-Launch default_launch(int mode, int aux, int lattice, int lds_per_cu)
+// Default launch shape, from sweeps on MI355X over 1024^2..8192^2 and 256^3 (the autotuner in the
+// Python package can override it per instance).  One row per wave (the one-row kernels have no
+// walking loop) on 256-column tiles.  D2Q9 local/no aux: tiles in hardware order below 2^26 nodes
+// and in XCD column bands from there (2048^2..6144^2: hardware order +5-8 % over row bands; 8192^2:
+// column bands +2 % over row bands and +5 % over hardware order for FP32, +3.5 % for FP16); at most
+// 5 waves per SIMD for FP32 storage and 4 for FP64 storage (+1-5 %), FP16 uncapped (a cap costs it
+// 4-20 %).  Flux form: two rows per wave, XCD-contiguous for FP32 with 4
+// waves (+16 % over 8 rows of 64-column tiles), hardware order for FP64.  D3Q19 and D3Q27: hardware
+// order, FP32 capped at 4 waves (+17 % on D3Q19 and +14 % on D3Q27 over 64-column tiles at full
+// occupancy).  A context of several instances keeps 64-column tiles, which the batched kernel
+// prefers (a 256-column tile of a small lattice leaves waves idle).
+Launch default_launch(const lbm_params &p, int mode, int n_inst, int lds_per_cu)
 {
-    Launch lc{1, 1, 1, 0, 0, 0};
-    if (lattice != LBM_LATTICE_D2Q9) {
-        lc.xcd_remap = 0;
-        lc.max_waves = mode == MODE_F32_F32 ? 4 : 0;
-    } else if (aux == LBM_AUX_FLUX) {
-        lc.rows = 8;
-        lc.wide = 0;
+    Launch lc{1, 0, 1, 0, 0, 0};
+    const bool f32 = mode == MODE_F32_F32, f16 = mode == MODE_F16S_F32;
+    if (p.lattice != LBM_LATTICE_D2Q9) {
+        lc.max_waves = f32 ? 4 : 0;
+    } else if (p.aux == LBM_AUX_FLUX) {
+        lc.rows = 2;
+        lc.xcd_remap = f32 ? 1 : 0;
+        lc.max_waves = f32 ? 4 : 0;
     } else {
-        lc.max_waves = mode == MODE_F32_F32 ? 5 : 0;
+        lc.xcd_remap = (int64_t)p.nx * p.ny >= ((int64_t)1 << 26) ? 2 : 0;
+        lc.max_waves = f16 ? 0 : (f32 ? 5 : 4);
+    }
+    if (n_inst > 1 && p.lattice == LBM_LATTICE_D2Q9) {
+        lc.wide = 0;
+        lc.xcd_remap = 1;
     }
     lc.lds_reserve = lds_reserve_for(lc.max_waves, lds_per_cu);
     return lc;
@@ -526,7 +535,7 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
         in.p = p[k];
         in.mode = mode_of(p[k]);
         in.L = layout_of(p[k]);
-        in.lc = default_launch(in.mode, in.p.aux, in.p.lattice, c->lds_per_cu);
+        in.lc = default_launch(in.p, in.mode, n_inst, c->lds_per_cu);
         const size_t pb = pops_bytes(p[k]), vb = vel_bytes(p[k]), fb = field_bytes(p[k]);
         in.buf[0] = w;
         in.buf[1] = w + pb;
@@ -761,7 +770,7 @@ int lbm_set_launch(lbm_ctx *c, int32_t inst, const lbm_launch *cfg)
         return fail(LBM_E_STATE, "lbm_set_launch: bad context or instance %d", inst);
     if (!cfg) return fail(LBM_E_ARG, "lbm_set_launch: cfg is NULL");
     if (cfg->rows < 1 || cfg->rows > 64) return fail(LBM_E_ARG, "lbm_set_launch: rows=%d outside 1..64", cfg->rows);
-    if (cfg->xcd_remap != 0 && cfg->xcd_remap != 1) return fail(LBM_E_ARG, "lbm_set_launch: xcd_remap must be 0 or 1");
+    if (cfg->xcd_remap < 0 || cfg->xcd_remap > 2) return fail(LBM_E_ARG, "lbm_set_launch: xcd_remap must be 0, 1 or 2");
     if (cfg->tile_width != 64 && cfg->tile_width != 256)
         return fail(LBM_E_ARG, "lbm_set_launch: tile_width=%d must be 64 or 256", cfg->tile_width);
     if (cfg->max_waves != 0 && (cfg->max_waves < 3 || cfg->max_waves > 8))

@@ -48,7 +48,7 @@ __host__ __device__ __forceinline__ int64_t fld_elems(const Layout &L) { return 
 // wide tiles put them side by side (256 columns x rows rows).
 struct Launch {
     int32_t rows;         // 1..64
-    int32_t xcd_remap;    // 1: give consecutive tiles to blocks on the same XCD
+    int32_t xcd_remap;    // tile order over the XCDs: 0 hardware, 1 row bands, 2 column bands
     int32_t wide;         // 1: 256-column tiles; 0: 64-column tiles
     int32_t max_waves;    // cap on resident waves per SIMD (0: none)
     int32_t lds_reserve;  // dynamic LDS bytes reserved per block to enforce max_waves (0: none)
@@ -99,17 +99,22 @@ __host__ __device__ __forceinline__ int tiles_of(const Layout &L, int rows, int 
     return wide ? ((L.nx + 255) / 256) * waves_y : ((L.nx + 63) / 64) * ((waves_y + 3) / 4);
 }
 
+// Tiles per lattice row.
+__host__ __device__ __forceinline__ int tiles_per_row(const Layout &L, const Launch &lc)
+{
+    return lc.wide ? (L.nx + 255) >> 8 : (L.nx + 63) >> 6;
+}
+
 // First column and first row of the strip that wave `wave` (0..3) of tile t walks.  The wave has
 // nothing to do when x0 >= nx or r0 >= rows_of(L).
 __host__ __device__ __forceinline__ void tile_origin(const Layout &L, const Launch &lc, int t, int wave, int &x0,
                                                      int &r0)
 {
+    const int ntx = tiles_per_row(L, lc);
     if (lc.wide) {
-        const int ntx = (L.nx + 255) >> 8;
         x0 = (t % ntx) * 256 + wave * 64;
         r0 = (t / ntx) * lc.rows;
     } else {
-        const int ntx = (L.nx + 63) >> 6;
         x0 = (t % ntx) * 64;
         r0 = ((t / ntx) * 4 + wave) * lc.rows;
     }

@@ -45,13 +45,24 @@ __device__ __forceinline__ void st_nt_at(T *base, unsigned byte_off, T v)
     __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off));
 }
 
-// Block b -> tile t.  With xcd_remap the hardware's round-robin of blocks over the 8 XCDs
-// (block b runs on XCD b % 8) is inverted so that XCD j works on one contiguous range of tiles.
-__device__ __forceinline__ int tile_of_block(int b, int nb, int remap)
+// Block b -> tile t (tiles numbered row-major, ntx per row).  The hardware hands block b to XCD
+// b % 8, and each XCD has its own L2.
+//   remap 0: t = b, so the XCDs interleave tile by tile along each row;
+//   remap 1: XCD j takes one contiguous range of tiles (a band of whole tile rows);
+//   remap 2: XCD j takes one band of ntx/8 tile columns and walks it row by row, so the 8 XCDs
+//            sweep the same rows together while each shares tile edges with at most two others
+//            (needs ntx % 8 == 0; otherwise it is remap 0).
+__device__ __forceinline__ int tile_of_block(int b, int nb, int remap, int ntx)
 {
-    if (!remap) return b;
-    const int q = nb >> 3, r = nb & 7, j = b & 7;
-    return j * q + min(j, r) + (b >> 3);
+    if (remap == 1) {
+        const int q = nb >> 3, r = nb & 7, j = b & 7;
+        return j * q + min(j, r) + (b >> 3);
+    }
+    if (remap == 2 && (ntx & 7) == 0) {
+        const int bw = ntx >> 3, i = b >> 3;
+        return (i / bw) * ntx + (b & 7) * bw + i % bw;
+    }
+    return b;
 }
 
 // ---- diagnostics ------------------------------------------------------------------------------

@@ -414,18 +414,43 @@ def test_launch_defaults_and_bad_launch_shapes():
     cfg = W.PulseConfig(N=64, steps=0)
     f = W.rotating_pulse(cfg)
     fields = {k: dev(f[k]) for k in ("phi0", "ux", "uy")}
-    want = {"f32": (1, 1, 256, 5), "f64": (1, 1, 256, 0), "f16s": (1, 1, 256, 0)}
+    want = {"f32": (1, 0, 256, 5), "f64": (1, 0, 256, 4), "f16s": (1, 0, 256, 0)}
     for mode, (rows, remap, width, cap) in want.items():
         s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, mode), fields)])
         assert s.get_launch() == {"rows": rows, "xcd_remap": remap, "tile_width": width, "max_waves": cap}
         s.close()
     s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, "f32", lbm.LBM_AUX_FLUX), fields)])
-    assert s.get_launch() == {"rows": 8, "xcd_remap": 1, "tile_width": 64, "max_waves": 0}
-    for kw in (dict(tile_width=128), dict(tile_width=0), dict(max_waves=2), dict(max_waves=9), dict(max_waves=-1)):
-        with pytest.raises(lbm.LbmError) as ei:
-            s.set_launch(1, 1, **kw)
-        assert ei.value.status == lbm.LBM_E_ARG, kw
+    assert s.get_launch() == {"rows": 2, "xcd_remap": 1, "tile_width": 256, "max_waves": 4}
     s.close()
+    two = [(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, "f32"), fields)] * 2
+    s = Solver(two)  # several instances: the batched kernel's 64-column tiles
+    assert s.get_launch(1) == {"rows": 1, "xcd_remap": 1, "tile_width": 64, "max_waves": 5}
+    for remap, kw in ((1, dict(tile_width=128)), (1, dict(tile_width=0)), (1, dict(max_waves=2)),
+                      (1, dict(max_waves=9)), (1, dict(max_waves=-1)), (3, {}), (-1, {})):
+        with pytest.raises(lbm.LbmError) as ei:
+            s.set_launch(1, remap, **kw)
+        assert ei.value.status == lbm.LBM_E_ARG, (remap, kw)
+    s.close()
+
+
+@pytest.mark.parametrize("mode", ["f32", "f16s", "f64"])
+def test_xcd_tile_orders_do_not_change_results(mode):
+    """The three block-to-tile orders (hardware, row bands, column bands) on a lattice whose tile
+    rows hold 8 tiles (256-column tiles) or 32 (64-column tiles), so that column bands apply, with
+    ragged last tiles in x and y: bitwise equal states."""
+    nx, ny = 2000, 37
+    X, Y, dx = W.mesh(nx, ny, -1.0, 1.0)
+    p = lbm.make_params(nx, ny, dx, dx / 10, 0.25, 1e-3, mode)
+    fields = {"phi0": dev(np.exp(-((X - 0.3) ** 2 + Y ** 2) / 0.02)), "ux": dev(-np.pi * Y), "uy": dev(np.pi * X)}
+    states = []
+    for remap, width, rows in ((0, 256, 1), (1, 256, 1), (2, 256, 1), (2, 64, 1), (2, 64, 3), (2, 256, 2)):
+        s = Solver([(p, fields)])
+        s.set_launch(rows, remap, tile_width=width)
+        s.step(25)
+        states.append(s.state_save())
+        s.close()
+    for st in states[1:]:
+        assert torch.equal(st, states[0])
 
 
 @pytest.mark.parametrize("mode,aux", [("f64", lbm.LBM_AUX_LOCAL), ("f16s", lbm.LBM_AUX_LOCAL),
