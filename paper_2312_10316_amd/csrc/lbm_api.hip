@@ -78,32 +78,47 @@ int lds_reserve_for(int max_waves, int lds_per_cu)
     return ((lo + hi) / 2) & ~511;
 }
 
-// Default launch shape, from sweeps on MI355X over 1024^2..8192^2 and 256^3 (the autotuner in the
-// Python package can override it per instance).  One row per wave (the one-row kernels have no
-// walking loop) on 256-column tiles.  D2Q9 local/no aux: tiles in hardware order below 2^26 nodes
-// and in XCD column bands from there (2048^2..6144^2: hardware order +5-8 % over row bands; 8192^2:
-// column bands +2 % over row bands and +5 % over hardware order for FP32, +3.5 % for FP16); at most
-// 5 waves per SIMD for FP32 storage and 4 for FP64 storage (+1-5 %), FP16 uncapped (a cap costs it
-// 4-20 %).  Flux form: two rows per wave, XCD-contiguous for FP32 with 4
-// waves (+16 % over 8 rows of 64-column tiles), hardware order for FP64.  D3Q19 and D3Q27: hardware
-// order, FP32 capped at 4 waves (+17 % on D3Q19 and +14 % on D3Q27 over 64-column tiles at full
-// occupancy).  A context of several instances keeps 64-column tiles, which the batched kernel
-// prefers (a 256-column tile of a small lattice leaves waves idle).
+// Default launch shape, from sweeps on MI355X over 2048^2..8192^2, 2049^2 and 256^3 (the autotuner
+// in the Python package can override it per instance).
+// D2Q9, periodic, local or no aux: one row per wave (the one-row kernels have no walking loop) on
+// 256-column tiles; XCD column bands when a row holds a multiple of 8 tiles, else row bands (hardware
+// order only helps when every XCD keeps to its own columns, i.e. a multiple of 8 tiles per row; at
+// 2049^2 it costs 8 %); at most 5 waves per SIMD for FP32 storage and 4 for FP64 storage (+1-5 %),
+// FP16 uncapped (a cap costs it 4-20 %).  2048^2 FP32: 80k MLUPS against 74k for 64-column tiles
+// in row bands at full occupancy.
+// Flux form: two rows per wave on 256-column tiles, FP32 in row bands with 4 waves (+16 % over 8 rows
+// of 64-column tiles), FP64 ordered as above and uncapped.
+// Dirichlet edges and walls (the walking-loop kernels): FP32 two rows on 256-column tiles in row
+// bands; FP64 one row on 64-column tiles in hardware order (2049^2: +17 % and +4 % over the
+// periodic defaults).
+// D3Q19 and D3Q27: one row on 256-column tiles in hardware order, FP32 capped at 4 waves (+17 % on
+// D3Q19 and +14 % on D3Q27 over 64-column tiles at full occupancy).
+// A context of several instances keeps 64-column tiles in row bands, which the batched kernel prefers
+// (a 256-column tile of a small lattice leaves waves idle).
 Launch default_launch(const lbm_params &p, int mode, int n_inst, int lds_per_cu)
 {
     Launch lc{1, 0, 1, 0, 0, 0};
     const bool f32 = mode == MODE_F32_F32, f16 = mode == MODE_F16S_F32;
+    const int bands = ((p.nx + 255) / 256) % 8 == 0 ? 2 : 1;
     if (p.lattice != LBM_LATTICE_D2Q9) {
         lc.max_waves = f32 ? 4 : 0;
+    } else if (p.boundary != LBM_BC_PERIODIC) {
+        if (f32) {
+            lc.rows = 2;
+            lc.xcd_remap = 1;
+        } else {
+            lc.wide = 0;
+        }
     } else if (p.aux == LBM_AUX_FLUX) {
         lc.rows = 2;
-        lc.xcd_remap = f32 ? 1 : 0;
+        lc.xcd_remap = f32 ? 1 : bands;
         lc.max_waves = f32 ? 4 : 0;
     } else {
-        lc.xcd_remap = (int64_t)p.nx * p.ny >= ((int64_t)1 << 26) ? 2 : 0;
+        lc.xcd_remap = bands;
         lc.max_waves = f16 ? 0 : (f32 ? 5 : 4);
     }
     if (n_inst > 1 && p.lattice == LBM_LATTICE_D2Q9) {
+        lc.rows = 1;
         lc.wide = 0;
         lc.xcd_remap = 1;
     }

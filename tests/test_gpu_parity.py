@@ -414,10 +414,20 @@ def test_launch_defaults_and_bad_launch_shapes():
     cfg = W.PulseConfig(N=64, steps=0)
     f = W.rotating_pulse(cfg)
     fields = {k: dev(f[k]) for k in ("phi0", "ux", "uy")}
-    want = {"f32": (1, 0, 256, 5), "f64": (1, 0, 256, 4), "f16s": (1, 0, 256, 0)}
+    want = {"f32": (1, 1, 256, 5), "f64": (1, 1, 256, 4), "f16s": (1, 1, 256, 0)}  # 1 tile per row: row bands
     for mode, (rows, remap, width, cap) in want.items():
         s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, mode), fields)])
         assert s.get_launch() == {"rows": rows, "xcd_remap": remap, "tile_width": width, "max_waves": cap}
+        s.close()
+    wide_row = {k: dev(np.ascontiguousarray(np.tile(f[k][:3], (1, 32)))) for k in ("phi0", "ux", "uy")}
+    s = Solver([(lbm.make_params(2048, 3, f["dx"], f["dt"], cfg.lam, cfg.D, "f32"), wide_row)])
+    assert s.get_launch()["xcd_remap"] == 2  # 8 tiles per row: column bands
+    s.close()
+    for mode, want_nee in (("f32", (2, 1, 256, 0)), ("f64", (1, 0, 64, 0))):
+        s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, mode, boundary=lbm.LBM_BC_NEE),
+                     fields)])
+        got = s.get_launch()
+        assert (got["rows"], got["xcd_remap"], got["tile_width"], got["max_waves"]) == want_nee, mode
         s.close()
     s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, "f32", lbm.LBM_AUX_FLUX), fields)])
     assert s.get_launch() == {"rows": 2, "xcd_remap": 1, "tile_width": 256, "max_waves": 4}
