@@ -202,7 +202,7 @@ int lbm_state_load(lbm_ctx *ctx, int32_t inst, const void *src, int64_t step);
  * side by side along x (256 columns x rows rows), so that each population row segment a block
  * reads or writes is 1 KiB (FP32) of contiguous memory.  max_waves caps the waves resident on each
  * SIMD (3..8; 0: as many as the registers allow) by reserving unused LDS per block; it applies to
- * one-instance launches (the SERIAL policy), not to the batched kernel. */
+ * one-instance launches (the SERIAL policy); the batched launch has its own cap (lbm_batch). */
 typedef struct lbm_launch {
     int32_t rows;        /* 1..64 */
     int32_t xcd_remap;   /* tile order over the 8 XCDs (each has its own L2): 0 hardware order (tiles of a row
@@ -229,8 +229,10 @@ int lbm_get_launch(lbm_ctx *ctx, int32_t inst, lbm_launch *cfg);
  * independent of the policy. */
 enum lbm_batch_policy { LBM_BATCH_SERIAL = 0, LBM_BATCH_FLAT = 1, LBM_BATCH_STRIDED = 2, LBM_BATCH_LPT = 3 };
 typedef struct lbm_batch {
-    int32_t policy;  /* enum lbm_batch_policy */
-    int32_t blocks;  /* persistent blocks for STRIDED / LPT (>= 1; capped at the number of tiles) */
+    int32_t policy;     /* enum lbm_batch_policy */
+    int32_t blocks;     /* persistent blocks for STRIDED / LPT (>= 1; capped at the number of tiles) */
+    int32_t max_waves;  /* cap on the batched launch's resident waves per SIMD, as lbm_launch.max_waves
+                           (0 or 3..8); the default batch of FP32 instances uses 6 */
 } lbm_batch;
 
 /* Sets or reads the batch policy; captured step graphs are dropped.  Synchronizes the stream. */

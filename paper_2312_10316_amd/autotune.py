@@ -44,8 +44,10 @@ def default_candidates(solver) -> list:
     for width in (64, 256):
         for rows in (1, 2, 4):
             out.append((rows, 1, width, 0, L.LBM_BATCH_SERIAL, 0))
-            out.append((rows, 1, width, 0, L.LBM_BATCH_FLAT, 0))
-            for mult in (2, 4, 8):
+            for cap in (0, 6):
+                out.append((rows, 1, width, cap, L.LBM_BATCH_FLAT, 0))
+                out.append((rows, 1, width, cap, L.LBM_BATCH_LPT, 4 * ncu))
+            for mult in (2, 8):
                 out.append((rows, 1, width, 0, L.LBM_BATCH_LPT, mult * ncu))
             out.append((rows, 1, width, 0, L.LBM_BATCH_STRIDED, 4 * ncu))
     return out
@@ -56,7 +58,7 @@ def _apply(solver, cand) -> None:
     solver.set_launch(rows, remap, tile_width=width, max_waves=cap)
     if len(solver.params) > 1:
         try:
-            solver.set_batch(policy, blocks)
+            solver.set_batch(policy, blocks, cap)  # the cap applies to the batched launch as well
         except L.LbmError as e:
             if e.status != L.LBM_E_UNSUPPORTED:
                 raise
@@ -108,7 +110,7 @@ def tune(solver, candidates: Optional[Iterable] = None, steps: int = 64, reps: i
             o = old_launch[k]
             solver.set_launch(o["rows"], o["xcd_remap"], inst=k, tile_width=o["tile_width"], max_waves=o["max_waves"])
         if old_batch is not None:
-            solver.set_batch(old_batch["policy"], old_batch["blocks"])
+            solver.set_batch(old_batch["policy"], old_batch["blocks"], old_batch["max_waves"])
         for k in range(n):
             solver.state_load(saved[k], steps0[k], inst=k)
         torch.cuda.synchronize()

@@ -268,7 +268,7 @@ struct lbm_ctx {
     std::vector<Instance> inst;
     int parity = 0;                   // the buffer every instance currently reads (they step together)
     bool uniform = false;             // all instances share mode and aux (a batched launch is possible)
-    lbm_batch batch = {LBM_BATCH_SERIAL, 0};
+    lbm_batch batch = {LBM_BATCH_SERIAL, 0, 0};
     InstDesc *d_desc = nullptr;       // device tables (in the workspace)
     WorkItem *d_items = nullptr;
     int32_t *d_block_start = nullptr;
@@ -418,7 +418,8 @@ int enqueue_step(lbm_ctx *c, hipStream_t st)
         a.parity = c->parity;
         a.one_row = 1;
         for (const Instance &in : c->inst) a.one_row &= in.lc.rows == 1 ? 1 : 0;
-        hipError_t e = launch_batched_step(c->inst[0].mode, c->inst[0].p.aux, a, c->nblocks, st);
+        hipError_t e = launch_batched_step(c->inst[0].mode, c->inst[0].p.aux, a, c->nblocks,
+                                           lds_reserve_for(c->batch.max_waves, c->lds_per_cu), st);
         if (e != hipSuccess) return hip_fail(e, "batched step kernel launch");
     } else {
         for (size_t k = 0; k < c->inst.size(); ++k) {
@@ -579,7 +580,8 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
     c->d_items = reinterpret_cast<WorkItem *>(w);
     w += align_up(items * sizeof(WorkItem), kAlign);
     c->d_block_start = reinterpret_cast<int32_t *>(w);
-    if (n_inst > 1 && c->uniform) c->batch = lbm_batch{LBM_BATCH_FLAT, 0};
+    // a uniform batch defaults to one flat launch; FP32 runs it with at most 6 waves per SIMD (+2 %)
+    if (n_inst > 1 && c->uniform) c->batch = lbm_batch{LBM_BATCH_FLAT, 0, c->inst[0].mode == MODE_F32_F32 ? 6 : 0};
 
     // Zero everything the library owns (padding columns included) so that a state is a
     // deterministic byte image; this also clears the flags.
@@ -819,6 +821,8 @@ int lbm_set_batch(lbm_ctx *c, const lbm_batch *cfg)
         return fail(LBM_E_ARG, "lbm_set_batch: unknown policy %d", cfg->policy);
     if ((cfg->policy == LBM_BATCH_STRIDED || cfg->policy == LBM_BATCH_LPT) && cfg->blocks < 1)
         return fail(LBM_E_ARG, "lbm_set_batch: persistent policies need blocks >= 1");
+    if (cfg->max_waves != 0 && (cfg->max_waves < 3 || cfg->max_waves > 8))
+        return fail(LBM_E_ARG, "lbm_set_batch: max_waves=%d must be 0 or 3..8", cfg->max_waves);
     if (cfg->policy != LBM_BATCH_SERIAL && !c->uniform)
         return fail(LBM_E_UNSUPPORTED, "lbm_set_batch: instances differ in storage/arithmetic or aux form");
     c->batch = *cfg;

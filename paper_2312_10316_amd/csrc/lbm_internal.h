@@ -187,7 +187,7 @@ struct AdjArgs {
 
 // Launchers (lbm_kernels.hip, lbm_adjoint.hip).  All return the hipError_t of the launch.
 hipError_t launch_step(int mode, int aux, const StepArgs &a, hipStream_t st);
-hipError_t launch_batched_step(int mode, int aux, const BatchArgs &a, int nblocks, hipStream_t st);
+hipError_t launch_batched_step(int mode, int aux, const BatchArgs &a, int nblocks, int lds_reserve, hipStream_t st);
 hipError_t launch_init(int mode, const InitArgs &a, hipStream_t st);
 hipError_t launch_prep(int mode, const PrepArgs &a, hipStream_t st);
 hipError_t launch_macros(int mode, const MacroArgs &a, double *result, hipStream_t st);

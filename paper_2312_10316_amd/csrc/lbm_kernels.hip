@@ -647,18 +647,18 @@ hipError_t launch_step_mode(int aux, const StepArgs &a, hipStream_t st)
 }
 
 template <int MODE>
-hipError_t launch_batched_mode(int aux, const BatchArgs &a, int nblocks, hipStream_t st)
+hipError_t launch_batched_mode(int aux, const BatchArgs &a, int nblocks, size_t lds, hipStream_t st)
 {
-    dim3 block(64, 4);
+    dim3 block(64, 4);  // lds: unused LDS that caps the resident waves
     switch (aux) {
     case 0:
-        if (a.one_row) batched_step_kernel<MODE, 0, 1><<<nblocks, block, 0, st>>>(a);
-        else batched_step_kernel<MODE, 0, 0><<<nblocks, block, 0, st>>>(a);
+        if (a.one_row) batched_step_kernel<MODE, 0, 1><<<nblocks, block, lds, st>>>(a);
+        else batched_step_kernel<MODE, 0, 0><<<nblocks, block, lds, st>>>(a);
         break;
-    case 1: batched_step_kernel<MODE, 1, 0><<<nblocks, block, 0, st>>>(a); break;
+    case 1: batched_step_kernel<MODE, 1, 0><<<nblocks, block, lds, st>>>(a); break;
     default:
-        if (a.one_row) batched_step_kernel<MODE, 2, 1><<<nblocks, block, 0, st>>>(a);
-        else batched_step_kernel<MODE, 2, 0><<<nblocks, block, 0, st>>>(a);
+        if (a.one_row) batched_step_kernel<MODE, 2, 1><<<nblocks, block, lds, st>>>(a);
+        else batched_step_kernel<MODE, 2, 0><<<nblocks, block, lds, st>>>(a);
         break;
     }
     return hipGetLastError();
@@ -679,14 +679,15 @@ hipError_t launch_step(int mode, int aux, const StepArgs &a, hipStream_t st)
     }
 }
 
-hipError_t launch_batched_step(int mode, int aux, const BatchArgs &a, int nblocks, hipStream_t st)
+hipError_t launch_batched_step(int mode, int aux, const BatchArgs &a, int nblocks, int lds_reserve, hipStream_t st)
 {
-    if (nblocks < 1) return hipErrorInvalidValue;
+    if (nblocks < 1 || lds_reserve < 0 || lds_reserve > 65536) return hipErrorInvalidValue;
+    const size_t lds = (size_t)lds_reserve;
     switch (mode) {
-    case MODE_F64_F64: return launch_batched_mode<MODE_F64_F64>(aux, a, nblocks, st);
-    case MODE_F64_F32: return launch_batched_mode<MODE_F64_F32>(aux, a, nblocks, st);
-    case MODE_F32_F32: return launch_batched_mode<MODE_F32_F32>(aux, a, nblocks, st);
-    case MODE_F16S_F32: return launch_batched_mode<MODE_F16S_F32>(aux, a, nblocks, st);
+    case MODE_F64_F64: return launch_batched_mode<MODE_F64_F64>(aux, a, nblocks, lds, st);
+    case MODE_F64_F32: return launch_batched_mode<MODE_F64_F32>(aux, a, nblocks, lds, st);
+    case MODE_F32_F32: return launch_batched_mode<MODE_F32_F32>(aux, a, nblocks, lds, st);
+    case MODE_F16S_F32: return launch_batched_mode<MODE_F16S_F32>(aux, a, nblocks, lds, st);
     default: return hipErrorInvalidValue;
     }
 }

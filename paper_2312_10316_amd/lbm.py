@@ -67,7 +67,7 @@ class lbm_launch(ctypes.Structure):
 
 
 class lbm_batch(ctypes.Structure):
-    _fields_ = [("policy", ctypes.c_int32), ("blocks", ctypes.c_int32)]
+    _fields_ = [("policy", ctypes.c_int32), ("blocks", ctypes.c_int32), ("max_waves", ctypes.c_int32)]
 
 
 LBM_BATCH_SERIAL, LBM_BATCH_FLAT, LBM_BATCH_STRIDED, LBM_BATCH_LPT = 0, 1, 2, 3
@@ -250,15 +250,15 @@ def lbm_get_launch(ctx, inst: int = 0) -> dict:
     return {"rows": cfg.rows, "xcd_remap": cfg.xcd_remap, "tile_width": cfg.tile_width, "max_waves": cfg.max_waves}
 
 
-def lbm_set_batch(ctx, policy: int, blocks: int = 0) -> None:
-    cfg = lbm_batch(int(policy), int(blocks))
+def lbm_set_batch(ctx, policy: int, blocks: int = 0, max_waves: int = 0) -> None:
+    cfg = lbm_batch(int(policy), int(blocks), int(max_waves))
     _check(lib().lbm_set_batch(ctx, ctypes.byref(cfg)))
 
 
 def lbm_get_batch(ctx) -> dict:
     cfg = lbm_batch()
     _check(lib().lbm_get_batch(ctx, ctypes.byref(cfg)))
-    return {"policy": cfg.policy, "blocks": cfg.blocks}
+    return {"policy": cfg.policy, "blocks": cfg.blocks, "max_waves": cfg.max_waves}
 
 
 def lbm_adjoint_bytes(ctx, inst: int = 0) -> int:

@@ -69,8 +69,8 @@ class Solver:
     def get_launch(self, inst: int = 0) -> dict:
         return L.lbm_get_launch(self.ctx, inst)
 
-    def set_batch(self, policy: int, blocks: int = 0) -> None:
-        L.lbm_set_batch(self.ctx, policy, blocks)
+    def set_batch(self, policy: int, blocks: int = 0, max_waves: int = 0) -> None:
+        L.lbm_set_batch(self.ctx, policy, blocks, max_waves)
 
     def get_batch(self) -> dict:
         return L.lbm_get_batch(self.ctx)

@@ -28,7 +28,8 @@ def mixed_configs():
             W.PulseConfig(N=3, D=1e-2), W.PulseConfig(N=200, U0=5.0, sigma0=0.15, D_variable=True)]
 
 
-POLICIES = [(lbm.LBM_BATCH_FLAT, 0), (lbm.LBM_BATCH_STRIDED, 7), (lbm.LBM_BATCH_LPT, 5), (lbm.LBM_BATCH_LPT, 4096)]
+POLICIES = [(lbm.LBM_BATCH_FLAT, 0, 0), (lbm.LBM_BATCH_STRIDED, 7, 0), (lbm.LBM_BATCH_LPT, 5, 0),
+            (lbm.LBM_BATCH_LPT, 4096, 0), (lbm.LBM_BATCH_FLAT, 0, 6), (lbm.LBM_BATCH_LPT, 5, 3)]
 
 
 @pytest.mark.parametrize("mode", ["f64", "f32", "f16s"])
@@ -39,10 +40,11 @@ def test_batched_policies_match_serial_bitwise(mode):
     ref.step(70)  # two graph replays of 32 steps + 6 eager steps
     want = [ref.state_save(k) for k in range(len(insts))]
     ref.close()
-    for policy, blocks in POLICIES:
+    for policy, blocks, cap in POLICIES:
         s = Solver(insts)
-        assert s.get_batch()["policy"] == lbm.LBM_BATCH_FLAT  # default for a uniform batch
-        s.set_batch(policy, blocks)
+        assert s.get_batch() == {"policy": lbm.LBM_BATCH_FLAT, "blocks": 0,  # default for a uniform batch
+                                 "max_waves": 6 if mode == "f32" else 0}
+        s.set_batch(policy, blocks, cap)
         s.step(3)
         s.macros()  # synchronizing work between eager steps and graph replays
         s.step(67)
@@ -111,6 +113,10 @@ def test_mixed_modes_fall_back_to_serial():
     with pytest.raises(lbm.LbmError) as ei:
         s.set_batch(lbm.LBM_BATCH_FLAT)
     assert ei.value.status == lbm.LBM_E_UNSUPPORTED
+    for cap in (2, 9, -1):
+        with pytest.raises(lbm.LbmError) as ei:
+            s.set_batch(lbm.LBM_BATCH_SERIAL, 0, cap)
+        assert ei.value.status == lbm.LBM_E_ARG, cap
     s.step(5)
     t = Solver([b])
     t.step(5)
