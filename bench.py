@@ -409,6 +409,94 @@ def _find(dirpath, suffix):
     raise FileNotFoundError(f"no *{suffix} under {dirpath}")
 
 
+def _kernel3_label(name: str):
+    """'step3_kernel<27, 2, 0, false, false>' (velocities, mode, aux, has_k, has_s) -> ('d3q27', 'f32')
+    for the constant-D, source-free kernels; copy -> ('copy',); other -> None."""
+    import re
+    m = re.search(r"step3_kernel<(19|27), (\d), (\d), false, false>", name)
+    if m:
+        return (f"d3q{m.group(1)}", KERNEL_MODES[m.group(2)])
+    if "copy_kernel" in name:
+        return ("copy",)
+    return None
+
+
+def bytes_per_lup3(q: int, mode: str) -> int:
+    """Algorithmic HBM bytes per 3D lattice update: q populations in + q out and u (3 components)."""
+    return {"f64": 2 * q * 8 + 24, "f64s_f32m": 2 * q * 8 + 12, "f32": 2 * q * 4 + 12}[mode]
+
+
+def run_profile3(torch, W, lbm, Solver, n, steps):
+    """The workload the 3D profiles are taken on: the rotating pulse at n^3 on D3Q19 and D3Q27, FP32
+    and FP64 storage, `steps` steps each in the default launch shape, then the copy calibration."""
+    import numpy as np
+    cfg = W.PulseConfig(N=n, steps=steps)
+    f = W.rotating_pulse3(cfg)
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    fields = {"phi0": dv(f["phi0"]), "ux": dv(f["u"][0]), "uy": dv(f["u"][1]), "uz": dv(f["u"][2])}
+    out = {}
+    for q in (19, 27):
+        for mode in ("f32", "f64"):
+            s = Solver([(lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, mode, nz=n, lattice=q), fields)])
+            s.step(2)  # graph capture happens outside the timed steps
+            ms = _timed_steps(torch, s, steps)
+            s.close()
+            out[f"d3q{q}_{mode}"] = {"mlups": n ** 3 / (ms * 1e-3) / 1e6, "ms_per_step": ms}
+            print(f"# d3q{q} {mode}: {out[f'd3q{q}_{mode}']['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    out["copy_gbps"] = copy_bandwidth(torch, lbm)
+    return out
+
+
+def summarize_profiles3(trace_dir, pmc_dirs, out_dir, n, command, pmc_commands):
+    """Kernel-trace statistics and copy-scaled FETCH_SIZE / WRITE_SIZE traffic of the D3Q19 and D3Q27
+    step kernels (written beside the two-dimensional summaries)."""
+    lines = [f"# rocprofv3 kernel trace: D3Q19 / D3Q27 step kernels, rotating pulse {n}^3", "",
+             f"Command: `{command}`", "",
+             "| kernel | lattice | mode | calls | average (us) | total (ms) |", "|---|---|---|---|---|---|"]
+    for r in _csv_rows(_find(trace_dir, "kernel_stats.csv")):
+        lab = _kernel3_label(r["Name"])
+        if lab is None or lab[0] == "copy":
+            continue
+        lines.append(f"| {r['Name'][:80]} | {lab[0]} | {lab[1]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} |")
+    with open(os.path.join(out_dir, f"step3_kernel_trace_{n}.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    entries, calib = {}, {}
+    for counter, d in pmc_dirs.items():
+        per = {}
+        for r in _csv_rows(_find(d, "counter_collection.csv")):
+            lab = _kernel3_label(r.get("Kernel_Name", ""))
+            if lab is None or r.get("Counter_Name") != counter:
+                continue
+            per.setdefault("copy" if lab[0] == "copy" else f"{lab[0]}_{lab[1]}", []).append(float(r["Counter_Value"]))
+        if "copy" in per:
+            c = sorted(per.pop("copy"))
+            calib[counter] = c[len(c) // 2] / (2 * 1024 * 1024)  # copy moves 2 GiB each way
+        for key, vals in per.items():
+            vals = sorted(vals)
+            entries.setdefault(key, {})[counter + "_KiB_median"] = vals[len(vals) // 2]
+    md = [f"# HBM traffic of the D3Q19 / D3Q27 step kernels at {n}^3 (rocprofv3 FETCH_SIZE / WRITE_SIZE)", "",
+          "Each counter is divided by what it reads for the library's 2 GiB copy kernel in the same run. "
+          f"Kernel sources hash: {kernel_hash()}.", ""] + [
+          f"- `{c}`" for c in pmc_commands] + [
+          "", "| lattice | mode | FETCH KiB/dispatch | WRITE KiB/dispatch | HBM bytes/launch | algorithmic bytes/launch | "
+              "ratio |", "|---|---|---|---|---|---|---|"]
+    for key in sorted(entries):
+        e = entries[key]
+        lat, mode = key.split("_", 1)
+        if "FETCH_SIZE_KiB_median" not in e or "WRITE_SIZE_KiB_median" not in e:
+            continue
+        hbm = 1024.0 * (e["FETCH_SIZE_KiB_median"] / calib.get("FETCH_SIZE", 1.0) +
+                        e["WRITE_SIZE_KiB_median"] / calib.get("WRITE_SIZE", 1.0))
+        alg = float(n) ** 3 * bytes_per_lup3(int(lat[3:]), mode)
+        e.update(bytes_per_launch=hbm, algorithmic_bytes_per_launch=alg, traffic_over_algorithmic=hbm / alg)
+        md.append(f"| {lat} | {mode} | {e['FETCH_SIZE_KiB_median']:.0f} | {e['WRITE_SIZE_KiB_median']:.0f} | "
+                  f"{hbm:.4g} | {alg:.4g} | {hbm / alg:.3f} |")
+    with open(os.path.join(out_dir, f"step3_kernel_traffic_{n}.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    return entries
+
+
 def _kernel_label(name: str):
     """'step_kernel<2, 0, false, false, 0, false, 1>' (mode, aux, has_k, has_s, boundary, MRT-R, walk) ->
     ('step', 'f32', aux 0, has_k, has_s) for the periodic TRT-R kernels; copy -> ('copy',); other -> None."""
@@ -500,9 +588,22 @@ def main():
                     help="skip the 8192^2 precision, refinement, flux-form and adjoint studies")
     ap.add_argument("--summarize", metavar="RUNDIR",
                     help="write profiles/ summaries from rocprofv3 output under RUNDIR (no GPU needed)")
+    ap.add_argument("--profile3d", type=int, metavar="N", default=0,
+                    help="run only the D3Q19/D3Q27 profile workload at N^3 (--steps steps per kernel)")
     args = ap.parse_args()
     if args.summarize:
         d = args.summarize
+        if os.path.isdir(os.path.join(d, "trace3")):
+            n3 = 256
+            pmc3 = {c: os.path.join(d, f"pmc3_{c.lower()}") for c in ("FETCH_SIZE", "WRITE_SIZE")}
+            pmc3 = {k: v for k, v in pmc3.items() if os.path.isdir(v)}
+            summarize_profiles3(os.path.join(d, "trace3"), pmc3, os.path.join(ROOT, "profiles"), n3,
+                                f"rocprofv3 --kernel-trace --stats --output-format csv -d RUNDIR/trace3 -o trace -- "
+                                f"python3 bench.py --profile3d {n3} --steps 100",
+                                [f"rocprofv3 --pmc {c} --output-format csv -d RUNDIR/pmc3_{c.lower()} -o pmc -- "
+                                 f"python3 bench.py --profile3d {n3} --steps 8" for c in sorted(pmc3)])
+        if not os.path.isdir(os.path.join(d, "trace")):
+            return
         pmc = {(c, n): os.path.join(d, f"pmc_{c.lower()}_{n}") for c in ("FETCH_SIZE", "WRITE_SIZE") for n in (2048, 8192)}
         pmc = {k: v for k, v in pmc.items() if os.path.isdir(v)}
         summarize_profiles(os.path.join(d, "trace"), pmc, os.path.join(ROOT, "profiles"),
@@ -526,6 +627,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     lbm.lib()  # the HIP library is required
+    if args.profile3d:
+        print(json.dumps(run_profile3(torch, W, lbm, Solver, args.profile3d, args.steps)))
+        return
 
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
     head = "f32" if "f32" in modes else modes[0]

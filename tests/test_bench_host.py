@@ -85,3 +85,37 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+STEP3 = "void lbm::(anonymous namespace)::step3_kernel<{q}, {m}, 0, false, false>(lbm::StepArgs)"
+
+
+def test_kernel3_label_and_bytes():
+    assert bench._kernel3_label(STEP3.format(q=19, m=2)) == ("d3q19", "f32")
+    assert bench._kernel3_label(STEP3.format(q=27, m=0)) == ("d3q27", "f64")
+    assert bench._kernel3_label(STEP3.format(q=27, m=0).replace("false, false", "true, false")) is None
+    assert bench._kernel3_label(COPY) == ("copy",)
+    assert bench._kernel_label(STEP3.format(q=19, m=2)) is None  # not a D2Q9 kernel
+    assert bench.bytes_per_lup3(19, "f32") == 164 and bench.bytes_per_lup3(19, "f64") == 328
+    assert bench.bytes_per_lup3(27, "f32") == 228 and bench.bytes_per_lup3(27, "f64") == 456
+
+
+def test_summarize3_scales_counters_by_the_copy_kernel(tmp_path):
+    n = 64
+    run = tmp_path / "run"
+    _write_csv(str(run / "trace3" / "t_kernel_stats.csv"), ["Name", "Calls", "TotalDurationNs", "AverageNs"],
+               [[STEP3.format(q=27, m=2), 100, 1000000, 10000]])
+    copy_kib = 2 * 1024 * 1024
+    alg = n ** 3 * bench.bytes_per_lup3(27, "f32")
+    pmc = {}
+    for counter, scale in (("FETCH_SIZE", 0.5), ("WRITE_SIZE", 1.0)):
+        d = run / f"pmc3_{counter.lower()}"
+        _write_csv(str(d / "p_counter_collection.csv"), ["Kernel_Name", "Counter_Name", "Counter_Value"],
+                   [[STEP3.format(q=27, m=2), counter, scale * alg / 2 / 1024]] * 3 + [[COPY, counter, scale * copy_kib]])
+        pmc[counter] = str(d)
+    out = tmp_path / "out"
+    out.mkdir()
+    e = bench.summarize_profiles3(str(run / "trace3"), pmc, str(out), n, "cmd", ["c"])
+    assert abs(e["d3q27_f32"]["traffic_over_algorithmic"] - 1.0) < 1e-12
+    assert "| d3q27 | f32 |" in open(out / f"step3_kernel_traffic_{n}.md").read()
+    assert "10.00" in open(out / f"step3_kernel_trace_{n}.md").read()
