@@ -201,8 +201,10 @@ int lbm_state_load(lbm_ctx *ctx, int32_t inst, const void *src, int64_t step);
  * tile_width 64 stacks the block's waves along y (tiles of 64 columns x 4*rows rows); 256 puts them
  * side by side along x (256 columns x rows rows), so that each population row segment a block
  * reads or writes is 1 KiB (FP32) of contiguous memory.  max_waves caps the waves resident on each
- * SIMD (3..8; 0: as many as the registers allow) by reserving unused LDS per block; it applies to
- * one-instance launches (the SERIAL policy); the batched launch has its own cap (lbm_batch). */
+ * SIMD (3..8; 0: as many as the registers allow) by reserving unused LDS per block (no effect if
+ * the device does not report its LDS size); it applies to one-instance launches (the SERIAL policy);
+ * the batched launch has its own cap (lbm_batch).  Defaults depend on the lattice, storage, aux form,
+ * boundary and tiles per row (lbm_get_launch reports them). */
 typedef struct lbm_launch {
     int32_t rows;        /* 1..64 */
     int32_t xcd_remap;   /* tile order over the 8 XCDs (each has its own L2): 0 hardware order (tiles of a row
