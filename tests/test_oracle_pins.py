@@ -312,43 +312,6 @@ def test_rotation_and_shift_covariance(aux):
 
 # ---- P7 / P8: closed forms and convergence ----------------------------------------------------
 
-def _pulse_error(cfg):
-    f = W.rotating_pulse(cfg)
-    p = O.Problem(cfg.N, cfg.N, f["dx"], cfg.dt, cfg.lam, cfg.D, O.AUX_LOCAL)
-    g = O.init(p, f["phi0"], f["ux"], f["uy"])
-    g = O.run(p, g, cfg.steps, f["ux"], f["uy"], f["D"])
-    return O.rms_error(O.phi(p, g), W.pulse_reference(cfg, f))
-
-
-def test_heat_kernel_second_order():
-    """u = 0: a Gaussian spreads as the heat kernel with kappa = (tau1 - 1/2) cs2 dt (Sec. 2.4).
-    Diffusive scaling (tau1 fixed); the error must fall at second order."""
-    errs = []
-    for N in (32, 64, 128):
-        dt = 0.00625 * (32 / N) ** 2
-        cfg = W.PulseConfig(N=N, steps=int(round(0.1 / dt)), U0=0.0, D=1e-2, xc0=0.0, yc0=0.0,
-                            dt_override=dt)
-        errs.append(_pulse_error(cfg))
-    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
-    assert errs[0] < 3e-3
-    assert all(1.8 < o < 2.2 for o in orders), (errs, orders)
-
-
-def test_rotating_pulse_closed_form_second_order():
-    """Solid-body rotation u = (-pi y, pi x), D = 1e-3, c = 10 (the 64^2 workload and two
-    refinements), t = 0.125: converges to the closed form at second order."""
-    errs = []
-    for N in (64, 128, 256):
-        dt = (2.0 / N) / 10.0
-        cfg = W.PulseConfig(N=N, steps=int(round(0.125 / dt)))
-        errs.append(_pulse_error(cfg))
-    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
-    assert errs[-1] < 4e-4
-    assert all(1.7 < o < 2.2 for o in orders), (errs, orders)
-
-
-# ---- Dirichlet edges by non-equilibrium extrapolation (the boundary scheme of Sec. 3) ----------
-
 def test_nee_edge_moments():
     """apply_nee rebuilds each edge node from its inward neighbour x_f (diagonal at a corner): the
     new node carries phi = phi_b and j = phi_b u_b + (j_f - phi_f u_f), because g_eq carries the
@@ -436,62 +399,6 @@ def test_slip_free_relation_of_the_free_parameter(tau1):
 
 # ---- P9 / P14: the paper's printed Table 2 ----------------------------------------------------
 
-def _x1_error(N, kappa, aux):
-    f = W.x1_problem(N, kappa)
-    p = O.Problem(N, N, f["dx"], f["dt"], f["lam"], kappa, aux)
-    g = O.init(p, f["phi0"], f["ux"], f["uy"])
-    for s in range(f["steps"]):
-        S, dS = f["source"](s * f["dt"])
-        g = O.step(p, g, f["ux"], f["uy"], None, S, dS)
-    er = O.rms_error(O.phi(p, g), f["exact"](f["steps"] * f["dt"]))
-    return er * N / (N + 1)  # E_r over the paper's (N+1)^2 nodes (fixture's normalisation note)
-
-
-def _table2():
-    with open(os.path.join(GOLDEN, "table2_present.json")) as fh:
-        return json.load(fh)
-
-
-@pytest.mark.parametrize("kappa", ["0.005", "0.01", "0.05"])
-def test_table2_present_column(kappa):
-    """The oracle on a periodic proxy of the Sec. 3 benchmark reproduces every printed E_r of the
-    'Present' column of Table 2 to its four printed digits, and the printed orders."""
-    t = _table2()
-    errs = [_x1_error(N, float(kappa), O.AUX_LOCAL) for N in t["N"]]
-    for N, e, want in zip(t["N"], errs, t["E_r"][kappa]):
-        assert abs(e / want - 1) < 1e-3, (N, e, want)
-    for k in range(1, 5):
-        order = math.log(errs[k - 1] / errs[k]) / math.log(t["N"][k] / t["N"][k - 1])
-        assert abs(order - t["order"][kappa][k]) < 0.01, (k, order)
-
-
-def _x1_error_dirichlet(N, kappa):
-    """The benchmark on the paper's own grid: N + 1 nodes per axis, the closed form imposed on the
-    four edges by non-equilibrium extrapolation before every step and before the final read-out."""
-    f = W.x1_problem(N, kappa, dirichlet=True)
-    n = f["nx"]
-    p = O.Problem(n, n, f["dx"], f["dt"], f["lam"], kappa, O.AUX_LOCAL, O.BC_NEE)
-    g = O.init(p, f["phi0"], f["ux"], f["uy"])
-    for s in range(f["steps"]):
-        t = s * f["dt"]
-        g = O.apply_nee(p, g, f["ux"], f["uy"], f["exact"](t))
-        S, dS = f["source"](t)
-        g = O.step(p, g, f["ux"], f["uy"], None, S, dS)
-    T = f["steps"] * f["dt"]
-    g = O.apply_nee(p, g, f["ux"], f["uy"], f["exact"](T))
-    return O.rms_error(O.phi(p, g), f["exact"](T))
-
-
-@pytest.mark.parametrize("kappa", ["0.005", "0.01", "0.05"])
-def test_table2_on_the_dirichlet_grid(kappa):
-    """On the (N+1)^2 grid with Dirichlet edges the oracle reproduces the 'Present' column of
-    Table 2 directly (no node-count factor) to its printed digits."""
-    t = _table2()
-    for N, want in zip(t["N"], t["E_r"][kappa]):
-        e = _x1_error_dirichlet(N, float(kappa))
-        assert abs(e / want - 1) < 1e-3, (N, e, want)
-
-
 def test_table2_typo_reading():
     t = _table2()
     e20, e40, e60 = (_x1_error(N, 0.005, O.AUX_LOCAL) for N in (20, 40, 60))
@@ -567,3 +474,99 @@ def test_complex_build_matches_real_and_fd():
     eps = 1e-4
     fd = (O.run(p, g0, 5, ux, uy, D + eps * dD) - O.run(p, g0, 5, ux, uy, D - eps * dD)) / (2 * eps)
     np.testing.assert_allclose(deriv, fd, rtol=0, atol=1e-8 * np.abs(deriv).max())
+
+
+# ---- the slower convergence and Table 2 pins run last (the mutation check stops at the first failure)
+
+def _x1_error(N, kappa, aux):
+    f = W.x1_problem(N, kappa)
+    p = O.Problem(N, N, f["dx"], f["dt"], f["lam"], kappa, aux)
+    g = O.init(p, f["phi0"], f["ux"], f["uy"])
+    for s in range(f["steps"]):
+        S, dS = f["source"](s * f["dt"])
+        g = O.step(p, g, f["ux"], f["uy"], None, S, dS)
+    er = O.rms_error(O.phi(p, g), f["exact"](f["steps"] * f["dt"]))
+    return er * N / (N + 1)  # E_r over the paper's (N+1)^2 nodes (fixture's normalisation note)
+
+
+def _table2():
+    with open(os.path.join(GOLDEN, "table2_present.json")) as fh:
+        return json.load(fh)
+
+
+@pytest.mark.parametrize("kappa", ["0.005", "0.01", "0.05"])
+def test_table2_present_column(kappa):
+    """The oracle on a periodic proxy of the Sec. 3 benchmark reproduces every printed E_r of the
+    'Present' column of Table 2 to its four printed digits, and the printed orders."""
+    t = _table2()
+    errs = [_x1_error(N, float(kappa), O.AUX_LOCAL) for N in t["N"]]
+    for N, e, want in zip(t["N"], errs, t["E_r"][kappa]):
+        assert abs(e / want - 1) < 1e-3, (N, e, want)
+    for k in range(1, 5):
+        order = math.log(errs[k - 1] / errs[k]) / math.log(t["N"][k] / t["N"][k - 1])
+        assert abs(order - t["order"][kappa][k]) < 0.01, (k, order)
+
+
+def _x1_error_dirichlet(N, kappa):
+    """The benchmark on the paper's own grid: N + 1 nodes per axis, the closed form imposed on the
+    four edges by non-equilibrium extrapolation before every step and before the final read-out."""
+    f = W.x1_problem(N, kappa, dirichlet=True)
+    n = f["nx"]
+    p = O.Problem(n, n, f["dx"], f["dt"], f["lam"], kappa, O.AUX_LOCAL, O.BC_NEE)
+    g = O.init(p, f["phi0"], f["ux"], f["uy"])
+    for s in range(f["steps"]):
+        t = s * f["dt"]
+        g = O.apply_nee(p, g, f["ux"], f["uy"], f["exact"](t))
+        S, dS = f["source"](t)
+        g = O.step(p, g, f["ux"], f["uy"], None, S, dS)
+    T = f["steps"] * f["dt"]
+    g = O.apply_nee(p, g, f["ux"], f["uy"], f["exact"](T))
+    return O.rms_error(O.phi(p, g), f["exact"](T))
+
+
+@pytest.mark.parametrize("kappa", ["0.005", "0.01", "0.05"])
+def test_table2_on_the_dirichlet_grid(kappa):
+    """On the (N+1)^2 grid with Dirichlet edges the oracle reproduces the 'Present' column of
+    Table 2 directly (no node-count factor) to its printed digits."""
+    t = _table2()
+    for N, want in zip(t["N"], t["E_r"][kappa]):
+        e = _x1_error_dirichlet(N, float(kappa))
+        assert abs(e / want - 1) < 1e-3, (N, e, want)
+
+
+def _pulse_error(cfg):
+    f = W.rotating_pulse(cfg)
+    p = O.Problem(cfg.N, cfg.N, f["dx"], cfg.dt, cfg.lam, cfg.D, O.AUX_LOCAL)
+    g = O.init(p, f["phi0"], f["ux"], f["uy"])
+    g = O.run(p, g, cfg.steps, f["ux"], f["uy"], f["D"])
+    return O.rms_error(O.phi(p, g), W.pulse_reference(cfg, f))
+
+
+def test_heat_kernel_second_order():
+    """u = 0: a Gaussian spreads as the heat kernel with kappa = (tau1 - 1/2) cs2 dt (Sec. 2.4).
+    Diffusive scaling (tau1 fixed); the error must fall at second order."""
+    errs = []
+    for N in (32, 64, 128):
+        dt = 0.00625 * (32 / N) ** 2
+        cfg = W.PulseConfig(N=N, steps=int(round(0.1 / dt)), U0=0.0, D=1e-2, xc0=0.0, yc0=0.0,
+                            dt_override=dt)
+        errs.append(_pulse_error(cfg))
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    assert errs[0] < 3e-3
+    assert all(1.8 < o < 2.2 for o in orders), (errs, orders)
+
+
+def test_rotating_pulse_closed_form_second_order():
+    """Solid-body rotation u = (-pi y, pi x), D = 1e-3, c = 10 (the 64^2 workload and two
+    refinements), t = 0.125: converges to the closed form at second order."""
+    errs = []
+    for N in (64, 128, 256):
+        dt = (2.0 / N) / 10.0
+        cfg = W.PulseConfig(N=N, steps=int(round(0.125 / dt)))
+        errs.append(_pulse_error(cfg))
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    assert errs[-1] < 4e-4
+    assert all(1.7 < o < 2.2 for o in orders), (errs, orders)
+
+
+# ---- Dirichlet edges by non-equilibrium extrapolation (the boundary scheme of Sec. 3) ----------
