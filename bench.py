@@ -201,11 +201,13 @@ def run_refinement(torch, W, lbm, Solver, sizes=(64, 128, 256, 512, 1024, 2048),
     """E_r against the closed-form pulse at t = 0.3125 under acoustic (c = 10) and diffusive
     (dx^2/dt fixed at its 256^2 value) refinement; least-squares orders over N >= 256 (the coarse grids
     under-resolve sigma0 = 0.1); N* = finest N at which a reduced-precision mode stays within 5 % of the
-    FP64 E_r."""
+    FP64 E_r; with acoustic scaling also each mode's MLUPS per N (400 more steps, timed after the
+    error is read) and its speedup over FP64 at N*, i.e. at equal error against the closed form."""
     import numpy as np
     out = {}
     for scaling in ("acoustic", "diffusive"):
         res = {m: [] for m in modes}
+        mlups = {m: [] for m in modes}
         for N in sizes:
             cfg = W.refinement(N, scaling)
             f = W.rotating_pulse(cfg)
@@ -215,8 +217,12 @@ def run_refinement(torch, W, lbm, Solver, sizes=(64, 128, 256, 512, 1024, 2048),
                 s = Solver([(lbm.make_params(N, N, f["dx"], cfg.dt, cfg.lam, cfg.D, m), dev)])
                 s.step(cfg.steps)
                 res[m].append(s.macros(ref=ref, raise_nonfinite=False)["rms_err"])
+                if scaling == "acoustic":
+                    mlups[m].append(N * N / (_timed_steps(torch, s, 400) * 1e-3) / 1e6)
                 s.close()
         entry = {"N": list(sizes), "E_r": res}
+        if scaling == "acoustic":
+            entry["mlups"] = mlups
         for m in modes:
             e = np.array(res[m])
             ok = np.isfinite(e) & (e > 0) & (np.array(sizes) >= 256)
@@ -225,6 +231,9 @@ def run_refinement(torch, W, lbm, Solver, sizes=(64, 128, 256, 512, 1024, 2048),
             if m != "f64":
                 within = [N for N, a, b in zip(sizes, res[m], res["f64"]) if np.isfinite(a) and a <= 1.05 * b]
                 entry.setdefault("N_star", {})[m] = max(within) if within else None
+                if within and scaling == "acoustic":
+                    k = list(sizes).index(max(within))
+                    entry.setdefault("speedup_at_N_star", {})[m] = mlups[m][k] / mlups["f64"][k]
         out[scaling] = entry
     return out
 
