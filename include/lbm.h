@@ -1,5 +1,5 @@
 /*
- * lbm.h -- C ABI of the MI355X (gfx950) TRT-R D2Q9 lattice Boltzmann library.
+ * lbm.h -- C ABI of the MI355X (gfx950) TRT-R lattice Boltzmann library (D2Q9; D3Q19 and D3Q27).
  *
  * The library advances the two-relaxation-time regularized (TRT-R) lattice Boltzmann model for the
  * convection-diffusion equation with variable coefficients (Y. Yu, Z. Qin, H. Yuan, S. Shu,
@@ -7,7 +7,8 @@
  *
  *     d_t phi + d_a(phi u_a) = d_a(kappa d_a phi) + S                     (Sec. 2.1, Eq. (1))
  *
- * on D2Q9 lattices, periodic or with Dirichlet edges.  One step is the evolution equation of Sec. 2.2, Eq. (14): the TRT-R
+ * on D2Q9 lattices, periodic or with Dirichlet edges or walls, and on periodic D3Q19 / D3Q27 lattices
+ * (enum lbm_lattice).  One step is the evolution equation of Sec. 2.2, Eq. (14): the TRT-R
  * collision of Eq. (12) (third-order Hermite equilibrium, Eq. (6); Hermite-regularized first- and
  * second-order non-equilibrium moments, Eqs. (8) and (13), relaxed with tau1 and tau2), the
  * first-order discrete-velocity source of Eq. (3) with its time derivative, and the space-derivative
@@ -18,7 +19,8 @@
  * Conventions shared by every entry point:
  *   - Memory: every pointer marked "device" is HIP device memory of the current device; pointers
  *     marked "host" are host memory.  The caller owns every buffer it passes.  Fields are FP64,
- *     row-major [ny][nx] (node (j, k) at index k*nx + j), with no padding.
+ *     row-major [ny][nx] (node (j, k) at index k*nx + j), with no padding; on the 3D lattices
+ *     [nz][ny][nx].
  *   - Streams: all work is enqueued on the stream given to lbm_init (a hipStream_t; NULL is the
  *     default stream).  Calls are asynchronous unless stated otherwise.  Input fields must stay
  *     valid until the stream has passed the call that reads them.
