@@ -219,6 +219,42 @@ def test_full_size_8192_variable_D_windows(mode):
             assert np.abs(got - want).max() <= 1e-6 * gmax
 
 
+@pytest.mark.parametrize("mode", ["f64", "f32", "f16s"])
+def test_longest_row_windows(mode):
+    """The longest row the ABI accepts (nx = 2^24, ny = 3): lane byte offsets and tile indices at their
+    extremes (65,536 tiles per row, column bands of 8,192 tiles).  One step after 3, checked on
+    windows at the start, the middle and the periodic end of the row against the oracle stepping the
+    GPU state (all three rows, which wrap in y exactly as on the GPU)."""
+    nx, ny, w, m = 1 << 24, 3, 64, 2
+    x = np.arange(nx) / nx
+    ux = np.broadcast_to(0.2 * np.sin(2 * np.pi * x), (ny, nx)).copy()
+    uy = np.broadcast_to(0.1 * np.cos(2 * np.pi * 3 * x), (ny, nx)).copy()
+    uy[1] *= -1.0
+    phi0 = 1.0 + 0.5 * np.broadcast_to(np.cos(2 * np.pi * 5 * x), (ny, nx))
+    dx, dt, lam, D = 1.0 / nx, 0.5 / nx, 0.25, 1.0 / (6.0 * nx)
+    p = lbm.make_params(nx, ny, dx, dt, lam, D, mode, phi_ref=1.0)
+    s = Solver([(p, {"phi0": dev(phi0), "ux": dev(ux), "uy": dev(uy)})])
+    assert s.get_launch()["xcd_remap"] == 2
+    s.step(3)
+    g0 = s.populations()
+    s.step(1)
+    g1 = s.populations()
+    s.close()
+    gmax = float(g1.abs().max())
+    for x0 in (0, nx // 2 + 12345, nx - w // 2):
+        xs = (np.arange(x0 - m, x0 + w + m)) % nx
+        ix = torch.as_tensor(xs, device=g0.device)
+        gw = g0.index_select(2, ix).cpu().numpy()
+        q = O.Problem(w + 2 * m, ny, dx, dt, lam, D, O.AUX_LOCAL)
+        want = O.step(q, gw, ux[:, xs], uy[:, xs])[:, :, m:-m]
+        got = g1.index_select(2, ix[m:-m]).cpu().numpy()
+        err = np.abs(got - want).max() / gmax
+        bound = {"f64": TOL64, "f32": 1e-6, "f16s": 2.0 ** -10}[mode]
+        assert err <= bound, (x0, err)
+    del g0, g1
+    torch.cuda.empty_cache()
+
+
 def test_full_size_8192_flux_window():
     cfg = W.C3
     f = W.rotating_pulse(cfg)
