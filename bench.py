@@ -307,7 +307,7 @@ def run_3d(torch, W, lbm, Solver, q=19, sizes=(64, 128, 256), tp_steps=400):
     D3Q27 lattice: E_r against the closed form per storage mode and size, and the step's throughput
     at the largest size."""
     import numpy as np
-    BYTES = {"f64": q * 16 + 24, "f64s_f32m": q * 16 + 12, "f32": q * 8 + 12}
+    BYTES = {"f64": q * 16 + 24, "f64s_f32m": q * 16 + 12, "f32": q * 8 + 12, "f16s": q * 4 + 12}
     out = {"N": list(sizes), "E_r": {m: [] for m in BYTES}, "throughput": {}}
     dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     for n in sizes:
@@ -432,7 +432,7 @@ def _kernel3_label(name: str):
 
 def bytes_per_lup3(q: int, mode: str) -> int:
     """Algorithmic HBM bytes per 3D lattice update: q populations in + q out and u (3 components)."""
-    return {"f64": 2 * q * 8 + 24, "f64s_f32m": 2 * q * 8 + 12, "f32": 2 * q * 4 + 12}[mode]
+    return {"f64": 2 * q * 8 + 24, "f64s_f32m": 2 * q * 8 + 12, "f32": 2 * q * 4 + 12, "f16s": 2 * q * 2 + 12}[mode]
 
 
 def run_profile3(torch, W, lbm, Solver, n, steps):

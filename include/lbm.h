@@ -85,9 +85,9 @@ enum lbm_boundary { LBM_BC_PERIODIC = 0, LBM_BC_NEE = 1, LBM_BC_WALLS = 2 };
  * weights 1/3, 1/18, 1/36 (D3Q19); D3Q27 adds the corners 19:(1,1,1) 20:(-1,-1,-1) 21:(1,1,-1)
  * 22:(-1,-1,1) 23:(1,-1,1) 24:(-1,1,-1) 25:(-1,1,1) 26:(1,-1,-1), with weights 8/27, 2/27, 1/54,
  * 1/216; c_s^2 = c^2/3.  The third-order equilibrium keeps every Hermite component the lattice
- * supports (D3Q27 keeps H_xyz, D3Q19 does not).  3D instances are periodic, use FP64 or FP32
- * storage, aux LOCAL or NONE and TRT-R (tau3 0 or 1), run one launch per instance and have no
- * adjoint. */
+ * supports (D3Q27 keeps H_xyz, D3Q19 does not).  3D instances are periodic, use any storage mode
+ * (FP64, FP32 or shifted FP16, with the lattice's own weights in w_i phi_ref), aux LOCAL or NONE
+ * and TRT-R (tau3 0 or 1), run one launch per instance and have no adjoint. */
 enum lbm_lattice { LBM_LATTICE_D2Q9 = 0, LBM_LATTICE_D3Q19 = 1, LBM_LATTICE_D3Q27 = 2 };
 
 /* One problem instance: the paper's problem statement on a lattice. */

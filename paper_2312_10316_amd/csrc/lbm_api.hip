@@ -91,8 +91,9 @@ int lds_reserve_for(int max_waves, int lds_per_cu)
 // Dirichlet edges and walls (the walking-loop kernels): FP32 two rows on 256-column tiles in row
 // bands; FP64 one row on 64-column tiles in hardware order (2049^2: +17 % and +4 % over the
 // periodic defaults).
-// D3Q19 and D3Q27: one row on 256-column tiles in hardware order, FP32 capped at 4 waves (+17 % on
-// D3Q19 and +14 % on D3Q27 over 64-column tiles at full occupancy).
+// D3Q19 and D3Q27: 256-column tiles in hardware order; one row per wave, FP32 capped at 4 waves (+17 %
+// on D3Q19 and +14 % on D3Q27 over 64-column tiles at full occupancy); FP16 storage walks two rows
+// uncapped (+14 % / +11 % over one row).  (256^3.)
 // A context of several instances keeps 64-column tiles in row bands, which the batched kernel prefers
 // (a 256-column tile of a small lattice leaves waves idle).
 Launch default_launch(const lbm_params &p, int mode, int n_inst, int lds_per_cu)
@@ -102,6 +103,7 @@ Launch default_launch(const lbm_params &p, int mode, int n_inst, int lds_per_cu)
     const int bands = ((p.nx + 255) / 256) % 8 == 0 ? 2 : 1;
     if (p.lattice != LBM_LATTICE_D2Q9) {
         lc.max_waves = f32 ? 4 : 0;
+        if (f16) lc.rows = 2;
     } else if (p.boundary != LBM_BC_PERIODIC) {
         if (f32) {
             lc.rows = 2;
@@ -156,7 +158,6 @@ int validate(const lbm_params &p, int k)
     if (p.tau3 != 0.0 && !(std::isfinite(p.tau3) && p.tau3 > 0.5))
         return fail(LBM_E_ARG, "instance %d: tau3 must be 0 (TRT-R) or finite and > 1/2", k);
     if (three_d) {
-        if (p.store == LBM_STORE_F16S) return fail(LBM_E_UNSUPPORTED, "instance %d: no FP16 storage on 3D lattices", k);
         if (p.aux == LBM_AUX_FLUX) return fail(LBM_E_UNSUPPORTED, "instance %d: the flux form is D2Q9 only", k);
         if (p.boundary != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "instance %d: 3D lattices are periodic only", k);
         if (p.tau3 != 0.0 && p.tau3 != 1.0) return fail(LBM_E_UNSUPPORTED, "instance %d: no MRT-R on 3D lattices", k);
@@ -169,13 +170,23 @@ int validate(const lbm_params &p, int k)
     return LBM_OK;
 }
 
+// Lattice weight w_i of velocity i on the 3D lattices (rest, 6 faces, 12 edges, 8 corners).
+double weight3(int q, int i)
+{
+    if (i == 0) return q == 27 ? 8.0 / 27.0 : 1.0 / 3.0;
+    if (i <= 6) return q == 27 ? 2.0 / 27.0 : 1.0 / 18.0;
+    if (i <= 18) return q == 27 ? 1.0 / 54.0 : 1.0 / 36.0;
+    return 1.0 / 216.0;
+}
+
 F16Params f16_of(const lbm_params &p)
 {
     F16Params f{};
     if (p.store == LBM_STORE_F16S) {
         f.scale = std::ldexp(1.0f, p.scale_log2);
         f.inv_scale = std::ldexp(1.0f, -p.scale_log2);
-        for (int i = 0; i < 9; ++i) f.wref[i] = (float)(kW[i] * p.phi_ref);
+        const int q = layout_of(p).q;
+        for (int i = 0; i < q; ++i) f.wref[i] = (float)((q == 9 ? kW[i] : weight3(q, i)) * p.phi_ref);
     } else {
         f.scale = f.inv_scale = 1.0f;
     }

@@ -135,7 +135,7 @@ struct StoreF16S {
 // F16S codec constants: h = f16((g - w_i phi_ref) * 2^k); g = h * 2^-k + w_i phi_ref.
 struct F16Params {
     float scale, inv_scale;
-    float wref[9];
+    float wref[27];  // w_i phi_ref per velocity (9, 19 or 27 used)
 };
 
 template <class St, class M>

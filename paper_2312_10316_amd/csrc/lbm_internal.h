@@ -164,7 +164,7 @@ constexpr int kMacroBlocks = 1024;
 
 struct PopArgs {
     const void *src;
-    double *out;  // dense FP64 [9][ny][nx]
+    double *out;  // dense FP64 [q][ny][nx] ([q][nz][ny][nx] on the 3D lattices)
     Layout L;
     F16Params f16;
     EdgeArgs edge;

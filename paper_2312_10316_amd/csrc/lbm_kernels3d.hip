@@ -160,17 +160,16 @@ __device__ __forceinline__ void collide3(const M (&g)[Q], M ux, M uy, M uz, cons
 // g_i(x, y, z) = buf_i(x - e_i) for one node (diagnostics).
 template <int Q, class St, class M>
 __device__ __forceinline__ void pull_node3(const typename St::T *__restrict__ src, const Layout &L, int x, int y, int z,
-                                           M (&g)[Q])
+                                           const F16Params &f, M (&g)[Q])
 {
     using C = Codec<St, M>;
-    const F16Params none{};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         int xs = x - kEx3[i], ys = y - kEy3[i], zs = z - kEz3[i];
         xs = xs < 0 ? xs + L.nx : (xs >= L.nx ? xs - L.nx : xs);
         ys = ys < 0 ? ys + L.ny : (ys >= L.ny ? ys - L.ny : ys);
         zs = zs < 0 ? zs + L.nz : (zs >= L.nz ? zs - L.nz : zs);
-        g[i] = C::dec(src[(((int64_t)zs * L.ny + ys) * Q + i) * L.pitch + xs], i, none);
+        g[i] = C::dec(src[(((int64_t)zs * L.ny + ys) * Q + i) * L.pitch + xs], i, f);
     }
 }
 
@@ -297,6 +296,7 @@ __global__ __launch_bounds__(256) void init3_kernel(const InitArgs a)
     const int64_t N = (int64_t)nx * ny * nz, pitch = a.L.pitch;
     T *dst = static_cast<T *>(a.dst);
     const M *u = static_cast<const M *>(a.u);
+    bool bad = false;
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(n % nx);
         const int64_t r = n / nx;
@@ -310,9 +310,14 @@ __global__ __launch_bounds__(256) void init3_kernel(const InitArgs a)
             xd = xd < 0 ? xd + nx : (xd >= nx ? xd - nx : xd);
             yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
             zd = zd < 0 ? zd + nz : (zd >= nz ? zd - nz : zd);
+            if (MODE == MODE_F16S_F32) {
+                const float v = ((float)P[i] - a.f16.wref[i]) * a.f16.scale;
+                bad |= !(fabsf(v) <= 65504.0f);
+            }
             dst[(((int64_t)zd * ny + yd) * Q + i) * pitch + xd] = C::enc(P[i], i, a.f16);
         }
     }
+    if (bad) *a.range_flag = 1;  // every writer stores the same value
 }
 
 template <int Q, int MODE>
@@ -330,7 +335,7 @@ __global__ __launch_bounds__(256) void macros3_kernel(const MacroArgs a)
         const int x = (int)(n % nx);
         const int64_t r = n / nx;
         M g[Q];
-        pull_node3<Q, St, M>(src, a.L, x, (int)(r % ny), (int)(r / ny), g);
+        pull_node3<Q, St, M>(src, a.L, x, (int)(r % ny), (int)(r / ny), a.f16, g);
         double phi = 0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) phi += (double)g[i];
@@ -374,7 +379,7 @@ __global__ __launch_bounds__(256) void populations3_kernel(const PopArgs a)
         const int x = (int)(n % nx);
         const int64_t r = n / nx;
         M g[Q];
-        pull_node3<Q, St, M>(src, a.L, x, (int)(r % ny), (int)(r / ny), g);
+        pull_node3<Q, St, M>(src, a.L, x, (int)(r % ny), (int)(r / ny), a.f16, g);
 #pragma unroll
         for (int i = 0; i < Q; ++i) a.out[i * N + n] = (double)g[i];
     }
@@ -419,6 +424,8 @@ hipError_t launch_step3(int mode, int aux, const StepArgs &a, hipStream_t st)
         return q27 ? launch_step3_mode<27, MODE_F64_F32>(aux, a, st) : launch_step3_mode<19, MODE_F64_F32>(aux, a, st);
     case MODE_F32_F32:
         return q27 ? launch_step3_mode<27, MODE_F32_F32>(aux, a, st) : launch_step3_mode<19, MODE_F32_F32>(aux, a, st);
+    case MODE_F16S_F32:
+        return q27 ? launch_step3_mode<27, MODE_F16S_F32>(aux, a, st) : launch_step3_mode<19, MODE_F16S_F32>(aux, a, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -433,6 +440,7 @@ hipError_t launch_init3_q(int mode, const InitArgs &a, hipStream_t st)
     case MODE_F64_F64: init3_kernel<Q, MODE_F64_F64><<<g, 256, 0, st>>>(a); break;
     case MODE_F64_F32: init3_kernel<Q, MODE_F64_F32><<<g, 256, 0, st>>>(a); break;
     case MODE_F32_F32: init3_kernel<Q, MODE_F32_F32><<<g, 256, 0, st>>>(a); break;
+    case MODE_F16S_F32: init3_kernel<Q, MODE_F16S_F32><<<g, 256, 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -446,6 +454,7 @@ hipError_t launch_macros3_q(int mode, const MacroArgs &a, double *result, hipStr
     case MODE_F64_F64: macros3_kernel<Q, MODE_F64_F64><<<g, 256, 0, st>>>(a); break;
     case MODE_F64_F32: macros3_kernel<Q, MODE_F64_F32><<<g, 256, 0, st>>>(a); break;
     case MODE_F32_F32: macros3_kernel<Q, MODE_F32_F32><<<g, 256, 0, st>>>(a); break;
+    case MODE_F16S_F32: macros3_kernel<Q, MODE_F16S_F32><<<g, 256, 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
@@ -461,6 +470,7 @@ hipError_t launch_populations3_q(int mode, const PopArgs &a, hipStream_t st)
     case MODE_F64_F64: populations3_kernel<Q, MODE_F64_F64><<<g, 256, 0, st>>>(a); break;
     case MODE_F64_F32: populations3_kernel<Q, MODE_F64_F32><<<g, 256, 0, st>>>(a); break;
     case MODE_F32_F32: populations3_kernel<Q, MODE_F32_F32><<<g, 256, 0, st>>>(a); break;
+    case MODE_F16S_F32: populations3_kernel<Q, MODE_F16S_F32><<<g, 256, 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -124,7 +124,7 @@ def test_invalid_3d_parameters(kw, msg):
 
 @pytest.mark.parametrize("q", [19, 27])
 def test_3d_unsupported_combinations(q):
-    for kw in (dict(mode="f16s"), dict(aux=L.LBM_AUX_FLUX), dict(boundary=L.LBM_BC_NEE), dict(tau3=0.9)):
+    for kw in (dict(aux=L.LBM_AUX_FLUX), dict(boundary=L.LBM_BC_NEE), dict(tau3=0.9)):
         with pytest.raises(L.LbmError) as ei:
             L.lbm_workspace_size([_p(nz=8, lattice=q, **kw)])
         assert ei.value.status == L.LBM_E_UNSUPPORTED, kw

@@ -98,6 +98,7 @@ def test_kernel3_label_and_bytes():
     assert bench._kernel_label(STEP3.format(q=19, m=2)) is None  # not a D2Q9 kernel
     assert bench.bytes_per_lup3(19, "f32") == 164 and bench.bytes_per_lup3(19, "f64") == 328
     assert bench.bytes_per_lup3(27, "f32") == 228 and bench.bytes_per_lup3(27, "f64") == 456
+    assert bench.bytes_per_lup3(19, "f16s") == 88
 
 
 def test_summarize3_scales_counters_by_the_copy_kernel(tmp_path):
