@@ -92,8 +92,8 @@ int lds_reserve_for(int max_waves, int lds_per_cu)
 // bands; FP64 one row on 64-column tiles in hardware order (2049^2: +17 % and +4 % over the
 // periodic defaults).
 // D3Q19 and D3Q27: 256-column tiles in hardware order; one row per wave, FP32 capped at 4 waves (+17 %
-// on D3Q19 and +14 % on D3Q27 over 64-column tiles at full occupancy); FP16 storage walks two rows
-// uncapped (+14 % / +11 % over one row).  (256^3.)
+// on D3Q19 and +14 % on D3Q27 over 64-column tiles at full occupancy); FP16 storage in its one-row
+// instantiation capped at 5 waves (+3 %).  (256^3.)
 // A context of several instances keeps 64-column tiles in row bands, which the batched kernel prefers
 // (a 256-column tile of a small lattice leaves waves idle).
 Launch default_launch(const lbm_params &p, int mode, int n_inst, int lds_per_cu)
@@ -102,8 +102,7 @@ Launch default_launch(const lbm_params &p, int mode, int n_inst, int lds_per_cu)
     const bool f32 = mode == MODE_F32_F32, f16 = mode == MODE_F16S_F32;
     const int bands = ((p.nx + 255) / 256) % 8 == 0 ? 2 : 1;
     if (p.lattice != LBM_LATTICE_D2Q9) {
-        lc.max_waves = f32 ? 4 : 0;
-        if (f16) lc.rows = 2;
+        lc.max_waves = f32 ? 4 : (f16 ? 5 : 0);
     } else if (p.boundary != LBM_BC_PERIODIC) {
         if (f32) {
             lc.rows = 2;

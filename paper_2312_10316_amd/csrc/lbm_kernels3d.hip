@@ -173,9 +173,10 @@ __device__ __forceinline__ void pull_node3(const typename St::T *__restrict__ sr
     }
 }
 
-// Unlike the D2Q9 kernel this one keeps the walking loop for the one-row default: a compile-time
-// one-row instantiation frees VGPRs but measured 2-8 % slower at 256^3 and 384^3.
-template <int Q, int MODE, int AUX, bool HAS_K, bool HAS_S>
+// ROWS > 0 fixes the walk length at compile time, 0 takes it from the launch shape.  Only FP16
+// storage uses the one-row instantiation: at 256^3 it is +19 % (D3Q19) and +24 % (D3Q27) over the
+// walking loop, while FP32 and FP64 are 1-2 % faster with the loop.
+template <int Q, int MODE, int AUX, bool HAS_K, bool HAS_S, int ROWS>
 __global__ __launch_bounds__(256) void step3_kernel(const StepArgs sa)
 {
     using St = typename ModeTraits<MODE>::St;
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(256) void step3_kernel(const StepArgs sa)
     const int nx = a.L.nx, ny = a.L.ny, nz = a.L.nz;
     const int R = ny * nz;
     const int64_t pitch = a.L.pitch;
-    const int rows = a.lc.rows;
+    const int rows = ROWS > 0 ? ROWS : a.lc.rows;
     int x0, r0;
     tile_origin(a.L, a.lc, t, wave, x0, r0);
     if (r0 >= R || x0 >= nx) return;
@@ -385,18 +386,27 @@ __global__ __launch_bounds__(256) void populations3_kernel(const PopArgs a)
     }
 }
 
-template <int Q, int MODE, int AUX>
-hipError_t launch_step3_aux(const StepArgs &a, hipStream_t st)
+template <int Q, int MODE, int AUX, int ROWS>
+hipError_t launch_step3_rows(const StepArgs &a, hipStream_t st)
 {
     dim3 block(64, 4);
     const int nblocks = tiles_of(a.d.L, a.d.lc.rows, a.d.lc.wide);
     const size_t lds = (size_t)a.d.lc.lds_reserve;  // unused LDS that caps the resident waves
     const bool hk = a.d.has_k, hs = a.d.has_s;
-    if (hk && hs) step3_kernel<Q, MODE, AUX, true, true><<<nblocks, block, lds, st>>>(a);
-    else if (hk) step3_kernel<Q, MODE, AUX, true, false><<<nblocks, block, lds, st>>>(a);
-    else if (hs) step3_kernel<Q, MODE, AUX, false, true><<<nblocks, block, lds, st>>>(a);
-    else step3_kernel<Q, MODE, AUX, false, false><<<nblocks, block, lds, st>>>(a);
+    if (hk && hs) step3_kernel<Q, MODE, AUX, true, true, ROWS><<<nblocks, block, lds, st>>>(a);
+    else if (hk) step3_kernel<Q, MODE, AUX, true, false, ROWS><<<nblocks, block, lds, st>>>(a);
+    else if (hs) step3_kernel<Q, MODE, AUX, false, true, ROWS><<<nblocks, block, lds, st>>>(a);
+    else step3_kernel<Q, MODE, AUX, false, false, ROWS><<<nblocks, block, lds, st>>>(a);
     return hipGetLastError();
+}
+
+template <int Q, int MODE, int AUX>
+hipError_t launch_step3_aux(const StepArgs &a, hipStream_t st)
+{
+    if constexpr (MODE == MODE_F16S_F32) {
+        if (a.d.lc.rows == 1) return launch_step3_rows<Q, MODE, AUX, 1>(a, st);
+    }
+    return launch_step3_rows<Q, MODE, AUX, 0>(a, st);
 }
 
 template <int Q, int MODE>
