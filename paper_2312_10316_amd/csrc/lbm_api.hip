@@ -85,12 +85,12 @@ int lds_reserve_for(int max_waves, int lds_per_cu)
 // order only helps when every XCD keeps to its own columns, i.e. a multiple of 8 tiles per row; at
 // 2049^2 it costs 8 %); at most 5 waves per SIMD for FP32 storage and 4 for FP64 storage (+1-5 %),
 // FP16 uncapped (a cap costs it 4-20 %).  2048^2 FP32: 80k MLUPS against 74k for 64-column tiles
-// in row bands at full occupancy.
+// in row bands at full occupancy.  FP64 storage on a lattice whose rows do not hold a multiple of 8
+// wide tiles takes 64-column tiles in hardware order instead (2049^2: +4 %).
 // Flux form: two rows per wave on 256-column tiles, FP32 in row bands with 4 waves (+16 % over 8 rows
 // of 64-column tiles), FP64 ordered as above and uncapped.
-// Dirichlet edges and walls (the walking-loop kernels): FP32 two rows on 256-column tiles in row
-// bands; FP64 one row on 64-column tiles in hardware order (2049^2: +17 % and +4 % over the
-// periodic defaults).
+// Dirichlet edges and walls: FP32 and FP16 storage on 256-column tiles in row bands (FP32 capped at 5
+// waves), FP64 on 64-column tiles in hardware order (2049^2: FP32 72-74k, FP64 37k MLUPS).
 // D3Q19 and D3Q27: 256-column tiles in hardware order; one row per wave, FP32 capped at 4 waves (+17 %
 // on D3Q19 and +14 % on D3Q27 over 64-column tiles at full occupancy); FP16 storage in its one-row
 // instantiation capped at 5 waves (+3 %).  (256^3.)
@@ -104,9 +104,9 @@ Launch default_launch(const lbm_params &p, int mode, int n_inst, int lds_per_cu)
     if (p.lattice != LBM_LATTICE_D2Q9) {
         lc.max_waves = f32 ? 4 : (f16 ? 5 : 0);
     } else if (p.boundary != LBM_BC_PERIODIC) {
-        if (f32) {
-            lc.rows = 2;
+        if (f32 || f16) {
             lc.xcd_remap = 1;
+            lc.max_waves = f32 ? 5 : 0;
         } else {
             lc.wide = 0;
         }
@@ -117,6 +117,10 @@ Launch default_launch(const lbm_params &p, int mode, int n_inst, int lds_per_cu)
     } else {
         lc.xcd_remap = bands;
         lc.max_waves = f16 ? 0 : (f32 ? 5 : 4);
+        if (!f16 && !f32 && bands != 2) {  // FP64 storage on ragged rows
+            lc.wide = 0;
+            lc.xcd_remap = 0;
+        }
     }
     if (n_inst > 1 && p.lattice == LBM_LATTICE_D2Q9) {
         lc.rows = 1;

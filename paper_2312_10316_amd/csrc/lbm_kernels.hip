@@ -88,15 +88,20 @@ __device__ __forceinline__ void wall_replace(const typename St::T *__restrict__ 
     using C = Codec<St, M>;
     M e[9];
     equilibrium<M>(phiw, ux, uy, e);
-    if (bottom) {
-        g[2] = (e[2] + e[4]) - C::dec(ld_at(row + 4 * pitch, boff), 4, f);
-        g[5] = (e[5] + e[7]) - C::dec(ld_at(row + 7 * pitch, boff), 7, f);
-        g[6] = (e[6] + e[8]) - C::dec(ld_at(row + 8 * pitch, boff), 8, f);
-    } else {
-        g[4] = (e[4] + e[2]) - C::dec(ld_at(row + 2 * pitch, boff), 2, f);
-        g[7] = (e[7] + e[5]) - C::dec(ld_at(row + 5 * pitch, boff), 5, f);
-        g[8] = (e[8] + e[6]) - C::dec(ld_at(row + 6 * pitch, boff), 6, f);
-    }
+    // every slot is written through a select (no slot-dependent branches), which keeps g in registers
+    const int o2 = bottom ? 4 : 2, o5 = bottom ? 7 : 5, o6 = bottom ? 8 : 6;  // stored slot reflected
+    const M p2 = C::dec(ld_at(row + o2 * pitch, boff), o2, f);
+    const M p5 = C::dec(ld_at(row + o5 * pitch, boff), o5, f);
+    const M p6 = C::dec(ld_at(row + o6 * pitch, boff), o6, f);
+    const M a = (bottom ? e[2] + e[4] : e[4] + e[2]) - p2;
+    const M b = (bottom ? e[5] + e[7] : e[7] + e[5]) - p5;
+    const M c = (bottom ? e[6] + e[8] : e[8] + e[6]) - p6;
+    g[2] = bottom ? a : g[2];
+    g[5] = bottom ? b : g[5];
+    g[6] = bottom ? c : g[6];
+    g[4] = bottom ? g[4] : a;
+    g[7] = bottom ? g[7] : b;
+    g[8] = bottom ? g[8] : c;
 }
 
 // The state of node (x, y) as the step sees it before collision: the pull, then the boundary rule.
@@ -600,14 +605,14 @@ hipError_t launch_step_rows(const StepArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-// The periodic TRT-R local/no-aux kernels have a one-row instantiation for the default shape: with
-// no loop left, every load keeps the scalar-base + 32-bit-offset form (the walking loop's strength-
-// reduced 64-bit vector addresses cost ~160 instructions and ~28 VGPRs per wave).  Every other shape
-// walks the launch's row count.
+// The local/no-aux kernels (periodic, Dirichlet edges, walls; TRT-R and MRT-R) have a one-row
+// instantiation for the default shape: with no loop left, every load keeps the scalar-base +
+// 32-bit-offset form (the walking loop's strength-reduced 64-bit vector addresses cost ~160
+// instructions and ~28 VGPRs per wave).  Every other shape walks the launch's row count.
 template <int MODE, int AUX, int BC, bool MRT>
 hipError_t launch_step_var(const StepArgs &a, hipStream_t st)
 {
-    if constexpr (AUX != 1 && BC == 0 && !MRT) {
+    if constexpr (AUX != 1) {
         if (a.d.lc.rows == 1) return launch_step_rows<MODE, AUX, BC, MRT, 1>(a, st);
     }
     return launch_step_rows<MODE, AUX, BC, MRT, 0>(a, st);

@@ -450,7 +450,8 @@ def test_launch_defaults_and_bad_launch_shapes():
     cfg = W.PulseConfig(N=64, steps=0)
     f = W.rotating_pulse(cfg)
     fields = {k: dev(f[k]) for k in ("phi0", "ux", "uy")}
-    want = {"f32": (1, 1, 256, 5), "f64": (1, 1, 256, 4), "f16s": (1, 1, 256, 0)}  # 1 tile per row: row bands
+    # 1 wide tile per row: row bands; FP64 storage on such ragged rows: 64-column tiles in hardware order
+    want = {"f32": (1, 1, 256, 5), "f64": (1, 0, 64, 4), "f16s": (1, 1, 256, 0)}
     for mode, (rows, remap, width, cap) in want.items():
         s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, mode), fields)])
         assert s.get_launch() == {"rows": rows, "xcd_remap": remap, "tile_width": width, "max_waves": cap}
@@ -459,7 +460,7 @@ def test_launch_defaults_and_bad_launch_shapes():
     s = Solver([(lbm.make_params(2048, 3, f["dx"], f["dt"], cfg.lam, cfg.D, "f32"), wide_row)])
     assert s.get_launch()["xcd_remap"] == 2  # 8 tiles per row: column bands
     s.close()
-    for mode, want_nee in (("f32", (2, 1, 256, 0)), ("f64", (1, 0, 64, 0))):
+    for mode, want_nee in (("f32", (1, 1, 256, 5)), ("f64", (1, 0, 64, 0))):
         s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, mode, boundary=lbm.LBM_BC_NEE),
                      fields)])
         got = s.get_launch()
