@@ -132,9 +132,9 @@ def run_batched(torch, W, lbm, Solver, n_inst=256, steps=2000, eager_steps=100):
     t = autotune.tune(s, steps=64, reps=2)
     ms = timed(lambda: s.step(steps), steps)
     out["batched"] = {"ms_per_step": ms, "mlups": nodes / (ms * 1e-3) / 1e6,
-                      "config": {"rows": t["best"][0], "xcd_remap": t["best"][1], "tile_width": t["best"][2],
-                                 "max_waves": t["best"][3],
-                                 "policy": ["serial", "flat", "strided", "lpt"][t["best"][4]], "blocks": t["best"][5]}}
+                      "config": {"rows": t["best"][0], "xcd_remap": t["best"][1], "xcd_rows": t["best"][2],
+                                 "tile_width": t["best"][3], "max_waves": t["best"][4],
+                                 "policy": ["serial", "flat", "strided", "lpt"][t["best"][5]], "blocks": t["best"][6]}}
     out["speedup_vs_serial_graph"] = out["serial_graph"]["ms_per_step"] / ms
     out["speedup_vs_serial_eager"] = out["serial_eager"]["ms_per_step"] / ms
     out["nonfinite_instances"] = sum(1 for k in range(n_inst) if s.macros(k, raise_nonfinite=False)["nonfinite"] > 0)

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 5
+#define LBM_ABI_VERSION 6
 
 enum lbm_status {
     LBM_OK = 0,
@@ -212,9 +212,13 @@ typedef struct lbm_launch {
     int32_t xcd_remap;   /* tile order over the 8 XCDs (each has its own L2): 0 hardware order (tiles of a row
                             interleave over the XCDs); 1 row bands (XCD j takes one contiguous range of
                             tiles); 2 column bands (XCD j takes 1/8 of the tile columns, row by row;
-                            as 0 when the tiles per row are not a multiple of 8) */
+                            as 0 when the tiles per row are not a multiple of 8); 3 row blocks (the tile
+                            rows are cut into blocks of xcd_rows tile rows and XCD j takes blocks j,
+                            j + 8, j + 16, ...; the last blocks, where fewer than 8 remain, go in
+                            hardware order) */
     int32_t tile_width;  /* 64 or 256 */
     int32_t max_waves;   /* 0 or 3..8 */
+    int32_t xcd_rows;    /* tile rows per block of order 3 (1..64); 0 with the other orders */
 } lbm_launch;
 
 /* Sets (inst = -1: every instance) or reads the launch shape; captured step graphs are dropped.

@@ -78,35 +78,48 @@ int lds_reserve_for(int max_waves, int lds_per_cu)
     return ((lo + hi) / 2) & ~511;
 }
 
-// Default launch shape, from sweeps on MI355X over 2048^2..8192^2, 2049^2 and 256^3 (the autotuner
-// in the Python package can override it per instance).
+// Default launch shape, from sweeps on MI355X over 1024^2..8192^2 (2049^2, 3000^2 and 6000^2 among
+// them) and 256^3 (the autotuner in the Python package can override it per instance).
+// ntx = 256-column tiles per row.
 // D2Q9, periodic, local or no aux: one row per wave (the one-row kernels have no walking loop) on
-// 256-column tiles; XCD column bands when a row holds a multiple of 8 tiles, else row bands (hardware
-// order only helps when every XCD keeps to its own columns, i.e. a multiple of 8 tiles per row; at
-// 2049^2 it costs 8 %); at most 5 waves per SIMD for FP32 storage and 4 for FP64 storage (+1-5 %),
-// FP16 uncapped (a cap costs it 4-20 %).  2048^2 FP32: 80k MLUPS against 74k for 64-column tiles
-// in row bands at full occupancy.  FP64 storage on a lattice whose rows do not hold a multiple of 8
-// wide tiles takes 64-column tiles in hardware order instead (2049^2: +4 %).
+// 256-column tiles, at most 5 waves per SIMD for FP32 storage (6 with a D(x) field) and 4 for FP64
+// storage (+1-5 %), FP16 uncapped (a cap costs it 4-20 %).  With ntx >= 4 the XCDs take row blocks
+// (order 3): FP32 h = 64 / ntx tile rows, FP64 storage h = 32 / ntx (both clamped to 2..8), FP16
+// h = 32 / ntx clamped to 2..4, except at ntx = 8 and 16, where column bands are as fast for FP16.
+// Against column bands (ntx a multiple of 8) or row bands: FP32 +2-9 %, FP64 +1-5 %, FP16 +2-6 %
+// (2048^2 FP32: 82k MLUPS).  Narrower lattices: row bands, FP64 storage on 64-column tiles in
+// hardware order.
 // Flux form: two rows per wave on 256-column tiles, FP32 in row bands with 4 waves (+16 % over 8 rows
-// of 64-column tiles), FP64 ordered as above and uncapped.
-// Dirichlet edges and walls: FP32 and FP16 storage on 256-column tiles in row bands (FP32 capped at 5
-// waves), FP64 on 64-column tiles in hardware order (2049^2: FP32 72-74k, FP64 37k MLUPS).
+// of 64-column tiles), FP64 in column bands (ntx a multiple of 8) or row bands, uncapped (row blocks
+// measured slower).
+// Dirichlet edges and walls with ntx >= 8: FP32 on 256-column tiles in row blocks of 4 tile rows capped
+// at 5 waves (2049^2 NEE: 76k against 72k MLUPS in row bands), FP64 the same with h = 2, uncapped;
+// FP16 in row bands, uncapped.  Narrower lattices: FP32 and FP16 in row bands, FP64 on 64-column tiles
+// in hardware order.
 // D3Q19 and D3Q27: 256-column tiles in hardware order; one row per wave, FP32 capped at 4 waves (+17 %
 // on D3Q19 and +14 % on D3Q27 over 64-column tiles at full occupancy); FP16 storage in its one-row
-// instantiation capped at 5 waves (+3 %).  (256^3.)
+// instantiation capped at 5 waves (+3 %).  (256^3; row blocks measured level or slower.)
 // A context of several instances keeps 64-column tiles in row bands, which the batched kernel prefers
 // (a 256-column tile of a small lattice leaves waves idle).
-Launch default_launch(const lbm_params &p, int mode, int n_inst, int lds_per_cu)
+Launch default_launch(const lbm_params &p, int mode, bool has_D, int n_inst, int lds_per_cu)
 {
     Launch lc{1, 0, 1, 0, 0, 0};
     const bool f32 = mode == MODE_F32_F32, f16 = mode == MODE_F16S_F32;
-    const int bands = ((p.nx + 255) / 256) % 8 == 0 ? 2 : 1;
+    const int ntx = (p.nx + 255) / 256;
+    const int bands = ntx % 8 == 0 ? 2 : 1;
+    const auto row_blocks = [&lc](int h) {
+        lc.xcd_remap = 3;
+        lc.xcd_rows = h;
+    };
     if (p.lattice != LBM_LATTICE_D2Q9) {
         lc.max_waves = f32 ? 4 : (f16 ? 5 : 0);
     } else if (p.boundary != LBM_BC_PERIODIC) {
         if (f32 || f16) {
             lc.xcd_remap = 1;
             lc.max_waves = f32 ? 5 : 0;
+            if (f32 && ntx >= 8) row_blocks(4);
+        } else if (ntx >= 8) {
+            row_blocks(2);
         } else {
             lc.wide = 0;
         }
@@ -115,9 +128,14 @@ Launch default_launch(const lbm_params &p, int mode, int n_inst, int lds_per_cu)
         lc.xcd_remap = f32 ? 1 : bands;
         lc.max_waves = f32 ? 4 : 0;
     } else {
-        lc.xcd_remap = bands;
-        lc.max_waves = f16 ? 0 : (f32 ? 5 : 4);
-        if (!f16 && !f32 && bands != 2) {  // FP64 storage on ragged rows
+        lc.xcd_remap = 1;
+        lc.max_waves = f16 ? 0 : (f32 ? (has_D ? 6 : 5) : 4);
+        if (ntx >= 4) {
+            if (f32) row_blocks(std::clamp(64 / ntx, 2, 8));
+            else if (!f16) row_blocks(std::clamp(32 / ntx, 2, 8));
+            else if (ntx == 8 || ntx == 16) lc.xcd_remap = 2;
+            else row_blocks(std::clamp(32 / ntx, 2, 4));
+        } else if (!f16 && !f32) {  // FP64 storage on narrow lattices
             lc.wide = 0;
             lc.xcd_remap = 0;
         }
@@ -126,6 +144,7 @@ Launch default_launch(const lbm_params &p, int mode, int n_inst, int lds_per_cu)
         lc.rows = 1;
         lc.wide = 0;
         lc.xcd_remap = 1;
+        lc.xcd_rows = 0;
     }
     lc.lds_reserve = lds_reserve_for(lc.max_waves, lds_per_cu);
     return lc;
@@ -565,7 +584,7 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
         in.p = p[k];
         in.mode = mode_of(p[k]);
         in.L = layout_of(p[k]);
-        in.lc = default_launch(in.p, in.mode, n_inst, c->lds_per_cu);
+        in.lc = default_launch(in.p, in.mode, f[k].D != nullptr, n_inst, c->lds_per_cu);
         const size_t pb = pops_bytes(p[k]), vb = vel_bytes(p[k]), fb = field_bytes(p[k]);
         in.buf[0] = w;
         in.buf[1] = w + pb;
@@ -801,13 +820,15 @@ int lbm_set_launch(lbm_ctx *c, int32_t inst, const lbm_launch *cfg)
         return fail(LBM_E_STATE, "lbm_set_launch: bad context or instance %d", inst);
     if (!cfg) return fail(LBM_E_ARG, "lbm_set_launch: cfg is NULL");
     if (cfg->rows < 1 || cfg->rows > 64) return fail(LBM_E_ARG, "lbm_set_launch: rows=%d outside 1..64", cfg->rows);
-    if (cfg->xcd_remap < 0 || cfg->xcd_remap > 2) return fail(LBM_E_ARG, "lbm_set_launch: xcd_remap must be 0, 1 or 2");
+    if (cfg->xcd_remap < 0 || cfg->xcd_remap > 3) return fail(LBM_E_ARG, "lbm_set_launch: xcd_remap must be 0..3");
+    if (cfg->xcd_remap == 3 && (cfg->xcd_rows < 1 || cfg->xcd_rows > 64))
+        return fail(LBM_E_ARG, "lbm_set_launch: xcd_rows=%d outside 1..64 (xcd_remap 3)", cfg->xcd_rows);
     if (cfg->tile_width != 64 && cfg->tile_width != 256)
         return fail(LBM_E_ARG, "lbm_set_launch: tile_width=%d must be 64 or 256", cfg->tile_width);
     if (cfg->max_waves != 0 && (cfg->max_waves < 3 || cfg->max_waves > 8))
         return fail(LBM_E_ARG, "lbm_set_launch: max_waves=%d must be 0 or 3..8", cfg->max_waves);
     const Launch lc{cfg->rows, cfg->xcd_remap, cfg->tile_width == 256 ? 1 : 0, cfg->max_waves,
-                    lds_reserve_for(cfg->max_waves, c->lds_per_cu), 0};
+                    lds_reserve_for(cfg->max_waves, c->lds_per_cu), cfg->xcd_remap == 3 ? cfg->xcd_rows : 0};
     for (int k = 0; k < (int)c->inst.size(); ++k)
         if (inst == -1 || inst == k) c->inst[k].lc = lc;
     return refresh_tables(c);
@@ -823,6 +844,7 @@ int lbm_get_launch(lbm_ctx *c, int32_t inst, lbm_launch *cfg)
     cfg->xcd_remap = lc.xcd_remap;
     cfg->tile_width = lc.wide ? 256 : 64;
     cfg->max_waves = lc.max_waves;
+    cfg->xcd_rows = lc.xcd_rows;
     return LBM_OK;
 }
 

@@ -48,11 +48,11 @@ __host__ __device__ __forceinline__ int64_t fld_elems(const Layout &L) { return 
 // wide tiles put them side by side (256 columns x rows rows).
 struct Launch {
     int32_t rows;         // 1..64
-    int32_t xcd_remap;    // tile order over the XCDs: 0 hardware, 1 row bands, 2 column bands
+    int32_t xcd_remap;    // tile order over the XCDs: 0 hardware, 1 row bands, 2 column bands, 3 row blocks
     int32_t wide;         // 1: 256-column tiles; 0: 64-column tiles
     int32_t max_waves;    // cap on resident waves per SIMD (0: none)
     int32_t lds_reserve;  // dynamic LDS bytes reserved per block to enforce max_waves (0: none)
-    int32_t pad_;
+    int32_t xcd_rows;     // tile rows per block of order 3
 };
 
 // Everything a step kernel needs about one instance.  Single-instance launches pass it by value;

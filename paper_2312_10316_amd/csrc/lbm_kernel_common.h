@@ -51,9 +51,21 @@ __device__ __forceinline__ void st_nt_at(T *base, unsigned byte_off, T v)
 //   remap 1: XCD j takes one contiguous range of tiles (a band of whole tile rows);
 //   remap 2: XCD j takes one band of ntx/8 tile columns and walks it row by row, so the 8 XCDs
 //            sweep the same rows together while each shares tile edges with at most two others
-//            (needs ntx % 8 == 0; otherwise it is remap 0).
-__device__ __forceinline__ int tile_of_block(int b, int nb, int remap, int ntx)
+//            (needs ntx % 8 == 0; otherwise it is remap 0);
+//   remap 3: XCD j takes row blocks j, j + 8, ... of h tile rows each, so the XCDs sweep a window
+//            of about 8h tile rows together and every strip edge of a row stays in one L2.
+__device__ __forceinline__ int tile_of_block(int b, int nb, int remap, int ntx, int h)
 {
+    if (remap == 3) {
+        // Blocks of hb tiles (h tile rows) dealt round-robin to the XCDs.  The first `full` blocks
+        // (a multiple of 8 blocks) are permuted among themselves; the rest keep their tile.
+        const int hb = max(h, 1) * ntx, full = nb - nb % (8 * hb);
+        if (b < full) {
+            const int i = b >> 3;
+            return ((i / hb) * 8 + (b & 7)) * hb + i % hb;
+        }
+        return b;
+    }
     if (remap == 1) {
         const int q = nb >> 3, r = nb & 7, j = b & 7;
         return j * q + min(j, r) + (b >> 3);

@@ -403,7 +403,7 @@ template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC, bool MRT, int ROWS>
 __global__ __launch_bounds__(256) void step_kernel(const StepArgs a)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
-    const int t = tile_of_block(blockIdx.x, gridDim.x, a.d.lc.xcd_remap, tiles_per_row(a.d.L, a.d.lc));
+    const int t = tile_of_block(blockIdx.x, gridDim.x, a.d.lc.xcd_remap, tiles_per_row(a.d.L, a.d.lc), a.d.lc.xcd_rows);
     run_tile<MODE, AUX, HAS_K, HAS_S, BC, MRT, ROWS>(a.d, a.parity, t, wave);
 }
 
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(256) void batched_step_kernel(const BatchArgs a)
         beg = a.block_start[blockIdx.x];
         end = a.block_start[blockIdx.x + 1];
     } else {
-        beg = tile_of_block(blockIdx.x, gridDim.x, 1, 0);
+        beg = tile_of_block(blockIdx.x, gridDim.x, 1, 0, 0);
         end = beg + 1;
     }
     for (int it = beg; it < end; ++it) {

@@ -185,7 +185,7 @@ __global__ __launch_bounds__(256) void step3_kernel(const StepArgs sa)
     using C = Codec<St, M>;
     const InstDesc &a = sa.d;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
-    const int t = tile_of_block(blockIdx.x, gridDim.x, a.lc.xcd_remap, tiles_per_row(a.L, a.lc));
+    const int t = tile_of_block(blockIdx.x, gridDim.x, a.lc.xcd_remap, tiles_per_row(a.L, a.lc), a.lc.xcd_rows);
     const int nx = a.L.nx, ny = a.L.ny, nz = a.L.nz;
     const int R = ny * nz;
     const int64_t pitch = a.L.pitch;

@@ -32,20 +32,22 @@ def test_library_exports_every_declared_symbol():
     out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True, check=True).stdout
     exported = set(re.findall(r" T (lbm_\w+)$", out, flags=re.M))
     assert set(declared_functions()) <= exported
-    assert L.lbm_abi_version() == 5
+    assert L.lbm_abi_version() == 6
 
 
 def test_struct_layout_matches_header(tmp_path):
     prog = tmp_path / "layout.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lbm.h"\n'
-                    'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(lbm_params), '
+                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lbm_params), '
                     'offsetof(lbm_params, phi_ref), offsetof(lbm_params, store), sizeof(lbm_fields), '
-                    'sizeof(lbm_stats), offsetof(lbm_stats, nonfinite)); return 0;}\n')
+                    'sizeof(lbm_stats), offsetof(lbm_stats, nonfinite), sizeof(lbm_launch), '
+                    'offsetof(lbm_launch, xcd_rows), sizeof(lbm_batch)); return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c11", f"-I{os.path.dirname(HEADER)}", str(prog), "-o", str(exe)], check=True)
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     assert vals == [ctypes.sizeof(L.lbm_params), L.lbm_params.phi_ref.offset, L.lbm_params.store.offset,
-                    ctypes.sizeof(L.lbm_fields), ctypes.sizeof(L.lbm_stats), L.lbm_stats.nonfinite.offset]
+                    ctypes.sizeof(L.lbm_fields), ctypes.sizeof(L.lbm_stats), L.lbm_stats.nonfinite.offset,
+                    ctypes.sizeof(L.lbm_launch), L.lbm_launch.xcd_rows.offset, ctypes.sizeof(L.lbm_batch)]
 
 
 def _p(**kw):

@@ -170,12 +170,14 @@ def test_3d_full_size_256_windows(mode, q):
 @pytest.mark.parametrize("mode", ["f64", "f32", "f16s"])
 def test_3d_launch_shape_does_not_change_results(q, mode):
     """Rows per wave, tile width, tile order and the wave cap are tuning knobs only: bitwise equal
-    states on a ragged lattice (70 columns: a 256-column tile holds two live waves)."""
+    states on a ragged lattice (70 columns: a 256-column tile holds two live waves; 7 x 5 rows, so
+    row blocks of 2 wide tile rows leave 3 tiles in hardware order)."""
     f = case3(70, 7, 5, 47)
     states = []
-    for rows, remap, width, cap in ((1, 0, 64, 0), (1, 0, 256, 5), (3, 1, 256, 0), (2, 1, 64, 6), (64, 0, 256, 8)):
+    for rows, remap, width, cap, h in ((1, 0, 64, 0, 0), (1, 0, 256, 5, 0), (3, 1, 256, 0, 0), (2, 1, 64, 6, 0),
+                                       (64, 0, 256, 8, 0), (1, 3, 256, 4, 2), (1, 3, 64, 0, 1)):
         s, _ = solver3(f, mode, q=q)
-        s.set_launch(rows, remap, tile_width=width, max_waves=cap)
+        s.set_launch(rows, remap, tile_width=width, max_waves=cap, xcd_rows=h)
         s.step(9)
         states.append(s.state_save())
         s.close()

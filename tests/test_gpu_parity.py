@@ -234,7 +234,9 @@ def test_longest_row_windows(mode):
     dx, dt, lam, D = 1.0 / nx, 0.5 / nx, 0.25, 1.0 / (6.0 * nx)
     p = lbm.make_params(nx, ny, dx, dt, lam, D, mode, phi_ref=1.0)
     s = Solver([(p, {"phi0": dev(phi0), "ux": dev(ux), "uy": dev(uy)})])
-    assert s.get_launch()["xcd_remap"] == 2
+    d = s.get_launch()
+    assert (d["xcd_remap"], d["xcd_rows"]) == (3, 2)  # row blocks (3 tile rows: all in hardware order)
+    s.set_launch(1, 2, tile_width=256, max_waves=d["max_waves"])
     s.step(3)
     g0 = s.populations()
     s.step(1)
@@ -450,30 +452,48 @@ def test_launch_defaults_and_bad_launch_shapes():
     cfg = W.PulseConfig(N=64, steps=0)
     f = W.rotating_pulse(cfg)
     fields = {k: dev(f[k]) for k in ("phi0", "ux", "uy")}
+    def launch(rows, remap, width, cap, h=0):
+        return {"rows": rows, "xcd_remap": remap, "tile_width": width, "max_waves": cap, "xcd_rows": h}
+
     # 1 wide tile per row: row bands; FP64 storage on such ragged rows: 64-column tiles in hardware order
-    want = {"f32": (1, 1, 256, 5), "f64": (1, 0, 64, 4), "f16s": (1, 1, 256, 0)}
-    for mode, (rows, remap, width, cap) in want.items():
+    want = {"f32": launch(1, 1, 256, 5), "f64": launch(1, 0, 64, 4), "f16s": launch(1, 1, 256, 0)}
+    for mode, w in want.items():
         s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, mode), fields)])
-        assert s.get_launch() == {"rows": rows, "xcd_remap": remap, "tile_width": width, "max_waves": cap}
+        assert s.get_launch() == w, mode
         s.close()
-    wide_row = {k: dev(np.ascontiguousarray(np.tile(f[k][:3], (1, 32)))) for k in ("phi0", "ux", "uy")}
-    s = Solver([(lbm.make_params(2048, 3, f["dx"], f["dt"], cfg.lam, cfg.D, "f32"), wide_row)])
-    assert s.get_launch()["xcd_remap"] == 2  # 8 tiles per row: column bands
-    s.close()
-    for mode, want_nee in (("f32", (1, 1, 256, 5)), ("f64", (1, 0, 64, 0))):
-        s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, mode, boundary=lbm.LBM_BC_NEE),
-                     fields)])
-        got = s.get_launch()
-        assert (got["rows"], got["xcd_remap"], got["tile_width"], got["max_waves"]) == want_nee, mode
+    # 4 or more wide tiles per row: row blocks (FP32 about 64 tiles each, FP64 about 32; FP16 keeps
+    # column bands at 8 and 16 tiles per row); FP32 with a D(x) field runs 6 waves per SIMD
+    for nx, mode, var, w in ((2048, "f32", False, launch(1, 3, 256, 5, 8)), (2048, "f64", False, launch(1, 3, 256, 4, 4)),
+                             (2048, "f16s", False, launch(1, 2, 256, 0)), (2049, "f32", False, launch(1, 3, 256, 5, 7)),
+                             (2049, "f16s", False, launch(1, 3, 256, 0, 3)), (8192, "f32", False, launch(1, 3, 256, 5, 2)),
+                             (1024, "f64", False, launch(1, 3, 256, 4, 8)), (1024, "f16s", False, launch(1, 3, 256, 0, 4)),
+                             (768, "f64", False, launch(1, 0, 64, 4)), (4096, "f32", True, launch(1, 3, 256, 6, 4))):
+        keys = ("phi0", "ux", "uy", "D") if var else ("phi0", "ux", "uy")
+        src = dict(f, D=np.full_like(f["phi0"], cfg.D))
+        wide_row = {k: dev(np.ascontiguousarray(np.resize(src[k][:3], (3, nx)))) for k in keys}
+        s = Solver([(lbm.make_params(nx, 3, f["dx"], f["dt"], cfg.lam, cfg.D, mode), wide_row)])
+        assert s.get_launch() == w, (nx, mode, var)
+        s.close()
+    for nx, mode, w in ((64, "f32", launch(1, 1, 256, 5)), (64, "f64", launch(1, 0, 64, 0)),
+                        (2048, "f32", launch(1, 3, 256, 5, 4)), (2048, "f64", launch(1, 3, 256, 0, 2))):
+        fl = {k: dev(np.ascontiguousarray(np.resize(f[k], (64, nx)))) for k in ("phi0", "ux", "uy")}
+        s = Solver([(lbm.make_params(nx, 64, f["dx"], f["dt"], cfg.lam, cfg.D, mode, boundary=lbm.LBM_BC_NEE),
+                     fl)])
+        assert s.get_launch() == w, (nx, mode)
         s.close()
     s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, "f32", lbm.LBM_AUX_FLUX), fields)])
-    assert s.get_launch() == {"rows": 2, "xcd_remap": 1, "tile_width": 256, "max_waves": 4}
+    assert s.get_launch() == launch(2, 1, 256, 4)
     s.close()
     two = [(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, "f32"), fields)] * 2
     s = Solver(two)  # several instances: the batched kernel's 64-column tiles
-    assert s.get_launch(1) == {"rows": 1, "xcd_remap": 1, "tile_width": 64, "max_waves": 5}
+    assert s.get_launch(1) == launch(1, 1, 64, 5)
+    s.set_launch(1, 3, tile_width=256, xcd_rows=4)
+    assert s.get_launch(0) == launch(1, 3, 256, 0, 4)
+    s.set_launch(1, 2, tile_width=256, xcd_rows=4)  # xcd_rows only counts with order 3
+    assert s.get_launch(1) == launch(1, 2, 256, 0)
     for remap, kw in ((1, dict(tile_width=128)), (1, dict(tile_width=0)), (1, dict(max_waves=2)),
-                      (1, dict(max_waves=9)), (1, dict(max_waves=-1)), (3, {}), (-1, {})):
+                      (1, dict(max_waves=9)), (1, dict(max_waves=-1)), (3, {}), (3, dict(xcd_rows=65)),
+                      (3, dict(xcd_rows=-2)), (4, {}), (-1, {})):
         with pytest.raises(lbm.LbmError) as ei:
             s.set_launch(1, remap, **kw)
         assert ei.value.status == lbm.LBM_E_ARG, (remap, kw)
@@ -482,17 +502,20 @@ def test_launch_defaults_and_bad_launch_shapes():
 
 @pytest.mark.parametrize("mode", ["f32", "f16s", "f64"])
 def test_xcd_tile_orders_do_not_change_results(mode):
-    """The three block-to-tile orders (hardware, row bands, column bands) on a lattice whose tile
-    rows hold 8 tiles (256-column tiles) or 32 (64-column tiles), so that column bands apply, with
-    ragged last tiles in x and y: bitwise equal states."""
+    """The four block-to-tile orders (hardware, row bands, column bands, row blocks) on a lattice whose
+    tile rows hold 8 tiles (256-column tiles) or 32 (64-column tiles), so that column bands apply, with
+    ragged last tiles in x and y and row blocks that leave a remainder in hardware order: bitwise
+    equal states."""
     nx, ny = 2000, 37
     X, Y, dx = W.mesh(nx, ny, -1.0, 1.0)
     p = lbm.make_params(nx, ny, dx, dx / 10, 0.25, 1e-3, mode)
     fields = {"phi0": dev(np.exp(-((X - 0.3) ** 2 + Y ** 2) / 0.02)), "ux": dev(-np.pi * Y), "uy": dev(np.pi * X)}
     states = []
-    for remap, width, rows in ((0, 256, 1), (1, 256, 1), (2, 256, 1), (2, 64, 1), (2, 64, 3), (2, 256, 2)):
+    for remap, width, rows, h in ((0, 256, 1, 0), (1, 256, 1, 0), (2, 256, 1, 0), (2, 64, 1, 0), (2, 64, 3, 0),
+                                  (2, 256, 2, 0), (3, 256, 1, 2), (3, 256, 1, 1), (3, 64, 1, 1), (3, 256, 2, 1),
+                                  (3, 256, 1, 64)):
         s = Solver([(p, fields)])
-        s.set_launch(rows, remap, tile_width=width)
+        s.set_launch(rows, remap, tile_width=width, xcd_rows=h)
         s.step(25)
         states.append(s.state_save())
         s.close()
@@ -508,11 +531,12 @@ def test_launch_shape_does_not_change_results(mode, aux):
     p = lbm.make_params(cfg.N, cfg.N - 37, f["dx"], f["dt"], cfg.lam, cfg.D, mode, aux)
     fields = {k: dev(np.ascontiguousarray(f[k][:cfg.N - 37])) for k in ("phi0", "ux", "uy", "D")}
     states = []
-    for rows, remap, width, cap in ((1, 0, 64, 0), (4, 1, 64, 6), (7, 1, 256, 0), (64, 0, 64, 0), (1, 1, 256, 5),
-                                    (3, 0, 256, 8)):
+    for rows, remap, width, cap, h in ((1, 0, 64, 0, 0), (4, 1, 64, 6, 0), (7, 1, 256, 0, 0), (64, 0, 64, 0, 0),
+                                       (1, 1, 256, 5, 0), (3, 0, 256, 8, 0), (1, 3, 256, 5, 2), (2, 3, 64, 4, 3)):
         s = Solver([(p, fields)])
-        s.set_launch(rows, remap, tile_width=width, max_waves=cap)
-        assert s.get_launch() == {"rows": rows, "xcd_remap": remap, "tile_width": width, "max_waves": cap}
+        s.set_launch(rows, remap, tile_width=width, max_waves=cap, xcd_rows=h)
+        assert s.get_launch() == {"rows": rows, "xcd_remap": remap, "tile_width": width, "max_waves": cap,
+                                  "xcd_rows": h}
         s.step(70)
         states.append(s.state_save())
         s.close()
