@@ -218,11 +218,13 @@ typedef struct lbm_launch {
                             hardware order) */
     int32_t tile_width;  /* 64 or 256 */
     int32_t max_waves;   /* 0 or 3..8 */
-    int32_t xcd_rows;    /* tile rows per block of order 3 (1..64); 0 with the other orders */
+    int32_t xcd_rows;    /* tile rows per block of order 3 (1..64); ignored with the other orders, where
+                            lbm_get_launch reports 0 */
 } lbm_launch;
 
 /* Sets (inst = -1: every instance) or reads the launch shape; captured step graphs are dropped.
- * lbm_set_launch synchronizes the stream. */
+ * lbm_set_launch synchronizes the stream.  LBM_E_ARG for a field outside its range (xcd_rows only
+ * with xcd_remap 3), LBM_E_STATE for a bad context or instance. */
 int lbm_set_launch(lbm_ctx *ctx, int32_t inst, const lbm_launch *cfg);
 int lbm_get_launch(lbm_ctx *ctx, int32_t inst, lbm_launch *cfg);
 
