@@ -37,7 +37,7 @@ def bytes_per_lup(mode: str, variable_D: bool) -> int:
 
 def kernel_hash() -> str:
     h = hashlib.sha256()
-    for name in ("lbm_kernels.hip", "lbm_device.h", "lbm_internal.h", "lbm_api.hip"):
+    for name in ("lbm_kernels.hip", "lbm_kernel_common.h", "lbm_device.h", "lbm_internal.h", "lbm_api.hip"):
         with open(os.path.join(ROOT, "paper_2312_10316_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
