@@ -133,8 +133,8 @@ def run_batched(torch, W, lbm, Solver, n_inst=256, steps=2000, eager_steps=100):
     ms = timed(lambda: s.step(steps), steps)
     out["batched"] = {"ms_per_step": ms, "mlups": nodes / (ms * 1e-3) / 1e6,
                       "config": {"rows": t["best"][0], "xcd_remap": t["best"][1], "xcd_rows": t["best"][2],
-                                 "tile_width": t["best"][3], "max_waves": t["best"][4],
-                                 "policy": ["serial", "flat", "strided", "lpt"][t["best"][5]], "blocks": t["best"][6]}}
+                                 "tile_width": t["best"][3], "max_waves": t["best"][4], "stores": t["best"][5],
+                                 "policy": ["serial", "flat", "strided", "lpt"][t["best"][6]], "blocks": t["best"][7]}}
     out["speedup_vs_serial_graph"] = out["serial_graph"]["ms_per_step"] / ms
     out["speedup_vs_serial_eager"] = out["serial_eager"]["ms_per_step"] / ms
     out["nonfinite_instances"] = sum(1 for k in range(n_inst) if s.macros(k, raise_nonfinite=False)["nonfinite"] > 0)
@@ -507,10 +507,11 @@ def summarize_profiles3(trace_dir, pmc_dirs, out_dir, n, command, pmc_commands):
 
 
 def _kernel_label(name: str):
-    """'step_kernel<2, 0, false, false, 0, false, 1>' (mode, aux, has_k, has_s, boundary, MRT-R, walk) ->
-    ('step', 'f32', aux 0, has_k, has_s) for the periodic TRT-R kernels; copy -> ('copy',); other -> None."""
+    """'step_kernel<2, 0, false, false, 0, false, 1, false>' (mode, aux, has_k, has_s, boundary, MRT-R, walk,
+    cached stores) -> ('step', 'f32', aux 0, has_k, has_s) for the periodic TRT-R kernels, either store
+    kind; copy -> ('copy',); other -> None."""
     import re
-    m = re.search(r"step_kernel<(\d), (\d), (true|false), (true|false), 0, false, \d>", name)
+    m = re.search(r"step_kernel<(\d), (\d), (true|false), (true|false), 0, false, \d(?:, (?:true|false))?>", name)
     if m:
         return ("step", KERNEL_MODES[m.group(1)], int(m.group(2)), m.group(3) == "true", m.group(4) == "true")
     if "copy_kernel" in name:

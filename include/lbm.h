@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 6
+#define LBM_ABI_VERSION 7
 
 enum lbm_status {
     LBM_OK = 0,
@@ -220,6 +220,13 @@ typedef struct lbm_launch {
     int32_t max_waves;   /* 0 or 3..8 */
     int32_t xcd_rows;    /* tile rows per block of order 3 (1..64); ignored with the other orders, where
                             lbm_get_launch reports 0 */
+    int32_t stores;      /* how the new state is written: 0 non-temporal (streamed to HBM); 1 cached (left
+                            in L2 and the 256 MiB Infinity Cache, where the next step reads it back).
+                            Honoured by one-row launches (rows = 1) of D2Q9 instances with the local or
+                            no auxiliary term, one instance per launch; other launches (flux form,
+                            rows > 1, D3Q19/D3Q27, the batched policies) store non-temporally.
+                            Default: 1 for such instances when both population buffers and the
+                            per-node fields of every instance of the context fit in 256 MiB, else 0 */
 } lbm_launch;
 
 /* Sets (inst = -1: every instance) or reads the launch shape; captured step graphs are dropped.

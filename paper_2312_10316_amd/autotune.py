@@ -1,5 +1,5 @@
 """Autotuner for the step launch: tile shape (rows walked per wave, XCD tile order and its row-block
-height, 64- or 256-column tiles), a cap on the waves resident per SIMD, and, for a multi-instance context, the
+height, 64- or 256-column tiles), non-temporal or cached stores of the new state, a cap on the waves resident per SIMD, and, for a multi-instance context, the
 batch schedule (serial launches, one flat launch, or persistent blocks with a round-robin or
 longest-processing-time assignment of tiles).
 
@@ -26,13 +26,15 @@ def _key(solver) -> str:
     dev = torch.cuda.get_device_name()
     shapes = [(p.nx, p.ny, p.nz, p.lattice, p.store, p.math, p.aux, p.boundary, p.tau3 not in (0.0, 1.0))
               for p in solver.params]
-    return hashlib.sha256(json.dumps(["launch-v3", dev, shapes]).encode()).hexdigest()[:20]
+    return hashlib.sha256(json.dumps(["launch-v4", dev, shapes]).encode()).hexdigest()[:20]
 
 
 def default_candidates(solver) -> list:
-    """(rows, xcd_remap, xcd_rows, tile_width, max_waves, policy, blocks) tuples worth timing for this
-    context."""
+    """(rows, xcd_remap, xcd_rows, tile_width, max_waves, stores, policy, blocks) tuples worth timing for
+    this context.  Stores: both kinds for one instance in one-row launches (the only ones that honour
+    cached stores); a batch keeps the context's default."""
     out = []
+    st0 = solver.get_launch(0)["stores"]
     multi = len(solver.params) > 1 and len({(p.store, p.math, p.aux) for p in solver.params}) == 1
     if not multi:
         for width, rows_set in ((64, (1, 2, 4)), (256, (1, 2))):
@@ -40,24 +42,25 @@ def default_candidates(solver) -> list:
                 orders = [(0, 0), (1, 0)] + ([(3, h) for h in (2, 4, 8)] if width == 256 else [])
                 for remap, h in orders:
                     for cap in (0, 4, 5):
-                        out.append((rows, remap, h, width, cap, L.LBM_BATCH_SERIAL, 0))
+                        for stores in ((st0, 1 - st0) if rows == 1 else (0,)):
+                            out.append((rows, remap, h, width, cap, stores, L.LBM_BATCH_SERIAL, 0))
         return out
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
     for width in (64, 256):
         for rows in (1, 2, 4):
-            out.append((rows, 1, 0, width, 0, L.LBM_BATCH_SERIAL, 0))
+            out.append((rows, 1, 0, width, 0, st0, L.LBM_BATCH_SERIAL, 0))
             for cap in (0, 6):
-                out.append((rows, 1, 0, width, cap, L.LBM_BATCH_FLAT, 0))
-                out.append((rows, 1, 0, width, cap, L.LBM_BATCH_LPT, 4 * ncu))
+                out.append((rows, 1, 0, width, cap, st0, L.LBM_BATCH_FLAT, 0))
+                out.append((rows, 1, 0, width, cap, st0, L.LBM_BATCH_LPT, 4 * ncu))
             for mult in (2, 8):
-                out.append((rows, 1, 0, width, 0, L.LBM_BATCH_LPT, mult * ncu))
-            out.append((rows, 1, 0, width, 0, L.LBM_BATCH_STRIDED, 4 * ncu))
+                out.append((rows, 1, 0, width, 0, st0, L.LBM_BATCH_LPT, mult * ncu))
+            out.append((rows, 1, 0, width, 0, st0, L.LBM_BATCH_STRIDED, 4 * ncu))
     return out
 
 
 def _apply(solver, cand) -> None:
-    rows, remap, h, width, cap, policy, blocks = cand
-    solver.set_launch(rows, remap, tile_width=width, max_waves=cap, xcd_rows=h)
+    rows, remap, h, width, cap, stores, policy, blocks = cand
+    solver.set_launch(rows, remap, tile_width=width, max_waves=cap, xcd_rows=h, stores=stores)
     if len(solver.params) > 1:
         try:
             solver.set_batch(policy, blocks, cap)  # the cap applies to the batched launch as well
@@ -84,7 +87,7 @@ def _time(solver, steps: int, reps: int) -> float:
 def tune(solver, candidates: Optional[Iterable] = None, steps: int = 64, reps: int = 2,
          cache_path: Optional[str] = None, force: bool = False) -> dict:
     """Times every candidate, applies the fastest and returns
-    {"best": (rows, xcd_remap, xcd_rows, tile_width, max_waves, policy, blocks), "ms_per_step": {...},
+    {"best": (rows, xcd_remap, xcd_rows, tile_width, max_waves, stores, policy, blocks), "ms_per_step": {...},
     "cached": bool}."""
     key = _key(solver)
     cached = None
@@ -111,7 +114,7 @@ def tune(solver, candidates: Optional[Iterable] = None, steps: int = 64, reps: i
         for k in range(n):
             o = old_launch[k]
             solver.set_launch(o["rows"], o["xcd_remap"], inst=k, tile_width=o["tile_width"], max_waves=o["max_waves"],
-                              xcd_rows=o["xcd_rows"])
+                              xcd_rows=o["xcd_rows"], stores=o["stores"])
         if old_batch is not None:
             solver.set_batch(old_batch["policy"], old_batch["blocks"], old_batch["max_waves"])
         for k in range(n):

@@ -34,6 +34,7 @@ int fail(int code, const char *fmt, ...)
 int hip_fail(hipError_t e, const char *what) { return fail(LBM_E_HIP, "%s: %s", what, hipGetErrorString(e)); }
 
 constexpr size_t kAlign = 256;
+constexpr size_t kInfinityCacheBytes = (size_t)256 << 20;  // MI355X's memory-side cache in front of HBM
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 int mode_of(const lbm_params &p)
@@ -607,6 +608,18 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
             (in.p.tau3 != 0.0 && in.p.tau3 != 1.0) || in.p.lattice != LBM_LATTICE_D2Q9)
             c->uniform = false;  // batched launches cover periodic D2Q9 TRT-R instances of one storage/aux form
     }
+    // Cached stores (honoured by the one-row D2Q9 local/no-aux launches) when what the steps touch
+    // (both population buffers and the per-node fields of every instance) fits in the 256 MiB Infinity
+    // Cache: the next step then reads the new state back from it (1024^2-1792^2: FP32 +7-11 %, FP64
+    // +10-14 %; FP16 up to 2304^2: +2-9 %).  Beyond that, the old buffer, the new one and the fields
+    // cycle through the cache and every line is evicted before its next use (-2 to -9 %), so the new
+    // state streams to HBM.
+    size_t touched = 0;
+    for (const Instance &in : c->inst)
+        touched += 2 * pops_bytes(in.p) + vel_bytes(in.p) + (in.has_D ? field_bytes(in.p) : 0);
+    for (Instance &in : c->inst)
+        in.lc.stores = touched <= kInfinityCacheBytes && in.p.lattice == LBM_LATTICE_D2Q9 &&
+                       in.p.aux != LBM_AUX_FLUX && in.lc.rows == 1;
     const size_t items = max_items_of(n_inst, p);
     c->d_desc = reinterpret_cast<InstDesc *>(w);
     w += align_up((size_t)n_inst * sizeof(InstDesc), kAlign);
@@ -823,12 +836,14 @@ int lbm_set_launch(lbm_ctx *c, int32_t inst, const lbm_launch *cfg)
     if (cfg->xcd_remap < 0 || cfg->xcd_remap > 3) return fail(LBM_E_ARG, "lbm_set_launch: xcd_remap must be 0..3");
     if (cfg->xcd_remap == 3 && (cfg->xcd_rows < 1 || cfg->xcd_rows > 64))
         return fail(LBM_E_ARG, "lbm_set_launch: xcd_rows=%d outside 1..64 (xcd_remap 3)", cfg->xcd_rows);
+    if (cfg->stores != 0 && cfg->stores != 1) return fail(LBM_E_ARG, "lbm_set_launch: stores=%d must be 0 or 1", cfg->stores);
     if (cfg->tile_width != 64 && cfg->tile_width != 256)
         return fail(LBM_E_ARG, "lbm_set_launch: tile_width=%d must be 64 or 256", cfg->tile_width);
     if (cfg->max_waves != 0 && (cfg->max_waves < 3 || cfg->max_waves > 8))
         return fail(LBM_E_ARG, "lbm_set_launch: max_waves=%d must be 0 or 3..8", cfg->max_waves);
     const Launch lc{cfg->rows, cfg->xcd_remap, cfg->tile_width == 256 ? 1 : 0, cfg->max_waves,
-                    lds_reserve_for(cfg->max_waves, c->lds_per_cu), cfg->xcd_remap == 3 ? cfg->xcd_rows : 0};
+                    lds_reserve_for(cfg->max_waves, c->lds_per_cu), cfg->xcd_remap == 3 ? cfg->xcd_rows : 0,
+                    cfg->stores, 0};
     for (int k = 0; k < (int)c->inst.size(); ++k)
         if (inst == -1 || inst == k) c->inst[k].lc = lc;
     return refresh_tables(c);
@@ -845,6 +860,7 @@ int lbm_get_launch(lbm_ctx *c, int32_t inst, lbm_launch *cfg)
     cfg->tile_width = lc.wide ? 256 : 64;
     cfg->max_waves = lc.max_waves;
     cfg->xcd_rows = lc.xcd_rows;
+    cfg->stores = lc.stores;
     return LBM_OK;
 }
 

@@ -53,6 +53,8 @@ struct Launch {
     int32_t max_waves;    // cap on resident waves per SIMD (0: none)
     int32_t lds_reserve;  // dynamic LDS bytes reserved per block to enforce max_waves (0: none)
     int32_t xcd_rows;     // tile rows per block of order 3
+    int32_t stores;       // 0: non-temporal stores of the new state; 1: cached stores
+    int32_t pad_;
 };
 
 // Everything a step kernel needs about one instance.  Single-instance launches pass it by value;

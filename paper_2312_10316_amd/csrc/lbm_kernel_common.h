@@ -39,10 +39,17 @@ __device__ __forceinline__ T ld_at(const T *base, unsigned byte_off)
 {
     return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
 }
+// Stores of the new state: non-temporal ones stream it to HBM; cached ones leave it in L2 and the
+// Infinity Cache, where the next step finds it when the step's working set fits there.
 template <class T>
 __device__ __forceinline__ void st_nt_at(T *base, unsigned byte_off, T v)
 {
     __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off));
+}
+template <class T>
+__device__ __forceinline__ void st_at(T *base, unsigned byte_off, T v)
+{
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
 }
 
 // Block b -> tile t (tiles numbered row-major, ntx per row).  The hardware hands block b to XCD

@@ -146,7 +146,7 @@ __device__ __forceinline__ double lane_read<double>(double v, int k)
 // scalar registers and each load or store needs only a 32-bit lane offset (x, x-1 or x+1).
 // ROWS > 0 fixes the walk length at compile time (the common one-row launch then has no loop, and
 // every access keeps the scalar-base + 32-bit-offset form); 0 takes it from the launch shape.
-template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC = 0, bool MRT = false, int ROWS = 0>
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC = 0, bool MRT = false, int ROWS = 0, bool CST = false>
 __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int t, int wave)
 {
     using St = typename ModeTraits<MODE>::St;
@@ -243,7 +243,10 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
             T *__restrict__ out = dst + (int64_t)y * 9 * pitch;
             const unsigned pb = (unsigned)(pitch * (int64_t)sizeof(T));
 #pragma unroll
-            for (int i = 0; i < 9; ++i) st_nt_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, a.f16));
+            for (int i = 0; i < 9; ++i) {
+                if constexpr (CST) st_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, a.f16));
+                else st_nt_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, a.f16));
+            }
         }
         ux_m = ux_c;
         uy_m = uy_c;
@@ -391,20 +394,20 @@ __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity,
 }
 
 // Dispatch of one tile to the aux-term form.
-template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC = 0, bool MRT = false, int ROWS = 0>
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC = 0, bool MRT = false, int ROWS = 0, bool CST = false>
 __device__ __forceinline__ void run_tile(const InstDesc &d, int parity, int t, int wave)
 {
     if constexpr (AUX == 1) process_tile_flux<MODE, HAS_K, HAS_S, MRT>(d, parity, t, wave);
-    else process_tile<MODE, AUX, HAS_K, HAS_S, BC, MRT, ROWS>(d, parity, t, wave);
+    else process_tile<MODE, AUX, HAS_K, HAS_S, BC, MRT, ROWS, CST>(d, parity, t, wave);
 }
 
 // Single instance: block b -> tile (XCD-remapped if requested).
-template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC, bool MRT, int ROWS>
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC, bool MRT, int ROWS, bool CST>
 __global__ __launch_bounds__(256) void step_kernel(const StepArgs a)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const int t = tile_of_block(blockIdx.x, gridDim.x, a.d.lc.xcd_remap, tiles_per_row(a.d.L, a.d.lc), a.d.lc.xcd_rows);
-    run_tile<MODE, AUX, HAS_K, HAS_S, BC, MRT, ROWS>(a.d, a.parity, t, wave);
+    run_tile<MODE, AUX, HAS_K, HAS_S, BC, MRT, ROWS, CST>(a.d, a.parity, t, wave);
 }
 
 // Many instances in one launch: each block runs a range of (instance, tile) work items; the
@@ -591,29 +594,34 @@ __global__ __launch_bounds__(256) void copy_kernel(const f32x4 *__restrict__ src
 }
 
 
-template <int MODE, int AUX, int BC, bool MRT, int ROWS>
+template <int MODE, int AUX, int BC, bool MRT, int ROWS, bool CST = false>
 hipError_t launch_step_rows(const StepArgs &a, hipStream_t st)
 {
     dim3 block(64, 4);
     const int nblocks = tiles_of(a.d.L, a.d.lc.rows, a.d.lc.wide);
     const size_t lds = (size_t)a.d.lc.lds_reserve;  // unused LDS that caps the resident waves
     const bool hk = a.d.has_k, hs = a.d.has_s;
-    if (hk && hs) step_kernel<MODE, AUX, true, true, BC, MRT, ROWS><<<nblocks, block, lds, st>>>(a);
-    else if (hk) step_kernel<MODE, AUX, true, false, BC, MRT, ROWS><<<nblocks, block, lds, st>>>(a);
-    else if (hs) step_kernel<MODE, AUX, false, true, BC, MRT, ROWS><<<nblocks, block, lds, st>>>(a);
-    else step_kernel<MODE, AUX, false, false, BC, MRT, ROWS><<<nblocks, block, lds, st>>>(a);
+    if (hk && hs) step_kernel<MODE, AUX, true, true, BC, MRT, ROWS, CST><<<nblocks, block, lds, st>>>(a);
+    else if (hk) step_kernel<MODE, AUX, true, false, BC, MRT, ROWS, CST><<<nblocks, block, lds, st>>>(a);
+    else if (hs) step_kernel<MODE, AUX, false, true, BC, MRT, ROWS, CST><<<nblocks, block, lds, st>>>(a);
+    else step_kernel<MODE, AUX, false, false, BC, MRT, ROWS, CST><<<nblocks, block, lds, st>>>(a);
     return hipGetLastError();
 }
 
 // The local/no-aux kernels (periodic, Dirichlet edges, walls; TRT-R and MRT-R) have a one-row
 // instantiation for the default shape: with no loop left, every load keeps the scalar-base +
 // 32-bit-offset form (the walking loop's strength-reduced 64-bit vector addresses cost ~160
-// instructions and ~28 VGPRs per wave).  Every other shape walks the launch's row count.
+// instructions and ~28 VGPRs per wave).  It comes with non-temporal or cached stores (Launch::stores;
+// a compile-time choice: a run-time branch between two store loops that differ only in the hint is
+// merged by the compiler, which drops the hint).  Every other shape walks the launch's row count and
+// stores non-temporally.
 template <int MODE, int AUX, int BC, bool MRT>
 hipError_t launch_step_var(const StepArgs &a, hipStream_t st)
 {
     if constexpr (AUX != 1) {
-        if (a.d.lc.rows == 1) return launch_step_rows<MODE, AUX, BC, MRT, 1>(a, st);
+        if (a.d.lc.rows == 1)
+            return a.d.lc.stores ? launch_step_rows<MODE, AUX, BC, MRT, 1, true>(a, st)
+                                 : launch_step_rows<MODE, AUX, BC, MRT, 1, false>(a, st);
     }
     return launch_step_rows<MODE, AUX, BC, MRT, 0>(a, st);
 }

@@ -63,7 +63,7 @@ class lbm_stats(ctypes.Structure):
 
 class lbm_launch(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int32), ("xcd_remap", ctypes.c_int32), ("tile_width", ctypes.c_int32),
-                ("max_waves", ctypes.c_int32), ("xcd_rows", ctypes.c_int32)]
+                ("max_waves", ctypes.c_int32), ("xcd_rows", ctypes.c_int32), ("stores", ctypes.c_int32)]
 
 
 class lbm_batch(ctypes.Structure):
@@ -240,8 +240,8 @@ def lbm_state_load(ctx, inst: int, src: torch.Tensor, step: int) -> None:
 
 
 def lbm_set_launch(ctx, inst: int, rows: int, xcd_remap: int = 1, tile_width: int = 64, max_waves: int = 0,
-                   xcd_rows: int = 0) -> None:
-    cfg = lbm_launch(int(rows), int(xcd_remap), int(tile_width), int(max_waves), int(xcd_rows))
+                   xcd_rows: int = 0, stores: int = 0) -> None:
+    cfg = lbm_launch(int(rows), int(xcd_remap), int(tile_width), int(max_waves), int(xcd_rows), int(stores))
     _check(lib().lbm_set_launch(ctx, int(inst), ctypes.byref(cfg)))
 
 
@@ -249,7 +249,7 @@ def lbm_get_launch(ctx, inst: int = 0) -> dict:
     cfg = lbm_launch()
     _check(lib().lbm_get_launch(ctx, int(inst), ctypes.byref(cfg)))
     return {"rows": cfg.rows, "xcd_remap": cfg.xcd_remap, "tile_width": cfg.tile_width, "max_waves": cfg.max_waves,
-            "xcd_rows": cfg.xcd_rows}
+            "xcd_rows": cfg.xcd_rows, "stores": cfg.stores}
 
 
 def lbm_set_batch(ctx, policy: int, blocks: int = 0, max_waves: int = 0) -> None:

@@ -11,17 +11,17 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
-STEP = "void lbm::(anonymous namespace)::step_kernel<{m}, 0, false, false, {bc}, {mrt}, {rows}>(lbm::StepArgs)"
+STEP = "void lbm::(anonymous namespace)::step_kernel<{m}, 0, false, false, {bc}, {mrt}, {rows}, {cst}>(lbm::StepArgs)"
 COPY = "lbm::(anonymous namespace)::copy_kernel(float __vector(4) const*, float __vector(4)*, long)"
 
 
 def test_kernel_label():
-    assert bench._kernel_label(STEP.format(m=2, bc=0, mrt="false", rows=1)) == ("step", "f32", 0, False, False)
-    assert bench._kernel_label(STEP.format(m=0, bc=0, mrt="false", rows=0))[1] == "f64"
-    assert bench._kernel_label(STEP.format(m=3, bc=0, mrt="false", rows=1))[1] == "f16s"
+    assert bench._kernel_label(STEP.format(m=2, bc=0, mrt="false", rows=1, cst="false")) == ("step", "f32", 0, False, False)
+    assert bench._kernel_label(STEP.format(m=0, bc=0, mrt="false", rows=0, cst="false"))[1] == "f64"
+    assert bench._kernel_label(STEP.format(m=3, bc=0, mrt="false", rows=1, cst="true"))[1] == "f16s"  # cached stores
     # boundary and MRT-R variants are not the periodic benchmark kernels
-    assert bench._kernel_label(STEP.format(m=2, bc=1, mrt="false", rows=0)) is None
-    assert bench._kernel_label(STEP.format(m=2, bc=0, mrt="true", rows=0)) is None
+    assert bench._kernel_label(STEP.format(m=2, bc=1, mrt="false", rows=0, cst="false")) is None
+    assert bench._kernel_label(STEP.format(m=2, bc=0, mrt="true", rows=0, cst="false")) is None
     assert bench._kernel_label(COPY) == ("copy",)
     assert bench._kernel_label("void lbm::(anonymous namespace)::macros_kernel<2>(lbm::MacroArgs)") is None
 
@@ -50,13 +50,13 @@ def test_summarize_scales_counters_by_the_copy_kernel(tmp_path):
     copy_kib = 2 * 1024 * 1024  # 2 GiB moved each way
     run = tmp_path / "run"
     _write_csv(str(run / "trace" / "t_kernel_stats.csv"), ["Name", "Calls", "TotalDurationNs", "AverageNs"],
-               [[STEP.format(m=2, bc=0, mrt="false", rows=1), 10, 570000, 57000], [COPY, 2, 1300000, 650000]])
+               [[STEP.format(m=2, bc=0, mrt="false", rows=1, cst="false"), 10, 570000, 57000], [COPY, 2, 1300000, 650000]])
     write_kib = 0.5 * alg / 1024                     # any split of alg into writes and reads ...
     fetch_kib = 0.5 * (alg - write_kib * 1024) / 1024  # ... with the reads seen at the copy's 0.5 scale
     for counter, step_val, copy_val in (("FETCH_SIZE", fetch_kib, 0.5 * copy_kib), ("WRITE_SIZE", write_kib, copy_kib)):
         _write_csv(str(run / f"pmc_{counter.lower()}_{n}" / "p_counter_collection.csv"),
                    ["Kernel_Name", "Counter_Name", "Counter_Value"],
-                   [[STEP.format(m=2, bc=0, mrt="false", rows=1), counter, step_val]] * 3 + [[COPY, counter, copy_val]])
+                   [[STEP.format(m=2, bc=0, mrt="false", rows=1, cst="false"), counter, step_val]] * 3 + [[COPY, counter, copy_val]])
     pmc = {(c, n): str(run / f"pmc_{c.lower()}_{n}") for c in ("FETCH_SIZE", "WRITE_SIZE")}
     out = tmp_path / "out"
     bench.summarize_profiles(str(run / "trace"), pmc, str(out), "cmd", ["c1", "c2"])

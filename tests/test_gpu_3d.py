@@ -174,10 +174,11 @@ def test_3d_launch_shape_does_not_change_results(q, mode):
     row blocks of 2 wide tile rows leave 3 tiles in hardware order)."""
     f = case3(70, 7, 5, 47)
     states = []
-    for rows, remap, width, cap, h in ((1, 0, 64, 0, 0), (1, 0, 256, 5, 0), (3, 1, 256, 0, 0), (2, 1, 64, 6, 0),
-                                       (64, 0, 256, 8, 0), (1, 3, 256, 4, 2), (1, 3, 64, 0, 1)):
+    for rows, remap, width, cap, h, st in ((1, 0, 64, 0, 0, 0), (1, 0, 256, 5, 0, 1), (3, 1, 256, 0, 0, 0),
+                                           (2, 1, 64, 6, 0, 1), (64, 0, 256, 8, 0, 0), (1, 3, 256, 4, 2, 1),
+                                           (1, 3, 64, 0, 1, 0)):
         s, _ = solver3(f, mode, q=q)
-        s.set_launch(rows, remap, tile_width=width, max_waves=cap, xcd_rows=h)
+        s.set_launch(rows, remap, tile_width=width, max_waves=cap, xcd_rows=h, stores=st)
         s.step(9)
         states.append(s.state_save())
         s.close()

@@ -31,19 +31,19 @@ def test_tuning_does_not_advance_and_results_do_not_depend_on_the_winner(multi, 
     s = Solver(inst)
     s.step(7)
     before = states(s)
-    cands = [(1, 1, 0, 64, 0, lbm.LBM_BATCH_SERIAL, 0), (2, 0, 0, 256, 5, lbm.LBM_BATCH_SERIAL, 0),
-             (1, 3, 2, 256, 5, lbm.LBM_BATCH_SERIAL, 0)]
+    cands = [(1, 1, 0, 64, 0, 0, lbm.LBM_BATCH_SERIAL, 0), (2, 0, 0, 256, 5, 1, lbm.LBM_BATCH_SERIAL, 0),
+             (1, 3, 2, 256, 5, 0, lbm.LBM_BATCH_SERIAL, 0)]
     if multi:
-        cands += [(1, 1, 0, 256, 0, lbm.LBM_BATCH_FLAT, 0), (1, 1, 0, 64, 0, lbm.LBM_BATCH_LPT, 512),
-                  (2, 1, 0, 256, 0, lbm.LBM_BATCH_STRIDED, 256), (1, 1, 0, 256, 0, lbm.LBM_BATCH_LPT, 512)]
+        cands += [(1, 1, 0, 256, 0, 1, lbm.LBM_BATCH_FLAT, 0), (1, 1, 0, 64, 0, 0, lbm.LBM_BATCH_LPT, 512),
+                  (2, 1, 0, 256, 0, 1, lbm.LBM_BATCH_STRIDED, 256), (1, 1, 0, 256, 0, 0, lbm.LBM_BATCH_LPT, 512)]
     cache = str(tmp_path / "tune.json")
     r = autotune.tune(s, cands, steps=16, reps=1, cache_path=cache, force=True)
     assert tuple(r["best"]) in [tuple(c) for c in cands] and not r["cached"]
     assert all(np.array_equal(a, b) for a, b in zip(before, states(s)))
     assert all(s.macros(k)["step"] == 7 for k in range(len(inst)))
-    rows, remap, h, width, cap, policy, blocks = r["best"]
+    rows, remap, h, width, cap, stores, policy, blocks = r["best"]
     assert s.get_launch(0) == {"rows": rows, "xcd_remap": remap, "tile_width": width, "max_waves": cap,
-                               "xcd_rows": h}
+                               "xcd_rows": h, "stores": stores}
     s.step(20)
     tuned = states(s)
     s.close()
@@ -63,8 +63,8 @@ def test_tuning_a_d3q19_instance():
     f = {"phi0": dev(1 + np.exp(-(X ** 2 + Y ** 2 + Z ** 2) / 0.1)), "ux": dev(-Y), "uy": dev(X), "uz": dev(0 * X)}
     s = Solver([(p, f)])
     before = states(s)
-    r = autotune.tune(s, [(1, 0, 0, 64, 0, 0, 0), (1, 1, 0, 256, 5, 0, 0), (2, 1, 0, 256, 0, 0, 0),
-                          (1, 3, 4, 256, 4, 0, 0)], steps=8, reps=1, force=True)
+    r = autotune.tune(s, [(1, 0, 0, 64, 0, 0, 0, 0), (1, 1, 0, 256, 5, 1, 0, 0), (2, 1, 0, 256, 0, 0, 0, 0),
+                          (1, 3, 4, 256, 4, 1, 0, 0)], steps=8, reps=1, force=True)
     assert all(np.array_equal(a, b) for a, b in zip(before, states(s)))
     assert s.get_launch(0)["rows"] == r["best"][0]
     s.close()

@@ -49,9 +49,9 @@ def run_nee_pair(nx, ny, f, steps, mode="f64", rows=None, lam=0.25):
     if f["D"] is not None:
         fields["D"] = dev(f["D"])
     s = Solver([(p, fields)])
-    if rows is not None:  # rows per wave, or (rows, xcd_remap, tile_width, xcd_rows)
-        r, remap, width, h = rows if isinstance(rows, tuple) else (rows, 1, 64, 0)
-        s.set_launch(r, remap, tile_width=width, xcd_rows=h)
+    if rows is not None:  # rows per wave, or (rows, xcd_remap, tile_width, xcd_rows, stores)
+        r, remap, width, h, st = rows if isinstance(rows, tuple) else (rows, 1, 64, 0, 0)
+        s.set_launch(r, remap, tile_width=width, xcd_rows=h, stores=st)
     op = O.Problem(nx, ny, f["dx"], f["dt"], lam, f["D_const"], O.AUX_LOCAL, O.BC_NEE)
     g = O.init(op, f["phi0"], f["ux"], f["uy"])
     for n in range(steps):
@@ -80,7 +80,7 @@ def test_nee_fp64_parity(shape):
     np.testing.assert_allclose(phi[edge], pb[edge], rtol=0, atol=1e-13)
 
 
-@pytest.mark.parametrize("rows", [1, 2, 4, (1, 3, 256, 1), (1, 3, 64, 2), (2, 3, 256, 4)])
+@pytest.mark.parametrize("rows", [1, 2, 4, (1, 3, 256, 1, 0), (1, 3, 64, 2, 1), (2, 3, 256, 4, 1)])
 def test_nee_launch_shape_does_not_change_results(rows):
     f = nee_case(97, 70, 3)
     a, _, _, _ = run_nee_pair(97, 70, f, 12, rows=1)

@@ -452,8 +452,11 @@ def test_launch_defaults_and_bad_launch_shapes():
     cfg = W.PulseConfig(N=64, steps=0)
     f = W.rotating_pulse(cfg)
     fields = {k: dev(f[k]) for k in ("phi0", "ux", "uy")}
-    def launch(rows, remap, width, cap, h=0):
-        return {"rows": rows, "xcd_remap": remap, "tile_width": width, "max_waves": cap, "xcd_rows": h}
+    def launch(rows, remap, width, cap, h=0, stores=1):
+        return {"rows": rows, "xcd_remap": remap, "tile_width": width, "max_waves": cap, "xcd_rows": h,
+                "stores": stores}
+
+    # every context below touches far less than 256 MiB per step: cached stores (one-row local kernels)
 
     # 1 wide tile per row: row bands; FP64 storage on such ragged rows: 64-column tiles in hardware order
     want = {"f32": launch(1, 1, 256, 5), "f64": launch(1, 0, 64, 4), "f16s": launch(1, 1, 256, 0)}
@@ -482,18 +485,24 @@ def test_launch_defaults_and_bad_launch_shapes():
         assert s.get_launch() == w, (nx, mode)
         s.close()
     s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, "f32", lbm.LBM_AUX_FLUX), fields)])
-    assert s.get_launch() == launch(2, 1, 256, 4)
+    assert s.get_launch() == launch(2, 1, 256, 4, stores=0)  # the flux form stores non-temporally
     s.close()
+    # 2048^2 FP32 touches 346 MB per step, more than the Infinity Cache holds: non-temporal stores
+    big = {k: dev(np.ascontiguousarray(np.resize(f[k], (2048, 2048)))) for k in ("phi0", "ux", "uy")}
+    s = Solver([(lbm.make_params(2048, 2048, f["dx"], f["dt"], cfg.lam, cfg.D, "f32"), big)])
+    assert s.get_launch() == launch(1, 3, 256, 5, 8, stores=0)
+    s.close()
+    del big
     two = [(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, "f32"), fields)] * 2
     s = Solver(two)  # several instances: the batched kernel's 64-column tiles
     assert s.get_launch(1) == launch(1, 1, 64, 5)
     s.set_launch(1, 3, tile_width=256, xcd_rows=4)
-    assert s.get_launch(0) == launch(1, 3, 256, 0, 4)
-    s.set_launch(1, 2, tile_width=256, xcd_rows=4)  # xcd_rows only counts with order 3
+    assert s.get_launch(0) == launch(1, 3, 256, 0, 4, stores=0)
+    s.set_launch(1, 2, tile_width=256, xcd_rows=4, stores=1)  # xcd_rows only counts with order 3
     assert s.get_launch(1) == launch(1, 2, 256, 0)
     for remap, kw in ((1, dict(tile_width=128)), (1, dict(tile_width=0)), (1, dict(max_waves=2)),
                       (1, dict(max_waves=9)), (1, dict(max_waves=-1)), (3, {}), (3, dict(xcd_rows=65)),
-                      (3, dict(xcd_rows=-2)), (4, {}), (-1, {})):
+                      (3, dict(xcd_rows=-2)), (4, {}), (-1, {}), (1, dict(stores=2)), (1, dict(stores=-1))):
         with pytest.raises(lbm.LbmError) as ei:
             s.set_launch(1, remap, **kw)
         assert ei.value.status == lbm.LBM_E_ARG, (remap, kw)
@@ -511,11 +520,11 @@ def test_xcd_tile_orders_do_not_change_results(mode):
     p = lbm.make_params(nx, ny, dx, dx / 10, 0.25, 1e-3, mode)
     fields = {"phi0": dev(np.exp(-((X - 0.3) ** 2 + Y ** 2) / 0.02)), "ux": dev(-np.pi * Y), "uy": dev(np.pi * X)}
     states = []
-    for remap, width, rows, h in ((0, 256, 1, 0), (1, 256, 1, 0), (2, 256, 1, 0), (2, 64, 1, 0), (2, 64, 3, 0),
-                                  (2, 256, 2, 0), (3, 256, 1, 2), (3, 256, 1, 1), (3, 64, 1, 1), (3, 256, 2, 1),
-                                  (3, 256, 1, 64)):
+    for remap, width, rows, h, stores in ((0, 256, 1, 0, 0), (1, 256, 1, 0, 1), (2, 256, 1, 0, 0), (2, 64, 1, 0, 1),
+                                          (2, 64, 3, 0, 0), (2, 256, 2, 0, 1), (3, 256, 1, 2, 0), (3, 256, 1, 1, 1),
+                                          (3, 64, 1, 1, 0), (3, 256, 2, 1, 1), (3, 256, 1, 64, 0)):
         s = Solver([(p, fields)])
-        s.set_launch(rows, remap, tile_width=width, xcd_rows=h)
+        s.set_launch(rows, remap, tile_width=width, xcd_rows=h, stores=stores)
         s.step(25)
         states.append(s.state_save())
         s.close()
@@ -531,12 +540,13 @@ def test_launch_shape_does_not_change_results(mode, aux):
     p = lbm.make_params(cfg.N, cfg.N - 37, f["dx"], f["dt"], cfg.lam, cfg.D, mode, aux)
     fields = {k: dev(np.ascontiguousarray(f[k][:cfg.N - 37])) for k in ("phi0", "ux", "uy", "D")}
     states = []
-    for rows, remap, width, cap, h in ((1, 0, 64, 0, 0), (4, 1, 64, 6, 0), (7, 1, 256, 0, 0), (64, 0, 64, 0, 0),
-                                       (1, 1, 256, 5, 0), (3, 0, 256, 8, 0), (1, 3, 256, 5, 2), (2, 3, 64, 4, 3)):
+    for rows, remap, width, cap, h, st in ((1, 0, 64, 0, 0, 0), (4, 1, 64, 6, 0, 1), (7, 1, 256, 0, 0, 0),
+                                           (64, 0, 64, 0, 0, 1), (1, 1, 256, 5, 0, 0), (3, 0, 256, 8, 0, 0),
+                                           (1, 3, 256, 5, 2, 1), (2, 3, 64, 4, 3, 0)):
         s = Solver([(p, fields)])
-        s.set_launch(rows, remap, tile_width=width, max_waves=cap, xcd_rows=h)
+        s.set_launch(rows, remap, tile_width=width, max_waves=cap, xcd_rows=h, stores=st)
         assert s.get_launch() == {"rows": rows, "xcd_remap": remap, "tile_width": width, "max_waves": cap,
-                                  "xcd_rows": h}
+                                  "xcd_rows": h, "stores": st}
         s.step(70)
         states.append(s.state_save())
         s.close()

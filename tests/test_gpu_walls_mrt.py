@@ -49,9 +49,9 @@ def run_wall_pair(nx, ny, f, steps, mode="f64", aux=lbm.LBM_AUX_LOCAL, tau3=0.0,
     values of the new time level."""
     p = lbm.make_params(nx, ny, f["dx"], f["dt"], lam, f["D_const"], mode, aux, boundary=lbm.LBM_BC_WALLS, tau3=tau3)
     s = Solver([(p, {k: dev(f[k]) for k in ("phi0", "ux", "uy", "D")})])
-    if rows is not None:  # rows per wave, or (rows, xcd_remap, tile_width, xcd_rows)
-        r, remap, width, h = rows if isinstance(rows, tuple) else (rows, 1, 64, 0)
-        s.set_launch(r, remap, tile_width=width, xcd_rows=h)
+    if rows is not None:  # rows per wave, or (rows, xcd_remap, tile_width, xcd_rows, stores)
+        r, remap, width, h, st = rows if isinstance(rows, tuple) else (rows, 1, 64, 0, 0)
+        s.set_launch(r, remap, tile_width=width, xcd_rows=h, stores=st)
     op = O.Problem(nx, ny, f["dx"], f["dt"], lam, f["D_const"], aux, O.BC_WALLS, tau3)
     g = O.init(op, f["phi0"], f["ux"], f["uy"])
     for n in range(steps):
@@ -86,7 +86,7 @@ def test_walls_initial_state_is_the_equilibrium():
     assert rel(g, O.init(op, f["phi0"], f["ux"], f["uy"])) <= 1e-15
 
 
-@pytest.mark.parametrize("rows", [2, 4, (1, 3, 256, 1), (1, 3, 64, 2)])
+@pytest.mark.parametrize("rows", [2, 4, (1, 3, 256, 1, 1), (1, 3, 64, 2, 0)])
 def test_walls_launch_shape_does_not_change_results(rows):
     f = wall_case(97, 70, 4)
     a, _, _ = run_wall_pair(97, 70, f, 10, rows=1)
