@@ -222,11 +222,11 @@ typedef struct lbm_launch {
                             lbm_get_launch reports 0 */
     int32_t stores;      /* how the new state is written: 0 non-temporal (streamed to HBM); 1 cached (left
                             in L2 and the 256 MiB Infinity Cache, where the next step reads it back).
-                            Honoured by one-row launches (rows = 1) of D2Q9 instances with the local or
-                            no auxiliary term, one instance per launch; other launches (flux form,
-                            rows > 1, D3Q19/D3Q27, the batched policies) store non-temporally.
-                            Default: 1 for such instances when both population buffers and the
-                            per-node fields of every instance of the context fit in 256 MiB, else 0 */
+                            Honoured by launches of one instance (the SERIAL policy) except the
+                            walking loop (rows > 1) of D2Q9 instances with the local or no auxiliary
+                            term; those and the batched policies store non-temporally.  Default: 1
+                            for honouring instances when both population buffers and the per-node
+                            fields of every instance of the context fit in 256 MiB, else 0 */
 } lbm_launch;
 
 /* Sets (inst = -1: every instance) or reads the launch shape; captured step graphs are dropped.

@@ -31,10 +31,11 @@ def _key(solver) -> str:
 
 def default_candidates(solver) -> list:
     """(rows, xcd_remap, xcd_rows, tile_width, max_waves, stores, policy, blocks) tuples worth timing for
-    this context.  Stores: both kinds for one instance in one-row launches (the only ones that honour
-    cached stores); a batch keeps the context's default."""
+    this context.  Stores: both kinds for one instance where they are honoured (not in the local
+    form's walking loop); a batch keeps the context's default."""
     out = []
     st0 = solver.get_launch(0)["stores"]
+    p0 = solver.params[0]
     multi = len(solver.params) > 1 and len({(p.store, p.math, p.aux) for p in solver.params}) == 1
     if not multi:
         for width, rows_set in ((64, (1, 2, 4)), (256, (1, 2))):
@@ -42,7 +43,8 @@ def default_candidates(solver) -> list:
                 orders = [(0, 0), (1, 0)] + ([(3, h) for h in (2, 4, 8)] if width == 256 else [])
                 for remap, h in orders:
                     for cap in (0, 4, 5):
-                        for stores in ((st0, 1 - st0) if rows == 1 else (0,)):
+                        honoured = rows == 1 or p0.aux == L.LBM_AUX_FLUX or p0.lattice != L.LBM_LATTICE_D2Q9
+                        for stores in ((st0, 1 - st0) if honoured else (0,)):
                             out.append((rows, remap, h, width, cap, stores, L.LBM_BATCH_SERIAL, 0))
         return out
     ncu = torch.cuda.get_device_properties(0).multi_processor_count

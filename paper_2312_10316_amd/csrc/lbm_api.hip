@@ -608,18 +608,20 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
             (in.p.tau3 != 0.0 && in.p.tau3 != 1.0) || in.p.lattice != LBM_LATTICE_D2Q9)
             c->uniform = false;  // batched launches cover periodic D2Q9 TRT-R instances of one storage/aux form
     }
-    // Cached stores (honoured by the one-row D2Q9 local/no-aux launches) when what the steps touch
-    // (both population buffers and the per-node fields of every instance) fits in the 256 MiB Infinity
-    // Cache: the next step then reads the new state back from it (1024^2-1792^2: FP32 +7-11 %, FP64
-    // +10-14 %; FP16 up to 2304^2: +2-9 %).  Beyond that, the old buffer, the new one and the fields
-    // cycle through the cache and every line is evicted before its next use (-2 to -9 %), so the new
-    // state streams to HBM.
+    // Cached stores (honoured by every one-instance launch but the local form's walking loop) when what
+    // the steps touch (both population buffers and the per-node fields of every instance, padding
+    // columns excluded) fits in the 256 MiB Infinity Cache: the next step then reads the new state back
+    // from it (1024^2-1792^2: FP32 +7-11 %, FP64 +10-14 %; FP16 up to 2304^2: +2-9 %; flux form
+    // +12-21 %; D3Q19/D3Q27 96^3-128^3 +8-23 %).  Beyond that, the old buffer, the new one and the
+    // fields cycle through the cache and every line is evicted before its next use (-2 to -9 %), so
+    // the new state streams to HBM.
     size_t touched = 0;
     for (const Instance &in : c->inst)
-        touched += 2 * pops_bytes(in.p) + vel_bytes(in.p) + (in.has_D ? field_bytes(in.p) : 0);
+        touched += (size_t)in.L.nx * rows_of(in.L) *
+                   (2 * in.L.q * store_bytes(in.mode) + (dim_of(in.L) + (in.has_D ? 1 : 0)) * math_bytes(in.mode));
     for (Instance &in : c->inst)
-        in.lc.stores = touched <= kInfinityCacheBytes && in.p.lattice == LBM_LATTICE_D2Q9 &&
-                       in.p.aux != LBM_AUX_FLUX && in.lc.rows == 1;
+        in.lc.stores = touched <= kInfinityCacheBytes &&
+                       (in.p.lattice != LBM_LATTICE_D2Q9 || in.p.aux == LBM_AUX_FLUX || in.lc.rows == 1);
     const size_t items = max_items_of(n_inst, p);
     c->d_desc = reinterpret_cast<InstDesc *>(w);
     w += align_up((size_t)n_inst * sizeof(InstDesc), kAlign);

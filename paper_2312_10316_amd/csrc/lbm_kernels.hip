@@ -263,7 +263,7 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
 // periodic seam) are pulled cooperatively: lanes 0-8 load the nine populations of the west node and
 // lanes 9-17 those of the east node in one gather, and their sums come back by lane reads, in the
 // same order as every other phi.
-template <int MODE, bool HAS_K, bool HAS_S, bool MRT = false>
+template <int MODE, bool HAS_K, bool HAS_S, bool MRT = false, bool CST = false>
 __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity, int t, int wave)
 {
     using St = typename ModeTraits<MODE>::St;
@@ -380,7 +380,10 @@ __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity,
             T *__restrict__ out = dst + (int64_t)y * 9 * pitch;
             const unsigned pb = (unsigned)(pitch * (int64_t)sizeof(T));
 #pragma unroll
-            for (int i = 0; i < 9; ++i) st_nt_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, a.f16));
+            for (int i = 0; i < 9; ++i) {
+                if constexpr (CST) st_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, a.f16));
+                else st_nt_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, a.f16));
+            }
         }
 #pragma unroll
         for (int i = 0; i < 9; ++i) g[i] = gn[i];
@@ -397,7 +400,7 @@ __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity,
 template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC = 0, bool MRT = false, int ROWS = 0, bool CST = false>
 __device__ __forceinline__ void run_tile(const InstDesc &d, int parity, int t, int wave)
 {
-    if constexpr (AUX == 1) process_tile_flux<MODE, HAS_K, HAS_S, MRT>(d, parity, t, wave);
+    if constexpr (AUX == 1) process_tile_flux<MODE, HAS_K, HAS_S, MRT, CST>(d, parity, t, wave);
     else process_tile<MODE, AUX, HAS_K, HAS_S, BC, MRT, ROWS, CST>(d, parity, t, wave);
 }
 
@@ -611,19 +614,22 @@ hipError_t launch_step_rows(const StepArgs &a, hipStream_t st)
 // The local/no-aux kernels (periodic, Dirichlet edges, walls; TRT-R and MRT-R) have a one-row
 // instantiation for the default shape: with no loop left, every load keeps the scalar-base +
 // 32-bit-offset form (the walking loop's strength-reduced 64-bit vector addresses cost ~160
-// instructions and ~28 VGPRs per wave).  It comes with non-temporal or cached stores (Launch::stores;
-// a compile-time choice: a run-time branch between two store loops that differ only in the hint is
-// merged by the compiler, which drops the hint).  Every other shape walks the launch's row count and
-// stores non-temporally.
+// instructions and ~28 VGPRs per wave); every other shape walks the launch's row count.  The one-row
+// kernels and the flux form come with non-temporal or cached stores (Launch::stores; a compile-time
+// choice: a run-time branch between two store loops that differ only in the hint is merged by the
+// compiler, which drops the hint); the walking loop of the local form stores non-temporally.
 template <int MODE, int AUX, int BC, bool MRT>
 hipError_t launch_step_var(const StepArgs &a, hipStream_t st)
 {
-    if constexpr (AUX != 1) {
+    if constexpr (AUX == 1) {
+        return a.d.lc.stores ? launch_step_rows<MODE, AUX, BC, MRT, 0, true>(a, st)
+                             : launch_step_rows<MODE, AUX, BC, MRT, 0, false>(a, st);
+    } else {
         if (a.d.lc.rows == 1)
             return a.d.lc.stores ? launch_step_rows<MODE, AUX, BC, MRT, 1, true>(a, st)
                                  : launch_step_rows<MODE, AUX, BC, MRT, 1, false>(a, st);
+        return launch_step_rows<MODE, AUX, BC, MRT, 0>(a, st);
     }
-    return launch_step_rows<MODE, AUX, BC, MRT, 0>(a, st);
 }
 
 // MRT-R (w3 != 0) is a separate instantiation so that the TRT-R kernels keep their registers.

@@ -176,7 +176,7 @@ __device__ __forceinline__ void pull_node3(const typename St::T *__restrict__ sr
 // ROWS > 0 fixes the walk length at compile time, 0 takes it from the launch shape.  Only FP16
 // storage uses the one-row instantiation: at 256^3 it is +19 % (D3Q19) and +24 % (D3Q27) over the
 // walking loop, while FP32 and FP64 are 1-2 % faster with the loop.
-template <int Q, int MODE, int AUX, bool HAS_K, bool HAS_S, int ROWS>
+template <int Q, int MODE, int AUX, bool HAS_K, bool HAS_S, int ROWS, bool CST>
 __global__ __launch_bounds__(256) void step3_kernel(const StepArgs sa)
 {
     using St = typename ModeTraits<MODE>::St;
@@ -281,7 +281,10 @@ __global__ __launch_bounds__(256) void step3_kernel(const StepArgs sa)
         if (live) {
             T *__restrict__ out = dst + (int64_t)r * Q * pitch;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) st_nt_at(out + i * pitch, bc, C::enc(P[i], i, f));
+            for (int i = 0; i < Q; ++i) {
+                if constexpr (CST) st_at(out + i * pitch, bc, C::enc(P[i], i, f));
+                else st_nt_at(out + i * pitch, bc, C::enc(P[i], i, f));
+            }
         }
     }
 }
@@ -386,27 +389,35 @@ __global__ __launch_bounds__(256) void populations3_kernel(const PopArgs a)
     }
 }
 
-template <int Q, int MODE, int AUX, int ROWS>
+template <int Q, int MODE, int AUX, int ROWS, bool CST>
 hipError_t launch_step3_rows(const StepArgs &a, hipStream_t st)
 {
     dim3 block(64, 4);
     const int nblocks = tiles_of(a.d.L, a.d.lc.rows, a.d.lc.wide);
     const size_t lds = (size_t)a.d.lc.lds_reserve;  // unused LDS that caps the resident waves
     const bool hk = a.d.has_k, hs = a.d.has_s;
-    if (hk && hs) step3_kernel<Q, MODE, AUX, true, true, ROWS><<<nblocks, block, lds, st>>>(a);
-    else if (hk) step3_kernel<Q, MODE, AUX, true, false, ROWS><<<nblocks, block, lds, st>>>(a);
-    else if (hs) step3_kernel<Q, MODE, AUX, false, true, ROWS><<<nblocks, block, lds, st>>>(a);
-    else step3_kernel<Q, MODE, AUX, false, false, ROWS><<<nblocks, block, lds, st>>>(a);
+    if (hk && hs) step3_kernel<Q, MODE, AUX, true, true, ROWS, CST><<<nblocks, block, lds, st>>>(a);
+    else if (hk) step3_kernel<Q, MODE, AUX, true, false, ROWS, CST><<<nblocks, block, lds, st>>>(a);
+    else if (hs) step3_kernel<Q, MODE, AUX, false, true, ROWS, CST><<<nblocks, block, lds, st>>>(a);
+    else step3_kernel<Q, MODE, AUX, false, false, ROWS, CST><<<nblocks, block, lds, st>>>(a);
     return hipGetLastError();
+}
+
+// Non-temporal or cached stores of the new state (Launch::stores), a compile-time choice.
+template <int Q, int MODE, int AUX, int ROWS>
+hipError_t launch_step3_st(const StepArgs &a, hipStream_t st)
+{
+    return a.d.lc.stores ? launch_step3_rows<Q, MODE, AUX, ROWS, true>(a, st)
+                         : launch_step3_rows<Q, MODE, AUX, ROWS, false>(a, st);
 }
 
 template <int Q, int MODE, int AUX>
 hipError_t launch_step3_aux(const StepArgs &a, hipStream_t st)
 {
     if constexpr (MODE == MODE_F16S_F32) {
-        if (a.d.lc.rows == 1) return launch_step3_rows<Q, MODE, AUX, 1>(a, st);
+        if (a.d.lc.rows == 1) return launch_step3_st<Q, MODE, AUX, 1>(a, st);
     }
-    return launch_step3_rows<Q, MODE, AUX, 0>(a, st);
+    return launch_step3_st<Q, MODE, AUX, 0>(a, st);
 }
 
 template <int Q, int MODE>

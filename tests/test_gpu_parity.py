@@ -456,7 +456,7 @@ def test_launch_defaults_and_bad_launch_shapes():
         return {"rows": rows, "xcd_remap": remap, "tile_width": width, "max_waves": cap, "xcd_rows": h,
                 "stores": stores}
 
-    # every context below touches far less than 256 MiB per step: cached stores (one-row local kernels)
+    # every context below touches far less than 256 MiB per step: cached stores
 
     # 1 wide tile per row: row bands; FP64 storage on such ragged rows: 64-column tiles in hardware order
     want = {"f32": launch(1, 1, 256, 5), "f64": launch(1, 0, 64, 4), "f16s": launch(1, 1, 256, 0)}
@@ -485,7 +485,7 @@ def test_launch_defaults_and_bad_launch_shapes():
         assert s.get_launch() == w, (nx, mode)
         s.close()
     s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, "f32", lbm.LBM_AUX_FLUX), fields)])
-    assert s.get_launch() == launch(2, 1, 256, 4, stores=0)  # the flux form stores non-temporally
+    assert s.get_launch() == launch(2, 1, 256, 4)
     s.close()
     # 2048^2 FP32 touches 346 MB per step, more than the Infinity Cache holds: non-temporal stores
     big = {k: dev(np.ascontiguousarray(np.resize(f[k], (2048, 2048)))) for k in ("phi0", "ux", "uy")}
