@@ -456,46 +456,45 @@ def test_launch_defaults_and_bad_launch_shapes():
         return {"rows": rows, "xcd_remap": remap, "tile_width": width, "max_waves": cap, "xcd_rows": h,
                 "stores": stores}
 
-    # every context below touches far less than 256 MiB per step: cached stores
-
-    # 1 wide tile per row: row bands; FP64 storage on such ragged rows: 64-column tiles in hardware order
-    want = {"f32": launch(1, 1, 256, 5), "f64": launch(1, 0, 64, 4), "f16s": launch(1, 1, 256, 0)}
-    for mode, w in want.items():
-        s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, mode), fields)])
-        assert s.get_launch() == w, mode
-        s.close()
-    # 4 or more wide tiles per row: row blocks (FP32 about 64 tiles each, FP64 about 32; FP16 keeps
-    # column bands at 8 and 16 tiles per row); FP32 with a D(x) field runs 6 waves per SIMD
-    for nx, mode, var, w in ((2048, "f32", False, launch(1, 3, 256, 5, 8)), (2048, "f64", False, launch(1, 3, 256, 4, 4)),
-                             (2048, "f16s", False, launch(1, 2, 256, 0)), (2049, "f32", False, launch(1, 3, 256, 5, 7)),
-                             (2049, "f16s", False, launch(1, 3, 256, 0, 3)), (8192, "f32", False, launch(1, 3, 256, 5, 2)),
-                             (1024, "f64", False, launch(1, 3, 256, 4, 8)), (1024, "f16s", False, launch(1, 3, 256, 0, 4)),
-                             (768, "f64", False, launch(1, 0, 64, 4)), (4096, "f32", True, launch(1, 3, 256, 6, 4))):
-        keys = ("phi0", "ux", "uy", "D") if var else ("phi0", "ux", "uy")
-        src = dict(f, D=np.full_like(f["phi0"], cfg.D))
-        wide_row = {k: dev(np.ascontiguousarray(np.resize(src[k][:3], (3, nx)))) for k in keys}
-        s = Solver([(lbm.make_params(nx, 3, f["dx"], f["dt"], cfg.lam, cfg.D, mode), wide_row)])
-        assert s.get_launch() == w, (nx, mode, var)
-        s.close()
-    for nx, mode, w in ((64, "f32", launch(1, 1, 256, 5)), (64, "f64", launch(1, 0, 64, 0)),
-                        (2048, "f32", launch(1, 3, 256, 5, 4)), (2048, "f64", launch(1, 3, 256, 0, 2))):
-        fl = {k: dev(np.ascontiguousarray(np.resize(f[k], (64, nx)))) for k in ("phi0", "ux", "uy")}
-        s = Solver([(lbm.make_params(nx, 64, f["dx"], f["dt"], cfg.lam, cfg.D, mode, boundary=lbm.LBM_BC_NEE),
-                     fl)])
-        assert s.get_launch() == w, (nx, mode)
-        s.close()
+    # A context that touches at most 256 MiB per step is served by the Infinity Cache: cached stores,
+    # row bands, every wave resident (64-column tiles kept for FP64 storage on narrow lattices).
+    for mode, w in (("f32", launch(1, 1, 256, 0)), ("f64", launch(1, 1, 64, 0)), ("f16s", launch(1, 1, 256, 0))):
+        for bc in (lbm.LBM_BC_PERIODIC, lbm.LBM_BC_NEE):
+            s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, mode, boundary=bc), fields)])
+            assert s.get_launch() == w, (mode, bc)
+            s.close()
     s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, "f32", lbm.LBM_AUX_FLUX), fields)])
-    assert s.get_launch() == launch(2, 1, 256, 4)
+    assert s.get_launch() == launch(2, 1, 256, 0)
     s.close()
-    # 2048^2 FP32 touches 346 MB per step, more than the Infinity Cache holds: non-temporal stores
-    big = {k: dev(np.ascontiguousarray(np.resize(f[k], (2048, 2048)))) for k in ("phi0", "ux", "uy")}
-    s = Solver([(lbm.make_params(2048, 2048, f["dx"], f["dt"], cfg.lam, cfg.D, "f32"), big)])
-    assert s.get_launch() == launch(1, 3, 256, 5, 8, stores=0)
-    s.close()
-    del big
+
+    # Larger contexts stream (non-temporal stores).  With 4 or more wide tiles per row: row blocks (FP32
+    # about 64 tiles each, FP64 about 32; FP16 keeps column bands at 8 and 16 tiles per row); FP32 with
+    # a D(x) field runs 6 waves per SIMD.  Narrower FP64: 64-column tiles in hardware order.
+    def fields_of(nx, ny, var=False):
+        src = dict(f, D=np.full_like(f["phi0"], cfg.D))
+        keys = ("phi0", "ux", "uy", "D") if var else ("phi0", "ux", "uy")
+        return {k: dev(np.ascontiguousarray(np.resize(src[k], (ny, nx)))) for k in keys}
+
+    for nx, ny, mode, var, bc, w in (
+            (2048, 1700, "f32", False, 0, launch(1, 3, 256, 5, 8, 0)),
+            (2048, 900, "f64", False, 0, launch(1, 3, 256, 4, 4, 0)),
+            (1024, 1700, "f64", False, 0, launch(1, 3, 256, 4, 8, 0)),
+            (768, 2200, "f64", False, 0, launch(1, 0, 64, 4, 0, 0)),
+            (2048, 3100, "f16s", False, 0, launch(1, 2, 256, 0, 0, 0)),
+            (2049, 1700, "f32", False, 0, launch(1, 3, 256, 5, 7, 0)),
+            (2049, 3000, "f16s", False, 0, launch(1, 3, 256, 0, 3, 0)),
+            (8192, 420, "f32", False, 0, launch(1, 3, 256, 5, 2, 0)),
+            (4096, 800, "f32", True, 0, launch(1, 3, 256, 6, 4, 0)),
+            (2048, 1700, "f32", False, lbm.LBM_BC_NEE, launch(1, 3, 256, 5, 4, 0)),
+            (2048, 900, "f64", False, lbm.LBM_BC_NEE, launch(1, 3, 256, 0, 2, 0))):
+        fl = fields_of(nx, ny, var)
+        s = Solver([(lbm.make_params(nx, ny, f["dx"], f["dt"], cfg.lam, cfg.D, mode, boundary=bc), fl)])
+        assert s.get_launch() == w, (nx, ny, mode, var, bc)
+        s.close()
+        del fl
     two = [(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, "f32"), fields)] * 2
     s = Solver(two)  # several instances: the batched kernel's 64-column tiles
-    assert s.get_launch(1) == launch(1, 1, 64, 5)
+    assert s.get_launch(1) == launch(1, 1, 64, 0)
     s.set_launch(1, 3, tile_width=256, xcd_rows=4)
     assert s.get_launch(0) == launch(1, 3, 256, 0, 4, stores=0)
     s.set_launch(1, 2, tile_width=256, xcd_rows=4, stores=1)  # xcd_rows only counts with order 3
