@@ -206,7 +206,8 @@ int lbm_state_load(lbm_ctx *ctx, int32_t inst, const void *src, int64_t step);
  * SIMD (3..8; 0: as many as the registers allow) by reserving unused LDS per block (no effect if
  * the device does not report its LDS size); it applies to one-instance launches (the SERIAL policy);
  * the batched launch has its own cap (lbm_batch).  Defaults depend on the lattice, storage, aux form,
- * boundary and tiles per row (lbm_get_launch reports them). */
+ * boundary, tiles per row and on whether what the context's steps touch fits in the 256 MiB Infinity
+ * Cache (lbm_get_launch reports them). */
 typedef struct lbm_launch {
     int32_t rows;        /* 1..64 */
     int32_t xcd_remap;   /* tile order over the 8 XCDs (each has its own L2): 0 hardware order (tiles of a row
