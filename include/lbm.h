@@ -222,12 +222,22 @@ typedef struct lbm_launch {
     int32_t xcd_rows;    /* tile rows per block of order 3 (1..64); ignored with the other orders, where
                             lbm_get_launch reports 0 */
     int32_t stores;      /* how the new state is written: 0 non-temporal (streamed to HBM); 1 cached (left
-                            in L2 and the 256 MiB Infinity Cache, where the next step reads it back).
-                            Honoured by launches of one instance (the SERIAL policy) except the
+                            in L2 and the 256 MiB Infinity Cache, where the next step reads it back);
+                            2 one buffer updated in place, cached (read-only: chosen by lbm_init).
+                            1 is honoured by launches of one instance (the SERIAL policy) except the
                             walking loop (rows > 1) of D2Q9 instances with the local or no auxiliary
                             term; those and the batched policies store non-temporally.  Default: 1
                             for honouring instances when both population buffers and the per-node
-                            fields of every instance of the context fit in 256 MiB, else 0 */
+                            fields of every instance of the context fit in 256 MiB, else 0.
+                            2: a context of one periodic D2Q9 TRT-R instance (local or no aux term)
+                            that fits in 256 MiB only with a single population buffer is updated in
+                            place: a streaming step (pull, then each P_i written back where the
+                            opposite population was read) alternates with a local step (the node's
+                            own slots), the AA pattern of Bailey et al. (2009).  Results are bitwise
+                            those of two buffers.  Such a context takes only rows = 1 and stores = 2
+                            in lbm_set_launch (else LBM_E_ARG), its state images follow the step
+                            parity (load one with the step count it was saved at), and it has no
+                            adjoint (LBM_E_UNSUPPORTED). */
 } lbm_launch;
 
 /* Sets (inst = -1: every instance) or reads the launch shape; captured step graphs are dropped.

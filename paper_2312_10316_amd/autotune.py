@@ -32,11 +32,18 @@ def _key(solver) -> str:
 def default_candidates(solver) -> list:
     """(rows, xcd_remap, xcd_rows, tile_width, max_waves, stores, policy, blocks) tuples worth timing for
     this context.  Stores: both kinds for one instance where they are honoured (not in the local
-    form's walking loop); a batch keeps the context's default."""
+    form's walking loop); a batch keeps the context's default; a one-buffer (in-place) context keeps
+    its one-row in-place launches."""
     out = []
     st0 = solver.get_launch(0)["stores"]
     p0 = solver.params[0]
     multi = len(solver.params) > 1 and len({(p.store, p.math, p.aux) for p in solver.params}) == 1
+    if not multi and st0 == 2:  # one buffer updated in place: one-row launches only
+        for width in (64, 256):
+            for remap, h in [(0, 0), (1, 0)] + ([(3, h) for h in (2, 4, 8)] if width == 256 else []):
+                for cap in (0, 4, 5):
+                    out.append((1, remap, h, width, cap, 2, L.LBM_BATCH_SERIAL, 0))
+        return out
     if not multi:
         for width, rows_set in ((64, (1, 2, 4)), (256, (1, 2))):
             for rows in rows_set:

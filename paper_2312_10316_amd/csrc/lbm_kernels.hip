@@ -11,6 +11,8 @@
 // for coalesced streaming: lane = column (a wave reads 64 consecutive elements of each row segment),
 // each wave walks a few rows so the velocity stencil's y-neighbours stay in registers, stores are
 // non-temporal, and the tile order can be remapped so neighbouring tiles share an XCD's L2.
+#include <type_traits>
+
 #include "lbm_internal.h"
 #include "lbm_kernel_common.h"
 
@@ -109,6 +111,12 @@ template <class St, class M>
 __device__ __forceinline__ void state_node(const typename St::T *__restrict__ src, const EdgeArgs &edge, const Layout &L,
                                            int x, int y, const F16Params &f, M (&g)[9])
 {
+    if (edge.kind == 3) {  // one buffer after its streaming step: g_i of the node sits in its slot opp(i)
+        const typename St::T *row = src + (int64_t)y * 9 * L.pitch;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = Codec<St, M>::dec(row[kOpp[i] * L.pitch + x], i, f);
+        return;
+    }
     pull_node<St, M>(src, L, x, y, f, g);
     const M *u = static_cast<const M *>(edge.u);
     const M *bc = static_cast<const M *>(edge.bc);
@@ -146,7 +154,15 @@ __device__ __forceinline__ double lane_read<double>(double v, int k)
 // scalar registers and each load or store needs only a 32-bit lane offset (x, x-1 or x+1).
 // ROWS > 0 fixes the walk length at compile time (the common one-row launch then has no loop, and
 // every access keeps the scalar-base + 32-bit-offset form); 0 takes it from the launch shape.
-template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC = 0, bool MRT = false, int ROWS = 0, bool CST = false>
+// IP: 0 two buffers (pull from buf[parity], store to buf[parity ^ 1]); 1 and 2: one buffer updated in
+// place (Bailey et al.'s AA pattern, one-row launches only).  In the standard state every node's
+// post-collision values sit at the node (slot i holds P_i), exactly the two-buffer layout.  Step 1
+// (streaming) pulls as usual and writes each P_j back to the address g_opp(j) came from, i.e. into
+// slot opp(j) of the node x + e_j; step 2 (local) reads g_j from the node's own slot opp(j) and writes
+// P_j to slot j, which restores the standard state.  A thread reads and writes only its own set of
+// addresses in either step, so no two threads touch one address.
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC = 0, bool MRT = false, int ROWS = 0, bool CST = false,
+          int IP = 0>
 __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int t, int wave)
 {
     using St = typename ModeTraits<MODE>::St;
@@ -165,8 +181,11 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
     const unsigned xm = xc == 0 ? (unsigned)nx - 1 : xc - 1;
     const unsigned xp = xc == (unsigned)nx - 1 ? 0u : xc + 1;
     const int y1 = min(y0 + rows, ny);
-    const T *__restrict__ src = static_cast<const T *>(a.buf[parity]);
-    T *__restrict__ dst = static_cast<T *>(a.buf[parity ^ 1]);
+    // in place, source and destination are one buffer: no restrict on the population pointers
+    using SrcP = std::conditional_t<IP == 0, const T *__restrict__, const T *>;
+    using DstP = std::conditional_t<IP == 0, T *__restrict__, T *>;
+    const SrcP src = static_cast<const T *>(a.buf[parity]);
+    const DstP dst = static_cast<T *>(a.buf[parity ^ 1]);
     const M *__restrict__ u = static_cast<const M *>(a.u);
     const M *__restrict__ kf = static_cast<const M *>(a.k);
     const M *__restrict__ sf = static_cast<const M *>(a.s);
@@ -189,19 +208,24 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
 
     for (int y = y0; y < y1; ++y) {
         const int ym = wrap_dec(y, ny), yn = wrap_inc(y, ny);
-        const T *__restrict__ rm = src + (int64_t)ym * 9 * pitch;
-        const T *__restrict__ rc = src + (int64_t)y * 9 * pitch;
-        const T *__restrict__ rp = src + (int64_t)yn * 9 * pitch;
+        const SrcP rm = src + (int64_t)ym * 9 * pitch;
+        const SrcP rc = src + (int64_t)y * 9 * pitch;
+        const SrcP rp = src + (int64_t)yn * 9 * pitch;
         M g[9];
-        g[0] = C::dec(ld_at(rc, bc), 0, a.f16);
-        g[1] = C::dec(ld_at(rc + pitch, bm), 1, a.f16);
-        g[2] = C::dec(ld_at(rm + 2 * pitch, bc), 2, a.f16);
-        g[3] = C::dec(ld_at(rc + 3 * pitch, bp), 3, a.f16);
-        g[4] = C::dec(ld_at(rp + 4 * pitch, bc), 4, a.f16);
-        g[5] = C::dec(ld_at(rm + 5 * pitch, bm), 5, a.f16);
-        g[6] = C::dec(ld_at(rm + 6 * pitch, bp), 6, a.f16);
-        g[7] = C::dec(ld_at(rp + 7 * pitch, bp), 7, a.f16);
-        g[8] = C::dec(ld_at(rp + 8 * pitch, bm), 8, a.f16);
+        if constexpr (IP == 2) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) g[i] = C::dec(ld_at(rc + kOpp[i] * pitch, bc), i, a.f16);
+        } else {
+            g[0] = C::dec(ld_at(rc, bc), 0, a.f16);
+            g[1] = C::dec(ld_at(rc + pitch, bm), 1, a.f16);
+            g[2] = C::dec(ld_at(rm + 2 * pitch, bc), 2, a.f16);
+            g[3] = C::dec(ld_at(rc + 3 * pitch, bp), 3, a.f16);
+            g[4] = C::dec(ld_at(rp + 4 * pitch, bc), 4, a.f16);
+            g[5] = C::dec(ld_at(rm + 5 * pitch, bm), 5, a.f16);
+            g[6] = C::dec(ld_at(rm + 6 * pitch, bp), 6, a.f16);
+            g[7] = C::dec(ld_at(rp + 7 * pitch, bp), 7, a.f16);
+            g[8] = C::dec(ld_at(rp + 8 * pitch, bm), 8, a.f16);
+        }
         if constexpr (BC == 1) {
             if (y == 0 || y == ny - 1 || xc == 0 || xc == (unsigned)nx - 1)
                 nee_replace<St, M>(src, u, static_cast<const M *>(a.bc), a.L, (int)xc, y, a.f16, g);
@@ -238,13 +262,26 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
         const M s = HAS_S ? ld_at(sf + (int64_t)y * pitch, fc) : M(0);
         M P[9];
         collide<M, MRT>(g, ux_c, uy_c, r, Ax, Ay, s, P);
-        if (live) {
+        if (live && IP == 1) {
+            // P_j to the address of g_opp(j): slot opp(j) of node x + e_j (every value is a function of
+            // all nine loads, so no store can move ahead of them)
+            T *wm = dst + (int64_t)ym * 9 * pitch, *wc = dst + (int64_t)y * 9 * pitch, *wp = dst + (int64_t)yn * 9 * pitch;
+            st_at(wc, bc, C::enc(P[0], 0, a.f16));
+            st_at(wc + 3 * pitch, bp, C::enc(P[1], 1, a.f16));
+            st_at(wp + 4 * pitch, bc, C::enc(P[2], 2, a.f16));
+            st_at(wc + pitch, bm, C::enc(P[3], 3, a.f16));
+            st_at(wm + 2 * pitch, bc, C::enc(P[4], 4, a.f16));
+            st_at(wp + 7 * pitch, bp, C::enc(P[5], 5, a.f16));
+            st_at(wp + 8 * pitch, bm, C::enc(P[6], 6, a.f16));
+            st_at(wm + 5 * pitch, bm, C::enc(P[7], 7, a.f16));
+            st_at(wm + 6 * pitch, bp, C::enc(P[8], 8, a.f16));
+        } else if (live) {
             // one scalar row base and 32-bit lane offsets keep every store in the saddr form
-            T *__restrict__ out = dst + (int64_t)y * 9 * pitch;
+            const DstP out = dst + (int64_t)y * 9 * pitch;
             const unsigned pb = (unsigned)(pitch * (int64_t)sizeof(T));
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                if constexpr (CST) st_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, a.f16));
+                if constexpr (CST || IP != 0) st_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, a.f16));
                 else st_nt_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, a.f16));
             }
         }
@@ -397,20 +434,21 @@ __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity,
 }
 
 // Dispatch of one tile to the aux-term form.
-template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC = 0, bool MRT = false, int ROWS = 0, bool CST = false>
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC = 0, bool MRT = false, int ROWS = 0, bool CST = false,
+          int IP = 0>
 __device__ __forceinline__ void run_tile(const InstDesc &d, int parity, int t, int wave)
 {
     if constexpr (AUX == 1) process_tile_flux<MODE, HAS_K, HAS_S, MRT, CST>(d, parity, t, wave);
-    else process_tile<MODE, AUX, HAS_K, HAS_S, BC, MRT, ROWS, CST>(d, parity, t, wave);
+    else process_tile<MODE, AUX, HAS_K, HAS_S, BC, MRT, ROWS, CST, IP>(d, parity, t, wave);
 }
 
 // Single instance: block b -> tile (XCD-remapped if requested).
-template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC, bool MRT, int ROWS, bool CST>
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, int BC, bool MRT, int ROWS, bool CST, int IP>
 __global__ __launch_bounds__(256) void step_kernel(const StepArgs a)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const int t = tile_of_block(blockIdx.x, gridDim.x, a.d.lc.xcd_remap, tiles_per_row(a.d.L, a.d.lc), a.d.lc.xcd_rows);
-    run_tile<MODE, AUX, HAS_K, HAS_S, BC, MRT, ROWS, CST>(a.d, a.parity, t, wave);
+    run_tile<MODE, AUX, HAS_K, HAS_S, BC, MRT, ROWS, CST, IP>(a.d, a.parity, t, wave);
 }
 
 // Many instances in one launch: each block runs a range of (instance, tile) work items; the
@@ -597,17 +635,17 @@ __global__ __launch_bounds__(256) void copy_kernel(const f32x4 *__restrict__ src
 }
 
 
-template <int MODE, int AUX, int BC, bool MRT, int ROWS, bool CST = false>
+template <int MODE, int AUX, int BC, bool MRT, int ROWS, bool CST = false, int IP = 0>
 hipError_t launch_step_rows(const StepArgs &a, hipStream_t st)
 {
     dim3 block(64, 4);
     const int nblocks = tiles_of(a.d.L, a.d.lc.rows, a.d.lc.wide);
     const size_t lds = (size_t)a.d.lc.lds_reserve;  // unused LDS that caps the resident waves
     const bool hk = a.d.has_k, hs = a.d.has_s;
-    if (hk && hs) step_kernel<MODE, AUX, true, true, BC, MRT, ROWS, CST><<<nblocks, block, lds, st>>>(a);
-    else if (hk) step_kernel<MODE, AUX, true, false, BC, MRT, ROWS, CST><<<nblocks, block, lds, st>>>(a);
-    else if (hs) step_kernel<MODE, AUX, false, true, BC, MRT, ROWS, CST><<<nblocks, block, lds, st>>>(a);
-    else step_kernel<MODE, AUX, false, false, BC, MRT, ROWS, CST><<<nblocks, block, lds, st>>>(a);
+    if (hk && hs) step_kernel<MODE, AUX, true, true, BC, MRT, ROWS, CST, IP><<<nblocks, block, lds, st>>>(a);
+    else if (hk) step_kernel<MODE, AUX, true, false, BC, MRT, ROWS, CST, IP><<<nblocks, block, lds, st>>>(a);
+    else if (hs) step_kernel<MODE, AUX, false, true, BC, MRT, ROWS, CST, IP><<<nblocks, block, lds, st>>>(a);
+    else step_kernel<MODE, AUX, false, false, BC, MRT, ROWS, CST, IP><<<nblocks, block, lds, st>>>(a);
     return hipGetLastError();
 }
 
@@ -625,6 +663,13 @@ hipError_t launch_step_var(const StepArgs &a, hipStream_t st)
         return a.d.lc.stores ? launch_step_rows<MODE, AUX, BC, MRT, 0, true>(a, st)
                              : launch_step_rows<MODE, AUX, BC, MRT, 0, false>(a, st);
     } else {
+        if constexpr (BC == 0 && !MRT) {  // one buffer in place (stores == 2): alternate the two steps
+            if (a.d.lc.stores == 2) {
+                if (a.d.lc.rows != 1) return hipErrorInvalidValue;
+                return a.parity == 0 ? launch_step_rows<MODE, AUX, BC, MRT, 1, true, 1>(a, st)
+                                     : launch_step_rows<MODE, AUX, BC, MRT, 1, true, 2>(a, st);
+            }
+        }
         if (a.d.lc.rows == 1)
             return a.d.lc.stores ? launch_step_rows<MODE, AUX, BC, MRT, 1, true>(a, st)
                                  : launch_step_rows<MODE, AUX, BC, MRT, 1, false>(a, st);

@@ -23,6 +23,14 @@ def test_kernel_label():
     assert bench._kernel_label(STEP.format(m=2, bc=1, mrt="false", rows=0, cst="false")) is None
     assert bench._kernel_label(STEP.format(m=2, bc=0, mrt="true", rows=0, cst="false")) is None
     assert bench._kernel_label(COPY) == ("copy",)
+    # the two alternating steps of a one-buffer (in-place) instance
+    for ip in (1, 2):
+        name = STEP.format(m=2, bc=0, mrt="false", rows=1, cst="true").replace(">(", f", {ip}>(")
+        assert bench._kernel_label(name) == ("step", "f32", 0, False, False)
+    # 3D kernels: velocities, mode, aux, has_k, has_s, walk, cached stores
+    k3 = "void lbm::(anonymous namespace)::step3_kernel<27, 3, 0, false, false, 1, true>(lbm::StepArgs)"
+    assert bench._kernel3_label(k3) == ("d3q27", "f16s")
+    assert bench._kernel3_label(k3.replace("false, false", "true, false")) is None
     assert bench._kernel_label("void lbm::(anonymous namespace)::macros_kernel<2>(lbm::MacroArgs)") is None
 
 

@@ -1,0 +1,83 @@
+"""One-buffer (in-place) stepping.  A single periodic D2Q9 instance whose two population buffers would
+not fit in the 256 MiB Infinity Cache, but whose one buffer does, is updated in place (the AA pattern:
+a streaming step and a local step alternate).  Its states are compared bitwise with the same instance
+advanced on two buffers: the reference context holds a second, small instance, which keeps it on two
+buffers, and runs one launch per instance."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from paper_2312_10316_amd import Solver, lbm
+
+pytestmark = pytest.mark.gpu
+
+# (mode, nx, ny, variable D): two buffers touch 278-280 MB per step, one buffer 153-165 MB
+CASES = [("f32", 2048, 1700, False), ("f32", 2048, 1700, True), ("f16s", 2048, 3100, False), ("f64", 1024, 1700, False)]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def instance(mode, nx, ny, var):
+    X, Y, dx = W.mesh(nx, ny, -1.0, 1.0)
+    fields = {"phi0": dev(1.0 + np.exp(-((X - 0.3) ** 2 + Y ** 2) / 0.05)), "ux": dev(-np.pi * Y), "uy": dev(np.pi * X)}
+    if var:
+        fields["D"] = dev(1e-3 * (1.0 + 0.5 * np.sin(np.pi * X) * np.sin(np.pi * Y)))
+    return lbm.make_params(nx, ny, dx, dx / 10, 0.25, 1e-3, mode, phi_ref=1.0), fields
+
+
+def pair(mode, nx, ny, var):
+    p, fields = instance(mode, nx, ny, var)
+    one = Solver([(p, fields)])
+    small = instance(mode, 64, 40, False)
+    two = Solver([(p, fields), small])
+    two.set_batch(lbm.LBM_BATCH_SERIAL)
+    return one, two
+
+
+@pytest.mark.parametrize("mode,nx,ny,var", CASES)
+def test_in_place_matches_two_buffers(mode, nx, ny, var):
+    one, two = pair(mode, nx, ny, var)
+    assert one.get_launch()["stores"] == 2 and two.get_launch()["stores"] != 2
+    for n in (1, 1, 5, 70, 3):  # odd and even counts; 70 replays a captured graph of 64 steps
+        one.step(n)
+        two.step(n)
+        assert torch.equal(one.populations(), two.populations(0)), n
+        a, b = one.macros(), two.macros(0)
+        assert a["mass"] == b["mass"] and a["step"] == b["step"], n
+    one.close()
+    two.close()
+
+
+def test_in_place_state_images_and_restrictions():
+    mode, nx, ny, var = CASES[0]
+    one, two = pair(mode, nx, ny, var)
+    one.step(3)
+    two.step(3)
+    img, at = one.state_save(), one.macros()["step"]  # an odd step: the post-streaming layout
+    one.step(4)
+    one.state_load(img, at)
+    one.step(2)
+    two.step(2)
+    assert torch.equal(one.populations(), two.populations(0))
+    one.step(1)
+    two.step(1)
+    assert torch.equal(one.state_save(), two.state_save(0))  # even step: the images agree byte for byte
+    for kw in (dict(stores=0), dict(stores=1), dict(stores=2, rows=2)):
+        with pytest.raises(lbm.LbmError) as ei:
+            one.set_launch(kw.pop("rows", 1), 1, tile_width=256, **kw)
+        assert ei.value.status == lbm.LBM_E_ARG, kw
+    one.set_launch(1, 3, tile_width=256, max_waves=5, xcd_rows=4, stores=2)  # launch shape: still bitwise
+    one.step(3)
+    two.step(3)
+    assert torch.equal(one.populations(), two.populations(0))
+    with pytest.raises(lbm.LbmError) as ei:
+        two.set_launch(1, 1, tile_width=256, stores=2)
+    assert ei.value.status == lbm.LBM_E_ARG
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.lbm_adjoint_bytes(one.ctx, 0)
+    assert ei.value.status == lbm.LBM_E_UNSUPPORTED
+    one.close()
+    two.close()
