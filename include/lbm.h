@@ -234,10 +234,9 @@ typedef struct lbm_launch {
                             place: a streaming step (pull, then each P_i written back where the
                             opposite population was read) alternates with a local step (the node's
                             own slots), the AA pattern of Bailey et al. (2009).  Results are bitwise
-                            those of two buffers.  Such a context takes only rows = 1 and stores = 2
-                            in lbm_set_launch (else LBM_E_ARG), its state images follow the step
-                            parity (load one with the step count it was saved at), and it has no
-                            adjoint (LBM_E_UNSUPPORTED). */
+                            those of two buffers, and so are its state images (lbm_state_save and
+                            lbm_state_load convert after an odd number of steps).  Such a context
+                            takes only rows = 1 and stores = 2 in lbm_set_launch (else LBM_E_ARG). */
 } lbm_launch;
 
 /* Sets (inst = -1: every instance) or reads the launch shape; captured step graphs are dropped.

@@ -833,7 +833,15 @@ int lbm_state_save(lbm_ctx *c, int32_t inst, void *dst)
     if (!check_inst(c, inst)) return fail(LBM_E_STATE, "lbm_state_save: bad context or instance %d", inst);
     if (!dst) return fail(LBM_E_ARG, "lbm_state_save: dst is NULL");
     Instance &in = c->inst[inst];
-    hipError_t e = hipMemcpyAsync(dst, in.buf[c->parity], pops_bytes(in.p), hipMemcpyDeviceToDevice, c->stream);
+    hipError_t e;
+    if (in.lc.stores == 2 && c->parity == 1) {  // one buffer after a streaming step: write the standard image
+        const size_t used = (size_t)pop_elems(in.L) * store_bytes(in.mode);
+        e = launch_relayout(store_bytes(in.mode), in.buf[0], dst, in.L, c->stream);
+        if (e == hipSuccess && pops_bytes(in.p) > used)
+            e = hipMemsetAsync(static_cast<char *>(dst) + used, 0, pops_bytes(in.p) - used, c->stream);
+    } else {
+        e = hipMemcpyAsync(dst, in.buf[c->parity], pops_bytes(in.p), hipMemcpyDeviceToDevice, c->stream);
+    }
     return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_state_save");
 }
 
@@ -844,10 +852,11 @@ int lbm_state_load(lbm_ctx *c, int32_t inst, const void *src, int64_t step)
     if (!src) return fail(LBM_E_ARG, "lbm_state_load: src is NULL");
     if (step < 0) return fail(LBM_E_ARG, "lbm_state_load: step < 0");
     Instance &in = c->inst[inst];
-    hipError_t e = hipMemcpyAsync(in.buf[c->parity], src, pops_bytes(in.p), hipMemcpyDeviceToDevice, c->stream);
+    hipError_t e = in.lc.stores == 2 && c->parity == 1  // one buffer after a streaming step: its layout
+                       ? launch_relayout(store_bytes(in.mode), src, in.buf[0], in.L, c->stream)
+                       : hipMemcpyAsync(in.buf[c->parity], src, pops_bytes(in.p), hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(e, "lbm_state_load");
     in.step = step;
-    if (in.lc.stores == 2) c->parity = (int)(step & 1);  // one buffer: the image's layout follows the step parity
     return LBM_OK;
 }
 
@@ -933,7 +942,6 @@ int adjoint_ok(lbm_ctx *c, int32_t inst, const char *who)
     if (in.p.boundary != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for Dirichlet edges or walls", who);
     if (in.p.tau3 != 0.0 && in.p.tau3 != 1.0) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for the MRT-R operator", who);
     if (is3d(in)) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint on 3D lattices", who);
-    if (in.lc.stores == 2) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint on a one-buffer (in-place) context", who);
     return LBM_OK;
 }
 }  // namespace

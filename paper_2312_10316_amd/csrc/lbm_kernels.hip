@@ -634,6 +634,27 @@ __global__ __launch_bounds__(256) void copy_kernel(const f32x4 *__restrict__ src
     if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
+// Between the standard state (slot j of node z holds P_j(z)) and the one-buffer state after its
+// streaming step (P_j(z) in slot opp(j) of node z + e_j): dst[z][j] = src[z + e_j][opp(j)], a map that
+// is its own inverse.  Raw storage elements (E: their size); padding columns are written as zero.
+template <class E>
+__global__ __launch_bounds__(256) void relayout_kernel(const E *__restrict__ src, E *__restrict__ dst, Layout L)
+{
+    const int64_t n = (int64_t)L.ny * L.pitch;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(k % L.pitch), y = (int)(k / L.pitch);
+        const bool live = x < L.nx;
+        const int xm = x == 0 ? L.nx - 1 : x - 1, xp = x == L.nx - 1 ? 0 : x + 1;
+        const int ym = y == 0 ? L.ny - 1 : y - 1, yp = y == L.ny - 1 ? 0 : y + 1;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            const int xs = kEx[j] < 0 ? xm : (kEx[j] > 0 ? xp : x);
+            const int ys = kEy[j] < 0 ? ym : (kEy[j] > 0 ? yp : y);
+            dst[((int64_t)y * 9 + j) * L.pitch + x] = live ? src[((int64_t)ys * 9 + kOpp[j]) * L.pitch + xs] : E(0);
+        }
+    }
+}
+
 
 template <int MODE, int AUX, int BC, bool MRT, int ROWS, bool CST = false, int IP = 0>
 hipError_t launch_step_rows(const StepArgs &a, hipStream_t st)
@@ -806,6 +827,19 @@ hipError_t launch_populations(int mode, const PopArgs &a, hipStream_t st)
     case MODE_F64_F32: populations_kernel<MODE_F64_F32><<<g, 256, 0, st>>>(a); break;
     case MODE_F32_F32: populations_kernel<MODE_F32_F32><<<g, 256, 0, st>>>(a); break;
     case MODE_F16S_F32: populations_kernel<MODE_F16S_F32><<<g, 256, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_relayout(size_t elem_bytes, const void *src, void *dst, const Layout &L, hipStream_t st)
+{
+    if (L.q != 9 || src == dst) return hipErrorInvalidValue;
+    const int g = grid_for((int64_t)L.ny * L.pitch, 256, 8192);
+    switch (elem_bytes) {
+    case 2: relayout_kernel<uint16_t><<<g, 256, 0, st>>>(static_cast<const uint16_t *>(src), static_cast<uint16_t *>(dst), L); break;
+    case 4: relayout_kernel<uint32_t><<<g, 256, 0, st>>>(static_cast<const uint32_t *>(src), static_cast<uint32_t *>(dst), L); break;
+    case 8: relayout_kernel<uint64_t><<<g, 256, 0, st>>>(static_cast<const uint64_t *>(src), static_cast<uint64_t *>(dst), L); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -52,19 +52,26 @@ def test_in_place_matches_two_buffers(mode, nx, ny, var):
 
 
 def test_in_place_state_images_and_restrictions():
+    """State images are the two-buffer ones at any step (converted after an odd count), load at either
+    parity, and move between the one- and two-buffer contexts."""
     mode, nx, ny, var = CASES[0]
     one, two = pair(mode, nx, ny, var)
     one.step(3)
     two.step(3)
-    img, at = one.state_save(), one.macros()["step"]  # an odd step: the post-streaming layout
-    one.step(4)
-    one.state_load(img, at)
+    img = one.state_save()
+    assert torch.equal(img, two.state_save(0))  # odd step: converted to the standard image
+    one.step(1)                                 # the other parity ...
+    one.state_load(img, 3)                      # ... takes the same image
     one.step(2)
     two.step(2)
     assert torch.equal(one.populations(), two.populations(0))
-    one.step(1)
+    assert torch.equal(one.state_save(), two.state_save(0))
     two.step(1)
-    assert torch.equal(one.state_save(), two.state_save(0))  # even step: the images agree byte for byte
+    one.state_load(two.state_save(0), 6)        # a two-buffer image into the one-buffer context (odd parity)
+    one.step(3)
+    two.step(3)
+    assert torch.equal(one.state_save(), two.state_save(0))
+    assert one.macros()["step"] == two.macros(0)["step"] == 9
     for kw in (dict(stores=0), dict(stores=1), dict(stores=2, rows=2)):
         with pytest.raises(lbm.LbmError) as ei:
             one.set_launch(kw.pop("rows", 1), 1, tile_width=256, **kw)
@@ -76,8 +83,6 @@ def test_in_place_state_images_and_restrictions():
     with pytest.raises(lbm.LbmError) as ei:
         two.set_launch(1, 1, tile_width=256, stores=2)
     assert ei.value.status == lbm.LBM_E_ARG
-    with pytest.raises(lbm.LbmError) as ei:
-        lbm.lbm_adjoint_bytes(one.ctx, 0)
-    assert ei.value.status == lbm.LBM_E_UNSUPPORTED
+    assert lbm.lbm_adjoint_bytes(one.ctx, 0) > 0  # the adjoint works on images, so it is available
     one.close()
     two.close()
