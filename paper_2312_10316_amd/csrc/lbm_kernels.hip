@@ -684,7 +684,7 @@ hipError_t launch_step_var(const StepArgs &a, hipStream_t st)
         return a.d.lc.stores ? launch_step_rows<MODE, AUX, BC, MRT, 0, true>(a, st)
                              : launch_step_rows<MODE, AUX, BC, MRT, 0, false>(a, st);
     } else {
-        if constexpr (BC == 0 && !MRT) {  // one buffer in place (stores == 2): alternate the two steps
+        if constexpr (BC == 0) {  // one buffer in place (stores == 2): alternate the two steps
             if (a.d.lc.stores == 2) {
                 if (a.d.lc.rows != 1) return hipErrorInvalidValue;
                 return a.parity == 0 ? launch_step_rows<MODE, AUX, BC, MRT, 1, true, 1>(a, st)

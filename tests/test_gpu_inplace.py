@@ -13,33 +13,34 @@ from paper_2312_10316_amd import Solver, lbm
 pytestmark = pytest.mark.gpu
 
 # (mode, nx, ny, variable D): two buffers touch 278-280 MB per step, one buffer 153-165 MB
-CASES = [("f32", 2048, 1700, False), ("f32", 2048, 1700, True), ("f16s", 2048, 3100, False), ("f64", 1024, 1700, False)]
+CASES = [("f32", 2048, 1700, False, 0.0), ("f32", 2048, 1700, True, 0.0), ("f16s", 2048, 3100, False, 0.0),
+         ("f64", 1024, 1700, False, 0.0), ("f32", 2048, 1700, False, 0.8)]  # last: MRT-R, tau3 = 0.8
 
 
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
-def instance(mode, nx, ny, var):
+def instance(mode, nx, ny, var, tau3=0.0):
     X, Y, dx = W.mesh(nx, ny, -1.0, 1.0)
     fields = {"phi0": dev(1.0 + np.exp(-((X - 0.3) ** 2 + Y ** 2) / 0.05)), "ux": dev(-np.pi * Y), "uy": dev(np.pi * X)}
     if var:
         fields["D"] = dev(1e-3 * (1.0 + 0.5 * np.sin(np.pi * X) * np.sin(np.pi * Y)))
-    return lbm.make_params(nx, ny, dx, dx / 10, 0.25, 1e-3, mode, phi_ref=1.0), fields
+    return lbm.make_params(nx, ny, dx, dx / 10, 0.25, 1e-3, mode, phi_ref=1.0, tau3=tau3), fields
 
 
-def pair(mode, nx, ny, var):
-    p, fields = instance(mode, nx, ny, var)
+def pair(mode, nx, ny, var, tau3=0.0):
+    p, fields = instance(mode, nx, ny, var, tau3)
     one = Solver([(p, fields)])
-    small = instance(mode, 64, 40, False)
+    small = instance(mode, 64, 40, False, tau3)
     two = Solver([(p, fields), small])
     two.set_batch(lbm.LBM_BATCH_SERIAL)
     return one, two
 
 
-@pytest.mark.parametrize("mode,nx,ny,var", CASES)
-def test_in_place_matches_two_buffers(mode, nx, ny, var):
-    one, two = pair(mode, nx, ny, var)
+@pytest.mark.parametrize("mode,nx,ny,var,tau3", CASES)
+def test_in_place_matches_two_buffers(mode, nx, ny, var, tau3):
+    one, two = pair(mode, nx, ny, var, tau3)
     assert one.get_launch()["stores"] == 2 and two.get_launch()["stores"] != 2
     for n in (1, 1, 5, 70, 3):  # odd and even counts; 70 replays a captured graph of 64 steps
         one.step(n)
@@ -54,8 +55,7 @@ def test_in_place_matches_two_buffers(mode, nx, ny, var):
 def test_in_place_state_images_and_restrictions():
     """State images are the two-buffer ones at any step (converted after an odd count), load at either
     parity, and move between the one- and two-buffer contexts."""
-    mode, nx, ny, var = CASES[0]
-    one, two = pair(mode, nx, ny, var)
+    one, two = pair(*CASES[0])
     one.step(3)
     two.step(3)
     img = one.state_save()
