@@ -53,7 +53,7 @@ struct Launch {
     int32_t max_waves;    // cap on resident waves per SIMD (0: none)
     int32_t lds_reserve;  // dynamic LDS bytes reserved per block to enforce max_waves (0: none)
     int32_t xcd_rows;     // tile rows per block of order 3
-    int32_t stores;       // 0: non-temporal stores of the new state; 1: cached stores
+    int32_t stores;       // 0: non-temporal stores of the new state; 1: cached; 2: one buffer in place, cached
     int32_t pad_;
 };
 
@@ -148,7 +148,7 @@ struct PrepArgs {
 struct EdgeArgs {
     const void *u;     // velocity (math type)
     const void *bc;    // Dirichlet values (math type), or nullptr for a periodic instance
-    int32_t kind;      // lbm_boundary: 1 NEE edges, 2 walls
+    int32_t kind;      // lbm_boundary: 1 NEE edges, 2 walls; 3: a one-buffer state after its streaming step
 };
 
 struct MacroArgs {
