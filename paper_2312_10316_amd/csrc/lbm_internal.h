@@ -206,6 +206,7 @@ hipError_t launch_step3(int mode, int aux, const StepArgs &a, hipStream_t st);
 hipError_t launch_init3(int mode, const InitArgs &a, hipStream_t st);
 hipError_t launch_macros3(int mode, const MacroArgs &a, double *result, hipStream_t st);
 hipError_t launch_populations3(int mode, const PopArgs &a, hipStream_t st);
+hipError_t launch_relayout3(size_t elem_bytes, const void *src, void *dst, const Layout &L, hipStream_t st);
 hipError_t launch_adjoint_seed(int mode, const double *dphi, void *lam, const Layout &L, hipStream_t st);
 hipError_t launch_adjoint_init(int mode, const void *lam, const void *u, double *dphi0, const Layout &L, hipStream_t st);
 

@@ -20,6 +20,9 @@
 // 64-column tile, so the row bases of the nine rows (y, z), (y+-1, z), (y, z+-1), (y+-1, z+-1) it
 // pulls from are wave-uniform scalars and every access is base + 32-bit lane offset.  Stores are
 // non-temporal and tiles follow the XCD-contiguous order of the D2Q9 kernels.
+#include <algorithm>
+#include <type_traits>
+
 #include "lbm_internal.h"
 #include "lbm_kernel_common.h"
 
@@ -29,6 +32,8 @@ namespace {
 constexpr int kEx3[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1};
 constexpr int kEy3[27] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, -1, 1, 1, -1};
 constexpr int kEz3[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1, 1, -1, -1, 1, 1, -1, 1, -1};
+// Opposite velocity: the tables keep i and i + 1 (odd i) opposite.
+__host__ __device__ constexpr int opp3(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
 // Weights of the rest, face (axis), edge and corner velocities.
 template <int Q>
@@ -173,10 +178,29 @@ __device__ __forceinline__ void pull_node3(const typename St::T *__restrict__ sr
     }
 }
 
+// The state of a node before collision: the pull, or for a one-buffer state after its streaming step
+// (edge kind 3) the node's own slots opp(i).
+template <int Q, class St, class M>
+__device__ __forceinline__ void state3(const typename St::T *__restrict__ src, const Layout &L, int kind, int x, int y,
+                                       int z, const F16Params &f, M (&g)[Q])
+{
+    if (kind == 3) {
+        const typename St::T *row = src + ((int64_t)z * L.ny + y) * Q * L.pitch;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) g[i] = Codec<St, M>::dec(row[opp3(i) * L.pitch + x], i, f);
+        return;
+    }
+    pull_node3<Q, St, M>(src, L, x, y, z, f, g);
+}
+
 // ROWS > 0 fixes the walk length at compile time, 0 takes it from the launch shape.  Only FP16
 // storage uses the one-row instantiation: at 256^3 it is +19 % (D3Q19) and +24 % (D3Q27) over the
 // walking loop, while FP32 and FP64 are 1-2 % faster with the loop.
-template <int Q, int MODE, int AUX, bool HAS_K, bool HAS_S, int ROWS, bool CST>
+// IP: 0 two buffers; 1 and 2: one buffer updated in place, as in the D2Q9 kernel (step 1 pulls and
+// writes each P_j back to the address g_opp(j) came from; step 2 reads g_j from the node's own slot
+// opp(j) and writes P_j to slot j).  Every node owns its own set of addresses, so the walking loop
+// stays race-free as well.
+template <int Q, int MODE, int AUX, bool HAS_K, bool HAS_S, int ROWS, bool CST, int IP>
 __global__ __launch_bounds__(256) void step3_kernel(const StepArgs sa)
 {
     using St = typename ModeTraits<MODE>::St;
@@ -200,8 +224,11 @@ __global__ __launch_bounds__(256) void step3_kernel(const StepArgs sa)
     const unsigned xp = xc == (unsigned)nx - 1 ? 0u : xc + 1;
     const unsigned bc = xc * (unsigned)sizeof(T), bm = xm * (unsigned)sizeof(T), bp = xp * (unsigned)sizeof(T);
     const unsigned fc = xc * (unsigned)sizeof(M), fm = xm * (unsigned)sizeof(M), fp = xp * (unsigned)sizeof(M);
-    const T *__restrict__ src = static_cast<const T *>(a.buf[sa.parity]);
-    T *__restrict__ dst = static_cast<T *>(a.buf[sa.parity ^ 1]);
+    // in place, source and destination are one buffer: no restrict on the population pointers
+    using SrcP = std::conditional_t<IP == 0, const T *__restrict__, const T *>;
+    using DstP = std::conditional_t<IP == 0, T *__restrict__, T *>;
+    const SrcP src = static_cast<const T *>(a.buf[sa.parity]);
+    const DstP dst = static_cast<T *>(a.buf[sa.parity ^ 1]);
     const M *__restrict__ u = static_cast<const M *>(a.u);
     const M *__restrict__ kf = static_cast<const M *>(a.k);
     const M *__restrict__ sf = static_cast<const M *>(a.s);
@@ -215,13 +242,25 @@ __global__ __launch_bounds__(256) void step3_kernel(const StepArgs sa)
         const int z = r / ny, y = r - z * ny;
         const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny), zm = wrap_dec(z, nz), zp = wrap_inc(z, nz);
         auto blk = [&](int yy, int zz) { return src + ((int64_t)zz * ny + yy) * Q * pitch; };
-        const T *__restrict__ b00 = blk(y, z);
-        const T *__restrict__ bm0 = blk(ym, z);
-        const T *__restrict__ bp0 = blk(yp, z);
-        const T *__restrict__ b0m = blk(y, zm);
-        const T *__restrict__ b0p = blk(y, zp);
+        const SrcP b00 = blk(y, z);
+        const SrcP bm0 = blk(ym, z);
+        const SrcP bp0 = blk(yp, z);
+        const SrcP b0m = blk(y, zm);
+        const SrcP b0p = blk(y, zp);
         const F16Params &f = a.f16;
+        // slot i of the node x - e_i (the pull's source) and its byte offset in the row segment
+        auto from = [&](int i) {
+            return blk(kEy3[i] > 0 ? ym : (kEy3[i] < 0 ? yp : y), kEz3[i] > 0 ? zm : (kEz3[i] < 0 ? zp : z)) + i * pitch;
+        };
+        auto from_off = [&](int i) { return kEx3[i] > 0 ? bm : (kEx3[i] < 0 ? bp : bc); };
         M g[Q];
+        if constexpr (IP == 2) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) g[i] = C::dec(ld_at(b00 + opp3(i) * pitch, bc), i, f);
+        } else if constexpr (IP == 1) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) g[i] = C::dec(ld_at(from(i), from_off(i)), i, f);
+        } else {
         g[0] = C::dec(ld_at(b00, bc), 0, f);
         g[1] = C::dec(ld_at(b00 + 1 * pitch, bm), 1, f);
         g[2] = C::dec(ld_at(b00 + 2 * pitch, bp), 2, f);
@@ -251,6 +290,7 @@ __global__ __launch_bounds__(256) void step3_kernel(const StepArgs sa)
             g[25] = C::dec(ld_at(blk(ym, zm) + 25 * pitch, bp), 25, f);
             g[26] = C::dec(ld_at(blk(yp, zp) + 26 * pitch, bm), 26, f);
         }
+        }
 
         auto vrow = [&](int yy, int zz) { return u + ((int64_t)zz * ny + yy) * 3 * pitch; };
         const M *__restrict__ uc = vrow(y, z);
@@ -278,11 +318,14 @@ __global__ __launch_bounds__(256) void step3_kernel(const StepArgs sa)
         const M s = HAS_S ? ld_at(sf + (int64_t)r * pitch, fc) : M(0);
         M P[Q];
         collide3<Q, M>(g, ux, uy, uz, rr, Ax, Ay, Az, s, P);
-        if (live) {
-            T *__restrict__ out = dst + (int64_t)r * Q * pitch;
+        if (live && IP == 1) {  // P_j to the address of g_opp(j) (each value depends on all Q loads)
+#pragma unroll
+            for (int j = 0; j < Q; ++j) st_at(const_cast<T *>(from(opp3(j))), from_off(opp3(j)), C::enc(P[j], j, f));
+        } else if (live) {
+            const DstP out = dst + (int64_t)r * Q * pitch;
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                if constexpr (CST) st_at(out + i * pitch, bc, C::enc(P[i], i, f));
+                if constexpr (CST || IP != 0) st_at(out + i * pitch, bc, C::enc(P[i], i, f));
                 else st_nt_at(out + i * pitch, bc, C::enc(P[i], i, f));
             }
         }
@@ -339,7 +382,7 @@ __global__ __launch_bounds__(256) void macros3_kernel(const MacroArgs a)
         const int x = (int)(n % nx);
         const int64_t r = n / nx;
         M g[Q];
-        pull_node3<Q, St, M>(src, a.L, x, (int)(r % ny), (int)(r / ny), a.f16, g);
+        state3<Q, St, M>(src, a.L, a.edge.kind, x, (int)(r % ny), (int)(r / ny), a.f16, g);
         double phi = 0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) phi += (double)g[i];
@@ -383,30 +426,34 @@ __global__ __launch_bounds__(256) void populations3_kernel(const PopArgs a)
         const int x = (int)(n % nx);
         const int64_t r = n / nx;
         M g[Q];
-        pull_node3<Q, St, M>(src, a.L, x, (int)(r % ny), (int)(r / ny), a.f16, g);
+        state3<Q, St, M>(src, a.L, a.edge.kind, x, (int)(r % ny), (int)(r / ny), a.f16, g);
 #pragma unroll
         for (int i = 0; i < Q; ++i) a.out[i * N + n] = (double)g[i];
     }
 }
 
-template <int Q, int MODE, int AUX, int ROWS, bool CST>
+template <int Q, int MODE, int AUX, int ROWS, bool CST, int IP = 0>
 hipError_t launch_step3_rows(const StepArgs &a, hipStream_t st)
 {
     dim3 block(64, 4);
     const int nblocks = tiles_of(a.d.L, a.d.lc.rows, a.d.lc.wide);
     const size_t lds = (size_t)a.d.lc.lds_reserve;  // unused LDS that caps the resident waves
     const bool hk = a.d.has_k, hs = a.d.has_s;
-    if (hk && hs) step3_kernel<Q, MODE, AUX, true, true, ROWS, CST><<<nblocks, block, lds, st>>>(a);
-    else if (hk) step3_kernel<Q, MODE, AUX, true, false, ROWS, CST><<<nblocks, block, lds, st>>>(a);
-    else if (hs) step3_kernel<Q, MODE, AUX, false, true, ROWS, CST><<<nblocks, block, lds, st>>>(a);
-    else step3_kernel<Q, MODE, AUX, false, false, ROWS, CST><<<nblocks, block, lds, st>>>(a);
+    if (hk && hs) step3_kernel<Q, MODE, AUX, true, true, ROWS, CST, IP><<<nblocks, block, lds, st>>>(a);
+    else if (hk) step3_kernel<Q, MODE, AUX, true, false, ROWS, CST, IP><<<nblocks, block, lds, st>>>(a);
+    else if (hs) step3_kernel<Q, MODE, AUX, false, true, ROWS, CST, IP><<<nblocks, block, lds, st>>>(a);
+    else step3_kernel<Q, MODE, AUX, false, false, ROWS, CST, IP><<<nblocks, block, lds, st>>>(a);
     return hipGetLastError();
 }
 
-// Non-temporal or cached stores of the new state (Launch::stores), a compile-time choice.
+// Non-temporal or cached stores of the new state, or one buffer in place (Launch::stores 0 / 1 / 2),
+// a compile-time choice.
 template <int Q, int MODE, int AUX, int ROWS>
 hipError_t launch_step3_st(const StepArgs &a, hipStream_t st)
 {
+    if (a.d.lc.stores == 2)
+        return a.parity == 0 ? launch_step3_rows<Q, MODE, AUX, ROWS, true, 1>(a, st)
+                             : launch_step3_rows<Q, MODE, AUX, ROWS, true, 2>(a, st);
     return a.d.lc.stores ? launch_step3_rows<Q, MODE, AUX, ROWS, true>(a, st)
                          : launch_step3_rows<Q, MODE, AUX, ROWS, false>(a, st);
 }
@@ -517,6 +564,55 @@ hipError_t launch_populations3(int mode, const PopArgs &a, hipStream_t st)
 {
     if (a.L.q == 27) return launch_populations3_q<27>(mode, a, st);
     if (a.L.q == 19) return launch_populations3_q<19>(mode, a, st);
+    return hipErrorInvalidValue;
+}
+
+namespace {
+
+// The 3D form of the D2Q9 relayout: dst[z][j] = src[z + e_j][opp(j)] (its own inverse); raw storage
+// elements, padding columns written as zero.
+template <int Q, class E>
+__global__ __launch_bounds__(256) void relayout3_kernel(const E *__restrict__ src, E *__restrict__ dst, Layout L)
+{
+    const int64_t n = rows_of(L) * L.pitch;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(k % L.pitch);
+        const int64_t r = k / L.pitch;
+        const int y = (int)(r % L.ny), z = (int)(r / L.ny);
+        const bool live = x < L.nx;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+            int xs = x + kEx3[j], ys = y + kEy3[j], zs = z + kEz3[j];
+            xs = xs < 0 ? L.nx - 1 : (xs == L.nx ? 0 : xs);
+            ys = ys < 0 ? L.ny - 1 : (ys == L.ny ? 0 : ys);
+            zs = zs < 0 ? L.nz - 1 : (zs == L.nz ? 0 : zs);
+            dst[(r * Q + j) * L.pitch + x] =
+                live ? src[(((int64_t)zs * L.ny + ys) * Q + opp3(j)) * L.pitch + xs] : E(0);
+        }
+    }
+}
+
+template <int Q>
+hipError_t relayout3_q(size_t elem_bytes, const void *src, void *dst, const Layout &L, hipStream_t st)
+{
+    const int64_t n = rows_of(L) * L.pitch;
+    const int g = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    switch (elem_bytes) {
+    case 2: relayout3_kernel<Q, uint16_t><<<g, 256, 0, st>>>(static_cast<const uint16_t *>(src), static_cast<uint16_t *>(dst), L); break;
+    case 4: relayout3_kernel<Q, uint32_t><<<g, 256, 0, st>>>(static_cast<const uint32_t *>(src), static_cast<uint32_t *>(dst), L); break;
+    case 8: relayout3_kernel<Q, uint64_t><<<g, 256, 0, st>>>(static_cast<const uint64_t *>(src), static_cast<uint64_t *>(dst), L); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_relayout3(size_t elem_bytes, const void *src, void *dst, const Layout &L, hipStream_t st)
+{
+    if (src == dst) return hipErrorInvalidValue;
+    if (L.q == 27) return relayout3_q<27>(elem_bytes, src, dst, L, st);
+    if (L.q == 19) return relayout3_q<19>(elem_bytes, src, dst, L, st);
     return hipErrorInvalidValue;
 }
 
