@@ -21,18 +21,18 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
-def instance(mode, nx, ny, var, tau3=0.0):
+def instance(mode, nx, ny, var, tau3=0.0, aux=lbm.LBM_AUX_LOCAL):
     X, Y, dx = W.mesh(nx, ny, -1.0, 1.0)
     fields = {"phi0": dev(1.0 + np.exp(-((X - 0.3) ** 2 + Y ** 2) / 0.05)), "ux": dev(-np.pi * Y), "uy": dev(np.pi * X)}
     if var:
         fields["D"] = dev(1e-3 * (1.0 + 0.5 * np.sin(np.pi * X) * np.sin(np.pi * Y)))
-    return lbm.make_params(nx, ny, dx, dx / 10, 0.25, 1e-3, mode, phi_ref=1.0, tau3=tau3), fields
+    return lbm.make_params(nx, ny, dx, dx / 10, 0.25, 1e-3, mode, aux, phi_ref=1.0, tau3=tau3), fields
 
 
-def pair(mode, nx, ny, var, tau3=0.0):
-    p, fields = instance(mode, nx, ny, var, tau3)
+def pair(mode, nx, ny, var, tau3=0.0, aux=lbm.LBM_AUX_LOCAL):
+    p, fields = instance(mode, nx, ny, var, tau3, aux)
     one = Solver([(p, fields)])
-    small = instance(mode, 64, 40, False, tau3)
+    small = instance(mode, 64, 40, False, tau3, aux)
     two = Solver([(p, fields), small])
     two.set_batch(lbm.LBM_BATCH_SERIAL)
     return one, two
@@ -84,6 +84,23 @@ def test_in_place_state_images_and_restrictions():
         two.set_launch(1, 1, tile_width=256, stores=2)
     assert ei.value.status == lbm.LBM_E_ARG
     assert lbm.lbm_adjoint_bytes(one.ctx, 0) > 0  # the adjoint works on images, so it is available
+    one.close()
+    two.close()
+
+
+@pytest.mark.parametrize("aux", [lbm.LBM_AUX_LOCAL, lbm.LBM_AUX_NONE])
+def test_in_place_with_a_source(aux):
+    """The source path (a time-dependent S and dS/dt every step) and the form without the auxiliary
+    term, in place and on two buffers: bitwise equal."""
+    one, two = pair("f32", 2048, 1700, False, 0.0, aux)
+    assert one.get_launch()["stores"] == 2
+    X, Y, _ = W.mesh(2048, 1700, -1.0, 1.0)
+    base = np.exp(-(X ** 2 + Y ** 2) / 0.1)
+    for t in range(5):
+        S, dS = dev(np.cos(0.3 * t) * base), dev(-0.3 * np.sin(0.3 * t) * base)
+        one.step(1, S=[S], dSdt=[dS])
+        two.step(1, S=[S, None], dSdt=[dS, None])
+        assert torch.equal(one.populations(), two.populations(0)), t
     one.close()
     two.close()
 
