@@ -230,7 +230,7 @@ typedef struct lbm_launch {
                             for honouring instances when both population buffers and the per-node
                             fields of every instance of the context fit in 256 MiB, else 0.
                             2: a context of one periodic instance (D2Q9 with the local or no aux
-                            term, D3Q19 or D3Q27)
+                            term; D3Q19 or D3Q27 without FP64 math)
                             that fits in 256 MiB only with a single population buffer is updated in
                             place: a streaming step (pull, then each P_i written back where the
                             opposite population was read) alternates with a local step (the node's

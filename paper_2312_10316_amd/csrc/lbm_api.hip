@@ -629,8 +629,11 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
     const Instance &i0 = c->inst[0];
     const size_t one_buffer = (size_t)i0.L.nx * rows_of(i0.L) * i0.L.q * store_bytes(i0.mode);
     const bool inplace = n_inst == 1 && touched > kInfinityCacheBytes && touched - one_buffer <= kInfinityCacheBytes &&
-                         (i0.p.lattice != LBM_LATTICE_D2Q9 ||  // D3Q19/D3Q27: periodic, local or no aux
-                          (i0.p.boundary == LBM_BC_PERIODIC && i0.p.aux != LBM_AUX_FLUX && i0.lc.rows == 1));
+                         // D3Q19/D3Q27 (periodic, local or no aux) except FP64 math: its in-place instantiation
+                         // fuses the collision's multiply-adds differently (equal to rounding, not bitwise)
+                         ((i0.p.lattice != LBM_LATTICE_D2Q9 && i0.mode != MODE_F64_F64) ||
+                          (i0.p.lattice == LBM_LATTICE_D2Q9 && i0.p.boundary == LBM_BC_PERIODIC &&
+                           i0.p.aux != LBM_AUX_FLUX && i0.lc.rows == 1));
     for (Instance &in : c->inst) {
         in.lc.stores = touched <= kInfinityCacheBytes &&
                        (in.p.lattice != LBM_LATTICE_D2Q9 || in.p.aux == LBM_AUX_FLUX || in.lc.rows == 1);

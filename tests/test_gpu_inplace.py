@@ -14,7 +14,8 @@ pytestmark = pytest.mark.gpu
 
 # (mode, nx, ny, variable D): two buffers touch 278-280 MB per step, one buffer 153-165 MB
 CASES = [("f32", 2048, 1700, False, 0.0), ("f32", 2048, 1700, True, 0.0), ("f16s", 2048, 3100, False, 0.0),
-         ("f64", 1024, 1700, False, 0.0), ("f32", 2048, 1700, False, 0.8)]  # last: MRT-R, tau3 = 0.8
+         ("f64", 1024, 1700, False, 0.0), ("f32", 2048, 1700, False, 0.8),  # MRT-R, tau3 = 0.8
+         ("f64", 1024, 1700, True, 0.8)]
 
 
 def dev(a):
@@ -106,7 +107,7 @@ def test_in_place_with_a_source(aux):
 
 
 # (velocities, mode, n): n^3 lattices where one population buffer fits in the cache and two do not
-CASES3 = [(19, "f32", 128), (27, "f32", 112), (27, "f16s", 140)]
+CASES3 = [(19, "f32", 128), (27, "f32", 112), (27, "f16s", 140), (19, "f64s_f32m", 104)]
 
 
 def instance3(q, mode, n):
@@ -139,3 +140,12 @@ def test_3d_in_place_matches_two_buffers(q, mode, n):
     assert a["mass"] == b["mass"]
     one.close()
     two.close()
+
+
+def test_3d_fp64_math_keeps_two_buffers():
+    """With FP64 math the in-place 3D instantiation would round the collision differently (the compiler
+    fuses its multiply-adds otherwise), so such an instance keeps two buffers even where only one fits."""
+    p, fields = instance3(19, "f64", 104)
+    s = Solver([(p, fields)])
+    assert s.get_launch()["stores"] == 0
+    s.close()
