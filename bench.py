@@ -700,11 +700,15 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": None if traffic is None else round(traffic),
-                     "traffic_unit": "HBM bytes/launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
+                     "traffic_unit": "bytes/launch filled into L2 from the fabric (rocprofv3 FETCH_SIZE+WRITE_SIZE, "
+                                     "copy-calibrated; HBM plus Infinity Cache hits)",
                      "algorithmic_bytes_per_launch": int(n2 * r["bytes_per_lup"]),
                      "bytes_per_lup": r["bytes_per_lup"], "lups_per_launch": int(n2),
                      "copy_gbps_measured": round(copy_gbps, 1),
-                     "frac_of_copy": round(achieved / copy_gbps, 4)},
+                     "frac_of_copy": round(achieved / copy_gbps, 4),
+                     "state": {0: "two buffers streamed from HBM (non-temporal stores)",
+                               1: "two buffers held in the 256 MiB Infinity Cache (cached stores)",
+                               2: "one buffer updated in place, held in the 256 MiB Infinity Cache"}[r["launch"]["stores"]]},
         "modes": {m: {k: (round(v, 6) if isinstance(v, float) and abs(v) >= 1e-3 else v) for k, v in results[m].items()}
                   for m in modes},
     }
