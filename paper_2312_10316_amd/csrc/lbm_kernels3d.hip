@@ -446,21 +446,28 @@ hipError_t launch_step3_rows(const StepArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-// Non-temporal or cached stores of the new state, or one buffer in place (Launch::stores 0 / 1 / 2),
-// a compile-time choice.
+// Non-temporal or cached stores of the new state (Launch::stores 0 / 1), a compile-time choice.
 template <int Q, int MODE, int AUX, int ROWS>
 hipError_t launch_step3_st(const StepArgs &a, hipStream_t st)
 {
-    if (a.d.lc.stores == 2)
-        return a.parity == 0 ? launch_step3_rows<Q, MODE, AUX, ROWS, true, 1>(a, st)
-                             : launch_step3_rows<Q, MODE, AUX, ROWS, true, 2>(a, st);
     return a.d.lc.stores ? launch_step3_rows<Q, MODE, AUX, ROWS, true>(a, st)
                          : launch_step3_rows<Q, MODE, AUX, ROWS, false>(a, st);
 }
 
+// One buffer in place (stores 2; one row per wave): the one-row instantiation, whose Q loads and
+// stores keep the scalar-base + 32-bit-offset form (the walking loop's 64-bit addresses would keep
+// up to 27 store addresses in vector registers).
 template <int Q, int MODE, int AUX>
 hipError_t launch_step3_aux(const StepArgs &a, hipStream_t st)
 {
+    if (a.d.lc.stores == 2) {  // never chosen with FP64 math (its in-place collision rounds differently)
+        if constexpr (MODE != MODE_F64_F64) {
+            if (a.d.lc.rows != 1) return hipErrorInvalidValue;
+            return a.parity == 0 ? launch_step3_rows<Q, MODE, AUX, 1, true, 1>(a, st)
+                                 : launch_step3_rows<Q, MODE, AUX, 1, true, 2>(a, st);
+        }
+        return hipErrorInvalidValue;
+    }
     if constexpr (MODE == MODE_F16S_F32) {
         if (a.d.lc.rows == 1) return launch_step3_st<Q, MODE, AUX, 1>(a, st);
     }
