@@ -629,8 +629,9 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
     const Instance &i0 = c->inst[0];
     const size_t one_buffer = (size_t)i0.L.nx * rows_of(i0.L) * i0.L.q * store_bytes(i0.mode);
     const bool inplace = n_inst == 1 && touched > kInfinityCacheBytes && touched - one_buffer <= kInfinityCacheBytes &&
-                         // D3Q19/D3Q27 (periodic, local or no aux) except FP64 math: its in-place instantiation
-                         // fuses the collision's multiply-adds differently (equal to rounding, not bitwise)
+                         // D3Q19/D3Q27 (periodic, local or no aux) except FP64 math: its one-row in-place
+                         // kernels fuse the collision's multiply-adds otherwise than the two-buffer walking loop
+                         // (equal to rounding, not bitwise)
                          ((i0.p.lattice != LBM_LATTICE_D2Q9 && i0.mode != MODE_F64_F64) ||
                           (i0.p.lattice == LBM_LATTICE_D2Q9 && i0.p.boundary == LBM_BC_PERIODIC &&
                            i0.p.aux != LBM_AUX_FLUX && i0.lc.rows == 1));

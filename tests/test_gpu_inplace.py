@@ -143,8 +143,9 @@ def test_3d_in_place_matches_two_buffers(q, mode, n):
 
 
 def test_3d_fp64_math_keeps_two_buffers():
-    """With FP64 math the in-place 3D instantiation would round the collision differently (the compiler
-    fuses its multiply-adds otherwise), so such an instance keeps two buffers even where only one fits."""
+    """With FP64 math the one-row in-place 3D kernels would round the collision differently from the
+    two-buffer walking loop (the compiler fuses its multiply-adds otherwise), so such an instance keeps
+    two buffers even where only one fits."""
     p, fields = instance3(19, "f64", 104)
     s = Solver([(p, fields)])
     assert s.get_launch()["stores"] == 0
