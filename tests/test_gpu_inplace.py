@@ -85,6 +85,15 @@ def test_in_place_state_images_and_restrictions():
         two.set_launch(1, 1, tile_width=256, stores=2)
     assert ei.value.status == lbm.LBM_E_ARG
     assert lbm.lbm_adjoint_bytes(one.ctx, 0) > 0  # the adjoint works on images, so it is available
+    X, Y, _ = W.mesh(CASES[0][1], CASES[0][2], -1.0, 1.0)  # a new velocity field after an odd step count
+    ux2, uy2 = dev(-2.0 * Y), dev(2.0 * X)
+    one.step(1)
+    two.step(1)
+    one.set_velocity(ux2, uy2)
+    two.set_velocity(ux2, uy2, inst=0)
+    one.step(65)
+    two.step(65)
+    assert torch.equal(one.state_save(), two.state_save(0))
     one.close()
     two.close()
 
