@@ -425,10 +425,11 @@ def _find(dirpath, suffix):
 
 
 def _kernel3_label(name: str):
-    """'step3_kernel<27, 2, 0, false, false, 0, false>' (velocities, mode, aux, has_k, has_s, walk, cached
-    stores) -> ('d3q27', 'f32') for the constant-D, source-free kernels; copy -> ('copy',); other -> None."""
+    """'step3_kernel<27, 2, 0, false, false, 0, false, 0>' (velocities, mode, aux, has_k, has_s, walk, cached
+    stores, in-place step) -> ('d3q27', 'f32') for the constant-D, source-free kernels; copy -> ('copy',);
+    other -> None."""
     import re
-    m = re.search(r"step3_kernel<(19|27), (\d), (\d), false, false(?:, \d)?(?:, (?:true|false))?>", name)
+    m = re.search(r"step3_kernel<(19|27), (\d), (\d), false, false(?:, \d)?(?:, (?:true|false))?(?:, \d)?>", name)
     if m:
         return (f"d3q{m.group(1)}", KERNEL_MODES[m.group(2)])
     if "copy_kernel" in name:
@@ -618,14 +619,16 @@ def main():
     args = ap.parse_args()
     if args.summarize:
         d = args.summarize
-        if os.path.isdir(os.path.join(d, "trace3")):
-            n3 = 256
-            pmc3 = {c: os.path.join(d, f"pmc3_{c.lower()}") for c in ("FETCH_SIZE", "WRITE_SIZE")}
+        # 256^3 (streaming) under trace3/, pmc3_*; 128^3 (held in the Infinity Cache) under trace3_128/, pmc3_*_128
+        for n3, sfx in ((256, ""), (128, "_128")):
+            if not os.path.isdir(os.path.join(d, "trace3" + sfx)):
+                continue
+            pmc3 = {c: os.path.join(d, f"pmc3_{c.lower()}{sfx}") for c in ("FETCH_SIZE", "WRITE_SIZE")}
             pmc3 = {k: v for k, v in pmc3.items() if os.path.isdir(v)}
-            summarize_profiles3(os.path.join(d, "trace3"), pmc3, os.path.join(ROOT, "profiles"), n3,
-                                f"rocprofv3 --kernel-trace --stats --output-format csv -d RUNDIR/trace3 -o trace -- "
+            summarize_profiles3(os.path.join(d, "trace3" + sfx), pmc3, os.path.join(ROOT, "profiles"), n3,
+                                f"rocprofv3 --kernel-trace --stats --output-format csv -d RUNDIR/trace3{sfx} -o trace -- "
                                 f"python3 bench.py --profile3d {n3} --steps 100",
-                                [f"rocprofv3 --pmc {c} --output-format csv -d RUNDIR/pmc3_{c.lower()} -o pmc -- "
+                                [f"rocprofv3 --pmc {c} --output-format csv -d RUNDIR/pmc3_{c.lower()}{sfx} -o pmc -- "
                                  f"python3 bench.py --profile3d {n3} --steps 8" for c in sorted(pmc3)])
         if not os.path.isdir(os.path.join(d, "trace")):
             return

@@ -28,8 +28,9 @@ def test_kernel_label():
         name = STEP.format(m=2, bc=0, mrt="false", rows=1, cst="true").replace(">(", f", {ip}>(")
         assert bench._kernel_label(name) == ("step", "f32", 0, False, False)
     # 3D kernels: velocities, mode, aux, has_k, has_s, walk, cached stores
-    k3 = "void lbm::(anonymous namespace)::step3_kernel<27, 3, 0, false, false, 1, true>(lbm::StepArgs)"
+    k3 = "void lbm::(anonymous namespace)::step3_kernel<27, 3, 0, false, false, 1, true, 0>(lbm::StepArgs)"
     assert bench._kernel3_label(k3) == ("d3q27", "f16s")
+    assert bench._kernel3_label(k3.replace("true, 0>", "true, 2>")) == ("d3q27", "f16s")  # an in-place step
     assert bench._kernel3_label(k3.replace("false, false", "true, false")) is None
     assert bench._kernel_label("void lbm::(anonymous namespace)::macros_kernel<2>(lbm::MacroArgs)") is None
 
