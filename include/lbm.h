@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 7
+#define LBM_ABI_VERSION 8
 
 enum lbm_status {
     LBM_OK = 0,
@@ -153,13 +153,24 @@ int lbm_init(lbm_ctx **ctx, int32_t n_inst, const lbm_params *p, const lbm_field
  *         velocity is replaced with lbm_set_velocity.
  * S, dSdt: host arrays [n_inst] of device FP64 [ny][nx] source S and its time derivative, held
  *         constant over this call's steps, or NULL (both) for no source.  An entry may be NULL for an
- *         instance without a source; dSdt entries may be NULL (zero derivative). */
+ *         instance without a source; dSdt entries may be NULL (zero derivative).
+ * If a launch fails (LBM_E_HIP), the step counters include only the steps enqueued in full before
+ * the failure, and the populations of an instance are unspecified from then on (reload a state with
+ * lbm_state_load). */
 int lbm_step(lbm_ctx *ctx, int32_t nsteps, const double *const *ux, const double *const *uy,
              const double *const *S, const double *const *dSdt);
 
 /* Replaces the velocity of instance inst from the next step on (device FP64 fields in the layout of
  * lbm_fields; uz required on 3D lattices, ignored on D2Q9).  Asynchronous (stream order). */
 int lbm_set_velocity(lbm_ctx *ctx, int32_t inst, const double *ux, const double *uy, const double *uz);
+
+/* Replaces the diffusion field kappa(x) of instance inst from the next step on (device FP64, layout of
+ * lbm_fields; tau1 = 1/2 + kappa / (c_s^2 dt) per node, Sec. 2.4).  The instance must have been created
+ * with a D field (LBM_E_STATE otherwise: a constant-D instance keeps no per-node field).  Synchronizes
+ * the stream to check the values: LBM_E_ARG if one is not finite and > 0, after which the instance's
+ * D is unspecified until a successful call.  With lbm_state_load this lets one context run the
+ * forward passes of a gradient loop over D without a new lbm_init per pass. */
+int lbm_set_diffusion(lbm_ctx *ctx, int32_t inst, const double *D);
 
 /* Dirichlet values of an LBM_BC_NEE or LBM_BC_WALLS instance: phi_b (device FP64 [ny][nx], copied;
  * only its boundary entries take effect: the edge nodes for NEE, rows 0 and ny - 1 as the bottom and
@@ -288,6 +299,16 @@ int lbm_adjoint_seed(lbm_ctx *ctx, int32_t inst, const double *dLdphi, void *lam
 int lbm_adjoint_step(lbm_ctx *ctx, int32_t inst, const void *state, const void *lam_in, void *lam_out,
                      double *dLdD);
 
+/* The backward pass over one checkpoint segment of nsteps >= 1 steps, enqueued by the library in one
+ * call.  states: device buffer of nsteps state images (lbm_state_bytes each, consecutive); image 0
+ * must hold g^{t0} (a checkpoint copied there by the caller).  The call first recomputes images
+ * 1 .. nsteps - 1 (image j + 1 = one step of image j, with the instance's current u, D and source;
+ * the context's own state is not touched), then applies nsteps adjoint steps (lbm_adjoint_step) from
+ * lam = dL/dg^{t0 + nsteps} down to dL/dg^{t0}, which it writes back into lam; lam_tmp (same size,
+ * must not alias lam) is scratch.  dLdD accumulates as in lbm_adjoint_step.  Asynchronous. */
+int lbm_adjoint_segment(lbm_ctx *ctx, int32_t inst, void *states, int32_t nsteps, void *lam, void *lam_tmp,
+                        double *dLdD);
+
 /* dLdphi0(x) = sum_i lam0_i(x) dg_eq_i/dphi0(x): the adjoint of the initial condition
  * g = g_eq(phi0, u).  dLdphi0: device FP64 [ny][nx] (overwritten). */
 int lbm_adjoint_init(lbm_ctx *ctx, int32_t inst, const void *lam0, double *dLdphi0);
@@ -296,6 +317,10 @@ int lbm_adjoint_init(lbm_ctx *ctx, int32_t inst, const void *lam0, double *dLdph
  * `stream`: 16-byte non-temporal vector loads and stores, one pass.  Not part of the method: it is
  * the reference kernel against which achievable HBM bandwidth and traffic counters are calibrated. */
 int lbm_bench_copy(void *dst, const void *src, size_t bytes, void *stream);
+/* The same copy with the default cache policy for loads and stores: buffers that together fit in
+ * the 256 MiB Infinity Cache stay resident across repeated calls, so it calibrates the rate that a
+ * step whose state is held in that cache can reach.  Same arguments and errors. */
+int lbm_bench_copy_cached(void *dst, const void *src, size_t bytes, void *stream);
 
 /* Synchronizes the context's stream and releases everything the library allocated (never caller
  * memory).  NULL is accepted. */

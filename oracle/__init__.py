@@ -27,27 +27,41 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _SRC3 = os.path.join(_HERE, "lbm_oracle_3d.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
+_LIB_OMP = os.path.join(_HERE, "liblbm_oracle_omp.so")
 
 AUX_LOCAL, AUX_FLUX, AUX_NONE = 0, 1, 2
 BC_PERIODIC, BC_NEE, BC_WALLS = 0, 1, 2
 
 
+_CFLAGS = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-Wall"]
+
+
+def _stale(lib: str) -> bool:
+    return not os.path.exists(lib) or os.path.getmtime(lib) < max(os.path.getmtime(_SRC), os.path.getmtime(_SRC3))
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle (both builds) into one shared object; returns its path."""
-    if (not force and os.path.exists(_LIB)
-            and os.path.getmtime(_LIB) >= max(os.path.getmtime(_SRC), os.path.getmtime(_SRC3))):
-        return _LIB
-    objs = []
-    for tag, src, extra in (("r", _SRC, []), ("z", _SRC, ["-DORC_COMPLEX"]), ("3", _SRC3, [])):
-        obj = os.path.join(_HERE, f"_lbm_oracle_{tag}.o")
-        subprocess.run(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                        "-Wall", "-c", src, "-o", obj] + extra, check=True)
-        objs.append(obj)
-    tmp = _LIB + ".tmp"
-    subprocess.run(["gcc", "-shared", "-o", tmp] + objs + ["-lm"], check=True)
-    os.replace(tmp, _LIB)
-    for o in objs:
-        os.remove(o)
+    """Compile the oracle into its shared objects; returns the path of the main one.
+
+    ``liblbm_oracle.so`` holds the FP64 build, the complex-step build and the 3D oracle, all
+    single-threaded.  ``liblbm_oracle_omp.so`` is the FP64 D2Q9 source compiled once more with
+    ``-fopenmp`` (rows of a step split over host threads; bitwise the same results), used only to time
+    the oracle on every host core and to write stored expected values of large cases."""
+    if force or _stale(_LIB):
+        objs = []
+        for tag, src, extra in (("r", _SRC, []), ("z", _SRC, ["-DORC_COMPLEX"]), ("3", _SRC3, [])):
+            obj = os.path.join(_HERE, f"_lbm_oracle_{tag}.o")
+            subprocess.run(_CFLAGS + ["-c", src, "-o", obj] + extra, check=True)
+            objs.append(obj)
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-shared", "-o", tmp] + objs + ["-lm"], check=True)
+        os.replace(tmp, _LIB)
+        for o in objs:
+            os.remove(o)
+    if force or _stale(_LIB_OMP):
+        tmp = _LIB_OMP + ".tmp"
+        subprocess.run(_CFLAGS + ["-fopenmp", "-shared", _SRC, "-o", tmp, "-lm"], check=True)
+        os.replace(tmp, _LIB_OMP)
     return _LIB
 
 
@@ -151,6 +165,39 @@ def collide_mrt(g, ux: float, uy: float, tau1: float, tau2: float, tau3: float, 
     out = np.zeros(9)
     _load().orc_collide_mrt(_ptr(g), ux, uy, tau1, tau2, tau3, c, _ptr(out))
     return out
+
+
+_lib_omp = None
+
+
+def _load_omp():
+    global _lib_omp
+    if _lib_omp is None:
+        build()
+        lib = ctypes.CDLL(_LIB_OMP)
+        P = ctypes.c_void_p
+        lib.orc_run.argtypes = [P, P, ctypes.c_int, P, P, P, P, P, P, P]
+        lib.orc_threads.argtypes = [ctypes.c_int]
+        lib.orc_threads.restype = ctypes.c_int
+        _lib_omp = lib
+    return _lib_omp
+
+
+def run_threads(p: Problem, g, nsteps: int, ux, uy, D=None, S=None, dSdt=None, threads: int = 0):
+    """``run`` (FP64, no walls) on ``threads`` host threads (0: every core OpenMP sees), through the
+    OpenMP build of the same source; returns (final populations, threads used).  Bitwise equal to
+    ``run``."""
+    lib = _load_omp()
+    used = lib.orc_threads(int(threads))
+    g = np.array(g, dtype=np.float64, copy=True, order="C")
+    ux, uy, D, S, dSdt = _fields(p, ux, uy, D, S, dSdt, False)
+    if p.boundary == BC_WALLS:
+        raise ValueError("run_threads covers lattices without walls")
+    work = np.empty_like(g)
+    pc = p._c()
+    lib.orc_run(ctypes.byref(pc), _ptr(g), int(nsteps), _ptr(ux), _ptr(uy), _ptr(D), _ptr(S), _ptr(dSdt),
+                None, _ptr(work))
+    return g, used
 
 
 def relaxation(kappa: float, dx: float, dt: float, lam: float):

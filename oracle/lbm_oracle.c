@@ -17,6 +17,12 @@
  * complex-step derivative of the same code (Squire & Trapp, SIAM Review 1998): perturbing an input
  * by i*h gives d(output)/d(input) = Im(output)/h with no cancellation error.  Nothing else differs.
  *
+ * The real build is also compiled a third time with -fopenmp (symbols unchanged, in their own
+ * shared object): the node loop of a step is then split over host threads by rows.  Every node is
+ * still evaluated by the same statements in the same order, and every destination is written by
+ * exactly one node, so the results are bitwise those of one thread; that build exists only to time
+ * the oracle on all host cores and to produce stored expected values of large cases.
+ *
  * Readings where the paper is silent (each is listed in the design notes of the repository):
  *   - D2Q9 velocity order (the paper lists the set only): 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0)
  *     4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1), times c.
@@ -37,6 +43,12 @@
  */
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#define ORC_ROWS_PARALLEL _Pragma("omp parallel for schedule(static)")
+#else
+#define ORC_ROWS_PARALLEL
+#endif
 
 #ifdef ORC_COMPLEX
 #include <complex.h>
@@ -228,6 +240,7 @@ void ORC(step)(const orc_problem *p, const real *g_in, real *g_out, const real *
         ORC(phi)(p, g_in, phi_all);
     }
 
+    ORC_ROWS_PARALLEL
     for (int y = 0; y < ny; ++y) {
         for (int x = 0; x < nx; ++x) {
             const size_t n = (size_t)y * nx + x;
@@ -348,6 +361,21 @@ void ORC(apply_nee)(const orc_problem *p, real *g, const real *ux, const real *u
         }
     }
 }
+
+#ifndef ORC_COMPLEX
+/* Host threads used by the row loop of a step in the OpenMP build (1 in the others); returns the
+ * number in effect. */
+int orc_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+#endif
 
 /* nsteps repeated steps on g (in place); work holds 9*nx*ny values of scratch. */
 void ORC(run)(const orc_problem *p, real *g, int nsteps, const real *ux, const real *uy,

@@ -91,9 +91,17 @@ def simulate(D: torch.Tensor, spec: RunSpec) -> torch.Tensor:
 
 
 def bspline_operator(n_nodes: int, n_ctrl: int, device="cuda") -> torch.Tensor:
-    """Periodic uniform cubic B-spline basis matrix [n_nodes, n_ctrl] as a torch tensor."""
-    import workloads as W
-    return torch.from_numpy(W.bspline_matrix(n_nodes, n_ctrl)).to(device)
+    """Periodic uniform cubic B-spline basis matrix [n_nodes, n_ctrl] (FP64): entry (j, a) is the cubic
+    B-spline b3(t) at t = j n_ctrl / n_nodes - a, wrapped to the period n_ctrl, with
+    b3(t) = (4 - 6|t|^2 + 3|t|^3)/6 for |t| < 1, (2 - |t|)^3/6 for 1 <= |t| < 2, else 0.  Every row
+    is a partition of unity with positive weights, so a positive theta gives a positive D."""
+    t = (torch.arange(n_nodes, dtype=torch.float64, device=device)[:, None] * (n_ctrl / n_nodes)
+         - torch.arange(n_ctrl, dtype=torch.float64, device=device)[None, :])
+    t = torch.remainder(t + n_ctrl / 2.0, float(n_ctrl)) - n_ctrl / 2.0
+    a = t.abs()
+    near = (4.0 - 6.0 * a * a + 3.0 * a ** 3) / 6.0
+    far = torch.clamp(2.0 - a, min=0.0) ** 3 / 6.0
+    return torch.where(a < 1.0, near, far)
 
 
 def D_from_control(theta: torch.Tensor, By: torch.Tensor, Bx: torch.Tensor) -> torch.Tensor:

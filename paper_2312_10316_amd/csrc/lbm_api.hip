@@ -11,6 +11,7 @@
 #include <functional>
 #include <new>
 #include <queue>
+#include <utility>
 #include <vector>
 
 #include "../../include/lbm.h"
@@ -297,6 +298,7 @@ InstDesc desc_of(const Instance &in)
 // Long runs replay a captured graph of kGraphSteps steps (an even count, so every buffer returns
 // to its role); one graph per buffer parity, dropped whenever a descriptor or the schedule changes.
 constexpr int kGraphSteps = 32;
+static_assert(kGraphSteps % 2 == 0, "a graph replay must keep the buffer parity");
 
 struct lbm_ctx {
     std::vector<Instance> inst;
@@ -485,6 +487,9 @@ int graph_for(lbm_ctx *c, hipGraphExec_t *out)
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     int rc = LBM_OK;
     for (int t = 0; t < kGraphSteps && rc == LBM_OK; ++t) rc = enqueue_step(c, c->capture);
+    // Capturing runs nothing: the buffer parity is the one the graph starts from, on every path out
+    // (a failed capture may have flipped it an odd number of times).
+    c->parity = par;
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(c->capture, &g);
     if (rc != LBM_OK) {
@@ -732,22 +737,27 @@ int lbm_step(lbm_ctx *c, int32_t nsteps, const double *const *ux, const double *
     }
     if (rc == LBM_OK && changed) rc = refresh_tables(c);
     if (rc) return rc;
+    // The step counters advance by the steps actually enqueued, also when a launch fails part-way
+    // (graph replays keep the buffer parity: a graph holds an even number of steps).
     int left = nsteps;
+    auto account = [&](int status) {
+        for (Instance &in : c->inst) in.step += nsteps - left;
+        return status;
+    };
     if (left >= 2 * kGraphSteps) {
         hipGraphExec_t x = nullptr;
         rc = graph_for(c, &x);
         if (rc) return rc;
         for (; left >= kGraphSteps; left -= kGraphSteps) {
             hipError_t e = hipGraphLaunch(x, c->stream);
-            if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+            if (e != hipSuccess) return account(hip_fail(e, "hipGraphLaunch"));
         }
     }
     for (; left > 0; --left) {
         rc = enqueue_step(c, c->stream);
-        if (rc) return rc;
+        if (rc) return account(rc);
     }
-    for (Instance &in : c->inst) in.step += nsteps;
-    return LBM_OK;
+    return account(LBM_OK);
 }
 
 int lbm_macros(lbm_ctx *c, int32_t inst, double *phi_out, const double *ref, lbm_stats *out)
@@ -975,18 +985,13 @@ int lbm_adjoint_seed(lbm_ctx *c, int32_t inst, const double *dLdphi, void *lam)
     return e == hipSuccess ? LBM_OK : hip_fail(e, "adjoint seed kernel launch");
 }
 
-int lbm_adjoint_step(lbm_ctx *c, int32_t inst, const void *state, const void *lam_in, void *lam_out, double *dLdD)
+namespace {
+AdjArgs adj_args(const Instance &in, double *dLdD)
 {
-    g_err[0] = 0;
-    int rc = adjoint_ok(c, inst, "lbm_adjoint_step");
-    if (rc) return rc;
-    if (!state || !lam_in || !lam_out || !dLdD) return fail(LBM_E_ARG, "lbm_adjoint_step: NULL pointer");
-    if (lam_in == lam_out) return fail(LBM_E_ARG, "lbm_adjoint_step: lam_in and lam_out must not alias");
-    const Instance &in = c->inst[inst];
     AdjArgs a;
-    a.state = state;
-    a.lam_in = lam_in;
-    a.lam_out = lam_out;
+    a.state = nullptr;
+    a.lam_in = nullptr;
+    a.lam_out = nullptr;
     a.u = in.u;
     a.k = in.has_D ? in.k : nullptr;
     a.s = in.has_src ? in.s : nullptr;
@@ -996,8 +1001,65 @@ int lbm_adjoint_step(lbm_ctx *c, int32_t inst, const void *state, const void *la
     a.dk_dD = 3.0 * in.p.dt / (in.p.dx * in.p.dx);
     a.f16 = in.f16;
     a.grad = dLdD;
-    hipError_t e = launch_adjoint(in.mode, in.p.aux, a, c->stream);
+    return a;
+}
+}  // namespace
+
+int lbm_adjoint_step(lbm_ctx *c, int32_t inst, const void *state, const void *lam_in, void *lam_out, double *dLdD)
+{
+    g_err[0] = 0;
+    int rc = adjoint_ok(c, inst, "lbm_adjoint_step");
+    if (rc) return rc;
+    if (!state || !lam_in || !lam_out || !dLdD) return fail(LBM_E_ARG, "lbm_adjoint_step: NULL pointer");
+    if (lam_in == lam_out) return fail(LBM_E_ARG, "lbm_adjoint_step: lam_in and lam_out must not alias");
+    AdjArgs a = adj_args(c->inst[inst], dLdD);
+    a.state = state;
+    a.lam_in = lam_in;
+    a.lam_out = lam_out;
+    hipError_t e = launch_adjoint(c->inst[inst].mode, c->inst[inst].p.aux, a, c->stream);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "adjoint kernel launch");
+}
+
+int lbm_adjoint_segment(lbm_ctx *c, int32_t inst, void *states, int32_t nsteps, void *lam, void *lam_tmp, double *dLdD)
+{
+    g_err[0] = 0;
+    int rc = adjoint_ok(c, inst, "lbm_adjoint_segment");
+    if (rc) return rc;
+    if (!states || !lam || !lam_tmp || !dLdD) return fail(LBM_E_ARG, "lbm_adjoint_segment: NULL pointer");
+    if (nsteps < 1) return fail(LBM_E_ARG, "lbm_adjoint_segment: nsteps must be >= 1");
+    if (lam == lam_tmp) return fail(LBM_E_ARG, "lbm_adjoint_segment: lam and lam_tmp must not alias");
+    const Instance &in = c->inst[inst];
+    const size_t sb = pops_bytes(in.p);
+    char *img = static_cast<char *>(states);
+    // Recomputation: image j + 1 = one step of image j, image to image with two buffers whatever the
+    // context's own store kind (state images are always in the two-buffer layout).
+    StepArgs a;
+    a.d = c->h_desc[inst];
+    if (a.d.lc.stores == 2) a.d.lc.stores = 1;
+    a.parity = 0;
+    for (int32_t j = 0; j + 1 < nsteps; ++j) {
+        a.d.buf[0] = img + (size_t)j * sb;
+        a.d.buf[1] = img + (size_t)(j + 1) * sb;
+        hipError_t e = launch_step(in.mode, in.p.aux, a, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "step kernel launch (adjoint segment)");
+    }
+    // Reverse sweep: dL/dg^{j} from dL/dg^{j+1}, j = nsteps - 1 .. 0, alternating the two arrays.
+    AdjArgs g = adj_args(in, dLdD);
+    void *cur = lam, *nxt = lam_tmp;
+    for (int32_t j = nsteps - 1; j >= 0; --j) {
+        g.state = img + (size_t)j * sb;
+        g.lam_in = cur;
+        g.lam_out = nxt;
+        hipError_t e = launch_adjoint(in.mode, in.p.aux, g, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "adjoint kernel launch (adjoint segment)");
+        std::swap(cur, nxt);
+    }
+    if (cur != lam) {
+        hipError_t e = hipMemcpyAsync(lam, cur, (size_t)pop_elems(in.L) * math_bytes(in.mode), hipMemcpyDeviceToDevice,
+                                      c->stream);
+        if (e != hipSuccess) return hip_fail(e, "lbm_adjoint_segment: copying the result");
+    }
+    return LBM_OK;
 }
 
 int lbm_adjoint_init(lbm_ctx *c, int32_t inst, const void *lam0, double *dLdphi0)
@@ -1011,15 +1073,47 @@ int lbm_adjoint_init(lbm_ctx *c, int32_t inst, const void *lam0, double *dLdphi0
     return e == hipSuccess ? LBM_OK : hip_fail(e, "adjoint init kernel launch");
 }
 
-int lbm_bench_copy(void *dst, const void *src, size_t bytes, void *stream)
+namespace {
+int bench_copy(void *dst, const void *src, size_t bytes, void *stream, bool cached, const char *who)
 {
     g_err[0] = 0;
-    if (!dst || !src) return fail(LBM_E_ARG, "lbm_bench_copy: NULL pointer");
+    if (!dst || !src) return fail(LBM_E_ARG, "%s: NULL pointer", who);
     if (bytes % 16 || (uintptr_t)dst % 16 || (uintptr_t)src % 16)
-        return fail(LBM_E_ARG, "lbm_bench_copy: bytes and pointers must be multiples of 16");
-    if (bytes / 16 > (size_t)UINT32_MAX * 256) return fail(LBM_E_ARG, "lbm_bench_copy: too large");
-    hipError_t e = launch_copy(dst, src, bytes, static_cast<hipStream_t>(stream));
+        return fail(LBM_E_ARG, "%s: bytes and pointers must be multiples of 16", who);
+    if (bytes / 16 > (size_t)UINT32_MAX * 256) return fail(LBM_E_ARG, "%s: too large", who);
+    hipError_t e = launch_copy(dst, src, bytes, cached, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? LBM_OK : hip_fail(e, "copy kernel launch");
+}
+}  // namespace
+
+int lbm_bench_copy(void *dst, const void *src, size_t bytes, void *stream)
+{
+    return bench_copy(dst, src, bytes, stream, false, "lbm_bench_copy");
+}
+
+int lbm_bench_copy_cached(void *dst, const void *src, size_t bytes, void *stream)
+{
+    return bench_copy(dst, src, bytes, stream, true, "lbm_bench_copy_cached");
+}
+
+int lbm_set_diffusion(lbm_ctx *c, int32_t inst, const double *D)
+{
+    g_err[0] = 0;
+    if (!check_inst(c, inst)) return fail(LBM_E_STATE, "lbm_set_diffusion: bad context or instance %d", inst);
+    if (!D) return fail(LBM_E_ARG, "lbm_set_diffusion: D is NULL");
+    Instance &in = c->inst[inst];
+    if (!in.has_D) return fail(LBM_E_STATE, "lbm_set_diffusion: instance %d was created with a constant D", inst);
+    hipError_t e = hipMemsetAsync(c->flag + 1, 0, sizeof(int), c->stream);
+    if (e != hipSuccess) return hip_fail(e, "lbm_set_diffusion: clearing the range flag");
+    // k = tau1 - 1/2 = kappa / (cs^2 dt) = 3 kappa dt / dx^2, as at lbm_init
+    int rc = prep_field(c, in, D, nullptr, 3.0 * in.p.dt / (in.p.dx * in.p.dx), 0.0, in.k, 1);
+    if (rc) return rc;
+    int flag = 0;
+    e = hipMemcpyAsync(&flag, c->flag + 1, sizeof flag, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "lbm_set_diffusion: synchronizing");
+    if (flag) return fail(LBM_E_ARG, "lbm_set_diffusion: D has a value that is not finite and > 0");
+    return LBM_OK;
 }
 
 int lbm_free(lbm_ctx *c)

@@ -198,7 +198,7 @@ hipError_t launch_populations(int mode, const PopArgs &a, hipStream_t st);
 // D2Q9 state images between the standard layout and the one-buffer layout after a streaming step
 // (either way: the map is its own inverse); src and dst must differ.
 hipError_t launch_relayout(size_t elem_bytes, const void *src, void *dst, const Layout &L, hipStream_t st);
-hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, bool cached, hipStream_t st);
 hipError_t launch_adjoint(int mode, int aux, const AdjArgs &a, hipStream_t st);
 // D3Q19 and D3Q27 (lbm_kernels3d.hip, chosen by L.q): storage modes F64_F64, F64_F32, F32_F32; aux
 // LOCAL or NONE; periodic.

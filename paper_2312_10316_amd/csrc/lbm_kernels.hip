@@ -634,6 +634,15 @@ __global__ __launch_bounds__(256) void copy_kernel(const f32x4 *__restrict__ src
     if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
+// The same copy with the default cache policy: buffers that fit in the 256 MiB Infinity Cache stay
+// there across repetitions, so it measures the rate a cache-resident step can reach.
+__global__ __launch_bounds__(256) void copy_cached_kernel(const f32x4 *__restrict__ src, f32x4 *__restrict__ dst,
+                                                          int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
 // Between the standard state (slot j of node z holds P_j(z)) and the one-buffer state after its
 // streaming step (P_j(z) in slot opp(j) of node z + e_j): dst[z][j] = src[z + e_j][opp(j)], a map that
 // is its own inverse.  Raw storage elements (E: their size); padding columns are written as zero.
@@ -845,12 +854,15 @@ hipError_t launch_relayout(size_t elem_bytes, const void *src, void *dst, const 
     return hipGetLastError();
 }
 
-hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st)
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, bool cached, hipStream_t st)
 {
     const int64_t n = (int64_t)(bytes / 16);
     if (n == 0) return hipSuccess;
     const int64_t blocks = (n + 255) / 256;
-    copy_kernel<<<(unsigned)blocks, 256, 0, st>>>(static_cast<const f32x4 *>(src), static_cast<f32x4 *>(dst), n);
+    if (cached)
+        copy_cached_kernel<<<(unsigned)blocks, 256, 0, st>>>(static_cast<const f32x4 *>(src), static_cast<f32x4 *>(dst), n);
+    else
+        copy_kernel<<<(unsigned)blocks, 256, 0, st>>>(static_cast<const f32x4 *>(src), static_cast<f32x4 *>(dst), n);
     return hipGetLastError();
 }
 

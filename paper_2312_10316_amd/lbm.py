@@ -75,7 +75,8 @@ LBM_BATCH_SERIAL, LBM_BATCH_FLAT, LBM_BATCH_STRIDED, LBM_BATCH_LPT = 0, 1, 2, 3
 EXPORTS = ["lbm_workspace_size", "lbm_init", "lbm_step", "lbm_set_velocity", "lbm_set_dirichlet", "lbm_macros", "lbm_populations", "lbm_state_bytes",
            "lbm_state_save", "lbm_state_load", "lbm_set_launch", "lbm_get_launch", "lbm_set_batch", "lbm_get_batch",
            "lbm_adjoint_bytes", "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_init", "lbm_bench_copy", "lbm_free",
-           "lbm_pitch", "lbm_last_error", "lbm_abi_version"]
+           "lbm_pitch", "lbm_last_error", "lbm_abi_version", "lbm_set_diffusion", "lbm_adjoint_segment",
+           "lbm_bench_copy_cached"]
 
 
 def pitch_of(p: "lbm_params") -> int:
@@ -111,6 +112,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lbm_adjoint_step.argtypes = [P, I32, P, P, P, P]
     lib.lbm_adjoint_init.argtypes = [P, I32, P, P]
     lib.lbm_bench_copy.argtypes = [P, P, SZ, P]
+    lib.lbm_bench_copy_cached.argtypes = [P, P, SZ, P]
+    lib.lbm_set_diffusion.argtypes = [P, I32, P]
+    lib.lbm_adjoint_segment.argtypes = [P, I32, P, I32, P, P, P]
     lib.lbm_free.argtypes = [P]
     lib.lbm_last_error.argtypes = []
     lib.lbm_last_error.restype = ctypes.c_char_p
@@ -206,6 +210,10 @@ def lbm_set_velocity(ctx, inst: int, ux: torch.Tensor, uy: torch.Tensor, uz: Opt
     _check(lib().lbm_set_velocity(ctx, int(inst), _dptr(ux), _dptr(uy), _dptr(uz)))
 
 
+def lbm_set_diffusion(ctx, inst: int, D: torch.Tensor) -> None:
+    _check(lib().lbm_set_diffusion(ctx, int(inst), _dptr(D)))
+
+
 def lbm_set_dirichlet(ctx, inst: int, phi_b: torch.Tensor) -> None:
     _check(lib().lbm_set_dirichlet(ctx, int(inst), _dptr(phi_b)))
 
@@ -279,6 +287,12 @@ def lbm_adjoint_step(ctx, inst: int, state: torch.Tensor, lam_in: torch.Tensor, 
                                   _dptr(lam_out, lam_out.dtype), _dptr(dLdD)))
 
 
+def lbm_adjoint_segment(ctx, inst: int, states: torch.Tensor, nsteps: int, lam: torch.Tensor, lam_tmp: torch.Tensor,
+                        dLdD: torch.Tensor) -> None:
+    _check(lib().lbm_adjoint_segment(ctx, int(inst), _dptr(states, states.dtype), int(nsteps), _dptr(lam, lam.dtype),
+                                     _dptr(lam_tmp, lam_tmp.dtype), _dptr(dLdD)))
+
+
 def lbm_adjoint_init(ctx, inst: int, lam0: torch.Tensor, dLdphi0: torch.Tensor) -> None:
     _check(lib().lbm_adjoint_init(ctx, int(inst), _dptr(lam0, lam0.dtype), _dptr(dLdphi0)))
 
@@ -289,6 +303,14 @@ def lbm_bench_copy(dst: torch.Tensor, src: torch.Tensor, stream: Optional[torch.
         raise ValueError("dst smaller than src")
     s = (stream or torch.cuda.current_stream()).cuda_stream
     _check(lib().lbm_bench_copy(dst.data_ptr(), src.data_ptr(), n, s))
+
+
+def lbm_bench_copy_cached(dst: torch.Tensor, src: torch.Tensor, stream: Optional[torch.cuda.Stream] = None) -> None:
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < n:
+        raise ValueError("dst smaller than src")
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    _check(lib().lbm_bench_copy_cached(dst.data_ptr(), src.data_ptr(), n, s))
 
 
 def lbm_free(ctx) -> None:

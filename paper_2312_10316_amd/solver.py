@@ -39,6 +39,9 @@ class Solver:
         self._keep_u = (ux, uy, uz)
         L.lbm_set_velocity(self.ctx, inst, ux, uy, uz)
 
+    def set_diffusion(self, D: torch.Tensor, inst: int = 0) -> None:
+        L.lbm_set_diffusion(self.ctx, inst, D)
+
     def set_dirichlet(self, phi_b: torch.Tensor, inst: int = 0) -> None:
         self._keep_bc = phi_b
         L.lbm_set_dirichlet(self.ctx, inst, phi_b)

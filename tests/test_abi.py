@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True, check=True).stdout
     exported = set(re.findall(r" T (lbm_\w+)$", out, flags=re.M))
     assert set(declared_functions()) <= exported
-    assert L.lbm_abi_version() == 7
+    assert L.lbm_abi_version() == 8
 
 
 def test_struct_layout_matches_header(tmp_path):
@@ -158,3 +158,7 @@ def test_null_context_calls_fail_cleanly():
     assert lib.lbm_macros(None, 0, None, None, ctypes.byref(st)) == L.LBM_E_STATE
     assert "bad context" in L.lbm_last_error()
     assert lib.lbm_init(None, 1, None, None, None, 0, None) == L.LBM_E_ARG
+    assert lib.lbm_set_diffusion(None, 0, None) == L.LBM_E_STATE
+    assert lib.lbm_adjoint_segment(None, 0, None, 1, None, None, None) == L.LBM_E_STATE
+    assert lib.lbm_bench_copy_cached(None, None, 16, None) == L.LBM_E_ARG
+    assert lib.lbm_bench_copy_cached(16, 16, 8, None) == L.LBM_E_ARG  # bytes not a multiple of 16

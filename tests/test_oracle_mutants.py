@@ -84,6 +84,21 @@ MUTANTS_3D = [
      "1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 216.0,\n                               1.0 / 54.0"),
 ]
 
+# the diagnostics written out in the oracle's Python layer
+MUTANTS_PY = [
+    ("L2 error without square root", "return math.sqrt(math.fsum((d * d).tolist()) / math.fsum((r * r).tolist()))",
+     "return math.fsum((d * d).tolist()) / math.fsum((r * r).tolist())"),
+    ("L2 error normalised by the numerical field", "r = np.asarray(phi_ref, np.float64).ravel()",
+     "r = np.asarray(phi_num, np.float64).ravel()"),
+    ("max error without absolute value",
+     "return float(np.max(np.abs(np.asarray(phi_num, np.float64) - np.asarray(phi_ref, np.float64))))",
+     "return float(np.max(np.asarray(phi_num, np.float64) - np.asarray(phi_ref, np.float64)))"),
+    ("RMS error node count", "return math.sqrt(math.fsum((d * d).tolist()) / d.size)",
+     "return math.sqrt(math.fsum((d * d).tolist()) / (d.size - 1))"),
+    ("mass by a plain float sum", "return math.fsum(np.asarray(phi_field, dtype=np.float64).ravel().tolist())",
+     "return float(np.asarray(phi_field, dtype=np.float64).ravel().sum())"),
+]
+
 _PLUGIN = '''
 import importlib.util, os, sys
 spec = importlib.util.spec_from_file_location("oracle", os.environ["MUTANT_ORACLE"])
@@ -117,3 +132,8 @@ def test_mutant_is_caught(name, old, new, tmp_path):
 @pytest.mark.parametrize("name,old,new", MUTANTS_3D, ids=[m[0] for m in MUTANTS_3D])
 def test_3d_mutant_is_caught(name, old, new, tmp_path):
     _run_mutant(name, old, new, tmp_path, "lbm_oracle_3d.c", PINS_3D)
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS_PY, ids=[m[0] for m in MUTANTS_PY])
+def test_diagnostics_mutant_is_caught(name, old, new, tmp_path):
+    _run_mutant(name, old, new, tmp_path, "__init__.py", PINS)

@@ -51,6 +51,32 @@ def test_lattice_isotropy():
                     assert abs((w * e[a] * e[b] * e[g] * e[d]).sum() - want) < 1e-12
 
 
+# ---- diagnostics: the error norms and mass written out (Sec. 3, Eq. (33)) ----------------------
+
+def test_error_norms_closed_form():
+    """Integer fields whose error norms are exact: the difference d = phi_num - phi_ref has
+    ||d||_2 = 5 with its largest magnitude (4) on a negative entry, ||phi_ref||_2 = 13, and
+    ||phi_num||_2^2 = 178, so a norm taken over phi_num, a dropped square root, a signed maximum or a
+    wrong node count gives a different number."""
+    ref = np.array([[3.0, 0.0, 4.0], [0.0, 12.0, 0.0]])
+    d = np.array([[-4.0, 2.0, 1.0], [2.0, 0.0, 0.0]])
+    num = ref + d
+    assert O.l2_rel_error(num, ref) == 5.0 / 13.0
+    assert O.max_abs_error(num, ref) == 4.0
+    assert O.rms_error(num, ref) == math.sqrt(25.0 / 6.0)
+    assert O.mass(num) == 20.0
+    # the same pair swapped: the norm is taken over the second argument, the maximum is symmetric
+    assert O.l2_rel_error(ref, num) == 5.0 / math.sqrt(178.0)
+    assert O.max_abs_error(ref, num) == 4.0
+    # a field equal to its reference has zero error; a zero field has relative error 1
+    assert O.l2_rel_error(ref, ref) == 0.0 and O.max_abs_error(ref, ref) == 0.0
+    assert O.l2_rel_error(np.zeros_like(ref), ref) == 1.0
+    # correctly rounded sums: cancelling magnitudes that a naive float sum loses
+    big = np.array([1e16, 1.0, -1e16, 1.0])
+    assert O.mass(big) == 2.0
+    assert O.l2_rel_error(np.array([1e8 + 3.0, 4.0]), np.array([1e8, 0.0])) == 5.0 / 1e8
+
+
 # ---- P2: equilibrium moments (Sec. 2.2, Eq. (6)) ----------------------------------------------
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
@@ -570,3 +596,19 @@ def test_rotating_pulse_closed_form_second_order():
 
 
 # ---- Dirichlet edges by non-equilibrium extrapolation (the boundary scheme of Sec. 3) ----------
+
+
+def test_threaded_oracle_is_bitwise_the_serial_one():
+    """The OpenMP build (rows of a step over host threads), used for the all-cores CPU baseline and
+    for stored expected values of large cases, gives exactly the single-threaded results."""
+    cfg = W.PulseConfig(N=48, steps=12, D_variable=True)
+    f = W.rotating_pulse(cfg)
+    rng = np.random.default_rng(7)
+    S = 0.1 * rng.uniform(-1, 1, (48, 48))
+    for aux in (O.AUX_LOCAL, O.AUX_FLUX):
+        p = O.Problem(48, 48, f["dx"], f["dt"], cfg.lam, cfg.D, aux)
+        g0 = O.init(p, f["phi0"], f["ux"], f["uy"])
+        a = O.run(p, g0, cfg.steps, f["ux"], f["uy"], D=f["D"], S=S, dSdt=-S)
+        b, used = O.run_threads(p, g0, cfg.steps, f["ux"], f["uy"], D=f["D"], S=S, dSdt=-S, threads=4)
+        assert used == 4
+        assert np.array_equal(a, b)
