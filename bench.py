@@ -35,9 +35,22 @@ def bytes_per_lup(mode: str, variable_D: bool) -> int:
     return 18 * STORE_BYTES[mode] + 2 * FIELD_BYTES[mode] + (FIELD_BYTES[mode] if variable_D else 0)
 
 
+def launch_bytes_per_lup(mode: str, variable_D: bool, launch: dict) -> float:
+    """Algorithmic bytes per lattice update of the launch that ran: a launch of two fused steps reads
+    the state and the fields once and writes the state once for two updates of every node."""
+    return bytes_per_lup(mode, variable_D) / max(int(launch.get("fuse", 1) or 1), 1)
+
+
+def roofline_bound(stores: int) -> str:
+    """What bounds a step by where its state lives: streamed to HBM (non-temporal stores, lbm_launch
+    stores 0), or held in the 256 MiB Infinity Cache (cached stores 1, one buffer in place 2)."""
+    return "hbm" if stores == 0 else "infinity_cache"
+
+
 def kernel_hash() -> str:
     h = hashlib.sha256()
-    for name in ("lbm_kernels.hip", "lbm_kernel_common.h", "lbm_device.h", "lbm_internal.h", "lbm_api.hip"):
+    for name in ("lbm_kernels.hip", "lbm_fused.hip", "lbm_kernel_common.h", "lbm_device.h", "lbm_internal.h",
+                 "lbm_api.hip"):
         with open(os.path.join(ROOT, "paper_2312_10316_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -93,17 +106,24 @@ def run_mode(mode, n, steps, warmup, torch, W, lbm, Solver, graph=True):
 
 def run_batched(torch, W, lbm, Solver, n_inst=256, steps=2000, eager_steps=100):
     """The seeded batch of uneven pulse instances (FP32): aggregate MLUPS of serial per-instance
-    launches (eager, and graph-replayed) against the autotuned single-launch batched step."""
+    launches (eager, and graph-replayed) against the autotuned single-launch batched step.  The
+    batched figure is one run of exactly `steps` steps from the initial state; after it every
+    instance's phi is checked (finite or not) and measured against its closed form."""
+    import numpy as np
+
     from paper_2312_10316_amd import autotune
     draws = W.batched_instances(n_inst, steps=steps)
-    insts = []
+    insts, refs = [], []
     for d in draws:
         cfg = d.config
         f = W.rotating_pulse(cfg)
         p = lbm.make_params(cfg.N, cfg.N, f["dx"], f["dt"], cfg.lam, cfg.D, "f32")
         insts.append((p, {k: torch.from_numpy(f[k]).cuda() for k in ("phi0", "ux", "uy")}))
-    nodes = float(sum(d.N * d.N for d in draws))
+        refs.append(torch.from_numpy(W.pulse_reference(cfg, f)).cuda())
+    sizes = np.array([d.N * d.N for d in draws], dtype=np.float64)
+    nodes = float(sizes.sum())
     s = Solver(insts)
+    init = [s.state_save(k) for k in range(n_inst)]
 
     def timed(fn, nsteps):
         torch.cuda.synchronize()
@@ -130,15 +150,33 @@ def run_batched(torch, W, lbm, Solver, n_inst=256, steps=2000, eager_steps=100):
     ms = timed(lambda: s.step(steps), steps)
     out["serial_graph"] = {"ms_per_step": ms, "mlups": nodes / (ms * 1e-3) / 1e6}
     t = autotune.tune(s, steps=64, reps=2)
+    s.step(64)  # captures the graphs of the tuned launch
+    for k in range(n_inst):
+        s.state_load(init[k], 0, inst=k)
     ms = timed(lambda: s.step(steps), steps)
     out["batched"] = {"ms_per_step": ms, "mlups": nodes / (ms * 1e-3) / 1e6,
                       "config": {"rows": t["best"][0], "xcd_remap": t["best"][1], "xcd_rows": t["best"][2],
                                  "tile_width": t["best"][3], "max_waves": t["best"][4], "stores": t["best"][5],
-                                 "policy": ["serial", "flat", "strided", "lpt"][t["best"][6]], "blocks": t["best"][7]}}
+                                 "policy": ["serial", "flat", "strided", "lpt"][t["best"][6]], "blocks": t["best"][7],
+                                 "fuse": t["best"][8]}}
     out["speedup_vs_serial_graph"] = out["serial_graph"]["ms_per_step"] / ms
     out["speedup_vs_serial_eager"] = out["serial_eager"]["ms_per_step"] / ms
-    out["nonfinite_instances"] = sum(1 for k in range(n_inst) if s.macros(k, raise_nonfinite=False)["nonfinite"] > 0)
+    stats = [s.macros(k, ref=refs[k], raise_nonfinite=False) for k in range(n_inst)]
     s.close()
+    finite = np.array([st["nonfinite"] == 0 and st["step"] == steps for st in stats])
+    er = np.array([st["rms_err"] for st in stats])
+    tau1 = np.array([0.5 + 3.0 * d.D * d.config.dt / d.config.dx ** 2 for d in draws])
+    out["accuracy"] = {
+        "finite_instances": int(finite.sum()), "nonfinite_instances": int((~finite).sum()),
+        "E_r_finite": {"min": float(er[finite].min()), "median": float(np.median(er[finite])),
+                       "max": float(er[finite].max())} if finite.any() else None,
+        "E_r_per_instance": [float(e) if ok else None for e, ok in zip(er, finite)],
+        "nonfinite_tau1_minus_half_max": float((tau1[~finite] - 0.5).max()) if (~finite).any() else None,
+        "finite_tau1_minus_half_min": float((tau1[finite] - 0.5).min()) if finite.any() else None,
+        "note": "instances that blow up (Sec. 3's stability criterion) all have small tau1 - 1/2, i.e. small D at "
+                "high cell Peclet number; the finite ones are measured against their closed form",
+    }
+    out["batched"]["mlups_finite_instances"] = float(sizes[finite].sum()) / (ms * 1e-3) / 1e6
     return out
 
 
@@ -151,6 +189,36 @@ def _timed_steps(torch, s, nsteps):
     e1.record(s.stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / max(nsteps, 1)
+
+
+def run_hbm(torch, W, lbm, Solver, n=8192, steps=200, warmup=32, modes=("f32", "f16s", "f64", "f64s_f32m")):
+    """The streaming regime: the rotating pulse (constant D) on a periodic n^2 lattice whose two
+    population buffers (1.2-9.7 GB at 8192^2) far exceed the 256 MiB Infinity Cache, so every step
+    reads and writes HBM.  Per storage mode: MLUPS over `steps` graph-replayed steps (HIP events on
+    the launch stream) and the algorithmic bytes per second against the 8 TB/s HBM peak."""
+    cfg = W.PulseConfig(N=n, steps=steps + warmup)
+    f = W.rotating_pulse(cfg)
+    dev = {k: torch.from_numpy(f[k]).cuda() for k in ("phi0", "ux", "uy")}
+    out = {"workload": f"rotating Gaussian pulse, periodic {n}^2, c=10, U0=pi, D=1e-3 (constant), "
+                       f"{warmup}+{steps} steps", "N": n}
+    for mode in modes:
+        s = Solver([(lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, mode), dev)])
+        s.step(warmup)
+        ms = _timed_steps(torch, s, steps)
+        launch = s.get_launch()
+        s.close()
+        bpl = launch_bytes_per_lup(mode, False, launch)
+        mlups = n * n / (ms * 1e-3) / 1e6
+        achieved = mlups * bpl / 1e3
+        traffic = traffic_from_profile(mode, n)
+        out[mode] = {"mlups": mlups, "ms_per_step": ms, "bytes_per_lup": bpl, "achieved_gbps": achieved,
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None if traffic is None else round(traffic),
+                     "launch": launch}
+        print(f"# hbm {n}^2 {mode}: {mlups:.0f} MLUPS, {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBPS:.3f})",
+              file=sys.stderr, flush=True)
+    del dev
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_precision_8192(torch, W, lbm, Solver, n=8192, steps=1000):
@@ -166,11 +234,13 @@ def run_precision_8192(torch, W, lbm, Solver, n=8192, steps=1000):
         s.step(64)
         ms = _timed_steps(torch, s, steps - 64)
         st, phi = s.macros(want_phi=True, raise_nonfinite=False)
+        launch = s.get_launch()
         s.close()
+        bpl = launch_bytes_per_lup(mode, True, launch)
         r = {"mlups": n * n / (ms * 1e-3) / 1e6, "ms_per_step": ms,
-             "hbm_gbps_algorithmic": n * n / (ms * 1e-3) * bytes_per_lup(mode, True) / 1e9,
-             "bytes_per_lup": bytes_per_lup(mode, True), "mass_drift": st["mass"] / m0 - 1.0,
-             "nonfinite": st["nonfinite"]}
+             "hbm_gbps_algorithmic": n * n / (ms * 1e-3) * bpl / 1e9,
+             "bytes_per_lup": bpl, "mass_drift": st["mass"] / m0 - 1.0,
+             "nonfinite": st["nonfinite"], "fuse": launch["fuse"]}
         if mode == "f64":
             ref = phi
         else:
@@ -344,7 +414,9 @@ def run_3d(torch, W, lbm, Solver, q=19, sizes=(64, 128, 256), tp_steps=400):
 
 def run_adjoint(torch, W, lbm, Solver):
     """512^2 pulse, 400 steps, FP32 forward with sqrt(T) checkpoints; D on a 32 x 32 bicubic control
-    grid; loss = 1/2 sum (phi_T - phi_target)^2 against the run with D = 1e-3."""
+    grid; loss = 1/2 sum (phi_T - phi_target)^2 against the run with D = 1e-3.  The context is created
+    by a first forward/backward pass; the second pass (same D) is timed: the forward (checkpoints
+    included) and the backward (per segment: recomputation and adjoint steps in one library call)."""
     from paper_2312_10316_amd import adjoint
     cfg = W.PulseConfig(N=W.C5_N, steps=W.C5_STEPS)
     f = W.rotating_pulse(cfg)
@@ -352,62 +424,242 @@ def run_adjoint(torch, W, lbm, Solver):
     mk = lambda mode: adjoint.RunSpec(cfg.N, cfg.N, f["dx"], f["dt"], cfg.lam, dv(f["phi0"]), dv(f["ux"]),
                                       dv(f["uy"]), cfg.steps, mode)
     B = adjoint.bspline_operator(cfg.N, W.C5_CTRL)
+    tspec = mk("f32")
     with torch.no_grad():
-        target = adjoint.simulate(torch.full((cfg.N, cfg.N), cfg.D, dtype=torch.float64, device="cuda"), mk("f32"))
-    theta = dv(W.control_theta(W.C5_CTRL)).requires_grad_(True)
+        target = adjoint.simulate(torch.full((cfg.N, cfg.N), cfg.D, dtype=torch.float64, device="cuda"), tspec)
+    tspec.close()
     spec = mk("f32")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    phi = adjoint.simulate(adjoint.D_from_control(theta, B, B), spec)
-    loss = 0.5 * ((phi - target) ** 2).sum()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    loss.backward()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    return {"N": cfg.N, "steps": cfg.steps, "control_grid": W.C5_CTRL, "checkpoints": spec.stats["checkpoints"],
-            "forward_s": t1 - t0, "backward_s": t2 - t1, "backward_over_forward": (t2 - t1) / (t1 - t0),
-            "loss": float(loss.detach()), "grad_norm": float(theta.grad.norm())}
+    out = {"N": cfg.N, "steps": cfg.steps, "control_grid": W.C5_CTRL}
+    for rep in range(2):
+        theta = dv(W.control_theta(W.C5_CTRL)).requires_grad_(True)
+        D = adjoint.D_from_control(theta, B, B)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phi = adjoint.simulate(D, spec)
+        loss = 0.5 * ((phi - target) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+    spec.close()
+    lups = float(cfg.N) ** 2 * cfg.steps
+    out.update(checkpoints=spec.stats["checkpoints"], segment=spec.stats["segment"],
+               forward_s=t1 - t0, backward_s=t2 - t1, backward_over_forward=(t2 - t1) / (t1 - t0),
+               forward_mlups=lups / (t1 - t0) / 1e6, adjoint_mlups=lups / (t2 - t1) / 1e6,
+               loss=float(loss.detach()), grad_norm=float(theta.grad.norm()),
+               note="timed on the second forward/backward pass of one context (the first creates it); "
+                    "adjoint MLUPS = N^2 x steps / backward seconds, the backward doing one recomputed "
+                    "forward step and one adjoint step per step")
+    return out
 
 
-def copy_bandwidth(torch, lbm, nbytes=2 << 30, reps=20):
-    """Read + write bandwidth of the library's plain streaming copy kernel (2 GiB, one pass)."""
+def run_tau2_sweep(torch, W, lbm, Solver, tau1=0.8, tau2s=(1.0, 1.1, 1.2, 1.3, 1.375, 1.45, 1.5, 1.6, 1.7, 1.8)):
+    """Sec. 3.3: steady diffusion with a uniform source across a channel between halfway
+    anti-bounce-back walls (x periodic, u = 0, FP64): relative RMS error of the converged profile
+    against the exact linear-plus-parabolic one, over the free relaxation time tau2 at tau1 = 0.8.
+    The paper's slip-free relation puts the minimum at tau2 = 3(1 - 4 tau1)/(8(1 - 2 tau1)) = 1.375."""
+    import numpy as np
+    nx, ny, lo, hi, S0 = 64, 24, 0.3, 0.7, 2e-3
+    kappa = (tau1 - 0.5) / 3.0
+    y = np.arange(ny)[:, None] + 0.5
+    exact = lo + (hi - lo) * y / ny + S0 / (2 * kappa) * y * (ny - y)
+    z = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    pb = torch.full((ny, nx), 0.5, dtype=torch.float64, device="cuda")
+    pb[0, :], pb[-1, :] = lo, hi
+    S = torch.full((ny, nx), S0, dtype=torch.float64, device="cuda")
+    errs, steps_used = [], []
+    for tau2 in tau2s:
+        p = lbm.make_params(nx, ny, 1.0, 1.0, (tau1 - 0.5) * (tau2 - 0.5), kappa, "f64", lbm.LBM_AUX_LOCAL,
+                            boundary=lbm.LBM_BC_WALLS)
+        s = Solver([(p, {"phi0": torch.full((ny, nx), 0.5, dtype=torch.float64, device="cuda"), "ux": z, "uy": z})])
+        s.set_dirichlet(pb)
+        prev, n = None, 0
+        while n < 400000:
+            s.step(4096, S=[S])
+            n += 4096
+            _, phi = s.macros(want_phi=True)
+            phi = phi.cpu().numpy()
+            if prev is not None and np.abs(phi - prev).max() < 1e-15:
+                break
+            prev = phi
+        s.close()
+        errs.append(float(np.sqrt(np.mean((phi - exact) ** 2)) / np.abs(exact).max()))
+        steps_used.append(n)
+    k = int(np.argmin(errs))
+    return {"tau1": tau1, "tau2": list(tau2s), "relative_rms_error": errs, "steps_to_converge": steps_used,
+            "argmin_tau2": tau2s[k], "slip_free_tau2_theory": 3 * (1 - 4 * tau1) / (8 * (1 - 2 * tau1)),
+            "channel": f"{nx} x {ny} lattice units, walls at y = -1/2 and {ny} - 1/2, values {lo} and {hi}, "
+                       f"uniform source {S0}"}
+
+
+def copy_bandwidth(torch, lbm, nbytes=2 << 30, reps=20, cached=False):
+    """Read + write bandwidth of the library's plain copy kernel, one pass per call: by default the
+    streaming (non-temporal) copy of 2 GiB, which calibrates HBM; with ``cached`` the default-policy
+    copy, which on buffers that together fit in the 256 MiB Infinity Cache calibrates a step whose
+    state stays in that cache."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     a.fill_(1.0)
-    for _ in range(3):
-        lbm.lbm_bench_copy(b, a)
+    fn = lbm.lbm_bench_copy_cached if cached else lbm.lbm_bench_copy
+    for _ in range(5):
+        fn(b, a)
+        fn(a, b)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        lbm.lbm_bench_copy(b, a)
+        fn(b, a)
+        fn(a, b)
     e1.record()
     torch.cuda.synchronize()
-    return 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    return 2.0 * nbytes * 2 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
-def cpu_baseline(n, budget_s=15.0):
-    """The FP64 oracle (single thread, as it stands) on a bounded sample of the same workload."""
+def cpu_host() -> dict:
+    """The host the oracle is timed on: core counts and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "model": model,
+            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
+
+
+def _oracle_threads(host) -> int:
+    """Threads of the all-cores leg: OMP_NUM_THREADS when set (the host's share), else every usable CPU."""
+    env = host.get("omp_num_threads_env")
+    return int(env) if env and env.isdigit() and int(env) > 0 else int(host["usable_cpus"] or 1)
+
+
+def cpu_baseline(n, budget_s=12.0, cross_check=True, cross_budget_s=150.0):
+    """The FP64 oracle as it stands (plain C, gcc -O2 -ffp-contract=off), timed on this host's cores:
+    single-threaded and with its OpenMP build over all cores (bitwise the same results), on bounded
+    samples of the benchmark workload and on the workloads the oracle is run on in full: the 64^2
+    parity pulse, the Sec. 3 benchmark at N = 100, the 256^2 and 512^2 refinement members, and the
+    1024^2 x 1000-step variable-D cross-check of the precision study.  Returns (json, the oracle's phi
+    of the cross-check or None)."""
+    import numpy as np
+
     import oracle as O
     import workloads as W
-    cfg = W.PulseConfig(N=n, steps=3200)
-    f = W.rotating_pulse(cfg)
-    p = O.Problem(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, O.AUX_LOCAL)
-    g = O.init(p, f["phi0"], f["ux"], f["uy"])
-    steps, t0 = 0, time.perf_counter()
-    while True:
-        g = O.step(p, g, f["ux"], f["uy"])
-        steps += 1
+    host = cpu_host()
+    threads = _oracle_threads(host)
+    legs = []
+
+    def pulse_problem(cfg):
+        f = W.rotating_pulse(cfg)
+        p = O.Problem(cfg.N, cfg.N, f["dx"], cfg.dt, cfg.lam, cfg.D, O.AUX_LOCAL)
+        return f, p, O.init(p, f["phi0"], f["ux"], f["uy"])
+
+    def timed_run(cfg, nsteps, nthreads):
+        f, p, g = pulse_problem(cfg)
+        t0 = time.perf_counter()
+        if nthreads == 1:
+            g = O.run(p, g, nsteps, f["ux"], f["uy"], D=f["D"])
+            used = 1
+        else:
+            g, used = O.run_threads(p, g, nsteps, f["ux"], f["uy"], D=f["D"], threads=nthreads)
         el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 50:
-            break
-    return {"value": n * n * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{n}^2 rotating pulse, {steps} of 3200 steps, FP64 plain C oracle, 1 thread, {el:.1f} s"}
+        return g, p, f, el, used
+
+    # the benchmark workload (2048^2 pulse), bounded samples: one thread, then all cores
+    cfg = W.PulseConfig(N=n, steps=3200)
+    probe = max(1, int(round(2.0e6 / (n * n)))) if n <= 1024 else 1
+    _, _, _, el, _ = timed_run(cfg, probe, 1)
+    k1 = max(1, min(3200, int(budget_s / max(el / probe, 1e-9))))
+    _, _, _, el1, _ = timed_run(cfg, k1, 1)
+    single = {"value": n * n * k1 / el1 / 1e6, "threads": 1, "steps": k1, "seconds": el1}
+    kt = max(1, min(3200, int(budget_s * threads / max(el / probe, 1e-9) / 2)))
+    _, _, _, elt, used = timed_run(cfg, kt, threads)
+    allc = {"value": n * n * kt / elt / 1e6, "threads": used, "steps": kt, "seconds": elt}
+
+    # workloads run in full
+    c1 = W.PulseConfig(N=64, steps=160)
+    g, p, f, el, used = timed_run(c1, c1.steps, 1)
+    legs.append({"workload": "64^2 rotating pulse, 160 steps (t = 0.5)", "threads": used, "seconds": el,
+                 "mlups": 64 * 64 * 160 / el / 1e6,
+                 "E_r": O.rms_error(O.phi(p, g), W.pulse_reference(c1, f))})
+    x1 = W.x1_problem(100, 0.05)
+    p = O.Problem(100, 100, x1["dx"], x1["dt"], x1["lam"], 0.05, O.AUX_LOCAL)
+    g = O.init(p, x1["phi0"], x1["ux"], x1["uy"])
+    t0 = time.perf_counter()
+    for k in range(x1["steps"]):
+        S, dS = x1["source"](k * x1["dt"])
+        g = O.step(p, g, x1["ux"], x1["uy"], None, S, dS)
+    el = time.perf_counter() - t0
+    legs.append({"workload": "Sec. 3 benchmark, periodic proxy N = 100, kappa = 0.05, t = 1 (100 steps, "
+                             "per-step source)", "threads": 1, "seconds": el,
+                 "mlups": 100 * 100 * x1["steps"] / el / 1e6,
+                 "E_r_times_N_over_N_plus_1": O.rms_error(O.phi(p, g), x1["exact"](x1["steps"] * x1["dt"])) * 100 / 101,
+                 "table2_printed": 5.984e-4})
+    for N in (256, 512):
+        cfg = W.refinement(N, "acoustic")
+        g, p, f, el, used = timed_run(cfg, cfg.steps, threads)
+        legs.append({"workload": f"{N}^2 rotating pulse, acoustic refinement member, {cfg.steps} steps (t = 0.3125)",
+                     "threads": used, "seconds": el, "mlups": N * N * cfg.steps / el / 1e6,
+                     "E_r": O.rms_error(O.phi(p, g), W.pulse_reference(cfg, f))})
+    phi_cross = None
+    if cross_check:
+        cfg = W.PulseConfig(N=1024, steps=1000, D_variable=True)
+        rate = allc["value"] * 1e6
+        projected = 1024 * 1024 * cfg.steps / max(rate, 1.0)
+        entry = {"workload": "1024^2 rotating pulse, D(x) = 1e-3 (1 + 0.5 sin(pi x) sin(pi y)), 1000 steps "
+                             "(the precision study's oracle cross-check)", "threads": threads,
+                 "projected_seconds": projected}
+        if projected <= cross_budget_s:
+            g, p, f, el, used = timed_run(cfg, cfg.steps, threads)
+            phi_cross = O.phi(p, g)
+            entry.update(seconds=el, mlups=1024 * 1024 * cfg.steps / el / 1e6, threads=used,
+                         mass=O.mass(phi_cross))
+        else:
+            entry["skipped"] = f"projected {projected:.0f} s > {cross_budget_s:.0f} s on this host"
+        legs.append(entry)
+    out = {"value": allc["value"], "unit": "MLUPS", "cores": allc["threads"], "kind": "oracle",
+           "sample": f"{n}^2 rotating pulse (the benchmark workload), {kt} of 3200 steps, FP64 plain C oracle, "
+                     f"OpenMP over rows on {allc['threads']} threads, {allc['seconds']:.1f} s",
+           "single_thread": {"value": single["value"], "unit": "MLUPS", "cores": 1,
+                             "sample": f"{n}^2 rotating pulse, {k1} of 3200 steps, 1 thread, {single['seconds']:.1f} s"},
+           "host": host, "workloads": legs}
+    return out, phi_cross
+
+
+def oracle_cross_check(torch, W, lbm, Solver, phi_orc):
+    """The GPU storage modes on the precision study's cross-check size (1024^2, 1000 steps, variable
+    D) against the FP64 oracle's phi of the same run (computed in the CPU-baseline leg): max and L2
+    errors, and E_r against the constant-D closed form (context: D varies)."""
+    import numpy as np
+    cfg = W.PulseConfig(N=1024, steps=1000, D_variable=True)
+    f = W.rotating_pulse(cfg)
+    dev = {k: torch.from_numpy(f[k]).cuda() for k in ("phi0", "ux", "uy", "D")}
+    ref = torch.from_numpy(W.pulse_reference(cfg, f)).cuda()
+    orc = torch.from_numpy(np.ascontiguousarray(phi_orc)).cuda()
+    out = {"N": 1024, "steps": 1000, "D": "1e-3 (1 + 0.5 sin(pi x) sin(pi y))"}
+    for mode in ("f64", "f64s_f32m", "f32", "f16s"):
+        s = Solver([(lbm.make_params(1024, 1024, f["dx"], f["dt"], cfg.lam, cfg.D, mode), dev)])
+        s.step(cfg.steps)
+        st, phi = s.macros(ref=ref, want_phi=True, raise_nonfinite=False)
+        s.close()
+        d = (phi - orc).abs()
+        out[mode] = {"max_err_vs_oracle": float(d.max()),
+                     "max_rel_err_vs_oracle": float(d.max() / orc.abs().max()),
+                     "l2_rel_err_vs_oracle": float(torch.sqrt((d * d).sum() / (orc * orc).sum())),
+                     "E_r_vs_constant_D_closed_form": st["rms_err"], "nonfinite": st["nonfinite"]}
+    return out
 
 
 KERNEL_MODES = {"0": "f64", "1": "f64s_f32m", "2": "f32", "3": "f16s"}
+TRACE_STEPS = {2048: 200, 8192: 100}  # timed steps of the kernel-trace runs
 
 
 def _csv_rows(path):
@@ -522,36 +774,62 @@ def _kernel_label(name: str):
                   name)
     if m:
         return ("step", KERNEL_MODES[m.group(1)], int(m.group(2)), m.group(3) == "true", m.group(4) == "true")
+    # two steps per launch: step2_kernel<mode, aux, has_k, has_s, MRT, interior waves, cached stores>
+    m = re.search(r"step2_kernel<(\d), (\d), (true|false), (true|false), false, \d, (?:true|false)>", name)
+    if m:
+        return ("step2", KERNEL_MODES[m.group(1)], int(m.group(2)), m.group(3) == "true", m.group(4) == "true")
     if "copy_kernel" in name:
         return ("copy",)
     return None
 
 
-def summarize_profiles(trace_dir, pmc_dirs, out_dir, command, pmc_commands):
-    """Writes the committed text summaries of rocprofv3 runs: kernel-trace statistics and the
-    FETCH_SIZE / WRITE_SIZE traffic per dispatch, scaled by the copy kernel's reading."""
+def summarize_trace(trace_dir, out_dir, n, command):
+    """Kernel-trace statistics of the D2Q9 step kernels of one run (profiles/step_kernel_trace_<n>.md),
+    with each mode's MLUPS and algorithmic GB/s recomputed from the average kernel duration."""
     os.makedirs(out_dir, exist_ok=True)
-    lines = ["# rocprofv3 kernel trace: TRT-R D2Q9 step kernels, rotating pulse 2048^2", "",
+    lines = [f"# rocprofv3 kernel trace: TRT-R D2Q9 step kernels, rotating pulse {n}^2 (constant D)", "",
              f"Command: `{command}`", "",
-             "| kernel | mode | calls | average (us) | total (ms) |", "|---|---|---|---|---|"]
+             "| kernel | mode | calls | average (us) | total (ms) | MLUPS | algorithmic GB/s | of 8 TB/s |",
+             "|---|---|---|---|---|---|---|---|"]
     stats = _csv_rows(_find(trace_dir, "kernel_stats.csv"))
     per_mode = {}
+
+    def rates(mode, avg_ns, steps=1):
+        """MLUPS and algorithmic GB/s of a launch of `steps` steps over the n^2 lattice (a fused launch
+        moves the state and fields once for two updates of every node)."""
+        if mode == "-":
+            return "", "", ""
+        mlups = steps * float(n) * n / (avg_ns * 1e-9) / 1e6
+        gbps = float(n) * n * bytes_per_lup(mode, False) / (avg_ns * 1e-9) / 1e9
+        return f"{mlups:.0f}", f"{gbps:.0f}", f"{gbps / HBM_PEAK_GBPS:.3f}"
+
     for r in stats:
         lab = _kernel_label(r["Name"])
         if lab is None:
             continue
-        mode = lab[1] if lab[0] == "step" else "-"
-        lines.append(f"| {r['Name'][:80]} | {mode} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
-                     f"{float(r['TotalDurationNs']) / 1e6:.2f} |")
-        if mode != "-":
+        mode = lab[1] if lab[0] in ("step", "step2") else "-"
+        steps = 2 if lab[0] == "step2" else 1
+        avg = float(r["AverageNs"])
+        lines.append(f"| {r['Name'][:80]} | {mode} | {r['Calls']} | {avg / 1e3:.2f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | " + " | ".join(rates(mode, avg, steps)) + " |")
+        if mode != "-" and steps == 1:
             per_mode.setdefault(mode, []).append((int(r["Calls"]), float(r["TotalDurationNs"])))
     for mode, ks in sorted(per_mode.items()):
         if len(ks) > 1:  # a one-buffer instance alternates two kernels: their launches together
             calls, total = sum(k[0] for k in ks), sum(k[1] for k in ks)
             lines.append(f"| all step kernels of the mode (alternating in-place steps) | {mode} | {calls} | "
-                         f"{total / calls / 1e3:.2f} | {total / 1e6:.2f} |")
-    with open(os.path.join(out_dir, "step_kernel_trace_2048.md"), "w") as fh:
+                         f"{total / calls / 1e3:.2f} | {total / 1e6:.2f} | " + " | ".join(rates(mode, total / calls)) + " |")
+    with open(os.path.join(out_dir, f"step_kernel_trace_{n}.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
+
+
+def summarize_profiles(trace_dirs, pmc_dirs, out_dir, commands, pmc_commands):
+    """Writes the committed text summaries of rocprofv3 runs: kernel-trace statistics per lattice size
+    (trace_dirs, commands: {n: ...}) and the FETCH_SIZE / WRITE_SIZE traffic per dispatch, scaled by
+    the copy kernel's reading."""
+    os.makedirs(out_dir, exist_ok=True)
+    for n, d in trace_dirs.items():
+        summarize_trace(d, out_dir, n, commands[n])
 
     entries, calib = {}, {}
     for (counter, n), d in pmc_dirs.items():
@@ -630,13 +908,16 @@ def main():
                                 f"python3 bench.py --profile3d {n3} --steps 100",
                                 [f"rocprofv3 --pmc {c} --output-format csv -d RUNDIR/pmc3_{c.lower()}{sfx} -o pmc -- "
                                  f"python3 bench.py --profile3d {n3} --steps 8" for c in sorted(pmc3)])
-        if not os.path.isdir(os.path.join(d, "trace")):
-            return
+        traces = {n: os.path.join(d, f"trace_{n}") for n in (2048, 8192)}
+        traces = {n: v for n, v in traces.items() if os.path.isdir(v)}
         pmc = {(c, n): os.path.join(d, f"pmc_{c.lower()}_{n}") for c in ("FETCH_SIZE", "WRITE_SIZE") for n in (2048, 8192)}
         pmc = {k: v for k, v in pmc.items() if os.path.isdir(v)}
-        summarize_profiles(os.path.join(d, "trace"), pmc, os.path.join(ROOT, "profiles"),
-                           "rocprofv3 --kernel-trace --stats --output-format csv -d RUNDIR/trace -o trace -- "
-                           "python3 bench.py --no-cpu --no-batched --no-studies",
+        if not traces and not pmc:
+            return
+        summarize_profiles(traces, pmc, os.path.join(ROOT, "profiles"),
+                           {n: f"rocprofv3 --kernel-trace --stats --output-format csv -d RUNDIR/trace_{n} -o trace -- "
+                               f"python3 bench.py --n {n} --steps {TRACE_STEPS[n]} --warmup 10 --modes f32,f64,f16s "
+                               f"--no-cpu --no-batched --no-studies" for n in traces},
                            [f"rocprofv3 --pmc {c} --output-format csv -d RUNDIR/pmc_{c.lower()}_{n} -o pmc -- "
                             f"python3 bench.py --n {n} --steps 12 --warmup 0 --modes f32,f64,f16s --no-cpu --no-batched --no-studies"
                             for (c, n) in sorted(pmc)])
@@ -674,16 +955,19 @@ def main():
             results[m]["l2_err_vs_f64"] = float(torch.sqrt((d * d).sum() / (ref * ref).sum()))
             results[m]["speedup_vs_f64"] = results[m]["mlups"] / results["f64"]["mlups"]
     for m in modes:
-        bpl = bytes_per_lup(m, False)
+        bpl = launch_bytes_per_lup(m, False, results[m]["launch"])
         results[m]["bytes_per_lup"] = bpl
         results[m]["hbm_gbps_algorithmic"] = results[m]["mlups"] * 1e6 * bpl / 1e9
         results[m]["roofline_frac"] = results[m]["hbm_gbps_algorithmic"] / HBM_PEAK_GBPS
 
     copy_gbps = copy_bandwidth(torch, lbm)
+    # two buffers of 92 MiB (184 MiB, the size of the in-place 2048^2 FP32 state) stay in the cache
+    cache_copy_gbps = copy_bandwidth(torch, lbm, nbytes=92 << 20, reps=50, cached=True)
     r = results[head]
     n2 = float(args.n) ** 2
     achieved = r["hbm_gbps_algorithmic"]
     traffic = traffic_from_profile(head, args.n)
+    stores = r["launch"]["stores"]
     out = {
         "metric": METRIC,
         "value": round(r["mlups"], 1),
@@ -700,21 +984,45 @@ def main():
         "config": {"workload": f"rotating Gaussian pulse, periodic {args.n}^2, c=10, U0=pi, D=1e-3, Lambda=1/4, "
                                f"{args.warmup}+{args.steps} steps", "N": args.n, "storage": head,
                    "aux": "local (Eq. 16)"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+        "roofline": {"bound": roofline_bound(stores),
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": None if traffic is None else round(traffic),
                      "traffic_unit": "bytes/launch filled into L2 from the fabric (rocprofv3 FETCH_SIZE+WRITE_SIZE, "
                                      "copy-calibrated; HBM plus Infinity Cache hits)",
-                     "algorithmic_bytes_per_launch": int(n2 * r["bytes_per_lup"]),
-                     "bytes_per_lup": r["bytes_per_lup"], "lups_per_launch": int(n2),
-                     "copy_gbps_measured": round(copy_gbps, 1),
-                     "frac_of_copy": round(achieved / copy_gbps, 4),
+                     "algorithmic_bytes_per_launch": int(n2 * bytes_per_lup(head, False)),
+                     "bytes_per_lup": r["bytes_per_lup"], "lups_per_launch": int(n2 * r["launch"]["fuse"]),
+                     "steps_per_launch": r["launch"]["fuse"],
+                     "single_step_equivalent_gbps": round(r["mlups"] * bytes_per_lup(head, False) / 1e3, 1),
+                     "peak_note": "8 TB/s is the HBM3E spec; a state held in the Infinity Cache is served partly "
+                                  "from that cache, whose ceiling is the measured cached copy below",
+                     "cache_copy_gbps_measured": round(cache_copy_gbps, 1),
+                     "frac_of_cache_copy": round(achieved / cache_copy_gbps, 4),
+                     "hbm_copy_gbps_measured": round(copy_gbps, 1),
+                     "frac_of_hbm_copy": round(achieved / copy_gbps, 4),
                      "state": {0: "two buffers streamed from HBM (non-temporal stores)",
                                1: "two buffers held in the 256 MiB Infinity Cache (cached stores)",
-                               2: "one buffer updated in place, held in the 256 MiB Infinity Cache"}[r["launch"]["stores"]]},
+                               2: "one buffer updated in place, held in the 256 MiB Infinity Cache"}[stores]},
         "modes": {m: {k: (round(v, 6) if isinstance(v, float) and abs(v) >= 1e-3 else v) for k, v in results[m].items()}
                   for m in modes},
     }
+    if not args.no_studies:
+        t0 = time.perf_counter()
+        hbm = run_hbm(torch, W, lbm, Solver)
+        h = hbm["f32"]
+        fz = h["launch"]["fuse"]
+        out["roofline_hbm"] = {"bound": "hbm", "kernel": ("step2_kernel FP32, two steps per launch" if fz == 2 else
+                                                          "step_kernel FP32, one row per wave") + ", non-temporal stores",
+                               "workload": hbm["workload"], "achieved": round(h["achieved_gbps"], 1),
+                               "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(h["frac"], 4),
+                               "traffic": h["traffic"],
+                               "algorithmic_bytes_per_launch": int(8192 ** 2 * bytes_per_lup("f32", False)),
+                               "bytes_per_lup": h["bytes_per_lup"], "lups_per_launch": 8192 ** 2 * fz,
+                               "steps_per_launch": fz, "mlups": round(h["mlups"], 1),
+                               "hbm_copy_gbps_measured": round(copy_gbps, 1),
+                               "frac_of_hbm_copy": round(h["achieved_gbps"] / copy_gbps, 4)}
+        out["hbm"] = hbm
+        print(f"# hbm: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     if not args.no_batched:
         out["batched"] = run_batched(torch, W, lbm, Solver)
         print(f"# batched: {out['batched']['batched']['mlups']:.0f} MLUPS vs serial graph "
@@ -722,7 +1030,8 @@ def main():
               file=sys.stderr, flush=True)
     if not args.no_studies:
         for name, fn in (("precision_8192_variable_D", run_precision_8192), ("refinement", run_refinement),
-                         ("flux_aux_2048", run_flux), ("dirichlet_sec3", run_dirichlet), ("d3q19", run_3d),
+                         ("flux_aux_2048", run_flux), ("dirichlet_sec3", run_dirichlet),
+                         ("tau2_sweep_walls", run_tau2_sweep), ("d3q19", run_3d),
                          ("d3q27", lambda *a: run_3d(*a, q=27)),
                          ("adjoint_512", run_adjoint)):
             t0 = time.perf_counter()
@@ -732,7 +1041,11 @@ def main():
                 out[name] = {"error": f"{type(e).__name__}: {e}"}
             print(f"# {name}: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.n)
+        t0 = time.perf_counter()
+        out["cpu_baseline"], phi_orc = cpu_baseline(args.n, cross_check=not args.no_studies)
+        print(f"# cpu_baseline: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        if phi_orc is not None:
+            out["oracle_cross_check_1024"] = oracle_cross_check(torch, W, lbm, Solver, phi_orc)
     print(json.dumps(out))
 
 

@@ -234,21 +234,32 @@ typedef struct lbm_launch {
                             lbm_get_launch reports 0 */
     int32_t stores;      /* how the new state is written: 0 non-temporal (streamed to HBM); 1 cached (left
                             in L2 and the 256 MiB Infinity Cache, where the next step reads it back);
-                            2 one buffer updated in place, cached (read-only: chosen by lbm_init).
+                            2 one buffer updated in place, cached.
                             1 is honoured by launches of one instance (the SERIAL policy) except the
                             walking loop (rows > 1) of D2Q9 instances with the local or no auxiliary
                             term; those and the batched policies store non-temporally.  Default: 1
                             for honouring instances when both population buffers and the per-node
                             fields of every instance of the context fit in 256 MiB, else 0.
                             2: a context of one periodic instance (D2Q9 with the local or no aux
-                            term; D3Q19 or D3Q27 without FP64 math)
-                            that fits in 256 MiB only with a single population buffer is updated in
-                            place: a streaming step (pull, then each P_i written back where the
+                            term; D3Q19 or D3Q27 without FP64 math) updates a single population buffer
+                            in place: a streaming step (pull, then each P_i written back where the
                             opposite population was read) alternates with a local step (the node's
                             own slots), the AA pattern of Bailey et al. (2009).  Results are bitwise
                             those of two buffers, and so are its state images (lbm_state_save and
-                            lbm_state_load convert after an odd number of steps).  Such a context
-                            takes only rows = 1 and stores = 2 in lbm_set_launch (else LBM_E_ARG). */
+                            lbm_state_load convert after an odd number of steps).  lbm_init chooses 2
+                            for such a context that fits in 256 MiB only with a single buffer (unless
+                            it defaults to fuse = 2); lbm_set_launch may switch between one and two
+                            buffers at any step (the state is carried over; the workspace always
+                            holds both); with stores = 2 it takes only rows = 1 and fuse 0 or 1. */
+    int32_t fuse;        /* time steps per launch: 1 (0 reads as 1), or 2: two steps of Eq. (14) fused in one
+                            launch (temporal blocking), each block computing the intermediate state of its
+                            tile and a one-node frame around it in LDS, so every population crosses memory
+                            once per two steps; bitwise the same results.  2 needs a context of one
+                            periodic D2Q9 TRT-R instance (tau3 0 or 1) with the local or no auxiliary term
+                            and two population buffers; tiles are then tile_width = 128, 256 or 512
+                            columns by rows = 1..256 rows, in the tile order xcd_remap (xcd_rows), with
+                            stores 0 or 1 and max_waves 0.  An odd step count ends with one single step in
+                            the context's one-step shape. */
 } lbm_launch;
 
 /* Sets (inst = -1: every instance) or reads the launch shape; captured step graphs are dropped.
@@ -303,7 +314,8 @@ int lbm_adjoint_step(lbm_ctx *ctx, int32_t inst, const void *state, const void *
  * call.  states: device buffer of nsteps state images (lbm_state_bytes each, consecutive); image 0
  * must hold g^{t0} (a checkpoint copied there by the caller).  The call first recomputes images
  * 1 .. nsteps - 1 (image j + 1 = one step of image j, with the instance's current u, D and source;
- * the context's own state is not touched), then applies nsteps adjoint steps (lbm_adjoint_step) from
+ * the context's own state is not touched; padding columns of those images are left as they were),
+ * then applies nsteps adjoint steps (lbm_adjoint_step) from
  * lam = dL/dg^{t0 + nsteps} down to dL/dg^{t0}, which it writes back into lam; lam_tmp (same size,
  * must not alias lam) is scratch.  dLdD accumulates as in lbm_adjoint_step.  Asynchronous. */
 int lbm_adjoint_segment(lbm_ctx *ctx, int32_t inst, void *states, int32_t nsteps, void *lam, void *lam_tmp,

@@ -21,7 +21,12 @@ from .solver import Solver
 
 @dataclass
 class RunSpec:
-    """Everything but D that defines one periodic run (device FP64 fields [ny, nx])."""
+    """Everything but D that defines one periodic run (device FP64 fields [ny, nx]).
+
+    The first forward pass creates one library context (with a D field) and keeps it in the spec;
+    later passes replace D (``lbm_set_diffusion``) and restart from the stored initial state
+    (``lbm_state_load``), so a gradient loop over D pays for ``lbm_init`` once.  ``close()`` releases
+    the context."""
     nx: int
     ny: int
     dx: float
@@ -35,14 +40,32 @@ class RunSpec:
     aux: int = L.LBM_AUX_LOCAL
     segment: Optional[int] = None          # checkpoint interval (default ceil(sqrt(nsteps)))
     stats: dict = field(default_factory=dict)
+    _solver: Optional[Solver] = field(default=None, repr=False)
+    _init_state: Optional[torch.Tensor] = field(default=None, repr=False)
+
+    def solver_for(self, D: torch.Tensor) -> Solver:
+        """The run's context with diffusion field D, reset to the initial state g_eq(phi0, u)."""
+        D = D.detach().to(torch.float64).contiguous()
+        if self._solver is None:
+            p = L.make_params(self.nx, self.ny, self.dx, self.dt, self.lam, float(D.mean()), self.mode, self.aux)
+            self._solver = Solver([(p, {"phi0": self.phi0, "ux": self.ux, "uy": self.uy, "D": D})])
+            self._init_state = self._solver.state_save()
+        else:
+            self._solver.set_diffusion(D)
+            self._solver.state_load(self._init_state, 0)
+        return self._solver
+
+    def close(self) -> None:
+        if self._solver is not None:
+            self._solver.close()
+            self._solver = None
+            self._init_state = None
 
 
 class _TRTRRun(torch.autograd.Function):
     @staticmethod
     def forward(ctx, D: torch.Tensor, spec: RunSpec):
-        p = L.make_params(spec.nx, spec.ny, spec.dx, spec.dt, spec.lam, float(D.mean()), spec.mode, spec.aux)
-        fields = {"phi0": spec.phi0, "ux": spec.ux, "uy": spec.uy, "D": D.detach().to(torch.float64).contiguous()}
-        solver = Solver([(p, fields)])
+        solver = spec.solver_for(D)
         T = int(spec.nsteps)
         K = int(spec.segment or max(1, math.ceil(math.sqrt(T))))
         ckpts = []
@@ -53,35 +76,35 @@ class _TRTRRun(torch.autograd.Function):
             solver.step(n)
             t += n
         _, phi = solver.macros(want_phi=True)
-        ctx.solver, ctx.ckpts, ctx.T, ctx.K, ctx.spec = solver, ckpts, T, K, spec
+        ctx.ckpts, ctx.T, ctx.K, ctx.spec = ckpts, T, K, spec
+        ctx.save_for_backward(D)
         spec.stats.update(checkpoints=len(ckpts), segment=K)
         return phi
 
     @staticmethod
     def backward(ctx, dphi: torch.Tensor):
-        solver, spec, T, K = ctx.solver, ctx.spec, ctx.T, ctx.K
+        spec, T, K = ctx.spec, ctx.T, ctx.K
+        (D,) = ctx.saved_tensors
+        solver = spec.solver_for(D)  # the D of this forward pass, whatever ran in between
         mdtype = torch.float64 if spec.mode == "f64" else torch.float32
         nbytes = L.lbm_adjoint_bytes(solver.ctx)
-        lam_a = torch.empty(nbytes // mdtype.itemsize, dtype=mdtype, device="cuda")
-        lam_b = torch.empty_like(lam_a)
-        L.lbm_adjoint_seed(solver.ctx, 0, dphi.detach().to(torch.float64).contiguous(), lam_a)
+        lam = torch.empty(nbytes // mdtype.itemsize, dtype=mdtype, device="cuda")
+        lam_tmp = torch.empty_like(lam)
+        sb = L.lbm_state_bytes(solver.ctx)
+        states = torch.empty(K * sb, dtype=torch.uint8, device="cuda")
         grad = torch.zeros((spec.ny, spec.nx), dtype=torch.float64, device="cuda")
-        for t0, ck in reversed(ctx.ckpts):
-            n = min(K, T - t0)
-            solver.state_load(ck, t0)
-            states = [solver.state_save()]
-            for _ in range(n - 1):  # recompute the segment's states g^{t0} .. g^{t0+n-1}
-                solver.step(1)
-                states.append(solver.state_save())
-            for j in reversed(range(n)):  # dL/dg^{t0+j} from dL/dg^{t0+j+1}
-                L.lbm_adjoint_step(solver.ctx, 0, states[j], lam_a, lam_b, grad)
-                lam_a, lam_b = lam_b, lam_a
-        if spec.stats is not None:
-            dphi0 = torch.empty((spec.ny, spec.nx), dtype=torch.float64, device="cuda")
-            L.lbm_adjoint_init(solver.ctx, 0, lam_a, dphi0)
-            spec.stats["dL_dphi0"] = dphi0
-        solver.close()
-        ctx.solver = None
+        with torch.cuda.stream(solver.stream):
+            L.lbm_adjoint_seed(solver.ctx, 0, dphi.detach().to(torch.float64).contiguous(), lam)
+            for t0, ck in reversed(ctx.ckpts):
+                # each segment: its checkpoint into image 0, then recomputation and K adjoint steps,
+                # enqueued by the library in one call
+                states[:sb].copy_(ck)
+                L.lbm_adjoint_segment(solver.ctx, 0, states, min(K, T - t0), lam, lam_tmp, grad)
+            if spec.stats is not None:
+                dphi0 = torch.empty((spec.ny, spec.nx), dtype=torch.float64, device="cuda")
+                L.lbm_adjoint_init(solver.ctx, 0, lam, dphi0)
+                spec.stats["dL_dphi0"] = dphi0
+        ctx.ckpts = None
         return grad, None
 
 

@@ -1,5 +1,7 @@
 """Autotuner for the step launch: tile shape (rows walked per wave, XCD tile order and its row-block
-height, 64- or 256-column tiles), non-temporal or cached stores of the new state, a cap on the waves resident per SIMD, and, for a multi-instance context, the
+height, 64- or 256-column tiles), non-temporal or cached stores of the new state, a cap on the waves
+resident per SIMD, one buffer updated in place, two steps per launch (tile width and height), and, for a
+multi-instance context, the
 batch schedule (serial launches, one flat launch, or persistent blocks with a round-robin or
 longest-processing-time assignment of tiles).
 
@@ -26,23 +28,40 @@ def _key(solver) -> str:
     dev = torch.cuda.get_device_name()
     shapes = [(p.nx, p.ny, p.nz, p.lattice, p.store, p.math, p.aux, p.boundary, p.tau3 not in (0.0, 1.0))
               for p in solver.params]
-    return hashlib.sha256(json.dumps(["launch-v4", dev, shapes]).encode()).hexdigest()[:20]
+    return hashlib.sha256(json.dumps(["launch-v5", dev, shapes]).encode()).hexdigest()[:20]
+
+
+def _fusable(solver) -> bool:
+    p = solver.params[0]
+    return (len(solver.params) == 1 and p.lattice == L.LBM_LATTICE_D2Q9 and p.boundary == L.LBM_BC_PERIODIC
+            and p.aux != L.LBM_AUX_FLUX and p.tau3 in (0.0, 1.0))
 
 
 def default_candidates(solver) -> list:
-    """(rows, xcd_remap, xcd_rows, tile_width, max_waves, stores, policy, blocks) tuples worth timing for
-    this context.  Stores: both kinds for one instance where they are honoured (not in the local
-    form's walking loop); a batch keeps the context's default; a one-buffer (in-place) context keeps
-    its one-row in-place launches."""
+    """(rows, xcd_remap, xcd_rows, tile_width, max_waves, stores, policy, blocks, fuse) tuples worth timing
+    for this context.  Stores: both kinds for one instance where they are honoured (not in the local
+    form's walking loop); a batch keeps the context's default.  A single periodic D2Q9 TRT-R instance
+    with the local or no aux term also tries one buffer in place (one-row launches) and two steps per
+    launch (fuse 2: tile width and height, row bands or hardware order, both store kinds)."""
     out = []
     st0 = solver.get_launch(0)["stores"]
     p0 = solver.params[0]
     multi = len(solver.params) > 1 and len({(p.store, p.math, p.aux) for p in solver.params}) == 1
-    if not multi and st0 == 2:  # one buffer updated in place: one-row launches only
+    if _fusable(solver):
+        for width in (128, 256, 512):
+            for rows in (8, 16, 32, 64):
+                for remap in (0, 1):
+                    for stores in (0, 1):
+                        out.append((rows, remap, 0, width, 0, stores, L.LBM_BATCH_SERIAL, 0, 2))
         for width in (64, 256):
             for remap, h in [(0, 0), (1, 0)] + ([(3, h) for h in (2, 4, 8)] if width == 256 else []):
                 for cap in (0, 4, 5):
-                    out.append((1, remap, h, width, cap, 2, L.LBM_BATCH_SERIAL, 0))
+                    out.append((1, remap, h, width, cap, 2, L.LBM_BATCH_SERIAL, 0, 1))
+    elif not multi and st0 == 2:  # one buffer updated in place (3D): one-row launches only
+        for width in (64, 256):
+            for remap, h in [(0, 0), (1, 0)] + ([(3, h) for h in (2, 4, 8)] if width == 256 else []):
+                for cap in (0, 4, 5):
+                    out.append((1, remap, h, width, cap, 2, L.LBM_BATCH_SERIAL, 0, 1))
         return out
     if not multi:
         for width, rows_set in ((64, (1, 2, 4)), (256, (1, 2))):
@@ -51,25 +70,25 @@ def default_candidates(solver) -> list:
                 for remap, h in orders:
                     for cap in (0, 4, 5):
                         honoured = rows == 1 or p0.aux == L.LBM_AUX_FLUX or p0.lattice != L.LBM_LATTICE_D2Q9
-                        for stores in ((st0, 1 - st0) if honoured else (0,)):
-                            out.append((rows, remap, h, width, cap, stores, L.LBM_BATCH_SERIAL, 0))
+                        for stores in ((0, 1) if honoured else (0,)):
+                            out.append((rows, remap, h, width, cap, stores, L.LBM_BATCH_SERIAL, 0, 1))
         return out
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
     for width in (64, 256):
         for rows in (1, 2, 4):
-            out.append((rows, 1, 0, width, 0, st0, L.LBM_BATCH_SERIAL, 0))
+            out.append((rows, 1, 0, width, 0, st0, L.LBM_BATCH_SERIAL, 0, 1))
             for cap in (0, 6):
-                out.append((rows, 1, 0, width, cap, st0, L.LBM_BATCH_FLAT, 0))
-                out.append((rows, 1, 0, width, cap, st0, L.LBM_BATCH_LPT, 4 * ncu))
+                out.append((rows, 1, 0, width, cap, st0, L.LBM_BATCH_FLAT, 0, 1))
+                out.append((rows, 1, 0, width, cap, st0, L.LBM_BATCH_LPT, 4 * ncu, 1))
             for mult in (2, 8):
-                out.append((rows, 1, 0, width, 0, st0, L.LBM_BATCH_LPT, mult * ncu))
-            out.append((rows, 1, 0, width, 0, st0, L.LBM_BATCH_STRIDED, 4 * ncu))
+                out.append((rows, 1, 0, width, 0, st0, L.LBM_BATCH_LPT, mult * ncu, 1))
+            out.append((rows, 1, 0, width, 0, st0, L.LBM_BATCH_STRIDED, 4 * ncu, 1))
     return out
 
 
 def _apply(solver, cand) -> None:
-    rows, remap, h, width, cap, stores, policy, blocks = cand
-    solver.set_launch(rows, remap, tile_width=width, max_waves=cap, xcd_rows=h, stores=stores)
+    rows, remap, h, width, cap, stores, policy, blocks, fuse = (tuple(cand) + (1,))[:9]
+    solver.set_launch(rows, remap, tile_width=width, max_waves=cap, xcd_rows=h, stores=stores, fuse=fuse)
     if len(solver.params) > 1:
         try:
             solver.set_batch(policy, blocks, cap)  # the cap applies to the batched launch as well
@@ -96,8 +115,8 @@ def _time(solver, steps: int, reps: int) -> float:
 def tune(solver, candidates: Optional[Iterable] = None, steps: int = 64, reps: int = 2,
          cache_path: Optional[str] = None, force: bool = False) -> dict:
     """Times every candidate, applies the fastest and returns
-    {"best": (rows, xcd_remap, xcd_rows, tile_width, max_waves, stores, policy, blocks), "ms_per_step": {...},
-    "cached": bool}."""
+    {"best": (rows, xcd_remap, xcd_rows, tile_width, max_waves, stores, policy, blocks, fuse),
+    "ms_per_step": {...}, "cached": bool}."""
     key = _key(solver)
     cached = None
     if not force:
@@ -123,7 +142,7 @@ def tune(solver, candidates: Optional[Iterable] = None, steps: int = 64, reps: i
         for k in range(n):
             o = old_launch[k]
             solver.set_launch(o["rows"], o["xcd_remap"], inst=k, tile_width=o["tile_width"], max_waves=o["max_waves"],
-                              xcd_rows=o["xcd_rows"], stores=o["stores"])
+                              xcd_rows=o["xcd_rows"], stores=o["stores"], fuse=o["fuse"])
         if old_batch is not None:
             solver.set_batch(old_batch["policy"], old_batch["blocks"], old_batch["max_waves"])
         for k in range(n):

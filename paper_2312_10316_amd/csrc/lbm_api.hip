@@ -91,9 +91,8 @@ int lds_reserve_for(int max_waves, int lds_per_cu)
 // Against column bands (ntx a multiple of 8) or row bands: FP32 +2-9 %, FP64 +1-5 %, FP16 +2-6 %
 // (2048^2 FP32: 82k MLUPS).  Narrower lattices: row bands, FP64 storage on 64-column tiles in
 // hardware order.
-// Flux form: two rows per wave on 256-column tiles, FP32 in row bands with 4 waves (+16 % over 8 rows
-// of 64-column tiles), FP64 in column bands (ntx a multiple of 8) or row bands, uncapped (row blocks
-// measured slower).
+// Flux form (one instance): the walking kernel (lbm_fused.hip) on 256-column tiles whose height gives
+// about 1024 tiles (4..64 rows), in row bands, uncapped.
 // Dirichlet edges and walls with ntx >= 8: FP32 on 256-column tiles in row blocks of 4 tile rows capped
 // at 5 waves (2049^2 NEE: 76k against 72k MLUPS in row bands), FP64 the same with h = 2, uncapped;
 // FP16 in row bands, uncapped.  Narrower lattices: FP32 and FP16 in row bands, FP64 on 64-column tiles
@@ -108,7 +107,6 @@ Launch default_launch(const lbm_params &p, int mode, bool has_D, int n_inst, int
     Launch lc{1, 0, 1, 0, 0, 0};
     const bool f32 = mode == MODE_F32_F32, f16 = mode == MODE_F16S_F32;
     const int ntx = (p.nx + 255) / 256;
-    const int bands = ntx % 8 == 0 ? 2 : 1;
     const auto row_blocks = [&lc](int h) {
         lc.xcd_remap = 3;
         lc.xcd_rows = h;
@@ -125,10 +123,9 @@ Launch default_launch(const lbm_params &p, int mode, bool has_D, int n_inst, int
         } else {
             lc.wide = 0;
         }
-    } else if (p.aux == LBM_AUX_FLUX) {
-        lc.rows = 2;
-        lc.xcd_remap = f32 ? 1 : bands;
-        lc.max_waves = f32 ? 4 : 0;
+    } else if (p.aux == LBM_AUX_FLUX) {  // the walking kernel: 256-column tiles, rows = tile height
+        lc.rows = std::clamp((int)(((int64_t)p.ny * ntx) / 1024), 4, 64);
+        lc.xcd_remap = 1;
     } else {
         lc.xcd_remap = 1;
         lc.max_waves = f16 ? 0 : (f32 ? (has_D ? 6 : 5) : 4);
@@ -150,6 +147,55 @@ Launch default_launch(const lbm_params &p, int mode, bool has_D, int n_inst, int
     }
     lc.lds_reserve = lds_reserve_for(lc.max_waves, lds_per_cu);
     return lc;
+}
+
+// Two steps per launch (temporal blocking, lbm_fused.hip) for a single periodic D2Q9 TRT-R instance
+// with the local or no auxiliary term.  Tile shapes from sweeps at 2048^2 and 8192^2 (constant and
+// variable D): with at most 8 tiles of 256 columns per row, FP32 and FP16 storage take 512-column
+// tiles of 16 rows (2048^2: FP32 122k, FP16 167k MLUPS), FP64 storage 256 x 32; wider lattices take
+// FP32 256 x 16 (8192^2: 135k), FP16 128 x 32 (171k) and FP64 storage 128 x 16 (64k).  Tiles never
+// wider than the lattice needs (at least 128 columns), and at least 256 tiles where the lattice allows
+// (down to 4 rows).  Row bands over the XCDs, so that the frame rows a tile shares with the next tile
+// down sit in the same L2.  (MRT-R stays on single steps: with FP64 math the compiler had fused its
+// third-order multiply-adds otherwise in the fused kernel.)
+bool fusable(const lbm_params &p, int n_inst)
+{
+    return n_inst == 1 && p.lattice == LBM_LATTICE_D2Q9 && p.boundary == LBM_BC_PERIODIC && p.aux != LBM_AUX_FLUX &&
+           (p.tau3 == 0.0 || p.tau3 == 1.0);
+}
+Launch fused_default(const lbm_params &p, int mode)
+{
+    Launch lc{};
+    lc.fuse = 2;
+    const bool narrow = (p.nx + 255) / 256 <= 8;
+    int width, rows;
+    if (mode == MODE_F32_F32) {
+        width = narrow ? 512 : 256;
+        rows = 16;
+    } else if (mode == MODE_F16S_F32) {
+        width = narrow ? 512 : 128;
+        rows = narrow ? 16 : 32;
+    } else {
+        width = narrow ? 256 : 128;
+        rows = narrow ? 32 : 16;
+    }
+    while (width > 128 && width / 2 >= p.nx) width /= 2;
+    auto tiles = [&](int h) { return (int64_t)((p.nx + width - 1) / width) * ((p.ny + h - 1) / h); };
+    while (rows > 4 && tiles(rows) < 256) rows /= 2;
+    lc.fuse_width = width;
+    lc.rows = rows;
+    lc.xcd_remap = 1;
+    return lc;
+}
+
+// One buffer updated in place (AA pattern): a context of one periodic instance, D2Q9 with the local or
+// no aux term, or D3Q19/D3Q27 except FP64 math (whose one-row in-place kernels fuse the collision's
+// multiply-adds otherwise than the two-buffer walking loop: equal to rounding, not bitwise).
+bool in_place_ok(const lbm_params &p, int mode, int n_inst)
+{
+    if (n_inst != 1 || p.boundary != LBM_BC_PERIODIC) return false;
+    if (p.lattice != LBM_LATTICE_D2Q9) return mode != MODE_F64_F64;
+    return p.aux != LBM_AUX_FLUX;
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -221,8 +267,10 @@ struct Instance {
     lbm_params p;
     int mode;
     Layout L;
-    Launch lc;
+    Launch lc;   // the configured launch (lc.fuse == 2: two steps per launch)
+    Launch lc1;  // the one-step launch used for single steps of a context whose lc is fused
     char *buf[2];
+    char *alt;   // the workspace's second population buffer (buf[1] unless the instance runs in place)
     void *u, *k, *s, *bc;
     bool has_D;
     bool has_src;
@@ -461,12 +509,28 @@ int enqueue_step(lbm_ctx *c, hipStream_t st)
         for (size_t k = 0; k < c->inst.size(); ++k) {
             StepArgs a;
             a.d = c->h_desc[k];
+            if (a.d.lc.fuse == 2) a.d.lc = c->inst[k].lc1;  // a single step of a fused context
             a.parity = c->parity;
             hipError_t e = is3d(c->inst[k]) ? launch_step3(c->inst[k].mode, c->inst[k].p.aux, a, st)
                                              : launch_step(c->inst[k].mode, c->inst[k].p.aux, a, st);
             if (e != hipSuccess) return hip_fail(e, "step kernel launch");
         }
     }
+    c->parity ^= 1;
+    return LBM_OK;
+}
+
+// A context whose one instance runs two steps per launch.
+bool fused(const lbm_ctx *c) { return c->inst.size() == 1 && c->inst[0].lc.fuse == 2; }
+
+// Enqueues two steps in one launch (fused contexts).
+int enqueue_fused(lbm_ctx *c, hipStream_t st)
+{
+    StepArgs a;
+    a.d = c->h_desc[0];
+    a.parity = c->parity;
+    hipError_t e = launch_step2(c->inst[0].mode, c->inst[0].p.aux, a, st);
+    if (e != hipSuccess) return hip_fail(e, "fused step kernel launch");
     c->parity ^= 1;
     return LBM_OK;
 }
@@ -486,7 +550,10 @@ int graph_for(lbm_ctx *c, hipGraphExec_t *out)
     hipError_t e = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     int rc = LBM_OK;
-    for (int t = 0; t < kGraphSteps && rc == LBM_OK; ++t) rc = enqueue_step(c, c->capture);
+    if (fused(c))
+        for (int t = 0; t < kGraphSteps / 2 && rc == LBM_OK; ++t) rc = enqueue_fused(c, c->capture);
+    else
+        for (int t = 0; t < kGraphSteps && rc == LBM_OK; ++t) rc = enqueue_step(c, c->capture);
     // Capturing runs nothing: the buffer parity is the one the graph starts from, on every path out
     // (a failed capture may have flipped it an odd number of times).
     c->parity = par;
@@ -590,10 +657,12 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
         in.p = p[k];
         in.mode = mode_of(p[k]);
         in.L = layout_of(p[k]);
-        in.lc = default_launch(in.p, in.mode, f[k].D != nullptr, n_inst, c->lds_per_cu);
+        in.lc1 = default_launch(in.p, in.mode, f[k].D != nullptr, n_inst, c->lds_per_cu);
+        in.lc = fusable(in.p, n_inst) ? fused_default(in.p, in.mode) : in.lc1;
         const size_t pb = pops_bytes(p[k]), vb = vel_bytes(p[k]), fb = field_bytes(p[k]);
         in.buf[0] = w;
         in.buf[1] = w + pb;
+        in.alt = w + pb;
         w += 2 * pb;
         in.u = w;
         w += vb;
@@ -633,26 +702,21 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
     // touches 185 MB per step instead of 335 MB (89.9k against 82.3k MLUPS).
     const Instance &i0 = c->inst[0];
     const size_t one_buffer = (size_t)i0.L.nx * rows_of(i0.L) * i0.L.q * store_bytes(i0.mode);
-    const bool inplace = n_inst == 1 && touched > kInfinityCacheBytes && touched - one_buffer <= kInfinityCacheBytes &&
-                         // D3Q19/D3Q27 (periodic, local or no aux) except FP64 math: its one-row in-place
-                         // kernels fuse the collision's multiply-adds otherwise than the two-buffer walking loop
-                         // (equal to rounding, not bitwise)
-                         ((i0.p.lattice != LBM_LATTICE_D2Q9 && i0.mode != MODE_F64_F64) ||
-                          (i0.p.lattice == LBM_LATTICE_D2Q9 && i0.p.boundary == LBM_BC_PERIODIC &&
-                           i0.p.aux != LBM_AUX_FLUX && i0.lc.rows == 1));
+    const bool inplace = touched > kInfinityCacheBytes && touched - one_buffer <= kInfinityCacheBytes &&
+                         in_place_ok(i0.p, i0.mode, n_inst) && i0.lc.rows == 1 && i0.lc.fuse != 2;
     for (Instance &in : c->inst) {
-        in.lc.stores = touched <= kInfinityCacheBytes &&
-                       (in.p.lattice != LBM_LATTICE_D2Q9 || in.p.aux == LBM_AUX_FLUX || in.lc.rows == 1);
-        if (inplace) {
-            in.lc.stores = 2;
-            in.buf[1] = in.buf[0];
+        for (Launch *lc : {&in.lc, &in.lc1}) {
+            lc->stores = touched <= kInfinityCacheBytes &&
+                         (in.p.lattice != LBM_LATTICE_D2Q9 || in.p.aux == LBM_AUX_FLUX || lc->rows == 1 || lc->fuse == 2);
+            if (inplace) lc->stores = 2;
+            if (lc->stores) {
+                lc->xcd_remap = 1;
+                lc->xcd_rows = 0;
+                lc->max_waves = 0;
+                lc->lds_reserve = 0;
+            }
         }
-        if (in.lc.stores) {
-            in.lc.xcd_remap = 1;
-            in.lc.xcd_rows = 0;
-            in.lc.max_waves = 0;
-            in.lc.lds_reserve = 0;
-        }
+        if (inplace) in.buf[1] = in.buf[0];
     }
     const size_t items = max_items_of(n_inst, p);
     c->d_desc = reinterpret_cast<InstDesc *>(w);
@@ -753,6 +817,11 @@ int lbm_step(lbm_ctx *c, int32_t nsteps, const double *const *ux, const double *
             if (e != hipSuccess) return account(hip_fail(e, "hipGraphLaunch"));
         }
     }
+    if (fused(c))
+        for (; left >= 2; left -= 2) {
+            rc = enqueue_fused(c, c->stream);
+            if (rc) return account(rc);
+        }
     for (; left > 0; --left) {
         rc = enqueue_step(c, c->stream);
         if (rc) return account(rc);
@@ -883,28 +952,70 @@ int lbm_set_launch(lbm_ctx *c, int32_t inst, const lbm_launch *cfg)
     if (!c || inst < -1 || inst >= (int32_t)c->inst.size())
         return fail(LBM_E_STATE, "lbm_set_launch: bad context or instance %d", inst);
     if (!cfg) return fail(LBM_E_ARG, "lbm_set_launch: cfg is NULL");
-    if (cfg->rows < 1 || cfg->rows > 64) return fail(LBM_E_ARG, "lbm_set_launch: rows=%d outside 1..64", cfg->rows);
+    if (cfg->fuse < 0 || cfg->fuse > 2) return fail(LBM_E_ARG, "lbm_set_launch: fuse=%d must be 0, 1 or 2", cfg->fuse);
+    const bool two = cfg->fuse == 2;
+    const int max_rows = two ? 256 : 64;
+    if (cfg->rows < 1 || cfg->rows > max_rows)
+        return fail(LBM_E_ARG, "lbm_set_launch: rows=%d outside 1..%d", cfg->rows, max_rows);
     if (cfg->xcd_remap < 0 || cfg->xcd_remap > 3) return fail(LBM_E_ARG, "lbm_set_launch: xcd_remap must be 0..3");
     if (cfg->xcd_remap == 3 && (cfg->xcd_rows < 1 || cfg->xcd_rows > 64))
         return fail(LBM_E_ARG, "lbm_set_launch: xcd_rows=%d outside 1..64 (xcd_remap 3)", cfg->xcd_rows);
     if (cfg->stores < 0 || cfg->stores > 2) return fail(LBM_E_ARG, "lbm_set_launch: stores=%d must be 0, 1 or 2", cfg->stores);
+    const bool want_one = cfg->stores == 2;
     for (int k = 0; k < (int)c->inst.size(); ++k) {
         if (inst != -1 && inst != k) continue;
-        const bool one = c->inst[k].lc.stores == 2;  // fixed at init: the state lives in one buffer
-        if (one && (cfg->stores != 2 || cfg->rows != 1))
-            return fail(LBM_E_ARG, "lbm_set_launch: a one-buffer (in-place) context needs stores=2 and rows=1");
-        if (!one && cfg->stores == 2)
-            return fail(LBM_E_ARG, "lbm_set_launch: stores=2 (in place) is chosen at init, not here");
+        const Instance &in = c->inst[k];
+        if (want_one && !in_place_ok(in.p, in.mode, (int)c->inst.size()))
+            return fail(LBM_E_ARG, "lbm_set_launch: stores=2 (one buffer in place) needs a context of one periodic "
+                                   "instance: D2Q9 with the local or no auxiliary term, or D3Q19/D3Q27 without FP64 math");
+        if (want_one && (cfg->rows != 1 || two))
+            return fail(LBM_E_ARG, "lbm_set_launch: stores=2 (one buffer in place) needs rows=1 and fuse 0 or 1");
+        if (two && !fusable(in.p, (int)c->inst.size()))
+            return fail(LBM_E_ARG, "lbm_set_launch: fuse=2 needs a context of one periodic D2Q9 TRT-R instance with "
+                                   "the local or no auxiliary term");
     }
-    if (cfg->tile_width != 64 && cfg->tile_width != 256)
-        return fail(LBM_E_ARG, "lbm_set_launch: tile_width=%d must be 64 or 256", cfg->tile_width);
-    if (cfg->max_waves != 0 && (cfg->max_waves < 3 || cfg->max_waves > 8))
-        return fail(LBM_E_ARG, "lbm_set_launch: max_waves=%d must be 0 or 3..8", cfg->max_waves);
-    const Launch lc{cfg->rows, cfg->xcd_remap, cfg->tile_width == 256 ? 1 : 0, cfg->max_waves,
-                    lds_reserve_for(cfg->max_waves, c->lds_per_cu), cfg->xcd_remap == 3 ? cfg->xcd_rows : 0,
-                    cfg->stores, 0};
-    for (int k = 0; k < (int)c->inst.size(); ++k)
-        if (inst == -1 || inst == k) c->inst[k].lc = lc;
+    if (two ? (cfg->tile_width != 128 && cfg->tile_width != 256 && cfg->tile_width != 512)
+            : (cfg->tile_width != 64 && cfg->tile_width != 256))
+        return fail(LBM_E_ARG, "lbm_set_launch: tile_width=%d must be %s", cfg->tile_width,
+                    two ? "128, 256 or 512 with fuse=2" : "64 or 256");
+    if (cfg->max_waves != 0 && (two || cfg->max_waves < 3 || cfg->max_waves > 8))
+        return fail(LBM_E_ARG, "lbm_set_launch: max_waves=%d must be 0 or 3..8 (0 with fuse=2)", cfg->max_waves);
+    Launch lc{};
+    lc.rows = cfg->rows;
+    lc.xcd_remap = cfg->xcd_remap;
+    lc.wide = cfg->tile_width == 256 ? 1 : 0;
+    lc.max_waves = cfg->max_waves;
+    lc.lds_reserve = lds_reserve_for(cfg->max_waves, c->lds_per_cu);
+    lc.xcd_rows = cfg->xcd_remap == 3 ? cfg->xcd_rows : 0;
+    lc.stores = cfg->stores;
+    lc.fuse = two ? 2 : 1;
+    lc.fuse_width = two ? cfg->tile_width : 0;
+    for (int k = 0; k < (int)c->inst.size(); ++k) {
+        if (inst != -1 && inst != k) continue;
+        Instance &in = c->inst[k];
+        const bool was_one = in.buf[1] == in.buf[0];
+        if (was_one && !want_one) {
+            // one buffer -> two: after an odd number of steps the state is in the streaming step's layout;
+            // its standard image goes to the second buffer, which then holds the state (parity 1)
+            if (c->parity == 1) {
+                hipError_t e = is3d(in) ? launch_relayout3(store_bytes(in.mode), in.buf[0], in.alt, in.L, c->stream)
+                                        : launch_relayout(store_bytes(in.mode), in.buf[0], in.alt, in.L, c->stream);
+                if (e != hipSuccess) return hip_fail(e, "lbm_set_launch: converting the one-buffer state");
+            }
+            in.buf[1] = in.alt;
+        } else if (!was_one && want_one) {
+            // two buffers -> one: the state must sit in buffer 0 in the standard layout (parity 0)
+            if (c->parity == 1) {
+                hipError_t e = hipMemcpyAsync(in.buf[0], in.buf[1], pops_bytes(in.p), hipMemcpyDeviceToDevice, c->stream);
+                if (e != hipSuccess) return hip_fail(e, "lbm_set_launch: moving the state to one buffer");
+                c->parity = 0;
+            }
+            in.buf[1] = in.buf[0];
+        }
+        in.lc = lc;
+        if (!two) in.lc1 = lc;  // fused: single steps keep a one-step launch of the same store kind
+        else in.lc1.stores = lc.stores;
+    }
     return refresh_tables(c);
 }
 
@@ -914,12 +1025,14 @@ int lbm_get_launch(lbm_ctx *c, int32_t inst, lbm_launch *cfg)
     if (!check_inst(c, inst)) return fail(LBM_E_STATE, "lbm_get_launch: bad context or instance %d", inst);
     if (!cfg) return fail(LBM_E_ARG, "lbm_get_launch: cfg is NULL");
     const Launch &lc = c->inst[inst].lc;
+    const bool two = lc.fuse == 2;
     cfg->rows = lc.rows;
     cfg->xcd_remap = lc.xcd_remap;
-    cfg->tile_width = lc.wide ? 256 : 64;
+    cfg->tile_width = two ? lc.fuse_width : (lc.wide ? 256 : 64);
     cfg->max_waves = lc.max_waves;
     cfg->xcd_rows = lc.xcd_rows;
     cfg->stores = lc.stores;
+    cfg->fuse = two ? 2 : 1;
     return LBM_OK;
 }
 
@@ -1035,6 +1148,7 @@ int lbm_adjoint_segment(lbm_ctx *c, int32_t inst, void *states, int32_t nsteps, 
     // context's own store kind (state images are always in the two-buffer layout).
     StepArgs a;
     a.d = c->h_desc[inst];
+    if (a.d.lc.fuse == 2) a.d.lc = in.lc1;
     if (a.d.lc.stores == 2) a.d.lc.stores = 1;
     a.parity = 0;
     for (int32_t j = 0; j + 1 < nsteps; ++j) {

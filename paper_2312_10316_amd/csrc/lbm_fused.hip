@@ -1,0 +1,421 @@
+// lbm_fused.hip -- D2Q9 kernels whose blocks walk a tile top to bottom with an LDS ring (gfx950): two
+// time steps of the TRT-R update per launch (temporal blocking), and one step with the flux form of the
+// auxiliary term.
+//
+// A step is bound by memory traffic: every population is read once and written once per step
+// (Sec. 2.2, Eq. (14) pulls nine values and stores nine).  Fusing two steps halves that traffic: a
+// block reads the state at t_n for its tile plus a halo, computes the intermediate state t_{n+1} of
+// the tile and a one-node frame around it into LDS, and writes only the state at t_{n+2}.  Every node
+// of both steps is evaluated by the same per-node arithmetic as the single-step kernel (the same
+// inlined collision), and the intermediate populations go through the storage codec exactly as if
+// they had been written to and read back from memory, so two fused steps are bitwise two single
+// steps.
+//
+// Block: NW "interior" waves (lane = column, W = 64 NW output columns x0 .. x0 + W - 1) and one
+// "frame" wave whose lanes 0 and 1 compute the intermediate nodes just left and right of the tile
+// (columns x0 - 1 and x0 + W, wrapped).  The block walks its H output rows top to bottom:
+// iteration r computes intermediate row r (from state rows r - 1 .. r + 1 in HBM/L2) and, one row
+// behind, output row r - 1 (from intermediate rows r - 2 .. r).  Intermediate populations that move
+// along x (i = 1, 3, 5, 6, 7, 8) are exchanged through a four-row LDS ring; those with e_x = 0
+// (i = 0, 2, 4) stay in the registers of the lane that computed them.  Four ring rows let the next
+// intermediate row be written while the previous output row is still being read, so one barrier
+// per row suffices.
+#include "lbm_internal.h"
+#include "lbm_kernel_common.h"
+
+namespace lbm {
+namespace {
+
+// LDS ring plane of each population that moves along x (-1: kept in registers).
+constexpr int kPlane[9] = {-1, 0, -1, 1, -1, 2, 3, 4, 5};
+
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, bool MRT, int NW, bool CST>
+__global__ __launch_bounds__(64 * (NW + 1)) void step2_kernel(const StepArgs a)
+{
+    using St = typename ModeTraits<MODE>::St;
+    using M = typename ModeTraits<MODE>::M;
+    using T = typename St::T;
+    using C = Codec<St, M>;
+    constexpr int W = 64 * NW, WC = W + 2;
+    __shared__ T ring[4][6][WC];
+
+    const InstDesc &d = a.d;
+    const int nx = d.L.nx, ny = d.L.ny;
+    const int64_t pitch = d.L.pitch;
+    const int H = d.lc.rows;
+    const int ntx = (nx + W - 1) / W;
+    const int t = tile_of_block(blockIdx.x, gridDim.x, d.lc.xcd_remap, ntx, d.lc.xcd_rows);
+    const int x0 = (t % ntx) * W, y0 = (t / ntx) * H;
+    const int y1 = min(y0 + H, ny);  // output rows y0 .. y1 - 1
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = (int)(threadIdx.x & 63u);
+    const bool frame = wave == NW;
+    // ring column of this thread's intermediate node (column x0 - 1 + c of the lattice, wrapped)
+    const int c = frame ? (lane == 0 ? 0 : (lane == 1 ? W + 1 : -1)) : 1 + wave * 64 + lane;
+    const bool act = c >= 0;
+    int xi = x0 - 1 + (act ? c : 1);
+    xi = xi % nx;
+    xi = xi < 0 ? xi + nx : xi;
+    const bool live = !frame && x0 + wave * 64 + lane < nx;  // an output column of this tile
+    const unsigned ux_ = (unsigned)xi;
+    const unsigned uxm = ux_ == 0 ? (unsigned)nx - 1 : ux_ - 1;
+    const unsigned uxp = ux_ == (unsigned)nx - 1 ? 0u : ux_ + 1;
+    const unsigned bc = ux_ * (unsigned)sizeof(T), bm = uxm * (unsigned)sizeof(T), bp = uxp * (unsigned)sizeof(T);
+    const unsigned fc = ux_ * (unsigned)sizeof(M), fm = uxm * (unsigned)sizeof(M), fp = uxp * (unsigned)sizeof(M);
+    const unsigned pb = (unsigned)(pitch * (int64_t)sizeof(T));
+
+    const T *__restrict__ src = static_cast<const T *>(d.buf[a.parity]);
+    T *__restrict__ dst = static_cast<T *>(d.buf[a.parity ^ 1]);
+    const M *__restrict__ u = static_cast<const M *>(d.u);
+    const M *__restrict__ kf = static_cast<const M *>(d.k);
+    const M *__restrict__ sf = static_cast<const M *>(d.s);
+    const M lam = (M)d.lambda;
+    Relax<M> rconst;
+    rconst.w1 = (M)d.w1;
+    rconst.w2 = (M)d.w2;
+    rconst.beta = (M)d.beta;
+    rconst.w3 = (M)d.w3;
+
+    auto wrapr = [ny](int r) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); };
+    // velocity at this column, rows r - 2 .. r + 1 of the walk (mm, m, c, p)
+    const int rs = y0 - 1;
+    M ux_mm = M(0), uy_mm = M(0);
+    M ux_m = ld_at(u + (int64_t)wrapr(rs - 1) * 2 * pitch, fc), uy_m = ld_at(u + ((int64_t)wrapr(rs - 1) * 2 + 1) * pitch, fc);
+    M ux_c = ld_at(u + (int64_t)wrapr(rs) * 2 * pitch, fc), uy_c = ld_at(u + ((int64_t)wrapr(rs) * 2 + 1) * pitch, fc);
+    // x-differences of u, the relaxation and the source of the previous intermediate row (reused by
+    // the output node of that row, which sits in the same column)
+    M dxux_m = M(0), dxuy_m = M(0);
+    Relax<M> r_m = rconst;
+    M s_m = M(0);
+    // e_x = 0 populations of earlier intermediate rows at this column, as a reader would decode them
+    M p0_m = M(0), p2_m = M(0), p2_mm = M(0);
+
+    for (int r = rs; r <= y1; ++r) {
+        const int rw = wrapr(r), rwm = wrapr(r - 1), rwp = wrapr(r + 1);
+        const M *__restrict__ un = u + (int64_t)rwp * 2 * pitch;
+        const M ux_p = ld_at(un, fc), uy_p = ld_at(un + pitch, fc);
+        // ---- phase 1: intermediate node (xi, r) of step n + 1 -----------------------------------------
+        M dxux = M(0), dxuy = M(0), s = M(0);
+        Relax<M> rr = rconst;
+        M P[9] = {};
+        if (act) {
+            const T *__restrict__ rm = src + (int64_t)rwm * 9 * pitch;
+            const T *__restrict__ rc = src + (int64_t)rw * 9 * pitch;
+            const T *__restrict__ rp = src + (int64_t)rwp * 9 * pitch;
+            M g[9];
+            g[0] = C::dec(ld_at(rc, bc), 0, d.f16);
+            g[1] = C::dec(ld_at(rc + pitch, bm), 1, d.f16);
+            g[2] = C::dec(ld_at(rm + 2 * pitch, bc), 2, d.f16);
+            g[3] = C::dec(ld_at(rc + 3 * pitch, bp), 3, d.f16);
+            g[4] = C::dec(ld_at(rp + 4 * pitch, bc), 4, d.f16);
+            g[5] = C::dec(ld_at(rm + 5 * pitch, bm), 5, d.f16);
+            g[6] = C::dec(ld_at(rm + 6 * pitch, bp), 6, d.f16);
+            g[7] = C::dec(ld_at(rp + 7 * pitch, bp), 7, d.f16);
+            g[8] = C::dec(ld_at(rp + 8 * pitch, bm), 8, d.f16);
+            M Ax = M(0), Ay = M(0);
+            const M *__restrict__ uc = u + (int64_t)rw * 2 * pitch;
+            if (AUX == 0) {  // Eq. (16): phi u_b d_b u_a, central differences of u
+                const M phi = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
+                dxux = (ld_at(uc, fp) - ld_at(uc, fm)) * M(0.5);
+                dxuy = (ld_at(uc + pitch, fp) - ld_at(uc + pitch, fm)) * M(0.5);
+                const M dyux = (ux_p - ux_m) * M(0.5);
+                const M dyuy = (uy_p - uy_m) * M(0.5);
+                Ax = phi * (ux_c * dxux + uy_c * dyux);
+                Ay = phi * (ux_c * dxuy + uy_c * dyuy);
+            }
+            rr = HAS_K ? relax_from_k<M>(ld_at(kf + (int64_t)rw * pitch, fc), lam, rconst.w3) : rconst;
+            s = HAS_S ? ld_at(sf + (int64_t)rw * pitch, fc) : M(0);
+            collide<M, MRT>(g, ux_c, uy_c, rr, Ax, Ay, s, P);
+            T(*slot)[WC] = ring[r & 3];
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                if (kPlane[i] >= 0) slot[kPlane[i]][c] = C::enc(P[i], i, d.f16);
+        }
+        __syncthreads();
+        // ---- phase 2: output node (x, y = r - 1) of step n + 2 ---------------------------------------
+        const M p4 = C::dec(C::enc(P[4], 4, d.f16), 4, d.f16);
+        if (!frame && r >= y0 + 1) {
+            const int y = r - 1;
+            M g[9];
+            T(*const sy)[WC] = ring[y & 3];
+            T(*const sm)[WC] = ring[(y - 1) & 3];
+            T(*const sp)[WC] = ring[(y + 1) & 3];
+            g[0] = p0_m;
+            g[1] = C::dec(sy[kPlane[1]][c - 1], 1, d.f16);
+            g[2] = p2_mm;
+            g[3] = C::dec(sy[kPlane[3]][c + 1], 3, d.f16);
+            g[4] = p4;
+            g[5] = C::dec(sm[kPlane[5]][c - 1], 5, d.f16);
+            g[6] = C::dec(sm[kPlane[6]][c + 1], 6, d.f16);
+            g[7] = C::dec(sp[kPlane[7]][c + 1], 7, d.f16);
+            g[8] = C::dec(sp[kPlane[8]][c - 1], 8, d.f16);
+            M Ax = M(0), Ay = M(0);
+            if (AUX == 0) {
+                const M phi = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
+                const M dyux = (ux_c - ux_mm) * M(0.5);
+                const M dyuy = (uy_c - uy_mm) * M(0.5);
+                Ax = phi * (ux_m * dxux_m + uy_m * dyux);
+                Ay = phi * (ux_m * dxuy_m + uy_m * dyuy);
+            }
+            M Q[9];
+            collide<M, MRT>(g, ux_m, uy_m, r_m, Ax, Ay, s_m, Q);
+            if (live) {
+                T *__restrict__ out = dst + (int64_t)y * 9 * pitch;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    if constexpr (CST) st_at(out, bc + (unsigned)i * pb, C::enc(Q[i], i, d.f16));
+                    else st_nt_at(out, bc + (unsigned)i * pb, C::enc(Q[i], i, d.f16));
+                }
+            }
+        }
+        // roll the walk down one row
+        p2_mm = p2_m;
+        p2_m = C::dec(C::enc(P[2], 2, d.f16), 2, d.f16);
+        p0_m = C::dec(C::enc(P[0], 0, d.f16), 0, d.f16);
+        dxux_m = dxux;
+        dxuy_m = dxuy;
+        r_m = rr;
+        s_m = s;
+        ux_mm = ux_m;
+        uy_mm = uy_m;
+        ux_m = ux_c;
+        uy_m = uy_c;
+        ux_c = ux_p;
+        uy_c = uy_p;
+    }
+}
+
+// One step with the flux form of the auxiliary term, d_b(phi u_a u_b) - u_a d_b(phi u_b) (Sec. 2.3;
+// equal to Eq. (16) by the product rule), which needs phi at the four axis neighbours at the same time
+// level.  Same block layout as the fused kernel: NW interior waves and a frame wave whose lanes 0 and
+// 1 pull the nodes just left and right of the tile.  Iteration r pulls row r (each population read
+// once per tile row, plus two frame rows per tile), sums phi(r) and puts it in a four-row LDS ring;
+// one row behind, the node (x, r - 1) takes phi at x -+ 1 from the ring, phi at r - 2 and r from its
+// own registers, and collides the populations it pulled in the previous iteration.  Every phi is the
+// sum of its node's nine populations in index order, as in the other kernels, so the results are
+// bitwise those of any other launch shape.
+template <int MODE, bool HAS_K, bool HAS_S, bool MRT, int NW, bool CST>
+__global__ __launch_bounds__(64 * (NW + 1)) void flux_walk_kernel(const StepArgs a)
+{
+    using St = typename ModeTraits<MODE>::St;
+    using M = typename ModeTraits<MODE>::M;
+    using T = typename St::T;
+    using C = Codec<St, M>;
+    constexpr int W = 64 * NW, WC = W + 2;
+    __shared__ M phis[4][WC];
+
+    const InstDesc &d = a.d;
+    const int nx = d.L.nx, ny = d.L.ny;
+    const int64_t pitch = d.L.pitch;
+    const int H = d.lc.rows;
+    const int ntx = (nx + W - 1) / W;
+    const int t = tile_of_block(blockIdx.x, gridDim.x, d.lc.xcd_remap, ntx, d.lc.xcd_rows);
+    const int x0 = (t % ntx) * W, y0 = (t / ntx) * H;
+    const int y1 = min(y0 + H, ny);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = (int)(threadIdx.x & 63u);
+    const bool frame = wave == NW;
+    const int c = frame ? (lane == 0 ? 0 : (lane == 1 ? W + 1 : -1)) : 1 + wave * 64 + lane;
+    const bool act = c >= 0;
+    int xi = x0 - 1 + (act ? c : 1);
+    xi = xi % nx;
+    xi = xi < 0 ? xi + nx : xi;
+    const bool live = !frame && x0 + wave * 64 + lane < nx;
+    const unsigned ux_ = (unsigned)xi;
+    const unsigned uxm = ux_ == 0 ? (unsigned)nx - 1 : ux_ - 1;
+    const unsigned uxp = ux_ == (unsigned)nx - 1 ? 0u : ux_ + 1;
+    const unsigned bc = ux_ * (unsigned)sizeof(T), bm = uxm * (unsigned)sizeof(T), bp = uxp * (unsigned)sizeof(T);
+    const unsigned fc = ux_ * (unsigned)sizeof(M), fm = uxm * (unsigned)sizeof(M), fp = uxp * (unsigned)sizeof(M);
+    const unsigned pb = (unsigned)(pitch * (int64_t)sizeof(T));
+
+    const T *__restrict__ src = static_cast<const T *>(d.buf[a.parity]);
+    T *__restrict__ dst = static_cast<T *>(d.buf[a.parity ^ 1]);
+    const M *__restrict__ u = static_cast<const M *>(d.u);
+    const M *__restrict__ kf = static_cast<const M *>(d.k);
+    const M *__restrict__ sf = static_cast<const M *>(d.s);
+    const M lam = (M)d.lambda;
+    Relax<M> rconst;
+    rconst.w1 = (M)d.w1;
+    rconst.w2 = (M)d.w2;
+    rconst.beta = (M)d.beta;
+    rconst.w3 = (M)d.w3;
+    auto wrapr = [ny](int r) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); };
+
+    // the nine stored values the node (xi, r) pulls, loaded one iteration ahead
+    auto pull_raw = [&](int r, T (&raw)[9]) {
+        const T *__restrict__ rm = src + (int64_t)wrapr(r - 1) * 9 * pitch;
+        const T *__restrict__ rc = src + (int64_t)wrapr(r) * 9 * pitch;
+        const T *__restrict__ rp = src + (int64_t)wrapr(r + 1) * 9 * pitch;
+        raw[0] = ld_at(rc, bc);
+        raw[1] = ld_at(rc + pitch, bm);
+        raw[2] = ld_at(rm + 2 * pitch, bc);
+        raw[3] = ld_at(rc + 3 * pitch, bp);
+        raw[4] = ld_at(rp + 4 * pitch, bc);
+        raw[5] = ld_at(rm + 5 * pitch, bm);
+        raw[6] = ld_at(rm + 6 * pitch, bp);
+        raw[7] = ld_at(rp + 7 * pitch, bp);
+        raw[8] = ld_at(rp + 8 * pitch, bm);
+    };
+    M gp[9] = {};                     // populations of the previous row at this column
+    M phi_m = M(0), phi_mm = M(0);    // phi of rows r - 1 and r - 2
+    M ux_m = M(0), uy_m = M(0), ux_mm = M(0), uy_mm = M(0);  // u of rows r - 1 and r - 2
+    T raw_n[9] = {};
+    if (act) pull_raw(y0 - 1, raw_n);
+    for (int r = y0 - 1; r <= y1; ++r) {
+        const int rw = wrapr(r);
+        T raw[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) raw[i] = raw_n[i];
+        if (act && r < y1) pull_raw(r + 1, raw_n);
+        M g[9] = {};
+        M phir = M(0);
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) g[i] = C::dec(raw[i], i, d.f16);
+            phir = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
+            phis[r & 3][c] = phir;
+        }
+        const M *__restrict__ ur = u + (int64_t)rw * 2 * pitch;
+        const M ux_c = frame ? M(0) : ld_at(ur, fc), uy_c = frame ? M(0) : ld_at(ur + pitch, fc);  // u of row r
+        __syncthreads();
+        if (!frame && r >= y0 + 1) {  // node (x, y = r - 1)
+            const int y = r - 1;
+            const int yw = wrapr(y);
+            const M pw = phis[y & 3][c - 1], pe = phis[y & 3][c + 1];
+            const M *__restrict__ uy_row = u + (int64_t)yw * 2 * pitch;
+            const M uxw = ld_at(uy_row, fm), uyw = ld_at(uy_row + pitch, fm);
+            const M uxe = ld_at(uy_row, fp), uye = ld_at(uy_row + pitch, fp);
+            const M fwx = pw * uxw, fex = pe * uxe;           // phi u_x at the west and east neighbours
+            const M fsy = phi_mm * uy_mm, fny = phir * uy_c;  // phi u_y at the south and north neighbours
+            const M div = (fex - fwx) * M(0.5) + (fny - fsy) * M(0.5);
+            const M Ax = (fex * uxe - fwx * uxw) * M(0.5) + (fny * ux_c - fsy * ux_mm) * M(0.5) - ux_m * div;
+            const M Ay = (fex * uye - fwx * uyw) * M(0.5) + (fny * uy_c - fsy * uy_mm) * M(0.5) - uy_m * div;
+            const Relax<M> rr = HAS_K ? relax_from_k<M>(ld_at(kf + (int64_t)yw * pitch, fc), lam, rconst.w3) : rconst;
+            const M s = HAS_S ? ld_at(sf + (int64_t)yw * pitch, fc) : M(0);
+            M P[9];
+            collide<M, MRT>(gp, ux_m, uy_m, rr, Ax, Ay, s, P);
+            if (live) {
+                T *__restrict__ out = dst + (int64_t)yw * 9 * pitch;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    if constexpr (CST) st_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, d.f16));
+                    else st_nt_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, d.f16));
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) gp[i] = g[i];
+        phi_mm = phi_m;
+        phi_m = phir;
+        ux_mm = ux_m;
+        uy_mm = uy_m;
+        ux_m = ux_c;
+        uy_m = uy_c;
+    }
+}
+
+template <int MODE, bool MRT, int NW, bool CST>
+hipError_t launch_flux_nw(const StepArgs &a, hipStream_t st)
+{
+    const int W = 64 * NW, H = a.d.lc.rows;
+    const int nblocks = ((a.d.L.nx + W - 1) / W) * ((a.d.L.ny + H - 1) / H);
+    const size_t lds = (size_t)a.d.lc.lds_reserve;
+    const dim3 block(64 * (NW + 1));
+    const bool hk = a.d.has_k, hs = a.d.has_s;
+    if (hk && hs) flux_walk_kernel<MODE, true, true, MRT, NW, CST><<<nblocks, block, lds, st>>>(a);
+    else if (hk) flux_walk_kernel<MODE, true, false, MRT, NW, CST><<<nblocks, block, lds, st>>>(a);
+    else if (hs) flux_walk_kernel<MODE, false, true, MRT, NW, CST><<<nblocks, block, lds, st>>>(a);
+    else flux_walk_kernel<MODE, false, false, MRT, NW, CST><<<nblocks, block, lds, st>>>(a);
+    return hipGetLastError();
+}
+
+template <int MODE, bool MRT>
+hipError_t launch_flux_var(const StepArgs &a, hipStream_t st)
+{
+    const bool cst = a.d.lc.stores == 1;
+    if (a.d.lc.wide)
+        return cst ? launch_flux_nw<MODE, MRT, 4, true>(a, st) : launch_flux_nw<MODE, MRT, 4, false>(a, st);
+    return cst ? launch_flux_nw<MODE, MRT, 1, true>(a, st) : launch_flux_nw<MODE, MRT, 1, false>(a, st);
+}
+
+template <int MODE>
+hipError_t launch_flux_mode(const StepArgs &a, hipStream_t st)
+{
+    return a.d.w3 != 0.0 ? launch_flux_var<MODE, true>(a, st) : launch_flux_var<MODE, false>(a, st);
+}
+
+template <int MODE, int AUX, bool MRT, int NW, bool CST>
+hipError_t launch_fused_nw(const StepArgs &a, hipStream_t st)
+{
+    const int W = 64 * NW, H = a.d.lc.rows;
+    const int nblocks = ((a.d.L.nx + W - 1) / W) * ((a.d.L.ny + H - 1) / H);
+    const size_t lds = (size_t)a.d.lc.lds_reserve;  // unused LDS that caps the resident waves
+    const dim3 block(64 * (NW + 1));
+    const bool hk = a.d.has_k, hs = a.d.has_s;
+    if (hk && hs) step2_kernel<MODE, AUX, true, true, MRT, NW, CST><<<nblocks, block, lds, st>>>(a);
+    else if (hk) step2_kernel<MODE, AUX, true, false, MRT, NW, CST><<<nblocks, block, lds, st>>>(a);
+    else if (hs) step2_kernel<MODE, AUX, false, true, MRT, NW, CST><<<nblocks, block, lds, st>>>(a);
+    else step2_kernel<MODE, AUX, false, false, MRT, NW, CST><<<nblocks, block, lds, st>>>(a);
+    return hipGetLastError();
+}
+
+template <int MODE, int AUX, bool MRT>
+hipError_t launch_fused_var(const StepArgs &a, hipStream_t st)
+{
+    const bool cst = a.d.lc.stores == 1;
+    switch (a.d.lc.fuse_width) {
+    case 128: return cst ? launch_fused_nw<MODE, AUX, MRT, 2, true>(a, st) : launch_fused_nw<MODE, AUX, MRT, 2, false>(a, st);
+    case 256: return cst ? launch_fused_nw<MODE, AUX, MRT, 4, true>(a, st) : launch_fused_nw<MODE, AUX, MRT, 4, false>(a, st);
+    case 512: return cst ? launch_fused_nw<MODE, AUX, MRT, 8, true>(a, st) : launch_fused_nw<MODE, AUX, MRT, 8, false>(a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// TRT-R only (the MRT-R operator runs single steps).
+template <int MODE, int AUX>
+hipError_t launch_fused_aux(const StepArgs &a, hipStream_t st)
+{
+    return a.d.w3 != 0.0 ? hipErrorInvalidValue : launch_fused_var<MODE, AUX, false>(a, st);
+}
+
+template <int MODE>
+hipError_t launch_fused_mode(int aux, const StepArgs &a, hipStream_t st)
+{
+    switch (aux) {
+    case 0: return launch_fused_aux<MODE, 0>(a, st);
+    case 2: return launch_fused_aux<MODE, 2>(a, st);
+    default: return hipErrorInvalidValue;  // the flux form needs phi at neighbours of the same step
+    }
+}
+
+}  // namespace
+
+hipError_t launch_flux_walk(int mode, const StepArgs &a, hipStream_t st)
+{
+    if (a.d.L.q != 9 || a.d.bckind != 0 || a.d.lc.stores == 2) return hipErrorInvalidValue;
+    if (a.d.lc.rows < 1 || a.d.lc.rows > 1024 || a.d.lc.lds_reserve < 0 || a.d.lc.lds_reserve > 65536)
+        return hipErrorInvalidValue;
+    switch (mode) {
+    case MODE_F64_F64: return launch_flux_mode<MODE_F64_F64>(a, st);
+    case MODE_F64_F32: return launch_flux_mode<MODE_F64_F32>(a, st);
+    case MODE_F32_F32: return launch_flux_mode<MODE_F32_F32>(a, st);
+    case MODE_F16S_F32: return launch_flux_mode<MODE_F16S_F32>(a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step2(int mode, int aux, const StepArgs &a, hipStream_t st)
+{
+    if (a.d.L.q != 9 || a.d.bckind != 0 || a.d.lc.stores == 2) return hipErrorInvalidValue;
+    if (a.d.lc.rows < 1 || a.d.lc.rows > 1024 || a.d.lc.lds_reserve < 0 || a.d.lc.lds_reserve > 65536)
+        return hipErrorInvalidValue;
+    switch (mode) {
+    case MODE_F64_F64: return launch_fused_mode<MODE_F64_F64>(aux, a, st);
+    case MODE_F64_F32: return launch_fused_mode<MODE_F64_F32>(aux, a, st);
+    case MODE_F32_F32: return launch_fused_mode<MODE_F32_F32>(aux, a, st);
+    case MODE_F16S_F32: return launch_fused_mode<MODE_F16S_F32>(aux, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace lbm

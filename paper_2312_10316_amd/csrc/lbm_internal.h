@@ -54,6 +54,8 @@ struct Launch {
     int32_t lds_reserve;  // dynamic LDS bytes reserved per block to enforce max_waves (0: none)
     int32_t xcd_rows;     // tile rows per block of order 3
     int32_t stores;       // 0: non-temporal stores of the new state; 1: cached; 2: one buffer in place, cached
+    int32_t fuse;         // time steps per launch: 1 (0 reads as 1), or 2 (step2_kernel, lbm_fused.hip)
+    int32_t fuse_width;   // fused launches: output columns per tile (128, 256 or 512); rows = tile height
     int32_t pad_;
 };
 
@@ -189,6 +191,12 @@ struct AdjArgs {
 
 // Launchers (lbm_kernels.hip, lbm_adjoint.hip).  All return the hipError_t of the launch.
 hipError_t launch_step(int mode, int aux, const StepArgs &a, hipStream_t st);
+// Two steps per launch (lbm_fused.hip): D2Q9, periodic, aux LOCAL or NONE, two buffers (reads
+// buf[parity], writes buf[parity ^ 1] two steps later).  lc.fuse_width columns x lc.rows rows per tile.
+hipError_t launch_step2(int mode, int aux, const StepArgs &a, hipStream_t st);
+// One step with the flux form of the auxiliary term (lbm_fused.hip): D2Q9, periodic, two buffers;
+// tiles of 256 (lc.wide) or 64 columns by lc.rows rows.
+hipError_t launch_flux_walk(int mode, const StepArgs &a, hipStream_t st);
 hipError_t launch_batched_step(int mode, int aux, const BatchArgs &a, int nblocks, int lds_reserve, hipStream_t st);
 hipError_t launch_init(int mode, const InitArgs &a, hipStream_t st);
 hipError_t launch_prep(int mode, const PrepArgs &a, hipStream_t st);

@@ -63,7 +63,8 @@ class lbm_stats(ctypes.Structure):
 
 class lbm_launch(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int32), ("xcd_remap", ctypes.c_int32), ("tile_width", ctypes.c_int32),
-                ("max_waves", ctypes.c_int32), ("xcd_rows", ctypes.c_int32), ("stores", ctypes.c_int32)]
+                ("max_waves", ctypes.c_int32), ("xcd_rows", ctypes.c_int32), ("stores", ctypes.c_int32),
+                ("fuse", ctypes.c_int32)]
 
 
 class lbm_batch(ctypes.Structure):
@@ -248,8 +249,9 @@ def lbm_state_load(ctx, inst: int, src: torch.Tensor, step: int) -> None:
 
 
 def lbm_set_launch(ctx, inst: int, rows: int, xcd_remap: int = 1, tile_width: int = 64, max_waves: int = 0,
-                   xcd_rows: int = 0, stores: int = 0) -> None:
-    cfg = lbm_launch(int(rows), int(xcd_remap), int(tile_width), int(max_waves), int(xcd_rows), int(stores))
+                   xcd_rows: int = 0, stores: int = 0, fuse: int = 1) -> None:
+    cfg = lbm_launch(int(rows), int(xcd_remap), int(tile_width), int(max_waves), int(xcd_rows), int(stores),
+                     int(fuse))
     _check(lib().lbm_set_launch(ctx, int(inst), ctypes.byref(cfg)))
 
 
@@ -257,7 +259,7 @@ def lbm_get_launch(ctx, inst: int = 0) -> dict:
     cfg = lbm_launch()
     _check(lib().lbm_get_launch(ctx, int(inst), ctypes.byref(cfg)))
     return {"rows": cfg.rows, "xcd_remap": cfg.xcd_remap, "tile_width": cfg.tile_width, "max_waves": cfg.max_waves,
-            "xcd_rows": cfg.xcd_rows, "stores": cfg.stores}
+            "xcd_rows": cfg.xcd_rows, "stores": cfg.stores, "fuse": cfg.fuse}
 
 
 def lbm_set_batch(ctx, policy: int, blocks: int = 0, max_waves: int = 0) -> None:

@@ -66,8 +66,8 @@ class Solver:
         L.lbm_state_load(self.ctx, inst, buf, step)
 
     def set_launch(self, rows: int, xcd_remap: int = 1, inst: int = -1, tile_width: int = 64,
-                   max_waves: int = 0, xcd_rows: int = 0, stores: int = 0) -> None:
-        L.lbm_set_launch(self.ctx, inst, rows, xcd_remap, tile_width, max_waves, xcd_rows, stores)
+                   max_waves: int = 0, xcd_rows: int = 0, stores: int = 0, fuse: int = 1) -> None:
+        L.lbm_set_launch(self.ctx, inst, rows, xcd_remap, tile_width, max_waves, xcd_rows, stores, fuse)
 
     def get_launch(self, inst: int = 0) -> dict:
         return L.lbm_get_launch(self.ctx, inst)

@@ -68,13 +68,25 @@ def test_summarize_scales_counters_by_the_copy_kernel(tmp_path):
                    [[STEP.format(m=2, bc=0, mrt="false", rows=1, cst="false"), counter, step_val]] * 3 + [[COPY, counter, copy_val]])
     pmc = {(c, n): str(run / f"pmc_{c.lower()}_{n}") for c in ("FETCH_SIZE", "WRITE_SIZE")}
     out = tmp_path / "out"
-    bench.summarize_profiles(str(run / "trace"), pmc, str(out), "cmd", ["c1", "c2"])
+    bench.summarize_profiles({n: str(run / "trace")}, pmc, str(out), {n: "cmd"}, ["c1", "c2"])
     d = json.load(open(out / "step_kernel_pmc.json"))
     e = d["entries"][f"f32_{n}"]
     assert abs(e["fetch_scale"] - 0.5) < 1e-12 and abs(e["write_scale"] - 1.0) < 1e-12
     assert abs(e["traffic_over_algorithmic"] - 1.0) < 1e-12
     assert d["kernel_hash"] == bench.kernel_hash()
-    assert "57.00" in open(out / "step_kernel_trace_2048.md").read()
+    trace = open(out / "step_kernel_trace_2048.md").read()
+    assert "57.00" in trace
+    # MLUPS and GB/s follow from the average duration: 2048^2 nodes in 57 us, 80 B per node
+    assert f"| {n * n / 57e-6 / 1e6:.0f} | {n * n / 57e-6 * 80 / 1e9:.0f} |" in trace
+
+
+def test_roofline_bound_follows_where_the_state_lives():
+    assert bench.roofline_bound(0) == "hbm"
+    assert bench.roofline_bound(1) == "infinity_cache"
+    assert bench.roofline_bound(2) == "infinity_cache"
+    # the cached copy is not mistaken for the calibration copy
+    assert bench._kernel_label("lbm::(anonymous namespace)::copy_cached_kernel(float __vector(4) const*, "
+                               "float __vector(4)*, long)") is None
 
 
 def test_traffic_is_withheld_when_the_kernel_changed(tmp_path, monkeypatch):

@@ -183,3 +183,118 @@ def test_adjoint_rejects_unsupported_modes():
             lbm.lbm_adjoint_bytes(s.ctx)
         assert ei.value.status == lbm.LBM_E_UNSUPPORTED
         s.close()
+
+
+@pytest.mark.parametrize("mode,n", [("f64", 7), ("f64", 6), ("f32", 5), ("f64s_f32m", 1)])
+def test_adjoint_segment_equals_single_adjoint_steps(mode, n):
+    """lbm_adjoint_segment (recomputation image to image, then n adjoint steps, one library call)
+    gives bitwise the states, lam and dL/dD of the same segment run step by step through lbm_step,
+    lbm_state_save and lbm_adjoint_step; the context's own state is left untouched."""
+    nx, ny = 70, 45
+    pr = tiny_problem(nx, ny, U0=1.1, c=3.0)
+    rng = np.random.default_rng(43)
+    D = pr["D0"] * (1 + 0.4 * rng.uniform(-1, 1, (ny, nx)))
+    p = lbm.make_params(nx, ny, pr["dx"], pr["dt"], pr["lam"], pr["D0"], mode)
+    s = Solver([(p, {"phi0": dev(pr["phi0"]), "ux": dev(pr["ux"]), "uy": dev(pr["uy"]), "D": dev(D)})])
+    s.step(4)
+    ck = s.state_save()
+    mdt = torch.float64 if mode == "f64" else torch.float32
+    nb = lbm.lbm_adjoint_bytes(s.ctx)
+    lam0 = torch.from_numpy(rng.uniform(-1, 1, nb // mdt.itemsize)).to(mdt).cuda()
+    # reference: step by step
+    states = [ck]
+    for _ in range(n - 1):
+        s.step(1)
+        states.append(s.state_save())
+    a, b = lam0.clone(), torch.empty_like(lam0)
+    g_ref = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    for j in reversed(range(n)):
+        lbm.lbm_adjoint_step(s.ctx, 0, states[j], a, b, g_ref)
+        a, b = b, a
+    before = s.state_save()
+    sb = lbm.lbm_state_bytes(s.ctx)
+    imgs = torch.empty(n * sb, dtype=torch.uint8, device="cuda")
+    imgs[:sb].copy_(ck)
+    lam = lam0.clone()
+    g = torch.zeros_like(g_ref)
+    lbm.lbm_adjoint_segment(s.ctx, 0, imgs, n, lam, torch.empty_like(lam), g)
+    torch.cuda.synchronize()
+    pitch = lbm.pitch_of(p)
+    sdt = torch.float64 if mode != "f32" else torch.float32
+
+    def live(img):  # the nine population rows of every lattice row, padding columns dropped
+        return img.view(sdt)[:ny * 9 * pitch].reshape(ny, 9, pitch)[:, :, :nx]
+
+    for j in range(n):  # recomputed images: equal populations (padding columns are not written)
+        assert torch.equal(live(imgs[j * sb:(j + 1) * sb]), live(states[j])), j
+
+    def live_lam(x):
+        return x[:ny * 9 * pitch].reshape(ny, 9, pitch)[:, :, :nx]
+
+    assert torch.equal(live_lam(lam), live_lam(a))
+    assert torch.equal(g, g_ref)
+    assert torch.equal(s.state_save(), before)
+    s.close()
+
+
+def test_set_diffusion_equals_a_new_context_and_rejects_bad_fields():
+    """A context whose D field is replaced (lbm_set_diffusion) and whose state is reloaded runs
+    bitwise as a context created with that D; errors for a constant-D instance and a D <= 0."""
+    nx, ny = 70, 45
+    pr = tiny_problem(nx, ny, U0=1.1, c=3.0)
+    rng = np.random.default_rng(47)
+    D1 = pr["D0"] * (1 + 0.4 * rng.uniform(-1, 1, (ny, nx)))
+    D2 = pr["D0"] * (1 + 0.4 * rng.uniform(-1, 1, (ny, nx)))
+    fields = {"phi0": dev(pr["phi0"]), "ux": dev(pr["ux"]), "uy": dev(pr["uy"])}
+    for mode in ("f64", "f32", "f16s"):
+        p = lbm.make_params(nx, ny, pr["dx"], pr["dt"], pr["lam"], pr["D0"], mode)
+        a = Solver([(p, dict(fields, D=dev(D1)))])
+        init = a.state_save()
+        a.step(9)
+        a.set_diffusion(dev(D2))
+        a.state_load(init, 0)
+        a.step(9)
+        b = Solver([(p, dict(fields, D=dev(D2)))])
+        b.step(9)
+        assert torch.equal(a.state_save(), b.state_save())
+        with pytest.raises(lbm.LbmError) as ei:
+            a.set_diffusion(dev(-D2))
+        assert ei.value.status == lbm.LBM_E_ARG
+        a.close()
+        b.close()
+    c = Solver([(lbm.make_params(nx, ny, pr["dx"], pr["dt"], pr["lam"], pr["D0"], "f64"), fields)])
+    with pytest.raises(lbm.LbmError) as ei:
+        c.set_diffusion(dev(D1))
+    assert ei.value.status == lbm.LBM_E_STATE
+    c.close()
+
+
+def test_reused_context_gives_the_gradients_of_fresh_ones():
+    """One RunSpec (one context) through two forward/backward passes with different D, with an
+    unrelated forward in between, gives bitwise the gradients of separate specs."""
+    pr = tiny_problem(24, 20)
+    nsteps = 13
+    rng = np.random.default_rng(53)
+    Ds = [pr["D0"] * (1 + 0.3 * rng.uniform(-1, 1, (20, 24))) for _ in range(3)]
+    target = dev(_target(pr, nsteps))
+
+    def grad_of(spec, Dnp):
+        D = dev(Dnp).requires_grad_(True)
+        phi = adjoint.simulate(D, spec)
+        (0.5 * ((phi - target) ** 2).sum()).backward()
+        return D.grad.clone()
+
+    for mode in ("f64", "f32"):
+        shared = _spec(pr, nsteps, mode, segment=4)
+        g0 = grad_of(shared, Ds[0])
+        D = dev(Ds[1]).requires_grad_(True)
+        phi = adjoint.simulate(D, shared)
+        with torch.no_grad():
+            adjoint.simulate(dev(Ds[2]), shared)  # a forward with another D before the backward
+        (0.5 * ((phi - target) ** 2).sum()).backward()
+        g1 = D.grad.clone()
+        shared.close()
+        for Dnp, g in ((Ds[0], g0), (Ds[1], g1)):
+            fresh = _spec(pr, nsteps, mode, segment=4)
+            assert torch.equal(grad_of(fresh, Dnp), g)
+            fresh.close()

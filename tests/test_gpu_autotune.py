@@ -33,6 +33,9 @@ def test_tuning_does_not_advance_and_results_do_not_depend_on_the_winner(multi, 
     before = states(s)
     cands = [(1, 1, 0, 64, 0, 0, lbm.LBM_BATCH_SERIAL, 0), (2, 0, 0, 256, 5, 1, lbm.LBM_BATCH_SERIAL, 0),
              (1, 3, 2, 256, 5, 0, lbm.LBM_BATCH_SERIAL, 0)]
+    if not multi:  # one instance also tries two steps per launch and one buffer in place
+        cands += [(16, 1, 0, 256, 0, 0, lbm.LBM_BATCH_SERIAL, 0, 2), (8, 0, 0, 128, 0, 1, lbm.LBM_BATCH_SERIAL, 0, 2),
+                  (1, 1, 0, 256, 0, 2, lbm.LBM_BATCH_SERIAL, 0, 1)]
     if multi:
         cands += [(1, 1, 0, 256, 0, 1, lbm.LBM_BATCH_FLAT, 0), (1, 1, 0, 64, 0, 0, lbm.LBM_BATCH_LPT, 512),
                   (2, 1, 0, 256, 0, 1, lbm.LBM_BATCH_STRIDED, 256), (1, 1, 0, 256, 0, 0, lbm.LBM_BATCH_LPT, 512)]
@@ -41,9 +44,9 @@ def test_tuning_does_not_advance_and_results_do_not_depend_on_the_winner(multi, 
     assert tuple(r["best"]) in [tuple(c) for c in cands] and not r["cached"]
     assert all(np.array_equal(a, b) for a, b in zip(before, states(s)))
     assert all(s.macros(k)["step"] == 7 for k in range(len(inst)))
-    rows, remap, h, width, cap, stores, policy, blocks = r["best"]
+    rows, remap, h, width, cap, stores, policy, blocks, fuse = (tuple(r["best"]) + (1,))[:9]
     assert s.get_launch(0) == {"rows": rows, "xcd_remap": remap, "tile_width": width, "max_waves": cap,
-                               "xcd_rows": h, "stores": stores}
+                               "xcd_rows": h, "stores": stores, "fuse": fuse}
     s.step(20)
     tuned = states(s)
     s.close()
@@ -67,4 +70,14 @@ def test_tuning_a_d3q19_instance():
                           (1, 3, 4, 256, 4, 1, 0, 0)], steps=8, reps=1, force=True)
     assert all(np.array_equal(a, b) for a, b in zip(before, states(s)))
     assert s.get_launch(0)["rows"] == r["best"][0]
+    s.close()
+
+
+def test_default_candidates_of_a_single_instance_include_fused_and_in_place_launches():
+    s = Solver([pulse_instance(128)])
+    cands = autotune.default_candidates(s)
+    assert any(c[8] == 2 for c in cands) and any(c[5] == 2 for c in cands)
+    s.close()
+    s = Solver([pulse_instance(64), pulse_instance(96)])
+    assert all(c[8] == 1 for c in autotune.default_candidates(s))
     s.close()

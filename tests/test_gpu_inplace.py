@@ -1,8 +1,9 @@
-"""One-buffer (in-place) stepping.  A single periodic D2Q9 instance whose two population buffers would
-not fit in the 256 MiB Infinity Cache, but whose one buffer does, is updated in place (the AA pattern:
-a streaming step and a local step alternate).  Its states are compared bitwise with the same instance
-advanced on two buffers: the reference context holds a second, small instance, which keeps it on two
-buffers, and runs one launch per instance."""
+"""One-buffer (in-place) stepping.  A single periodic instance updates one population buffer in place
+(the AA pattern: a streaming step and a local step alternate): D3Q19/D3Q27 instances whose two buffers
+would not fit in the 256 MiB Infinity Cache but whose one buffer does by default, D2Q9 instances on
+request (lbm_set_launch stores = 2; their default is two steps per launch on two buffers).  States are
+compared bitwise with the same instance advanced on two buffers: the reference context holds a second,
+small instance, which keeps it on two buffers, and runs one launch per instance."""
 import numpy as np
 import pytest
 import torch
@@ -33,6 +34,7 @@ def instance(mode, nx, ny, var, tau3=0.0, aux=lbm.LBM_AUX_LOCAL):
 def pair(mode, nx, ny, var, tau3=0.0, aux=lbm.LBM_AUX_LOCAL):
     p, fields = instance(mode, nx, ny, var, tau3, aux)
     one = Solver([(p, fields)])
+    one.set_launch(1, 1, tile_width=256, stores=2)
     small = instance(mode, 64, 40, False, tau3, aux)
     two = Solver([(p, fields), small])
     two.set_batch(lbm.LBM_BATCH_SERIAL)
@@ -73,10 +75,17 @@ def test_in_place_state_images_and_restrictions():
     two.step(3)
     assert torch.equal(one.state_save(), two.state_save(0))
     assert one.macros()["step"] == two.macros(0)["step"] == 9
-    for kw in (dict(stores=0), dict(stores=1), dict(stores=2, rows=2)):
+    for kw in (dict(stores=2, rows=2), dict(stores=2, fuse=2, tile_width=256)):
         with pytest.raises(lbm.LbmError) as ei:
-            one.set_launch(kw.pop("rows", 1), 1, tile_width=256, **kw)
+            one.set_launch(kw.pop("rows", 1), 1, **dict(dict(tile_width=256), **kw))
         assert ei.value.status == lbm.LBM_E_ARG, kw
+    # switching between one buffer and two at either parity carries the state over
+    for stores, n in ((0, 3), (2, 1), (1, 2), (2, 2), (0, 1)):
+        one.set_launch(1, 1, tile_width=256, stores=stores)
+        assert one.get_launch()["stores"] == stores
+        one.step(n)
+        two.step(n)
+        assert torch.equal(one.state_save(), two.state_save(0)), (stores, n)
     one.set_launch(1, 3, tile_width=256, max_waves=5, xcd_rows=4, stores=2)  # launch shape: still bitwise
     one.step(3)
     two.step(3)

@@ -225,7 +225,8 @@ def test_longest_row_windows(mode):
     """The longest row the ABI accepts (nx = 2^24, ny = 3): lane byte offsets and tile indices at their
     extremes (65,536 tiles per row, column bands of 8,192 tiles).  One step after 3, checked on
     windows at the start, the middle and the periodic end of the row against the oracle stepping the
-    GPU state (all three rows, which wrap in y exactly as on the GPU)."""
+    GPU state (all three rows, which wrap in y exactly as on the GPU); then two more steps in one fused
+    launch (32,768 tiles of 512 columns), bitwise equal to two single steps."""
     nx, ny, w, m = 1 << 24, 3, 64, 2
     x = np.arange(nx) / nx
     ux = np.broadcast_to(0.2 * np.sin(2 * np.pi * x), (ny, nx)).copy()
@@ -235,26 +236,31 @@ def test_longest_row_windows(mode):
     dx, dt, lam, D = 1.0 / nx, 0.5 / nx, 0.25, 1.0 / (6.0 * nx)
     p = lbm.make_params(nx, ny, dx, dt, lam, D, mode, phi_ref=1.0)
     s = Solver([(p, {"phi0": dev(phi0), "ux": dev(ux), "uy": dev(uy)})])
-    d = s.get_launch()
-    assert (d["xcd_remap"], d["xcd_rows"]) == (3, 2)  # row blocks (3 tile rows: all in hardware order)
-    s.set_launch(1, 2, tile_width=256, max_waves=d["max_waves"])
+    assert s.get_launch()["fuse"] == 2  # one periodic instance: two steps per launch by default
+    s.set_launch(1, 2, tile_width=256)  # one step per launch, column bands of 8,192 tiles
     s.step(3)
     g0 = s.populations()
     s.step(1)
     g1 = s.populations()
+    img = s.state_save()
+    s.step(2)  # two more single steps, then the same two steps in one fused launch (32,768 tiles per row)
+    g3 = s.populations()
+    s.state_load(img, 4)
+    s.set_launch(4, 1, tile_width=512, fuse=2)
+    s.step(2)
+    assert torch.equal(s.populations(), g3)
     s.close()
     gmax = float(g1.abs().max())
+    bound = {"f64": TOL64, "f32": 1e-6, "f16s": 2.0 ** -10}[mode]
     for x0 in (0, nx // 2 + 12345, nx - w // 2):
         xs = (np.arange(x0 - m, x0 + w + m)) % nx
         ix = torch.as_tensor(xs, device=g0.device)
-        gw = g0.index_select(2, ix).cpu().numpy()
         q = O.Problem(w + 2 * m, ny, dx, dt, lam, D, O.AUX_LOCAL)
-        want = O.step(q, gw, ux[:, xs], uy[:, xs])[:, :, m:-m]
+        want = O.step(q, g0.index_select(2, ix).cpu().numpy(), ux[:, xs], uy[:, xs])[:, :, m:-m]
         got = g1.index_select(2, ix[m:-m]).cpu().numpy()
         err = np.abs(got - want).max() / gmax
-        bound = {"f64": TOL64, "f32": 1e-6, "f16s": 2.0 ** -10}[mode]
         assert err <= bound, (x0, err)
-    del g0, g1
+    del g0, g1, g3
     torch.cuda.empty_cache()
 
 
@@ -453,48 +459,68 @@ def test_launch_defaults_and_bad_launch_shapes():
     cfg = W.PulseConfig(N=64, steps=0)
     f = W.rotating_pulse(cfg)
     fields = {k: dev(f[k]) for k in ("phi0", "ux", "uy")}
-    def launch(rows, remap, width, cap, h=0, stores=1):
+    def launch(rows, remap, width, cap, h=0, stores=1, fuse=1):
         return {"rows": rows, "xcd_remap": remap, "tile_width": width, "max_waves": cap, "xcd_rows": h,
-                "stores": stores}
+                "stores": stores, "fuse": fuse}
 
-    # A context that touches at most 256 MiB per step is served by the Infinity Cache: cached stores,
-    # row bands, every wave resident (64-column tiles kept for FP64 storage on narrow lattices).
+    def fused(nx, ny, stores, mode):  # two steps per launch: the tile shapes of the sweeps
+        narrow = (nx + 255) // 256 <= 8
+        width, rows = {"f32": (512 if narrow else 256, 16), "f16s": (512, 16) if narrow else (128, 32)}.get(
+            mode, (256, 32) if narrow else (128, 16))
+        while width > 128 and width // 2 >= nx:
+            width //= 2
+        while rows > 4 and -(-nx // width) * -(-ny // rows) < 256:
+            rows //= 2
+        return launch(rows, 1, width, 0, 0, stores, 2)
+
+    # One periodic D2Q9 TRT-R instance (local or no aux term) runs two steps per launch.  A context that
+    # touches at most 256 MiB per step is served by the Infinity Cache: cached stores, row bands, every
+    # wave resident; so are the one-step launches of the other kinds (64-column tiles kept for FP64
+    # storage on narrow lattices).
+    for mode in ("f32", "f64", "f16s"):
+        s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, mode), fields)])
+        assert s.get_launch() == fused(64, 64, 1, mode), mode
+        s.close()
     for mode, w in (("f32", launch(1, 1, 256, 0)), ("f64", launch(1, 1, 64, 0)), ("f16s", launch(1, 1, 256, 0))):
-        for bc in (lbm.LBM_BC_PERIODIC, lbm.LBM_BC_NEE):
-            s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, mode, boundary=bc), fields)])
-            assert s.get_launch() == w, (mode, bc)
-            s.close()
+        s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, mode, boundary=lbm.LBM_BC_NEE), fields)])
+        assert s.get_launch() == w, mode
+        s.close()
     s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, "f32", lbm.LBM_AUX_FLUX), fields)])
-    assert s.get_launch() == launch(2, 1, 256, 0)
+    assert s.get_launch() == launch(4, 1, 256, 0)  # the flux form's walking kernel: tile height 4..64
+    s.close()
+    s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, "f32", tau3=0.7), fields)])
+    assert s.get_launch() == launch(1, 1, 256, 0)  # MRT-R: one step per launch
     s.close()
 
-    # One periodic instance that fits only with one population buffer is updated in place (stores 2),
-    # with the cache's launch shape.
-    # Larger contexts stream (non-temporal stores).  With 4 or more wide tiles per row: row blocks (FP32
-    # about 64 tiles each, FP64 about 32; FP16 keeps column bands at 8 and 16 tiles per row); FP32 with
-    # a D(x) field runs 6 waves per SIMD.  Narrower FP64: 64-column tiles in hardware order.  (Sizes:
-    # more than 256 MiB even with one population buffer; boundary instances never run in place.)
+    # Larger contexts stream (non-temporal stores).  One-step launches with 4 or more wide tiles per row:
+    # row blocks (FP32 about 64 tiles each, FP64 about 32; FP16 keeps column bands at 8 and 16 tiles per
+    # row); FP32 with a D(x) field runs 6 waves per SIMD.  Narrower FP64: 64-column tiles in hardware
+    # order.  (Sizes: more than 256 MiB even with one population buffer; boundary instances never run in
+    # place.)
     def fields_of(nx, ny, var=False):
         src = dict(f, D=np.full_like(f["phi0"], cfg.D))
         keys = ("phi0", "ux", "uy", "D") if var else ("phi0", "ux", "uy")
         return {k: dev(np.ascontiguousarray(np.resize(src[k], (ny, nx)))) for k in keys}
 
-    for nx, ny, mode, var, bc, w in (
-            (2048, 1700, "f32", False, 0, launch(1, 1, 256, 0, 0, 2)),
-            (2048, 3000, "f32", False, 0, launch(1, 3, 256, 5, 8, 0)),
-            (2048, 1500, "f64", False, 0, launch(1, 3, 256, 4, 4, 0)),
-            (1024, 3000, "f64", False, 0, launch(1, 3, 256, 4, 8, 0)),
-            (768, 4000, "f64", False, 0, launch(1, 0, 64, 4, 0, 0)),
-            (2048, 5100, "f16s", False, 0, launch(1, 2, 256, 0, 0, 0)),
-            (2049, 3000, "f32", False, 0, launch(1, 3, 256, 5, 7, 0)),
-            (2049, 5100, "f16s", False, 0, launch(1, 3, 256, 0, 3, 0)),
-            (8192, 800, "f32", False, 0, launch(1, 3, 256, 5, 2, 0)),
-            (4096, 1500, "f32", True, 0, launch(1, 3, 256, 6, 4, 0)),
-            (2048, 1700, "f32", False, lbm.LBM_BC_NEE, launch(1, 3, 256, 5, 4, 0)),
-            (2048, 900, "f64", False, lbm.LBM_BC_NEE, launch(1, 3, 256, 0, 2, 0))):
+    for nx, ny, mode, var, bc, tau3, w in (
+            (2048, 1700, "f32", False, 0, 0.0, fused(2048, 1700, 0, "f32")),
+            (2048, 1700, "f32", False, 0, 0.8, launch(1, 1, 256, 0, 0, 2)),  # MRT-R: one buffer in place
+            (2048, 3000, "f32", False, 0, 0.8, launch(1, 3, 256, 5, 8, 0)),
+            (2048, 1500, "f64", False, 0, 0.0, fused(2048, 1500, 0, "f64")),
+            (2048, 1500, "f64", False, 0, 0.8, launch(1, 3, 256, 4, 4, 0)),
+            (1024, 3000, "f64", False, 0, 0.8, launch(1, 3, 256, 4, 8, 0)),
+            (768, 4000, "f64", False, 0, 0.8, launch(1, 0, 64, 4, 0, 0)),
+            (2048, 5100, "f16s", False, 0, 0.8, launch(1, 2, 256, 0, 0, 0)),
+            (2049, 3000, "f32", False, 0, 0.8, launch(1, 3, 256, 5, 7, 0)),
+            (2049, 5100, "f16s", False, 0, 0.0, fused(2049, 5100, 0, "f16s")),
+            (2049, 5100, "f16s", False, 0, 0.8, launch(1, 3, 256, 0, 3, 0)),
+            (8192, 800, "f32", False, 0, 0.8, launch(1, 3, 256, 5, 2, 0)),
+            (4096, 1500, "f32", True, 0, 0.8, launch(1, 3, 256, 6, 4, 0)),
+            (2048, 1700, "f32", False, lbm.LBM_BC_NEE, 0.0, launch(1, 3, 256, 5, 4, 0)),
+            (2048, 900, "f64", False, lbm.LBM_BC_NEE, 0.0, launch(1, 3, 256, 0, 2, 0))):
         fl = fields_of(nx, ny, var)
-        s = Solver([(lbm.make_params(nx, ny, f["dx"], f["dt"], cfg.lam, cfg.D, mode, boundary=bc), fl)])
-        assert s.get_launch() == w, (nx, ny, mode, var, bc)
+        s = Solver([(lbm.make_params(nx, ny, f["dx"], f["dt"], cfg.lam, cfg.D, mode, boundary=bc, tau3=tau3), fl)])
+        assert s.get_launch() == w, (nx, ny, mode, var, bc, tau3)
         s.close()
         del fl
     two = [(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, "f32"), fields)] * 2
@@ -506,7 +532,8 @@ def test_launch_defaults_and_bad_launch_shapes():
     assert s.get_launch(1) == launch(1, 2, 256, 0)
     for remap, kw in ((1, dict(tile_width=128)), (1, dict(tile_width=0)), (1, dict(max_waves=2)),
                       (1, dict(max_waves=9)), (1, dict(max_waves=-1)), (3, {}), (3, dict(xcd_rows=65)),
-                      (3, dict(xcd_rows=-2)), (4, {}), (-1, {}), (1, dict(stores=2)), (1, dict(stores=-1))):
+                      (3, dict(xcd_rows=-2)), (4, {}), (-1, {}), (1, dict(stores=2)), (1, dict(stores=-1)),
+                      (1, dict(fuse=2, tile_width=256))):
         with pytest.raises(lbm.LbmError) as ei:
             s.set_launch(1, remap, **kw)
         assert ei.value.status == lbm.LBM_E_ARG, (remap, kw)
@@ -550,7 +577,7 @@ def test_launch_shape_does_not_change_results(mode, aux):
         s = Solver([(p, fields)])
         s.set_launch(rows, remap, tile_width=width, max_waves=cap, xcd_rows=h, stores=st)
         assert s.get_launch() == {"rows": rows, "xcd_remap": remap, "tile_width": width, "max_waves": cap,
-                                  "xcd_rows": h, "stores": st}
+                                  "xcd_rows": h, "stores": st, "fuse": 1}
         s.step(70)
         states.append(s.state_save())
         s.close()
