@@ -187,6 +187,18 @@ int lbm_set_dirichlet(lbm_ctx *ctx, int32_t inst, const double *phi_b);
  * Returns LBM_E_NONFINITE if any phi is NaN or infinite (out is still filled). */
 int lbm_macros(lbm_ctx *ctx, int32_t inst, double *phi_out, const double *ref, lbm_stats *out);
 
+/* lbm_macros for callers that cannot allocate or use a library workspace while they run (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation): the same diagnostics and
+ * arguments, with the reduction's partial sums and result in a static device array of the library
+ * (82,000 bytes per GPU, allocated with the code object and held until the process ends) instead of
+ * the context's workspace.  Calls no hipMalloc or hipFree.  The array is shared by every context on a
+ * GPU and keeps the last call's contents (each call writes every entry it reads, so nothing needs
+ * clearing): calls that overlap on one GPU (from several host threads or streams) race.  The
+ * reduction needs at most 1024 x 10 doubles of it for any lattice the ABI accepts; a larger need
+ * would be refused with LBM_E_ARG.  LBM_E_STATE if the device's array address could not be resolved
+ * (it is resolved at the first lbm_init on each device).  Synchronizes the stream. */
+int lbm_macros_static(lbm_ctx *ctx, int32_t inst, double *phi_out, const double *ref, lbm_stats *out);
+
 /* Pre-collision populations g_i(x, t) of instance inst, decoded to FP64, into g_out (device FP64
  * [9][ny][nx], velocity order 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1)
  * 8:(1,-1); D3Q19 / D3Q27: [19 / 27][nz][ny][nx] in the order of enum lbm_lattice).  Asynchronous. */

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <new>
 #include <queue>
 #include <utility>
@@ -348,6 +349,17 @@ InstDesc desc_of(const Instance &in)
 constexpr int kGraphSteps = 32;
 static_assert(kGraphSteps % 2 == 0, "a graph replay must keep the buffer parity");
 
+// Device scratch of lbm_macros_static: the per-block partial sums of the diagnostics reduction
+// (kMacroBlocks x kMacroPartialDoubles) and its final result (8 doubles).  One copy per GPU, held until
+// the process ends; host code never passes `scratch` itself (in host code the name is a stand-in, not
+// a device address) but the address hipGetSymbolAddress returns for the current device, resolved once
+// per device at its first lbm_init.
+constexpr size_t kStaticScratchDoubles = (size_t)kMacroBlocks * kMacroPartialDoubles + 8;  // 82,000 bytes
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
 struct lbm_ctx {
     std::vector<Instance> inst;
     int parity = 0;                   // the buffer every instance currently reads (they step together)
@@ -370,6 +382,7 @@ struct lbm_ctx {
     double *result = nullptr;
     int *flag = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int device = -1;                  // the device current at lbm_init (its stream's device)
 };
 
 namespace {
@@ -631,9 +644,24 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
     c->stream = static_cast<hipStream_t>(stream);
     {
         int dev = 0, lds = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess)
-            c->lds_per_cu = lds;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            c->device = dev;
+            if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess)
+                c->lds_per_cu = lds;
+        }
+        // the address of this device's copy of the static scratch array (once per device, with it current)
+        if (dev >= 0 && dev < kMaxDevices) {
+            std::lock_guard<std::mutex> lock(g_scratch_mu);
+            if (!g_scratch_ptr[dev]) {
+                void *ptr = nullptr;
+                hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+                if (e != hipSuccess) {
+                    delete c;
+                    return hip_fail(e, "lbm_init: hipGetSymbolAddress of the static scratch array");
+                }
+                g_scratch_ptr[dev] = static_cast<double *>(ptr);
+            }
+        }
     }
     if (workspace) {
         c->ws = static_cast<char *>(workspace);
@@ -829,11 +857,12 @@ int lbm_step(lbm_ctx *c, int32_t nsteps, const double *const *ux, const double *
     return account(LBM_OK);
 }
 
-int lbm_macros(lbm_ctx *c, int32_t inst, double *phi_out, const double *ref, lbm_stats *out)
+namespace {
+// The diagnostics of lbm_macros with the reduction's per-block partials and result in `partials` and
+// `result` (device).
+int macros_into(lbm_ctx *c, int32_t inst, double *phi_out, const double *ref, lbm_stats *out, double *partials,
+                double *result)
 {
-    g_err[0] = 0;
-    if (!check_inst(c, inst)) return fail(LBM_E_STATE, "lbm_macros: bad context or instance %d", inst);
-    if (!out) return fail(LBM_E_ARG, "lbm_macros: out is NULL");
     Instance &in = c->inst[inst];
     MacroArgs a;
     a.src = in.buf[c->parity];
@@ -844,12 +873,12 @@ int lbm_macros(lbm_ctx *c, int32_t inst, double *phi_out, const double *ref, lbm
     a.edge.u = in.u;
     a.edge.bc = in.bc;
     a.edge.kind = in.lc.stores == 2 && c->parity == 1 ? 3 : in.p.boundary;  // 3: one buffer after a streaming step
-    a.partials = c->partials;
-    hipError_t e = is3d(in) ? launch_macros3(in.mode, a, c->result, c->stream)
-                            : launch_macros(in.mode, a, c->result, c->stream);
+    a.partials = partials;
+    hipError_t e = is3d(in) ? launch_macros3(in.mode, a, result, c->stream)
+                            : launch_macros(in.mode, a, result, c->stream);
     if (e != hipSuccess) return hip_fail(e, "macros kernel launch");
     double r[6];
-    e = hipMemcpyAsync(r, c->result, sizeof r, hipMemcpyDeviceToHost, c->stream);
+    e = hipMemcpyAsync(r, result, sizeof r, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "lbm_macros: reading the result");
     const double nn = (double)in.L.nx * in.L.ny * in.L.nz;
@@ -863,6 +892,33 @@ int lbm_macros(lbm_ctx *c, int32_t inst, double *phi_out, const double *ref, lbm
     if (out->nonfinite > 0)
         return fail(LBM_E_NONFINITE, "instance %d: %lld non-finite phi values (blow-up)", inst, (long long)out->nonfinite);
     return LBM_OK;
+}
+}  // namespace
+
+int lbm_macros(lbm_ctx *c, int32_t inst, double *phi_out, const double *ref, lbm_stats *out)
+{
+    g_err[0] = 0;
+    if (!check_inst(c, inst)) return fail(LBM_E_STATE, "lbm_macros: bad context or instance %d", inst);
+    if (!out) return fail(LBM_E_ARG, "lbm_macros: out is NULL");
+    return macros_into(c, inst, phi_out, ref, out, c->partials, c->result);
+}
+
+int lbm_macros_static(lbm_ctx *c, int32_t inst, double *phi_out, const double *ref, lbm_stats *out)
+{
+    g_err[0] = 0;
+    if (!check_inst(c, inst)) return fail(LBM_E_STATE, "lbm_macros_static: bad context or instance %d", inst);
+    if (!out) return fail(LBM_E_ARG, "lbm_macros_static: out is NULL");
+    double *sp = c->device >= 0 && c->device < kMaxDevices ? g_scratch_ptr[c->device] : nullptr;
+    if (!sp) return fail(LBM_E_STATE, "lbm_macros_static: no static scratch on device %d", c->device);
+    // the reduction runs at most kMacroBlocks blocks (each writes its partials before the single-block
+    // pass reads them), so nothing needs clearing; refuse a grid that would not fit all the same
+    const Instance &in = c->inst[inst];
+    const int64_t nodes = (int64_t)in.L.nx * in.L.ny * in.L.nz;
+    const int64_t blocks = std::min<int64_t>(std::max<int64_t>((nodes + 255) / 256, 1), kMacroBlocks);
+    if ((size_t)blocks * kMacroPartialDoubles + 8 > kStaticScratchDoubles)
+        return fail(LBM_E_ARG, "lbm_macros_static: %lld reduction blocks exceed the static scratch of %zu bytes",
+                    (long long)blocks, kStaticScratchDoubles * sizeof(double));
+    return macros_into(c, inst, phi_out, ref, out, sp, sp + (size_t)kMacroBlocks * kMacroPartialDoubles);
 }
 
 int lbm_set_velocity(lbm_ctx *c, int32_t inst, const double *ux, const double *uy, const double *uz)

@@ -77,7 +77,7 @@ EXPORTS = ["lbm_workspace_size", "lbm_init", "lbm_step", "lbm_set_velocity", "lb
            "lbm_state_save", "lbm_state_load", "lbm_set_launch", "lbm_get_launch", "lbm_set_batch", "lbm_get_batch",
            "lbm_adjoint_bytes", "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_init", "lbm_bench_copy", "lbm_free",
            "lbm_pitch", "lbm_last_error", "lbm_abi_version", "lbm_set_diffusion", "lbm_adjoint_segment",
-           "lbm_bench_copy_cached"]
+           "lbm_bench_copy_cached", "lbm_macros_static"]
 
 
 def pitch_of(p: "lbm_params") -> int:
@@ -97,6 +97,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lbm_init.argtypes = [ctypes.POINTER(P), I32, ctypes.POINTER(lbm_params), ctypes.POINTER(lbm_fields), P, SZ, P]
     lib.lbm_step.argtypes = [P, I32, PP, PP, PP, PP]
     lib.lbm_macros.argtypes = [P, I32, P, P, ctypes.POINTER(lbm_stats)]
+    lib.lbm_macros_static.argtypes = [P, I32, P, P, ctypes.POINTER(lbm_stats)]
     lib.lbm_set_dirichlet.argtypes = [P, I32, P]
     lib.lbm_set_velocity.argtypes = [P, I32, P, P, P]
     lib.lbm_populations.argtypes = [P, I32, P]
@@ -223,6 +224,17 @@ def lbm_macros(ctx, inst: int = 0, phi_out: Optional[torch.Tensor] = None, ref: 
                raise_nonfinite: bool = True) -> dict:
     st = lbm_stats()
     rc = lib().lbm_macros(ctx, int(inst), _dptr(phi_out), _dptr(ref), ctypes.byref(st))
+    if rc != LBM_OK and not (rc == LBM_E_NONFINITE and not raise_nonfinite):
+        _check(rc)
+    d = st.as_dict()
+    d["status"] = rc
+    return d
+
+
+def lbm_macros_static(ctx, inst: int = 0, phi_out: Optional[torch.Tensor] = None, ref: Optional[torch.Tensor] = None,
+                      raise_nonfinite: bool = True) -> dict:
+    st = lbm_stats()
+    rc = lib().lbm_macros_static(ctx, int(inst), _dptr(phi_out), _dptr(ref), ctypes.byref(st))
     if rc != LBM_OK and not (rc == LBM_E_NONFINITE and not raise_nonfinite):
         _check(rc)
     d = st.as_dict()
