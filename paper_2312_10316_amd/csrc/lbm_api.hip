@@ -92,8 +92,9 @@ int lds_reserve_for(int max_waves, int lds_per_cu)
 // Against column bands (ntx a multiple of 8) or row bands: FP32 +2-9 %, FP64 +1-5 %, FP16 +2-6 %
 // (2048^2 FP32: 82k MLUPS).  Narrower lattices: row bands, FP64 storage on 64-column tiles in
 // hardware order.
-// Flux form (one instance): the walking kernel (lbm_fused.hip) on 256-column tiles whose height gives
-// about 1024 tiles (4..64 rows), in row bands, uncapped.
+// Flux form: two rows per wave on 256-column tiles, FP32 in row bands with 4 waves (+16 % over 8 rows
+// of 64-column tiles), FP64 in column bands (ntx a multiple of 8) or row bands, uncapped (row blocks
+// measured slower).
 // Dirichlet edges and walls with ntx >= 8: FP32 on 256-column tiles in row blocks of 4 tile rows capped
 // at 5 waves (2049^2 NEE: 76k against 72k MLUPS in row bands), FP64 the same with h = 2, uncapped;
 // FP16 in row bands, uncapped.  Narrower lattices: FP32 and FP16 in row bands, FP64 on 64-column tiles
@@ -108,6 +109,7 @@ Launch default_launch(const lbm_params &p, int mode, bool has_D, int n_inst, int
     Launch lc{1, 0, 1, 0, 0, 0};
     const bool f32 = mode == MODE_F32_F32, f16 = mode == MODE_F16S_F32;
     const int ntx = (p.nx + 255) / 256;
+    const int bands = ntx % 8 == 0 ? 2 : 1;
     const auto row_blocks = [&lc](int h) {
         lc.xcd_remap = 3;
         lc.xcd_rows = h;
@@ -124,9 +126,10 @@ Launch default_launch(const lbm_params &p, int mode, bool has_D, int n_inst, int
         } else {
             lc.wide = 0;
         }
-    } else if (p.aux == LBM_AUX_FLUX) {  // the walking kernel: 256-column tiles, rows = tile height
-        lc.rows = std::clamp((int)(((int64_t)p.ny * ntx) / 1024), 4, 64);
-        lc.xcd_remap = 1;
+    } else if (p.aux == LBM_AUX_FLUX) {
+        lc.rows = 2;
+        lc.xcd_remap = f32 ? 1 : bands;
+        lc.max_waves = f32 ? 4 : 0;
     } else {
         lc.xcd_remap = 1;
         lc.max_waves = f16 ? 0 : (f32 ? (has_D ? 6 : 5) : 4);

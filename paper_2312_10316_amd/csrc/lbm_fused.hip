@@ -1,6 +1,5 @@
-// lbm_fused.hip -- D2Q9 kernels whose blocks walk a tile top to bottom with an LDS ring (gfx950): two
-// time steps of the TRT-R update per launch (temporal blocking), and one step with the flux form of the
-// auxiliary term.
+// lbm_fused.hip -- two time steps of the D2Q9 TRT-R update per launch (temporal blocking, gfx950): a
+// block walks its tile top to bottom and passes the intermediate state through an LDS ring.
 //
 // A step is bound by memory traffic: every population is read once and written once per step
 // (Sec. 2.2, Eq. (14) pulls nine values and stores nine).  Fusing two steps halves that traffic: a
@@ -29,8 +28,19 @@ namespace {
 // LDS ring plane of each population that moves along x (-1: kept in registers).
 constexpr int kPlane[9] = {-1, 0, -1, 1, -1, 2, 3, 4, 5};
 
+// Resident waves per SIMD that the registers of step2_kernel are allocated for (see there).
+constexpr int step2_waves(int mode, int nw)
+{
+    return mode == MODE_F64_F64 || mode == MODE_F64_F32 ? (nw == 2 ? 4 : (nw == 4 ? 3 : 2)) : 6;
+}
+
+// amdgpu_waves_per_eu: register allocation for at least six resident waves per SIMD, or as many as the
+// LDS ring of FP64 storage lets 160 KB hold (2 to 4): FP32 and FP16 storage then fit 41-49 VGPRs,
+// against 65-83 by default.
+// The walk is bound by the loads each wave keeps in flight, so resident waves count more than registers.
 template <int MODE, int AUX, bool HAS_K, bool HAS_S, bool MRT, int NW, bool CST>
-__global__ __launch_bounds__(64 * (NW + 1)) void step2_kernel(const StepArgs a)
+__global__ __launch_bounds__(64 * (NW + 1))
+__attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW)))) void step2_kernel(const StepArgs a)
 {
     using St = typename ModeTraits<MODE>::St;
     using M = typename ModeTraits<MODE>::M;
@@ -60,8 +70,8 @@ __global__ __launch_bounds__(64 * (NW + 1)) void step2_kernel(const StepArgs a)
     const unsigned ux_ = (unsigned)xi;
     const unsigned uxm = ux_ == 0 ? (unsigned)nx - 1 : ux_ - 1;
     const unsigned uxp = ux_ == (unsigned)nx - 1 ? 0u : ux_ + 1;
-    const unsigned bc = ux_ * (unsigned)sizeof(T), bm = uxm * (unsigned)sizeof(T), bp = uxp * (unsigned)sizeof(T);
-    const unsigned fc = ux_ * (unsigned)sizeof(M), fm = uxm * (unsigned)sizeof(M), fp = uxp * (unsigned)sizeof(M);
+    unsigned bc = ux_ * (unsigned)sizeof(T), bm = uxm * (unsigned)sizeof(T), bp = uxp * (unsigned)sizeof(T);
+    unsigned fc = ux_ * (unsigned)sizeof(M), fm = uxm * (unsigned)sizeof(M), fp = uxp * (unsigned)sizeof(M);
     const unsigned pb = (unsigned)(pitch * (int64_t)sizeof(T));
 
     const T *__restrict__ src = static_cast<const T *>(d.buf[a.parity]);
@@ -91,7 +101,15 @@ __global__ __launch_bounds__(64 * (NW + 1)) void step2_kernel(const StepArgs a)
     M p0_m = M(0), p2_m = M(0), p2_mm = M(0);
 
     for (int r = rs; r <= y1; ++r) {
-        const int rw = wrapr(r), rwm = wrapr(r - 1), rwp = wrapr(r + 1);
+        // row indices through readfirstlane: uniform values the compiler cannot strength-reduce into
+        // per-lane 64-bit address recurrences, so every access keeps the scalar-base + 32-bit-offset form
+        const int rw = __builtin_amdgcn_readfirstlane(wrapr(r));
+        const int rwm = __builtin_amdgcn_readfirstlane(wrapr(r - 1));
+        const int rwp = __builtin_amdgcn_readfirstlane(wrapr(r + 1));
+        // the lane offsets are re-read every row (an empty asm that claims to update them), so the compiler
+        // keeps each access as one scalar row base plus a 32-bit lane offset instead of hoisting 64-bit
+        // per-lane addresses out of the walk
+        asm volatile("" : "+v"(bc), "+v"(bm), "+v"(bp), "+v"(fc), "+v"(fm), "+v"(fp));
         const M *__restrict__ un = u + (int64_t)rwp * 2 * pitch;
         const M ux_p = ld_at(un, fc), uy_p = ld_at(un + pitch, fc);
         // ---- phase 1: intermediate node (xi, r) of step n + 1 -----------------------------------------
@@ -135,7 +153,7 @@ __global__ __launch_bounds__(64 * (NW + 1)) void step2_kernel(const StepArgs a)
         // ---- phase 2: output node (x, y = r - 1) of step n + 2 ---------------------------------------
         const M p4 = C::dec(C::enc(P[4], 4, d.f16), 4, d.f16);
         if (!frame && r >= y0 + 1) {
-            const int y = r - 1;
+            const int y = __builtin_amdgcn_readfirstlane(r - 1);
             M g[9];
             T(*const sy)[WC] = ring[y & 3];
             T(*const sm)[WC] = ring[(y - 1) & 3];
@@ -185,165 +203,6 @@ __global__ __launch_bounds__(64 * (NW + 1)) void step2_kernel(const StepArgs a)
     }
 }
 
-// One step with the flux form of the auxiliary term, d_b(phi u_a u_b) - u_a d_b(phi u_b) (Sec. 2.3;
-// equal to Eq. (16) by the product rule), which needs phi at the four axis neighbours at the same time
-// level.  Same block layout as the fused kernel: NW interior waves and a frame wave whose lanes 0 and
-// 1 pull the nodes just left and right of the tile.  Iteration r pulls row r (each population read
-// once per tile row, plus two frame rows per tile), sums phi(r) and puts it in a four-row LDS ring;
-// one row behind, the node (x, r - 1) takes phi at x -+ 1 from the ring, phi at r - 2 and r from its
-// own registers, and collides the populations it pulled in the previous iteration.  Every phi is the
-// sum of its node's nine populations in index order, as in the other kernels, so the results are
-// bitwise those of any other launch shape.
-template <int MODE, bool HAS_K, bool HAS_S, bool MRT, int NW, bool CST>
-__global__ __launch_bounds__(64 * (NW + 1)) void flux_walk_kernel(const StepArgs a)
-{
-    using St = typename ModeTraits<MODE>::St;
-    using M = typename ModeTraits<MODE>::M;
-    using T = typename St::T;
-    using C = Codec<St, M>;
-    constexpr int W = 64 * NW, WC = W + 2;
-    __shared__ M phis[4][WC];
-
-    const InstDesc &d = a.d;
-    const int nx = d.L.nx, ny = d.L.ny;
-    const int64_t pitch = d.L.pitch;
-    const int H = d.lc.rows;
-    const int ntx = (nx + W - 1) / W;
-    const int t = tile_of_block(blockIdx.x, gridDim.x, d.lc.xcd_remap, ntx, d.lc.xcd_rows);
-    const int x0 = (t % ntx) * W, y0 = (t / ntx) * H;
-    const int y1 = min(y0 + H, ny);
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int lane = (int)(threadIdx.x & 63u);
-    const bool frame = wave == NW;
-    const int c = frame ? (lane == 0 ? 0 : (lane == 1 ? W + 1 : -1)) : 1 + wave * 64 + lane;
-    const bool act = c >= 0;
-    int xi = x0 - 1 + (act ? c : 1);
-    xi = xi % nx;
-    xi = xi < 0 ? xi + nx : xi;
-    const bool live = !frame && x0 + wave * 64 + lane < nx;
-    const unsigned ux_ = (unsigned)xi;
-    const unsigned uxm = ux_ == 0 ? (unsigned)nx - 1 : ux_ - 1;
-    const unsigned uxp = ux_ == (unsigned)nx - 1 ? 0u : ux_ + 1;
-    const unsigned bc = ux_ * (unsigned)sizeof(T), bm = uxm * (unsigned)sizeof(T), bp = uxp * (unsigned)sizeof(T);
-    const unsigned fc = ux_ * (unsigned)sizeof(M), fm = uxm * (unsigned)sizeof(M), fp = uxp * (unsigned)sizeof(M);
-    const unsigned pb = (unsigned)(pitch * (int64_t)sizeof(T));
-
-    const T *__restrict__ src = static_cast<const T *>(d.buf[a.parity]);
-    T *__restrict__ dst = static_cast<T *>(d.buf[a.parity ^ 1]);
-    const M *__restrict__ u = static_cast<const M *>(d.u);
-    const M *__restrict__ kf = static_cast<const M *>(d.k);
-    const M *__restrict__ sf = static_cast<const M *>(d.s);
-    const M lam = (M)d.lambda;
-    Relax<M> rconst;
-    rconst.w1 = (M)d.w1;
-    rconst.w2 = (M)d.w2;
-    rconst.beta = (M)d.beta;
-    rconst.w3 = (M)d.w3;
-    auto wrapr = [ny](int r) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); };
-
-    // the nine stored values the node (xi, r) pulls, loaded one iteration ahead
-    auto pull_raw = [&](int r, T (&raw)[9]) {
-        const T *__restrict__ rm = src + (int64_t)wrapr(r - 1) * 9 * pitch;
-        const T *__restrict__ rc = src + (int64_t)wrapr(r) * 9 * pitch;
-        const T *__restrict__ rp = src + (int64_t)wrapr(r + 1) * 9 * pitch;
-        raw[0] = ld_at(rc, bc);
-        raw[1] = ld_at(rc + pitch, bm);
-        raw[2] = ld_at(rm + 2 * pitch, bc);
-        raw[3] = ld_at(rc + 3 * pitch, bp);
-        raw[4] = ld_at(rp + 4 * pitch, bc);
-        raw[5] = ld_at(rm + 5 * pitch, bm);
-        raw[6] = ld_at(rm + 6 * pitch, bp);
-        raw[7] = ld_at(rp + 7 * pitch, bp);
-        raw[8] = ld_at(rp + 8 * pitch, bm);
-    };
-    M gp[9] = {};                     // populations of the previous row at this column
-    M phi_m = M(0), phi_mm = M(0);    // phi of rows r - 1 and r - 2
-    M ux_m = M(0), uy_m = M(0), ux_mm = M(0), uy_mm = M(0);  // u of rows r - 1 and r - 2
-    T raw_n[9] = {};
-    if (act) pull_raw(y0 - 1, raw_n);
-    for (int r = y0 - 1; r <= y1; ++r) {
-        const int rw = wrapr(r);
-        T raw[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) raw[i] = raw_n[i];
-        if (act && r < y1) pull_raw(r + 1, raw_n);
-        M g[9] = {};
-        M phir = M(0);
-        if (act) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) g[i] = C::dec(raw[i], i, d.f16);
-            phir = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
-            phis[r & 3][c] = phir;
-        }
-        const M *__restrict__ ur = u + (int64_t)rw * 2 * pitch;
-        const M ux_c = frame ? M(0) : ld_at(ur, fc), uy_c = frame ? M(0) : ld_at(ur + pitch, fc);  // u of row r
-        __syncthreads();
-        if (!frame && r >= y0 + 1) {  // node (x, y = r - 1)
-            const int y = r - 1;
-            const int yw = wrapr(y);
-            const M pw = phis[y & 3][c - 1], pe = phis[y & 3][c + 1];
-            const M *__restrict__ uy_row = u + (int64_t)yw * 2 * pitch;
-            const M uxw = ld_at(uy_row, fm), uyw = ld_at(uy_row + pitch, fm);
-            const M uxe = ld_at(uy_row, fp), uye = ld_at(uy_row + pitch, fp);
-            const M fwx = pw * uxw, fex = pe * uxe;           // phi u_x at the west and east neighbours
-            const M fsy = phi_mm * uy_mm, fny = phir * uy_c;  // phi u_y at the south and north neighbours
-            const M div = (fex - fwx) * M(0.5) + (fny - fsy) * M(0.5);
-            const M Ax = (fex * uxe - fwx * uxw) * M(0.5) + (fny * ux_c - fsy * ux_mm) * M(0.5) - ux_m * div;
-            const M Ay = (fex * uye - fwx * uyw) * M(0.5) + (fny * uy_c - fsy * uy_mm) * M(0.5) - uy_m * div;
-            const Relax<M> rr = HAS_K ? relax_from_k<M>(ld_at(kf + (int64_t)yw * pitch, fc), lam, rconst.w3) : rconst;
-            const M s = HAS_S ? ld_at(sf + (int64_t)yw * pitch, fc) : M(0);
-            M P[9];
-            collide<M, MRT>(gp, ux_m, uy_m, rr, Ax, Ay, s, P);
-            if (live) {
-                T *__restrict__ out = dst + (int64_t)yw * 9 * pitch;
-#pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    if constexpr (CST) st_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, d.f16));
-                    else st_nt_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, d.f16));
-                }
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 9; ++i) gp[i] = g[i];
-        phi_mm = phi_m;
-        phi_m = phir;
-        ux_mm = ux_m;
-        uy_mm = uy_m;
-        ux_m = ux_c;
-        uy_m = uy_c;
-    }
-}
-
-template <int MODE, bool MRT, int NW, bool CST>
-hipError_t launch_flux_nw(const StepArgs &a, hipStream_t st)
-{
-    const int W = 64 * NW, H = a.d.lc.rows;
-    const int nblocks = ((a.d.L.nx + W - 1) / W) * ((a.d.L.ny + H - 1) / H);
-    const size_t lds = (size_t)a.d.lc.lds_reserve;
-    const dim3 block(64 * (NW + 1));
-    const bool hk = a.d.has_k, hs = a.d.has_s;
-    if (hk && hs) flux_walk_kernel<MODE, true, true, MRT, NW, CST><<<nblocks, block, lds, st>>>(a);
-    else if (hk) flux_walk_kernel<MODE, true, false, MRT, NW, CST><<<nblocks, block, lds, st>>>(a);
-    else if (hs) flux_walk_kernel<MODE, false, true, MRT, NW, CST><<<nblocks, block, lds, st>>>(a);
-    else flux_walk_kernel<MODE, false, false, MRT, NW, CST><<<nblocks, block, lds, st>>>(a);
-    return hipGetLastError();
-}
-
-template <int MODE, bool MRT>
-hipError_t launch_flux_var(const StepArgs &a, hipStream_t st)
-{
-    const bool cst = a.d.lc.stores == 1;
-    if (a.d.lc.wide)
-        return cst ? launch_flux_nw<MODE, MRT, 4, true>(a, st) : launch_flux_nw<MODE, MRT, 4, false>(a, st);
-    return cst ? launch_flux_nw<MODE, MRT, 1, true>(a, st) : launch_flux_nw<MODE, MRT, 1, false>(a, st);
-}
-
-template <int MODE>
-hipError_t launch_flux_mode(const StepArgs &a, hipStream_t st)
-{
-    return a.d.w3 != 0.0 ? launch_flux_var<MODE, true>(a, st) : launch_flux_var<MODE, false>(a, st);
-}
-
 template <int MODE, int AUX, bool MRT, int NW, bool CST>
 hipError_t launch_fused_nw(const StepArgs &a, hipStream_t st)
 {
@@ -389,20 +248,6 @@ hipError_t launch_fused_mode(int aux, const StepArgs &a, hipStream_t st)
 }
 
 }  // namespace
-
-hipError_t launch_flux_walk(int mode, const StepArgs &a, hipStream_t st)
-{
-    if (a.d.L.q != 9 || a.d.bckind != 0 || a.d.lc.stores == 2) return hipErrorInvalidValue;
-    if (a.d.lc.rows < 1 || a.d.lc.rows > 1024 || a.d.lc.lds_reserve < 0 || a.d.lc.lds_reserve > 65536)
-        return hipErrorInvalidValue;
-    switch (mode) {
-    case MODE_F64_F64: return launch_flux_mode<MODE_F64_F64>(a, st);
-    case MODE_F64_F32: return launch_flux_mode<MODE_F64_F32>(a, st);
-    case MODE_F32_F32: return launch_flux_mode<MODE_F32_F32>(a, st);
-    case MODE_F16S_F32: return launch_flux_mode<MODE_F16S_F32>(a, st);
-    default: return hipErrorInvalidValue;
-    }
-}
 
 hipError_t launch_step2(int mode, int aux, const StepArgs &a, hipStream_t st)
 {

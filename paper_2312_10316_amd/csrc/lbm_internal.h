@@ -194,9 +194,6 @@ hipError_t launch_step(int mode, int aux, const StepArgs &a, hipStream_t st);
 // Two steps per launch (lbm_fused.hip): D2Q9, periodic, aux LOCAL or NONE, two buffers (reads
 // buf[parity], writes buf[parity ^ 1] two steps later).  lc.fuse_width columns x lc.rows rows per tile.
 hipError_t launch_step2(int mode, int aux, const StepArgs &a, hipStream_t st);
-// One step with the flux form of the auxiliary term (lbm_fused.hip): D2Q9, periodic, two buffers;
-// tiles of 256 (lc.wide) or 64 columns by lc.rows rows.
-hipError_t launch_flux_walk(int mode, const StepArgs &a, hipStream_t st);
 hipError_t launch_batched_step(int mode, int aux, const BatchArgs &a, int nblocks, int lds_reserve, hipStream_t st);
 hipError_t launch_init(int mode, const InitArgs &a, hipStream_t st);
 hipError_t launch_prep(int mode, const PrepArgs &a, hipStream_t st);

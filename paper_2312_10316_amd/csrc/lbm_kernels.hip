@@ -690,7 +690,8 @@ template <int MODE, int AUX, int BC, bool MRT>
 hipError_t launch_step_var(const StepArgs &a, hipStream_t st)
 {
     if constexpr (AUX == 1) {
-        return launch_flux_walk(MODE, a, st);  // one instance: the walking kernel of lbm_fused.hip
+        return a.d.lc.stores ? launch_step_rows<MODE, AUX, BC, MRT, 0, true>(a, st)
+                             : launch_step_rows<MODE, AUX, BC, MRT, 0, false>(a, st);
     } else {
         if constexpr (BC == 0) {  // one buffer in place (stores == 2): alternate the two steps
             if (a.d.lc.stores == 2) {
