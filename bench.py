@@ -24,8 +24,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "D2Q9 TRT-R MLUPS & % HBM roofline, FP32/FP16 vs FP64 at fixed L2 error"
 HBM_PEAK_GBPS = 8000.0
-STORE_BYTES = {"f64": 8, "f64s_f32m": 8, "f32": 4, "f16s": 2}
-FIELD_BYTES = {"f64": 8, "f64s_f32m": 4, "f32": 4, "f16s": 4}
+STORE_BYTES = {"f64": 8, "f64s_f32m": 8, "f32": 4, "f16s": 2, "f16sr": 2}
+FIELD_BYTES = {"f64": 8, "f64s_f32m": 4, "f32": 4, "f16s": 4, "f16sr": 4}
 KERNEL_SRC = os.path.join(ROOT, "paper_2312_10316_amd", "csrc", "lbm_kernels.hip")
 
 
@@ -203,7 +203,7 @@ def _timed_steps(torch, s, nsteps):
     return e0.elapsed_time(e1) / max(nsteps, 1)
 
 
-def run_hbm(torch, W, lbm, Solver, n=8192, steps=200, warmup=32, modes=("f32", "f16s", "f64", "f64s_f32m")):
+def run_hbm(torch, W, lbm, Solver, n=8192, steps=200, warmup=32, modes=("f32", "f16s", "f16sr", "f64", "f64s_f32m")):
     """The streaming regime: the rotating pulse (constant D) on a periodic n^2 lattice whose two
     population buffers (1.2-9.7 GB at 8192^2) far exceed the 256 MiB Infinity Cache, so every step
     reads and writes HBM.  Per storage mode: MLUPS over `steps` graph-replayed steps (HIP events on
@@ -240,7 +240,7 @@ def run_precision_8192(torch, W, lbm, Solver, n=8192, steps=1000):
     f = W.rotating_pulse(cfg)
     dev = {k: torch.from_numpy(f[k]).cuda() for k in ("phi0", "ux", "uy", "D")}
     out, ref = {}, None
-    for mode in ("f64", "f64s_f32m", "f32", "f16s"):
+    for mode in ("f64", "f64s_f32m", "f32", "f16s", "f16sr"):
         s = Solver([(lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, mode), dev)])
         m0 = s.macros()["mass"]
         s.step(64)
@@ -279,7 +279,8 @@ def run_precision_8192(torch, W, lbm, Solver, n=8192, steps=1000):
     return out
 
 
-def run_refinement(torch, W, lbm, Solver, sizes=(64, 128, 256, 512, 1024, 2048), modes=("f64", "f32", "f16s")):
+def run_refinement(torch, W, lbm, Solver, sizes=(64, 128, 256, 512, 1024, 2048),
+                   modes=("f64", "f32", "f16s", "f16sr")):
     """E_r against the closed-form pulse at t = 0.3125 under acoustic (c = 10) and diffusive
     (dx^2/dt fixed at its 256^2 value) refinement; least-squares orders over N >= 256 (the coarse grids
     under-resolve sigma0 = 0.1); N* = finest N at which a reduced-precision mode stays within 5 % of the
@@ -342,7 +343,7 @@ def run_dirichlet(torch, W, lbm, Solver, sizes=(100, 200, 400, 800), kappa=0.05,
     Dirichlet-edge step kernel at (n_tp+1)^2 (graph-replayed, S and phi_b held fixed)."""
     import numpy as np
     out = {"kappa": kappa, "N": list(sizes), "E_r": {}, "order": {}}
-    for mode in ("f64", "f32", "f16s"):
+    for mode in ("f64", "f32", "f16s", "f16sr"):
         errs = []
         for N in sizes:
             x1 = W.x1_problem(N, kappa, dirichlet=True)
@@ -657,7 +658,7 @@ def oracle_cross_check(torch, W, lbm, Solver, phi_orc):
     ref = torch.from_numpy(W.pulse_reference(cfg, f)).cuda()
     orc = torch.from_numpy(np.ascontiguousarray(phi_orc)).cuda()
     out = {"N": 1024, "steps": 1000, "D": "1e-3 (1 + 0.5 sin(pi x) sin(pi y))"}
-    for mode in ("f64", "f64s_f32m", "f32", "f16s"):
+    for mode in ("f64", "f64s_f32m", "f32", "f16s", "f16sr"):
         s = Solver([(lbm.make_params(1024, 1024, f["dx"], f["dt"], cfg.lam, cfg.D, mode), dev)])
         s.step(cfg.steps)
         st, phi = s.macros(ref=ref, want_phi=True, raise_nonfinite=False)
@@ -670,7 +671,7 @@ def oracle_cross_check(torch, W, lbm, Solver, phi_orc):
     return out
 
 
-KERNEL_MODES = {"0": "f64", "1": "f64s_f32m", "2": "f32", "3": "f16s"}
+KERNEL_MODES = {"0": "f64", "1": "f64s_f32m", "2": "f32", "3": "f16s", "4": "f16sr"}
 TRACE_STEPS = {2048: 200, 8192: 100}  # timed steps of the kernel-trace runs
 
 
@@ -897,7 +898,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--n", type=int, default=2048)
-    ap.add_argument("--modes", default="f32,f64,f64s_f32m,f16s")
+    ap.add_argument("--modes", default="f32,f64,f64s_f32m,f16s,f16sr")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-studies", action="store_true",
@@ -991,7 +992,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f32": "f32", "f64": "f64", "f64s_f32m": "f64-store/f32", "f16s": "f16-store/f32"}[head],
+        "dtype": {"f32": "f32", "f64": "f64", "f64s_f32m": "f64-store/f32", "f16s": "f16-store/f32",
+                  "f16sr": "f16-store (stochastic rounding)/f32"}[head],
         "data": "synthetic",
         "config": {"workload": f"rotating Gaussian pulse, periodic {args.n}^2, c=10, U0=pi, D=1e-3, Lambda=1/4, "
                                f"{args.warmup}+{args.steps} steps", "N": args.n, "storage": head,

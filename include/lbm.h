@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 8
+#define LBM_ABI_VERSION 9
 
 enum lbm_status {
     LBM_OK = 0,
@@ -52,8 +52,21 @@ enum lbm_status {
 };
 
 /* Population storage.  F16S stores h = f16_rne((g_i - w_i phi_ref) * 2^scale_log2) and decodes
- * g_i = h * 2^-scale_log2 + w_i phi_ref; collision arithmetic is then FP32. */
-enum lbm_store { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16S = 2 };
+ * g_i = h * 2^-scale_log2 + w_i phi_ref; collision arithmetic is then FP32.
+ * F16SR (D2Q9 only) stores the same code, rounded stochastically instead of to nearest (an addition
+ * to the paper, after Croci & Giles 2020, who showed that round-to-nearest stagnates in low-precision
+ * time stepping of diffusion and stochastic rounding does not): with v the FP32 value
+ * (g_i - w_i phi_ref) * 2^scale_log2, lo <= |v| < lo + ulp its FP16 neighbours and r a 13-bit integer,
+ * |v| rounds up to lo + ulp iff r < floor(2^13 (|v| - lo) / ulp) (probability (|v| - lo) / ulp exactly
+ * for FP16 normal values; bits below 2^-13 ulp, which exist only in the FP16 subnormal range, are
+ * dropped); rounding up from 65504, or |v| >= 65536, gives infinity.  The r of population i of node
+ * j = y nx + x written at time level t (the step count of the new state; 0 at init) is bits
+ * 13 i .. 13 i + 12 of the 128-bit value hi:lo, where lo and hi are outputs 2(t nx ny + j) and
+ * 2(t nx ny + j) + 1 (counted from 0) of SplitMix64 (Steele, Lea & Flood 2014: output k is
+ * mix(seed + (k + 1) * 0x9e3779b97f4a7c15)) started at seed = (uint32_t)round_seed.  The codes are
+ * therefore a pure function of the state, the step count and the seed: bitwise independent of the
+ * launch shape, and a state saved at step n resumes bitwise when loaded with step n. */
+enum lbm_store { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16S = 2, LBM_STORE_F16SR = 3 };
 /* Collision arithmetic.  LBM_MATH_F64 requires LBM_STORE_F64. */
 enum lbm_math { LBM_MATH_F64 = 0, LBM_MATH_F32 = 1 };
 /* Auxiliary term G_i (Sec. 2.3):
@@ -99,10 +112,10 @@ typedef struct lbm_params {
     int32_t store;        /* enum lbm_store */
     int32_t math;         /* enum lbm_math */
     int32_t aux;          /* enum lbm_aux */
-    int32_t scale_log2;   /* F16S only: 0..24 */
-    double phi_ref;       /* F16S only: background value removed before encoding */
+    int32_t scale_log2;   /* F16S and F16SR only: 0..24 */
+    double phi_ref;       /* F16S and F16SR only: background value removed before encoding */
     int32_t boundary;     /* enum lbm_boundary */
-    int32_t reserved;     /* must be 0 */
+    int32_t round_seed;   /* F16SR: seed of the rounding stream (any value); must be 0 for the other stores */
     double tau3;          /* MRT-R (Sec. 2.2, Eq. (11), truncated after third order): relaxation time of
                              the third-order Hermite non-equilibrium moments, finite and > 1/2;
                              0 (or 1) selects the TRT-R operator of Eq. (12), which drops them */

@@ -43,9 +43,9 @@ int mode_of(const lbm_params &p)
 {
     if (p.store == LBM_STORE_F64) return p.math == LBM_MATH_F64 ? MODE_F64_F64 : MODE_F64_F32;
     if (p.store == LBM_STORE_F32) return MODE_F32_F32;
-    return MODE_F16S_F32;
+    return p.store == LBM_STORE_F16SR ? MODE_F16SR_F32 : MODE_F16S_F32;
 }
-size_t store_bytes(int mode) { return mode == MODE_F32_F32 ? 4 : (mode == MODE_F16S_F32 ? 2 : 8); }
+size_t store_bytes(int mode) { return mode == MODE_F32_F32 ? 4 : (is_f16_mode(mode) ? 2 : 8); }
 size_t math_bytes(int mode) { return mode == MODE_F64_F64 ? 8 : 4; }
 
 // Row pitch: nx rounded up to 64 elements, plus 64 more when the population row segment would be a
@@ -107,7 +107,7 @@ int lds_reserve_for(int max_waves, int lds_per_cu)
 Launch default_launch(const lbm_params &p, int mode, bool has_D, int n_inst, int lds_per_cu)
 {
     Launch lc{1, 0, 1, 0, 0, 0};
-    const bool f32 = mode == MODE_F32_F32, f16 = mode == MODE_F16S_F32;
+    const bool f32 = mode == MODE_F32_F32, f16 = is_f16_mode(mode);
     const int ntx = (p.nx + 255) / 256;
     const int bands = ntx % 8 == 0 ? 2 : 1;
     const auto row_blocks = [&lc](int h) {
@@ -176,7 +176,7 @@ Launch fused_default(const lbm_params &p, int mode)
     if (mode == MODE_F32_F32) {
         width = narrow ? 512 : 256;
         rows = 16;
-    } else if (mode == MODE_F16S_F32) {
+    } else if (is_f16_mode(mode)) {
         width = narrow ? 512 : 128;
         rows = narrow ? 16 : 32;
     } else {
@@ -219,14 +219,15 @@ int validate(const lbm_params &p, int k)
         return fail(LBM_E_ARG, "instance %d: nx=%d exceeds 2^24", k, p.nx);
     if (!finite_pos(p.dx) || !finite_pos(p.dt)) return fail(LBM_E_ARG, "instance %d: dx and dt must be finite and > 0", k);
     if (!finite_pos(p.lambda)) return fail(LBM_E_ARG, "instance %d: lambda must be finite and > 0", k);
-    if (p.store < LBM_STORE_F64 || p.store > LBM_STORE_F16S) return fail(LBM_E_ARG, "instance %d: unknown store %d", k, p.store);
+    if (p.store < LBM_STORE_F64 || p.store > LBM_STORE_F16SR) return fail(LBM_E_ARG, "instance %d: unknown store %d", k, p.store);
     if (p.math != LBM_MATH_F64 && p.math != LBM_MATH_F32) return fail(LBM_E_ARG, "instance %d: unknown math %d", k, p.math);
     if (p.math == LBM_MATH_F64 && p.store != LBM_STORE_F64)
         return fail(LBM_E_ARG, "instance %d: FP64 math needs FP64 storage", k);
     if (p.aux < LBM_AUX_LOCAL || p.aux > LBM_AUX_NONE) return fail(LBM_E_ARG, "instance %d: unknown aux %d", k, p.aux);
     if (p.boundary < LBM_BC_PERIODIC || p.boundary > LBM_BC_WALLS)
         return fail(LBM_E_ARG, "instance %d: unknown boundary %d", k, p.boundary);
-    if (p.reserved != 0) return fail(LBM_E_ARG, "instance %d: reserved field must be 0", k);
+    if (p.round_seed != 0 && p.store != LBM_STORE_F16SR)
+        return fail(LBM_E_ARG, "instance %d: round_seed is for LBM_STORE_F16SR only (0 otherwise)", k);
     if (p.boundary != LBM_BC_PERIODIC && p.aux == LBM_AUX_FLUX)
         return fail(LBM_E_UNSUPPORTED, "instance %d: the flux form of the aux term is periodic only", k);
     if (p.tau3 != 0.0 && !(std::isfinite(p.tau3) && p.tau3 > 0.5))
@@ -235,8 +236,10 @@ int validate(const lbm_params &p, int k)
         if (p.aux == LBM_AUX_FLUX) return fail(LBM_E_UNSUPPORTED, "instance %d: the flux form is D2Q9 only", k);
         if (p.boundary != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "instance %d: 3D lattices are periodic only", k);
         if (p.tau3 != 0.0 && p.tau3 != 1.0) return fail(LBM_E_UNSUPPORTED, "instance %d: no MRT-R on 3D lattices", k);
+        if (p.store == LBM_STORE_F16SR)
+            return fail(LBM_E_UNSUPPORTED, "instance %d: stochastic rounding is D2Q9 only", k);
     }
-    if (p.store == LBM_STORE_F16S) {
+    if (p.store == LBM_STORE_F16S || p.store == LBM_STORE_F16SR) {
         if (p.scale_log2 < 0 || p.scale_log2 > 24)
             return fail(LBM_E_ARG, "instance %d: scale_log2=%d outside 0..24", k, p.scale_log2);
         if (!std::isfinite(p.phi_ref)) return fail(LBM_E_ARG, "instance %d: phi_ref is not finite", k);
@@ -256,11 +259,13 @@ double weight3(int q, int i)
 F16Params f16_of(const lbm_params &p)
 {
     F16Params f{};
-    if (p.store == LBM_STORE_F16S) {
+    if (p.store == LBM_STORE_F16S || p.store == LBM_STORE_F16SR) {
         f.scale = std::ldexp(1.0f, p.scale_log2);
         f.inv_scale = std::ldexp(1.0f, -p.scale_log2);
         const int q = layout_of(p).q;
         for (int i = 0; i < q; ++i) f.wref[i] = (float)((q == 9 ? kW[i] : weight3(q, i)) * p.phi_ref);
+        f.seed = (uint64_t)(uint32_t)p.round_seed;
+        f.nodes = (int64_t)p.nx * p.ny;
     } else {
         f.scale = f.inv_scale = 1.0f;
     }
@@ -280,6 +285,7 @@ struct Instance {
     bool has_src;
     int64_t step;
     F16Params f16;
+    int64_t *clock;  // device pair: time level of the state in each buffer slot (stochastic rounding)
 };
 
 // Per instance: 2 population buffers, the velocity pair, and the k and s fields (math type).
@@ -310,7 +316,7 @@ size_t tables_bytes(int32_t n_inst, const lbm_params *p)
 {
     const size_t items = max_items_of(n_inst, p);
     return align_up((size_t)n_inst * sizeof(InstDesc), kAlign) + align_up(items * sizeof(WorkItem), kAlign) +
-           align_up((items + 1) * sizeof(int32_t), kAlign);
+           align_up((items + 1) * sizeof(int32_t), kAlign) + align_up((size_t)n_inst * 2 * sizeof(int64_t), kAlign);
 }
 
 // Constant-D relaxation: tau1 - 1/2 = kappa / (cs^2 dt) = 3 kappa dt / dx^2 (Sec. 2.4), and
@@ -342,6 +348,7 @@ InstDesc desc_of(const Instance &in)
     d.w3 = in.p.tau3 == 0.0 ? 0.0 : 1.0 - 1.0 / in.p.tau3;
     d.lambda = in.p.lambda;
     d.f16 = in.f16;
+    d.clock = in.clock;
     return d;
 }
 
@@ -506,6 +513,16 @@ int set_velocity(lbm_ctx *c, Instance &in, const double *ux, const double *uy, c
 }
 
 bool is3d(const Instance &in) { return in.L.q != 9; }
+
+// Stochastic rounding indexes its random bits by the time level, which the kernels advance in device
+// memory (graph replays included).  Where the host sets a state or moves it to the other buffer slot,
+// it writes the level of the slot that now holds the state.
+int sync_clock(lbm_ctx *c, Instance &in)
+{
+    if (in.mode != MODE_F16SR_F32) return LBM_OK;
+    hipError_t e = launch_set_clock(in.clock + c->parity, in.step, c->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "setting the time level of a stochastically rounded state");
+}
 
 // Enqueues one step of every instance on stream st.
 int enqueue_step(lbm_ctx *c, hipStream_t st)
@@ -755,6 +772,8 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
     c->d_items = reinterpret_cast<WorkItem *>(w);
     w += align_up(items * sizeof(WorkItem), kAlign);
     c->d_block_start = reinterpret_cast<int32_t *>(w);
+    w += align_up((items + 1) * sizeof(int32_t), kAlign);
+    for (int k = 0; k < n_inst; ++k) c->inst[k].clock = reinterpret_cast<int64_t *>(w) + 2 * k;  // zeroed below
     // a uniform batch defaults to one flat launch; FP32 runs it with at most 6 waves per SIMD (+2 %)
     if (n_inst > 1 && c->uniform) c->batch = lbm_batch{LBM_BATCH_FLAT, 0, c->inst[0].mode == MODE_F32_F32 ? 6 : 0};
 
@@ -1002,7 +1021,7 @@ int lbm_state_load(lbm_ctx *c, int32_t inst, const void *src, int64_t step)
                        : hipMemcpyAsync(in.buf[c->parity], src, pops_bytes(in.p), hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(e, "lbm_state_load");
     in.step = step;
-    return LBM_OK;
+    return sync_clock(c, in);
 }
 
 int lbm_set_launch(lbm_ctx *c, int32_t inst, const lbm_launch *cfg)
@@ -1068,6 +1087,8 @@ int lbm_set_launch(lbm_ctx *c, int32_t inst, const lbm_launch *cfg)
                 hipError_t e = hipMemcpyAsync(in.buf[0], in.buf[1], pops_bytes(in.p), hipMemcpyDeviceToDevice, c->stream);
                 if (e != hipSuccess) return hip_fail(e, "lbm_set_launch: moving the state to one buffer");
                 c->parity = 0;
+                const int rc = sync_clock(c, in);
+                if (rc) return rc;
             }
             in.buf[1] = in.buf[0];
         }
@@ -1126,7 +1147,7 @@ int adjoint_ok(lbm_ctx *c, int32_t inst, const char *who)
 {
     if (!check_inst(c, inst)) return fail(LBM_E_STATE, "%s: bad context or instance %d", who, inst);
     const Instance &in = c->inst[inst];
-    if (in.mode == MODE_F16S_F32) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for FP16 storage", who);
+    if (is_f16_mode(in.mode)) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for FP16 storage", who);
     if (in.p.aux == LBM_AUX_FLUX) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for the flux form of the aux term", who);
     if (in.p.boundary != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for Dirichlet edges or walls", who);
     if (in.p.tau3 != 0.0 && in.p.tau3 != 1.0) return fail(LBM_E_UNSUPPORTED, "%s: no adjoint for the MRT-R operator", who);

@@ -131,44 +131,142 @@ struct StoreF32 {
 struct StoreF16S {
     using T = _Float16;
 };
+struct StoreF16SR {  // the F16S code, written with stochastic rounding
+    using T = _Float16;
+};
 
 // F16S codec constants: h = f16((g - w_i phi_ref) * 2^k); g = h * 2^-k + w_i phi_ref.
 struct F16Params {
     float scale, inv_scale;
     float wref[27];  // w_i phi_ref per velocity (9, 19 or 27 used)
+    uint64_t seed;   // F16SR: start state of the rounding stream
+    int64_t nodes;   // F16SR: nodes of the lattice (the stream's stride per time level)
 };
 
+// ---- random bits of the stochastic rounding (F16SR) ------------------------------------------
+//
+// Stochastic rounding (Croci & Giles 2020 studied it for low-precision time stepping of the heat
+// equation) rounds a value to one of its two FP16 neighbours with probability proportional to its
+// distance from the other, so the rounding error has zero mean and small updates are not lost on
+// average.  The random bits are a pure function of (time level, node): every launch shape, tile
+// order and kernel gives the same codes.  Node j of a lattice of n nodes at time level t takes
+// outputs 2(t n + j) and 2(t n + j) + 1 of SplitMix64 (Steele, Lea & Flood 2014: output k of the
+// generator started at state s is mix(s + (k + 1) gamma)), 128 bits hi:lo, and population i uses bits
+// 13 i .. 13 i + 12 (117 bits for the nine) as its integer r.  Thirteen bits are what FP32 carries
+// below the FP16 unit in the last place (24 - 11 significand bits), so the rounding of a normal FP16
+// value is exactly unbiased for its FP32 input.
+
+constexpr uint64_t kSplitMixGamma = 0x9e3779b97f4a7c15ull;
+
+__device__ __forceinline__ uint64_t splitmix64_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+struct NoBits {};  // what the deterministic codecs take in place of random bits
+struct NodeBits {
+    uint64_t lo, hi;  // stream outputs 2(t n + j) and 2(t n + j) + 1
+};
+
+// The random operand of the conversion below for population i: its bits 19..31 are the complement of
+// bits 13 i .. 13 i + 12 of hi:lo (i.e. 2^13 - 1 - r); the conversion reads no other bits.  i is a
+// compile-time constant once the callers' loops unroll, so this is one shift or funnel shift.
+__device__ __forceinline__ uint32_t sr_operand(const NodeBits &b, int i)
+{
+    const int sh = 13 * i - 19;
+    const uint64_t lo = ~b.lo, hi = ~b.hi;
+    if (sh < 0) return (uint32_t)(lo << -sh);
+    if (sh + 32 <= 64) return (uint32_t)(lo >> sh);
+    if (sh >= 64) return (uint32_t)(hi >> (sh - 64));
+    return (uint32_t)((lo >> sh) | (hi << (64 - sh)));
+}
+
+// FP32 -> FP16 with stochastic rounding, by gfx950's v_cvt_sr_f16_f32: with lo <= |s| < lo + ulp the
+// FP16 neighbours of |s| and m the 13 bits of |s| just below the FP16 spacing (m = floor(2^13 (|s| -
+// lo) / ulp); bits further down, which exist only in the FP16 subnormal range, are dropped), the
+// conversion adds the top 13 bits R of its random operand to m and keeps the carry: |s| goes up iff
+// m + R >= 2^13.  With R = 2^13 - 1 - r that is r < m: probability m / 2^13, exactly (|s| - lo) / ulp
+// for FP16 normal values.  Rounding up from 65504, or any |s| from 65536 on, gives infinity; NaN, the
+// infinities and signed zeros are kept.  (Measured on the device over 2^17 value/operand pairs and the
+// special values; the tests hold every stored code to this rule, bitwise.)
+__device__ __forceinline__ _Float16 sr_half(float s, uint32_t operand)
+{
+    typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+    const half2_t z = {(_Float16)0.0f, (_Float16)0.0f};
+    return __builtin_amdgcn_cvt_sr_f16_f32(z, s, operand, false)[0];
+}
+
+// A codec decodes a stored element to the math type and encodes one back.  `bits(f, level, row_node, x)`
+// gives what enc needs besides the value: the random bits of node row_node + x (row_node = y nx) at time
+// level `level` (the step count of the state being written) for F16SR, nothing for the others;
+// kStochastic says whether a kernel has to track the time level.
 template <class St, class M>
 struct Codec;
 
+template <class M>
+struct DetCodecBase {
+    static constexpr bool kStochastic = false;
+    using Bits = NoBits;
+    __device__ __forceinline__ static NoBits bits(const F16Params &, int64_t, int64_t, unsigned) { return {}; }
+};
+
 template <>
-struct Codec<StoreF64, double> {
+struct Codec<StoreF64, double> : DetCodecBase<double> {
     __device__ __forceinline__ static double dec(double v, int, const F16Params &) { return v; }
-    __device__ __forceinline__ static double enc(double v, int, const F16Params &) { return v; }
+    __device__ __forceinline__ static double enc(double v, int, const F16Params &, NoBits = {}) { return v; }
 };
 template <>
-struct Codec<StoreF64, float> {
+struct Codec<StoreF64, float> : DetCodecBase<float> {
     __device__ __forceinline__ static float dec(double v, int, const F16Params &) { return (float)v; }
-    __device__ __forceinline__ static double enc(float v, int, const F16Params &) { return (double)v; }
+    __device__ __forceinline__ static double enc(float v, int, const F16Params &, NoBits = {}) { return (double)v; }
 };
 template <>
-struct Codec<StoreF32, float> {
+struct Codec<StoreF32, float> : DetCodecBase<float> {
     __device__ __forceinline__ static float dec(float v, int, const F16Params &) { return v; }
-    __device__ __forceinline__ static float enc(float v, int, const F16Params &) { return v; }
+    __device__ __forceinline__ static float enc(float v, int, const F16Params &, NoBits = {}) { return v; }
 };
 template <>
-struct Codec<StoreF16S, float> {
+struct Codec<StoreF16S, float> : DetCodecBase<float> {
     __device__ __forceinline__ static float dec(_Float16 v, int i, const F16Params &c)
     {
         return (float)v * c.inv_scale + c.wref[i];
     }
-    __device__ __forceinline__ static _Float16 enc(float v, int i, const F16Params &c)
+    __device__ __forceinline__ static _Float16 enc(float v, int i, const F16Params &c, NoBits = {})
     {
         // The shift is a plain FP32 subtraction of the rounded value v (never fused with the product
         // that formed v), so the stored code does not depend on how the caller's arithmetic is
         // contracted; the power-of-two scale is exact; v_cvt_f16_f32 rounds to nearest even.
 #pragma clang fp contract(off)
         return (_Float16)((v - c.wref[i]) * c.scale);
+    }
+};
+template <>
+struct Codec<StoreF16SR, float> {
+    static constexpr bool kStochastic = true;
+    using Bits = NodeBits;
+    // Node j = row_node + x: the generator state of output 2(level n + j) is seed + (2(level n + j) + 1)
+    // gamma, split into a part uniform over the row and 2 gamma x, which stays in registers along a walk.
+    __device__ __forceinline__ static NodeBits bits(const F16Params &c, int64_t level, int64_t row_node, unsigned x)
+    {
+        const uint64_t s0 = c.seed + kSplitMixGamma * (2u * ((uint64_t)level * (uint64_t)c.nodes + (uint64_t)row_node) + 1u) +
+                            (2u * kSplitMixGamma) * (uint64_t)x;
+        return {splitmix64_mix(s0), splitmix64_mix(s0 + kSplitMixGamma)};
+    }
+    __device__ __forceinline__ static float dec(_Float16 v, int i, const F16Params &c)
+    {
+        return (float)v * c.inv_scale + c.wref[i];
+    }
+    __device__ __forceinline__ static _Float16 enc(float v, int i, const F16Params &c, const NodeBits &b)
+    {
+        // the same FP32 value as F16S encodes (shift not fused, exact scale), rounded stochastically
+        float t;
+        {
+#pragma clang fp contract(off)
+            t = (v - c.wref[i]) * c.scale;
+        }
+        return sr_half(t, sr_operand(b, i));
     }
 };
 

@@ -100,6 +100,10 @@ __attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW)))) void step2_kernel(co
     // e_x = 0 populations of earlier intermediate rows at this column, as a reader would decode them
     M p0_m = M(0), p2_m = M(0), p2_mm = M(0);
 
+    // stochastic rounding: time level of the state this launch reads; it writes levels + 1 and + 2
+    const int64_t level = launch_level<C>(d, a.parity);
+    advance_level<C>(d, a.parity, level, 2, t == 0 && threadIdx.x == 0);
+
     for (int r = rs; r <= y1; ++r) {
         // row indices through readfirstlane: uniform values the compiler cannot strength-reduce into
         // per-lane 64-bit address recurrences, so every access keeps the scalar-base + 32-bit-offset form
@@ -116,6 +120,7 @@ __attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW)))) void step2_kernel(co
         M dxux = M(0), dxuy = M(0), s = M(0);
         Relax<M> rr = rconst;
         M P[9] = {};
+        const auto rb1 = C::bits(d.f16, level + 1, (int64_t)rw * nx, (unsigned)xi);  // intermediate node (xi, r)
         if (act) {
             const T *__restrict__ rm = src + (int64_t)rwm * 9 * pitch;
             const T *__restrict__ rc = src + (int64_t)rw * 9 * pitch;
@@ -147,11 +152,11 @@ __attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW)))) void step2_kernel(co
             T(*slot)[WC] = ring[r & 3];
 #pragma unroll
             for (int i = 0; i < 9; ++i)
-                if (kPlane[i] >= 0) slot[kPlane[i]][c] = C::enc(P[i], i, d.f16);
+                if (kPlane[i] >= 0) slot[kPlane[i]][c] = C::enc(P[i], i, d.f16, rb1);
         }
         __syncthreads();
         // ---- phase 2: output node (x, y = r - 1) of step n + 2 ---------------------------------------
-        const M p4 = C::dec(C::enc(P[4], 4, d.f16), 4, d.f16);
+        const M p4 = C::dec(C::enc(P[4], 4, d.f16, rb1), 4, d.f16);
         if (!frame && r >= y0 + 1) {
             const int y = __builtin_amdgcn_readfirstlane(r - 1);
             M g[9];
@@ -179,17 +184,18 @@ __attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW)))) void step2_kernel(co
             collide<M, MRT>(g, ux_m, uy_m, r_m, Ax, Ay, s_m, Q);
             if (live) {
                 T *__restrict__ out = dst + (int64_t)y * 9 * pitch;
+                const auto rb2 = C::bits(d.f16, level + 2, (int64_t)y * nx, (unsigned)xi);  // output node (xi, y)
 #pragma unroll
                 for (int i = 0; i < 9; ++i) {
-                    if constexpr (CST) st_at(out, bc + (unsigned)i * pb, C::enc(Q[i], i, d.f16));
-                    else st_nt_at(out, bc + (unsigned)i * pb, C::enc(Q[i], i, d.f16));
+                    if constexpr (CST) st_at(out, bc + (unsigned)i * pb, C::enc(Q[i], i, d.f16, rb2));
+                    else st_nt_at(out, bc + (unsigned)i * pb, C::enc(Q[i], i, d.f16, rb2));
                 }
             }
         }
         // roll the walk down one row
         p2_mm = p2_m;
-        p2_m = C::dec(C::enc(P[2], 2, d.f16), 2, d.f16);
-        p0_m = C::dec(C::enc(P[0], 0, d.f16), 0, d.f16);
+        p2_m = C::dec(C::enc(P[2], 2, d.f16, rb1), 2, d.f16);
+        p0_m = C::dec(C::enc(P[0], 0, d.f16, rb1), 0, d.f16);
         dxux_m = dxux;
         dxuy_m = dxuy;
         r_m = rr;
@@ -259,6 +265,7 @@ hipError_t launch_step2(int mode, int aux, const StepArgs &a, hipStream_t st)
     case MODE_F64_F32: return launch_fused_mode<MODE_F64_F32>(aux, a, st);
     case MODE_F32_F32: return launch_fused_mode<MODE_F32_F32>(aux, a, st);
     case MODE_F16S_F32: return launch_fused_mode<MODE_F16S_F32>(aux, a, st);
+    case MODE_F16SR_F32: return launch_fused_mode<MODE_F16SR_F32>(aux, a, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -27,8 +27,10 @@ enum Mode : int {
     MODE_F64_F64 = 0,  // FP64 storage, FP64 math
     MODE_F64_F32 = 1,  // FP64 storage, FP32 math
     MODE_F32_F32 = 2,  // FP32 storage, FP32 math
-    MODE_F16S_F32 = 3  // shifted/scaled FP16 storage, FP32 math
+    MODE_F16S_F32 = 3,  // shifted/scaled FP16 storage, FP32 math
+    MODE_F16SR_F32 = 4  // the same FP16 code written with stochastic rounding (D2Q9 only)
 };
+constexpr bool is_f16_mode(int mode) { return mode == MODE_F16S_F32 || mode == MODE_F16SR_F32; }
 
 struct Layout {
     int32_t nx, ny;
@@ -76,6 +78,8 @@ struct InstDesc {
     double w3;          // 1 - 1/tau3 (MRT-R); 0 for TRT-R
     double lambda;
     F16Params f16;
+    int64_t *clock;     // F16SR: time level of the state in buf[0] and buf[1] (a launch reads
+                        // clock[parity] and its first thread writes clock[parity ^ 1]); else unused
 };
 
 struct StepArgs {
@@ -196,6 +200,8 @@ hipError_t launch_step(int mode, int aux, const StepArgs &a, hipStream_t st);
 hipError_t launch_step2(int mode, int aux, const StepArgs &a, hipStream_t st);
 hipError_t launch_batched_step(int mode, int aux, const BatchArgs &a, int nblocks, int lds_reserve, hipStream_t st);
 hipError_t launch_init(int mode, const InitArgs &a, hipStream_t st);
+// F16SR: sets *slot = level (one lane of one block; kept out of graph captures by the callers).
+hipError_t launch_set_clock(int64_t *slot, int64_t level, hipStream_t st);
 hipError_t launch_prep(int mode, const PrepArgs &a, hipStream_t st);
 hipError_t launch_macros(int mode, const MacroArgs &a, double *result, hipStream_t st);
 hipError_t launch_macros_finalize(const double *partials, int nblocks, double *result, hipStream_t st);

@@ -28,6 +28,34 @@ struct ModeTraits<MODE_F16S_F32> {
     using St = StoreF16S;
     using M = float;
 };
+template <>
+struct ModeTraits<MODE_F16SR_F32> {
+    using St = StoreF16SR;
+    using M = float;
+};
+
+// Time level of the state a launch reads (stochastic rounding only; 0 otherwise).  The counter pair
+// lives in device memory so that graph replays see the level advance: a launch reads clock[parity],
+// which no thread of it writes, and one thread of it writes clock[parity ^ 1] for the next launch.
+template <class C>
+__device__ __forceinline__ int64_t launch_level(const InstDesc &d, int parity)
+{
+    if constexpr (C::kStochastic) {
+        const int64_t v = __hip_atomic_load(d.clock + parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+        return (int64_t)(((uint64_t)hi << 32) | lo);
+    } else {
+        return 0;
+    }
+}
+template <class C>
+__device__ __forceinline__ void advance_level(const InstDesc &d, int parity, int64_t level, int steps, bool writer)
+{
+    if constexpr (C::kStochastic) {
+        if (writer) __hip_atomic_store(d.clock + (parity ^ 1), level + steps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
 
 __device__ __forceinline__ int wrap_dec(int v, int n) { return v == 0 ? n - 1 : v - 1; }
 __device__ __forceinline__ int wrap_inc(int v, int n) { return v == n - 1 ? 0 : v + 1; }

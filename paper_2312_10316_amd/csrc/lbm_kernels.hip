@@ -175,6 +175,8 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
     int x0, y0;
     tile_origin(a.L, a.lc, t, wave, x0, y0);
     if (y0 >= ny || x0 >= nx) return;
+    const int64_t level = launch_level<C>(a, parity) + 1;  // time level written (stochastic rounding)
+    advance_level<C>(a, parity, level - 1, 1, t == 0 && wave == 0 && threadIdx.x == 0);
     const unsigned x = (unsigned)x0 + threadIdx.x;
     const bool live = x < (unsigned)nx;
     const unsigned xc = live ? x : 0u;  // dead lanes of a ragged tile read column 0 and store nothing
@@ -262,27 +264,28 @@ __device__ __forceinline__ void process_tile(const InstDesc &a, int parity, int 
         const M s = HAS_S ? ld_at(sf + (int64_t)y * pitch, fc) : M(0);
         M P[9];
         collide<M, MRT>(g, ux_c, uy_c, r, Ax, Ay, s, P);
+        const auto rb = C::bits(a.f16, level, (int64_t)y * nx, xc);
         if (live && IP == 1) {
             // P_j to the address of g_opp(j): slot opp(j) of node x + e_j (every value is a function of
             // all nine loads, so no store can move ahead of them)
             T *wm = dst + (int64_t)ym * 9 * pitch, *wc = dst + (int64_t)y * 9 * pitch, *wp = dst + (int64_t)yn * 9 * pitch;
-            st_at(wc, bc, C::enc(P[0], 0, a.f16));
-            st_at(wc + 3 * pitch, bp, C::enc(P[1], 1, a.f16));
-            st_at(wp + 4 * pitch, bc, C::enc(P[2], 2, a.f16));
-            st_at(wc + pitch, bm, C::enc(P[3], 3, a.f16));
-            st_at(wm + 2 * pitch, bc, C::enc(P[4], 4, a.f16));
-            st_at(wp + 7 * pitch, bp, C::enc(P[5], 5, a.f16));
-            st_at(wp + 8 * pitch, bm, C::enc(P[6], 6, a.f16));
-            st_at(wm + 5 * pitch, bm, C::enc(P[7], 7, a.f16));
-            st_at(wm + 6 * pitch, bp, C::enc(P[8], 8, a.f16));
+            st_at(wc, bc, C::enc(P[0], 0, a.f16, rb));
+            st_at(wc + 3 * pitch, bp, C::enc(P[1], 1, a.f16, rb));
+            st_at(wp + 4 * pitch, bc, C::enc(P[2], 2, a.f16, rb));
+            st_at(wc + pitch, bm, C::enc(P[3], 3, a.f16, rb));
+            st_at(wm + 2 * pitch, bc, C::enc(P[4], 4, a.f16, rb));
+            st_at(wp + 7 * pitch, bp, C::enc(P[5], 5, a.f16, rb));
+            st_at(wp + 8 * pitch, bm, C::enc(P[6], 6, a.f16, rb));
+            st_at(wm + 5 * pitch, bm, C::enc(P[7], 7, a.f16, rb));
+            st_at(wm + 6 * pitch, bp, C::enc(P[8], 8, a.f16, rb));
         } else if (live) {
             // one scalar row base and 32-bit lane offsets keep every store in the saddr form
             const DstP out = dst + (int64_t)y * 9 * pitch;
             const unsigned pb = (unsigned)(pitch * (int64_t)sizeof(T));
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                if constexpr (CST || IP != 0) st_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, a.f16));
-                else st_nt_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, a.f16));
+                if constexpr (CST || IP != 0) st_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, a.f16, rb));
+                else st_nt_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, a.f16, rb));
             }
         }
         ux_m = ux_c;
@@ -314,6 +317,8 @@ __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity,
     int x0t, y0;  // the wave's first column and first row
     tile_origin(a.L, a.lc, t, wave, x0t, y0);
     if (y0 >= ny || x0t >= nx) return;
+    const int64_t level = launch_level<C>(a, parity) + 1;  // time level written (stochastic rounding)
+    advance_level<C>(a, parity, level - 1, 1, t == 0 && wave == 0 && lane == 0);
     const unsigned x = (unsigned)x0t + lane;
     const bool live = x < (unsigned)nx;
     const unsigned xc = live ? x : 0u;
@@ -333,7 +338,7 @@ __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity,
     int hxs = (lane < 9u ? xw : xe) - hex;
     hxs = hxs < 0 ? hxs + nx : (hxs >= nx ? hxs - nx : hxs);
     M hwref = M(0);
-    if constexpr (MODE == MODE_F16S_F32) {
+    if constexpr (is_f16_mode(MODE)) {
         const F16Params &f = a.f16;
         hwref = hi == 0 ? f.wref[0] : hi == 1 ? f.wref[1] : hi == 2 ? f.wref[2] : hi == 3 ? f.wref[3]
               : hi == 4 ? f.wref[4] : hi == 5 ? f.wref[5] : hi == 6 ? f.wref[6] : hi == 7 ? f.wref[7] : f.wref[8];
@@ -391,7 +396,7 @@ __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity,
             M hv = M(0);
             if (lane < 18u) {
                 const T raw = src[((int64_t)hys * 9 + hi) * pitch + hxs];
-                if constexpr (MODE == MODE_F16S_F32) hv = (float)raw * a.f16.inv_scale + hwref;
+                if constexpr (is_f16_mode(MODE)) hv = (float)raw * a.f16.inv_scale + hwref;
                 else hv = C::dec(raw, 0, a.f16);
             }
             M phw = lane_read<M>(hv, 0), phe = lane_read<M>(hv, 9);
@@ -416,10 +421,11 @@ __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity,
         if (live) {
             T *__restrict__ out = dst + (int64_t)y * 9 * pitch;
             const unsigned pb = (unsigned)(pitch * (int64_t)sizeof(T));
+            const auto rb = C::bits(a.f16, level, (int64_t)y * nx, xc);
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                if constexpr (CST) st_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, a.f16));
-                else st_nt_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, a.f16));
+                if constexpr (CST) st_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, a.f16, rb));
+                else st_nt_at(out, bc + (unsigned)i * pb, C::enc(P[i], i, a.f16, rb));
             }
         }
 #pragma unroll
@@ -494,13 +500,14 @@ __global__ __launch_bounds__(256) void init_kernel(const InitArgs a)
         const int x = (int)(n % nx), y = (int)(n / nx);
         M P[9];
         equilibrium<M>((M)a.phi0[n], u[(int64_t)y * 2 * pitch + x], u[((int64_t)y * 2 + 1) * pitch + x], P);
+        const auto rb = C::bits(a.f16, 0, (int64_t)y * nx, (unsigned)x);  // time level 0
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             int xd = x - kEx[i], yd = y - kEy[i];
             xd = xd < 0 ? xd + nx : (xd >= nx ? xd - nx : xd);
             const bool across = yd < 0 || yd >= ny;
             yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
-            if (MODE == MODE_F16S_F32) {
+            if (is_f16_mode(MODE)) {
                 const float v = ((float)P[i] - a.f16.wref[i]) * a.f16.scale;
                 bad |= !(fabsf(v) <= 65504.0f);
             }
@@ -509,10 +516,10 @@ __global__ __launch_bounds__(256) void init_kernel(const InitArgs a)
                 // wall-bound direction (read only by the reflection) takes g_eq_opp(i), so that the
                 // reflection returns g_eq_i while the wall value is phi0's.
                 const int o = kOpp[i];
-                dst[((int64_t)y * 9 + o) * pitch + x] = C::enc(P[o], o, a.f16);
+                dst[((int64_t)y * 9 + o) * pitch + x] = C::enc(P[o], o, a.f16, rb);
                 continue;
             }
-            dst[((int64_t)yd * 9 + i) * pitch + xd] = C::enc(P[i], i, a.f16);
+            dst[((int64_t)yd * 9 + i) * pitch + xd] = C::enc(P[i], i, a.f16, rb);
         }
     }
     if (bad) *a.range_flag = 1;  // every writer stores the same value
@@ -769,6 +776,7 @@ hipError_t launch_step(int mode, int aux, const StepArgs &a, hipStream_t st)
     case MODE_F64_F32: return launch_step_mode<MODE_F64_F32>(aux, a, st);
     case MODE_F32_F32: return launch_step_mode<MODE_F32_F32>(aux, a, st);
     case MODE_F16S_F32: return launch_step_mode<MODE_F16S_F32>(aux, a, st);
+    case MODE_F16SR_F32: return launch_step_mode<MODE_F16SR_F32>(aux, a, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -782,8 +790,23 @@ hipError_t launch_batched_step(int mode, int aux, const BatchArgs &a, int nblock
     case MODE_F64_F32: return launch_batched_mode<MODE_F64_F32>(aux, a, nblocks, lds, st);
     case MODE_F32_F32: return launch_batched_mode<MODE_F32_F32>(aux, a, nblocks, lds, st);
     case MODE_F16S_F32: return launch_batched_mode<MODE_F16S_F32>(aux, a, nblocks, lds, st);
+    case MODE_F16SR_F32: return launch_batched_mode<MODE_F16SR_F32>(aux, a, nblocks, lds, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+namespace {
+__global__ void set_clock_kernel(int64_t *slot, int64_t level)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *slot = level;
+}
+}  // namespace
+
+hipError_t launch_set_clock(int64_t *slot, int64_t level, hipStream_t st)
+{
+    if (!slot || level < 0) return hipErrorInvalidValue;
+    set_clock_kernel<<<1, 64, 0, st>>>(slot, level);
+    return hipGetLastError();
 }
 
 hipError_t launch_init(int mode, const InitArgs &a, hipStream_t st)
@@ -794,6 +817,7 @@ hipError_t launch_init(int mode, const InitArgs &a, hipStream_t st)
     case MODE_F64_F32: init_kernel<MODE_F64_F32><<<g, 256, 0, st>>>(a); break;
     case MODE_F32_F32: init_kernel<MODE_F32_F32><<<g, 256, 0, st>>>(a); break;
     case MODE_F16S_F32: init_kernel<MODE_F16S_F32><<<g, 256, 0, st>>>(a); break;
+    case MODE_F16SR_F32: init_kernel<MODE_F16SR_F32><<<g, 256, 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -814,7 +838,8 @@ hipError_t launch_macros(int mode, const MacroArgs &a, double *result, hipStream
     case MODE_F64_F64: macros_kernel<MODE_F64_F64><<<g, 256, 0, st>>>(a); break;
     case MODE_F64_F32: macros_kernel<MODE_F64_F32><<<g, 256, 0, st>>>(a); break;
     case MODE_F32_F32: macros_kernel<MODE_F32_F32><<<g, 256, 0, st>>>(a); break;
-    case MODE_F16S_F32: macros_kernel<MODE_F16S_F32><<<g, 256, 0, st>>>(a); break;
+    case MODE_F16S_F32:
+    case MODE_F16SR_F32: macros_kernel<MODE_F16S_F32><<<g, 256, 0, st>>>(a); break;  // one code format
     default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
@@ -835,7 +860,8 @@ hipError_t launch_populations(int mode, const PopArgs &a, hipStream_t st)
     case MODE_F64_F64: populations_kernel<MODE_F64_F64><<<g, 256, 0, st>>>(a); break;
     case MODE_F64_F32: populations_kernel<MODE_F64_F32><<<g, 256, 0, st>>>(a); break;
     case MODE_F32_F32: populations_kernel<MODE_F32_F32><<<g, 256, 0, st>>>(a); break;
-    case MODE_F16S_F32: populations_kernel<MODE_F16S_F32><<<g, 256, 0, st>>>(a); break;
+    case MODE_F16S_F32:
+    case MODE_F16SR_F32: populations_kernel<MODE_F16S_F32><<<g, 256, 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

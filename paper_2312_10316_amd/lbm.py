@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_E_ARG, LBM_E_HIP, LBM_E_STATE, LBM_E_NONFINITE, LBM_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-LBM_STORE_F64, LBM_STORE_F32, LBM_STORE_F16S = 0, 1, 2
+LBM_STORE_F64, LBM_STORE_F32, LBM_STORE_F16S, LBM_STORE_F16SR = 0, 1, 2, 3
 LBM_MATH_F64, LBM_MATH_F32 = 0, 1
 LBM_AUX_LOCAL, LBM_AUX_FLUX, LBM_AUX_NONE = 0, 1, 2
 LBM_BC_PERIODIC, LBM_BC_NEE, LBM_BC_WALLS = 0, 1, 2
@@ -29,8 +29,9 @@ MODES = {
     "f64s_f32m": (LBM_STORE_F64, LBM_MATH_F32),
     "f32": (LBM_STORE_F32, LBM_MATH_F32),
     "f16s": (LBM_STORE_F16S, LBM_MATH_F32),
+    "f16sr": (LBM_STORE_F16SR, LBM_MATH_F32),  # the F16S code with stochastic rounding
 }
-STORE_BYTES = {LBM_STORE_F64: 8, LBM_STORE_F32: 4, LBM_STORE_F16S: 2}
+STORE_BYTES = {LBM_STORE_F64: 8, LBM_STORE_F32: 4, LBM_STORE_F16S: 2, LBM_STORE_F16SR: 2}
 
 
 class LbmError(RuntimeError):
@@ -43,7 +44,7 @@ class lbm_params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("dx", ctypes.c_double), ("dt", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("D_const", ctypes.c_double), ("store", ctypes.c_int32),
                 ("math", ctypes.c_int32), ("aux", ctypes.c_int32), ("scale_log2", ctypes.c_int32),
-                ("phi_ref", ctypes.c_double), ("boundary", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("phi_ref", ctypes.c_double), ("boundary", ctypes.c_int32), ("round_seed", ctypes.c_int32),
                 ("tau3", ctypes.c_double), ("lattice", ctypes.c_int32), ("nz", ctypes.c_int32)]
 
 
@@ -159,16 +160,17 @@ def _ptr_array(ts: Optional[Sequence[Optional[torch.Tensor]]]):
 
 
 def make_params(nx, ny, dx, dt, lam, D_const=0.0, mode="f64", aux=LBM_AUX_LOCAL, scale_log2=15,
-                phi_ref=0.0, boundary=LBM_BC_PERIODIC, tau3=0.0, nz=0, lattice=None) -> lbm_params:
+                phi_ref=0.0, boundary=LBM_BC_PERIODIC, tau3=0.0, nz=0, lattice=None, round_seed=0) -> lbm_params:
     """nz >= 3 selects a 3D lattice (nx * ny * nz nodes): D3Q19 unless lattice says D3Q27 (19 or 27
-    are accepted for the LBM_LATTICE_* values); nz = 0 is D2Q9."""
+    are accepted for the LBM_LATTICE_* values); nz = 0 is D2Q9.  round_seed: seed of the rounding
+    stream of mode "f16sr"."""
     store, math = MODES[mode]
     if lattice is None:
         lattice = LBM_LATTICE_D3Q19 if nz else LBM_LATTICE_D2Q9
     else:
         lattice = {9: LBM_LATTICE_D2Q9, 19: LBM_LATTICE_D3Q19, 27: LBM_LATTICE_D3Q27}.get(int(lattice), int(lattice))
     return lbm_params(int(nx), int(ny), float(dx), float(dt), float(lam), float(D_const), store, math, int(aux),
-                      int(scale_log2), float(phi_ref), int(boundary), 0, float(tau3), lattice, int(nz))
+                      int(scale_log2), float(phi_ref), int(boundary), int(round_seed), float(tau3), lattice, int(nz))
 
 
 def lbm_abi_version() -> int:

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True, check=True).stdout
     exported = set(re.findall(r" T (lbm_\w+)$", out, flags=re.M))
     assert set(declared_functions()) <= exported
-    assert L.lbm_abi_version() == 8
+    assert L.lbm_abi_version() == 9
 
 
 def test_struct_layout_matches_header(tmp_path):

@@ -49,7 +49,7 @@ SHAPES = [(256, 16, 1, 0, 1), (128, 3, 0, 0, 0), (512, 1, 2, 0, 1), (256, 64, 3,
           (512, 256, 1, 0, 0)]
 
 
-@pytest.mark.parametrize("mode", ["f64", "f64s_f32m", "f32", "f16s"])
+@pytest.mark.parametrize("mode", ["f64", "f64s_f32m", "f32", "f16s", "f16sr"])
 @pytest.mark.parametrize("nx,ny", [(70, 45), (130, 67), (3, 3), (64, 5), (300, 7), (513, 130)])
 def test_fused_equals_single_steps(mode, nx, ny):
     for k, shape in enumerate(SHAPES[:3] if nx * ny < 1000 else SHAPES):
@@ -94,7 +94,8 @@ def test_fused_fp64_matches_the_oracle():
     two.close()
 
 
-@pytest.mark.parametrize("mode,n", [("f32", 2048), ("f16s", 2048), ("f64", 2048), ("f32", 8192), ("f16s", 8192)])
+@pytest.mark.parametrize("mode,n", [("f32", 2048), ("f16s", 2048), ("f64", 2048), ("f32", 8192), ("f16s", 8192),
+                                    ("f16sr", 8192)])
 def test_fused_full_size_equals_single_steps(mode, n):
     """The benchmark's lattice sizes in the fused default shape: four steps, bitwise."""
     cfg = W.PulseConfig(N=n, steps=4, D_variable=(n == 8192))

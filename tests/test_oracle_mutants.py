@@ -99,6 +99,31 @@ MUTANTS_PY = [
      "return float(np.asarray(phi_field, dtype=np.float64).ravel().sum())"),
 ]
 
+# Mistakes in the FP16 storage codes (oracle/rounding.py), checked against their own pins.
+PINS_SR = os.path.join(ROOT, "tests", "test_oracle_pins_sr.py")
+MUTANTS_SR = [
+    ("stochastic rounding comparison inclusive", "up = np.asarray(r, dtype=np.float64) < m",
+     "up = np.asarray(r, dtype=np.float64) <= m"),
+    ("rounding up for the large integers", "up = np.asarray(r, dtype=np.float64) < m",
+     "up = np.asarray(r, dtype=np.float64) >= 2 ** RBITS - m"),
+    ("finer bits rounded up", "m = np.floor((a - lo) / ulp * 2 ** RBITS)", "m = np.ceil((a - lo) / ulp * 2 ** RBITS)"),
+    ("twelve random bits per value", "RBITS = 13  #", "RBITS = 12  #"),
+    ("SplitMix64 increment", "GAMMA = 0x9E3779B97F4A7C15", "GAMMA = 0x9E3779B97F4A7C13"),
+    ("SplitMix64 first shift", "z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64",
+     "z = ((z ^ (z >> 31)) * 0xBF58476D1CE4E5B9) & MASK64"),
+    ("SplitMix64 array shift", "z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)",
+     "z = (z ^ (z >> np.uint64(28))) * np.uint64(0x94D049BB133111EB)"),
+    ("stream output counted from 1", "(k + np.uint64(1)) * np.uint64(GAMMA)", "k * np.uint64(GAMMA)"),
+    ("one output per node", "first = 2 * (level.astype(np.uint64)", "first = (level.astype(np.uint64)"),
+    ("straddling field halves swapped", "v = (lo >> np.uint64(b)) | (hi << np.uint64(64 - b))",
+     "v = (hi >> np.uint64(b - 64 + 13)) | (lo << np.uint64(64 - b))"),
+    ("nearest instead of lower neighbour", "h = np.where(h.astype(np.float64) > a, np.nextafter(h, np.float16(0)), h)",
+     "h = h"),
+    ("sign dropped", "return np.where(np.signbit(v), -out, out)", "return out"),
+    ("shift after scaling", "return ((g32 - w32) * np.float32(2.0 ** scale_log2)).astype(np.float32)",
+     "return (g32 * np.float32(2.0 ** scale_log2) - w32).astype(np.float32)"),
+]
+
 _PLUGIN = '''
 import importlib.util, os, sys
 spec = importlib.util.spec_from_file_location("oracle", os.environ["MUTANT_ORACLE"])
@@ -137,3 +162,8 @@ def test_3d_mutant_is_caught(name, old, new, tmp_path):
 @pytest.mark.parametrize("name,old,new", MUTANTS_PY, ids=[m[0] for m in MUTANTS_PY])
 def test_diagnostics_mutant_is_caught(name, old, new, tmp_path):
     _run_mutant(name, old, new, tmp_path, "__init__.py", PINS)
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS_SR, ids=[m[0] for m in MUTANTS_SR])
+def test_rounding_mutant_is_caught(name, old, new, tmp_path):
+    _run_mutant(name, old, new, tmp_path, "rounding.py", PINS_SR)
