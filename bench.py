@@ -139,6 +139,9 @@ def run_batched(torch, W, lbm, Solver, n_inst=256, steps=2000, eager_steps=100):
            "sizes": f"N log-uniform in [32, 512], seed 231210316 (min {min(d.N for d in draws)}, "
                     f"max {max(d.N for d in draws)})"}
     s.set_batch(lbm.LBM_BATCH_SERIAL)
+    # serial baselines: one launch per instance and step in the one-step shape of a batch (two steps per
+    # launch of a small lattice is a latency-bound walk of few blocks, far slower one instance at a time)
+    s.set_launch(1, 1, tile_width=64)
     s.step(2)
 
     def eager():
@@ -159,6 +162,13 @@ def run_batched(torch, W, lbm, Solver, n_inst=256, steps=2000, eager_steps=100):
                                  "tile_width": t["best"][3], "max_waves": t["best"][4], "stores": t["best"][5],
                                  "policy": ["serial", "flat", "strided", "lpt"][t["best"][6]], "blocks": t["best"][7],
                                  "fuse": t["best"][8]}}
+    # the tuner's best one-step and best two-step candidates (ms per step while tuning)
+    by_fuse = {}
+    for cand, t_ms in t["ms_per_step"].items():
+        fz = json.loads(cand)[8] if len(json.loads(cand)) > 8 else 1
+        by_fuse[fz] = min(by_fuse.get(fz, float("inf")), t_ms)
+    out["tuning"] = {f"best_{'two' if fz == 2 else 'one'}_step_launch": {"ms_per_step": v, "mlups": nodes / (v * 1e-3) / 1e6}
+                     for fz, v in sorted(by_fuse.items())}
     out["speedup_vs_serial_graph"] = out["serial_graph"]["ms_per_step"] / ms
     out["speedup_vs_serial_eager"] = out["serial_eager"]["ms_per_step"] / ms
     stats = [s.macros(k, ref=refs[k], raise_nonfinite=False) for k in range(n_inst)]
@@ -672,7 +682,8 @@ def oracle_cross_check(torch, W, lbm, Solver, phi_orc):
 
 
 KERNEL_MODES = {"0": "f64", "1": "f64s_f32m", "2": "f32", "3": "f16s", "4": "f16sr"}
-TRACE_STEPS = {2048: 200, 8192: 100}  # timed steps of the kernel-trace runs
+TRACE_STEPS = {2048: 1000, 8192: 100}  # timed steps of the kernel-trace runs
+PROFILE_STEPS = {"batched": 200, "adjoint": 400, "flux": 100}  # --steps of the profile workloads
 
 
 def _csv_rows(path):
@@ -708,8 +719,8 @@ def bytes_per_lup3(q: int, mode: str) -> int:
 
 
 def run_profile3(torch, W, lbm, Solver, n, steps):
-    """The workload the 3D profiles are taken on: the rotating pulse at n^3 on D3Q19 and D3Q27, FP32
-    and FP64 storage, `steps` steps each in the default launch shape, then the copy calibration."""
+    """The workload the 3D profiles are taken on: the rotating pulse at n^3 on D3Q19 and D3Q27, FP32,
+    FP64 and FP16S storage, `steps` steps each in the default launch shape, then the copy calibration."""
     import numpy as np
     cfg = W.PulseConfig(N=n, steps=steps)
     f = W.rotating_pulse3(cfg)
@@ -717,7 +728,7 @@ def run_profile3(torch, W, lbm, Solver, n, steps):
     fields = {"phi0": dv(f["phi0"]), "ux": dv(f["u"][0]), "uy": dv(f["u"][1]), "uz": dv(f["u"][2])}
     out = {}
     for q in (19, 27):
-        for mode in ("f32", "f64"):
+        for mode in ("f32", "f64", "f16s"):
             s = Solver([(lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, mode, nz=n, lattice=q), fields)])
             s.step(2)  # graph capture happens outside the timed steps
             ms = _timed_steps(torch, s, steps)
@@ -726,6 +737,125 @@ def run_profile3(torch, W, lbm, Solver, n, steps):
             print(f"# d3q{q} {mode}: {out[f'd3q{q}_{mode}']['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     out["copy_gbps"] = copy_bandwidth(torch, lbm)
     return out
+
+
+# Profiles of the other hot kernels: the batched step (256 instances), the adjoint (512^2 x 400 steps,
+# checkpointed) and the one-step flux form (2048^2 or 8192^2).  Each workload runs its kernels, then
+# the copy calibration; summarize_workload() reads one kernel-trace run and one FETCH_SIZE and one
+# WRITE_SIZE run of it.
+PROFILE_WORKLOADS = ("batched", "adjoint", "flux")
+
+
+def run_profile_workload(torch, W, lbm, Solver, name, n, steps):
+    import numpy as np
+    out = {"workload": name}
+    if name == "batched":
+        draws = W.batched_instances(256, steps=steps)
+        insts = []
+        for d in draws:
+            cfg = d.config
+            f = W.rotating_pulse(cfg)
+            p = lbm.make_params(cfg.N, cfg.N, f["dx"], f["dt"], cfg.lam, cfg.D, "f32")
+            insts.append((p, {k: torch.from_numpy(f[k]).cuda() for k in ("phi0", "ux", "uy")}))
+        s = Solver(insts)
+        s.step(64)
+        ms = _timed_steps(torch, s, steps)
+        nodes = int(sum(d.N * d.N for d in draws))
+        out.update(nodes=nodes, mlups=nodes / (ms * 1e-3) / 1e6, batch=s.get_batch(), launch=s.get_launch())
+        s.close()
+    elif name == "adjoint":
+        out.update(run_adjoint(torch, W, lbm, Solver))
+    elif name == "flux":
+        cfg = W.PulseConfig(N=n, steps=steps)
+        f = W.rotating_pulse(cfg)
+        dev = {k: torch.from_numpy(f[k]).cuda() for k in ("phi0", "ux", "uy")}
+        for mode in ("f32", "f64"):
+            s = Solver([(lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, mode, lbm.LBM_AUX_FLUX), dev)])
+            s.step(64)
+            ms = _timed_steps(torch, s, steps)
+            out[mode] = {"mlups": n * n / (ms * 1e-3) / 1e6, "launch": s.get_launch()}
+            s.close()
+        del dev
+        torch.cuda.empty_cache()
+    else:
+        raise ValueError(f"unknown profile workload {name}")
+    out["copy_gbps"] = copy_bandwidth(torch, lbm)
+    return out
+
+
+def _workload_kernels(name: str, n: int):
+    """(label, regex on the kernel name, algorithmic bytes per launch, lattice updates per launch) of
+    the kernels a profile workload is about."""
+    if name == "batched":
+        import workloads as W
+        nodes = sum(d.N * d.N for d in W.batched_instances(256))
+        return [("batched_step_kernel FP32, 256 instances", r"batched_step_kernel<2, 0, \d>", nodes * 80.0, nodes)]
+    if name == "adjoint":
+        import workloads as W
+        nodes = W.C5_N ** 2
+        # state 9 x 4 B and lam 9 x 4 B in, lam 9 x 4 B out, u 8 B and k 4 B in, dL/dD (FP64) read and written
+        return [("adjoint_kernel FP32 (D field, local aux)", r"adjoint_kernel<2, true, false, true>", nodes * 136.0, nodes),
+                ("step_kernel FP32, D field (recomputation, one step per launch)", r"step_kernel<2, 0, true, false, 0, false",
+                 nodes * 84.0, nodes),
+                ("step2_kernel FP32, D field (forward, two steps per launch)", r"step2_kernel<2, 0, true, false", nodes * 84.0,
+                 2 * nodes)]
+    if name == "flux":
+        return [("step_kernel FP32, flux form", r"step_kernel<2, 1, false, false", float(n) * n * 80.0, n * n),
+                ("step_kernel FP64, flux form", r"step_kernel<0, 1, false, false", float(n) * n * 160.0, n * n)]
+    raise ValueError(name)
+
+
+def summarize_workload(name, n, trace_dir, pmc_dirs, out_dir, command, pmc_commands):
+    """profiles/<name>_kernel_profile[_n].md: per kernel of the workload the trace's calls and average
+    duration, MLUPS and algorithmic GB/s from it, and the copy-calibrated FETCH_SIZE + WRITE_SIZE bytes
+    per launch against the algorithmic bytes."""
+    import re
+    kernels = _workload_kernels(name, n)
+    stats = _csv_rows(_find(trace_dir, "kernel_stats.csv"))
+    per, calib = {}, {}
+    for counter, d in pmc_dirs.items():
+        vals, cal = {}, []
+        for r in _csv_rows(_find(d, "counter_collection.csv")):
+            if r.get("Counter_Name") != counter:
+                continue
+            kn = r.get("Kernel_Name", "")
+            if "copy_kernel" in kn and "cached" not in kn:
+                cal.append(float(r["Counter_Value"]))
+            for lab, rx, _, _ in kernels:
+                if re.search(rx, kn):
+                    vals.setdefault(lab, []).append(float(r["Counter_Value"]))
+        if cal:
+            calib[counter] = sorted(cal)[len(cal) // 2] / (2 * 1024 * 1024)  # copy moves 2 GiB each way
+        for lab, v in vals.items():
+            v = sorted(v)
+            per.setdefault(lab, {})[counter] = v[len(v) // 2]
+    size = f" at {n}^2" if name == "flux" else ""
+    md = [f"# rocprofv3 profile: {name} workload{size}", "",
+          f"Kernel sources hash: {kernel_hash()}.", "", f"- trace: `{command}`"] + [f"- counters: `{c}`" for c in pmc_commands] + [
+          "", "FETCH_SIZE and WRITE_SIZE (KiB per dispatch, median) are divided by what they read for the library's "
+              "2 GiB copy kernel in the same run.", "",
+          "| kernel | calls | average (us) | MLUPS | algorithmic GB/s | of 8 TB/s | FETCH KiB | WRITE KiB | "
+          "counted bytes/launch | algorithmic bytes/launch | ratio |", "|---|---|---|---|---|---|---|---|---|---|---|"]
+    for lab, rx, alg, lups in kernels:
+        rows = [r for r in stats if re.search(rx, r["Name"])]
+        if not rows:
+            continue
+        calls = sum(int(r["Calls"]) for r in rows)
+        total = sum(float(r["TotalDurationNs"]) for r in rows)
+        avg = total / calls
+        gbps = alg / (avg * 1e-9) / 1e9
+        c = per.get(lab, {})
+        fetch, write = c.get("FETCH_SIZE"), c.get("WRITE_SIZE")
+        if fetch is not None and write is not None and "FETCH_SIZE" in calib and "WRITE_SIZE" in calib:
+            hbm = 1024.0 * (fetch / calib["FETCH_SIZE"] + write / calib["WRITE_SIZE"])
+            cnt = f"{fetch:.0f} | {write:.0f} | {hbm:.4g} | {alg:.4g} | {hbm / alg:.3f}"
+        else:
+            cnt = f" | | | {alg:.4g} | "
+        md.append(f"| {lab} | {calls} | {avg / 1e3:.2f} | {lups / (avg * 1e-9) / 1e6:.0f} | {gbps:.0f} | "
+                  f"{gbps / HBM_PEAK_GBPS:.3f} | {cnt} |")
+    fn = f"{name}_kernel_profile" + (f"_{n}" if name == "flux" else "") + ".md"
+    with open(os.path.join(out_dir, fn), "w") as fh:
+        fh.write("\n".join(md) + "\n")
 
 
 def summarize_profiles3(trace_dir, pmc_dirs, out_dir, n, command, pmc_commands):
@@ -907,6 +1037,8 @@ def main():
                     help="write profiles/ summaries from rocprofv3 output under RUNDIR (no GPU needed)")
     ap.add_argument("--profile3d", type=int, metavar="N", default=0,
                     help="run only the D3Q19/D3Q27 profile workload at N^3 (--steps steps per kernel)")
+    ap.add_argument("--profile", choices=PROFILE_WORKLOADS,
+                    help="run only one profile workload (batched, adjoint, or the flux form at --n), --steps steps")
     args = ap.parse_args()
     if args.summarize:
         d = args.summarize
@@ -921,6 +1053,21 @@ def main():
                                 f"python3 bench.py --profile3d {n3} --steps 100",
                                 [f"rocprofv3 --pmc {c} --output-format csv -d RUNDIR/pmc3_{c.lower()}{sfx} -o pmc -- "
                                  f"python3 bench.py --profile3d {n3} --steps 8" for c in sorted(pmc3)])
+        for name in PROFILE_WORKLOADS:
+            for n in ((2048, 8192) if name == "flux" else (0,)):
+                sfx = f"{name}_{n}" if n else name
+                tdir = os.path.join(d, f"trace_{sfx}")
+                if not os.path.isdir(tdir):
+                    continue
+                steps = PROFILE_STEPS[name]
+                nflag = f" --n {n}" if n else ""
+                pmcw = {c: os.path.join(d, f"pmc_{c.lower()}_{sfx}") for c in ("FETCH_SIZE", "WRITE_SIZE")}
+                pmcw = {k: v for k, v in pmcw.items() if os.path.isdir(v)}
+                summarize_workload(name, n, tdir, pmcw, os.path.join(ROOT, "profiles"),
+                                   f"rocprofv3 --kernel-trace --stats --output-format csv -d RUNDIR/trace_{sfx} -o trace -- "
+                                   f"python3 bench.py --profile {name}{nflag} --steps {steps}",
+                                   [f"rocprofv3 --pmc {c} --output-format csv -d RUNDIR/pmc_{c.lower()}_{sfx} -o pmc -- "
+                                    f"python3 bench.py --profile {name}{nflag} --steps {steps}" for c in sorted(pmcw)])
         traces = {n: os.path.join(d, f"trace_{n}") for n in (2048, 8192)}
         traces = {n: v for n, v in traces.items() if os.path.isdir(v)}
         pmc = {(c, n): os.path.join(d, f"pmc_{c.lower()}_{n}") for c in ("FETCH_SIZE", "WRITE_SIZE") for n in (2048, 8192)}
@@ -929,10 +1076,10 @@ def main():
             return
         summarize_profiles(traces, pmc, os.path.join(ROOT, "profiles"),
                            {n: f"rocprofv3 --kernel-trace --stats --output-format csv -d RUNDIR/trace_{n} -o trace -- "
-                               f"python3 bench.py --n {n} --steps {TRACE_STEPS[n]} --warmup 10 --modes f32,f64,f16s "
+                               f"python3 bench.py --n {n} --steps {TRACE_STEPS[n]} --warmup 10 --modes f32,f64,f16s,f16sr "
                                f"--no-cpu --no-batched --no-studies" for n in traces},
                            [f"rocprofv3 --pmc {c} --output-format csv -d RUNDIR/pmc_{c.lower()}_{n} -o pmc -- "
-                            f"python3 bench.py --n {n} --steps 12 --warmup 0 --modes f32,f64,f16s --no-cpu --no-batched --no-studies"
+                            f"python3 bench.py --n {n} --steps 12 --warmup 0 --modes f32,f64,f16s,f16sr --no-cpu --no-batched --no-studies"
                             for (c, n) in sorted(pmc)])
         return
     if args.gpus != 1:
@@ -951,6 +1098,9 @@ def main():
     lbm.lib()  # the HIP library is required
     if args.profile3d:
         print(json.dumps(run_profile3(torch, W, lbm, Solver, args.profile3d, args.steps)))
+        return
+    if args.profile:
+        print(json.dumps(run_profile_workload(torch, W, lbm, Solver, args.profile, args.n, args.steps), default=str))
         return
 
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]

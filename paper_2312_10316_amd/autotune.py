@@ -28,13 +28,23 @@ def _key(solver) -> str:
     dev = torch.cuda.get_device_name()
     shapes = [(p.nx, p.ny, p.nz, p.lattice, p.store, p.math, p.aux, p.boundary, p.tau3 not in (0.0, 1.0))
               for p in solver.params]
-    return hashlib.sha256(json.dumps(["launch-v5", dev, shapes]).encode()).hexdigest()[:20]
+    return hashlib.sha256(json.dumps(["launch-v6", dev, shapes]).encode()).hexdigest()[:20]
+
+
+def _fusable_params(p) -> bool:
+    return (p.lattice == L.LBM_LATTICE_D2Q9 and p.boundary == L.LBM_BC_PERIODIC and p.aux != L.LBM_AUX_FLUX
+            and p.tau3 in (0.0, 1.0))
 
 
 def _fusable(solver) -> bool:
-    p = solver.params[0]
-    return (len(solver.params) == 1 and p.lattice == L.LBM_LATTICE_D2Q9 and p.boundary == L.LBM_BC_PERIODIC
-            and p.aux != L.LBM_AUX_FLUX and p.tau3 in (0.0, 1.0))
+    return len(solver.params) == 1 and _fusable_params(solver.params[0])
+
+
+def _fusable_batch(solver) -> bool:
+    """A uniform batch (one storage and aux form, periodic D2Q9 TRT-R) can run two steps per launch."""
+    ps = solver.params
+    return (len(ps) > 1 and all(_fusable_params(p) for p in ps)
+            and len({(p.store, p.math, p.aux) for p in ps}) == 1)
 
 
 def default_candidates(solver) -> list:
@@ -42,7 +52,8 @@ def default_candidates(solver) -> list:
     for this context.  Stores: both kinds for one instance where they are honoured (not in the local
     form's walking loop); a batch keeps the context's default.  A single periodic D2Q9 TRT-R instance
     with the local or no aux term also tries one buffer in place (one-row launches) and two steps per
-    launch (fuse 2: tile width and height, row bands or hardware order, both store kinds)."""
+    launch (fuse 2: tile width and height, row bands or hardware order, both store kinds); a uniform
+    batch of such instances tries two steps per launch too (tile width and height, flat or LPT)."""
     out = []
     st0 = solver.get_launch(0)["stores"]
     p0 = solver.params[0]
@@ -74,6 +85,11 @@ def default_candidates(solver) -> list:
                             out.append((rows, remap, h, width, cap, stores, L.LBM_BATCH_SERIAL, 0, 1))
         return out
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    if _fusable_batch(solver):  # two steps per launch, one batched launch (non-temporal stores)
+        for width in (128, 256):
+            for rows in (8, 16, 32):
+                out.append((rows, 1, 0, width, 0, 0, L.LBM_BATCH_FLAT, 0, 2))
+                out.append((rows, 1, 0, width, 0, 0, L.LBM_BATCH_LPT, 4 * ncu, 2))
     for width in (64, 256):
         for rows in (1, 2, 4):
             out.append((rows, 1, 0, width, 0, st0, L.LBM_BATCH_SERIAL, 0, 1))
@@ -139,8 +155,10 @@ def tune(solver, candidates: Optional[Iterable] = None, steps: int = 64, reps: i
             _apply(solver, cand)
             times[json.dumps(list(cand))] = _time(solver, steps, reps)
     finally:
-        for k in range(n):
-            o = old_launch[k]
+        # a fused batch is configured as a whole (inst -1); anything else instance by instance
+        whole = n > 1 and old_launch[0]["fuse"] == 2
+        for k in ([-1] if whole else range(n)):
+            o = old_launch[max(k, 0)]
             solver.set_launch(o["rows"], o["xcd_remap"], inst=k, tile_width=o["tile_width"], max_waves=o["max_waves"],
                               xcd_rows=o["xcd_rows"], stores=o["stores"], fuse=o["fuse"])
         if old_batch is not None:

@@ -159,12 +159,14 @@ Launch default_launch(const lbm_params &p, int mode, bool has_D, int n_inst, int
 // tiles of 16 rows (2048^2: FP32 122k, FP16 167k MLUPS), FP64 storage 256 x 32; wider lattices take
 // FP32 256 x 16 (8192^2: 135k), FP16 128 x 32 (171k) and FP64 storage 128 x 16 (64k).  Tiles never
 // wider than the lattice needs (at least 128 columns), and at least 256 tiles where the lattice allows
-// (down to 4 rows).  Row bands over the XCDs, so that the frame rows a tile shares with the next tile
+// (down to 4 rows, then down to 128 columns: a 512^2 lattice in 512 x 4 tiles kept half the CUs idle).  Row bands over the XCDs, so that the frame rows a tile shares with the next tile
 // down sit in the same L2.  (MRT-R stays on single steps: with FP64 math the compiler had fused its
 // third-order multiply-adds otherwise in the fused kernel.)
-bool fusable(const lbm_params &p, int n_inst)
+// An instance whose steps can be fused (a periodic D2Q9 TRT-R instance, local or no aux term).  A
+// context fuses its one instance, or every instance of a uniform batch at once.
+bool fusable(const lbm_params &p)
 {
-    return n_inst == 1 && p.lattice == LBM_LATTICE_D2Q9 && p.boundary == LBM_BC_PERIODIC && p.aux != LBM_AUX_FLUX &&
+    return p.lattice == LBM_LATTICE_D2Q9 && p.boundary == LBM_BC_PERIODIC && p.aux != LBM_AUX_FLUX &&
            (p.tau3 == 0.0 || p.tau3 == 1.0);
 }
 Launch fused_default(const lbm_params &p, int mode)
@@ -186,6 +188,7 @@ Launch fused_default(const lbm_params &p, int mode)
     while (width > 128 && width / 2 >= p.nx) width /= 2;
     auto tiles = [&](int h) { return (int64_t)((p.nx + width - 1) / width) * ((p.ny + h - 1) / h); };
     while (rows > 4 && tiles(rows) < 256) rows /= 2;
+    while (width > 128 && tiles(rows) < 256) width /= 2;  // small lattices: narrower tiles fill the CUs
     lc.fuse_width = width;
     lc.rows = rows;
     lc.xcd_remap = 1;
@@ -306,6 +309,13 @@ size_t max_items_of(int32_t n_inst, const lbm_params *p)
     }
     return items;
 }
+// Two steps per launch: tiles of at least 128 columns and one row.
+size_t max_items2_of(int32_t n_inst, const lbm_params *p)
+{
+    size_t items = 0;
+    for (int k = 0; k < n_inst; ++k) items += (size_t)((p[k].nx + 127) / 128) * (size_t)p[k].ny;
+    return items;
+}
 
 // Shared scratch: macro partials, the macro result, two flag words; then the batch tables
 // (instance descriptors, work items, block ranges).
@@ -314,9 +324,10 @@ constexpr size_t kScratchBytes = kPartialBytes + 256 + 256;
 
 size_t tables_bytes(int32_t n_inst, const lbm_params *p)
 {
-    const size_t items = max_items_of(n_inst, p);
-    return align_up((size_t)n_inst * sizeof(InstDesc), kAlign) + align_up(items * sizeof(WorkItem), kAlign) +
-           align_up((items + 1) * sizeof(int32_t), kAlign) + align_up((size_t)n_inst * 2 * sizeof(int64_t), kAlign);
+    size_t b = align_up((size_t)n_inst * sizeof(InstDesc), kAlign) + align_up((size_t)n_inst * 2 * sizeof(int64_t), kAlign);
+    for (size_t items : {max_items_of(n_inst, p), n_inst > 1 ? max_items2_of(n_inst, p) : (size_t)0})
+        b += align_up(items * sizeof(WorkItem), kAlign) + align_up((items + 1) * sizeof(int32_t), kAlign);
+    return b;
 }
 
 // Constant-D relaxation: tau1 - 1/2 = kappa / (cs^2 dt) = 3 kappa dt / dx^2 (Sec. 2.4), and
@@ -330,6 +341,9 @@ void const_relax(const lbm_params &p, double &w1, double &w2, double &beta)
     beta = 1.0 - 0.5 / tau1;
 }
 
+// The launch of a single step: the configured one, or the one kept beside a fused configuration.
+const Launch &one_step(const Instance &in) { return in.lc.fuse == 2 ? in.lc1 : in.lc; }
+
 InstDesc desc_of(const Instance &in)
 {
     InstDesc d{};
@@ -339,7 +353,8 @@ InstDesc desc_of(const Instance &in)
     d.k = in.k;
     d.s = in.s;
     d.L = in.L;
-    d.lc = in.lc;
+    d.lc = one_step(in);
+    if (in.lc.fuse == 2) d.lcf = in.lc;
     d.has_k = in.has_D ? 1 : 0;
     d.has_s = in.has_src ? 1 : 0;
     d.bc = in.bc;
@@ -370,19 +385,24 @@ constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 double *g_scratch_ptr[kMaxDevices] = {};
 
+// Work list of a batched launch: (instance, tile) items, either one per block (flat) or in ranges.
+struct Schedule {
+    WorkItem *d_items = nullptr;      // device (in the workspace)
+    int32_t *d_block_start = nullptr;
+    int nblocks = 0;                  // grid of the launch
+    bool use_block_start = false;
+    std::vector<WorkItem> h_items;    // host staging
+    std::vector<int32_t> h_block_start;
+};
+
 struct lbm_ctx {
     std::vector<Instance> inst;
     int parity = 0;                   // the buffer every instance currently reads (they step together)
     bool uniform = false;             // all instances share mode and aux (a batched launch is possible)
     lbm_batch batch = {LBM_BATCH_SERIAL, 0, 0};
     InstDesc *d_desc = nullptr;       // device tables (in the workspace)
-    WorkItem *d_items = nullptr;
-    int32_t *d_block_start = nullptr;
-    int nblocks = 0;                  // grid of the batched launch
-    bool use_block_start = false;
-    std::vector<InstDesc> h_desc;     // host staging of the tables
-    std::vector<WorkItem> h_items;
-    std::vector<int32_t> h_block_start;
+    std::vector<InstDesc> h_desc;     // host staging of the descriptors
+    Schedule sched[2];                // batched work lists: one step per launch, two steps per launch
     hipStream_t stream = nullptr;
     hipStream_t capture = nullptr;    // private stream used only to record graphs
     int lds_per_cu = 0;               // LDS bytes per CU of the device (for the wave cap)
@@ -409,6 +429,88 @@ void drop_graphs(lbm_ctx *c)
 
 bool batched(const lbm_ctx *c) { return c->inst.size() > 1 && c->uniform && c->batch.policy != LBM_BATCH_SERIAL; }
 
+// A context whose instances all run two steps per launch (one instance, or a whole uniform batch).
+bool fused(const lbm_ctx *c)
+{
+    for (const Instance &in : c->inst)
+        if (in.lc.fuse != 2) return false;
+    return !c->inst.empty();
+}
+
+// Builds and uploads the work list of the batched one-step launch (two = false) or of the batched
+// two-step launch (two = true): items in instance order, costed by the live nodes of their tile, then
+// one per block (flat), dealt round-robin (strided) or longest first to the least-loaded block (LPT).
+int build_schedule(lbm_ctx *c, bool two)
+{
+    Schedule &sc = c->sched[two ? 1 : 0];
+    const int n = (int)c->inst.size();
+    std::vector<WorkItem> items;
+    std::vector<int64_t> cost;
+    for (int k = 0; k < n; ++k) {
+        const Layout &L = c->inst[k].L;
+        const Launch &lc = two ? c->inst[k].lc : one_step(c->inst[k]);
+        if (two) {
+            const int W = lc.fuse_width, H = lc.rows, ntx = (L.nx + W - 1) / W, nt = ntx * ((L.ny + H - 1) / H);
+            for (int t = 0; t < nt; ++t) {
+                const int x0 = (t % ntx) * W, y0 = (t / ntx) * H;
+                items.push_back(WorkItem{k, t});
+                cost.push_back((int64_t)std::min(W, L.nx - x0) * std::min(H, L.ny - y0));
+            }
+        } else {
+            const int nt = tiles_of(L, lc.rows, lc.wide);
+            const int tw = lc.wide ? 256 : 64, th = lc.wide ? lc.rows : 4 * lc.rows;  // tile extent
+            for (int t = 0; t < nt; ++t) {
+                int x0, y0;
+                tile_origin(L, lc, t, 0, x0, y0);
+                items.push_back(WorkItem{k, t});
+                cost.push_back((int64_t)std::min(tw, L.nx - x0) * std::min(th, L.ny - y0));
+            }
+        }
+    }
+    const int ni = (int)items.size();
+    const lbm_batch &b = c->batch;
+    if (b.policy == LBM_BATCH_FLAT) {
+        sc.h_items = items;
+        sc.use_block_start = false;
+        sc.nblocks = ni;
+    } else {
+        const int P = std::min(b.blocks, ni);
+        std::vector<std::vector<int>> per(P);
+        if (b.policy == LBM_BATCH_STRIDED) {
+            for (int i = 0; i < ni; ++i) per[i % P].push_back(i);
+        } else {  // LPT: longest tile first, to the least-loaded block
+            std::vector<int> order(ni);
+            for (int i = 0; i < ni; ++i) order[i] = i;
+            std::stable_sort(order.begin(), order.end(), [&](int a, int z) { return cost[a] > cost[z]; });
+            using Load = std::pair<int64_t, int>;
+            std::priority_queue<Load, std::vector<Load>, std::greater<Load>> pq;
+            for (int j = 0; j < P; ++j) pq.push({0, j});
+            for (int i : order) {
+                Load l = pq.top();
+                pq.pop();
+                per[l.second].push_back(i);
+                pq.push({l.first + cost[i], l.second});
+            }
+            for (auto &v : per) std::sort(v.begin(), v.end());  // each block walks its tiles in memory order
+        }
+        sc.h_items.clear();
+        sc.h_block_start.assign(P + 1, 0);
+        for (int j = 0; j < P; ++j) {
+            sc.h_block_start[j] = (int32_t)sc.h_items.size();
+            for (int i : per[j]) sc.h_items.push_back(items[i]);
+        }
+        sc.h_block_start[P] = (int32_t)sc.h_items.size();
+        sc.use_block_start = true;
+        sc.nblocks = P;
+        hipError_t e = hipMemcpyAsync(sc.d_block_start, sc.h_block_start.data(), (P + 1) * sizeof(int32_t),
+                                      hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "uploading block ranges");
+    }
+    hipError_t e = hipMemcpyAsync(sc.d_items, sc.h_items.data(), sc.h_items.size() * sizeof(WorkItem),
+                                  hipMemcpyHostToDevice, c->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "uploading work items");
+}
+
 // Rebuilds the descriptors and (for a batched policy) the work list, and uploads them.  The host
 // staging vectors are only rewritten after the stream has drained.
 int refresh_tables(lbm_ctx *c)
@@ -422,63 +524,9 @@ int refresh_tables(lbm_ctx *c)
     e = hipMemcpyAsync(c->d_desc, c->h_desc.data(), n * sizeof(InstDesc), hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(e, "uploading instance descriptors");
     if (batched(c)) {
-        // work items in instance order; cost = live nodes of the tile
-        std::vector<WorkItem> items;
-        std::vector<int64_t> cost;
-        for (int k = 0; k < n; ++k) {
-            const Layout &L = c->inst[k].L;
-            const Launch &lc = c->inst[k].lc;
-            const int nt = tiles_of(L, lc.rows, lc.wide);
-            const int tw = lc.wide ? 256 : 64, th = lc.wide ? lc.rows : 4 * lc.rows;  // tile extent
-            for (int t = 0; t < nt; ++t) {
-                int x0, y0;
-                tile_origin(L, lc, t, 0, x0, y0);
-                items.push_back(WorkItem{k, t});
-                cost.push_back((int64_t)std::min(tw, L.nx - x0) * std::min(th, L.ny - y0));
-            }
-        }
-        const int ni = (int)items.size();
-        const lbm_batch &b = c->batch;
-        if (b.policy == LBM_BATCH_FLAT) {
-            c->h_items = items;
-            c->use_block_start = false;
-            c->nblocks = ni;
-        } else {
-            const int P = std::min(b.blocks, ni);
-            std::vector<std::vector<int>> per(P);
-            if (b.policy == LBM_BATCH_STRIDED) {
-                for (int i = 0; i < ni; ++i) per[i % P].push_back(i);
-            } else {  // LPT: longest tile first, to the least-loaded block
-                std::vector<int> order(ni);
-                for (int i = 0; i < ni; ++i) order[i] = i;
-                std::stable_sort(order.begin(), order.end(), [&](int a, int z) { return cost[a] > cost[z]; });
-                using Load = std::pair<int64_t, int>;
-                std::priority_queue<Load, std::vector<Load>, std::greater<Load>> pq;
-                for (int j = 0; j < P; ++j) pq.push({0, j});
-                for (int i : order) {
-                    Load l = pq.top();
-                    pq.pop();
-                    per[l.second].push_back(i);
-                    pq.push({l.first + cost[i], l.second});
-                }
-                for (auto &v : per) std::sort(v.begin(), v.end());  // each block walks its tiles in memory order
-            }
-            c->h_items.clear();
-            c->h_block_start.assign(P + 1, 0);
-            for (int j = 0; j < P; ++j) {
-                c->h_block_start[j] = (int32_t)c->h_items.size();
-                for (int i : per[j]) c->h_items.push_back(items[i]);
-            }
-            c->h_block_start[P] = (int32_t)c->h_items.size();
-            c->use_block_start = true;
-            c->nblocks = P;
-            e = hipMemcpyAsync(c->d_block_start, c->h_block_start.data(), (P + 1) * sizeof(int32_t),
-                               hipMemcpyHostToDevice, c->stream);
-            if (e != hipSuccess) return hip_fail(e, "uploading block ranges");
-        }
-        e = hipMemcpyAsync(c->d_items, c->h_items.data(), c->h_items.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
-                           c->stream);
-        if (e != hipSuccess) return hip_fail(e, "uploading work items");
+        int rc = build_schedule(c, false);
+        if (rc == LBM_OK && fused(c)) rc = build_schedule(c, true);
+        if (rc) return rc;
     }
     e = hipStreamSynchronize(c->stream);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "synchronizing after a table update");
@@ -528,21 +576,21 @@ int sync_clock(lbm_ctx *c, Instance &in)
 int enqueue_step(lbm_ctx *c, hipStream_t st)
 {
     if (batched(c)) {
+        const Schedule &sc = c->sched[0];
         BatchArgs a;
         a.inst = c->d_desc;
-        a.items = c->d_items;
-        a.block_start = c->use_block_start ? c->d_block_start : nullptr;
+        a.items = sc.d_items;
+        a.block_start = sc.use_block_start ? sc.d_block_start : nullptr;
         a.parity = c->parity;
         a.one_row = 1;
-        for (const Instance &in : c->inst) a.one_row &= in.lc.rows == 1 ? 1 : 0;
-        hipError_t e = launch_batched_step(c->inst[0].mode, c->inst[0].p.aux, a, c->nblocks,
+        for (const Instance &in : c->inst) a.one_row &= one_step(in).rows == 1 ? 1 : 0;
+        hipError_t e = launch_batched_step(c->inst[0].mode, c->inst[0].p.aux, a, sc.nblocks,
                                            lds_reserve_for(c->batch.max_waves, c->lds_per_cu), st);
         if (e != hipSuccess) return hip_fail(e, "batched step kernel launch");
     } else {
         for (size_t k = 0; k < c->inst.size(); ++k) {
             StepArgs a;
-            a.d = c->h_desc[k];
-            if (a.d.lc.fuse == 2) a.d.lc = c->inst[k].lc1;  // a single step of a fused context
+            a.d = c->h_desc[k];  // its lc is the one-step launch, also in a fused context
             a.parity = c->parity;
             hipError_t e = is3d(c->inst[k]) ? launch_step3(c->inst[k].mode, c->inst[k].p.aux, a, st)
                                              : launch_step(c->inst[k].mode, c->inst[k].p.aux, a, st);
@@ -553,17 +601,28 @@ int enqueue_step(lbm_ctx *c, hipStream_t st)
     return LBM_OK;
 }
 
-// A context whose one instance runs two steps per launch.
-bool fused(const lbm_ctx *c) { return c->inst.size() == 1 && c->inst[0].lc.fuse == 2; }
-
-// Enqueues two steps in one launch (fused contexts).
+// Enqueues two steps of every instance (fused contexts): one launch for a batch, else one per instance.
 int enqueue_fused(lbm_ctx *c, hipStream_t st)
 {
-    StepArgs a;
-    a.d = c->h_desc[0];
-    a.parity = c->parity;
-    hipError_t e = launch_step2(c->inst[0].mode, c->inst[0].p.aux, a, st);
-    if (e != hipSuccess) return hip_fail(e, "fused step kernel launch");
+    if (batched(c)) {
+        const Schedule &sc = c->sched[1];
+        BatchArgs a;
+        a.inst = c->d_desc;
+        a.items = sc.d_items;
+        a.block_start = sc.use_block_start ? sc.d_block_start : nullptr;
+        a.parity = c->parity;
+        a.one_row = 0;
+        hipError_t e = launch_batched_step2(c->inst[0].mode, c->inst[0].p.aux, a, sc.nblocks, c->inst[0].lc.fuse_width, st);
+        if (e != hipSuccess) return hip_fail(e, "batched fused step kernel launch");
+    } else {
+        for (size_t k = 0; k < c->inst.size(); ++k) {
+            StepArgs a;
+            a.d = c->h_desc[k];
+            a.parity = c->parity;
+            hipError_t e = launch_step2(c->inst[k].mode, c->inst[k].p.aux, a, st);
+            if (e != hipSuccess) return hip_fail(e, "fused step kernel launch");
+        }
+    }
     c->parity ^= 1;
     return LBM_OK;
 }
@@ -706,7 +765,7 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
         in.mode = mode_of(p[k]);
         in.L = layout_of(p[k]);
         in.lc1 = default_launch(in.p, in.mode, f[k].D != nullptr, n_inst, c->lds_per_cu);
-        in.lc = fusable(in.p, n_inst) ? fused_default(in.p, in.mode) : in.lc1;
+        in.lc = n_inst == 1 && fusable(in.p) ? fused_default(in.p, in.mode) : in.lc1;
         const size_t pb = pops_bytes(p[k]), vb = vel_bytes(p[k]), fb = field_bytes(p[k]);
         in.buf[0] = w;
         in.buf[1] = w + pb;
@@ -730,6 +789,19 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
             (in.p.tau3 != 0.0 && in.p.tau3 != 1.0) || in.p.lattice != LBM_LATTICE_D2Q9)
             c->uniform = false;  // batched launches cover periodic D2Q9 TRT-R instances of one storage/aux form
     }
+    // A uniform batch of instances that can be fused runs two steps per launch, in one batched launch of
+    // 128 x 16 tiles (the 256-instance C4 batch, N = 32..508, FP32: 99k MLUPS against 67k for the
+    // best one-step schedule; 256-column tiles and 8 or 32 rows, flat or LPT, measured slower).
+    bool batch_fuses = n_inst > 1 && c->uniform;
+    for (const Instance &in : c->inst) batch_fuses &= fusable(in.p);
+    if (batch_fuses)
+        for (Instance &in : c->inst) {
+            in.lc = Launch{};
+            in.lc.rows = 16;
+            in.lc.xcd_remap = 1;
+            in.lc.fuse = 2;
+            in.lc.fuse_width = 128;
+        }
     // Cached stores (honoured by every one-instance launch but the local form's walking loop) when what
     // the steps touch (both population buffers and the per-node fields of every instance, padding
     // columns excluded) fits in the 256 MiB Infinity Cache: the next step then reads the new state back
@@ -769,10 +841,13 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
     const size_t items = max_items_of(n_inst, p);
     c->d_desc = reinterpret_cast<InstDesc *>(w);
     w += align_up((size_t)n_inst * sizeof(InstDesc), kAlign);
-    c->d_items = reinterpret_cast<WorkItem *>(w);
-    w += align_up(items * sizeof(WorkItem), kAlign);
-    c->d_block_start = reinterpret_cast<int32_t *>(w);
-    w += align_up((items + 1) * sizeof(int32_t), kAlign);
+    for (int j = 0; j < 2; ++j) {
+        const size_t ni = j == 0 ? items : (n_inst > 1 ? max_items2_of(n_inst, p) : 0);
+        c->sched[j].d_items = reinterpret_cast<WorkItem *>(w);
+        w += align_up(ni * sizeof(WorkItem), kAlign);
+        c->sched[j].d_block_start = reinterpret_cast<int32_t *>(w);
+        w += align_up((ni + 1) * sizeof(int32_t), kAlign);
+    }
     for (int k = 0; k < n_inst; ++k) c->inst[k].clock = reinterpret_cast<int64_t *>(w) + 2 * k;  // zeroed below
     // a uniform batch defaults to one flat launch; FP32 runs it with at most 6 waves per SIMD (+2 %)
     if (n_inst > 1 && c->uniform) c->batch = lbm_batch{LBM_BATCH_FLAT, 0, c->inst[0].mode == MODE_F32_F32 ? 6 : 0};
@@ -1048,9 +1123,9 @@ int lbm_set_launch(lbm_ctx *c, int32_t inst, const lbm_launch *cfg)
                                    "instance: D2Q9 with the local or no auxiliary term, or D3Q19/D3Q27 without FP64 math");
         if (want_one && (cfg->rows != 1 || two))
             return fail(LBM_E_ARG, "lbm_set_launch: stores=2 (one buffer in place) needs rows=1 and fuse 0 or 1");
-        if (two && !fusable(in.p, (int)c->inst.size()))
-            return fail(LBM_E_ARG, "lbm_set_launch: fuse=2 needs a context of one periodic D2Q9 TRT-R instance with "
-                                   "the local or no auxiliary term");
+        if (two && (!fusable(in.p) || (c->inst.size() > 1 && (!c->uniform || inst != -1))))
+            return fail(LBM_E_ARG, "lbm_set_launch: fuse=2 needs periodic D2Q9 TRT-R instances with the local or no "
+                                   "auxiliary term: one instance, or every instance of a uniform batch at once (inst -1)");
     }
     if (two ? (cfg->tile_width != 128 && cfg->tile_width != 256 && cfg->tile_width != 512)
             : (cfg->tile_width != 64 && cfg->tile_width != 256))
@@ -1228,8 +1303,7 @@ int lbm_adjoint_segment(lbm_ctx *c, int32_t inst, void *states, int32_t nsteps, 
     // context's own store kind (state images are always in the two-buffer layout).
     StepArgs a;
     a.d = c->h_desc[inst];
-    if (a.d.lc.fuse == 2) a.d.lc = in.lc1;
-    if (a.d.lc.stores == 2) a.d.lc.stores = 1;
+    if (a.d.lc.stores == 2) a.d.lc.stores = 1;  // its lc is the one-step launch
     a.parity = 0;
     for (int32_t j = 0; j + 1 < nsteps; ++j) {
         a.d.buf[0] = img + (size_t)j * sb;

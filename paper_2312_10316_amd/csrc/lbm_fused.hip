@@ -38,23 +38,25 @@ constexpr int step2_waves(int mode, int nw)
 // LDS ring of FP64 storage lets 160 KB hold (2 to 4): FP32 and FP16 storage then fit 41-49 VGPRs,
 // against 65-83 by default.
 // The walk is bound by the loads each wave keeps in flight, so resident waves count more than registers.
+// The LDS ring of a block: four rows of the six x-moving intermediate populations, W + 2 columns.
+template <int MODE, int NW>
+using Ring = typename ModeTraits<MODE>::St::T[4][6][64 * NW + 2];
+
+// Two steps of tile t of one instance (tiles numbered row-major, ceil(nx / W) per row, d.lcf.rows high),
+// reading buf[parity] and writing buf[parity ^ 1]; called by every thread of the block.
 template <int MODE, int AUX, bool HAS_K, bool HAS_S, bool MRT, int NW, bool CST>
-__global__ __launch_bounds__(64 * (NW + 1))
-__attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW)))) void step2_kernel(const StepArgs a)
+__device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t, Ring<MODE, NW> &ring)
 {
     using St = typename ModeTraits<MODE>::St;
     using M = typename ModeTraits<MODE>::M;
     using T = typename St::T;
     using C = Codec<St, M>;
     constexpr int W = 64 * NW, WC = W + 2;
-    __shared__ T ring[4][6][WC];
 
-    const InstDesc &d = a.d;
     const int nx = d.L.nx, ny = d.L.ny;
     const int64_t pitch = d.L.pitch;
-    const int H = d.lc.rows;
+    const int H = d.lcf.rows;
     const int ntx = (nx + W - 1) / W;
-    const int t = tile_of_block(blockIdx.x, gridDim.x, d.lc.xcd_remap, ntx, d.lc.xcd_rows);
     const int x0 = (t % ntx) * W, y0 = (t / ntx) * H;
     const int y1 = min(y0 + H, ny);  // output rows y0 .. y1 - 1
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -74,8 +76,8 @@ __attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW)))) void step2_kernel(co
     unsigned fc = ux_ * (unsigned)sizeof(M), fm = uxm * (unsigned)sizeof(M), fp = uxp * (unsigned)sizeof(M);
     const unsigned pb = (unsigned)(pitch * (int64_t)sizeof(T));
 
-    const T *__restrict__ src = static_cast<const T *>(d.buf[a.parity]);
-    T *__restrict__ dst = static_cast<T *>(d.buf[a.parity ^ 1]);
+    const T *__restrict__ src = static_cast<const T *>(d.buf[parity]);
+    T *__restrict__ dst = static_cast<T *>(d.buf[parity ^ 1]);
     const M *__restrict__ u = static_cast<const M *>(d.u);
     const M *__restrict__ kf = static_cast<const M *>(d.k);
     const M *__restrict__ sf = static_cast<const M *>(d.s);
@@ -101,8 +103,8 @@ __attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW)))) void step2_kernel(co
     M p0_m = M(0), p2_m = M(0), p2_mm = M(0);
 
     // stochastic rounding: time level of the state this launch reads; it writes levels + 1 and + 2
-    const int64_t level = launch_level<C>(d, a.parity);
-    advance_level<C>(d, a.parity, level, 2, t == 0 && threadIdx.x == 0);
+    const int64_t level = launch_level<C>(d, parity);
+    advance_level<C>(d, parity, level, 2, t == 0 && threadIdx.x == 0);
 
     for (int r = rs; r <= y1; ++r) {
         // row indices through readfirstlane: uniform values the compiler cannot strength-reduce into
@@ -209,12 +211,53 @@ __attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW)))) void step2_kernel(co
     }
 }
 
+// One instance: block b -> tile (XCD-remapped as the launch says).
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, bool MRT, int NW, bool CST>
+__global__ __launch_bounds__(64 * (NW + 1))
+__attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW)))) void step2_kernel(const StepArgs a)
+{
+    const InstDesc &d = a.d;
+    const int ntx = (d.L.nx + 64 * NW - 1) / (64 * NW);
+    const int t = tile_of_block(blockIdx.x, gridDim.x, d.lcf.xcd_remap, ntx, d.lcf.xcd_rows);
+    __shared__ Ring<MODE, NW> ring;
+    fused_tile<MODE, AUX, HAS_K, HAS_S, MRT, NW, CST>(d, a.parity, t, ring);
+}
+
+// Many instances (periodic D2Q9 TRT-R, one storage form and aux form): each block runs a range of
+// (instance, fused tile) work items, non-temporal stores; the descriptor is wave-uniform (scalar loads).
+template <int MODE, int AUX, int NW>
+__global__ __launch_bounds__(64 * (NW + 1))
+__attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW)))) void batched_step2_kernel(const BatchArgs a)
+{
+    int beg, end;
+    if (a.block_start) {
+        beg = a.block_start[blockIdx.x];
+        end = a.block_start[blockIdx.x + 1];
+    } else {
+        beg = tile_of_block(blockIdx.x, gridDim.x, 1, 0, 0);
+        end = beg + 1;
+    }
+    __shared__ Ring<MODE, NW> ring;
+    for (int it = beg; it < end; ++it) {
+        const WorkItem w = a.items[it];
+        const InstDesc &d = a.inst[w.inst];
+        if (d.has_k) {
+            if (d.has_s) fused_tile<MODE, AUX, true, true, false, NW, false>(d, a.parity, w.tile, ring);
+            else fused_tile<MODE, AUX, true, false, false, NW, false>(d, a.parity, w.tile, ring);
+        } else {
+            if (d.has_s) fused_tile<MODE, AUX, false, true, false, NW, false>(d, a.parity, w.tile, ring);
+            else fused_tile<MODE, AUX, false, false, false, NW, false>(d, a.parity, w.tile, ring);
+        }
+        __syncthreads();  // the next tile rewrites the ring the last rows of this one were read from
+    }
+}
+
 template <int MODE, int AUX, bool MRT, int NW, bool CST>
 hipError_t launch_fused_nw(const StepArgs &a, hipStream_t st)
 {
-    const int W = 64 * NW, H = a.d.lc.rows;
+    const int W = 64 * NW, H = a.d.lcf.rows;
     const int nblocks = ((a.d.L.nx + W - 1) / W) * ((a.d.L.ny + H - 1) / H);
-    const size_t lds = (size_t)a.d.lc.lds_reserve;  // unused LDS that caps the resident waves
+    const size_t lds = (size_t)a.d.lcf.lds_reserve;  // unused LDS that caps the resident waves
     const dim3 block(64 * (NW + 1));
     const bool hk = a.d.has_k, hs = a.d.has_s;
     if (hk && hs) step2_kernel<MODE, AUX, true, true, MRT, NW, CST><<<nblocks, block, lds, st>>>(a);
@@ -227,8 +270,8 @@ hipError_t launch_fused_nw(const StepArgs &a, hipStream_t st)
 template <int MODE, int AUX, bool MRT>
 hipError_t launch_fused_var(const StepArgs &a, hipStream_t st)
 {
-    const bool cst = a.d.lc.stores == 1;
-    switch (a.d.lc.fuse_width) {
+    const bool cst = a.d.lcf.stores == 1;
+    switch (a.d.lcf.fuse_width) {
     case 128: return cst ? launch_fused_nw<MODE, AUX, MRT, 2, true>(a, st) : launch_fused_nw<MODE, AUX, MRT, 2, false>(a, st);
     case 256: return cst ? launch_fused_nw<MODE, AUX, MRT, 4, true>(a, st) : launch_fused_nw<MODE, AUX, MRT, 4, false>(a, st);
     case 512: return cst ? launch_fused_nw<MODE, AUX, MRT, 8, true>(a, st) : launch_fused_nw<MODE, AUX, MRT, 8, false>(a, st);
@@ -253,12 +296,47 @@ hipError_t launch_fused_mode(int aux, const StepArgs &a, hipStream_t st)
     }
 }
 
+template <int MODE, int AUX>
+hipError_t launch_batched_fused_aux(const BatchArgs &a, int nblocks, int width, hipStream_t st)
+{
+    switch (width) {
+    case 128: batched_step2_kernel<MODE, AUX, 2><<<nblocks, 64 * 3, 0, st>>>(a); break;
+    case 256: batched_step2_kernel<MODE, AUX, 4><<<nblocks, 64 * 5, 0, st>>>(a); break;
+    case 512: batched_step2_kernel<MODE, AUX, 8><<<nblocks, 64 * 9, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_batched_fused_mode(int aux, const BatchArgs &a, int nblocks, int width, hipStream_t st)
+{
+    switch (aux) {
+    case 0: return launch_batched_fused_aux<MODE, 0>(a, nblocks, width, st);
+    case 2: return launch_batched_fused_aux<MODE, 2>(a, nblocks, width, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_batched_step2(int mode, int aux, const BatchArgs &a, int nblocks, int width, hipStream_t st)
+{
+    if (nblocks < 1) return hipErrorInvalidValue;
+    switch (mode) {
+    case MODE_F64_F64: return launch_batched_fused_mode<MODE_F64_F64>(aux, a, nblocks, width, st);
+    case MODE_F64_F32: return launch_batched_fused_mode<MODE_F64_F32>(aux, a, nblocks, width, st);
+    case MODE_F32_F32: return launch_batched_fused_mode<MODE_F32_F32>(aux, a, nblocks, width, st);
+    case MODE_F16S_F32: return launch_batched_fused_mode<MODE_F16S_F32>(aux, a, nblocks, width, st);
+    case MODE_F16SR_F32: return launch_batched_fused_mode<MODE_F16SR_F32>(aux, a, nblocks, width, st);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_step2(int mode, int aux, const StepArgs &a, hipStream_t st)
 {
-    if (a.d.L.q != 9 || a.d.bckind != 0 || a.d.lc.stores == 2) return hipErrorInvalidValue;
-    if (a.d.lc.rows < 1 || a.d.lc.rows > 1024 || a.d.lc.lds_reserve < 0 || a.d.lc.lds_reserve > 65536)
+    if (a.d.L.q != 9 || a.d.bckind != 0 || a.d.lcf.fuse != 2 || a.d.lcf.stores == 2) return hipErrorInvalidValue;
+    if (a.d.lcf.rows < 1 || a.d.lcf.rows > 1024 || a.d.lcf.lds_reserve < 0 || a.d.lcf.lds_reserve > 65536)
         return hipErrorInvalidValue;
     switch (mode) {
     case MODE_F64_F64: return launch_fused_mode<MODE_F64_F64>(aux, a, st);

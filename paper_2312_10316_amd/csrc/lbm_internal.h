@@ -69,7 +69,8 @@ struct InstDesc {
     const void *k;      // math type, tau1 - 1/2 per node (used when has_k)
     const void *s;      // math type, dt S + dt^2/2 dS/dt per node (used when has_s)
     Layout L;
-    Launch lc;
+    Launch lc;          // one step per launch (every one-step kernel, single or batched)
+    Launch lcf;         // two steps per launch (lcf.fuse == 2): fuse_width x rows tiles, tile order
     int32_t has_k, has_s;
     const void *bc;     // Dirichlet values (math type, [ny][pitch]): phi_b of the edge nodes (NEE), or
                         // the wall values of the walls below row 0 / above row ny - 1 (walls)
@@ -196,8 +197,11 @@ struct AdjArgs {
 // Launchers (lbm_kernels.hip, lbm_adjoint.hip).  All return the hipError_t of the launch.
 hipError_t launch_step(int mode, int aux, const StepArgs &a, hipStream_t st);
 // Two steps per launch (lbm_fused.hip): D2Q9, periodic, aux LOCAL or NONE, two buffers (reads
-// buf[parity], writes buf[parity ^ 1] two steps later).  lc.fuse_width columns x lc.rows rows per tile.
+// buf[parity], writes buf[parity ^ 1] two steps later).  lcf.fuse_width columns x lcf.rows rows per tile.
 hipError_t launch_step2(int mode, int aux, const StepArgs &a, hipStream_t st);
+// The same for many instances in one launch: block b runs work items (instance, fused tile) as the
+// one-step batched kernel does; every instance has tiles of `width` columns (128, 256 or 512).
+hipError_t launch_batched_step2(int mode, int aux, const BatchArgs &a, int nblocks, int width, hipStream_t st);
 hipError_t launch_batched_step(int mode, int aux, const BatchArgs &a, int nblocks, int lds_reserve, hipStream_t st);
 hipError_t launch_init(int mode, const InitArgs &a, hipStream_t st);
 // F16SR: sets *slot = level (one lane of one block; kept out of graph captures by the callers).

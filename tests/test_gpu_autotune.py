@@ -78,6 +78,8 @@ def test_default_candidates_of_a_single_instance_include_fused_and_in_place_laun
     cands = autotune.default_candidates(s)
     assert any(c[8] == 2 for c in cands) and any(c[5] == 2 for c in cands)
     s.close()
-    s = Solver([pulse_instance(64), pulse_instance(96)])
-    assert all(c[8] == 1 for c in autotune.default_candidates(s))
+    s = Solver([pulse_instance(64), pulse_instance(96)])  # a uniform batch: fused candidates as a whole
+    cands = autotune.default_candidates(s)
+    assert any(c[8] == 1 for c in cands) and any(c[8] == 2 for c in cands)
+    assert all(c[6] in (lbm.LBM_BATCH_FLAT, lbm.LBM_BATCH_LPT) and c[3] in (128, 256) for c in cands if c[8] == 2)
     s.close()

@@ -141,3 +141,46 @@ def test_seeded_instance_draws_batched():
         assert st["nonfinite"] == 0
     s.close()
     r.close()
+
+
+FUSED_SHAPES = [(128, 16), (256, 4), (512, 1), (128, 37)]
+
+
+@pytest.mark.parametrize("mode", ["f64", "f32", "f16s", "f16sr"])
+def test_batched_two_steps_per_launch_match_serial_single_steps(mode):
+    """Every instance of a uniform batch fused (two steps per launch, one batched launch): bitwise the
+    serial single steps, for every schedule, tile width and height, at odd and even step counts and
+    through graph replays; the single steps of the fused context take the one-step batched kernel."""
+    insts = [instance(c, mode)[:2] for c in mixed_configs()]
+    ref = Solver(insts)
+    ref.set_batch(lbm.LBM_BATCH_SERIAL)
+    ref.set_launch(1, 1, tile_width=256)
+    ref.step(71)
+    want = [ref.state_save(k) for k in range(len(insts))]
+    ref.close()
+    for (width, rows), (policy, blocks, _) in zip(FUSED_SHAPES * 2, POLICIES[:4] * 2):
+        s = Solver(insts)
+        s.set_launch(rows, 1, tile_width=width, fuse=2)
+        assert all(s.get_launch(k)["fuse"] == 2 for k in range(len(insts)))
+        s.set_batch(policy, blocks)
+        s.step(3)
+        s.macros()
+        s.step(68)  # two graph replays of 16 fused launches, then 2 fused launches
+        for k in range(len(insts)):
+            assert torch.equal(s.state_save(k), want[k]), (mode, width, rows, policy, k)
+        s.close()
+
+
+def test_batched_two_steps_per_launch_rejections():
+    insts = [instance(c, "f32")[:2] for c in mixed_configs()]
+    s = Solver(insts)
+    with pytest.raises(lbm.LbmError) as ei:
+        s.set_launch(16, 1, inst=0, tile_width=128, fuse=2)  # one instance of several: all or none
+    assert ei.value.status == lbm.LBM_E_ARG
+    s.close()
+    mixed = [instance(mixed_configs()[0], "f32")[:2], instance(mixed_configs()[1], "f64")[:2]]
+    s = Solver(mixed)  # not a uniform batch
+    with pytest.raises(lbm.LbmError) as ei:
+        s.set_launch(16, 1, tile_width=128, fuse=2)
+    assert ei.value.status == lbm.LBM_E_ARG
+    s.close()

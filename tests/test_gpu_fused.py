@@ -123,11 +123,12 @@ def test_fused_rejects_what_it_does_not_cover():
     def mk(**kw):
         return lbm.make_params(64, 40, dx, dt, 0.25, 2e-3, "f32", **kw)
 
-    for params in ([mk(aux=lbm.LBM_AUX_FLUX)], [mk(boundary=lbm.LBM_BC_NEE)], [mk(boundary=lbm.LBM_BC_WALLS)],
-                   [mk(), mk()], [mk(tau3=0.7)]):
+    for params, inst in (([mk(aux=lbm.LBM_AUX_FLUX)], -1), ([mk(boundary=lbm.LBM_BC_NEE)], -1),
+                         ([mk(boundary=lbm.LBM_BC_WALLS)], -1), ([mk(), mk()], 1), ([mk(), mk(tau3=0.7)], -1),
+                         ([mk(tau3=0.7)], -1)):
         s = Solver([(p, fields) for p in params])
         with pytest.raises(lbm.LbmError) as ei:
-            s.set_launch(8, 1, tile_width=256, fuse=2)
+            s.set_launch(8, 1, inst=inst, tile_width=256, fuse=2)
         assert ei.value.status == lbm.LBM_E_ARG
         s.close()
     s = Solver([(mk(), fields)])

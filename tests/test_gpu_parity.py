@@ -471,6 +471,8 @@ def test_launch_defaults_and_bad_launch_shapes():
             width //= 2
         while rows > 4 and -(-nx // width) * -(-ny // rows) < 256:
             rows //= 2
+        while width > 128 and -(-nx // width) * -(-ny // rows) < 256:
+            width //= 2
         return launch(rows, 1, width, 0, 0, stores, 2)
 
     # One periodic D2Q9 TRT-R instance (local or no aux term) runs two steps per launch.  A context that
@@ -524,8 +526,13 @@ def test_launch_defaults_and_bad_launch_shapes():
         s.close()
         del fl
     two = [(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, "f32"), fields)] * 2
-    s = Solver(two)  # several instances: the batched kernel's 64-column tiles
-    assert s.get_launch(1) == launch(1, 1, 64, 0)
+    s = Solver(two)  # a uniform batch: two steps per launch in 128 x 16 tiles
+    assert s.get_launch(1) == launch(16, 1, 128, 0, 0, 1, 2)
+    with pytest.raises(lbm.LbmError) as ei:  # a batch fuses as a whole or not at all
+        s.set_launch(16, 1, inst=0, tile_width=128, fuse=2)
+    assert ei.value.status == lbm.LBM_E_ARG
+    s.set_launch(1, 1, tile_width=64)  # one step per launch: the batched kernel's 64-column tiles
+    assert s.get_launch(1) == launch(1, 1, 64, 0, 0, 0)
     s.set_launch(1, 3, tile_width=256, xcd_rows=4)
     assert s.get_launch(0) == launch(1, 3, 256, 0, 4, stores=0)
     s.set_launch(1, 2, tile_width=256, xcd_rows=4, stores=1)  # xcd_rows only counts with order 3
@@ -533,7 +540,7 @@ def test_launch_defaults_and_bad_launch_shapes():
     for remap, kw in ((1, dict(tile_width=128)), (1, dict(tile_width=0)), (1, dict(max_waves=2)),
                       (1, dict(max_waves=9)), (1, dict(max_waves=-1)), (3, {}), (3, dict(xcd_rows=65)),
                       (3, dict(xcd_rows=-2)), (4, {}), (-1, {}), (1, dict(stores=2)), (1, dict(stores=-1)),
-                      (1, dict(fuse=2, tile_width=256))):
+                      (1, dict(fuse=2, tile_width=64))):
         with pytest.raises(lbm.LbmError) as ei:
             s.set_launch(1, remap, **kw)
         assert ei.value.status == lbm.LBM_E_ARG, (remap, kw)
