@@ -758,10 +758,14 @@ def run_profile_workload(torch, W, lbm, Solver, name, n, steps):
             p = lbm.make_params(cfg.N, cfg.N, f["dx"], f["dt"], cfg.lam, cfg.D, "f32")
             insts.append((p, {k: torch.from_numpy(f[k]).cuda() for k in ("phi0", "ux", "uy")}))
         s = Solver(insts)
-        s.step(64)
-        ms = _timed_steps(torch, s, steps)
         nodes = int(sum(d.N * d.N for d in draws))
-        out.update(nodes=nodes, mlups=nodes / (ms * 1e-3) / 1e6, batch=s.get_batch(), launch=s.get_launch())
+        for label in ("two_steps_per_launch", "one_step_per_launch"):  # the default, then one step per launch
+            if label == "one_step_per_launch":
+                s.set_launch(1, 1, tile_width=64)
+            s.step(64)
+            ms = _timed_steps(torch, s, steps)
+            out[label] = {"mlups": nodes / (ms * 1e-3) / 1e6, "launch": s.get_launch()}
+        out.update(nodes=nodes, batch=s.get_batch())
         s.close()
     elif name == "adjoint":
         out.update(run_adjoint(torch, W, lbm, Solver))
@@ -789,7 +793,10 @@ def _workload_kernels(name: str, n: int):
     if name == "batched":
         import workloads as W
         nodes = sum(d.N * d.N for d in W.batched_instances(256))
-        return [("batched_step_kernel FP32, 256 instances", r"batched_step_kernel<2, 0, \d>", nodes * 80.0, nodes)]
+        return [("batched_step2_kernel FP32, 256 instances, two steps per launch", r"batched_step2_kernel<2, 0, \d>",
+                 nodes * 80.0, 2 * nodes),
+                ("batched_step_kernel FP32, 256 instances, one step per launch", r"batched_step_kernel<2, 0, \d>",
+                 nodes * 80.0, nodes)]
     if name == "adjoint":
         import workloads as W
         nodes = W.C5_N ** 2
