@@ -331,18 +331,29 @@ def run_refinement(torch, W, lbm, Solver, sizes=(64, 128, 256, 512, 1024, 2048),
     return out
 
 
-def run_flux(torch, W, lbm, Solver, n=2048, steps=3000):
-    cfg = W.PulseConfig(N=n, steps=steps)
-    f = W.rotating_pulse(cfg)
-    dev = {k: torch.from_numpy(f[k]).cuda() for k in ("phi0", "ux", "uy")}
+def run_flux(torch, W, lbm, Solver, sizes=((2048, 3000), (8192, 200))):
+    """The flux form of the aux term (default launch: two steps per launch) at 2048^2 and 8192^2, FP32 and
+    FP64: MLUPS, the launch's algorithmic bytes per second against 8 TB/s, and the single-step-equivalent
+    rate (the bytes a one-step launch would move for the same updates)."""
     out = {}
-    for mode in ("f32", "f64"):
-        s = Solver([(lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, mode, lbm.LBM_AUX_FLUX), dev)])
-        s.step(64)
-        ms = _timed_steps(torch, s, steps)
-        launch = s.get_launch()
-        s.close()
-        out[mode] = {"mlups": n * n / (ms * 1e-3) / 1e6, "ms_per_step": ms, "launch": launch}
+    for n, steps in sizes:
+        cfg = W.PulseConfig(N=n, steps=steps)
+        f = W.rotating_pulse(cfg)
+        dev = {k: torch.from_numpy(f[k]).cuda() for k in ("phi0", "ux", "uy")}
+        for mode in ("f32", "f64"):
+            s = Solver([(lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, mode, lbm.LBM_AUX_FLUX), dev)])
+            s.step(64)
+            ms = _timed_steps(torch, s, steps)
+            launch = s.get_launch()
+            s.close()
+            mlups = n * n / (ms * 1e-3) / 1e6
+            bpl = launch_bytes_per_lup(mode, False, launch)
+            key = mode if n == 2048 else f"{mode}_{n}"
+            out[key] = {"N": n, "mlups": mlups, "ms_per_step": ms, "launch": launch, "bytes_per_lup": bpl,
+                        "frac": mlups * bpl / 1e3 / HBM_PEAK_GBPS,
+                        "single_step_equivalent_frac": mlups * bytes_per_lup(mode, False) / 1e3 / HBM_PEAK_GBPS}
+        del dev
+        torch.cuda.empty_cache()
     return out
 
 
@@ -775,9 +786,12 @@ def run_profile_workload(torch, W, lbm, Solver, name, n, steps):
         dev = {k: torch.from_numpy(f[k]).cuda() for k in ("phi0", "ux", "uy")}
         for mode in ("f32", "f64"):
             s = Solver([(lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, mode, lbm.LBM_AUX_FLUX), dev)])
-            s.step(64)
-            ms = _timed_steps(torch, s, steps)
-            out[mode] = {"mlups": n * n / (ms * 1e-3) / 1e6, "launch": s.get_launch()}
+            for label in ("two_steps_per_launch", "one_step_per_launch"):  # the default, then one step
+                if label == "one_step_per_launch":
+                    s.set_launch(2, 1, tile_width=256)
+                s.step(64)
+                ms = _timed_steps(torch, s, steps)
+                out[f"{mode}_{label}"] = {"mlups": n * n / (ms * 1e-3) / 1e6, "launch": s.get_launch()}
             s.close()
         del dev
         torch.cuda.empty_cache()
@@ -807,8 +821,13 @@ def _workload_kernels(name: str, n: int):
                 ("step2_kernel FP32, D field (forward, two steps per launch)", r"step2_kernel<2, 0, true, false", nodes * 84.0,
                  2 * nodes)]
     if name == "flux":
-        return [("step_kernel FP32, flux form", r"step_kernel<2, 1, false, false", float(n) * n * 80.0, n * n),
-                ("step_kernel FP64, flux form", r"step_kernel<0, 1, false, false", float(n) * n * 160.0, n * n)]
+        return [("flux2_kernel FP32, two steps per launch", r"flux2_kernel<2, false, false", float(n) * n * 80.0, 2 * n * n),
+                ("flux2_kernel FP64, two steps per launch", r"flux2_kernel<0, false, false", float(n) * n * 160.0,
+                 2 * n * n),
+                ("step_kernel FP32, flux form, one step per launch", r"step_kernel<2, 1, false, false", float(n) * n * 80.0,
+                 n * n),
+                ("step_kernel FP64, flux form, one step per launch", r"step_kernel<0, 1, false, false", float(n) * n * 160.0,
+                 n * n)]
     raise ValueError(name)
 
 
@@ -1201,7 +1220,7 @@ def main():
               file=sys.stderr, flush=True)
     if not args.no_studies:
         for name, fn in (("precision_8192_variable_D", run_precision_8192), ("refinement", run_refinement),
-                         ("flux_aux_2048", run_flux), ("dirichlet_sec3", run_dirichlet),
+                         ("flux_aux", run_flux), ("dirichlet_sec3", run_dirichlet),
                          ("tau2_sweep_walls", run_tau2_sweep), ("d3q19", run_3d),
                          ("d3q27", lambda *a: run_3d(*a, q=27)),
                          ("adjoint_512", run_adjoint)):

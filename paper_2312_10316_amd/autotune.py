@@ -32,8 +32,7 @@ def _key(solver) -> str:
 
 
 def _fusable_params(p) -> bool:
-    return (p.lattice == L.LBM_LATTICE_D2Q9 and p.boundary == L.LBM_BC_PERIODIC and p.aux != L.LBM_AUX_FLUX
-            and p.tau3 in (0.0, 1.0))
+    return p.lattice == L.LBM_LATTICE_D2Q9 and p.boundary == L.LBM_BC_PERIODIC and p.tau3 in (0.0, 1.0)
 
 
 def _fusable(solver) -> bool:
@@ -43,7 +42,7 @@ def _fusable(solver) -> bool:
 def _fusable_batch(solver) -> bool:
     """A uniform batch (one storage and aux form, periodic D2Q9 TRT-R) can run two steps per launch."""
     ps = solver.params
-    return (len(ps) > 1 and all(_fusable_params(p) for p in ps)
+    return (len(ps) > 1 and all(_fusable_params(p) and p.aux != L.LBM_AUX_FLUX for p in ps)
             and len({(p.store, p.math, p.aux) for p in ps}) == 1)
 
 
@@ -59,11 +58,13 @@ def default_candidates(solver) -> list:
     p0 = solver.params[0]
     multi = len(solver.params) > 1 and len({(p.store, p.math, p.aux) for p in solver.params}) == 1
     if _fusable(solver):
-        for width in (128, 256, 512):
+        flux = p0.aux == L.LBM_AUX_FLUX  # the flux form: 128- or 256-column tiles, never in place
+        for width in ((128, 256) if flux else (128, 256, 512)):
             for rows in (8, 16, 32, 64):
                 for remap in (0, 1):
                     for stores in (0, 1):
                         out.append((rows, remap, 0, width, 0, stores, L.LBM_BATCH_SERIAL, 0, 2))
+    if _fusable(solver) and p0.aux != L.LBM_AUX_FLUX:
         for width in (64, 256):
             for remap, h in [(0, 0), (1, 0)] + ([(3, h) for h in (2, 4, 8)] if width == 256 else []):
                 for cap in (0, 4, 5):

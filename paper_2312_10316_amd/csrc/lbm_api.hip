@@ -159,15 +159,16 @@ Launch default_launch(const lbm_params &p, int mode, bool has_D, int n_inst, int
 // tiles of 16 rows (2048^2: FP32 122k, FP16 167k MLUPS), FP64 storage 256 x 32; wider lattices take
 // FP32 256 x 16 (8192^2: 135k), FP16 128 x 32 (171k) and FP64 storage 128 x 16 (64k).  Tiles never
 // wider than the lattice needs (at least 128 columns), and at least 256 tiles where the lattice allows
-// (down to 4 rows, then down to 128 columns: a 512^2 lattice in 512 x 4 tiles kept half the CUs idle).  Row bands over the XCDs, so that the frame rows a tile shares with the next tile
+// (down to 4 rows, then down to 128 columns: a 512^2 lattice in 512 x 4 tiles kept half the CUs idle).
+// The flux form (sweep of 128/256 columns x 4..64 rows x tile order x stores): 128-column tiles, 16 rows
+// for FP32 up to 2048 columns (2048^2: 96k MLUPS), else 32 (8192^2 FP32 107k, FP16 108k, FP64 54k).  Row bands over the XCDs, so that the frame rows a tile shares with the next tile
 // down sit in the same L2.  (MRT-R stays on single steps: with FP64 math the compiler had fused its
 // third-order multiply-adds otherwise in the fused kernel.)
-// An instance whose steps can be fused (a periodic D2Q9 TRT-R instance, local or no aux term).  A
-// context fuses its one instance, or every instance of a uniform batch at once.
+// An instance whose steps can be fused (a periodic D2Q9 TRT-R instance, any aux form).  A context fuses
+// its one instance, or every instance of a uniform batch at once (local or no aux term).
 bool fusable(const lbm_params &p)
 {
-    return p.lattice == LBM_LATTICE_D2Q9 && p.boundary == LBM_BC_PERIODIC && p.aux != LBM_AUX_FLUX &&
-           (p.tau3 == 0.0 || p.tau3 == 1.0);
+    return p.lattice == LBM_LATTICE_D2Q9 && p.boundary == LBM_BC_PERIODIC && (p.tau3 == 0.0 || p.tau3 == 1.0);
 }
 Launch fused_default(const lbm_params &p, int mode)
 {
@@ -184,6 +185,10 @@ Launch fused_default(const lbm_params &p, int mode)
     } else {
         width = narrow ? 256 : 128;
         rows = narrow ? 32 : 16;
+    }
+    if (p.aux == LBM_AUX_FLUX) {  // 128-column tiles: FP32 16 rows up to 2048 columns, else 32 rows
+        width = 128;
+        rows = mode == MODE_F32_F32 && narrow ? 16 : 32;
     }
     while (width > 128 && width / 2 >= p.nx) width /= 2;
     auto tiles = [&](int h) { return (int64_t)((p.nx + width - 1) / width) * ((p.ny + h - 1) / h); };
@@ -793,7 +798,7 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
     // 128 x 16 tiles (the 256-instance C4 batch, N = 32..508, FP32: 99k MLUPS against 67k for the
     // best one-step schedule; 256-column tiles and 8 or 32 rows, flat or LPT, measured slower).
     bool batch_fuses = n_inst > 1 && c->uniform;
-    for (const Instance &in : c->inst) batch_fuses &= fusable(in.p);
+    for (const Instance &in : c->inst) batch_fuses &= fusable(in.p) && in.p.aux != LBM_AUX_FLUX;
     if (batch_fuses)
         for (Instance &in : c->inst) {
             in.lc = Launch{};
@@ -1123,9 +1128,12 @@ int lbm_set_launch(lbm_ctx *c, int32_t inst, const lbm_launch *cfg)
                                    "instance: D2Q9 with the local or no auxiliary term, or D3Q19/D3Q27 without FP64 math");
         if (want_one && (cfg->rows != 1 || two))
             return fail(LBM_E_ARG, "lbm_set_launch: stores=2 (one buffer in place) needs rows=1 and fuse 0 or 1");
-        if (two && (!fusable(in.p) || (c->inst.size() > 1 && (!c->uniform || inst != -1))))
-            return fail(LBM_E_ARG, "lbm_set_launch: fuse=2 needs periodic D2Q9 TRT-R instances with the local or no "
-                                   "auxiliary term: one instance, or every instance of a uniform batch at once (inst -1)");
+        if (two && (!fusable(in.p) ||
+                    (c->inst.size() > 1 && (!c->uniform || inst != -1 || in.p.aux == LBM_AUX_FLUX))))
+            return fail(LBM_E_ARG, "lbm_set_launch: fuse=2 needs periodic D2Q9 TRT-R instances: one instance, or every "
+                                   "instance of a uniform batch at once (inst -1) with the local or no auxiliary term");
+        if (two && in.p.aux == LBM_AUX_FLUX && cfg->tile_width == 512)
+            return fail(LBM_E_ARG, "lbm_set_launch: the flux form's two-step tiles are 128 or 256 columns wide");
     }
     if (two ? (cfg->tile_width != 128 && cfg->tile_width != 256 && cfg->tile_width != 512)
             : (cfg->tile_width != 64 && cfg->tile_width != 256))

@@ -211,6 +211,212 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
     }
 }
 
+// ---- two steps with the flux form of the auxiliary term ----------------------------------------------
+//
+// The flux form needs phi at the four axis neighbours, at the time level of the step.  A two-step tile of
+// W output columns therefore carries three frame columns on each side (ring column cc holds lattice
+// column x0 - 3 + cc, wrapped): phi at level n + 1 for all W + 6 columns (each the sum of the node's pulls
+// from the state at n), intermediate nodes (level n + 1) for the inner W + 4, phi at level n + 2 for the
+// inner W + 2 (the sums of the pulls from the intermediate state) and outputs for the W interior
+// columns.  Iteration r of the walk pulls state row r + 1 (its phi into a ring, its populations kept for
+// the next iteration), computes intermediate row r (the x-moving populations into a ring); after the
+// block's one barrier it pulls intermediate rows r - 2 .. r for the node of row r - 1 (its phi into a
+// ring, its populations kept) and computes output row r - 2.  Frame wave lanes 0-2 and 3-5 take the
+// three frame columns on the left and on the right.  Every node runs the arithmetic of the one-step flux
+// kernel (the same pulls, sums in index order, flux_aux, collide) and the intermediate populations go
+// through the storage codec, so the results are bitwise those of two single steps.
+template <int MODE, int NW>
+struct FluxRings {
+    typename ModeTraits<MODE>::St::T pop[4][6][64 * NW + 6];  // intermediate x-moving populations
+    typename ModeTraits<MODE>::M phi1[4][64 * NW + 6];        // phi at level n + 1
+    typename ModeTraits<MODE>::M phi2[4][64 * NW + 6];        // phi at level n + 2
+};
+
+template <int MODE, bool HAS_K, bool HAS_S, int NW, bool CST>
+__device__ __forceinline__ void flux_tile(const InstDesc &d, int parity, int t, FluxRings<MODE, NW> &R)
+{
+    using St = typename ModeTraits<MODE>::St;
+    using M = typename ModeTraits<MODE>::M;
+    using T = typename St::T;
+    using C = Codec<St, M>;
+    constexpr int W = 64 * NW;
+
+    const int nx = d.L.nx, ny = d.L.ny;
+    const int64_t pitch = d.L.pitch;
+    const int H = d.lcf.rows;
+    const int ntx = (nx + W - 1) / W;
+    const int x0 = (t % ntx) * W, y0 = (t / ntx) * H;
+    const int y1 = min(y0 + H, ny);  // output rows y0 .. y1 - 1
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = (int)(threadIdx.x & 63u);
+    const bool frame = wave == NW;
+    const int cc = frame ? (lane < 3 ? lane : (lane < 6 ? W + lane : -1)) : 3 + wave * 64 + lane;
+    const bool act = cc >= 0;                         // pulls the state (phi at n + 1)
+    const bool inter = act && cc >= 1 && cc < W + 5;  // an intermediate node
+    const bool mid = act && cc >= 2 && cc < W + 4;    // phi at n + 2
+    const bool live = !frame && x0 + wave * 64 + lane < nx;  // an output node
+    int xi = x0 - 3 + (act ? cc : 3);
+    xi = xi % nx;
+    xi = xi < 0 ? xi + nx : xi;
+    const unsigned ux_ = (unsigned)xi;
+    const unsigned uxm = ux_ == 0 ? (unsigned)nx - 1 : ux_ - 1;
+    const unsigned uxp = ux_ == (unsigned)nx - 1 ? 0u : ux_ + 1;
+    unsigned bc = ux_ * (unsigned)sizeof(T), bm = uxm * (unsigned)sizeof(T), bp = uxp * (unsigned)sizeof(T);
+    unsigned fc = ux_ * (unsigned)sizeof(M), fm = uxm * (unsigned)sizeof(M), fp = uxp * (unsigned)sizeof(M);
+    const unsigned pb = (unsigned)(pitch * (int64_t)sizeof(T));
+    const int cl = act ? cc : 0;  // a ring column every lane may address
+
+    const T *__restrict__ src = static_cast<const T *>(d.buf[parity]);
+    T *__restrict__ dst = static_cast<T *>(d.buf[parity ^ 1]);
+    const M *__restrict__ u = static_cast<const M *>(d.u);
+    const M *__restrict__ kf = static_cast<const M *>(d.k);
+    const M *__restrict__ sf = static_cast<const M *>(d.s);
+    const M lam = (M)d.lambda;
+    Relax<M> rconst;
+    rconst.w1 = (M)d.w1;
+    rconst.w2 = (M)d.w2;
+    rconst.beta = (M)d.beta;
+    rconst.w3 = (M)d.w3;
+
+    // rows y0 - 4 .. y1 + 3 wrapped (twice at most: ny >= 3)
+    auto wrapr = [ny](int r) {
+        r = r < 0 ? r + ny : (r >= ny ? r - ny : r);
+        return r < 0 ? r + ny : (r >= ny ? r - ny : r);
+    };
+    auto sum9 = [](const M (&g)[9]) { return g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8]; };
+    // the nine populations node (xi, row) pulls from the state
+    auto pull = [&](int row, M (&g)[9]) {
+        const T *__restrict__ rm = src + (int64_t)__builtin_amdgcn_readfirstlane(wrapr(row - 1)) * 9 * pitch;
+        const T *__restrict__ rc = src + (int64_t)__builtin_amdgcn_readfirstlane(wrapr(row)) * 9 * pitch;
+        const T *__restrict__ rp = src + (int64_t)__builtin_amdgcn_readfirstlane(wrapr(row + 1)) * 9 * pitch;
+        g[0] = C::dec(ld_at(rc, bc), 0, d.f16);
+        g[1] = C::dec(ld_at(rc + pitch, bm), 1, d.f16);
+        g[2] = C::dec(ld_at(rm + 2 * pitch, bc), 2, d.f16);
+        g[3] = C::dec(ld_at(rc + 3 * pitch, bp), 3, d.f16);
+        g[4] = C::dec(ld_at(rp + 4 * pitch, bc), 4, d.f16);
+        g[5] = C::dec(ld_at(rm + 5 * pitch, bm), 5, d.f16);
+        g[6] = C::dec(ld_at(rm + 6 * pitch, bp), 6, d.f16);
+        g[7] = C::dec(ld_at(rp + 7 * pitch, bp), 7, d.f16);
+        g[8] = C::dec(ld_at(rp + 8 * pitch, bm), 8, d.f16);
+    };
+    auto urow = [&](int row) { return u + (int64_t)__builtin_amdgcn_readfirstlane(wrapr(row)) * 2 * pitch; };
+
+    const int64_t level = launch_level<C>(d, parity);  // stochastic rounding: writes levels + 1 and + 2
+    advance_level<C>(d, parity, level, 2, t == 0 && threadIdx.x == 0);
+
+    // the walk starts at r = y0 - 2 with the state pulls of rows y0 - 3 (phi only) and y0 - 2
+    M gc[9], p1_m, p1_c;
+    {
+        M gm[9];
+        pull(y0 - 3, gm);
+        p1_m = sum9(gm);
+        pull(y0 - 2, gc);
+        p1_c = sum9(gc);
+        if (act) {
+            R.phi1[(y0 - 3) & 3][cc] = p1_m;
+            R.phi1[(y0 - 2) & 3][cc] = p1_c;
+        }
+    }
+    // u at this column, rows r - 3 .. r + 1 of the walk
+    M ux3 = M(0), uy3 = M(0), ux2 = M(0), uy2 = M(0);
+    M ux1 = ld_at(urow(y0 - 3), fc), uy1 = ld_at(urow(y0 - 3) + pitch, fc);
+    M ux0 = ld_at(urow(y0 - 2), fc), uy0 = ld_at(urow(y0 - 2) + pitch, fc);
+    // e_x = 0 intermediate populations of this column as a reader decodes them, rows r - 1 and r - 2
+    M p0_m = M(0), p2_m = M(0), p2_mm = M(0);
+    // phi at n + 2 of this column, rows r - 3 and r - 2, and the populations node (xi, r - 2) pulled
+    M q_m3 = M(0), q_m2 = M(0);
+    M g2[9] = {};
+    __syncthreads();  // phi1 of the first two rows
+
+    for (int r = y0 - 2; r <= y1 + 1; ++r) {
+        asm volatile("" : "+v"(bc), "+v"(bm), "+v"(bp), "+v"(fc), "+v"(fm), "+v"(fp));
+        // ---- the state pulls of row r + 1 and their phi ------------------------------------------------
+        M gn[9];
+        pull(r + 1, gn);
+        const M p1_p = sum9(gn);
+        if (act) R.phi1[(r + 1) & 3][cc] = p1_p;
+        const M *__restrict__ un = urow(r + 1);
+        const M uxp1 = ld_at(un, fc), uyp1 = ld_at(un + pitch, fc);
+        // ---- intermediate node (xi, r), level n + 1 -------------------------------------------------------
+        const int rw = __builtin_amdgcn_readfirstlane(wrapr(r));
+        M P[9] = {};
+        const auto rb1 = C::bits(d.f16, level + 1, (int64_t)rw * nx, (unsigned)xi);
+        if (inter) {
+            const M *__restrict__ uc = u + (int64_t)rw * 2 * pitch;
+            const M uxw = ld_at(uc, fm), uyw = ld_at(uc + pitch, fm), uxe = ld_at(uc, fp), uye = ld_at(uc + pitch, fp);
+            M Ax, Ay;
+            flux_aux<M>(R.phi1[r & 3][cc - 1], R.phi1[r & 3][cc + 1], p1_m, p1_p, uxw, uyw, uxe, uye, ux1, uy1, uxp1, uyp1,
+                        ux0, uy0, Ax, Ay);
+            const Relax<M> rr = HAS_K ? relax_from_k<M>(ld_at(kf + (int64_t)rw * pitch, fc), lam, rconst.w3) : rconst;
+            const M s = HAS_S ? ld_at(sf + (int64_t)rw * pitch, fc) : M(0);
+            collide<M, false>(gc, ux0, uy0, rr, Ax, Ay, s, P);
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                if (kPlane[i] >= 0) R.pop[r & 3][kPlane[i]][cc] = C::enc(P[i], i, d.f16, rb1);
+        }
+        const M p4 = C::dec(C::enc(P[4], 4, d.f16, rb1), 4, d.f16);
+        __syncthreads();
+        // ---- phi at n + 2 of node (xi, r - 1), from intermediate rows r - 2 .. r ----------------------------
+        M q_m1 = M(0);
+        M gq[9] = {};
+        if (r >= y0 && mid) {
+            const int y = r - 1;
+            gq[0] = p0_m;
+            gq[1] = C::dec(R.pop[y & 3][kPlane[1]][cl - 1], 1, d.f16);
+            gq[2] = p2_mm;
+            gq[3] = C::dec(R.pop[y & 3][kPlane[3]][cl + 1], 3, d.f16);
+            gq[4] = p4;
+            gq[5] = C::dec(R.pop[(y - 1) & 3][kPlane[5]][cl - 1], 5, d.f16);
+            gq[6] = C::dec(R.pop[(y - 1) & 3][kPlane[6]][cl + 1], 6, d.f16);
+            gq[7] = C::dec(R.pop[(y + 1) & 3][kPlane[7]][cl + 1], 7, d.f16);
+            gq[8] = C::dec(R.pop[(y + 1) & 3][kPlane[8]][cl - 1], 8, d.f16);
+            q_m1 = sum9(gq);
+            R.phi2[y & 3][cc] = q_m1;
+        }
+        // ---- output node (xi, r - 2), level n + 2 ---------------------------------------------------------
+        if (r >= y0 + 2 && live) {
+            const int y = __builtin_amdgcn_readfirstlane(wrapr(r - 2));
+            const M *__restrict__ uc = u + (int64_t)y * 2 * pitch;
+            const M uxw = ld_at(uc, fm), uyw = ld_at(uc + pitch, fm), uxe = ld_at(uc, fp), uye = ld_at(uc + pitch, fp);
+            M Ax, Ay;
+            flux_aux<M>(R.phi2[(r - 2) & 3][cc - 1], R.phi2[(r - 2) & 3][cc + 1], q_m3, q_m1, uxw, uyw, uxe, uye, ux3, uy3,
+                        ux1, uy1, ux2, uy2, Ax, Ay);
+            const Relax<M> rr = HAS_K ? relax_from_k<M>(ld_at(kf + (int64_t)y * pitch, fc), lam, rconst.w3) : rconst;
+            const M s = HAS_S ? ld_at(sf + (int64_t)y * pitch, fc) : M(0);
+            M Q[9];
+            collide<M, false>(g2, ux2, uy2, rr, Ax, Ay, s, Q);
+            T *__restrict__ out = dst + (int64_t)y * 9 * pitch;
+            const auto rb2 = C::bits(d.f16, level + 2, (int64_t)y * nx, (unsigned)xi);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                if constexpr (CST) st_at(out, bc + (unsigned)i * pb, C::enc(Q[i], i, d.f16, rb2));
+                else st_nt_at(out, bc + (unsigned)i * pb, C::enc(Q[i], i, d.f16, rb2));
+            }
+        }
+        // ---- roll the walk down one row -------------------------------------------------------------------
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            gc[i] = gn[i];
+            g2[i] = gq[i];
+        }
+        p1_m = p1_c;
+        p1_c = p1_p;
+        q_m3 = q_m2;
+        q_m2 = q_m1;
+        p2_mm = p2_m;
+        p2_m = C::dec(C::enc(P[2], 2, d.f16, rb1), 2, d.f16);
+        p0_m = C::dec(C::enc(P[0], 0, d.f16, rb1), 0, d.f16);
+        ux3 = ux2;
+        uy3 = uy2;
+        ux2 = ux1;
+        uy2 = uy1;
+        ux1 = ux0;
+        uy1 = uy0;
+        ux0 = uxp1;
+        uy0 = uyp1;
+    }
+}
+
 // One instance: block b -> tile (XCD-remapped as the launch says).
 template <int MODE, int AUX, bool HAS_K, bool HAS_S, bool MRT, int NW, bool CST>
 __global__ __launch_bounds__(64 * (NW + 1))
@@ -221,6 +427,17 @@ __attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW)))) void step2_kernel(co
     const int t = tile_of_block(blockIdx.x, gridDim.x, d.lcf.xcd_remap, ntx, d.lcf.xcd_rows);
     __shared__ Ring<MODE, NW> ring;
     fused_tile<MODE, AUX, HAS_K, HAS_S, MRT, NW, CST>(d, a.parity, t, ring);
+}
+
+// One instance, flux form: block b -> tile.
+template <int MODE, bool HAS_K, bool HAS_S, int NW, bool CST>
+__global__ __launch_bounds__(64 * (NW + 1)) void flux2_kernel(const StepArgs a)
+{
+    const InstDesc &d = a.d;
+    const int ntx = (d.L.nx + 64 * NW - 1) / (64 * NW);
+    const int t = tile_of_block(blockIdx.x, gridDim.x, d.lcf.xcd_remap, ntx, d.lcf.xcd_rows);
+    __shared__ FluxRings<MODE, NW> rings;
+    flux_tile<MODE, HAS_K, HAS_S, NW, CST>(d, a.parity, t, rings);
 }
 
 // Many instances (periodic D2Q9 TRT-R, one storage form and aux form): each block runs a range of
@@ -286,13 +503,41 @@ hipError_t launch_fused_aux(const StepArgs &a, hipStream_t st)
     return a.d.w3 != 0.0 ? hipErrorInvalidValue : launch_fused_var<MODE, AUX, false>(a, st);
 }
 
+template <int MODE, int NW, bool CST>
+hipError_t launch_flux2_nw(const StepArgs &a, hipStream_t st)
+{
+    const int W = 64 * NW, H = a.d.lcf.rows;
+    const int nblocks = ((a.d.L.nx + W - 1) / W) * ((a.d.L.ny + H - 1) / H);
+    const dim3 block(64 * (NW + 1));
+    const bool hk = a.d.has_k, hs = a.d.has_s;
+    if (hk && hs) flux2_kernel<MODE, true, true, NW, CST><<<nblocks, block, 0, st>>>(a);
+    else if (hk) flux2_kernel<MODE, true, false, NW, CST><<<nblocks, block, 0, st>>>(a);
+    else if (hs) flux2_kernel<MODE, false, true, NW, CST><<<nblocks, block, 0, st>>>(a);
+    else flux2_kernel<MODE, false, false, NW, CST><<<nblocks, block, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+// The flux form: TRT-R, tiles of 128 or 256 columns.
+template <int MODE>
+hipError_t launch_flux2(const StepArgs &a, hipStream_t st)
+{
+    if (a.d.w3 != 0.0) return hipErrorInvalidValue;
+    const bool cst = a.d.lcf.stores == 1;
+    switch (a.d.lcf.fuse_width) {
+    case 128: return cst ? launch_flux2_nw<MODE, 2, true>(a, st) : launch_flux2_nw<MODE, 2, false>(a, st);
+    case 256: return cst ? launch_flux2_nw<MODE, 4, true>(a, st) : launch_flux2_nw<MODE, 4, false>(a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <int MODE>
 hipError_t launch_fused_mode(int aux, const StepArgs &a, hipStream_t st)
 {
     switch (aux) {
     case 0: return launch_fused_aux<MODE, 0>(a, st);
+    case 1: return launch_flux2<MODE>(a, st);
     case 2: return launch_fused_aux<MODE, 2>(a, st);
-    default: return hipErrorInvalidValue;  // the flux form needs phi at neighbours of the same step
+    default: return hipErrorInvalidValue;
     }
 }
 

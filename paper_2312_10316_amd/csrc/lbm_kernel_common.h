@@ -34,6 +34,21 @@ struct ModeTraits<MODE_F16SR_F32> {
     using M = float;
 };
 
+// The flux form of the auxiliary term at one node (Sec. 2.3): d_b(phi u_a u_b) - u_a d_b(phi u_b) by
+// central differences, from phi and u at the west, east, south and north neighbours (same time level)
+// and u at the node.  Every kernel that uses the flux form calls this one expression sequence, so they
+// all round alike.
+template <class M>
+__device__ __forceinline__ void flux_aux(M pw, M pe, M ps, M pn, M uxw, M uyw, M uxe, M uye, M uxs, M uys, M uxn,
+                                         M uyn, M uxc, M uyc, M &Ax, M &Ay)
+{
+    const M fwx = pw * uxw, fex = pe * uxe;  // phi u_x at the west and east neighbours
+    const M fsy = ps * uys, fny = pn * uyn;  // phi u_y at the south and north neighbours
+    const M div = (fex - fwx) * M(0.5) + (fny - fsy) * M(0.5);
+    Ax = (fex * uxe - fwx * uxw) * M(0.5) + (fny * uxn - fsy * uxs) * M(0.5) - uxc * div;
+    Ay = (fex * uye - fwx * uyw) * M(0.5) + (fny * uyn - fsy * uys) * M(0.5) - uyc * div;
+}
+
 // Time level of the state a launch reads (stochastic rounding only; 0 otherwise).  The counter pair
 // lives in device memory so that graph replays see the level advance: a launch reads clock[parity],
 // which no thread of it writes, and one thread of it writes clock[parity ^ 1] for the next launch.

@@ -409,11 +409,8 @@ __device__ __forceinline__ void process_tile_flux(const InstDesc &a, int parity,
             if ((int)lane == last) pe = phe;
         }
         const M uxw = ld_at(uc, fm), uyw = ld_at(uc + pitch, fm), uxe = ld_at(uc, fp), uye = ld_at(uc + pitch, fp);
-        const M fwx = pw * uxw, fex = pe * uxe;          // phi u_x at the west and east neighbours
-        const M fsy = phi_m * uy_m, fny = phi_p * uy_p;  // phi u_y at the south and north neighbours
-        const M div = (fex - fwx) * M(0.5) + (fny - fsy) * M(0.5);
-        const M Ax = (fex * uxe - fwx * uxw) * M(0.5) + (fny * ux_p - fsy * ux_m) * M(0.5) - ux_c * div;
-        const M Ay = (fex * uye - fwx * uyw) * M(0.5) + (fny * uy_p - fsy * uy_m) * M(0.5) - uy_c * div;
+        M Ax, Ay;
+        flux_aux<M>(pw, pe, phi_m, phi_p, uxw, uyw, uxe, uye, ux_m, uy_m, ux_p, uy_p, ux_c, uy_c, Ax, Ay);
         const Relax<M> r = HAS_K ? relax_from_k<M>(ld_at(kf + (int64_t)y * pitch, fc), lam, rconst.w3) : rconst;
         const M s = HAS_S ? ld_at(sf + (int64_t)y * pitch, fc) : M(0);
         M P[9];

@@ -123,12 +123,13 @@ def test_fused_rejects_what_it_does_not_cover():
     def mk(**kw):
         return lbm.make_params(64, 40, dx, dt, 0.25, 2e-3, "f32", **kw)
 
-    for params, inst in (([mk(aux=lbm.LBM_AUX_FLUX)], -1), ([mk(boundary=lbm.LBM_BC_NEE)], -1),
-                         ([mk(boundary=lbm.LBM_BC_WALLS)], -1), ([mk(), mk()], 1), ([mk(), mk(tau3=0.7)], -1),
-                         ([mk(tau3=0.7)], -1)):
+    for params, inst, width in (([mk(boundary=lbm.LBM_BC_NEE)], -1, 256), ([mk(boundary=lbm.LBM_BC_WALLS)], -1, 256),
+                                ([mk(), mk()], 1, 256), ([mk(), mk(tau3=0.7)], -1, 256), ([mk(tau3=0.7)], -1, 256),
+                                ([mk(aux=lbm.LBM_AUX_FLUX)], -1, 512),
+                                ([mk(aux=lbm.LBM_AUX_FLUX), mk(aux=lbm.LBM_AUX_FLUX)], -1, 256)):
         s = Solver([(p, fields) for p in params])
         with pytest.raises(lbm.LbmError) as ei:
-            s.set_launch(8, 1, inst=inst, tile_width=256, fuse=2)
+            s.set_launch(8, 1, inst=inst, tile_width=width, fuse=2)
         assert ei.value.status == lbm.LBM_E_ARG
         s.close()
     s = Solver([(mk(), fields)])
@@ -140,3 +141,71 @@ def test_fused_rejects_what_it_does_not_cover():
             s.set_launch(args.pop("rows"), args.pop("xcd_remap"), **args)
         assert ei.value.status == lbm.LBM_E_ARG, kw
     s.close()
+
+
+FLUX_SHAPES = [(256, 16, 1, 0, 1), (128, 3, 0, 0, 0), (256, 1, 2, 0, 0), (128, 64, 3, 2, 1)]
+
+
+@pytest.mark.parametrize("mode", ["f64", "f64s_f32m", "f32", "f16s", "f16sr"])
+@pytest.mark.parametrize("nx,ny", [(70, 45), (3, 3), (64, 5), (300, 7), (513, 130), (130, 4)])
+def test_fused_flux_form_equals_single_steps(mode, nx, ny):
+    """The flux form's two-step tiles (three frame columns each side, phi rings at both levels):
+    bitwise the one-step flux kernel, for four tile shapes, at odd and even step counts."""
+    for k, shape in enumerate(FLUX_SHAPES[:2] if nx * ny < 1000 else FLUX_SHAPES):
+        one, two, _ = contexts(mode, nx, ny, seed=nx + ny + k, aux=lbm.LBM_AUX_FLUX, shape=shape)
+        for n in (2, 1, 5, 70, 4):
+            one.step(n)
+            two.step(n)
+            assert torch.equal(one.state_save(), two.state_save()), (shape, n)
+        one.close()
+        two.close()
+
+
+@pytest.mark.parametrize("var,tau3,src", [(False, 0.0, False), (True, 1.0, True), (False, 0.0, True)])
+@pytest.mark.parametrize("mode", ["f64", "f32"])
+def test_fused_flux_form_variants(mode, var, tau3, src):
+    """Constant D, tau3 = 1 (TRT-R written as MRT-R) and a per-call source in the flux form."""
+    one, two, (p, f, dx, dt) = contexts(mode, 200, 90, seed=17, aux=lbm.LBM_AUX_FLUX, var=var, tau3=tau3,
+                                        shape=(256, 8, 1, 0, 0))
+    rng = np.random.default_rng(7)
+    S = dev(0.05 * rng.uniform(-1, 1, (90, 200)))
+    for n in (4, 3, 6):
+        kw = dict(S=[S], dSdt=[S * 0.25]) if src else {}
+        one.step(n, **kw)
+        two.step(n, **kw)
+        assert torch.equal(one.state_save(), two.state_save()), n
+    one.close()
+    two.close()
+
+
+def test_fused_flux_form_fp64_matches_the_oracle():
+    nx, ny, steps = 70, 45, 26
+    one, two, (p, f, dx, dt) = contexts("f64", nx, ny, seed=5, aux=lbm.LBM_AUX_FLUX, shape=(128, 5, 0, 0, 0))
+    two.step(steps)
+    op = O.Problem(nx, ny, dx, dt, 0.25, 2e-3, O.AUX_FLUX)
+    g = O.run(op, O.init(op, f["phi0"], f["ux"], f["uy"]), steps, f["ux"], f["uy"], f["D"])
+    got = two.populations().cpu().numpy()
+    assert np.abs(got - g).max() <= 1e-12 * np.abs(g).max()
+    one.close()
+    two.close()
+
+
+@pytest.mark.parametrize("mode", ["f32", "f64"])
+def test_fused_flux_form_full_size_equals_single_steps(mode):
+    """8192^2 with D(x) in the flux form's default two-step shape: four steps, bitwise."""
+    n = 8192
+    cfg = W.PulseConfig(N=n, steps=4, D_variable=True)
+    f = W.rotating_pulse(cfg)
+    fields = {k: dev(f[k]) for k in ("phi0", "ux", "uy", "D")}
+    p = lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, mode, lbm.LBM_AUX_FLUX)
+    print(f"fused flux full size: {mode} {n}^2", flush=True)
+    one = Solver([(p, fields)])
+    one.set_launch(2, 1, tile_width=256, stores=0)
+    one.step(4)
+    ref = one.state_save()
+    one.close()
+    two = Solver([(p, fields)])
+    assert two.get_launch()["fuse"] == 2
+    two.step(4)
+    assert torch.equal(two.state_save(), ref)
+    two.close()

@@ -488,7 +488,7 @@ def test_launch_defaults_and_bad_launch_shapes():
         assert s.get_launch() == w, mode
         s.close()
     s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, "f32", lbm.LBM_AUX_FLUX), fields)])
-    assert s.get_launch() == launch(2, 1, 256, 0)  # the flux form: two rows per wave
+    assert s.get_launch() == launch(4, 1, 128, 0, 0, 1, 2)  # the flux form: two steps per launch, 128 columns
     s.close()
     s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, "f32", tau3=0.7), fields)])
     assert s.get_launch() == launch(1, 1, 256, 0)  # MRT-R: one step per launch
