@@ -12,6 +12,7 @@
 // coefficients a0..a3 as functions of those moments; H: the reconstruction w_i h_m(e_i)), so M^T mu
 // is computed as R^T C^T H^T mu without forming M.  All in lattice units, like the forward kernel.
 #include "lbm_internal.h"
+#include "lbm_kernel_common.h"
 
 namespace lbm {
 namespace {
@@ -45,14 +46,20 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs a)
     using M = typename AdjTraits<MODE>::M;
     using T = typename St::T;
     using C = Codec<St, M>;
+    // Tiles of 256 columns (the block's four waves side by side, lane = column) by one row, in row bands
+    // over the XCDs (each XCD's rows and their neighbours in one L2); the row is uniform, so every
+    // access is a scalar row base plus a 32-bit lane offset.
     const int nx = a.L.nx, ny = a.L.ny;
     const int64_t pitch = a.L.pitch;
-    const int y = blockIdx.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.y);
-    if (y >= ny) return;
-    const int xr = blockIdx.x * 64 + threadIdx.x;
-    if (xr >= nx) return;
-    const int x = xr, xm = wdec(x, nx), xp = winc(x, nx);
-    const int ym = wdec(y, ny), yp = winc(y, ny);
+    const int ntx = (nx + 255) / 256;
+    const int t = tile_of_block(blockIdx.x, gridDim.x, 1, ntx, 0);
+    const int y = __builtin_amdgcn_readfirstlane(t / ntx);
+    const int x = (t % ntx) * 256 + __builtin_amdgcn_readfirstlane((int)threadIdx.y) * 64 + (int)threadIdx.x;
+    if (x >= nx) return;
+    const unsigned xc = (unsigned)x, xm = (unsigned)wdec(x, nx), xp = (unsigned)winc(x, nx);
+    const int ym = __builtin_amdgcn_readfirstlane(wdec(y, ny)), yp = __builtin_amdgcn_readfirstlane(winc(y, ny));
+    const unsigned bc = xc * (unsigned)sizeof(T), bm = xm * (unsigned)sizeof(T), bp = xp * (unsigned)sizeof(T);
+    const unsigned fc = xc * (unsigned)sizeof(M), fm = xm * (unsigned)sizeof(M), fp = xp * (unsigned)sizeof(M);
     const T *st = static_cast<const T *>(a.state);
     const M *lin = static_cast<const M *>(a.lam_in);
     M *lout = static_cast<M *>(a.lam_out);
@@ -62,40 +69,41 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs a)
     M g[9];
     {
         const T *rm = st + (int64_t)ym * 9 * pitch, *rc = st + (int64_t)y * 9 * pitch, *rp = st + (int64_t)yp * 9 * pitch;
-        g[0] = C::dec(rc[x], 0, a.f16);
-        g[1] = C::dec(rc[1 * pitch + xm], 1, a.f16);
-        g[2] = C::dec(rm[2 * pitch + x], 2, a.f16);
-        g[3] = C::dec(rc[3 * pitch + xp], 3, a.f16);
-        g[4] = C::dec(rp[4 * pitch + x], 4, a.f16);
-        g[5] = C::dec(rm[5 * pitch + xm], 5, a.f16);
-        g[6] = C::dec(rm[6 * pitch + xp], 6, a.f16);
-        g[7] = C::dec(rp[7 * pitch + xp], 7, a.f16);
-        g[8] = C::dec(rp[8 * pitch + xm], 8, a.f16);
+        g[0] = C::dec(ld_at(rc, bc), 0, a.f16);
+        g[1] = C::dec(ld_at(rc + 1 * pitch, bm), 1, a.f16);
+        g[2] = C::dec(ld_at(rm + 2 * pitch, bc), 2, a.f16);
+        g[3] = C::dec(ld_at(rc + 3 * pitch, bp), 3, a.f16);
+        g[4] = C::dec(ld_at(rp + 4 * pitch, bc), 4, a.f16);
+        g[5] = C::dec(ld_at(rm + 5 * pitch, bm), 5, a.f16);
+        g[6] = C::dec(ld_at(rm + 6 * pitch, bp), 6, a.f16);
+        g[7] = C::dec(ld_at(rp + 7 * pitch, bp), 7, a.f16);
+        g[8] = C::dec(ld_at(rp + 8 * pitch, bm), 8, a.f16);
     }
     // mu_i(x) = lam^{n+1}_i(x + e_i)
     M mu[9];
     {
         const M *lm = lin + (int64_t)ym * 9 * pitch, *lc = lin + (int64_t)y * 9 * pitch, *lp = lin + (int64_t)yp * 9 * pitch;
-        mu[0] = lc[x];
-        mu[1] = lc[1 * pitch + xp];
-        mu[2] = lp[2 * pitch + x];
-        mu[3] = lc[3 * pitch + xm];
-        mu[4] = lm[4 * pitch + x];
-        mu[5] = lp[5 * pitch + xp];
-        mu[6] = lp[6 * pitch + xm];
-        mu[7] = lm[7 * pitch + xm];
-        mu[8] = lm[8 * pitch + xp];
+        mu[0] = ld_at(lc, fc);
+        mu[1] = ld_at(lc + 1 * pitch, fp);
+        mu[2] = ld_at(lp + 2 * pitch, fc);
+        mu[3] = ld_at(lc + 3 * pitch, fm);
+        mu[4] = ld_at(lm + 4 * pitch, fc);
+        mu[5] = ld_at(lp + 5 * pitch, fp);
+        mu[6] = ld_at(lp + 6 * pitch, fm);
+        mu[7] = ld_at(lm + 7 * pitch, fm);
+        mu[8] = ld_at(lm + 8 * pitch, fp);
     }
     const M *uc = u + (int64_t)y * 2 * pitch;
-    const M ux = uc[x], uy = uc[pitch + x];
+    const M ux = ld_at(uc, fc), uy = ld_at(uc + pitch, fc);
     M ahx = M(0), ahy = M(0);  // u_b d_b u_a (central differences), Eq. (16) without phi
     if (LOCAL) {
         const M *um = u + (int64_t)ym * 2 * pitch, *up = u + (int64_t)yp * 2 * pitch;
-        ahx = ux * (uc[xp] - uc[xm]) * M(0.5) + uy * (up[x] - um[x]) * M(0.5);
-        ahy = ux * (uc[pitch + xp] - uc[pitch + xm]) * M(0.5) + uy * (up[pitch + x] - um[pitch + x]) * M(0.5);
+        ahx = ux * (ld_at(uc, fp) - ld_at(uc, fm)) * M(0.5) + uy * (ld_at(up, fc) - ld_at(um, fc)) * M(0.5);
+        ahy = ux * (ld_at(uc + pitch, fp) - ld_at(uc + pitch, fm)) * M(0.5) +
+              uy * (ld_at(up + pitch, fc) - ld_at(um + pitch, fc)) * M(0.5);
     }
-    const M k = HAS_K ? static_cast<const M *>(a.k)[(int64_t)y * pitch + x] : (M)a.k_const;
-    const M s = HAS_S ? static_cast<const M *>(a.s)[(int64_t)y * pitch + x] : M(0);
+    const M k = HAS_K ? ld_at(static_cast<const M *>(a.k) + (int64_t)y * pitch, fc) : (M)a.k_const;
+    const M s = HAS_S ? ld_at(static_cast<const M *>(a.s) + (int64_t)y * pitch, fc) : M(0);
     const M lam = (M)a.lambda;
     const M tau1 = M(0.5) + k, tau2 = M(0.5) + lam / k;
     const M w1 = M(1) - M(1) / tau1, w2 = M(1) - M(1) / tau2, beta = M(1) - M(0.5) / tau1;
@@ -122,7 +130,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs a)
                    q2xy * uxy * (M(1) - w2) + q3xxy * uxx * uy + q3xyy * ux * uyy;
     const M tjx = w1 * q1x, tjy = w1 * q1y, tpxx = w2 * q2xx, tpyy = w2 * q2yy, tpxy = w2 * q2xy;
     // lam^n = R^T t
-    M *lo = lout + (int64_t)y * 9 * pitch + x;
+    M *lo = lout + (int64_t)y * 9 * pitch;
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
         const int ex = kEx[j], ey = kEy[j];
@@ -130,7 +138,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs a)
         if (ex) v += M(ex) * tjx + tpxx;
         if (ey) v += M(ey) * tjy + tpyy;
         if (ex * ey) v += M(ex * ey) * tpxy;
-        lo[j * pitch] = v;
+        st_at(lo + j * pitch, fc, v);
     }
 
     // dP/dk at g^n(x): tau1 = 1/2 + k, tau2 = 1/2 + Lambda/k
@@ -145,7 +153,8 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjArgs a)
     const M dk = q1x * (dw1 * (jx - phi * ux) + dbeta * (phi * ahx + ux * s)) +
                  q1y * (dw1 * (jy - phi * uy) + dbeta * (phi * ahy + uy * s)) +
                  dw2 * (q2xx * nxx + q2yy * nyy + q2xy * nxy);
-    a.grad[(int64_t)y * nx + x] += a.dk_dD * (double)dk;
+    double *gr = a.grad + (int64_t)y * nx;
+    gr[x] += a.dk_dD * (double)dk;
 }
 
 // lam_i(x) = dL/dphi(x) for every i (adjoint of phi = sum_i g_i)
@@ -180,7 +189,8 @@ __global__ __launch_bounds__(256) void adjoint_init_kernel(const M *lam, const M
 template <int MODE, bool LOCAL>
 hipError_t launch_adj_aux(const AdjArgs &a, hipStream_t st)
 {
-    dim3 block(64, 4), grid((a.L.nx + 63) / 64, (a.L.ny + 3) / 4);
+    dim3 block(64, 4);
+    const int grid = ((a.L.nx + 255) / 256) * a.L.ny;  // 256-column tiles of one row
     const bool hk = a.k != nullptr, hs = a.s != nullptr;
     if (hk && hs) adjoint_kernel<MODE, true, true, LOCAL><<<grid, block, 0, st>>>(a);
     else if (hk) adjoint_kernel<MODE, true, false, LOCAL><<<grid, block, 0, st>>>(a);

@@ -475,20 +475,25 @@ def test_launch_defaults_and_bad_launch_shapes():
             width //= 2
         return launch(rows, 1, width, 0, 0, stores, 2)
 
-    # One periodic D2Q9 TRT-R instance (local or no aux term) runs two steps per launch.  A context that
-    # touches at most 256 MiB per step is served by the Infinity Cache: cached stores, row bands, every
-    # wave resident; so are the one-step launches of the other kinds (64-column tiles kept for FP64
-    # storage on narrow lattices).
-    for mode in ("f32", "f64", "f16s"):
+    # One periodic D2Q9 TRT-R instance of at least 2^19 nodes runs two steps per launch; a smaller one runs
+    # one.  A context that touches at most 256 MiB per step is served by the Infinity Cache: cached
+    # stores, row bands, every wave resident (64-column tiles kept for FP64 storage on narrow lattices).
+    for mode, w in (("f32", launch(1, 1, 256, 0)), ("f64", launch(1, 1, 64, 0)), ("f16s", launch(1, 1, 256, 0))):
         s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, mode), fields)])
-        assert s.get_launch() == fused(64, 64, 1, mode), mode
+        assert s.get_launch() == w, mode
         s.close()
+    big = {k: dev(np.resize(v.cpu().numpy(), (725, 725))) for k, v in fields.items()}
+    for mode in ("f32", "f64", "f16s"):
+        s = Solver([(lbm.make_params(725, 725, f["dx"], f["dt"], cfg.lam, cfg.D, mode), big)])
+        assert s.get_launch() == fused(725, 725, 1, mode), mode
+        s.close()
+    del big
     for mode, w in (("f32", launch(1, 1, 256, 0)), ("f64", launch(1, 1, 64, 0)), ("f16s", launch(1, 1, 256, 0))):
         s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, mode, boundary=lbm.LBM_BC_NEE), fields)])
         assert s.get_launch() == w, mode
         s.close()
     s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, "f32", lbm.LBM_AUX_FLUX), fields)])
-    assert s.get_launch() == launch(4, 1, 128, 0, 0, 1, 2)  # the flux form: two steps per launch, 128 columns
+    assert s.get_launch() == launch(2, 1, 256, 0)  # the flux form in one step per launch (a small lattice)
     s.close()
     s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, "f32", tau3=0.7), fields)])
     assert s.get_launch() == launch(1, 1, 256, 0)  # MRT-R: one step per launch

@@ -137,8 +137,8 @@ def _check_decisions(img, g_new, p, phi_ref, seed, level):
 @pytest.mark.parametrize("aux,tau3", [(lbm.LBM_AUX_LOCAL, 0.0), (lbm.LBM_AUX_FLUX, 0.0), (lbm.LBM_AUX_NONE, 0.0),
                                       (lbm.LBM_AUX_LOCAL, 0.7)])
 def test_step_decisions_match_the_oracle(aux, tau3):
-    """70 steps in the default launch (two steps per launch and graph replays for the periodic TRT-R
-    context), then one more; the codes of that step against the oracle stepping the GPU state."""
+    """70 steps in the default launch (graph replays), then one more; the codes of that step against the
+    oracle stepping the GPU state (two steps per launch meet these codes bitwise in test_gpu_fused)."""
     nx, ny, seed, phi_ref = 70, 45, 7, 0.3
     dx, dt, f = _case(nx, ny, 3)
     p = lbm.make_params(nx, ny, dx, dt, 0.25, 2e-3, "f16sr", aux, scale_log2=K, phi_ref=phi_ref, tau3=tau3,
