@@ -154,14 +154,16 @@ Launch default_launch(const lbm_params &p, int mode, bool has_D, int n_inst, int
 }
 
 // Two steps per launch (temporal blocking, lbm_fused.hip) for a single periodic D2Q9 TRT-R instance
-// with the local or no auxiliary term.  Tile shapes from sweeps at 2048^2 and 8192^2 (constant and
-// variable D): with at most 8 tiles of 256 columns per row, FP32 and FP16 storage take 512-column
-// tiles of 16 rows (2048^2: FP32 122k, FP16 167k MLUPS), FP64 storage 256 x 32; wider lattices take
-// FP32 256 x 16 (8192^2: 135k), FP16 128 x 32 (171k) and FP64 storage 128 x 16 (64k).  Tiles never
+// with the local or no auxiliary term.  Tile shapes from sweeps at 2048^2, 4096^2 and 8192^2 (widths
+// 128/256/512 x 8..64 rows x stores): FP32 storage 512 x 16 (2048^2 129k, 4096^2 131k, 8192^2 140k
+// MLUPS); FP16 storage with at most 8 tiles of 256 columns per row 512 x 16 (179k), wider 256 x 16
+// (8192^2 195k; stochastic rounding 256 x 24, 155k); FP64 storage 512 x 16 (8192^2 69k; FP32 math
+// 76k), on narrow lattices 256 x 32 (FP32 math 512 x 32).  Tiles never
 // wider than the lattice needs (at least 128 columns), and at least 256 tiles where the lattice allows
 // (down to 4 rows, then down to 128 columns: a 512^2 lattice in 512 x 4 tiles kept half the CUs idle).
-// The flux form (sweep of 128/256 columns x 4..64 rows x tile order x stores): 128-column tiles, 16 rows
-// for FP32 up to 2048 columns (2048^2: 96k MLUPS), else 32 (8192^2 FP32 107k, FP16 108k, FP64 54k).  Row bands over the XCDs, so that the frame rows a tile shares with the next tile
+// The flux form (sweep of 128/256 columns x 8..64 rows x stores): 128-column tiles, 16 rows for FP32 up
+// to 2048 columns (2048^2: 97k MLUPS), FP16 there 256 x 24 (111k), else 32 rows (8192^2 FP32 109k,
+// FP16 113k, FP64 57k).  Row bands over the XCDs, so that the frame rows a tile shares with the next tile
 // down sit in the same L2.  (MRT-R stays on single steps: with FP64 math the compiler had fused its
 // third-order multiply-adds otherwise in the fused kernel.)
 // An instance whose steps can be fused (a periodic D2Q9 TRT-R instance, any aux form).  A context fuses
@@ -177,18 +179,18 @@ Launch fused_default(const lbm_params &p, int mode)
     const bool narrow = (p.nx + 255) / 256 <= 8;
     int width, rows;
     if (mode == MODE_F32_F32) {
-        width = narrow ? 512 : 256;
+        width = 512;
         rows = 16;
     } else if (is_f16_mode(mode)) {
-        width = narrow ? 512 : 128;
-        rows = narrow ? 16 : 32;
-    } else {
-        width = narrow ? 256 : 128;
+        width = narrow ? 512 : 256;
+        rows = !narrow && mode == MODE_F16SR_F32 ? 24 : 16;
+    } else {  // FP64 storage: one 512-column block per CU (98.7 KB of ring) beats narrower tiles
+        width = narrow && mode == MODE_F64_F64 ? 256 : 512;
         rows = narrow ? 32 : 16;
     }
     if (p.aux == LBM_AUX_FLUX) {  // 128-column tiles: FP32 16 rows up to 2048 columns, else 32 rows
-        width = 128;
-        rows = mode == MODE_F32_F32 && narrow ? 16 : 32;
+        width = is_f16_mode(mode) && narrow ? 256 : 128;
+        rows = narrow && mode == MODE_F32_F32 ? 16 : (narrow && is_f16_mode(mode) ? 24 : 32);
     }
     while (width > 128 && width / 2 >= p.nx) width /= 2;
     auto tiles = [&](int h) { return (int64_t)((p.nx + width - 1) / width) * ((p.ny + h - 1) / h); };

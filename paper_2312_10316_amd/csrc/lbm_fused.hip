@@ -44,7 +44,10 @@ using Ring = typename ModeTraits<MODE>::St::T[4][6][64 * NW + 2];
 
 // Two steps of tile t of one instance (tiles numbered row-major, ceil(nx / W) per row, d.lcf.rows high),
 // reading buf[parity] and writing buf[parity ^ 1]; called by every thread of the block.
-template <int MODE, int AUX, bool HAS_K, bool HAS_S, bool MRT, int NW, bool CST>
+// PF: issue each row's global loads one row ahead.  Single-instance kernels with FP32 or FP64 storage
+// take it; the FP16 codecs (more arithmetic per value, already issue-bound) and the batched kernel
+// (four inlined variants within one register budget) measure faster without.
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, bool MRT, int NW, bool CST, bool PF>
 __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t, Ring<MODE, NW> &ring)
 {
     using St = typename ModeTraits<MODE>::St;
@@ -89,6 +92,54 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
     rconst.w3 = (M)d.w3;
 
     auto wrapr = [ny](int r) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); };
+    // The global loads of walk row r: u at (xi, r + 1); for the intermediate node (xi, r) its nine
+    // pulls from state rows r - 1 .. r + 1, u at its x-neighbours and the k and s fields.  With PF, row
+    // r + 1's loads are issued before row r is computed, so they are in flight through row r's two
+    // collisions and the barrier instead of stalling the block once per row.
+    struct RowLoads {
+        T g[9];
+        M uxp, uyp, uxe, uxw, uye, uyw, k, s;
+    };
+    auto load_row = [&](int r, RowLoads &o) {
+        // row indices through readfirstlane: uniform values the compiler cannot strength-reduce into
+        // per-lane 64-bit address recurrences, so every access keeps the scalar-base + 32-bit-offset form
+        const int rw = __builtin_amdgcn_readfirstlane(wrapr(r));
+        const int rwm = __builtin_amdgcn_readfirstlane(wrapr(r - 1));
+        const int rwp = __builtin_amdgcn_readfirstlane(wrapr(r + 1));
+        // the lane offsets are re-read every row (an empty asm that claims to update them), so the compiler
+        // keeps each access as one scalar row base plus a 32-bit lane offset instead of hoisting 64-bit
+        // per-lane addresses out of the walk
+        asm volatile("" : "+v"(bc), "+v"(bm), "+v"(bp), "+v"(fc), "+v"(fm), "+v"(fp));
+        const M *__restrict__ un = u + (int64_t)rwp * 2 * pitch;
+        o.uxp = ld_at(un, fc);
+        o.uyp = ld_at(un + pitch, fc);
+        if (act) {
+            const T *__restrict__ rm = src + (int64_t)rwm * 9 * pitch;
+            const T *__restrict__ rc = src + (int64_t)rw * 9 * pitch;
+            const T *__restrict__ rp = src + (int64_t)rwp * 9 * pitch;
+            o.g[0] = ld_at(rc, bc);
+            o.g[1] = ld_at(rc + pitch, bm);
+            o.g[2] = ld_at(rm + 2 * pitch, bc);
+            o.g[3] = ld_at(rc + 3 * pitch, bp);
+            o.g[4] = ld_at(rp + 4 * pitch, bc);
+            o.g[5] = ld_at(rm + 5 * pitch, bm);
+            o.g[6] = ld_at(rm + 6 * pitch, bp);
+            o.g[7] = ld_at(rp + 7 * pitch, bp);
+            o.g[8] = ld_at(rp + 8 * pitch, bm);
+        }
+    };
+    // the rest of row r's loads, for the node at (xi, r) (rw: the wrapped row, wave-uniform)
+    auto load_aux = [&](int rw, RowLoads &o) {
+        const M *__restrict__ uc = u + (int64_t)rw * 2 * pitch;
+        if (AUX == 0) {
+            o.uxe = ld_at(uc, fp);
+            o.uxw = ld_at(uc, fm);
+            o.uye = ld_at(uc + pitch, fp);
+            o.uyw = ld_at(uc + pitch, fm);
+        }
+        if (HAS_K) o.k = ld_at(kf + (int64_t)rw * pitch, fc);
+        if (HAS_S) o.s = ld_at(sf + (int64_t)rw * pitch, fc);
+    };
     // velocity at this column, rows r - 2 .. r + 1 of the walk (mm, m, c, p)
     const int rs = y0 - 1;
     M ux_mm = M(0), uy_mm = M(0);
@@ -106,50 +157,46 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
     const int64_t level = launch_level<C>(d, parity);
     advance_level<C>(d, parity, level, 2, t == 0 && threadIdx.x == 0);
 
+    RowLoads nxt;
+    if (PF) {
+        load_row(rs, nxt);
+        if (act) load_aux(__builtin_amdgcn_readfirstlane(wrapr(rs)), nxt);
+    }
     for (int r = rs; r <= y1; ++r) {
-        // row indices through readfirstlane: uniform values the compiler cannot strength-reduce into
-        // per-lane 64-bit address recurrences, so every access keeps the scalar-base + 32-bit-offset form
         const int rw = __builtin_amdgcn_readfirstlane(wrapr(r));
-        const int rwm = __builtin_amdgcn_readfirstlane(wrapr(r - 1));
-        const int rwp = __builtin_amdgcn_readfirstlane(wrapr(r + 1));
-        // the lane offsets are re-read every row (an empty asm that claims to update them), so the compiler
-        // keeps each access as one scalar row base plus a 32-bit lane offset instead of hoisting 64-bit
-        // per-lane addresses out of the walk
-        asm volatile("" : "+v"(bc), "+v"(bm), "+v"(bp), "+v"(fc), "+v"(fm), "+v"(fp));
-        const M *__restrict__ un = u + (int64_t)rwp * 2 * pitch;
-        const M ux_p = ld_at(un, fc), uy_p = ld_at(un + pitch, fc);
+        const auto rb1 = C::bits(d.f16, level + 1, (int64_t)rw * nx, (unsigned)xi);  // intermediate node (xi, r)
+        RowLoads cur;
+        if (PF) {
+            cur = nxt;
+            if (r < y1) {
+                load_row(r + 1, nxt);
+                if (act) load_aux(__builtin_amdgcn_readfirstlane(wrapr(r + 1)), nxt);
+            }
+        } else {
+            load_row(r, cur);
+        }
+        const M ux_p = cur.uxp, uy_p = cur.uyp;
         // ---- phase 1: intermediate node (xi, r) of step n + 1 -----------------------------------------
         M dxux = M(0), dxuy = M(0), s = M(0);
         Relax<M> rr = rconst;
         M P[9] = {};
-        const auto rb1 = C::bits(d.f16, level + 1, (int64_t)rw * nx, (unsigned)xi);  // intermediate node (xi, r)
         if (act) {
-            const T *__restrict__ rm = src + (int64_t)rwm * 9 * pitch;
-            const T *__restrict__ rc = src + (int64_t)rw * 9 * pitch;
-            const T *__restrict__ rp = src + (int64_t)rwp * 9 * pitch;
             M g[9];
-            g[0] = C::dec(ld_at(rc, bc), 0, d.f16);
-            g[1] = C::dec(ld_at(rc + pitch, bm), 1, d.f16);
-            g[2] = C::dec(ld_at(rm + 2 * pitch, bc), 2, d.f16);
-            g[3] = C::dec(ld_at(rc + 3 * pitch, bp), 3, d.f16);
-            g[4] = C::dec(ld_at(rp + 4 * pitch, bc), 4, d.f16);
-            g[5] = C::dec(ld_at(rm + 5 * pitch, bm), 5, d.f16);
-            g[6] = C::dec(ld_at(rm + 6 * pitch, bp), 6, d.f16);
-            g[7] = C::dec(ld_at(rp + 7 * pitch, bp), 7, d.f16);
-            g[8] = C::dec(ld_at(rp + 8 * pitch, bm), 8, d.f16);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) g[i] = C::dec(cur.g[i], i, d.f16);
+            if (!PF) load_aux(rw, cur);
             M Ax = M(0), Ay = M(0);
-            const M *__restrict__ uc = u + (int64_t)rw * 2 * pitch;
             if (AUX == 0) {  // Eq. (16): phi u_b d_b u_a, central differences of u
                 const M phi = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
-                dxux = (ld_at(uc, fp) - ld_at(uc, fm)) * M(0.5);
-                dxuy = (ld_at(uc + pitch, fp) - ld_at(uc + pitch, fm)) * M(0.5);
+                dxux = (cur.uxe - cur.uxw) * M(0.5);
+                dxuy = (cur.uye - cur.uyw) * M(0.5);
                 const M dyux = (ux_p - ux_m) * M(0.5);
                 const M dyuy = (uy_p - uy_m) * M(0.5);
                 Ax = phi * (ux_c * dxux + uy_c * dyux);
                 Ay = phi * (ux_c * dxuy + uy_c * dyuy);
             }
-            rr = HAS_K ? relax_from_k<M>(ld_at(kf + (int64_t)rw * pitch, fc), lam, rconst.w3) : rconst;
-            s = HAS_S ? ld_at(sf + (int64_t)rw * pitch, fc) : M(0);
+            rr = HAS_K ? relax_from_k<M>(cur.k, lam, rconst.w3) : rconst;
+            s = HAS_S ? cur.s : M(0);
             collide<M, MRT>(g, ux_c, uy_c, rr, Ax, Ay, s, P);
             T(*slot)[WC] = ring[r & 3];
 #pragma unroll
@@ -232,7 +279,7 @@ struct FluxRings {
     typename ModeTraits<MODE>::M phi2[4][64 * NW + 6];        // phi at level n + 2
 };
 
-template <int MODE, bool HAS_K, bool HAS_S, int NW, bool CST>
+template <int MODE, bool HAS_K, bool HAS_S, int NW, bool CST, bool PF>
 __device__ __forceinline__ void flux_tile(const InstDesc &d, int parity, int t, FluxRings<MODE, NW> &R)
 {
     using St = typename ModeTraits<MODE>::St;
@@ -300,6 +347,30 @@ __device__ __forceinline__ void flux_tile(const InstDesc &d, int parity, int t, 
         g[8] = C::dec(ld_at(rp + 8 * pitch, bm), 8, d.f16);
     };
     auto urow = [&](int row) { return u + (int64_t)__builtin_amdgcn_readfirstlane(wrapr(row)) * 2 * pitch; };
+    // with PF the state pulls of row r + 2 and u at (xi, r + 2) are loaded during iteration r, one row
+    // ahead of their decoding, so the loads stay in flight through the row's collisions and barrier
+    // (FP64 storage: +2-3 %; FP32 storage measured slower with the extra registers)
+    struct Fetched {
+        T g[9];
+        M ux, uy;
+    };
+    auto fetch = [&](int row, Fetched &o) {
+        const T *__restrict__ rm = src + (int64_t)__builtin_amdgcn_readfirstlane(wrapr(row - 1)) * 9 * pitch;
+        const T *__restrict__ rc = src + (int64_t)__builtin_amdgcn_readfirstlane(wrapr(row)) * 9 * pitch;
+        const T *__restrict__ rp = src + (int64_t)__builtin_amdgcn_readfirstlane(wrapr(row + 1)) * 9 * pitch;
+        o.g[0] = ld_at(rc, bc);
+        o.g[1] = ld_at(rc + pitch, bm);
+        o.g[2] = ld_at(rm + 2 * pitch, bc);
+        o.g[3] = ld_at(rc + 3 * pitch, bp);
+        o.g[4] = ld_at(rp + 4 * pitch, bc);
+        o.g[5] = ld_at(rm + 5 * pitch, bm);
+        o.g[6] = ld_at(rm + 6 * pitch, bp);
+        o.g[7] = ld_at(rp + 7 * pitch, bp);
+        o.g[8] = ld_at(rp + 8 * pitch, bm);
+        const M *__restrict__ un = urow(row);
+        o.ux = ld_at(un, fc);
+        o.uy = ld_at(un + pitch, fc);
+    };
 
     const int64_t level = launch_level<C>(d, parity);  // stochastic rounding: writes levels + 1 and + 2
     advance_level<C>(d, parity, level, 2, t == 0 && threadIdx.x == 0);
@@ -326,17 +397,29 @@ __device__ __forceinline__ void flux_tile(const InstDesc &d, int parity, int t, 
     // phi at n + 2 of this column, rows r - 3 and r - 2, and the populations node (xi, r - 2) pulled
     M q_m3 = M(0), q_m2 = M(0);
     M g2[9] = {};
+    Fetched nxt;
+    if (PF) fetch(y0 - 1, nxt);
     __syncthreads();  // phi1 of the first two rows
 
     for (int r = y0 - 2; r <= y1 + 1; ++r) {
         asm volatile("" : "+v"(bc), "+v"(bm), "+v"(bp), "+v"(fc), "+v"(fm), "+v"(fp));
         // ---- the state pulls of row r + 1 and their phi ------------------------------------------------
-        M gn[9];
-        pull(r + 1, gn);
+        M gn[9], uxp1, uyp1;
+        if (PF) {
+            const Fetched cur = nxt;
+            if (r <= y1) fetch(r + 2, nxt);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) gn[i] = C::dec(cur.g[i], i, d.f16);
+            uxp1 = cur.ux;
+            uyp1 = cur.uy;
+        } else {
+            pull(r + 1, gn);
+            const M *__restrict__ un = urow(r + 1);
+            uxp1 = ld_at(un, fc);
+            uyp1 = ld_at(un + pitch, fc);
+        }
         const M p1_p = sum9(gn);
         if (act) R.phi1[(r + 1) & 3][cc] = p1_p;
-        const M *__restrict__ un = urow(r + 1);
-        const M uxp1 = ld_at(un, fc), uyp1 = ld_at(un + pitch, fc);
         // ---- intermediate node (xi, r), level n + 1 -------------------------------------------------------
         const int rw = __builtin_amdgcn_readfirstlane(wrapr(r));
         M P[9] = {};
@@ -426,7 +509,7 @@ __attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW)))) void step2_kernel(co
     const int ntx = (d.L.nx + 64 * NW - 1) / (64 * NW);
     const int t = tile_of_block(blockIdx.x, gridDim.x, d.lcf.xcd_remap, ntx, d.lcf.xcd_rows);
     __shared__ Ring<MODE, NW> ring;
-    fused_tile<MODE, AUX, HAS_K, HAS_S, MRT, NW, CST>(d, a.parity, t, ring);
+    fused_tile<MODE, AUX, HAS_K, HAS_S, MRT, NW, CST, !is_f16_mode(MODE)>(d, a.parity, t, ring);
 }
 
 // One instance, flux form: block b -> tile.
@@ -437,7 +520,7 @@ __global__ __launch_bounds__(64 * (NW + 1)) void flux2_kernel(const StepArgs a)
     const int ntx = (d.L.nx + 64 * NW - 1) / (64 * NW);
     const int t = tile_of_block(blockIdx.x, gridDim.x, d.lcf.xcd_remap, ntx, d.lcf.xcd_rows);
     __shared__ FluxRings<MODE, NW> rings;
-    flux_tile<MODE, HAS_K, HAS_S, NW, CST>(d, a.parity, t, rings);
+    flux_tile<MODE, HAS_K, HAS_S, NW, CST, MODE == MODE_F64_F64 || MODE == MODE_F64_F32>(d, a.parity, t, rings);
 }
 
 // Many instances (periodic D2Q9 TRT-R, one storage form and aux form): each block runs a range of
@@ -459,11 +542,11 @@ __attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW)))) void batched_step2_k
         const WorkItem w = a.items[it];
         const InstDesc &d = a.inst[w.inst];
         if (d.has_k) {
-            if (d.has_s) fused_tile<MODE, AUX, true, true, false, NW, false>(d, a.parity, w.tile, ring);
-            else fused_tile<MODE, AUX, true, false, false, NW, false>(d, a.parity, w.tile, ring);
+            if (d.has_s) fused_tile<MODE, AUX, true, true, false, NW, false, false>(d, a.parity, w.tile, ring);
+            else fused_tile<MODE, AUX, true, false, false, NW, false, false>(d, a.parity, w.tile, ring);
         } else {
-            if (d.has_s) fused_tile<MODE, AUX, false, true, false, NW, false>(d, a.parity, w.tile, ring);
-            else fused_tile<MODE, AUX, false, false, false, NW, false>(d, a.parity, w.tile, ring);
+            if (d.has_s) fused_tile<MODE, AUX, false, true, false, NW, false, false>(d, a.parity, w.tile, ring);
+            else fused_tile<MODE, AUX, false, false, false, NW, false, false>(d, a.parity, w.tile, ring);
         }
         __syncthreads();  // the next tile rewrites the ring the last rows of this one were read from
     }
