@@ -12,9 +12,10 @@
 //
 // Block: NW "interior" waves (lane = column, W = 64 NW output columns x0 .. x0 + W - 1) and one
 // "frame" wave whose lanes 0 and 1 compute the intermediate nodes just left and right of the tile
-// (columns x0 - 1 and x0 + W, wrapped).  The block walks its H output rows top to bottom:
-// iteration r computes intermediate row r (from state rows r - 1 .. r + 1 in HBM/L2) and, one row
-// behind, output row r - 1 (from intermediate rows r - 2 .. r).  Intermediate populations that move
+// (columns x0 - 1 and x0 + W, wrapped).  The block walks its H output rows top to bottom (with FP32
+// and FP64 storage, odd tile rows bottom to top): iteration r computes intermediate row r (from state
+// rows r - 1 .. r + 1 in HBM/L2) and, one row behind, output row r - 1 (from intermediate rows
+// r - 2 .. r; r + 1 and rows r .. r + 2 walking up).  Intermediate populations that move
 // along x (i = 1, 3, 5, 6, 7, 8) are exchanged through a four-row LDS ring; those with e_x = 0
 // (i = 0, 2, 4) stay in the registers of the lane that computed them.  Four ring rows let the next
 // intermediate row be written while the previous output row is still being read, so one barrier
@@ -92,7 +93,14 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
     rconst.w3 = (M)d.w3;
 
     auto wrapr = [ny](int r) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); };
-    // The global loads of walk row r: u at (xi, r + 1); for the intermediate node (xi, r) its nine
+    // Walk direction: top to bottom (dir = +1), or bottom to top (dir = -1) for odd tile rows, so that two
+    // vertically adjacent tiles reach the state rows they both read (two each way) at about the same time
+    // (both at their first rows, or both at their last) and the second read finds them in L2: 2048^2
+    // FP32 reads 1.01x its algorithmic bytes instead of 1.15x.  With PF only: the FP16 walks, bound by
+    // VALU issue, measured up to 8 % slower with the direction selects.
+    const int dir = PF && ((t / ntx) & 1) ? -1 : 1;
+    const bool up = dir < 0;
+    // The global loads of walk row r: u at (xi, r + dir); for the intermediate node (xi, r) its nine
     // pulls from state rows r - 1 .. r + 1, u at its x-neighbours and the k and s fields.  With PF, row
     // r + 1's loads are issued before row r is computed, so they are in flight through row r's two
     // collisions and the barrier instead of stalling the block once per row.
@@ -106,11 +114,12 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
         const int rw = __builtin_amdgcn_readfirstlane(wrapr(r));
         const int rwm = __builtin_amdgcn_readfirstlane(wrapr(r - 1));
         const int rwp = __builtin_amdgcn_readfirstlane(wrapr(r + 1));
+        const int rwa = __builtin_amdgcn_readfirstlane(wrapr(r + dir));
         // the lane offsets are re-read every row (an empty asm that claims to update them), so the compiler
         // keeps each access as one scalar row base plus a 32-bit lane offset instead of hoisting 64-bit
         // per-lane addresses out of the walk
         asm volatile("" : "+v"(bc), "+v"(bm), "+v"(bp), "+v"(fc), "+v"(fm), "+v"(fp));
-        const M *__restrict__ un = u + (int64_t)rwp * 2 * pitch;
+        const M *__restrict__ un = u + (int64_t)rwa * 2 * pitch;
         o.uxp = ld_at(un, fc);
         o.uyp = ld_at(un + pitch, fc);
         if (act) {
@@ -140,18 +149,22 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
         if (HAS_K) o.k = ld_at(kf + (int64_t)rw * pitch, fc);
         if (HAS_S) o.s = ld_at(sf + (int64_t)rw * pitch, fc);
     };
-    // velocity at this column, rows r - 2 .. r + 1 of the walk (mm, m, c, p)
-    const int rs = y0 - 1;
+    // the walk: intermediate rows rs, rs + dir, ..., nk of them; output row r - dir one iteration behind
+    const int rs = up ? y1 : y0 - 1;
+    const int nk = y1 - y0 + 2;
+    // velocity at this column, rows r - 2 dir .. r + dir of the walk (mm, m, c, p)
     M ux_mm = M(0), uy_mm = M(0);
-    M ux_m = ld_at(u + (int64_t)wrapr(rs - 1) * 2 * pitch, fc), uy_m = ld_at(u + ((int64_t)wrapr(rs - 1) * 2 + 1) * pitch, fc);
+    M ux_m = ld_at(u + (int64_t)wrapr(rs - dir) * 2 * pitch, fc), uy_m = ld_at(u + ((int64_t)wrapr(rs - dir) * 2 + 1) * pitch, fc);
     M ux_c = ld_at(u + (int64_t)wrapr(rs) * 2 * pitch, fc), uy_c = ld_at(u + ((int64_t)wrapr(rs) * 2 + 1) * pitch, fc);
     // x-differences of u, the relaxation and the source of the previous intermediate row (reused by
     // the output node of that row, which sits in the same column)
     M dxux_m = M(0), dxuy_m = M(0);
     Relax<M> r_m = rconst;
     M s_m = M(0);
-    // e_x = 0 populations of earlier intermediate rows at this column, as a reader would decode them
-    M p0_m = M(0), p2_m = M(0), p2_mm = M(0);
+    // e_x = 0 populations of earlier intermediate rows at this column, as a reader would decode them:
+    // p0 of the previous row, and the one moving against the walk (i = 2 walking down, 4 walking up)
+    // of the two previous rows
+    M p0_m = M(0), pb_m = M(0), pb_mm = M(0);
 
     // stochastic rounding: time level of the state this launch reads; it writes levels + 1 and + 2
     const int64_t level = launch_level<C>(d, parity);
@@ -162,15 +175,16 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
         load_row(rs, nxt);
         if (act) load_aux(__builtin_amdgcn_readfirstlane(wrapr(rs)), nxt);
     }
-    for (int r = rs; r <= y1; ++r) {
+    for (int k = 0; k < nk; ++k) {
+        const int r = __builtin_amdgcn_readfirstlane(rs + dir * k);
         const int rw = __builtin_amdgcn_readfirstlane(wrapr(r));
         const auto rb1 = C::bits(d.f16, level + 1, (int64_t)rw * nx, (unsigned)xi);  // intermediate node (xi, r)
         RowLoads cur;
         if (PF) {
             cur = nxt;
-            if (r < y1) {
-                load_row(r + 1, nxt);
-                if (act) load_aux(__builtin_amdgcn_readfirstlane(wrapr(r + 1)), nxt);
+            if (k + 1 < nk) {
+                load_row(r + dir, nxt);
+                if (act) load_aux(__builtin_amdgcn_readfirstlane(wrapr(r + dir)), nxt);
             }
         } else {
             load_row(r, cur);
@@ -190,8 +204,9 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
                 const M phi = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
                 dxux = (cur.uxe - cur.uxw) * M(0.5);
                 dxuy = (cur.uye - cur.uyw) * M(0.5);
-                const M dyux = (ux_p - ux_m) * M(0.5);
-                const M dyuy = (uy_p - uy_m) * M(0.5);
+                // u at rows r + 1 and r - 1 (ahead and behind, or behind and ahead walking up)
+                const M dyux = ((up ? ux_m : ux_p) - (up ? ux_p : ux_m)) * M(0.5);
+                const M dyuy = ((up ? uy_m : uy_p) - (up ? uy_p : uy_m)) * M(0.5);
                 Ax = phi * (ux_c * dxux + uy_c * dyux);
                 Ay = phi * (ux_c * dxuy + uy_c * dyuy);
             }
@@ -204,19 +219,20 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
                 if (kPlane[i] >= 0) slot[kPlane[i]][c] = C::enc(P[i], i, d.f16, rb1);
         }
         __syncthreads();
-        // ---- phase 2: output node (x, y = r - 1) of step n + 2 ---------------------------------------
+        // ---- phase 2: output node (x, y = r - dir) of step n + 2 -------------------------------------
+        const M p2 = C::dec(C::enc(P[2], 2, d.f16, rb1), 2, d.f16);
         const M p4 = C::dec(C::enc(P[4], 4, d.f16, rb1), 4, d.f16);
-        if (!frame && r >= y0 + 1) {
-            const int y = __builtin_amdgcn_readfirstlane(r - 1);
+        if (!frame && k >= 2) {
+            const int y = __builtin_amdgcn_readfirstlane(r - dir);
             M g[9];
             T(*const sy)[WC] = ring[y & 3];
             T(*const sm)[WC] = ring[(y - 1) & 3];
             T(*const sp)[WC] = ring[(y + 1) & 3];
             g[0] = p0_m;
             g[1] = C::dec(sy[kPlane[1]][c - 1], 1, d.f16);
-            g[2] = p2_mm;
+            g[2] = up ? p2 : pb_mm;  // from row y - 1
             g[3] = C::dec(sy[kPlane[3]][c + 1], 3, d.f16);
-            g[4] = p4;
+            g[4] = up ? pb_mm : p4;  // from row y + 1
             g[5] = C::dec(sm[kPlane[5]][c - 1], 5, d.f16);
             g[6] = C::dec(sm[kPlane[6]][c + 1], 6, d.f16);
             g[7] = C::dec(sp[kPlane[7]][c + 1], 7, d.f16);
@@ -224,8 +240,8 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
             M Ax = M(0), Ay = M(0);
             if (AUX == 0) {
                 const M phi = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
-                const M dyux = (ux_c - ux_mm) * M(0.5);
-                const M dyuy = (uy_c - uy_mm) * M(0.5);
+                const M dyux = ((up ? ux_mm : ux_c) - (up ? ux_c : ux_mm)) * M(0.5);  // u at y + 1 and y - 1
+                const M dyuy = ((up ? uy_mm : uy_c) - (up ? uy_c : uy_mm)) * M(0.5);
                 Ax = phi * (ux_m * dxux_m + uy_m * dyux);
                 Ay = phi * (ux_m * dxuy_m + uy_m * dyuy);
             }
@@ -241,9 +257,9 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
                 }
             }
         }
-        // roll the walk down one row
-        p2_mm = p2_m;
-        p2_m = C::dec(C::enc(P[2], 2, d.f16, rb1), 2, d.f16);
+        // roll the walk on by one row
+        pb_mm = pb_m;
+        pb_m = up ? p4 : p2;
         p0_m = C::dec(C::enc(P[0], 0, d.f16, rb1), 0, d.f16);
         dxux_m = dxux;
         dxuy_m = dxuy;
