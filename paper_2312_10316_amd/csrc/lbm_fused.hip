@@ -39,9 +39,10 @@ constexpr int step2_waves(int mode, int nw)
 // LDS ring of FP64 storage lets 160 KB hold (2 to 4): FP32 and FP16 storage then fit 41-49 VGPRs,
 // against 65-83 by default.
 // The walk is bound by the loads each wave keeps in flight, so resident waves count more than registers.
-// The LDS ring of a block: four rows of the six x-moving intermediate populations, W + 2 columns.
+// The LDS ring of a block: four rows of the six x-moving intermediate populations, W + 2 columns and
+// one more that the frame wave's idle lanes write (and nothing reads).
 template <int MODE, int NW>
-using Ring = typename ModeTraits<MODE>::St::T[4][6][64 * NW + 2];
+using Ring = typename ModeTraits<MODE>::St::T[4][6][64 * NW + 3];
 
 // Two steps of tile t of one instance (tiles numbered row-major, ceil(nx / W) per row, d.lcf.rows high),
 // reading buf[parity] and writing buf[parity ^ 1]; called by every thread of the block.
@@ -55,7 +56,7 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
     using M = typename ModeTraits<MODE>::M;
     using T = typename St::T;
     using C = Codec<St, M>;
-    constexpr int W = 64 * NW, WC = W + 2;
+    constexpr int W = 64 * NW, WC = W + 3;
 
     const int nx = d.L.nx, ny = d.L.ny;
     const int64_t pitch = d.L.pitch;
@@ -69,6 +70,9 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
     // ring column of this thread's intermediate node (column x0 - 1 + c of the lattice, wrapped)
     const int c = frame ? (lane == 0 ? 0 : (lane == 1 ? W + 1 : -1)) : 1 + wave * 64 + lane;
     const bool act = c >= 0;
+    // every lane runs the intermediate node's loads and collision (no divergent branch, whose merges had
+    // cost copies and waits); the frame wave's idle lanes take column x0 and write the spare ring column
+    const int cw = act ? c : W + 2;
     int xi = x0 - 1 + (act ? c : 1);
     xi = xi % nx;
     xi = xi < 0 ? xi + nx : xi;
@@ -122,20 +126,18 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
         const M *__restrict__ un = u + (int64_t)rwa * 2 * pitch;
         o.uxp = ld_at(un, fc);
         o.uyp = ld_at(un + pitch, fc);
-        if (act) {
-            const T *__restrict__ rm = src + (int64_t)rwm * 9 * pitch;
-            const T *__restrict__ rc = src + (int64_t)rw * 9 * pitch;
-            const T *__restrict__ rp = src + (int64_t)rwp * 9 * pitch;
-            o.g[0] = ld_at(rc, bc);
-            o.g[1] = ld_at(rc + pitch, bm);
-            o.g[2] = ld_at(rm + 2 * pitch, bc);
-            o.g[3] = ld_at(rc + 3 * pitch, bp);
-            o.g[4] = ld_at(rp + 4 * pitch, bc);
-            o.g[5] = ld_at(rm + 5 * pitch, bm);
-            o.g[6] = ld_at(rm + 6 * pitch, bp);
-            o.g[7] = ld_at(rp + 7 * pitch, bp);
-            o.g[8] = ld_at(rp + 8 * pitch, bm);
-        }
+        const T *__restrict__ rm = src + (int64_t)rwm * 9 * pitch;
+        const T *__restrict__ rc = src + (int64_t)rw * 9 * pitch;
+        const T *__restrict__ rp = src + (int64_t)rwp * 9 * pitch;
+        o.g[0] = ld_at(rc, bc);
+        o.g[1] = ld_at(rc + pitch, bm);
+        o.g[2] = ld_at(rm + 2 * pitch, bc);
+        o.g[3] = ld_at(rc + 3 * pitch, bp);
+        o.g[4] = ld_at(rp + 4 * pitch, bc);
+        o.g[5] = ld_at(rm + 5 * pitch, bm);
+        o.g[6] = ld_at(rm + 6 * pitch, bp);
+        o.g[7] = ld_at(rp + 7 * pitch, bp);
+        o.g[8] = ld_at(rp + 8 * pitch, bm);
     };
     // the rest of row r's loads, for the node at (xi, r) (rw: the wrapped row, wave-uniform)
     auto load_aux = [&](int rw, RowLoads &o) {
@@ -173,9 +175,11 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
     RowLoads nxt;
     if (PF) {
         load_row(rs, nxt);
-        if (act) load_aux(__builtin_amdgcn_readfirstlane(wrapr(rs)), nxt);
+        load_aux(__builtin_amdgcn_readfirstlane(wrapr(rs)), nxt);
     }
-    for (int k = 0; k < nk; ++k) {
+    // one row of the walk; with PF the walk is unrolled by two, so the values rolled from row to row are
+    // renamed instead of copied
+    auto walk_row = [&](const int k) __attribute__((always_inline)) {
         const int r = __builtin_amdgcn_readfirstlane(rs + dir * k);
         const int rw = __builtin_amdgcn_readfirstlane(wrapr(r));
         const auto rb1 = C::bits(d.f16, level + 1, (int64_t)rw * nx, (unsigned)xi);  // intermediate node (xi, r)
@@ -184,7 +188,7 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
             cur = nxt;
             if (k + 1 < nk) {
                 load_row(r + dir, nxt);
-                if (act) load_aux(__builtin_amdgcn_readfirstlane(wrapr(r + dir)), nxt);
+                load_aux(__builtin_amdgcn_readfirstlane(wrapr(r + dir)), nxt);
             }
         } else {
             load_row(r, cur);
@@ -193,8 +197,8 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
         // ---- phase 1: intermediate node (xi, r) of step n + 1 -----------------------------------------
         M dxux = M(0), dxuy = M(0), s = M(0);
         Relax<M> rr = rconst;
-        M P[9] = {};
-        if (act) {
+        M P[9];
+        {
             M g[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) g[i] = C::dec(cur.g[i], i, d.f16);
@@ -216,7 +220,7 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
             T(*slot)[WC] = ring[r & 3];
 #pragma unroll
             for (int i = 0; i < 9; ++i)
-                if (kPlane[i] >= 0) slot[kPlane[i]][c] = C::enc(P[i], i, d.f16, rb1);
+                if (kPlane[i] >= 0) slot[kPlane[i]][cw] = C::enc(P[i], i, d.f16, rb1);
         }
         __syncthreads();
         // ---- phase 2: output node (x, y = r - dir) of step n + 2 -------------------------------------
@@ -271,7 +275,15 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
         uy_m = uy_c;
         ux_c = ux_p;
         uy_c = uy_p;
+    };
+    int k = 0;
+    if constexpr (PF) {
+        for (; k + 1 < nk; k += 2) {
+            walk_row(k);
+            walk_row(k + 1);
+        }
     }
+    for (; k < nk; ++k) walk_row(k);
 }
 
 // ---- two steps with the flux form of the auxiliary term ----------------------------------------------
