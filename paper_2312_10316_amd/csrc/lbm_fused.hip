@@ -301,10 +301,10 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
 // kernel (the same pulls, sums in index order, flux_aux, collide) and the intermediate populations go
 // through the storage codec, so the results are bitwise those of two single steps.
 template <int MODE, int NW>
-struct FluxRings {
-    typename ModeTraits<MODE>::St::T pop[4][6][64 * NW + 6];  // intermediate x-moving populations
-    typename ModeTraits<MODE>::M phi1[4][64 * NW + 6];        // phi at level n + 1
-    typename ModeTraits<MODE>::M phi2[4][64 * NW + 6];        // phi at level n + 2
+struct FluxRings {  // W + 6 columns and a spare one that lanes without a node of that kind write
+    typename ModeTraits<MODE>::St::T pop[4][6][64 * NW + 7];  // intermediate x-moving populations
+    typename ModeTraits<MODE>::M phi1[4][64 * NW + 7];        // phi at level n + 1
+    typename ModeTraits<MODE>::M phi2[4][64 * NW + 7];        // phi at level n + 2
 };
 
 template <int MODE, bool HAS_K, bool HAS_S, int NW, bool CST, bool PF>
@@ -339,7 +339,11 @@ __device__ __forceinline__ void flux_tile(const InstDesc &d, int parity, int t, 
     unsigned bc = ux_ * (unsigned)sizeof(T), bm = uxm * (unsigned)sizeof(T), bp = uxp * (unsigned)sizeof(T);
     unsigned fc = ux_ * (unsigned)sizeof(M), fm = uxm * (unsigned)sizeof(M), fp = uxp * (unsigned)sizeof(M);
     const unsigned pb = (unsigned)(pitch * (int64_t)sizeof(T));
-    const int cl = act ? cc : 0;  // a ring column every lane may address
+    // Every lane runs the pulls, the intermediate node and the phi at n + 2 (no divergent branches):
+    // lanes without such a node read the ring at a column inside it and write the spare column W + 6.
+    const int c1w = act ? cc : W + 6;
+    const int ci = inter ? cc : 1, ciw = inter ? cc : W + 6;
+    const int cm = mid ? cc : 2, cmw = mid ? cc : W + 6;
 
     const T *__restrict__ src = static_cast<const T *>(d.buf[parity]);
     T *__restrict__ dst = static_cast<T *>(d.buf[parity ^ 1]);
@@ -411,10 +415,8 @@ __device__ __forceinline__ void flux_tile(const InstDesc &d, int parity, int t, 
         p1_m = sum9(gm);
         pull(y0 - 2, gc);
         p1_c = sum9(gc);
-        if (act) {
-            R.phi1[(y0 - 3) & 3][cc] = p1_m;
-            R.phi1[(y0 - 2) & 3][cc] = p1_c;
-        }
+        R.phi1[(y0 - 3) & 3][c1w] = p1_m;
+        R.phi1[(y0 - 2) & 3][c1w] = p1_c;
     }
     // u at this column, rows r - 3 .. r + 1 of the walk
     M ux3 = M(0), uy3 = M(0), ux2 = M(0), uy2 = M(0);
@@ -447,42 +449,42 @@ __device__ __forceinline__ void flux_tile(const InstDesc &d, int parity, int t, 
             uyp1 = ld_at(un + pitch, fc);
         }
         const M p1_p = sum9(gn);
-        if (act) R.phi1[(r + 1) & 3][cc] = p1_p;
+        R.phi1[(r + 1) & 3][c1w] = p1_p;
         // ---- intermediate node (xi, r), level n + 1 -------------------------------------------------------
         const int rw = __builtin_amdgcn_readfirstlane(wrapr(r));
-        M P[9] = {};
+        M P[9];
         const auto rb1 = C::bits(d.f16, level + 1, (int64_t)rw * nx, (unsigned)xi);
-        if (inter) {
+        {
             const M *__restrict__ uc = u + (int64_t)rw * 2 * pitch;
             const M uxw = ld_at(uc, fm), uyw = ld_at(uc + pitch, fm), uxe = ld_at(uc, fp), uye = ld_at(uc + pitch, fp);
             M Ax, Ay;
-            flux_aux<M>(R.phi1[r & 3][cc - 1], R.phi1[r & 3][cc + 1], p1_m, p1_p, uxw, uyw, uxe, uye, ux1, uy1, uxp1, uyp1,
+            flux_aux<M>(R.phi1[r & 3][ci - 1], R.phi1[r & 3][ci + 1], p1_m, p1_p, uxw, uyw, uxe, uye, ux1, uy1, uxp1, uyp1,
                         ux0, uy0, Ax, Ay);
             const Relax<M> rr = HAS_K ? relax_from_k<M>(ld_at(kf + (int64_t)rw * pitch, fc), lam, rconst.w3) : rconst;
             const M s = HAS_S ? ld_at(sf + (int64_t)rw * pitch, fc) : M(0);
             collide<M, false>(gc, ux0, uy0, rr, Ax, Ay, s, P);
 #pragma unroll
             for (int i = 0; i < 9; ++i)
-                if (kPlane[i] >= 0) R.pop[r & 3][kPlane[i]][cc] = C::enc(P[i], i, d.f16, rb1);
+                if (kPlane[i] >= 0) R.pop[r & 3][kPlane[i]][ciw] = C::enc(P[i], i, d.f16, rb1);
         }
         const M p4 = C::dec(C::enc(P[4], 4, d.f16, rb1), 4, d.f16);
         __syncthreads();
         // ---- phi at n + 2 of node (xi, r - 1), from intermediate rows r - 2 .. r ----------------------------
         M q_m1 = M(0);
         M gq[9] = {};
-        if (r >= y0 && mid) {
+        if (r >= y0) {
             const int y = r - 1;
             gq[0] = p0_m;
-            gq[1] = C::dec(R.pop[y & 3][kPlane[1]][cl - 1], 1, d.f16);
+            gq[1] = C::dec(R.pop[y & 3][kPlane[1]][cm - 1], 1, d.f16);
             gq[2] = p2_mm;
-            gq[3] = C::dec(R.pop[y & 3][kPlane[3]][cl + 1], 3, d.f16);
+            gq[3] = C::dec(R.pop[y & 3][kPlane[3]][cm + 1], 3, d.f16);
             gq[4] = p4;
-            gq[5] = C::dec(R.pop[(y - 1) & 3][kPlane[5]][cl - 1], 5, d.f16);
-            gq[6] = C::dec(R.pop[(y - 1) & 3][kPlane[6]][cl + 1], 6, d.f16);
-            gq[7] = C::dec(R.pop[(y + 1) & 3][kPlane[7]][cl + 1], 7, d.f16);
-            gq[8] = C::dec(R.pop[(y + 1) & 3][kPlane[8]][cl - 1], 8, d.f16);
+            gq[5] = C::dec(R.pop[(y - 1) & 3][kPlane[5]][cm - 1], 5, d.f16);
+            gq[6] = C::dec(R.pop[(y - 1) & 3][kPlane[6]][cm + 1], 6, d.f16);
+            gq[7] = C::dec(R.pop[(y + 1) & 3][kPlane[7]][cm + 1], 7, d.f16);
+            gq[8] = C::dec(R.pop[(y + 1) & 3][kPlane[8]][cm - 1], 8, d.f16);
             q_m1 = sum9(gq);
-            R.phi2[y & 3][cc] = q_m1;
+            R.phi2[y & 3][cmw] = q_m1;
         }
         // ---- output node (xi, r - 2), level n + 2 ---------------------------------------------------------
         if (r >= y0 + 2 && live) {
