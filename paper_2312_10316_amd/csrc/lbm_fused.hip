@@ -180,9 +180,10 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
     // one row of the walk; with PF the walk is unrolled by two, so the values rolled from row to row are
     // renamed instead of copied
     // FP16 with stochastic rounding raises the issue priority of its waves for the output node (after the
-    // barrier) and lowers it for the intermediate node: 2048^2 146k -> 158k, 8192^2 156k -> 168k MLUPS
-    // (round-to-nearest FP16 gained at 2048^2 and lost at 8192^2, FP32 and FP64 were level or slower)
-    constexpr bool kPrio = MODE == MODE_F16SR_F32;
+    // barrier) and lowers it for the intermediate node: 2048^2 146k -> 158k, 8192^2 156k -> 168k MLUPS.
+    // Round-to-nearest FP16 gained with 512-column tiles (2048^2 188k -> 195k) and lost with 256-column
+    // ones (8192^2 201k -> 190k); FP32 and FP64 were level or slower.
+    constexpr bool kPrio = MODE == MODE_F16SR_F32 || (MODE == MODE_F16S_F32 && NW == 8);
     auto walk_row = [&](const int k) __attribute__((always_inline)) {
         if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
         const int r = __builtin_amdgcn_readfirstlane(rs + dir * k);
