@@ -49,7 +49,7 @@ using Ring = typename ModeTraits<MODE>::St::T[4][6][64 * NW + 3];
 // PF: issue each row's global loads one row ahead.  Single-instance kernels with FP32 or FP64 storage
 // take it; the FP16 codecs (more arithmetic per value, already issue-bound) and the batched kernel
 // (four inlined variants within one register budget) measure faster without.
-template <int MODE, int AUX, bool HAS_K, bool HAS_S, bool MRT, int NW, bool CST, bool PF>
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, bool MRT, int NW, bool CST, bool PF, bool UP>
 __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t, Ring<MODE, NW> &ring)
 {
     using St = typename ModeTraits<MODE>::St;
@@ -97,13 +97,13 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
     rconst.w3 = (M)d.w3;
 
     auto wrapr = [ny](int r) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); };
-    // Walk direction: top to bottom (dir = +1), or bottom to top (dir = -1) for odd tile rows, so that two
-    // vertically adjacent tiles reach the state rows they both read (two each way) at about the same time
-    // (both at their first rows, or both at their last) and the second read finds them in L2: 2048^2
-    // FP32 reads 1.01x its algorithmic bytes instead of 1.15x.  With PF only: the FP16 walks, bound by
-    // VALU issue, measured up to 8 % slower with the direction selects.
-    const int dir = PF && ((t / ntx) & 1) ? -1 : 1;
-    const bool up = dir < 0;
+    // Walk direction: top to bottom (dir = +1), or with UP bottom to top (dir = -1).  The single-instance
+    // kernel walks odd tile rows up, so that two vertically adjacent tiles reach the state rows they both
+    // read (two each way) at about the same time (both at their first rows, or both at their last) and
+    // the second read finds them in L2: 2048^2 FP32 reads 1.01x its algorithmic bytes instead of 1.15x.
+    // A compile-time direction keeps the row arithmetic free of selects.
+    constexpr int dir = UP ? -1 : 1;
+    constexpr bool up = UP;
     // The global loads of walk row r: u at (xi, r + dir); for the intermediate node (xi, r) its nine
     // pulls from state rows r - 1 .. r + 1, u at its x-neighbours and the k and s fields.  With PF, row
     // r + 1's loads are issued before row r is computed, so they are in flight through row r's two
@@ -551,7 +551,9 @@ __attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW)))) void step2_kernel(co
     const int ntx = (d.L.nx + 64 * NW - 1) / (64 * NW);
     const int t = tile_of_block(blockIdx.x, gridDim.x, d.lcf.xcd_remap, ntx, d.lcf.xcd_rows);
     __shared__ Ring<MODE, NW> ring;
-    fused_tile<MODE, AUX, HAS_K, HAS_S, MRT, NW, CST, !is_f16_mode(MODE)>(d, a.parity, t, ring);
+    constexpr bool PF = !is_f16_mode(MODE);
+    if ((t / ntx) & 1) fused_tile<MODE, AUX, HAS_K, HAS_S, MRT, NW, CST, PF, true>(d, a.parity, t, ring);
+    else fused_tile<MODE, AUX, HAS_K, HAS_S, MRT, NW, CST, PF, false>(d, a.parity, t, ring);
 }
 
 // One instance, flux form: block b -> tile.
@@ -584,11 +586,11 @@ __attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW)))) void batched_step2_k
         const WorkItem w = a.items[it];
         const InstDesc &d = a.inst[w.inst];
         if (d.has_k) {
-            if (d.has_s) fused_tile<MODE, AUX, true, true, false, NW, false, false>(d, a.parity, w.tile, ring);
-            else fused_tile<MODE, AUX, true, false, false, NW, false, false>(d, a.parity, w.tile, ring);
+            if (d.has_s) fused_tile<MODE, AUX, true, true, false, NW, false, false, false>(d, a.parity, w.tile, ring);
+            else fused_tile<MODE, AUX, true, false, false, NW, false, false, false>(d, a.parity, w.tile, ring);
         } else {
-            if (d.has_s) fused_tile<MODE, AUX, false, true, false, NW, false, false>(d, a.parity, w.tile, ring);
-            else fused_tile<MODE, AUX, false, false, false, NW, false, false>(d, a.parity, w.tile, ring);
+            if (d.has_s) fused_tile<MODE, AUX, false, true, false, NW, false, false, false>(d, a.parity, w.tile, ring);
+            else fused_tile<MODE, AUX, false, false, false, NW, false, false, false>(d, a.parity, w.tile, ring);
         }
         __syncthreads();  // the next tile rewrites the ring the last rows of this one were read from
     }
