@@ -314,7 +314,7 @@ struct FluxRings {  // W + 6 columns and a spare one that lanes without a node o
     typename ModeTraits<MODE>::M phi2[4][64 * NW + 7];        // phi at level n + 2
 };
 
-template <int MODE, bool HAS_K, bool HAS_S, int NW, bool CST, bool PF>
+template <int MODE, bool HAS_K, bool HAS_S, int NW, bool CST, bool PF, bool UP>
 __device__ __forceinline__ void flux_tile(const InstDesc &d, int parity, int t, FluxRings<MODE, NW> &R)
 {
     using St = typename ModeTraits<MODE>::St;
@@ -414,53 +414,63 @@ __device__ __forceinline__ void flux_tile(const InstDesc &d, int parity, int t, 
     const int64_t level = launch_level<C>(d, parity);  // stochastic rounding: writes levels + 1 and + 2
     advance_level<C>(d, parity, level, 2, t == 0 && threadIdx.x == 0);
 
-    // the walk starts at r = y0 - 2 with the state pulls of rows y0 - 3 (phi only) and y0 - 2
+    // The walk goes top to bottom (dir = +1) or, with UP, bottom to top (dir = -1; the kernel walks odd
+    // tile rows up, so that adjacent tiles read the rows they share at about the same time).  Iteration k
+    // handles intermediate row r = rs + k dir; "behind" is r - dir, "ahead" r + dir, and the south and
+    // north neighbours of a node are the behind and ahead ones walking down, the other way round up.
+    constexpr int dir = UP ? -1 : 1;
+    const int rs = UP ? y1 + 1 : y0 - 2;
+    const int nk = y1 - y0 + 4;
+    // the walk starts with the state pulls of rows rs - dir (phi only) and rs
     M gc[9], p1_m, p1_c;
     {
         M gm[9];
-        pull(y0 - 3, gm);
+        pull(rs - dir, gm);
         p1_m = sum9(gm);
-        pull(y0 - 2, gc);
+        pull(rs, gc);
         p1_c = sum9(gc);
-        R.phi1[(y0 - 3) & 3][c1w] = p1_m;
-        R.phi1[(y0 - 2) & 3][c1w] = p1_c;
+        R.phi1[(rs - dir) & 3][c1w] = p1_m;
+        R.phi1[rs & 3][c1w] = p1_c;
     }
-    // u at this column, rows r - 3 .. r + 1 of the walk
+    // u at this column, rows r - 3 dir .. r + dir of the walk
     M ux3 = M(0), uy3 = M(0), ux2 = M(0), uy2 = M(0);
-    M ux1 = ld_at(urow(y0 - 3), fc), uy1 = ld_at(urow(y0 - 3) + pitch, fc);
-    M ux0 = ld_at(urow(y0 - 2), fc), uy0 = ld_at(urow(y0 - 2) + pitch, fc);
-    // e_x = 0 intermediate populations of this column as a reader decodes them, rows r - 1 and r - 2
-    M p0_m = M(0), p2_m = M(0), p2_mm = M(0);
-    // phi at n + 2 of this column, rows r - 3 and r - 2, and the populations node (xi, r - 2) pulled
+    M ux1 = ld_at(urow(rs - dir), fc), uy1 = ld_at(urow(rs - dir) + pitch, fc);
+    M ux0 = ld_at(urow(rs), fc), uy0 = ld_at(urow(rs) + pitch, fc);
+    // e_x = 0 intermediate populations of this column as a reader decodes them: p0 of the row behind,
+    // and the one moving against the walk (i = 2 walking down, 4 up) of the two rows behind
+    M p0_m = M(0), pb_m = M(0), pb_mm = M(0);
+    // phi at n + 2 of this column, rows r - 3 dir and r - 2 dir, and the populations node (xi, r - 2 dir)
+    // pulled
     M q_m3 = M(0), q_m2 = M(0);
     M g2[9] = {};
     Fetched nxt;
-    if (PF) fetch(y0 - 1, nxt);
+    if (PF) fetch(rs + dir, nxt);
     __syncthreads();  // phi1 of the first two rows
 
     // FP32 and FP16 storage raise the waves' issue priority for the work after the barrier (2048^2 FP32
     // 95k -> 98k, FP16S 120k -> 133k MLUPS; FP64 storage level)
     constexpr bool kPrio = !(MODE == MODE_F64_F64 || MODE == MODE_F64_F32);
-    for (int r = y0 - 2; r <= y1 + 1; ++r) {
+    for (int k = 0; k < nk; ++k) {
+        const int r = rs + dir * k;
         if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
         asm volatile("" : "+v"(bc), "+v"(bm), "+v"(bp), "+v"(fc), "+v"(fm), "+v"(fp));
-        // ---- the state pulls of row r + 1 and their phi ------------------------------------------------
+        // ---- the state pulls of row r + dir and their phi ----------------------------------------------
         M gn[9], uxp1, uyp1;
         if (PF) {
             const Fetched cur = nxt;
-            if (r <= y1) fetch(r + 2, nxt);
+            if (k + 1 < nk) fetch(r + 2 * dir, nxt);
 #pragma unroll
             for (int i = 0; i < 9; ++i) gn[i] = C::dec(cur.g[i], i, d.f16);
             uxp1 = cur.ux;
             uyp1 = cur.uy;
         } else {
-            pull(r + 1, gn);
-            const M *__restrict__ un = urow(r + 1);
+            pull(r + dir, gn);
+            const M *__restrict__ un = urow(r + dir);
             uxp1 = ld_at(un, fc);
             uyp1 = ld_at(un + pitch, fc);
         }
         const M p1_p = sum9(gn);
-        R.phi1[(r + 1) & 3][c1w] = p1_p;
+        R.phi1[(r + dir) & 3][c1w] = p1_p;
         // ---- intermediate node (xi, r), level n + 1 -------------------------------------------------------
         const int rw = __builtin_amdgcn_readfirstlane(wrapr(r));
         M P[9];
@@ -469,8 +479,12 @@ __device__ __forceinline__ void flux_tile(const InstDesc &d, int parity, int t, 
             const M *__restrict__ uc = u + (int64_t)rw * 2 * pitch;
             const M uxw = ld_at(uc, fm), uyw = ld_at(uc + pitch, fm), uxe = ld_at(uc, fp), uye = ld_at(uc + pitch, fp);
             M Ax, Ay;
-            flux_aux<M>(R.phi1[r & 3][ci - 1], R.phi1[r & 3][ci + 1], p1_m, p1_p, uxw, uyw, uxe, uye, ux1, uy1, uxp1, uyp1,
-                        ux0, uy0, Ax, Ay);
+            if constexpr (UP)  // south: the row ahead, north: the row behind
+                flux_aux<M>(R.phi1[r & 3][ci - 1], R.phi1[r & 3][ci + 1], p1_p, p1_m, uxw, uyw, uxe, uye, uxp1, uyp1, ux1,
+                            uy1, ux0, uy0, Ax, Ay);
+            else
+                flux_aux<M>(R.phi1[r & 3][ci - 1], R.phi1[r & 3][ci + 1], p1_m, p1_p, uxw, uyw, uxe, uye, ux1, uy1, uxp1,
+                            uyp1, ux0, uy0, Ax, Ay);
             const Relax<M> rr = HAS_K ? relax_from_k<M>(ld_at(kf + (int64_t)rw * pitch, fc), lam, rconst.w3) : rconst;
             const M s = HAS_S ? ld_at(sf + (int64_t)rw * pitch, fc) : M(0);
             collide<M, false>(gc, ux0, uy0, rr, Ax, Ay, s, P);
@@ -478,19 +492,20 @@ __device__ __forceinline__ void flux_tile(const InstDesc &d, int parity, int t, 
             for (int i = 0; i < 9; ++i)
                 if (kPlane[i] >= 0) R.pop[r & 3][kPlane[i]][ciw] = C::enc(P[i], i, d.f16, rb1);
         }
+        const M p2 = C::dec(C::enc(P[2], 2, d.f16, rb1), 2, d.f16);
         const M p4 = C::dec(C::enc(P[4], 4, d.f16, rb1), 4, d.f16);
         __syncthreads();
         if constexpr (kPrio) __builtin_amdgcn_s_setprio(1);
-        // ---- phi at n + 2 of node (xi, r - 1), from intermediate rows r - 2 .. r ----------------------------
+        // ---- phi at n + 2 of node (xi, y = r - dir), from intermediate rows y - 1 .. y + 1 -----------------
         M q_m1 = M(0);
         M gq[9] = {};
-        if (r >= y0) {
-            const int y = r - 1;
+        if (k >= 2) {
+            const int y = r - dir;
             gq[0] = p0_m;
             gq[1] = C::dec(R.pop[y & 3][kPlane[1]][cm - 1], 1, d.f16);
-            gq[2] = p2_mm;
+            gq[2] = UP ? p2 : pb_mm;  // from row y - 1
             gq[3] = C::dec(R.pop[y & 3][kPlane[3]][cm + 1], 3, d.f16);
-            gq[4] = p4;
+            gq[4] = UP ? pb_mm : p4;  // from row y + 1
             gq[5] = C::dec(R.pop[(y - 1) & 3][kPlane[5]][cm - 1], 5, d.f16);
             gq[6] = C::dec(R.pop[(y - 1) & 3][kPlane[6]][cm + 1], 6, d.f16);
             gq[7] = C::dec(R.pop[(y + 1) & 3][kPlane[7]][cm + 1], 7, d.f16);
@@ -498,14 +513,18 @@ __device__ __forceinline__ void flux_tile(const InstDesc &d, int parity, int t, 
             q_m1 = sum9(gq);
             R.phi2[y & 3][cmw] = q_m1;
         }
-        // ---- output node (xi, r - 2), level n + 2 ---------------------------------------------------------
-        if (r >= y0 + 2 && live) {
-            const int y = __builtin_amdgcn_readfirstlane(wrapr(r - 2));
+        // ---- output node (xi, r - 2 dir), level n + 2 -----------------------------------------------------
+        if (k >= 4 && live) {
+            const int y = __builtin_amdgcn_readfirstlane(wrapr(r - 2 * dir));
             const M *__restrict__ uc = u + (int64_t)y * 2 * pitch;
             const M uxw = ld_at(uc, fm), uyw = ld_at(uc + pitch, fm), uxe = ld_at(uc, fp), uye = ld_at(uc + pitch, fp);
             M Ax, Ay;
-            flux_aux<M>(R.phi2[(r - 2) & 3][cc - 1], R.phi2[(r - 2) & 3][cc + 1], q_m3, q_m1, uxw, uyw, uxe, uye, ux3, uy3,
-                        ux1, uy1, ux2, uy2, Ax, Ay);
+            if constexpr (UP)  // south: row r + dir (phi2 of this iteration), north: row r + 3
+                flux_aux<M>(R.phi2[(r - 2 * dir) & 3][cc - 1], R.phi2[(r - 2 * dir) & 3][cc + 1], q_m1, q_m3, uxw, uyw, uxe,
+                            uye, ux1, uy1, ux3, uy3, ux2, uy2, Ax, Ay);
+            else
+                flux_aux<M>(R.phi2[(r - 2 * dir) & 3][cc - 1], R.phi2[(r - 2 * dir) & 3][cc + 1], q_m3, q_m1, uxw, uyw, uxe,
+                            uye, ux3, uy3, ux1, uy1, ux2, uy2, Ax, Ay);
             const Relax<M> rr = HAS_K ? relax_from_k<M>(ld_at(kf + (int64_t)y * pitch, fc), lam, rconst.w3) : rconst;
             const M s = HAS_S ? ld_at(sf + (int64_t)y * pitch, fc) : M(0);
             M Q[9];
@@ -518,7 +537,7 @@ __device__ __forceinline__ void flux_tile(const InstDesc &d, int parity, int t, 
                 else st_nt_at(out, bc + (unsigned)i * pb, C::enc(Q[i], i, d.f16, rb2));
             }
         }
-        // ---- roll the walk down one row -------------------------------------------------------------------
+        // ---- roll the walk on by one row -------------------------------------------------------------------
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             gc[i] = gn[i];
@@ -528,8 +547,8 @@ __device__ __forceinline__ void flux_tile(const InstDesc &d, int parity, int t, 
         p1_c = p1_p;
         q_m3 = q_m2;
         q_m2 = q_m1;
-        p2_mm = p2_m;
-        p2_m = C::dec(C::enc(P[2], 2, d.f16, rb1), 2, d.f16);
+        pb_mm = pb_m;
+        pb_m = UP ? p4 : p2;
         p0_m = C::dec(C::enc(P[0], 0, d.f16, rb1), 0, d.f16);
         ux3 = ux2;
         uy3 = uy2;
@@ -557,14 +576,19 @@ __attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW)))) void step2_kernel(co
 }
 
 // One instance, flux form: block b -> tile.
+// FP32 storage on 128-column tiles (the default shape): registers for six resident waves per SIMD (80
+// VGPRs), which a 2048^2 lattice in 16-row tiles needs for every block to be resident at once
 template <int MODE, bool HAS_K, bool HAS_S, int NW, bool CST>
-__global__ __launch_bounds__(64 * (NW + 1)) void flux2_kernel(const StepArgs a)
+__global__ __launch_bounds__(64 * (NW + 1))
+__attribute__((amdgpu_waves_per_eu(MODE == MODE_F32_F32 && NW == 2 ? 6 : 1))) void flux2_kernel(const StepArgs a)
 {
     const InstDesc &d = a.d;
     const int ntx = (d.L.nx + 64 * NW - 1) / (64 * NW);
     const int t = tile_of_block(blockIdx.x, gridDim.x, d.lcf.xcd_remap, ntx, d.lcf.xcd_rows);
     __shared__ FluxRings<MODE, NW> rings;
-    flux_tile<MODE, HAS_K, HAS_S, NW, CST, MODE == MODE_F64_F64 || MODE == MODE_F64_F32>(d, a.parity, t, rings);
+    constexpr bool PF = MODE == MODE_F64_F64 || MODE == MODE_F64_F32;
+    if ((t / ntx) & 1) flux_tile<MODE, HAS_K, HAS_S, NW, CST, PF, true>(d, a.parity, t, rings);
+    else flux_tile<MODE, HAS_K, HAS_S, NW, CST, PF, false>(d, a.parity, t, rings);
 }
 
 // Many instances (periodic D2Q9 TRT-R, one storage form and aux form): each block runs a range of
