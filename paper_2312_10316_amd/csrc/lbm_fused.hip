@@ -29,15 +29,19 @@ namespace {
 // LDS ring plane of each population that moves along x (-1: kept in registers).
 constexpr int kPlane[9] = {-1, 0, -1, 1, -1, 2, 3, 4, 5};
 
-// Resident waves per SIMD that the registers of step2_kernel are allocated for (see there).
-constexpr int step2_waves(int mode, int nw)
+// Resident waves per SIMD that the registers of the two-step kernels are allocated for (see below).
+constexpr int step2_waves(int mode, int nw, bool batched)
 {
-    return mode == MODE_F64_F64 || mode == MODE_F64_F32 ? (nw == 2 ? 4 : (nw == 4 ? 3 : 2)) : 6;
+    if (mode == MODE_F64_F64 || mode == MODE_F64_F32) return nw == 2 ? 4 : (nw == 4 ? 3 : 2);
+    if (batched) return 6;
+    return mode == MODE_F16S_F32 && nw <= 4 ? 8 : 6;
 }
 
-// amdgpu_waves_per_eu: register allocation for at least six resident waves per SIMD, or as many as the
-// LDS ring of FP64 storage lets 160 KB hold (2 to 4): FP32 and FP16 storage then fit 41-49 VGPRs,
-// against 65-83 by default.
+// amdgpu_waves_per_eu: register allocation for as many resident waves per SIMD as the blocks of the
+// default shapes can use, or as the LDS ring of FP64 storage lets 160 KB hold (2 to 4): FP32 six
+// (80 VGPRs), FP16 eight on tiles of up to 256 columns (64; with a D field the walk had grown to 65 and
+// lost a wave per SIMD: 8192^2 162k -> 169k MLUPS with the cap), the 9-wave blocks of 512-column tiles,
+// stochastic rounding (capped at seven it spilled and lost 2-6 %) and the batched kernel six.
 // The walk is bound by the loads each wave keeps in flight, so resident waves count more than registers.
 // The LDS ring of a block: four rows of the six x-moving intermediate populations, W + 2 columns and
 // one more that the frame wave's idle lanes write (and nothing reads).
@@ -564,7 +568,7 @@ __device__ __forceinline__ void flux_tile(const InstDesc &d, int parity, int t, 
 // One instance: block b -> tile (XCD-remapped as the launch says).
 template <int MODE, int AUX, bool HAS_K, bool HAS_S, bool MRT, int NW, bool CST>
 __global__ __launch_bounds__(64 * (NW + 1))
-__attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW)))) void step2_kernel(const StepArgs a)
+__attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW, false)))) void step2_kernel(const StepArgs a)
 {
     const InstDesc &d = a.d;
     const int ntx = (d.L.nx + 64 * NW - 1) / (64 * NW);
@@ -595,7 +599,7 @@ __attribute__((amdgpu_waves_per_eu(MODE == MODE_F32_F32 && NW == 2 ? 6 : 1))) vo
 // (instance, fused tile) work items, non-temporal stores; the descriptor is wave-uniform (scalar loads).
 template <int MODE, int AUX, int NW>
 __global__ __launch_bounds__(64 * (NW + 1))
-__attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW)))) void batched_step2_kernel(const BatchArgs a)
+__attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW, true)))) void batched_step2_kernel(const BatchArgs a)
 {
     int beg, end;
     if (a.block_start) {
