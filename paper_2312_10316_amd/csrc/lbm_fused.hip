@@ -1,5 +1,5 @@
 // lbm_fused.hip -- two time steps of the D2Q9 TRT-R update per launch (temporal blocking, gfx950): a
-// block walks its tile top to bottom and passes the intermediate state through an LDS ring.
+// block walks its tile row by row and passes the intermediate state through an LDS ring.
 //
 // A step is bound by memory traffic: every population is read once and written once per step
 // (Sec. 2.2, Eq. (14) pulls nine values and stores nine).  Fusing two steps halves that traffic: a
@@ -12,10 +12,10 @@
 //
 // Block: NW "interior" waves (lane = column, W = 64 NW output columns x0 .. x0 + W - 1) and one
 // "frame" wave whose lanes 0 and 1 compute the intermediate nodes just left and right of the tile
-// (columns x0 - 1 and x0 + W, wrapped).  The block walks its H output rows top to bottom (with FP32
-// and FP64 storage, odd tile rows bottom to top): iteration r computes intermediate row r (from state
-// rows r - 1 .. r + 1 in HBM/L2) and, one row behind, output row r - 1 (from intermediate rows
-// r - 2 .. r; r + 1 and rows r .. r + 2 walking up).  Intermediate populations that move
+// (columns x0 - 1 and x0 + W, wrapped).  The block walks its H output rows top to bottom (the
+// single-instance kernel walks odd tile rows bottom to top): iteration r computes intermediate row r
+// (from state rows r - 1 .. r + 1 in HBM/L2) and, one row behind, output row r - 1 (from intermediate
+// rows r - 2 .. r; r + 1 and rows r .. r + 2 walking up).  Intermediate populations that move
 // along x (i = 1, 3, 5, 6, 7, 8) are exchanged through a four-row LDS ring; those with e_x = 0
 // (i = 0, 2, 4) stay in the registers of the lane that computed them.  Four ring rows let the next
 // intermediate row be written while the previous output row is still being read, so one barrier
@@ -181,13 +181,13 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
         load_row(rs, nxt);
         load_aux(__builtin_amdgcn_readfirstlane(wrapr(rs)), nxt);
     }
-    // one row of the walk; with PF the walk is unrolled by two, so the values rolled from row to row are
-    // renamed instead of copied
     // FP16 with stochastic rounding raises the issue priority of its waves for the output node (after the
     // barrier) and lowers it for the intermediate node: 2048^2 146k -> 158k, 8192^2 156k -> 168k MLUPS.
     // Round-to-nearest FP16 gained with 512-column tiles (2048^2 188k -> 195k) and lost with 256-column
     // ones (8192^2 201k -> 190k); FP32 and FP64 were level or slower.
     constexpr bool kPrio = MODE == MODE_F16SR_F32 || (MODE == MODE_F16S_F32 && NW == 8);
+    // one row of the walk; with PF the walk is unrolled by two, so the values rolled from row to row are
+    // renamed instead of copied
     auto walk_row = [&](const int k) __attribute__((always_inline)) {
         if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
         const int r = __builtin_amdgcn_readfirstlane(rs + dir * k);
@@ -304,10 +304,11 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
 // column x0 - 3 + cc, wrapped): phi at level n + 1 for all W + 6 columns (each the sum of the node's pulls
 // from the state at n), intermediate nodes (level n + 1) for the inner W + 4, phi at level n + 2 for the
 // inner W + 2 (the sums of the pulls from the intermediate state) and outputs for the W interior
-// columns.  Iteration r of the walk pulls state row r + 1 (its phi into a ring, its populations kept for
-// the next iteration), computes intermediate row r (the x-moving populations into a ring); after the
-// block's one barrier it pulls intermediate rows r - 2 .. r for the node of row r - 1 (its phi into a
-// ring, its populations kept) and computes output row r - 2.  Frame wave lanes 0-2 and 3-5 take the
+// columns.  Iteration r of the walk (top to bottom; odd tile rows bottom to top, with r + 1 read as the
+// row ahead) pulls state row r + 1 (its phi into a ring, its populations kept for the next iteration),
+// computes intermediate row r (the x-moving populations into a ring); after the block's one barrier it
+// pulls intermediate rows r - 2 .. r for the node of row r - 1 (its phi into a ring, its populations
+// kept) and computes output row r - 2.  Frame wave lanes 0-2 and 3-5 take the
 // three frame columns on the left and on the right.  Every node runs the arithmetic of the one-step flux
 // kernel (the same pulls, sums in index order, flux_aux, collide) and the intermediate populations go
 // through the storage codec, so the results are bitwise those of two single steps.
