@@ -280,14 +280,16 @@ typedef struct lbm_launch {
                             launch (temporal blocking), each block computing the intermediate state of its
                             tile and a one-node frame around it in LDS, so every population crosses memory
                             once per two steps; bitwise the same results.  2 needs periodic D2Q9 TRT-R
-                            instances (tau3 0 or 1) with the local or no auxiliary term and two
-                            population buffers: a context of one such instance, or every instance of a
-                            uniform batch at once (inst = -1; one batched launch per two steps, tiles of
-                            every instance in the batch schedule, non-temporal stores).  Tiles are then
-                            tile_width = 128, 256 or 512 columns by rows = 1..256 rows, in the tile order
-                            xcd_remap (xcd_rows), with stores 0 or 1 and max_waves 0.  An odd step count
+                            instances (tau3 0 or 1) and two population buffers: a context of one such
+                            instance (any auxiliary term), or every instance of a uniform batch with the
+                            local or no auxiliary term at once (inst = -1; one batched launch per two
+                            steps, tiles of every instance in the batch schedule, non-temporal stores).
+                            Tiles are then tile_width = 128, 256 or 512 columns by rows = 1..256 rows,
+                            in the tile order xcd_remap (xcd_rows), with stores 0 or 1 and max_waves 0.
+                            An odd step count
                             ends with one single step in the context's one-step shape.  Default: 2 for
-                            such a single instance and for such a uniform batch (128 x 16 tiles). */
+                            such a single instance of at least 2^18 nodes (2^21 with FP16 storage) and
+                            for such a uniform batch (128 x 16 tiles). */
 } lbm_launch;
 
 /* Sets (inst = -1: every instance) or reads the launch shape; captured step graphs are dropped.

@@ -172,6 +172,16 @@ bool fusable(const lbm_params &p)
 {
     return p.lattice == LBM_LATTICE_D2Q9 && p.boundary == LBM_BC_PERIODIC && (p.tau3 == 0.0 || p.tau3 == 1.0);
 }
+// Nodes from which one periodic instance takes two steps per launch.  A fused launch walks each tile's
+// rows one after the other, which small lattices do not hide; measured (MLUPS, one step / two steps per
+// launch): FP64 384^2 26.9k / 26.4k, 512^2 34.3k / 45.0k; FP32 384^2 40.0k / 37.6k, 512^2 58.4k /
+// 63.2k; FP16 1024^2 113.9k / 107.8k, 2048^2 about 163k / 191k (its one-step state stays in the
+// Infinity Cache longer).
+int64_t fuse_min_nodes(int mode)
+{
+    return is_f16_mode(mode) ? ((int64_t)1 << 21) : ((int64_t)1 << 18);
+}
+
 Launch fused_default(const lbm_params &p, int mode)
 {
     Launch lc{};
@@ -772,10 +782,7 @@ int lbm_init(lbm_ctx **out, int32_t n_inst, const lbm_params *p, const lbm_field
         in.mode = mode_of(p[k]);
         in.L = layout_of(p[k]);
         in.lc1 = default_launch(in.p, in.mode, f[k].D != nullptr, n_inst, c->lds_per_cu);
-        // two steps per launch from 2^19 nodes on: a fused launch walks each tile's rows one after the
-        // other, which small lattices do not hide (512^2 FP32: 46.9k against 54.7k MLUPS one step per
-        // launch; 1024^2: 101k against 81k)
-        in.lc = n_inst == 1 && fusable(in.p) && (int64_t)in.p.nx * in.p.ny >= ((int64_t)1 << 19)
+        in.lc = n_inst == 1 && fusable(in.p) && (int64_t)in.p.nx * in.p.ny >= fuse_min_nodes(in.mode)
                     ? fused_default(in.p, in.mode)
                     : in.lc1;
         const size_t pb = pops_bytes(p[k]), vb = vel_bytes(p[k]), fb = field_bytes(p[k]);

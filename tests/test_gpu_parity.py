@@ -476,19 +476,22 @@ def test_launch_defaults_and_bad_launch_shapes():
             width //= 2
         return launch(rows, 1, width, 0, 0, stores, 2)
 
-    # One periodic D2Q9 TRT-R instance of at least 2^19 nodes runs two steps per launch; a smaller one runs
-    # one.  A context that touches at most 256 MiB per step is served by the Infinity Cache: cached
-    # stores, row bands, every wave resident (64-column tiles kept for FP64 storage on narrow lattices).
+    # One periodic D2Q9 TRT-R instance of at least 2^18 nodes (2^21 with FP16 storage) runs two steps per
+    # launch; a smaller one runs one.  A context that touches at most 256 MiB per step is served by the
+    # Infinity Cache: cached stores, row bands, every wave resident (64-column tiles kept for FP64
+    # storage on narrow lattices).
     for mode, w in (("f32", launch(1, 1, 256, 0)), ("f64", launch(1, 1, 64, 0)), ("f16s", launch(1, 1, 256, 0))):
         s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, mode), fields)])
         assert s.get_launch() == w, mode
         s.close()
-    big = {k: dev(np.resize(v.cpu().numpy(), (725, 725))) for k, v in fields.items()}
-    for mode in ("f32", "f64", "f16s"):
-        s = Solver([(lbm.make_params(725, 725, f["dx"], f["dt"], cfg.lam, cfg.D, mode), big)])
-        assert s.get_launch() == fused(725, 725, 1, mode), mode
+    for n, mode, w in ((725, "f32", None), (725, "f64", None), (725, "f16s", launch(1, 1, 256, 0)),
+                       (512, "f32", None), (512, "f64", None), (511, "f64", launch(1, 1, 64, 0)),
+                       (1449, "f16s", None), (1448, "f16s", launch(1, 1, 256, 0))):
+        big = {k: dev(np.resize(v.cpu().numpy(), (n, n))) for k, v in fields.items()}
+        s = Solver([(lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, mode), big)])
+        assert s.get_launch() == (w or fused(n, n, 1, mode)), (n, mode)
         s.close()
-    del big
+        del big
     for mode, w in (("f32", launch(1, 1, 256, 0)), ("f64", launch(1, 1, 64, 0)), ("f16s", launch(1, 1, 256, 0))):
         s = Solver([(lbm.make_params(64, 64, f["dx"], f["dt"], cfg.lam, cfg.D, mode, boundary=lbm.LBM_BC_NEE), fields)])
         assert s.get_launch() == w, mode
