@@ -153,35 +153,35 @@ Launch default_launch(const lbm_params &p, int mode, bool has_D, int n_inst, int
     return lc;
 }
 
-// Two steps per launch (temporal blocking, lbm_fused.hip) for a single periodic D2Q9 TRT-R instance
-// with the local or no auxiliary term.  Tile shapes from sweeps at 2048^2, 4096^2 and 8192^2 (widths
-// 128/256/512 x 8..64 rows x stores): FP32 storage 512 x 16 (2048^2 129k, 4096^2 131k, 8192^2 140k
-// MLUPS); FP16 storage with at most 8 tiles of 256 columns per row 512 x 16 (179k), wider 256 x 16
-// (8192^2 195k; stochastic rounding 256 x 24, 155k); FP64 storage 512 x 16 (8192^2 69k; FP32 math
-// 76k), on narrow lattices 256 x 32 (FP32 math 512 x 32).  Tiles never
-// wider than the lattice needs (at least 128 columns), and at least 256 tiles where the lattice allows
-// (down to 4 rows, then down to 128 columns: a 512^2 lattice in 512 x 4 tiles kept half the CUs idle).
-// The flux form (sweep of 128/256 columns x 8..64 rows x stores): 128-column tiles, 16 rows for FP32 up
-// to 2048 columns (2048^2: 97k MLUPS), FP16 there 256 x 24 (111k), else 32 rows (8192^2 FP32 109k,
-// FP16 113k, FP64 57k).  Row bands over the XCDs, so that the frame rows a tile shares with the next tile
-// down sit in the same L2.  (MRT-R stays on single steps: with FP64 math the compiler had fused its
-// third-order multiply-adds otherwise in the fused kernel.)
 // An instance whose steps can be fused (a periodic D2Q9 TRT-R instance, any aux form).  A context fuses
 // its one instance, or every instance of a uniform batch at once (local or no aux term).
 bool fusable(const lbm_params &p)
 {
     return p.lattice == LBM_LATTICE_D2Q9 && p.boundary == LBM_BC_PERIODIC && (p.tau3 == 0.0 || p.tau3 == 1.0);
 }
+
 // Nodes from which one periodic instance takes two steps per launch.  A fused launch walks each tile's
 // rows one after the other, which small lattices do not hide; measured (MLUPS, one step / two steps per
-// launch): FP64 384^2 26.9k / 26.4k, 512^2 34.3k / 45.0k; FP32 384^2 40.0k / 37.6k, 512^2 58.4k /
-// 63.2k; FP16 1024^2 113.9k / 107.8k, 2048^2 about 163k / 191k (its one-step state stays in the
+// launch): FP64 384^2 26.5k / 26.4k, 512^2 34.4k / 44.8k; FP32 384^2 40.3k / 37.7k, 512^2 59.3k /
+// 63.0k; FP16 1024^2 117.2k / 107.4k, 2048^2 about 163k / 191k (its one-step state stays in the
 // Infinity Cache longer).
 int64_t fuse_min_nodes(int mode)
 {
     return is_f16_mode(mode) ? ((int64_t)1 << 21) : ((int64_t)1 << 18);
 }
 
+// Two steps per launch (temporal blocking, lbm_fused.hip) for a single periodic D2Q9 TRT-R instance.
+// Tile shapes from sweeps at 2048^2, 4096^2 and 8192^2 (widths 128/256/512 x 8..64 rows x stores):
+// FP32 storage 512 x 16 (2048^2 131k, 4096^2 131k, 8192^2 140k MLUPS); FP16 storage with at most 8
+// tiles of 256 columns per row 512 x 16 (193k), wider 256 x 16 (8192^2 200k; stochastic rounding
+// 256 x 24, 164k); FP64 storage 512 x 16 (8192^2 69k; FP32 math 76k), on narrow lattices 256 x 32
+// (FP32 math 512 x 32).  Tiles never wider than the lattice needs (at least 128 columns), and at least
+// 256 tiles where the lattice allows (down to 4 rows, then down to 128 columns: a 512^2 lattice in
+// 512 x 4 tiles kept half the CUs idle).  The flux form (128/256 columns x 8..64 rows x stores):
+// 128-column tiles, 16 rows for FP32 up to 2048 columns (2048^2: 99k MLUPS), FP16 there 256 x 24 (133k),
+// else 32 rows (8192^2 FP32 113k, FP16 136k, FP64 57k).  Row bands over the XCDs, so that the frame
+// rows a tile shares with the next tile down sit in the same L2.  (MRT-R stays on single steps: with
+// FP64 math the compiler had fused its third-order multiply-adds otherwise in the fused kernel.)
 Launch fused_default(const lbm_params &p, int mode)
 {
     Launch lc{};
