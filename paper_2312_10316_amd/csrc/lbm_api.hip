@@ -163,7 +163,7 @@ bool fusable(const lbm_params &p)
 // Nodes from which one periodic instance takes two steps per launch.  A fused launch walks each tile's
 // rows one after the other, which small lattices do not hide; measured (MLUPS, one step / two steps per
 // launch): FP64 384^2 26.5k / 26.4k, 512^2 34.4k / 44.8k; FP32 384^2 40.3k / 37.7k, 512^2 59.3k /
-// 63.0k; FP16 1024^2 117.2k / 107.4k, 2048^2 about 163k / 191k (its one-step state stays in the
+// 63.0k; FP16 1024^2 117.2k / 107.4k, 2048^2 about 163k / 203k (its one-step state stays in the
 // Infinity Cache longer).
 int64_t fuse_min_nodes(int mode)
 {
@@ -173,7 +173,7 @@ int64_t fuse_min_nodes(int mode)
 // Two steps per launch (temporal blocking, lbm_fused.hip) for a single periodic D2Q9 TRT-R instance.
 // Tile shapes from sweeps at 2048^2, 4096^2 and 8192^2 (widths 128/256/512 x 8..64 rows x stores):
 // FP32 storage 512 x 16 (2048^2 131k, 4096^2 131k, 8192^2 140k MLUPS); FP16 storage with at most 8
-// tiles of 256 columns per row 512 x 16 (193k), wider 256 x 16 (8192^2 200k; stochastic rounding
+// tiles of 256 columns per row 512 x 16 (203k), wider 256 x 16 (8192^2 200k; stochastic rounding
 // 256 x 24, 164k); FP64 storage 512 x 16 (8192^2 69k; FP32 math 76k), on narrow lattices 256 x 32
 // (FP32 math 512 x 32).  Tiles never wider than the lattice needs (at least 128 columns), and at least
 // 256 tiles where the lattice allows (down to 4 rows, then down to 128 columns: a 512^2 lattice in

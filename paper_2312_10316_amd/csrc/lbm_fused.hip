@@ -12,7 +12,8 @@
 //
 // Block: NW "interior" waves (lane = column, W = 64 NW output columns x0 .. x0 + W - 1) and one
 // "frame" wave whose lanes 0 and 1 compute the intermediate nodes just left and right of the tile
-// (columns x0 - 1 and x0 + W, wrapped).  The block walks its H output rows top to bottom (the
+// (columns x0 - 1 and x0 + W, wrapped; FP16 storage on 512-column tiles computes them for 32 rows at a
+// time, one node per lane, and hands them out row by row).  The block walks its H output rows top to bottom (the
 // single-instance kernel walks odd tile rows bottom to top): iteration r computes intermediate row r
 // (from state rows r - 1 .. r + 1 in HBM/L2) and, one row behind, output row r - 1 (from intermediate
 // rows r - 2 .. r; r + 1 and rows r .. r + 2 walking up).  Intermediate populations that move
@@ -47,6 +48,23 @@ constexpr int step2_waves(int mode, int nw, bool batched)
 // one more that the frame wave's idle lanes write (and nothing reads).
 template <int MODE, int NW>
 using Ring = typename ModeTraits<MODE>::St::T[4][6][64 * NW + 3];
+
+// Value of v in lane l of the wave (l wave-uniform), for 2-, 4- and 8-byte storage types.
+template <class T>
+__device__ __forceinline__ T read_lane(T v, int l)
+{
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t b = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    } else if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+    } else {
+        const int b = (int)__builtin_bit_cast(uint16_t, v);
+        return __builtin_bit_cast(T, (uint16_t)__builtin_amdgcn_readlane(b, l));
+    }
+}
 
 // Two steps of tile t of one instance (tiles numbered row-major, ceil(nx / W) per row, d.lcf.rows high),
 // reading buf[parity] and writing buf[parity ^ 1]; called by every thread of the block.
@@ -175,6 +193,90 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
     // stochastic rounding: time level of the state this launch reads; it writes levels + 1 and + 2
     const int64_t level = launch_level<C>(d, parity);
     advance_level<C>(d, parity, level, 2, t == 0 && threadIdx.x == 0);
+
+    // FP16 storage on 512-column tiles: the frame wave computes the intermediate nodes of columns x0 - 1
+    // (lanes 0-31) and x0 + W (lanes 32-63), wrapped, for 32 walk rows at a time, one node per lane (lane
+    // l: walk row k0 + l % 32), and holds them in registers; each iteration lanes 0 and 1 copy that row's
+    // pair into the ring's frame columns (the other lanes write the spare column).  The nodes run the
+    // interior waves' arithmetic, with their pulls and u neighbours addressed per lane.  That walk is bound
+    // by VALU issue, and the frame wave's collision once per 32 rows instead of once per row gains 5 %
+    // (2048^2 194.5k -> 204.4k MLUPS).  Elsewhere the frame wave keeps computing its two nodes in step
+    // with the walk: FP32 and FP64 were level, FP16 on 256-column tiles lost 5 % (8192^2 201.9k ->
+    // 192.7k), stochastic rounding lost a resident wave to one more VGPR (8192^2 169k -> 143k) and the
+    // batched kernel 2 %.
+    constexpr bool kFramePass = MODE == MODE_F16S_F32 && NW == 8;
+    if (kFramePass && frame) {
+        int xf = lane < 32 ? x0 - 1 + nx : x0 + W;
+        xf %= nx;
+        const int xfm = xf == 0 ? nx - 1 : xf - 1, xfp = xf == nx - 1 ? 0 : xf + 1;
+        const int col = lane == 0 ? 0 : (lane == 1 ? W + 1 : W + 2);
+        T fv[6];
+        for (int k = 0; k < nk; ++k) {
+            if ((k & 31) == 0) {
+                const int r = rs + dir * (k + min(lane & 31, nk - 1 - k));
+                const int rw = wrapr(r), rwm = wrapr(r - 1), rwp = wrapr(r + 1);
+                const T *__restrict__ rm = src + (int64_t)rwm * 9 * pitch;
+                const T *__restrict__ rc = src + (int64_t)rw * 9 * pitch;
+                const T *__restrict__ rp = src + (int64_t)rwp * 9 * pitch;
+                T gt[9];
+                gt[0] = rc[xf];
+                gt[1] = rc[pitch + xfm];
+                gt[2] = rm[2 * pitch + xf];
+                gt[3] = rc[3 * pitch + xfp];
+                gt[4] = rp[4 * pitch + xf];
+                gt[5] = rm[5 * pitch + xfm];
+                gt[6] = rm[6 * pitch + xfp];
+                gt[7] = rp[7 * pitch + xfp];
+                gt[8] = rp[8 * pitch + xfm];
+                const M *__restrict__ uc = u + (int64_t)rw * 2 * pitch;
+                const M fux = uc[xf], fuy = uc[pitch + xf];
+                M uxe = M(0), uxw = M(0), uye = M(0), uyw = M(0), uxn = M(0), uxs = M(0), uyn = M(0), uys = M(0);
+                if (AUX == 0) {
+                    const M *__restrict__ us = u + (int64_t)rwm * 2 * pitch;
+                    const M *__restrict__ un = u + (int64_t)rwp * 2 * pitch;
+                    uxe = uc[xfp];
+                    uxw = uc[xfm];
+                    uye = uc[pitch + xfp];
+                    uyw = uc[pitch + xfm];
+                    uxn = un[xf];
+                    uyn = un[pitch + xf];
+                    uxs = us[xf];
+                    uys = us[pitch + xf];
+                }
+                const M kv = HAS_K ? kf[(int64_t)rw * pitch + xf] : M(0);
+                const M sv = HAS_S ? sf[(int64_t)rw * pitch + xf] : M(0);
+                M g[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) g[i] = C::dec(gt[i], i, d.f16);
+                M Ax = M(0), Ay = M(0);
+                if (AUX == 0) {  // as the interior node: u at rows r + 1 and r - 1 for the y-differences
+                    const M phi = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
+                    const M dxux = (uxe - uxw) * M(0.5);
+                    const M dxuy = (uye - uyw) * M(0.5);
+                    const M dyux = (uxn - uxs) * M(0.5);
+                    const M dyuy = (uyn - uys) * M(0.5);
+                    Ax = phi * (fux * dxux + fuy * dyux);
+                    Ay = phi * (fux * dxuy + fuy * dyuy);
+                }
+                const Relax<M> rr = HAS_K ? relax_from_k<M>(kv, lam, rconst.w3) : rconst;
+                M P[9];
+                collide<M, MRT>(g, fux, fuy, rr, Ax, Ay, sv, P);
+                const auto rb = C::bits(d.f16, level + 1, (int64_t)rw * nx, (unsigned)xf);
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    if (kPlane[i] >= 0) fv[kPlane[i]] = C::enc(P[i], i, d.f16, rb);
+            }
+            const int j = k & 31;
+            T(*slot)[WC] = ring[(rs + dir * k) & 3];
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                const T left = read_lane(fv[p], j), right = read_lane(fv[p], 32 + j);
+                slot[p][col] = lane == 0 ? left : right;
+            }
+            __syncthreads();
+        }
+        return;
+    }
 
     RowLoads nxt;
     if (PF) {
