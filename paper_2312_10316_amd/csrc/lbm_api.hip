@@ -173,8 +173,8 @@ int64_t fuse_min_nodes(int mode)
 // Two steps per launch (temporal blocking, lbm_fused.hip) for a single periodic D2Q9 TRT-R instance.
 // Tile shapes from sweeps at 2048^2, 4096^2 and 8192^2 (widths 128/256/512 x 8..64 rows x stores):
 // FP32 storage 512 x 16 (2048^2 131k, 4096^2 131k, 8192^2 140k MLUPS); FP16 storage with at most 8
-// tiles of 256 columns per row 512 x 16 (203k), wider 256 x 16 (8192^2 200k; stochastic rounding
-// 256 x 24, 164k); FP64 storage 512 x 16 (8192^2 69k; FP32 math 76k), on narrow lattices 256 x 32
+// tiles of 256 columns per row 512 x 16 (203k), wider 256 x 24 (3072^2 177k, 8192^2 206k, 2 % above
+// 256 x 16; stochastic rounding 167k); FP64 storage 512 x 16 (8192^2 69k; FP32 math 76k), on narrow lattices 256 x 32
 // (FP32 math 512 x 32).  Tiles never wider than the lattice needs (at least 128 columns), and at least
 // 256 tiles where the lattice allows (down to 4 rows, then down to 128 columns: a 512^2 lattice in
 // 512 x 4 tiles kept half the CUs idle).  The flux form (128/256 columns x 8..64 rows x stores):
@@ -193,7 +193,7 @@ Launch fused_default(const lbm_params &p, int mode)
         rows = 16;
     } else if (is_f16_mode(mode)) {
         width = narrow ? 512 : 256;
-        rows = !narrow && mode == MODE_F16SR_F32 ? 24 : 16;
+        rows = narrow ? 16 : 24;
     } else {  // FP64 storage: one 512-column block per CU (98.7 KB of ring) beats narrower tiles
         width = narrow && mode == MODE_F64_F64 ? 256 : 512;
         rows = narrow ? 32 : 16;

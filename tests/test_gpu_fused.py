@@ -68,9 +68,11 @@ def test_fused_equals_single_steps(mode, nx, ny):
 @pytest.mark.parametrize("aux,var,tau3", [(lbm.LBM_AUX_NONE, True, 0.0), (lbm.LBM_AUX_LOCAL, False, 0.0),
                                           (lbm.LBM_AUX_LOCAL, True, 1.0), (lbm.LBM_AUX_NONE, False, 0.0)])
 @pytest.mark.parametrize("mode", ["f64", "f32", "f16s"])
-def test_fused_variants_equal_single_steps(mode, aux, var, tau3):
-    """No auxiliary term, constant D, tau3 = 1 (TRT-R written as MRT-R), and a per-call source."""
-    one, two, (p, f, dx, dt) = contexts(mode, 200, 90, seed=11, aux=aux, var=var, tau3=tau3, shape=(256, 8, 1, 0, 0))
+@pytest.mark.parametrize("shape", [(256, 8, 1, 0, 0), (512, 40, 1, 0, 0)])
+def test_fused_variants_equal_single_steps(mode, aux, var, tau3, shape):
+    """No auxiliary term, constant D, tau3 = 1 (TRT-R written as MRT-R), and a per-call source; on
+    512-column tiles 42 walk rows (FP16 storage there computes the frame nodes 32 rows at a time)."""
+    one, two, (p, f, dx, dt) = contexts(mode, 200, 90, seed=11, aux=aux, var=var, tau3=tau3, shape=shape)
     rng = np.random.default_rng(5)
     S = dev(0.05 * rng.uniform(-1, 1, (90, 200)))
     for n, src in ((4, True), (3, False), (6, True)):

@@ -465,7 +465,7 @@ def test_launch_defaults_and_bad_launch_shapes():
 
     def fused(nx, ny, stores, mode):  # two steps per launch: the tile shapes of the sweeps
         narrow = (nx + 255) // 256 <= 8
-        width, rows = {"f32": (512, 16), "f16s": (512, 16) if narrow else (256, 16),
+        width, rows = {"f32": (512, 16), "f16s": (512, 16) if narrow else (256, 24),
                        "f16sr": (512, 16) if narrow else (256, 24),
                        "f64s_f32m": (512, 32) if narrow else (512, 16)}.get(mode, (256, 32) if narrow else (512, 16))
         while width > 128 and width // 2 >= nx:
