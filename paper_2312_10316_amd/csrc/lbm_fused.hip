@@ -12,8 +12,8 @@
 //
 // Block: NW "interior" waves (lane = column, W = 64 NW output columns x0 .. x0 + W - 1) and one
 // "frame" wave whose lanes 0 and 1 compute the intermediate nodes just left and right of the tile
-// (columns x0 - 1 and x0 + W, wrapped; FP16 storage on 512-column tiles computes them for 32 rows at a
-// time, one node per lane, and hands them out row by row).  The block walks its H output rows top to bottom (the
+// (columns x0 - 1 and x0 + W, wrapped; where it measured faster, the frame wave computes them for 4 or
+// 32 rows at a time, one node per lane, and hands them out row by row).  The block walks its H output rows top to bottom (the
 // single-instance kernel walks odd tile rows bottom to top): iteration r computes intermediate row r
 // (from state rows r - 1 .. r + 1 in HBM/L2) and, one row behind, output row r - 1 (from intermediate
 // rows r - 2 .. r; r + 1 and rows r .. r + 2 walking up).  Intermediate populations that move
@@ -70,8 +70,9 @@ __device__ __forceinline__ T read_lane(T v, int l)
 // reading buf[parity] and writing buf[parity ^ 1]; called by every thread of the block.
 // PF: issue each row's global loads one row ahead.  Single-instance kernels with FP32 or FP64 storage
 // take it; the FP16 codecs (more arithmetic per value, already issue-bound) and the batched kernel
-// (four inlined variants within one register budget) measure faster without.
-template <int MODE, int AUX, bool HAS_K, bool HAS_S, bool MRT, int NW, bool CST, bool PF, bool UP>
+// (four inlined variants within one register budget) measure faster without.  BATCH: called by the
+// batched kernel, which keeps the frame wave's nodes in step with the walk (below).
+template <int MODE, int AUX, bool HAS_K, bool HAS_S, bool MRT, int NW, bool CST, bool PF, bool UP, bool BATCH>
 __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t, Ring<MODE, NW> &ring)
 {
     using St = typename ModeTraits<MODE>::St;
@@ -194,17 +195,25 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
     const int64_t level = launch_level<C>(d, parity);
     advance_level<C>(d, parity, level, 2, t == 0 && threadIdx.x == 0);
 
-    // FP16 storage on 512-column tiles: the frame wave computes the intermediate nodes of columns x0 - 1
-    // (lanes 0-31) and x0 + W (lanes 32-63), wrapped, for 32 walk rows at a time, one node per lane (lane
-    // l: walk row k0 + l % 32), and holds them in registers; each iteration lanes 0 and 1 copy that row's
-    // pair into the ring's frame columns (the other lanes write the spare column).  The nodes run the
-    // interior waves' arithmetic, with their pulls and u neighbours addressed per lane.  That walk is bound
-    // by VALU issue, and the frame wave's collision once per 32 rows instead of once per row gains 5 %
-    // (2048^2 194.5k -> 204.4k MLUPS).  Elsewhere the frame wave keeps computing its two nodes in step
-    // with the walk: FP32 and FP64 were level, FP16 on 256-column tiles lost 5 % (8192^2 201.9k ->
-    // 192.7k), stochastic rounding lost a resident wave to one more VGPR (8192^2 169k -> 143k) and the
-    // batched kernel 2 %.
-    constexpr bool kFramePass = MODE == MODE_F16S_F32 && NW == 8;
+    // Frame pass: the frame wave computes the intermediate nodes of columns x0 - 1 (lanes 0-31) and
+    // x0 + W (lanes 32-63), wrapped, for FR walk rows at a time, one node per lane (lane l: walk row
+    // k0 + min(l % 32, FR - 1)), and holds them in registers; each iteration lanes 0 and 1 copy that
+    // row's pair into the ring's frame columns (the other lanes write the spare column).  The nodes run
+    // the interior waves' arithmetic, with their pulls and u neighbours addressed per lane.  The frame
+    // wave then runs one collision per FR rows instead of one per row, which pays where the walk is
+    // bound by VALU issue and the pass does not fetch rows far ahead of the walk:
+    //  - FP16 storage on 512-column tiles, 32 rows (2048^2 194.5k -> 204.4k MLUPS); with a D field
+    //    (whose relaxation costs three divisions per node) 4 rows;
+    //  - with a D field, FP16 storage on 256-column tiles (8192^2 172.1k -> 180.0k) and FP64 storage on
+    //    256-column tiles (2048^2 56.2k -> 58.2k), 4 rows.
+    // Elsewhere the frame wave keeps computing its two nodes in step with the walk: FP32 was level,
+    // FP64 on 512-column tiles 1 % slower; without a D field 256-column FP16 tiles lost 6-9 % in
+    // streaming (32 rows: edge lines fetched a whole tile ahead are evicted from L2 before the walk
+    // reaches them) and were level with 4 rows; stochastic rounding lost a resident wave to one more
+    // VGPR (8192^2 169k -> 143k), and the batched kernel (128-column tiles) lost 2 %.
+    constexpr bool kFramePass = !BATCH && (MODE == MODE_F16S_F32 ? (NW == 8 || (NW == 4 && HAS_K))
+                                                                 : MODE == MODE_F64_F64 && NW == 4 && HAS_K);
+    constexpr int FR = HAS_K ? 4 : 32;
     if (kFramePass && frame) {
         int xf = lane < 32 ? x0 - 1 + nx : x0 + W;
         xf %= nx;
@@ -212,8 +221,8 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
         const int col = lane == 0 ? 0 : (lane == 1 ? W + 1 : W + 2);
         T fv[6];
         for (int k = 0; k < nk; ++k) {
-            if ((k & 31) == 0) {
-                const int r = rs + dir * (k + min(lane & 31, nk - 1 - k));
+            if (k % FR == 0) {
+                const int r = rs + dir * (k + min(min(lane & 31, FR - 1), nk - 1 - k));
                 const int rw = wrapr(r), rwm = wrapr(r - 1), rwp = wrapr(r + 1);
                 const T *__restrict__ rm = src + (int64_t)rwm * 9 * pitch;
                 const T *__restrict__ rc = src + (int64_t)rw * 9 * pitch;
@@ -266,7 +275,7 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
                 for (int i = 0; i < 9; ++i)
                     if (kPlane[i] >= 0) fv[kPlane[i]] = C::enc(P[i], i, d.f16, rb);
             }
-            const int j = k & 31;
+            const int j = k % FR;
             T(*slot)[WC] = ring[(rs + dir * k) & 3];
 #pragma unroll
             for (int p = 0; p < 6; ++p) {
@@ -678,8 +687,8 @@ __attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW, false)))) void step2_ke
     const int t = tile_of_block(blockIdx.x, gridDim.x, d.lcf.xcd_remap, ntx, d.lcf.xcd_rows);
     __shared__ Ring<MODE, NW> ring;
     constexpr bool PF = !is_f16_mode(MODE);
-    if ((t / ntx) & 1) fused_tile<MODE, AUX, HAS_K, HAS_S, MRT, NW, CST, PF, true>(d, a.parity, t, ring);
-    else fused_tile<MODE, AUX, HAS_K, HAS_S, MRT, NW, CST, PF, false>(d, a.parity, t, ring);
+    if ((t / ntx) & 1) fused_tile<MODE, AUX, HAS_K, HAS_S, MRT, NW, CST, PF, true, false>(d, a.parity, t, ring);
+    else fused_tile<MODE, AUX, HAS_K, HAS_S, MRT, NW, CST, PF, false, false>(d, a.parity, t, ring);
 }
 
 // One instance, flux form: block b -> tile.
@@ -717,11 +726,11 @@ __attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW, true)))) void batched_s
         const WorkItem w = a.items[it];
         const InstDesc &d = a.inst[w.inst];
         if (d.has_k) {
-            if (d.has_s) fused_tile<MODE, AUX, true, true, false, NW, false, false, false>(d, a.parity, w.tile, ring);
-            else fused_tile<MODE, AUX, true, false, false, NW, false, false, false>(d, a.parity, w.tile, ring);
+            if (d.has_s) fused_tile<MODE, AUX, true, true, false, NW, false, false, false, true>(d, a.parity, w.tile, ring);
+            else fused_tile<MODE, AUX, true, false, false, NW, false, false, false, true>(d, a.parity, w.tile, ring);
         } else {
-            if (d.has_s) fused_tile<MODE, AUX, false, true, false, NW, false, false, false>(d, a.parity, w.tile, ring);
-            else fused_tile<MODE, AUX, false, false, false, NW, false, false, false>(d, a.parity, w.tile, ring);
+            if (d.has_s) fused_tile<MODE, AUX, false, true, false, NW, false, false, false, true>(d, a.parity, w.tile, ring);
+            else fused_tile<MODE, AUX, false, false, false, NW, false, false, false, true>(d, a.parity, w.tile, ring);
         }
         __syncthreads();  // the next tile rewrites the ring the last rows of this one were read from
     }
