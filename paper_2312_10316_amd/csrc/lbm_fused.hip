@@ -204,15 +204,17 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
     // bound by VALU issue and the pass does not fetch rows far ahead of the walk:
     //  - FP16 storage on 512-column tiles, 32 rows (2048^2 194.5k -> 204.4k MLUPS); with a D field
     //    (whose relaxation costs three divisions per node) 4 rows;
-    //  - with a D field, FP16 storage on 256-column tiles (8192^2 172.1k -> 180.0k) and FP64 storage on
-    //    256-column tiles (2048^2 56.2k -> 58.2k), 4 rows.
+    //  - with a D field, FP16 storage on 256-column tiles (8192^2 172.1k -> 180.0k), FP16 with
+    //    stochastic rounding on 256- and 512-column tiles (8192^2 132.0k -> 139.7k, 2048^2 128.1k ->
+    //    137.4k) and FP64 storage on 256-column tiles (2048^2 56.2k -> 58.2k), 4 rows.
     // Elsewhere the frame wave keeps computing its two nodes in step with the walk: FP32 was level,
     // FP64 on 512-column tiles 1 % slower; without a D field 256-column FP16 tiles lost 6-9 % in
     // streaming (32 rows: edge lines fetched a whole tile ahead are evicted from L2 before the walk
-    // reaches them) and were level with 4 rows; stochastic rounding lost a resident wave to one more
-    // VGPR (8192^2 169k -> 143k), and the batched kernel (128-column tiles) lost 2 %.
+    // reaches them) and were level with 4 rows; stochastic rounding without a D field lost a resident
+    // wave to one more VGPR (8192^2 169k -> 143k), and the batched kernel (128-column tiles) lost 2 %.
     constexpr bool kFramePass = !BATCH && (MODE == MODE_F16S_F32 ? (NW == 8 || (NW == 4 && HAS_K))
-                                                                 : MODE == MODE_F64_F64 && NW == 4 && HAS_K);
+                                           : MODE == MODE_F16SR_F32 ? (NW >= 4 && HAS_K)
+                                                                    : MODE == MODE_F64_F64 && NW == 4 && HAS_K);
     constexpr int FR = HAS_K ? 4 : 32;
     if (kFramePass && frame) {
         int xf = lane < 32 ? x0 - 1 + nx : x0 + W;
