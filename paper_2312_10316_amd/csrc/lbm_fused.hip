@@ -206,16 +206,19 @@ __device__ __forceinline__ void fused_tile(const InstDesc &d, int parity, int t,
     //    (whose relaxation costs three divisions per node) 4 rows;
     //  - with a D field, FP16 storage on 256-column tiles (8192^2 172.1k -> 180.0k), FP16 with
     //    stochastic rounding on 256- and 512-column tiles (8192^2 132.0k -> 139.7k, 2048^2 128.1k ->
-    //    137.4k) and FP64 storage on 256-column tiles (2048^2 56.2k -> 58.2k), 4 rows.
+    //    137.4k) and FP64 storage on 256-column tiles (2048^2 56.2k -> 58.2k), 4 rows;
+    //  - FP16 with stochastic rounding and streaming stores on 256-column tiles, 4 rows, its registers
+    //    capped for seven resident waves (8192^2 168.4k -> 171.9k, 4096^2 155.0k -> 158.2k).
     // Elsewhere the frame wave keeps computing its two nodes in step with the walk: FP32 was level,
     // FP64 on 512-column tiles 1 % slower; without a D field 256-column FP16 tiles lost 6-9 % in
     // streaming (32 rows: edge lines fetched a whole tile ahead are evicted from L2 before the walk
-    // reaches them) and were level with 4 rows; stochastic rounding without a D field lost a resident
-    // wave to one more VGPR (8192^2 169k -> 143k), and the batched kernel (128-column tiles) lost 2 %.
+    // reaches them) and were level with 4 rows; stochastic rounding with 32 rows and no cap lost a
+    // resident wave to one more VGPR (8192^2 169k -> 143k), and the batched kernel (128-column tiles)
+    // lost 2 % (0.5 % with 4 rows).
     constexpr bool kFramePass = !BATCH && (MODE == MODE_F16S_F32 ? (NW == 8 || (NW == 4 && HAS_K))
-                                           : MODE == MODE_F16SR_F32 ? (NW >= 4 && HAS_K)
+                                           : MODE == MODE_F16SR_F32 ? ((NW >= 4 && HAS_K) || (NW == 4 && !CST))
                                                                     : MODE == MODE_F64_F64 && NW == 4 && HAS_K);
-    constexpr int FR = HAS_K ? 4 : 32;
+    constexpr int FR = HAS_K || MODE == MODE_F16SR_F32 ? 4 : 32;
     if (kFramePass && frame) {
         int xf = lane < 32 ? x0 - 1 + nx : x0 + W;
         xf %= nx;
@@ -679,10 +682,14 @@ __device__ __forceinline__ void flux_tile(const InstDesc &d, int parity, int t, 
     }
 }
 
-// One instance: block b -> tile (XCD-remapped as the launch says).
+// One instance: block b -> tile (XCD-remapped as the launch says).  FP16 with stochastic rounding on
+// 256-column tiles with streaming stores and no D field runs the frame pass (above) within registers for
+// seven resident waves (72 VGPRs; one value is spilled before the walk and reloaded after it, once
+// per tile).
 template <int MODE, int AUX, bool HAS_K, bool HAS_S, bool MRT, int NW, bool CST>
 __global__ __launch_bounds__(64 * (NW + 1))
-__attribute__((amdgpu_waves_per_eu(step2_waves(MODE, NW, false)))) void step2_kernel(const StepArgs a)
+__attribute__((amdgpu_waves_per_eu(MODE == MODE_F16SR_F32 && NW == 4 && !HAS_K && !CST ? 7 : step2_waves(MODE, NW, false))))
+void step2_kernel(const StepArgs a)
 {
     const InstDesc &d = a.d;
     const int ntx = (d.L.nx + 64 * NW - 1) / (64 * NW);
