@@ -182,6 +182,25 @@ def test_two_steps_per_launch_and_launch_shapes_are_bitwise(shape):
     two.close()
 
 
+@pytest.mark.parametrize("shape", [(256, 24, 1, 0, 0), (256, 7, 3, 1, 0), (512, 16, 1, 0, 1)])
+def test_two_steps_per_launch_constant_D_is_bitwise(shape):
+    """Without a D field: on 256-column tiles with streaming stores the fused walk computes its frame
+    nodes four rows at a time (on 512-column tiles in step with the walk); bitwise the single steps."""
+    dx, dt, f = _case(300, 130, 12)
+    p = lbm.make_params(300, 130, dx, dt, 0.25, 2e-3, "f16sr", scale_log2=K, phi_ref=0.3, round_seed=9)
+    fields = {k: dev(f[k]) for k in ("phi0", "ux", "uy")}
+    one, two = Solver([(p, fields)]), Solver([(p, fields)])
+    one.set_launch(1, 1, tile_width=256, stores=0)
+    width, rows, remap, h, stores = shape
+    two.set_launch(rows, remap, tile_width=width, xcd_rows=h, stores=stores, fuse=2)
+    for n in (2, 1, 5, 70, 4):
+        one.step(n)
+        two.step(n)
+        assert torch.equal(one.state_save(), two.state_save()), (shape, n)
+    one.close()
+    two.close()
+
+
 def test_checkpoint_resume_needs_the_step_count():
     p, a, b = _pair(96, 64)
     a.step(33)
