@@ -174,10 +174,11 @@ int64_t fuse_min_nodes(int mode)
 // Tile shapes from sweeps at 2048^2, 4096^2 and 8192^2 (widths 128/256/512 x 8..64 rows x stores):
 // FP32 storage 512 x 16 (2048^2 131k, 4096^2 131k, 8192^2 140k MLUPS); FP16 storage with at most 8
 // tiles of 256 columns per row 512 x 16 (203k), wider 256 x 24 (3072^2 177k, 8192^2 206k, 2 % above
-// 256 x 16; stochastic rounding 167k); FP64 storage 512 x 16 (8192^2 69k; FP32 math 76k), on narrow lattices 256 x 32
-// (FP32 math 512 x 32).  Tiles never wider than the lattice needs (at least 128 columns), and at least
-// 256 tiles where the lattice allows (down to 4 rows, then down to 128 columns: a 512^2 lattice in
-// 512 x 4 tiles kept half the CUs idle).  The flux form (128/256 columns x 8..64 rows x stores):
+// 256 x 16; stochastic rounding 167k); FP64 storage 512 x 16 (8192^2 69k; FP32 math 76k), on narrow
+// lattices 256 x 32 (FP32 math 512 x 32).  Tiles never wider than the lattice needs (at least 128
+// columns); rows halved (down to 4) until there are 512 tiles, 256 where a CU holds one block, then
+// the width halved (down to 128) until there are 256 (a 512^2 lattice in 512 x 4 tiles kept half the
+// CUs idle).  The flux form (128/256 columns x 8..64 rows x stores):
 // 128-column tiles, 16 rows for FP32 up to 2048 columns (2048^2: 99k MLUPS), FP16 there 256 x 24 (133k),
 // else 32 rows (8192^2 FP32 113k, FP16 136k, FP64 57k).  Row bands over the XCDs, so that the frame
 // rows a tile shares with the next tile down sit in the same L2.  (MRT-R stays on single steps: with
@@ -204,7 +205,12 @@ Launch fused_default(const lbm_params &p, int mode)
     }
     while (width > 128 && width / 2 >= p.nx) width /= 2;
     auto tiles = [&](int h) { return (int64_t)((p.nx + width - 1) / width) * ((p.ny + h - 1) / h); };
-    while (rows > 4 && tiles(rows) < 256) rows /= 2;
+    // rows halved until every CU has two tiles (one where a CU holds a single block: FP64 storage on
+    // 512-column tiles; and the flux form, not measured otherwise): 1024^2 FP32 512 x 8 -> 512 x 4
+    // 122.4k -> 135.4k MLUPS, FP64 256 x 16 -> 256 x 8 71.9k -> 73.3k
+    const bool one_block = (mode == MODE_F64_F64 || mode == MODE_F64_F32) && width == 512;
+    const int64_t want = one_block || p.aux == LBM_AUX_FLUX ? 256 : 512;
+    while (rows > 4 && tiles(rows) < want) rows /= 2;
     while (width > 128 && tiles(rows) < 256) width /= 2;  // small lattices: narrower tiles fill the CUs
     lc.fuse_width = width;
     lc.rows = rows;

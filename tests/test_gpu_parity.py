@@ -470,7 +470,8 @@ def test_launch_defaults_and_bad_launch_shapes():
                        "f64s_f32m": (512, 32) if narrow else (512, 16)}.get(mode, (256, 32) if narrow else (512, 16))
         while width > 128 and width // 2 >= nx:
             width //= 2
-        while rows > 4 and -(-nx // width) * -(-ny // rows) < 256:
+        want = 256 if mode in ("f64", "f64s_f32m") and width == 512 else 512  # two tiles per CU
+        while rows > 4 and -(-nx // width) * -(-ny // rows) < want:
             rows //= 2
         while width > 128 and -(-nx // width) * -(-ny // rows) < 256:
             width //= 2
