@@ -490,7 +490,8 @@ def test_launch_defaults_and_bad_launch_shapes():
                        (1449, "f16s", None), (1448, "f16s", launch(1, 1, 256, 0))):
         big = {k: dev(np.resize(v.cpu().numpy(), (n, n))) for k, v in fields.items()}
         s = Solver([(lbm.make_params(n, n, f["dx"], f["dt"], cfg.lam, cfg.D, mode), big)])
-        assert s.get_launch() == (w or fused(n, n, 1, mode)), (n, mode)
+        l2 = mode == "f32" and n * n * 80 <= 32 << 20  # FP32 within the L2 caches streams its stores
+        assert s.get_launch() == (w or fused(n, n, 0 if l2 else 1, mode)), (n, mode)
         s.close()
         del big
     for mode, w in (("f32", launch(1, 1, 256, 0)), ("f64", launch(1, 1, 64, 0)), ("f16s", launch(1, 1, 256, 0))):
