@@ -1209,6 +1209,7 @@ int lbm_set_launch(lbm_ctx *c, int32_t inst, const lbm_launch *cfg)
         if (!two) in.lc1 = lc;  // fused: single steps keep a one-step launch of the same store kind
         else in.lc1.stores = lc.stores;
     }
+    c->l2_streams = false;  // the caller's store kind holds for the adjoint's recomputation too
     return refresh_tables(c);
 }
 
